@@ -1,0 +1,351 @@
+"""Pins of the FP64 oracle against facts fixed by the mathematics.
+
+None of these re-types the oracle's own formulas: each expected value comes
+from a closed form, a brute-force enumeration written independently here, an
+invariant, a finite difference, or a different library routine.
+"""
+import copy
+import itertools
+
+import numpy as np
+import pytest
+from scipy.linalg import expm, expm_frechet
+
+from oracle import epoch_oracle as O
+from paper_1309_3075_amd import workloads as W
+
+
+def jc69_Q():
+    Q = np.full((4, 4), 1.0 / 3.0)
+    np.fill_diagonal(Q, -1.0)
+    return Q
+
+
+def jc69_P(t):
+    """Closed form for JC69 with unit mean rate."""
+    e = np.exp(-4.0 * t / 3.0)
+    P = np.full((4, 4), 0.25 - 0.25 * e)
+    np.fill_diagonal(P, 0.25 + 0.75 * e)
+    return P
+
+
+def two_state_P(a, b, t):
+    """Closed form for Q = [[-a, a], [b, -b]]."""
+    s = a + b
+    e = np.exp(-s * t)
+    return np.array([[b + a * e, a - a * e], [b - b * e, a + b * e]]) / s
+
+
+def make_problem(parent, height, Qs, boundaries, phi, tips, pi_root, cat_rates=(1.0,),
+                 cat_weights=(1.0,), weights=None, branch_rate=None):
+    tips = np.asarray(tips, dtype=np.int32)
+    P = tips.shape[1]
+    return W.Problem(name="pin", parent=np.asarray(parent, np.int32),
+                     height=np.asarray(height, float),
+                     branch_rate=np.ones(len(parent)) if branch_rate is None else np.asarray(branch_rate, float),
+                     boundaries=np.asarray(boundaries, float),
+                     interval_process=np.asarray(phi, np.int32), Q=[np.asarray(q) for q in Qs],
+                     pi_process=[None] * len(Qs), pi_root=np.asarray(pi_root, float),
+                     cat_rates=np.asarray(cat_rates, float), cat_weights=np.asarray(cat_weights, float),
+                     tips=tips, weights=np.ones(P) if weights is None else np.asarray(weights, float))
+
+
+# ---------------------------------------------------------------------------
+# exp(tQ)
+# ---------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("t", [0.0, 1e-6, 0.1, 0.7, 3.0, 25.0])
+def test_homogeneous_matches_jc69_closed_form(t):
+    np.testing.assert_allclose(O.homogeneous_P(jc69_Q(), t), jc69_P(t), rtol=0, atol=1e-14)
+
+
+def test_rows_sum_to_one_identity_at_zero_and_semigroup():
+    rng = np.random.default_rng(5)
+    for reversible in (True, False):
+        prob = W.random_problem(rng, 4, 7, 3, reversible=reversible)
+        Q = prob.Q[0]
+        np.testing.assert_allclose(O.homogeneous_P(Q, 0.0), np.eye(7), atol=0)
+        for t in (0.01, 0.5, 4.0):
+            P = O.homogeneous_P(Q, t)
+            np.testing.assert_allclose(P.sum(axis=1), 1.0, atol=1e-13)
+        np.testing.assert_allclose(O.homogeneous_P(Q, 0.3) @ O.homogeneous_P(Q, 0.45),
+                                   O.homogeneous_P(Q, 0.75), atol=1e-13)
+
+
+def test_taylor_for_tiny_time():
+    rng = np.random.default_rng(6)
+    Q = W.sparse_asymmetric(6, 0.5, rng)
+    t = 1e-4
+    taylor = np.eye(6) + t * Q + (t * Q) @ (t * Q) / 2 + (t * Q) @ (t * Q) @ (t * Q) / 6
+    np.testing.assert_allclose(O.homogeneous_P(Q, t), taylor, atol=1e-16)
+
+
+# ---------------------------------------------------------------------------
+# Segmentation and the ordered product (Eq. 6, Eq. 7)
+# ---------------------------------------------------------------------------
+
+
+def test_segments_cover_the_branch_in_parent_first_order():
+    b = [0.2, 0.5, 0.9]
+    phi = [3, 1, 2, 0]
+    segs = O.branch_segments(0.95, 0.1, b, phi)
+    assert [s for s, _ in segs] == [0, 2, 1, 3]
+    np.testing.assert_allclose([d for _, d in segs], [0.05, 0.4, 0.3, 0.1])
+    # node exactly on a boundary: the zero-length stretch is dropped
+    segs = O.branch_segments(0.5, 0.2, b, phi)
+    assert [s for s, _ in segs] == [1]
+    np.testing.assert_allclose(segs[0][1], 0.3)
+    # a single interval (no boundaries)
+    assert O.branch_segments(2.0, 0.0, [], [0]) == [(0, 2.0)]
+
+
+def test_identical_epochs_reproduce_single_exponential():
+    rng = np.random.default_rng(7)
+    Q = W.sparse_asymmetric(5, 0.6, rng)
+    segs = [(0, 0.13), (0, 0.4), (0, 0.07)]
+    np.testing.assert_allclose(O.epoch_P([Q], segs, 1.7), expm(Q * 1.7 * 0.6), atol=1e-13)
+
+
+def test_jc69_rate_multipliers_commute_to_closed_form():
+    Qs = [0.5 * jc69_Q(), 2.0 * jc69_Q(), 1.3 * jc69_Q()]
+    segs = [(0, 0.2), (1, 0.35), (2, 0.1)]
+    np.testing.assert_allclose(O.epoch_P(Qs, segs, 1.0), jc69_P(0.5 * 0.2 + 2.0 * 0.35 + 1.3 * 0.1),
+                               atol=1e-14)
+
+
+def test_two_state_product_order_parent_first():
+    """Older interval's matrix multiplies on the left (rows = parent state)."""
+    Qa = np.array([[-1.0, 1.0], [3.0, -3.0]])
+    Qb = np.array([[-2.5, 2.5], [0.2, -0.2]])
+    segs = [(0, 0.3), (1, 0.8)]
+    expected = two_state_P(1.0, 3.0, 0.3) @ two_state_P(2.5, 0.2, 0.8)
+    wrong = two_state_P(2.5, 0.2, 0.8) @ two_state_P(1.0, 3.0, 0.3)
+    got = O.epoch_P([Qa, Qb], segs, 1.0)
+    np.testing.assert_allclose(got, expected, atol=1e-14)
+    assert np.abs(got - wrong).max() > 1e-3
+
+
+# ---------------------------------------------------------------------------
+# Likelihood: brute force with data augmentation at every boundary crossing
+# ---------------------------------------------------------------------------
+
+
+def brute_force_site_likelihood(prob):
+    """Sum over the states of every internal node and every boundary crossing.
+
+    Each branch is cut at the boundaries it crosses; each piece is a homogeneous
+    stretch with its own exp(t Q).  No matrix product and no recursion.
+    """
+    K = prob.Q[0].shape[0]
+    N = prob.n_tips
+    root = prob.parent.shape[0] - 1
+    edges = []  # (parent var, child var or ('tip', t), process, time)
+    n_var = 0
+    var_of = {}
+    for u in range(N, root + 1):
+        var_of[u] = n_var
+        n_var += 1
+    bnd = list(prob.boundaries)
+    edge_list = []
+    for v in range(root):
+        u = prob.parent[v]
+        hu, hv = prob.height[u], prob.height[v]
+        cuts = [b for b in reversed(bnd) if hv < b < hu]
+        points = [hu] + cuts + [hv]
+        prev = var_of[u]
+        for k in range(len(points) - 1):
+            mid = 0.5 * (points[k] + points[k + 1])
+            interval = int(np.searchsorted(bnd, mid, side="right"))
+            s = prob.interval_process[interval]
+            dt = (points[k] - points[k + 1]) * prob.branch_rate[v]
+            if k == len(points) - 2:
+                child = ("tip", v) if v < N else var_of[v]
+            else:
+                child = n_var
+                n_var += 1
+            edge_list.append((prev, child, s, dt))
+            prev = child
+    npat = prob.tips.shape[1]
+    grid = np.array(list(itertools.product(range(K), repeat=n_var)))
+    total = np.zeros(npat)
+    for c, (rho, wc) in enumerate(zip(prob.cat_rates, prob.cat_weights)):
+        f = np.repeat(prob.pi_root[grid[:, var_of[root]]][:, None], npat, axis=1)
+        for par, child, s, dt in edge_list:
+            Pm = expm(prob.Q[s] * dt * rho)
+            xp = grid[:, par]
+            if isinstance(child, tuple):
+                st = prob.tips[child[1]]
+                col = np.where(st[None, :] < K, Pm[xp][:, np.minimum(st, K - 1)], 1.0)
+                f = f * col
+            else:
+                f = f * Pm[xp, grid[:, child]][:, None]
+        total += wc * f.sum(axis=0)
+    return total
+
+
+@pytest.mark.parametrize("seed,n_tips,K,n_int,C", [(1, 3, 3, 3, 1), (2, 3, 4, 2, 2),
+                                                    (3, 4, 3, 2, 1), (4, 4, 2, 3, 2)])
+def test_pruning_matches_brute_force_augmentation(seed, n_tips, K, n_int, C):
+    rng = np.random.default_rng(seed)
+    prob = W.random_problem(rng, n_tips, K, 6, n_categories=C, n_intervals=n_int,
+                            reversible=(seed % 2 == 0), tip_height_max=0.2,
+                            branch_rate_spread=0.3, missing_frac=0.1)
+    want = np.log(brute_force_site_likelihood(prob))
+    got = O.site_log_likelihoods(prob)
+    np.testing.assert_allclose(got, want, rtol=1e-12, atol=0)
+
+
+def test_two_taxon_jc69_closed_form():
+    """Two tips under JC69: L = pi_a P_ab(t1 + t2) (pulley through the root)."""
+    t1, t2 = 0.3, 0.55
+    tips = np.array([[0, 1, 2, 3, 0], [0, 2, 2, 1, 3]])
+    prob = make_problem([2, 2, -1], [0.55 - t1 + 0.0, 0.0, 0.55], [jc69_Q()], [], [0], tips,
+                        np.full(4, 0.25))
+    prob.height[:] = [0.55 - t1, 0.0, 0.55]
+    P = jc69_P(t1 + t2)
+    want = np.log(0.25 * P[tips[0], tips[1]])
+    np.testing.assert_allclose(O.site_log_likelihoods(prob), want, rtol=1e-14)
+
+
+def test_all_missing_tips_give_zero():
+    rng = np.random.default_rng(9)
+    prob = W.random_problem(rng, 6, 4, 5, n_categories=2, n_intervals=3)
+    prob.tips[:] = 4
+    np.testing.assert_allclose(O.site_log_likelihoods(prob), 0.0, atol=1e-14)
+
+
+def test_single_epoch_reduction():
+    """Every interval running the same matrix equals a homogeneous model."""
+    rng = np.random.default_rng(10)
+    prob = W.random_problem(rng, 7, 4, 9, n_categories=3, n_intervals=4, n_processes=1)
+    homo = copy.deepcopy(prob)
+    homo.boundaries = np.zeros(0)
+    homo.interval_process = np.zeros(1, np.int32)
+    assert np.all(prob.interval_process == 0)
+    np.testing.assert_allclose(O.log_likelihood(prob), O.log_likelihood(homo), rtol=1e-13)
+
+
+def test_pulley_principle_single_epoch_reversible():
+    """Moving the root along its branch leaves a reversible, stationary model unchanged."""
+    rng = np.random.default_rng(11)
+    pi = rng.dirichlet(np.ones(4) * 2)
+    Q = W.gtr(rng.dirichlet(np.ones(6)), pi)
+    tips = rng.integers(0, 4, size=(3, 8))
+    # root r joins tip0 (len a) and node x (len b); x joins tip1 (c), tip2 (d)
+    a, b, c, d = 0.3, 0.2, 0.45, 0.1
+    for shift in (0.0, 0.15, -0.1):
+        aa, bb = a + shift, b - shift
+        hr = 1.0
+        hx = hr - bb
+        height = [hr - aa, hx - c, hx - d, hx, hr]
+        lo = min(height)
+        height = [h - lo for h in height]
+        prob = make_problem([4, 3, 3, 4, -1], height, [Q], [], [0], tips, pi)
+        val = O.log_likelihood(prob)
+        if shift == 0.0:
+            ref = val
+        np.testing.assert_allclose(val, ref, rtol=1e-13)
+
+
+def test_scaling_on_off_and_weight_doubling():
+    rng = np.random.default_rng(12)
+    prob = W.random_problem(rng, 9, 5, 6, n_categories=2, n_intervals=3)
+    np.testing.assert_allclose(O.site_log_likelihoods(prob, rescale=True),
+                               O.site_log_likelihoods(prob, rescale=False), rtol=1e-14)
+    dup = copy.deepcopy(prob)
+    dup.tips = np.concatenate([prob.tips, prob.tips[:, :1]], axis=1)
+    dup.weights = np.concatenate([prob.weights, prob.weights[:1]])
+    dbl = copy.deepcopy(prob)
+    dbl.weights[0] *= 2
+    np.testing.assert_allclose(O.log_likelihood(dup), O.log_likelihood(dbl), rtol=1e-14)
+
+
+def test_rescaling_survives_underflow():
+    """A 400-tip tree underflows float64 without scaling; with it logL is finite."""
+    rng = np.random.default_rng(13)
+    prob = W.random_problem(rng, 400, 4, 3, n_categories=1, n_intervals=2, root_height=6.0)
+    with np.errstate(divide="ignore"):
+        raw = O.site_log_likelihoods(prob, rescale=False)
+    scaled = O.site_log_likelihoods(prob, rescale=True)
+    assert np.all(np.isfinite(scaled))
+    assert not np.all(np.isfinite(raw)) or np.allclose(raw, scaled)
+
+
+# ---------------------------------------------------------------------------
+# Gradient
+# ---------------------------------------------------------------------------
+
+
+def test_adjoint_frechet_against_scipy_frechet():
+    rng = np.random.default_rng(14)
+    A = W.sparse_asymmetric(6, 0.5, rng) * 0.7
+    G = rng.normal(size=(6, 6))
+    E = rng.normal(size=(6, 6))
+    lhs = np.sum(G * expm_frechet(A, E, compute_expm=False))
+    rhs = np.sum(O.adjoint_frechet_exp(A, G) * E)
+    np.testing.assert_allclose(lhs, rhs, rtol=1e-12)
+
+
+def _fd_branch(prob, v, h=1e-5):
+    tau = prob.height[prob.parent[v]] - prob.height[v]
+    r = prob.branch_rate[v]
+    vals = []
+    for sgn in (1, -1):
+        p = copy.deepcopy(prob)
+        p.branch_rate[v] = r * (1 + sgn * h)
+        vals.append(O.log_likelihood(p))
+    return (vals[0] - vals[1]) / (2 * h * r * tau)
+
+
+def _fd_Q(prob, s, i, j, h=1e-5):
+    vals = []
+    step = h * max(abs(prob.Q[s][i, j]), 1e-3)
+    for sgn in (1, -1):
+        p = copy.deepcopy(prob)
+        p.Q[s] = p.Q[s].copy()
+        p.Q[s][i, j] += sgn * step
+        vals.append(O.log_likelihood(p))
+    return (vals[0] - vals[1]) / (2 * step)
+
+
+@pytest.mark.parametrize("seed,reversible", [(21, True), (22, False)])
+def test_gradient_against_central_differences(seed, reversible):
+    rng = np.random.default_rng(seed)
+    prob = W.random_problem(rng, 6, 4, 7, n_categories=2, n_intervals=3, n_processes=2,
+                            reversible=reversible, tip_height_max=0.2, branch_rate_spread=0.2,
+                            missing_frac=0.05)
+    d_branch, d_Q = O.gradient(prob)
+    for v in range(prob.parent.shape[0] - 1):
+        np.testing.assert_allclose(d_branch[v], _fd_branch(prob, v), rtol=2e-6, atol=1e-7)
+    assert d_branch[-1] == 0.0
+    for (s, i, j) in [(0, 0, 1), (0, 2, 2), (1, 3, 0), (1, 1, 3), (0, 3, 2)]:
+        np.testing.assert_allclose(d_Q[s, i, j], _fd_Q(prob, s, i, j), rtol=2e-6, atol=1e-6)
+
+
+def test_euler_identity_branch_vs_Q_gradients():
+    """Scaling every Q by c equals scaling every branch length by c."""
+    rng = np.random.default_rng(23)
+    prob = W.random_problem(rng, 7, 3, 5, n_categories=2, n_intervals=3, reversible=False,
+                            branch_rate_spread=0.3)
+    d_branch, d_Q = O.gradient(prob)
+    ell = np.array([prob.branch_rate[v] * (prob.height[prob.parent[v]] - prob.height[v])
+                    for v in range(prob.parent.shape[0] - 1)])
+    lhs = float(np.dot(ell, d_branch[:-1]))
+    rhs = float(sum(np.sum(dq * q) for dq, q in zip(d_Q, prob.Q)))
+    np.testing.assert_allclose(lhs, rhs, rtol=1e-11)
+
+
+def test_two_taxon_jc69_branch_derivative():
+    """d/dt1 log(pi_a P_ab(t1 + t2)) from the JC69 closed form."""
+    t1, t2 = 0.25, 0.4
+    tips = np.array([[0, 1, 3], [0, 2, 3]])
+    prob = make_problem([2, 2, -1], [t2 - t1, 0.0, t2], [jc69_Q()], [], [0], tips, np.full(4, 0.25))
+    d_branch, _ = O.gradient(prob)
+    t = t1 + t2
+    e = np.exp(-4 * t / 3)
+    same = (-e) / (0.25 + 0.75 * e)          # d/dt log(1/4 + 3/4 e)
+    diff = (e / 3) / (0.25 - 0.25 * e)        # d/dt log(1/4 - 1/4 e)
+    want = same + diff + same
+    np.testing.assert_allclose(d_branch[0], want, rtol=1e-12)
+    np.testing.assert_allclose(d_branch[1], want, rtol=1e-12)
