@@ -1,0 +1,189 @@
+/*
+ * epochlik — epoch-model (time-inhomogeneous) phylogenetic likelihood on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The method (Bielejec et al., "Inferring heterogeneous evolutionary processes
+ * through time"):
+ *   - S rate matrices Q_s; a change-point process with fixed boundaries picks
+ *     which Q_s is active in each time interval (Methods, "Relaxing
+ *     time-homogeneity").
+ *   - A branch that crosses boundaries gets the ordered product of per-interval
+ *     exponentials, parent-side interval first (Eq. 5-7, Fig. 1); each factor
+ *     is V_s diag(exp(lambda_s * rho_c * r_b * t_bk)) V_s^-1, reusing one
+ *     eigensystem for any rate and time (Appendix A).
+ *   - Felsenstein pruning over every node, pattern and rate category (Eq. 4),
+ *     then the root sum over pi and categories, aggregated over patterns with
+ *     integer weights (text after Eq. 4).
+ *   - Additions the paper does not contain: per-(node, pattern) power-of-two
+ *     rescaling, an adjoint (pre-order) pass giving dlogL/d(branch length) and
+ *     dlogL/dQ_s, an FP32 bulk path next to FP64, and batched evaluation.
+ *
+ * Conventions
+ *   - Times are HEIGHTS (time before the youngest tip, >= 0 or any real).
+ *     Interval k covers heights [b_k, b_{k+1}) with b_0 = -inf, b_M = +inf;
+ *     interval 0 is the youngest.  A zero-length stretch (a node exactly on a
+ *     boundary) contributes no factor.
+ *   - Nodes: tips 0..N-1, internal nodes N..2N-2 in any order; exactly one
+ *     node has parent -1 (the root).  The tree must be binary.
+ *   - Matrices passed in are row-major K x K, rows = the earlier (parent-side)
+ *     state.  Transition matrices read back are row-major too.
+ *   - The library pads K internally (4 -> 4, up to 64 -> multiple of 16);
+ *     padding is invisible at the ABI.
+ *
+ * Ownership: every host pointer is borrowed for the duration of the call and
+ * copied; the library owns all device memory it allocates.  Device pointers
+ * are never taken or returned except by epoch_device_info().  An instance is
+ * not thread-safe; distinct instances are independent.  All device work runs
+ * on the stream given in EpochConfig (NULL = the default stream); calls that
+ * return host results synchronise that stream.
+ *
+ * Errors: functions return EPOCH_OK (0), a negative error code, or a positive
+ * warning.  epoch_last_error() returns a thread-local message for the last
+ * non-zero return on the calling thread.
+ */
+#ifndef EPOCHLIK_H
+#define EPOCHLIK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EPOCH_OK 0
+#define EPOCH_ERR_ARG (-1)       /* invalid argument (shape, range, non-finite value) */
+#define EPOCH_ERR_STATE (-2)     /* call-order violation (a required set_/update_ step missing) */
+#define EPOCH_ERR_OOM (-3)       /* device allocation failed */
+#define EPOCH_ERR_HIP (-4)       /* a HIP runtime call failed */
+#define EPOCH_ERR_NUMERIC (-5)   /* non-finite likelihood (e.g. zero probability data) */
+#define EPOCH_WARN_EIGEN_RESIDUAL 1 /* eigensystem reconstruction residual above 1e-8 (relative) */
+
+#define EPOCH_FP32 1
+#define EPOCH_FP64 2
+
+#define EPOCH_GRAD_BRANCH 0x1u   /* keep what log_likelihood_gradient needs for dlogL/dl_b */
+#define EPOCH_GRAD_Q 0x2u        /* ... and for dlogL/dQ_s */
+
+#define EPOCH_KERNEL_AUTO 0      /* pick the specialised kernels where they exist */
+#define EPOCH_KERNEL_GENERIC 1   /* force the generic any-K kernels (reference GPU path) */
+
+typedef struct EpochInstance EpochInstance;
+
+typedef struct EpochConfig {
+  int32_t n_tips;          /* N >= 2 */
+  int32_t n_patterns;      /* P >= 1 (unique site patterns) */
+  int32_t n_states;        /* K, 2 <= K <= 64 */
+  int32_t n_categories;    /* C, 1 <= C <= 8 (among-site rate categories) */
+  int32_t n_processes;     /* S >= 1 (distinct rate matrices) */
+  int32_t max_intervals;   /* upper bound on M passed to set_tree_epochs, >= 1 */
+  int32_t precision;       /* EPOCH_FP32 or EPOCH_FP64: arithmetic of P matrices and partials */
+  uint32_t flags;          /* EPOCH_GRAD_* */
+  int32_t kernel_path;     /* EPOCH_KERNEL_AUTO or EPOCH_KERNEL_GENERIC */
+  int32_t reserved;        /* must be 0 */
+  void* stream;            /* hipStream_t to run on, or NULL for the default stream */
+} EpochConfig;
+
+/* Message for the last non-zero return on this thread ("" if none). */
+const char* epoch_last_error(void);
+
+/* Library version string. */
+const char* epoch_version(void);
+
+/* Create an instance: validates cfg (before any HIP call), then allocates the
+ * device buffers whose size depends only on cfg.  *out receives the handle. */
+int epoch_create(const EpochConfig* cfg, EpochInstance** out);
+
+/* Free every device buffer of the instance (NULL is accepted). */
+int epoch_destroy(EpochInstance* inst);
+
+/* Tip data (text after Eq. 4: tips are 0/1 indicators of the observed state).
+ * states: host [N][P] row-major int32; value in [0, K) = observed state,
+ * value K = missing (all-ones vector).  Any other value -> EPOCH_ERR_ARG. */
+int epoch_set_tip_states(EpochInstance* inst, const int32_t* states);
+
+/* Pattern weights w_p: host [P], finite and >= 0. */
+int epoch_set_pattern_weights(EpochInstance* inst, const double* weights);
+
+/* Among-site rate categories (text after Eq. 4): rates rho_c > 0 and weights
+ * w_c >= 0 summing to 1 (within 1e-9), host [C] each. */
+int epoch_set_categories(EpochInstance* inst, const double* rates, const double* weights);
+
+/* Root distribution pi (text after Eq. 4: L = sum_i pi_i L_root(i)): host [K],
+ * entries >= 0, summing to 1 within 1e-9. */
+int epoch_set_root_frequencies(EpochInstance* inst, const double* pi);
+
+/* Eigensystem of process s (Appendix A: one decomposition reused for every
+ * rate and time): Q_s = V diag(lambda) V^-1 in real form.
+ *   V, Vinv: host K x K row-major.  lambda_re, lambda_im: host [K].
+ *   lambda_im may be NULL (all eigenvalues real).  A complex pair occupies two
+ *   consecutive columns j, j+1 with lambda_im[j] = b > 0, lambda_im[j+1] = -b,
+ *   lambda_re[j] = lambda_re[j+1] = a; V[:, j] and V[:, j+1] hold the real and
+ *   imaginary parts of the eigenvector of a + ib, so that Q V = V B with the
+ *   2x2 block B = [[a, b], [-b, a]].
+ *   Q: host K x K or NULL.  If given, an FP64 device kernel measures
+ *   max|V B V^-1 - Q| / max|Q| and max|V V^-1 - I|; the larger is written to
+ *   *residual_out (if not NULL) and EPOCH_WARN_EIGEN_RESIDUAL is returned when
+ *   it exceeds 1e-8.  Invalidates transition matrices. */
+int set_epoch_eigensystems(EpochInstance* inst, int32_t s, const double* V, const double* Vinv,
+                           const double* lambda_re, const double* lambda_im, const double* Q,
+                           double* residual_out);
+
+/* Tree and epoch structure (Methods, change-point process; Coarse-grain
+ * implementation: per-branch times spent in each interval).
+ *   parent: host [2N-1], -1 at the root; height: host [2N-1] finite,
+ *   height[parent[v]] >= height[v]; branch_rate: host [2N-1] > 0 (entry v is
+ *   the rate r_v of the branch above v; the root entry is ignored) or NULL = 1.
+ *   n_intervals M in [1, max_intervals]; boundaries: host [M-1] strictly
+ *   ascending finite heights (NULL when M = 1); interval_process: host [M],
+ *   values in [0, S).
+ * The host planner splits every branch into its per-interval segments and
+ * builds the traversal schedules.  Invalidates everything downstream. */
+int set_tree_epochs(EpochInstance* inst, const int32_t* parent, const double* height,
+                    const double* branch_rate, int32_t n_intervals, const double* boundaries,
+                    const int32_t* interval_process);
+
+/* Transition matrices of every branch and category (Eq. 3, 6, 7), plus their
+ * derivatives with respect to the branch length when EPOCH_GRAD_BRANCH is set.
+ * Requires all eigensystems, categories and the tree. */
+int update_transition_matrices(EpochInstance* inst);
+
+/* Post-order partial likelihoods with rescaling (Eq. 4).  Requires
+ * update_transition_matrices, tip states. */
+int update_partials(EpochInstance* inst);
+
+/* logL = sum_p w_p log L_p (text after Eq. 4), reduced in FP64.
+ *   logL: host double (required); site_logL: host [P] or NULL.
+ * Requires update_partials, pattern weights, root frequencies.  Returns
+ * EPOCH_ERR_NUMERIC if logL is not finite. */
+int root_log_likelihood(EpochInstance* inst, double* logL, double* site_logL);
+
+/* Gradient of logL (an addition to the paper):
+ *   d_branch: host [2N-1] or NULL: entry v = dlogL/dl_v for l_v = r_v * tau_v,
+ *     the per-interval fractions of the branch held fixed; root entry 0.
+ *     Needs EPOCH_GRAD_BRANCH.
+ *   d_Q: host [S][K][K] or NULL: dlogL/dQ_s entrywise, for the Q_s whose
+ *     eigensystems were set.  Needs EPOCH_GRAD_Q.
+ * Requires root_log_likelihood for the current state. */
+int log_likelihood_gradient(EpochInstance* inst, double* d_branch, double* d_Q);
+
+/* Read back the transition matrices: host [2N-1][C][K][K] doubles (row-major,
+ * entry v = branch above node v; root block left as zeros).  Requires
+ * update_transition_matrices. */
+int epoch_get_transition_matrices(EpochInstance* inst, double* out);
+
+/* Host planner only (no device work, usable without a GPU): the per-interval
+ * segments of every branch, parent side first.
+ *   seg_offset: host [2N] out (CSR offsets indexed by child node);
+ *   seg_process, seg_time: host [capacity] out; *n_segments receives the total.
+ * Returns EPOCH_ERR_ARG if capacity is too small (n_segments still set). */
+int epoch_plan_segments(int32_t n_tips, const int32_t* parent, const double* height,
+                        int32_t n_intervals, const double* boundaries,
+                        const int32_t* interval_process, int32_t n_processes,
+                        int32_t capacity, int32_t* seg_offset, int32_t* seg_process,
+                        double* seg_time, int32_t* n_segments);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EPOCHLIK_H */

@@ -1,0 +1,155 @@
+"""ctypes binding of libepochlik.so: argument marshalling only.
+
+Every step of the likelihood runs inside the HIP library; this module only
+converts numpy arrays to pointers and error codes to exceptions.  If the
+library is not built, importing the binding raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libepochlik.so")
+
+EPOCH_OK = 0
+EPOCH_ERR_ARG = -1
+EPOCH_ERR_STATE = -2
+EPOCH_ERR_OOM = -3
+EPOCH_ERR_HIP = -4
+EPOCH_ERR_NUMERIC = -5
+EPOCH_WARN_EIGEN_RESIDUAL = 1
+EPOCH_FP32 = 1
+EPOCH_FP64 = 2
+EPOCH_GRAD_BRANCH = 0x1
+EPOCH_GRAD_Q = 0x2
+EPOCH_KERNEL_AUTO = 0
+EPOCH_KERNEL_GENERIC = 1
+
+# Every symbol include/epochlik.h declares.
+EXPORTED = [
+    "epoch_last_error", "epoch_version", "epoch_create", "epoch_destroy", "epoch_set_tip_states",
+    "epoch_set_pattern_weights", "epoch_set_categories", "epoch_set_root_frequencies",
+    "set_epoch_eigensystems", "set_tree_epochs", "update_transition_matrices", "update_partials",
+    "root_log_likelihood", "log_likelihood_gradient", "epoch_get_transition_matrices",
+    "epoch_plan_segments",
+]
+
+
+class EpochConfig(ctypes.Structure):
+    _fields_ = [
+        ("n_tips", ctypes.c_int32),
+        ("n_patterns", ctypes.c_int32),
+        ("n_states", ctypes.c_int32),
+        ("n_categories", ctypes.c_int32),
+        ("n_processes", ctypes.c_int32),
+        ("max_intervals", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+        ("kernel_path", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class EpochError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"[{code}] {message}")
+        self.code = code
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1309_3075_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    i32, u32, dbl = ctypes.c_int32, ctypes.c_uint32, ctypes.c_double
+    ip, dp = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "epoch_last_error": (ctypes.c_char_p, []),
+        "epoch_version": (ctypes.c_char_p, []),
+        "epoch_create": (i32, [ctypes.POINTER(EpochConfig), ctypes.POINTER(P)]),
+        "epoch_destroy": (i32, [P]),
+        "epoch_set_tip_states": (i32, [P, ip]),
+        "epoch_set_pattern_weights": (i32, [P, dp]),
+        "epoch_set_categories": (i32, [P, dp, dp]),
+        "epoch_set_root_frequencies": (i32, [P, dp]),
+        "set_epoch_eigensystems": (i32, [P, i32, dp, dp, dp, dp, dp, dp]),
+        "set_tree_epochs": (i32, [P, ip, dp, dp, i32, dp, ip]),
+        "update_transition_matrices": (i32, [P]),
+        "update_partials": (i32, [P]),
+        "root_log_likelihood": (i32, [P, dp, dp]),
+        "log_likelihood_gradient": (i32, [P, dp, dp]),
+        "epoch_get_transition_matrices": (i32, [P, dp]),
+        "epoch_plan_segments": (i32, [i32, ip, dp, i32, dp, ip, i32, i32, ip, ip, dp, ip]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _dp(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None and a.shape != tuple(shape):
+        a = a.reshape(shape)
+    return a
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def check(code: int, allow_warning: bool = True) -> int:
+    if code == EPOCH_OK or (allow_warning and code > 0):
+        return code
+    msg = load().epoch_last_error().decode()
+    raise EpochError(code, msg)
+
+
+def last_error() -> str:
+    return load().epoch_last_error().decode()
+
+
+def plan_segments(parent, height, boundaries, interval_process, n_processes):
+    """Host planner segmentation (no GPU needed): (offsets[2N], process[], time[])."""
+    lib = load()
+    parent = _i32(parent)
+    height = _f64(height)
+    n_nodes = parent.shape[0]
+    n_tips = (n_nodes + 1) // 2
+    b = _f64(boundaries) if len(boundaries) else None
+    phi = _i32(interval_process)
+    off = np.zeros(n_nodes + 1, np.int32)
+    nseg = ctypes.c_int32(0)
+    cap = n_nodes * (len(phi) + 1)
+    proc = np.zeros(cap, np.int32)
+    tim = np.zeros(cap, np.float64)
+    check(lib.epoch_plan_segments(n_tips, _ip(parent), _dp(height), len(phi), _dp(b), _ip(phi),
+                                  n_processes, cap, _ip(off), _ip(proc), _dp(tim), ctypes.byref(nseg)))
+    n = nseg.value
+    return off, proc[:n].copy(), tim[:n].copy()

@@ -1,0 +1,541 @@
+// C ABI of the epoch-model likelihood library: instance lifecycle, argument
+// validation (always before any HIP call), host->device uploads and the
+// dispatch of the kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "instance.h"
+#include "fastpath.h"
+#include "device_common.h"
+
+using namespace epochlik;
+
+namespace epochlik {
+
+thread_local std::string g_error;
+
+int set_error(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return code;
+}
+
+int hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return EPOCH_OK;
+  return set_error(EPOCH_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int ensure(DevBuf& b, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (b.ptr && b.bytes >= bytes) return EPOCH_OK;
+  if (b.ptr) {
+    (void)hipFree(b.ptr);
+    b.ptr = nullptr;
+    b.bytes = 0;
+  }
+  hipError_t e = hipMalloc(&b.ptr, bytes);
+  if (e != hipSuccess) {
+    b.ptr = nullptr;
+    (void)hipGetLastError();
+    return set_error(EPOCH_ERR_OOM, "hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+  }
+  b.bytes = bytes;
+  return EPOCH_OK;
+}
+
+}  // namespace epochlik
+
+namespace {
+
+void release(DevBuf& b) {
+  if (b.ptr) (void)hipFree(b.ptr);
+  b.ptr = nullptr;
+  b.bytes = 0;
+}
+
+int padded_states(int K) {
+  if (K <= 4) return 4;
+  if (K <= 8) return 8;
+  return (K + 15) / 16 * 16;
+}
+
+#define EPOCH_TRY(expr)          \
+  do {                           \
+    int _rc = (expr);            \
+    if (_rc != EPOCH_OK) return _rc; \
+  } while (0)
+
+int upload(EpochInstance* in, void* dst, const void* src, size_t bytes) {
+  if (bytes == 0) return EPOCH_OK;
+  EPOCH_TRY(hip_check(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, in->stream), "upload"));
+  return hip_check(hipStreamSynchronize(in->stream), "upload sync");
+}
+
+int download(EpochInstance* in, void* dst, const void* src, size_t bytes) {
+  if (bytes == 0) return EPOCH_OK;
+  EPOCH_TRY(hip_check(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, in->stream), "download"));
+  return hip_check(hipStreamSynchronize(in->stream), "download sync");
+}
+
+bool all_finite(const double* x, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(x[i])) return false;
+  return true;
+}
+
+int choose_chunks(EpochInstance* in) {
+  int q = 4;
+  while (q < in->Kp) q <<= 1;
+  const int TP = 256 / q;
+  const long tiles = (in->P + TP - 1) / TP;
+  const size_t per_chunk = (size_t)in->n_nodes * in->C * in->Kp * in->Kp * sizeof(double);
+  long cap = (long)std::max<size_t>(1, (size_t)(256u << 20) / std::max<size_t>(per_chunk, 1));
+  long n = std::min<long>({tiles, 64L, cap});
+  return (int)std::max<long>(1, n);
+}
+
+void invalidate_downstream(EpochInstance* in) {
+  in->P_valid = false;
+  in->partials_valid = false;
+  in->logL_valid = false;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* epoch_last_error(void) { return g_error.c_str(); }
+
+const char* epoch_version(void) { return "epochlik 0.1.0 (gfx950)"; }
+
+int epoch_create(const EpochConfig* cfg, EpochInstance** out) {
+  g_error.clear();
+  if (!cfg || !out) return set_error(EPOCH_ERR_ARG, "cfg and out must not be NULL");
+  *out = nullptr;
+  const EpochConfig& c = *cfg;
+  if (c.n_tips < 2) return set_error(EPOCH_ERR_ARG, "n_tips must be >= 2 (got %d)", c.n_tips);
+  if (c.n_tips > (1 << 24)) return set_error(EPOCH_ERR_ARG, "n_tips too large (%d)", c.n_tips);
+  if (c.n_patterns < 1) return set_error(EPOCH_ERR_ARG, "n_patterns must be >= 1 (got %d)", c.n_patterns);
+  if (c.n_states < 2 || c.n_states > 64)
+    return set_error(EPOCH_ERR_ARG, "n_states must be in [2, 64] (got %d)", c.n_states);
+  if (c.n_categories < 1 || c.n_categories > kMaxCategories)
+    return set_error(EPOCH_ERR_ARG, "n_categories must be in [1, 8] (got %d)", c.n_categories);
+  if (c.n_processes < 1) return set_error(EPOCH_ERR_ARG, "n_processes must be >= 1");
+  if (c.max_intervals < 1) return set_error(EPOCH_ERR_ARG, "max_intervals must be >= 1");
+  if (c.precision != EPOCH_FP32 && c.precision != EPOCH_FP64)
+    return set_error(EPOCH_ERR_ARG, "precision must be EPOCH_FP32 or EPOCH_FP64");
+  if (c.flags & ~(EPOCH_GRAD_BRANCH | EPOCH_GRAD_Q)) return set_error(EPOCH_ERR_ARG, "unknown flags");
+  if (c.kernel_path != EPOCH_KERNEL_AUTO && c.kernel_path != EPOCH_KERNEL_GENERIC)
+    return set_error(EPOCH_ERR_ARG, "unknown kernel_path");
+  if (c.reserved != 0) return set_error(EPOCH_ERR_ARG, "reserved must be 0");
+  const size_t N = c.n_tips, P = c.n_patterns;
+  if ((N - 1) * P > ((size_t)1 << 40)) return set_error(EPOCH_ERR_ARG, "problem too large");
+
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    (void)hipGetLastError();
+    return set_error(EPOCH_ERR_HIP, "no HIP device available");
+  }
+  auto* in = new EpochInstance();
+  in->cfg = c;
+  in->N = c.n_tips;
+  in->P = c.n_patterns;
+  in->K = c.n_states;
+  in->Kp = padded_states(c.n_states);
+  in->C = c.n_categories;
+  in->S = c.n_processes;
+  in->n_nodes = 2 * c.n_tips - 1;
+  in->n_int = c.n_tips - 1;
+  in->fp64 = c.precision == EPOCH_FP64;
+  in->real_size = in->fp64 ? 8 : 4;
+  in->stream = static_cast<hipStream_t>(c.stream);
+  (void)hipGetDevice(&in->device);
+  const size_t Kp = in->Kp, KK = Kp * Kp, S = in->S, C = in->C, n = in->n_nodes, R = in->real_size;
+  const bool grad = (c.flags & (EPOCH_GRAD_BRANCH | EPOCH_GRAD_Q)) != 0;
+  in->h_V.assign(S * KK, 0.0);
+  in->h_Vinv.assign(S * KK, 0.0);
+  in->h_lre.assign(S * Kp, 0.0);
+  in->h_lim.assign(S * Kp, 0.0);
+  in->have_eig.assign(S, 0);
+  in->n_chunks = choose_chunks(in);
+  int rc = EPOCH_OK;
+  auto A = [&](DevBuf& b, size_t bytes) {
+    if (rc == EPOCH_OK) rc = ensure(b, bytes);
+  };
+  A(in->eigT, (2 * S * KK + 2 * S * Kp) * R);
+  A(in->eig64, (2 * S * KK + 2 * S * Kp) * sizeof(double));
+  A(in->check, (KK + 8) * sizeof(double));
+  A(in->tips, N * P);
+  A(in->weights, P * sizeof(double));
+  A(in->weightsT, P * R);
+  A(in->pi, Kp * sizeof(double));
+  A(in->cat, 2 * kMaxCategories * sizeof(double));
+  A(in->Pm, n * C * KK * R);
+  if (grad) A(in->dPm, n * C * KK * R);
+  A(in->partials, (N - 1) * C * P * Kp * R);
+  A(in->scales, (N - 1) * P * sizeof(int32_t));
+  if (grad) A(in->pre, (N - 1) * C * P * Kp * R);
+  A(in->site, P * sizeof(double));
+  A(in->blocksum, ((P + 255) / 256 + 1) * sizeof(double));
+  A(in->result, 8 * sizeof(double));
+  if (grad) {
+    A(in->Gpart, (size_t)in->n_chunks * n * C * KK * sizeof(double));
+    A(in->G, n * C * KK * sizeof(double));
+    A(in->dbranch, n * sizeof(double));
+  }
+  if (c.flags & EPOCH_GRAD_Q) A(in->dQ, S * KK * sizeof(double));
+  if (rc == EPOCH_OK) rc = fastpath_init(in);
+  if (rc != EPOCH_OK) {
+    std::string keep = g_error;
+    epoch_destroy(in);
+    g_error = keep;
+    return rc;
+  }
+  // zero the eigen buffers so padding is well defined
+  rc = hip_check(hipMemsetAsync(in->eigT.ptr, 0, in->eigT.bytes, in->stream), "memset");
+  if (rc == EPOCH_OK) rc = hip_check(hipMemsetAsync(in->eig64.ptr, 0, in->eig64.bytes, in->stream), "memset");
+  if (rc == EPOCH_OK) rc = hip_check(hipStreamSynchronize(in->stream), "create sync");
+  if (rc != EPOCH_OK) {
+    std::string keep = g_error;
+    epoch_destroy(in);
+    g_error = keep;
+    return rc;
+  }
+  *out = in;
+  return EPOCH_OK;
+}
+
+int epoch_destroy(EpochInstance* in) {
+  if (!in) return EPOCH_OK;
+  fastpath_release(in);
+  for (DevBuf* b : {&in->eigT, &in->eig64, &in->check, &in->tips, &in->weights, &in->weightsT, &in->pi,
+                    &in->cat, &in->tree_i, &in->tree_d, &in->Pm, &in->dPm, &in->partials, &in->scales,
+                    &in->pre, &in->site, &in->blocksum, &in->result, &in->Gpart, &in->G, &in->dbranch,
+                    &in->qseg, &in->qscratch, &in->dQ, &in->seglist})
+    release(*b);
+  delete in;
+  return EPOCH_OK;
+}
+
+int epoch_set_tip_states(EpochInstance* in, const int32_t* states) {
+  if (!in || !states) return set_error(EPOCH_ERR_ARG, "instance and states must not be NULL");
+  const size_t n = (size_t)in->N * in->P;
+  std::vector<uint8_t> h(n);
+  for (size_t k = 0; k < n; ++k) {
+    const int32_t s = states[k];
+    if (s < 0 || s > in->K)
+      return set_error(EPOCH_ERR_ARG, "tip state %d at (%zu, %zu) outside [0, %d]", s, k / in->P,
+                       k % in->P, in->K);
+    h[k] = (uint8_t)s;
+  }
+  EPOCH_TRY(upload(in, in->tips.ptr, h.data(), n));
+  in->have_tips = true;
+  in->partials_valid = false;
+  in->logL_valid = false;
+  return fastpath_tips_changed(in);
+}
+
+int epoch_set_pattern_weights(EpochInstance* in, const double* w) {
+  if (!in || !w) return set_error(EPOCH_ERR_ARG, "instance and weights must not be NULL");
+  for (int p = 0; p < in->P; ++p)
+    if (!std::isfinite(w[p]) || w[p] < 0) return set_error(EPOCH_ERR_ARG, "weight %d is negative or not finite", p);
+  EPOCH_TRY(upload(in, in->weights.ptr, w, (size_t)in->P * sizeof(double)));
+  if (in->fp64) {
+    EPOCH_TRY(upload(in, in->weightsT.ptr, w, (size_t)in->P * sizeof(double)));
+  } else {
+    std::vector<float> f(w, w + in->P);
+    EPOCH_TRY(upload(in, in->weightsT.ptr, f.data(), f.size() * sizeof(float)));
+  }
+  in->have_weights = true;
+  in->logL_valid = false;
+  return EPOCH_OK;
+}
+
+int epoch_set_categories(EpochInstance* in, const double* rates, const double* weights) {
+  if (!in || !rates || !weights) return set_error(EPOCH_ERR_ARG, "NULL argument");
+  double sum = 0;
+  for (int c = 0; c < in->C; ++c) {
+    if (!std::isfinite(rates[c]) || !(rates[c] > 0)) return set_error(EPOCH_ERR_ARG, "category rate %d must be > 0", c);
+    if (!std::isfinite(weights[c]) || weights[c] < 0) return set_error(EPOCH_ERR_ARG, "category weight %d must be >= 0", c);
+    sum += weights[c];
+  }
+  if (std::fabs(sum - 1.0) > 1e-9) return set_error(EPOCH_ERR_ARG, "category weights sum to %.17g, not 1", sum);
+  double h[2 * kMaxCategories] = {0};
+  for (int c = 0; c < in->C; ++c) {
+    h[c] = rates[c];
+    h[kMaxCategories + c] = weights[c];
+    in->h_cat_rates[c] = rates[c];
+    in->h_cat_weights[c] = weights[c];
+  }
+  EPOCH_TRY(upload(in, in->cat.ptr, h, sizeof(h)));
+  in->have_cats = true;
+  invalidate_downstream(in);
+  return EPOCH_OK;
+}
+
+int epoch_set_root_frequencies(EpochInstance* in, const double* pi) {
+  if (!in || !pi) return set_error(EPOCH_ERR_ARG, "NULL argument");
+  double sum = 0;
+  std::vector<double> h(in->Kp, 0.0);
+  for (int i = 0; i < in->K; ++i) {
+    if (!std::isfinite(pi[i]) || pi[i] < 0) return set_error(EPOCH_ERR_ARG, "pi[%d] must be >= 0", i);
+    sum += pi[i];
+    h[i] = pi[i];
+  }
+  if (std::fabs(sum - 1.0) > 1e-9) return set_error(EPOCH_ERR_ARG, "pi sums to %.17g, not 1", sum);
+  EPOCH_TRY(upload(in, in->pi.ptr, h.data(), h.size() * sizeof(double)));
+  in->have_pi = true;
+  in->logL_valid = false;
+  return EPOCH_OK;
+}
+
+int set_epoch_eigensystems(EpochInstance* in, int32_t s, const double* V, const double* Vinv,
+                           const double* lambda_re, const double* lambda_im, const double* Q,
+                           double* residual_out) {
+  if (!in || !V || !Vinv || !lambda_re) return set_error(EPOCH_ERR_ARG, "NULL argument");
+  if (s < 0 || s >= in->S) return set_error(EPOCH_ERR_ARG, "process index %d outside [0, %d)", s, in->S);
+  const int K = in->K, Kp = in->Kp;
+  if (!all_finite(V, (size_t)K * K) || !all_finite(Vinv, (size_t)K * K) || !all_finite(lambda_re, K))
+    return set_error(EPOCH_ERR_ARG, "eigensystem %d has non-finite entries", s);
+  if (lambda_im) {
+    if (!all_finite(lambda_im, K)) return set_error(EPOCH_ERR_ARG, "lambda_im has non-finite entries");
+    for (int j = 0; j < K; ++j) {
+      if (lambda_im[j] > 0) {
+        if (j + 1 >= K || lambda_im[j + 1] != -lambda_im[j] || lambda_re[j + 1] != lambda_re[j])
+          return set_error(EPOCH_ERR_ARG, "complex pair at column %d is not followed by its conjugate", j);
+        ++j;
+      } else if (lambda_im[j] < 0) {
+        return set_error(EPOCH_ERR_ARG, "negative imaginary part at column %d without its pair", j);
+      }
+    }
+  }
+  if (Q && !all_finite(Q, (size_t)K * K)) return set_error(EPOCH_ERR_ARG, "Q has non-finite entries");
+  const size_t KK = (size_t)Kp * Kp, S = in->S;
+  double* hV = in->h_V.data() + s * KK;
+  double* hVi = in->h_Vinv.data() + s * KK;
+  double* hr = in->h_lre.data() + (size_t)s * Kp;
+  double* hi = in->h_lim.data() + (size_t)s * Kp;
+  std::fill(hV, hV + KK, 0.0);
+  std::fill(hVi, hVi + KK, 0.0);
+  std::fill(hr, hr + Kp, 0.0);
+  std::fill(hi, hi + Kp, 0.0);
+  for (int i = 0; i < K; ++i) {
+    for (int j = 0; j < K; ++j) {
+      hV[i * Kp + j] = V[i * K + j];
+      hVi[i * Kp + j] = Vinv[i * K + j];
+    }
+    hr[i] = lambda_re[i];
+    hi[i] = lambda_im ? lambda_im[i] : 0.0;
+  }
+  in->any_complex = false;
+  for (double x : in->h_lim)
+    if (x != 0.0) in->any_complex = true;
+  // upload this process's slices in double and in the compute type
+  auto up_slice = [&](DevBuf& buf, size_t elem, bool as_float) -> int {
+    char* base = static_cast<char*>(buf.ptr);
+    struct Part {
+      size_t off, count;
+      const double* src;
+    } parts[4] = {{s * KK, KK, hV}, {S * KK + s * KK, KK, hVi}, {2 * S * KK + (size_t)s * Kp, (size_t)Kp, hr},
+                  {2 * S * KK + S * Kp + (size_t)s * Kp, (size_t)Kp, hi}};
+    for (auto& pt : parts) {
+      if (as_float) {
+        std::vector<float> f(pt.src, pt.src + pt.count);
+        EPOCH_TRY(upload(in, base + pt.off * elem, f.data(), pt.count * sizeof(float)));
+      } else {
+        EPOCH_TRY(upload(in, base + pt.off * elem, pt.src, pt.count * sizeof(double)));
+      }
+    }
+    return EPOCH_OK;
+  };
+  EPOCH_TRY(up_slice(in->eig64, sizeof(double), false));
+  EPOCH_TRY(up_slice(in->eigT, in->real_size, !in->fp64));
+  in->have_eig[s] = 1;
+  invalidate_downstream(in);
+  int ret = EPOCH_OK;
+  if (Q) {
+    double* dQ = static_cast<double*>(in->check.ptr);
+    double* dout = dQ + (size_t)Kp * Kp;
+    EPOCH_TRY(upload(in, dQ, Q, (size_t)K * K * sizeof(double)));
+    EPOCH_TRY(launch_eigen_check(in, s, dQ, dout));
+    double r[3];
+    EPOCH_TRY(download(in, r, dout, sizeof(r)));
+    const double res = std::max(r[2] > 0 ? r[0] / r[2] : r[0], r[1]);
+    if (residual_out) *residual_out = res;
+    if (!(res <= 1e-8)) {
+      set_error(EPOCH_WARN_EIGEN_RESIDUAL, "eigensystem %d reconstruction residual %.3g", s, res);
+      ret = EPOCH_WARN_EIGEN_RESIDUAL;
+    }
+  } else if (residual_out) {
+    *residual_out = NAN;
+  }
+  return ret;
+}
+
+int set_tree_epochs(EpochInstance* in, const int32_t* parent, const double* height, const double* branch_rate,
+                    int32_t n_intervals, const double* boundaries, const int32_t* interval_process) {
+  if (!in) return set_error(EPOCH_ERR_ARG, "NULL instance");
+  if (n_intervals > in->cfg.max_intervals)
+    return set_error(EPOCH_ERR_ARG, "n_intervals %d exceeds max_intervals %d", n_intervals, in->cfg.max_intervals);
+  TreePlan plan;
+  std::string err;
+  if (plan_tree(in->N, parent, height, branch_rate, n_intervals, boundaries, interval_process, in->S, plan, err))
+    return set_error(EPOCH_ERR_ARG, "set_tree_epochs: %s", err.c_str());
+  const size_t n = in->n_nodes, nseg = plan.seg_process.size(), Nm1 = in->N - 1;
+  // int32 block: parent, left, right [n], level_nodes [N-1], seg_offset [n+1], seg_process [nseg], walk [N-1]
+  std::vector<int32_t> hi;
+  hi.reserve(3 * n + 2 * Nm1 + n + 1 + nseg);
+  hi.insert(hi.end(), plan.parent.begin(), plan.parent.end());
+  hi.insert(hi.end(), plan.left.begin(), plan.left.end());
+  hi.insert(hi.end(), plan.right.begin(), plan.right.end());
+  hi.insert(hi.end(), plan.level_nodes.begin(), plan.level_nodes.end());
+  hi.insert(hi.end(), plan.seg_offset.begin(), plan.seg_offset.end());
+  hi.insert(hi.end(), plan.seg_process.begin(), plan.seg_process.end());
+  hi.insert(hi.end(), plan.walk.begin(), plan.walk.end());
+  std::vector<double> hd;
+  hd.reserve(2 * n + 2 * nseg);
+  hd.insert(hd.end(), plan.rate.begin(), plan.rate.end());
+  hd.insert(hd.end(), plan.tau.begin(), plan.tau.end());
+  hd.insert(hd.end(), plan.seg_time.begin(), plan.seg_time.end());
+  hd.insert(hd.end(), plan.seg_frac.begin(), plan.seg_frac.end());
+  EPOCH_TRY(ensure(in->tree_i, hi.size() * sizeof(int32_t)));
+  EPOCH_TRY(ensure(in->tree_d, hd.size() * sizeof(double)));
+  EPOCH_TRY(upload(in, in->tree_i.ptr, hi.data(), hi.size() * sizeof(int32_t)));
+  EPOCH_TRY(upload(in, in->tree_d.ptr, hd.data(), hd.size() * sizeof(double)));
+  int32_t* bi = static_cast<int32_t*>(in->tree_i.ptr);
+  in->d_parent = bi;
+  in->d_left = bi + n;
+  in->d_right = bi + 2 * n;
+  in->d_level_nodes = bi + 3 * n;
+  in->d_seg_offset = bi + 3 * n + Nm1;
+  in->d_seg_process = in->d_seg_offset + n + 1;
+  in->d_walk = in->d_seg_process + nseg;
+  double* bd = static_cast<double*>(in->tree_d.ptr);
+  in->d_rate = bd;
+  in->d_tau = bd + n;
+  in->d_seg_time = bd + 2 * n;
+  in->d_seg_frac = bd + 2 * n + nseg;
+  if (in->cfg.flags & EPOCH_GRAD_Q) {
+    const size_t KK = (size_t)in->Kp * in->Kp, C = in->C;
+    EPOCH_TRY(ensure(in->qscratch, std::max<size_t>(1, nseg) * C * KK * in->real_size));
+    EPOCH_TRY(ensure(in->qseg, (nseg * C * KK * 2 + (size_t)in->S * KK * 2) * sizeof(double)));
+    std::vector<int32_t> off(in->S + 1, 0), items;
+    for (size_t g = 0; g < nseg; ++g) off[plan.seg_process[g] + 1] += (int32_t)C;
+    for (int s = 0; s < in->S; ++s) off[s + 1] += off[s];
+    items.assign(off[in->S], 0);
+    std::vector<int32_t> fill(off.begin(), off.end());
+    for (size_t g = 0; g < nseg; ++g)
+      for (size_t c = 0; c < C; ++c) items[fill[plan.seg_process[g]]++] = (int32_t)(g * C + c);
+    std::vector<int32_t> all(off);
+    all.insert(all.end(), items.begin(), items.end());
+    EPOCH_TRY(ensure(in->seglist, all.size() * sizeof(int32_t)));
+    EPOCH_TRY(upload(in, in->seglist.ptr, all.data(), all.size() * sizeof(int32_t)));
+  }
+  in->plan = std::move(plan);
+  in->have_tree = true;
+  invalidate_downstream(in);
+  return fastpath_tree_changed(in);
+}
+
+int update_transition_matrices(EpochInstance* in) {
+  if (!in) return set_error(EPOCH_ERR_ARG, "NULL instance");
+  if (!in->have_tree) return set_error(EPOCH_ERR_STATE, "set_tree_epochs has not been called");
+  if (!in->have_cats) return set_error(EPOCH_ERR_STATE, "epoch_set_categories has not been called");
+  for (int s = 0; s < in->S; ++s)
+    if (!in->have_eig[s]) return set_error(EPOCH_ERR_STATE, "eigensystem %d has not been set", s);
+  EPOCH_TRY(fastpath_pstage(in));
+  in->P_valid = true;
+  in->partials_valid = false;
+  in->logL_valid = false;
+  return EPOCH_OK;
+}
+
+int update_partials(EpochInstance* in) {
+  if (!in) return set_error(EPOCH_ERR_ARG, "NULL instance");
+  if (!in->P_valid) return set_error(EPOCH_ERR_STATE, "update_transition_matrices has not been called");
+  if (!in->have_tips) return set_error(EPOCH_ERR_STATE, "epoch_set_tip_states has not been called");
+  EPOCH_TRY(fastpath_post(in));
+  in->partials_valid = true;
+  in->logL_valid = false;
+  return EPOCH_OK;
+}
+
+int root_log_likelihood(EpochInstance* in, double* logL, double* site_logL) {
+  if (!in || !logL) return set_error(EPOCH_ERR_ARG, "instance and logL must not be NULL");
+  if (!in->partials_valid) return set_error(EPOCH_ERR_STATE, "update_partials has not been called");
+  if (!in->have_weights) return set_error(EPOCH_ERR_STATE, "epoch_set_pattern_weights has not been called");
+  if (!in->have_pi) return set_error(EPOCH_ERR_STATE, "epoch_set_root_frequencies has not been called");
+  EPOCH_TRY(fastpath_root(in));
+  EPOCH_TRY(download(in, logL, in->result.ptr, sizeof(double)));
+  if (site_logL) EPOCH_TRY(download(in, site_logL, in->site.ptr, (size_t)in->P * sizeof(double)));
+  if (!std::isfinite(*logL)) {
+    in->logL_valid = false;
+    return set_error(EPOCH_ERR_NUMERIC, "log-likelihood is not finite (%g)", *logL);
+  }
+  in->logL_valid = true;
+  return EPOCH_OK;
+}
+
+int log_likelihood_gradient(EpochInstance* in, double* d_branch, double* d_Q) {
+  if (!in) return set_error(EPOCH_ERR_ARG, "NULL instance");
+  if (d_branch && !(in->cfg.flags & EPOCH_GRAD_BRANCH))
+    return set_error(EPOCH_ERR_STATE, "instance created without EPOCH_GRAD_BRANCH");
+  if (d_Q && !(in->cfg.flags & EPOCH_GRAD_Q))
+    return set_error(EPOCH_ERR_STATE, "instance created without EPOCH_GRAD_Q");
+  if (!in->logL_valid) return set_error(EPOCH_ERR_STATE, "root_log_likelihood has not been called for this state");
+  if (!d_branch && !d_Q) return EPOCH_OK;
+  EPOCH_TRY(fastpath_gradient(in, d_Q != nullptr));
+  if (d_branch) EPOCH_TRY(download(in, d_branch, in->dbranch.ptr, (size_t)in->n_nodes * sizeof(double)));
+  if (d_Q) EPOCH_TRY(download(in, d_Q, in->dQ.ptr, (size_t)in->S * in->K * in->K * sizeof(double)));
+  return EPOCH_OK;
+}
+
+int epoch_get_transition_matrices(EpochInstance* in, double* out) {
+  if (!in || !out) return set_error(EPOCH_ERR_ARG, "NULL argument");
+  if (!in->P_valid) return set_error(EPOCH_ERR_STATE, "update_transition_matrices has not been called");
+  const size_t n = in->n_nodes, C = in->C, Kp = in->Kp, K = in->K, KK = Kp * Kp;
+  std::vector<char> raw(n * C * KK * in->real_size);
+  EPOCH_TRY(download(in, raw.data(), in->Pm.ptr, raw.size()));
+  for (size_t v = 0; v < n; ++v)
+    for (size_t c = 0; c < C; ++c)
+      for (size_t i = 0; i < K; ++i)
+        for (size_t j = 0; j < K; ++j) {
+          const size_t src = (v * C + c) * KK + i * Kp + j;
+          double x = in->fp64 ? reinterpret_cast<double*>(raw.data())[src] : reinterpret_cast<float*>(raw.data())[src];
+          if ((int)v == in->plan.root) x = 0.0;
+          out[((v * C + c) * K + i) * K + j] = x;
+        }
+  return EPOCH_OK;
+}
+
+int epoch_plan_segments(int32_t n_tips, const int32_t* parent, const double* height, int32_t n_intervals,
+                        const double* boundaries, const int32_t* interval_process, int32_t n_processes,
+                        int32_t capacity, int32_t* seg_offset, int32_t* seg_process, double* seg_time,
+                        int32_t* n_segments) {
+  g_error.clear();
+  if (!seg_offset || !n_segments) return set_error(EPOCH_ERR_ARG, "NULL output");
+  TreePlan plan;
+  std::string err;
+  if (plan_tree(n_tips, parent, height, nullptr, n_intervals, boundaries, interval_process, n_processes, plan, err))
+    return set_error(EPOCH_ERR_ARG, "%s", err.c_str());
+  const int nseg = (int)plan.seg_process.size();
+  *n_segments = nseg;
+  std::copy(plan.seg_offset.begin(), plan.seg_offset.end(), seg_offset);
+  if (nseg > capacity) return set_error(EPOCH_ERR_ARG, "capacity %d < %d segments", capacity, nseg);
+  std::copy(plan.seg_process.begin(), plan.seg_process.end(), seg_process);
+  std::copy(plan.seg_time.begin(), plan.seg_time.end(), seg_time);
+  return EPOCH_OK;
+}
+
+}  // extern "C"

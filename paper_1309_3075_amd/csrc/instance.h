@@ -1,0 +1,95 @@
+// Instance state shared by the ABI implementation and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/epochlik.h"
+#include "planner.h"
+
+namespace epochlik {
+
+// One growable device allocation owned by the instance.
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+struct EpochInstanceImpl;
+
+}  // namespace epochlik
+
+struct EpochInstance {
+  EpochConfig cfg{};
+  int N = 0, P = 0, K = 0, Kp = 0, C = 0, S = 0, n_nodes = 0, n_int = 0;
+  bool fp64 = false;
+  size_t real_size = 4;  // bytes of the compute type
+  hipStream_t stream = nullptr;
+  int device = 0;
+
+  // host-side copies and validity flags
+  std::vector<double> h_V, h_Vinv, h_lre, h_lim;  // padded [S][Kp][Kp], [S][Kp]
+  std::vector<char> have_eig;
+  bool any_complex = false;
+  double h_cat_rates[8] = {0}, h_cat_weights[8] = {0};
+  bool have_tips = false, have_weights = false, have_cats = false, have_pi = false;
+  bool have_tree = false;
+  bool P_valid = false, partials_valid = false, logL_valid = false;
+  bool eig_dirty = true;
+  epochlik::TreePlan plan;
+  int n_chunks = 1;  // pattern chunks of the gradient accumulation
+
+  // device buffers (compute type T unless noted)
+  epochlik::DevBuf eigT;       // V[S][Kp][Kp], Vinv[S][Kp][Kp], lre[S][Kp], lim[S][Kp]
+  epochlik::DevBuf eig64;      // the same in double
+  epochlik::DevBuf check;      // double scratch for the eigen check
+  epochlik::DevBuf tips;       // uint8 [N][P]
+  epochlik::DevBuf weights;    // double [P]
+  epochlik::DevBuf weightsT;   // T [P]
+  epochlik::DevBuf pi;         // double [Kp]
+  epochlik::DevBuf cat;        // double rates[8], weights[8]
+  epochlik::DevBuf tree_i;     // int32: parent, left, right [n], level_nodes [N-1], seg_offset [n+1], seg_process [nseg], walk [N-1]
+  epochlik::DevBuf tree_d;     // double: rate [n], tau [n], seg_time [nseg], seg_frac [nseg]
+  epochlik::DevBuf Pm;         // T [n][C][Kp][Kp]
+  epochlik::DevBuf dPm;        // T [n][C][Kp][Kp]
+  epochlik::DevBuf partials;   // T [N-1][C][P][Kp]
+  epochlik::DevBuf scales;     // int32 [N-1][P]
+  epochlik::DevBuf pre;        // T [N-1][C][P][Kp]
+  epochlik::DevBuf site;       // double [P]
+  epochlik::DevBuf blocksum;   // double [ceil(P/256)+1]
+  epochlik::DevBuf result;     // double [4]
+  epochlik::DevBuf Gpart;      // double [chunks][n][C][Kp][Kp]
+  epochlik::DevBuf G;          // double [n][C][Kp][Kp]
+  epochlik::DevBuf dbranch;    // double [n]
+  epochlik::DevBuf qseg;       // double complex per segment [nseg][C][Kp][Kp][2]
+  epochlik::DevBuf qscratch;   // T prefix products [nseg][C][Kp][Kp]
+  epochlik::DevBuf dQ;         // double [S][Kp][Kp]
+  epochlik::DevBuf seglist;    // int32 segments grouped by process: offsets [S+1], items [nseg*C]
+
+  // device pointers into tree_i / tree_d
+  int32_t *d_parent = nullptr, *d_left = nullptr, *d_right = nullptr, *d_level_nodes = nullptr,
+          *d_seg_offset = nullptr, *d_seg_process = nullptr, *d_walk = nullptr;
+  double *d_rate = nullptr, *d_tau = nullptr, *d_seg_time = nullptr, *d_seg_frac = nullptr;
+};
+
+namespace epochlik {
+
+// error helpers (thread-local message)
+int set_error(int code, const char* fmt, ...);
+int hip_check(hipError_t e, const char* what);
+
+// grows a device buffer (contents not preserved); returns EPOCH_OK or an error code
+int ensure(DevBuf& b, size_t bytes);
+
+// kernel launchers (kernels_generic.hip); all return EPOCH_OK or an error code
+int launch_eigen_check(EpochInstance* in, int s, const double* dQ, double* d_out);
+int launch_pstage_generic(EpochInstance* in);
+int launch_post_generic(EpochInstance* in);
+int launch_root_generic(EpochInstance* in);
+int launch_pre_generic(EpochInstance* in);
+int launch_grad_branch_generic(EpochInstance* in);
+int launch_grad_Q_generic(EpochInstance* in);
+
+}  // namespace epochlik

@@ -1,0 +1,158 @@
+"""Thin object wrapper over the C ABI, one method per entry point.
+
+Argument marshalling only: validation and every computation happen inside
+libepochlik.so.  The instance runs on torch's current HIP stream when torch
+has a GPU, else on the default stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _abi
+from ._abi import _dp, _f64, _i32, _ip, check
+from .eigen import eigensystem
+
+
+def _current_stream():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except Exception:  # pragma: no cover - torch missing or no device
+        pass
+    return ctypes.c_void_p(None)
+
+
+class EpochLikelihood:
+    """One likelihood instance (tree size, patterns, states fixed at creation)."""
+
+    def __init__(self, n_tips: int, n_patterns: int, n_states: int, n_categories: int = 1,
+                 n_processes: int = 1, max_intervals: int = 1, precision: str = "fp64",
+                 grad_branch: bool = False, grad_Q: bool = False, kernel: str = "auto",
+                 stream=None):
+        lib = _abi.load()
+        cfg = _abi.EpochConfig()
+        cfg.n_tips = n_tips
+        cfg.n_patterns = n_patterns
+        cfg.n_states = n_states
+        cfg.n_categories = n_categories
+        cfg.n_processes = n_processes
+        cfg.max_intervals = max_intervals
+        cfg.precision = {"fp32": _abi.EPOCH_FP32, "fp64": _abi.EPOCH_FP64}[precision]
+        cfg.flags = (_abi.EPOCH_GRAD_BRANCH if grad_branch else 0) | (_abi.EPOCH_GRAD_Q if grad_Q else 0)
+        cfg.kernel_path = {"auto": _abi.EPOCH_KERNEL_AUTO, "generic": _abi.EPOCH_KERNEL_GENERIC}[kernel]
+        cfg.reserved = 0
+        cfg.stream = stream if stream is not None else _current_stream()
+        self._cfg = cfg
+        h = ctypes.c_void_p()
+        check(lib.epoch_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._lib = lib
+        self.n_tips, self.n_patterns, self.n_states = n_tips, n_patterns, n_states
+        self.n_categories, self.n_processes = n_categories, n_processes
+        self.n_nodes = 2 * n_tips - 1
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.epoch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- data ---------------------------------------------------------------
+    def set_tip_states(self, states):
+        s = _i32(states)
+        check(self._lib.epoch_set_tip_states(self._h, _ip(s)))
+
+    def set_pattern_weights(self, w):
+        w = _f64(w)
+        check(self._lib.epoch_set_pattern_weights(self._h, _dp(w)))
+
+    def set_categories(self, rates, weights):
+        r, w = _f64(rates), _f64(weights)
+        check(self._lib.epoch_set_categories(self._h, _dp(r), _dp(w)))
+
+    def set_root_frequencies(self, pi):
+        p = _f64(pi)
+        check(self._lib.epoch_set_root_frequencies(self._h, _dp(p)))
+
+    def set_eigensystem(self, s: int, V, Vinv, lambda_re, lambda_im=None, Q=None) -> float:
+        V, Vi, lr = _f64(V), _f64(Vinv), _f64(lambda_re)
+        li = None if lambda_im is None else _f64(lambda_im)
+        q = None if Q is None else _f64(Q)
+        res = ctypes.c_double(float("nan"))
+        check(self._lib.set_epoch_eigensystems(self._h, s, _dp(V), _dp(Vi), _dp(lr), _dp(li), _dp(q),
+                                               ctypes.byref(res)))
+        return res.value
+
+    def set_rate_matrix(self, s: int, Q, pi=None, check_residual: bool = True) -> float:
+        """Decompose Q on the host and hand the eigensystem to the library."""
+        e = eigensystem(Q, pi)
+        return self.set_eigensystem(s, e.V, e.Vinv, e.lambda_re,
+                                    e.lambda_im if e.is_complex else None,
+                                    Q if check_residual else None)
+
+    def set_tree(self, parent, height, branch_rate=None, boundaries=(), interval_process=(0,)):
+        par, h = _i32(parent), _f64(height)
+        r = None if branch_rate is None else _f64(branch_rate)
+        b = _f64(boundaries) if len(boundaries) else None
+        phi = _i32(interval_process)
+        check(self._lib.set_tree_epochs(self._h, _ip(par), _dp(h), _dp(r), len(phi), _dp(b), _ip(phi)))
+
+    # -- the path -----------------------------------------------------------
+    def update_transition_matrices(self):
+        check(self._lib.update_transition_matrices(self._h))
+
+    def update_partials(self):
+        check(self._lib.update_partials(self._h))
+
+    def root_log_likelihood(self, site: bool = False):
+        out = ctypes.c_double(0.0)
+        s = np.zeros(self.n_patterns) if site else None
+        check(self._lib.root_log_likelihood(self._h, ctypes.byref(out), _dp(s)))
+        return (out.value, s) if site else out.value
+
+    def gradient(self, branch: bool = True, Q: bool = False):
+        db = np.zeros(self.n_nodes) if branch else None
+        dq = np.zeros((self.n_processes, self.n_states, self.n_states)) if Q else None
+        check(self._lib.log_likelihood_gradient(self._h, _dp(db), _dp(dq)))
+        return db, dq
+
+    def transition_matrices(self):
+        out = np.zeros((self.n_nodes, self.n_categories, self.n_states, self.n_states))
+        check(self._lib.epoch_get_transition_matrices(self._h, _dp(out)))
+        return out
+
+    def log_likelihood(self, site: bool = False):
+        self.update_transition_matrices()
+        self.update_partials()
+        return self.root_log_likelihood(site)
+
+
+def from_problem(prob, precision: str = "fp64", grad_branch: bool = False, grad_Q: bool = False,
+                 kernel: str = "auto", use_pi: bool = True) -> EpochLikelihood:
+    """Instance loaded with every input of a generated problem."""
+    lik = EpochLikelihood(prob.n_tips, prob.n_patterns, prob.n_states, len(prob.cat_rates),
+                          prob.n_processes, prob.n_intervals, precision, grad_branch, grad_Q, kernel)
+    lik.set_tip_states(prob.tips)
+    lik.set_pattern_weights(prob.weights)
+    lik.set_categories(prob.cat_rates, prob.cat_weights)
+    lik.set_root_frequencies(prob.pi_root)
+    for s, Q in enumerate(prob.Q):
+        pi = prob.pi_process[s] if use_pi else None
+        lik.set_rate_matrix(s, Q, pi)
+    lik.set_tree(prob.parent, prob.height, prob.branch_rate, prob.boundaries, prob.interval_process)
+    return lik

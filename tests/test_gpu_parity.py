@@ -1,0 +1,131 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: |dlogL|/|logL| <= 1e-12 (FP64) and <= 1e-5 (FP32); gradients
+||dg||_2 / ||g||_2 <= 1e-6 (FP64) and <= 1e-3 (FP32); transition matrices
+entrywise to 1e-12 (FP64) / 2e-6 (FP32).
+"""
+import numpy as np
+import pytest
+
+from oracle import epoch_oracle as O
+from paper_1309_3075_amd import _abi
+from paper_1309_3075_amd import workloads as W
+from paper_1309_3075_amd.likelihood import EpochLikelihood, from_problem
+
+pytestmark = pytest.mark.gpu
+
+TOL_LOGL = {"fp64": 1e-12, "fp32": 1e-5}
+TOL_GRAD = {"fp64": 1e-6, "fp32": 1e-3}
+TOL_P = {"fp64": 1e-12, "fp32": 2e-6}
+
+
+def rel(a, b):
+    return abs(a - b) / abs(b)
+
+
+def grad_rel(g, ref):
+    return np.linalg.norm(g - ref) / np.linalg.norm(ref)
+
+
+RANDOM_CASES = [
+    # seed, tips, K, patterns, C, intervals, processes, reversible, tip_h, missing
+    (101, 5, 2, 37, 1, 2, 2, True, 0.0, 0.0),
+    (102, 9, 3, 300, 3, 3, 2, False, 0.2, 0.05),
+    (103, 24, 4, 777, 4, 4, 3, True, 0.1, 0.02),
+    (104, 7, 5, 65, 2, 2, 2, False, 0.0, 0.0),
+    (105, 13, 20, 130, 2, 3, 3, True, 0.3, 0.0),
+    (106, 11, 40, 19, 1, 6, 4, False, 0.0, 0.0),
+    (107, 10, 61, 70, 1, 4, 4, True, 0.0, 0.0),
+    (108, 6, 64, 33, 2, 2, 1, True, 0.0, 0.1),
+]
+
+
+def _prob(case):
+    seed, n, K, P, C, M, S, rev, th, miss = case
+    rng = np.random.default_rng(seed)
+    return W.random_problem(rng, n, K, P, n_categories=C, n_intervals=M, n_processes=S,
+                            reversible=rev, tip_height_max=th, missing_frac=miss,
+                            branch_rate_spread=0.25)
+
+
+@pytest.mark.parametrize("kernel", ["generic", "auto"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", RANDOM_CASES, ids=[f"K{c[2]}_n{c[1]}_P{c[3]}" for c in RANDOM_CASES])
+def test_random_problem_logL_and_P(case, precision, kernel):
+    prob = _prob(case)
+    with from_problem(prob, precision, kernel=kernel, use_pi=False) as lik:
+        logL, site = lik.log_likelihood(site=True)
+        P = lik.transition_matrices()
+    want_site = O.site_log_likelihoods(prob)
+    want = float(np.dot(prob.weights, want_site))
+    assert rel(logL, want) <= TOL_LOGL[precision], (logL, want)
+    np.testing.assert_allclose(site, want_site, rtol=TOL_LOGL[precision] * 10,
+                               atol=TOL_LOGL[precision] * np.abs(want_site).max())
+    Pw = O.transition_matrices(prob)
+    Pw[-1] = 0.0
+    np.testing.assert_allclose(P, Pw, rtol=0, atol=TOL_P[precision] * max(1.0, prob.n_states / 8))
+
+
+@pytest.mark.parametrize("kernel", ["generic", "auto"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_C1_full_size(precision, kernel):
+    prob = W.make_config(1)
+    with from_problem(prob, precision, kernel=kernel) as lik:
+        logL = lik.log_likelihood()
+    want = O.log_likelihood(prob)
+    assert rel(logL, want) <= TOL_LOGL[precision]
+
+
+@pytest.mark.parametrize("kernel", ["generic", "auto"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", RANDOM_CASES[:6], ids=[f"K{c[2]}_n{c[1]}" for c in RANDOM_CASES[:6]])
+def test_gradients_against_oracle(case, precision, kernel):
+    prob = _prob(case)
+    with from_problem(prob, precision, grad_branch=True, grad_Q=True, kernel=kernel, use_pi=False) as lik:
+        lik.log_likelihood()
+        db, dq = lik.gradient(branch=True, Q=True)
+    ref_b, ref_q = O.gradient(prob)
+    assert grad_rel(db, ref_b) <= TOL_GRAD[precision], grad_rel(db, ref_b)
+    assert grad_rel(dq, ref_q) <= TOL_GRAD[precision], grad_rel(dq, ref_q)
+    assert db[-1] == 0.0
+
+
+def test_call_order_and_argument_errors():
+    prob = _prob(RANDOM_CASES[0])
+    lik = EpochLikelihood(prob.n_tips, prob.n_patterns, prob.n_states, 1, prob.n_processes,
+                          prob.n_intervals, "fp64", grad_branch=True)
+    with pytest.raises(_abi.EpochError) as e:
+        lik.update_transition_matrices()
+    assert e.value.code == _abi.EPOCH_ERR_STATE
+    with pytest.raises(_abi.EpochError) as e:
+        lik.update_partials()
+    assert e.value.code == _abi.EPOCH_ERR_STATE
+    bad = prob.tips.copy()
+    bad[0, 0] = prob.n_states + 1
+    with pytest.raises(_abi.EpochError) as e:
+        lik.set_tip_states(bad)
+    assert e.value.code == _abi.EPOCH_ERR_ARG
+    with pytest.raises(_abi.EpochError):
+        lik.set_categories([1.0], [0.5])
+    with pytest.raises(_abi.EpochError):
+        lik.set_root_frequencies(np.full(prob.n_states, 0.3))
+    lik.close()
+    lik = from_problem(prob, "fp64")
+    lik.log_likelihood()
+    with pytest.raises(_abi.EpochError) as e:
+        lik.gradient()
+    assert e.value.code == _abi.EPOCH_ERR_STATE
+    lik.close()
+
+
+def test_eigensystem_residual_warning():
+    prob = _prob(RANDOM_CASES[2])
+    with from_problem(prob, "fp64", use_pi=False) as lik:
+        from paper_1309_3075_amd.eigen import eigensystem
+        e = eigensystem(prob.Q[0])
+        res = lik.set_eigensystem(0, e.V, e.Vinv, e.lambda_re, None, prob.Q[0])
+        assert res < 1e-12
+        wrong = e.lambda_re.copy()
+        wrong[0] += 0.1
+        res_bad = lik.set_eigensystem(0, e.V, e.Vinv, wrong, None, prob.Q[0])
+        assert res_bad > 1e-3
