@@ -32,7 +32,7 @@
  *
  * Ownership: every host pointer is borrowed for the duration of the call and
  * copied; the library owns all device memory it allocates.  Device pointers
- * are never taken or returned except by epoch_device_info().  An instance is
+ * are never taken or returned.  An instance is
  * not thread-safe; distinct instances are independent.  All device work runs
  * on the stream given in EpochConfig (NULL = the default stream); calls that
  * return host results synchronise that stream.
@@ -170,6 +170,18 @@ int log_likelihood_gradient(EpochInstance* inst, double* d_branch, double* d_Q);
  * entry v = branch above node v; root block left as zeros).  Requires
  * update_transition_matrices. */
 int epoch_get_transition_matrices(EpochInstance* inst, double* out);
+
+/* Per-phase device timing (tracing): when enabled, the library brackets each
+ * phase with HIP events on the instance's stream and accumulates their elapsed
+ * times.  Phases: 0 transition matrices, 1 post-order partials, 2 root
+ * reduction, 3 pre-order + dlogL/dP accumulation, 4 gradient reduction and
+ * dlogL/dl, 5 dlogL/dQ.  enable != 0 resets the accumulators. */
+#define EPOCH_N_PHASES 6
+int epoch_set_timing(EpochInstance* inst, int32_t enable);
+
+/* Accumulated milliseconds and launch-group counts per phase, host [EPOCH_N_PHASES]
+ * each (either may be NULL).  Synchronises the stream. */
+int epoch_get_timing(EpochInstance* inst, double* ms_out, int64_t* counts_out);
 
 /* Host planner only (no device work, usable without a GPU): the per-interval
  * segments of every branch, parent side first.

@@ -246,8 +246,10 @@ def branch_adjoints(prob, P=None):
     return G
 
 
-def gradient(prob):
+def gradient(prob, wrt=("branch", "Q")):
     """(dlogL/dl_b per child node [2N-1] with root entry 0, dlogL/dQ_s [S][K][K]).
+
+    ``wrt`` selects which of the two to form (the other is returned as zeros).
 
     l_b = r_b * tau_b; the per-interval fractions of the branch stay fixed, so
     the factor of interval k is exp(rho_c * l_b * f_bk * Q_s).
@@ -280,7 +282,9 @@ def gradient(prob):
                 s, dt = segs[k]
                 # d F_k / d l_b = rho_c * (dt / tau) * Q_s F_k
                 dF = prob.cat_rates[c] * (dt / tau) * (prob.Q[s] @ F[k])
-                d_branch[v] += float(np.sum(Gk * dF))
+                if "branch" in wrt:
+                    d_branch[v] += float(np.sum(Gk * dF))
                 # d F_k / d Q_s [E] = L_exp(scale*dt*Q_s)[scale*dt*E]
-                d_Q[s] += scale * dt * adjoint_frechet_exp(scale * dt * prob.Q[s], Gk)
+                if "Q" in wrt:
+                    d_Q[s] += scale * dt * adjoint_frechet_exp(scale * dt * prob.Q[s], Gk)
     return d_branch, d_Q

@@ -35,8 +35,9 @@ EXPORTED = [
     "epoch_set_pattern_weights", "epoch_set_categories", "epoch_set_root_frequencies",
     "set_epoch_eigensystems", "set_tree_epochs", "update_transition_matrices", "update_partials",
     "root_log_likelihood", "log_likelihood_gradient", "epoch_get_transition_matrices",
-    "epoch_plan_segments",
+    "epoch_plan_segments", "epoch_set_timing", "epoch_get_timing",
 ]
+PHASES = ["transition_matrices", "post_order", "root", "pre_order_dP", "grad_reduce", "grad_Q"]
 
 
 class EpochConfig(ctypes.Structure):
@@ -71,6 +72,10 @@ def load() -> ctypes.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1309_3075_amd.build`")
+    # torch ships its own HIP runtime with the same SONAME as the system one;
+    # loading torch first makes the library bind to that single runtime, so
+    # torch's streams and device memory are valid inside the library.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
     i32, u32, dbl = ctypes.c_int32, ctypes.c_uint32, ctypes.c_double
@@ -92,6 +97,8 @@ def load() -> ctypes.CDLL:
         "log_likelihood_gradient": (i32, [P, dp, dp]),
         "epoch_get_transition_matrices": (i32, [P, dp]),
         "epoch_plan_segments": (i32, [i32, ip, dp, i32, dp, ip, i32, i32, ip, ip, dp, ip]),
+        "epoch_set_timing": (i32, [P, i32]),
+        "epoch_get_timing": (i32, [P, dp, ctypes.POINTER(ctypes.c_int64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -1,24 +1,62 @@
-// Kernel selection for each step of the path.
+// Kernel selection for each step of the path: the specialised 4-state
+// kernels when K == 4 (unless the generic path is forced), the generic any-K
+// kernels otherwise.
+#include <algorithm>
+
 #include "fastpath.h"
 
 namespace epochlik {
 
-int fastpath_init(EpochInstance*) { return EPOCH_OK; }
+namespace {
+bool nuc(const EpochInstance* in) { return in->path == 1; }
+}  // namespace
+
+int fastpath_init(EpochInstance* in) {
+  in->path = (in->K == 4 && in->cfg.kernel_path == EPOCH_KERNEL_AUTO) ? 1 : 0;
+  if (nuc(in) && (in->cfg.flags & (EPOCH_GRAD_BRANCH | EPOCH_GRAD_Q))) {
+    const size_t chunks = nuc_chunks(in->P, in->nuc_R);
+    const size_t bytes = chunks * in->n_nodes * in->C * 16 * sizeof(double);
+    return ensure(in->Gpart, std::max(bytes, in->Gpart.bytes));
+  }
+  return EPOCH_OK;
+}
 void fastpath_release(EpochInstance*) {}
 int fastpath_tips_changed(EpochInstance*) { return EPOCH_OK; }
 int fastpath_tree_changed(EpochInstance*) { return EPOCH_OK; }
 
-int fastpath_pstage(EpochInstance* in) { return launch_pstage_generic(in); }
-int fastpath_post(EpochInstance* in) { return launch_post_generic(in); }
-int fastpath_root(EpochInstance* in) { return launch_root_generic(in); }
+#define EPOCH_PHASE(k, expr)            \
+  do {                                  \
+    int _rc = phase_begin(in, k);       \
+    if (!_rc) _rc = (expr);             \
+    if (!_rc) _rc = phase_end(in, k);   \
+    if (_rc) return _rc;                \
+  } while (0)
+
+int fastpath_pstage(EpochInstance* in) {
+  EPOCH_PHASE(0, launch_pstage_generic(in));
+  return EPOCH_OK;
+}
+
+int fastpath_post(EpochInstance* in) {
+  EPOCH_PHASE(1, nuc(in) ? launch_nuc_post(in) : launch_post_generic(in));
+  return EPOCH_OK;
+}
+
+int fastpath_root(EpochInstance* in) {
+  EPOCH_PHASE(2, nuc(in) ? launch_nuc_root(in) : launch_root_generic(in));
+  return EPOCH_OK;
+}
 
 int fastpath_gradient(EpochInstance* in, bool want_Q) {
-  int rc = launch_pre_generic(in);
-  if (rc) return rc;
-  rc = launch_grad_branch_generic(in);
-  if (rc) return rc;
-  if (want_Q) rc = launch_grad_Q_generic(in);
-  return rc;
+  if (nuc(in)) {
+    EPOCH_PHASE(3, launch_nuc_pre_grad(in, in->nuc_R));
+    EPOCH_PHASE(4, launch_grad_reduce(in, nuc_chunks(in->P, in->nuc_R)));
+  } else {
+    EPOCH_PHASE(3, launch_pre_generic(in));
+    EPOCH_PHASE(4, launch_grad_branch_generic(in));
+  }
+  if (want_Q) EPOCH_PHASE(5, launch_grad_Q_generic(in));
+  return EPOCH_OK;
 }
 
 }  // namespace epochlik

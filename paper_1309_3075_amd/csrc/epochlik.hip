@@ -54,9 +54,41 @@ int ensure(DevBuf& b, size_t bytes) {
   return EPOCH_OK;
 }
 
+namespace {
+int collect_phase(EpochInstance* in, int k) {
+  if (!in->ev_pending[k]) return EPOCH_OK;
+  int rc = hip_check(hipEventSynchronize(in->ev[k][1]), "timing event sync");
+  if (rc) return rc;
+  float ms = 0.f;
+  rc = hip_check(hipEventElapsedTime(&ms, in->ev[k][0], in->ev[k][1]), "timing elapsed");
+  if (rc) return rc;
+  in->phase_ms[k] += ms;
+  in->ev_pending[k] = false;
+  return EPOCH_OK;
+}
+}  // namespace
+
+int phase_begin(EpochInstance* in, int k) {
+  if (!in->timing) return EPOCH_OK;
+  int rc = collect_phase(in, k);
+  if (rc) return rc;
+  return hip_check(hipEventRecord(in->ev[k][0], in->stream), "timing record");
+}
+
+int phase_end(EpochInstance* in, int k) {
+  if (!in->timing) return EPOCH_OK;
+  int rc = hip_check(hipEventRecord(in->ev[k][1], in->stream), "timing record");
+  in->ev_pending[k] = true;
+  in->phase_count[k]++;
+  return rc;
+}
+
 }  // namespace epochlik
 
 namespace {
+
+// Above this condition number of V the FP32 path reconstructs exp(tQ) in FP64.
+constexpr double kCondFP32 = 32.0;
 
 void release(DevBuf& b) {
   if (b.ptr) (void)hipFree(b.ptr);
@@ -143,9 +175,11 @@ int epoch_create(const EpochConfig* cfg, EpochInstance** out) {
   if ((N - 1) * P > ((size_t)1 << 40)) return set_error(EPOCH_ERR_ARG, "problem too large");
 
   int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+  const hipError_t derr = hipGetDeviceCount(&ndev);
+  if (derr != hipSuccess || ndev < 1) {
     (void)hipGetLastError();
-    return set_error(EPOCH_ERR_HIP, "no HIP device available");
+    return set_error(EPOCH_ERR_HIP, "no HIP device available (hipGetDeviceCount: %s, count %d)",
+                     hipGetErrorString(derr), ndev);
   }
   auto* in = new EpochInstance();
   in->cfg = c;
@@ -168,6 +202,7 @@ int epoch_create(const EpochConfig* cfg, EpochInstance** out) {
   in->h_lre.assign(S * Kp, 0.0);
   in->h_lim.assign(S * Kp, 0.0);
   in->have_eig.assign(S, 0);
+  in->cond.assign(S, 1.0);
   in->n_chunks = choose_chunks(in);
   int rc = EPOCH_OK;
   auto A = [&](DevBuf& b, size_t bytes) {
@@ -187,7 +222,7 @@ int epoch_create(const EpochConfig* cfg, EpochInstance** out) {
   A(in->scales, (N - 1) * P * sizeof(int32_t));
   if (grad) A(in->pre, (N - 1) * C * P * Kp * R);
   A(in->site, P * sizeof(double));
-  A(in->blocksum, ((P + 255) / 256 + 1) * sizeof(double));
+  A(in->blocksum, ((P + 63) / 64 + 1) * sizeof(double));
   A(in->result, 8 * sizeof(double));
   if (grad) {
     A(in->Gpart, (size_t)in->n_chunks * n * C * KK * sizeof(double));
@@ -216,8 +251,48 @@ int epoch_create(const EpochConfig* cfg, EpochInstance** out) {
   return EPOCH_OK;
 }
 
+int epoch_set_timing(EpochInstance* in, int32_t enable) {
+  if (!in) return set_error(EPOCH_ERR_ARG, "NULL instance");
+  if (enable && !in->ev[0][0]) {
+    for (int k = 0; k < EPOCH_N_PHASES; ++k)
+      for (int j = 0; j < 2; ++j) EPOCH_TRY(hip_check(hipEventCreate(&in->ev[k][j]), "hipEventCreate"));
+  }
+  EPOCH_TRY(hip_check(hipStreamSynchronize(in->stream), "timing sync"));
+  for (int k = 0; k < EPOCH_N_PHASES; ++k) {
+    in->ev_pending[k] = false;
+    in->phase_ms[k] = 0.0;
+    in->phase_count[k] = 0;
+  }
+  in->timing = enable != 0;
+  return EPOCH_OK;
+}
+
+int epoch_get_timing(EpochInstance* in, double* ms_out, int64_t* counts_out) {
+  if (!in) return set_error(EPOCH_ERR_ARG, "NULL instance");
+  if (in->timing)
+    for (int k = 0; k < EPOCH_N_PHASES; ++k) {
+      int rc = EPOCH_OK;
+      if (in->ev_pending[k]) {
+        rc = hip_check(hipEventSynchronize(in->ev[k][1]), "timing event sync");
+        float ms = 0.f;
+        if (!rc) rc = hip_check(hipEventElapsedTime(&ms, in->ev[k][0], in->ev[k][1]), "timing elapsed");
+        if (rc) return rc;
+        in->phase_ms[k] += ms;
+        in->ev_pending[k] = false;
+      }
+    }
+  for (int k = 0; k < EPOCH_N_PHASES; ++k) {
+    if (ms_out) ms_out[k] = in->phase_ms[k];
+    if (counts_out) counts_out[k] = in->phase_count[k];
+  }
+  return EPOCH_OK;
+}
+
 int epoch_destroy(EpochInstance* in) {
   if (!in) return EPOCH_OK;
+  for (int k = 0; k < EPOCH_N_PHASES; ++k)
+    for (int j = 0; j < 2; ++j)
+      if (in->ev[k][j]) (void)hipEventDestroy(in->ev[k][j]);
   fastpath_release(in);
   for (DevBuf* b : {&in->eigT, &in->eig64, &in->check, &in->tips, &in->weights, &in->weightsT, &in->pi,
                     &in->cat, &in->tree_i, &in->tree_d, &in->Pm, &in->dPm, &in->partials, &in->scales,
@@ -341,6 +416,22 @@ int set_epoch_eigensystems(EpochInstance* in, int32_t s, const double* V, const 
   in->any_complex = false;
   for (double x : in->h_lim)
     if (x != 0.0) in->any_complex = true;
+  {
+    double nv = 0.0, ni = 0.0;
+    for (int i = 0; i < K; ++i) {
+      double rv = 0.0, ri = 0.0;
+      for (int j = 0; j < K; ++j) {
+        rv += std::fabs(V[i * K + j]);
+        ri += std::fabs(Vinv[i * K + j]);
+      }
+      nv = std::max(nv, rv);
+      ni = std::max(ni, ri);
+    }
+    in->cond[s] = nv * ni;
+    in->eig_fp64 = false;
+    for (int k = 0; k < in->S; ++k)
+      if (in->cond[k] > kCondFP32) in->eig_fp64 = true;
+  }
   // upload this process's slices in double and in the compute type
   auto up_slice = [&](DevBuf& buf, size_t elem, bool as_float) -> int {
     char* base = static_cast<char*>(buf.ptr);
@@ -428,7 +519,8 @@ int set_tree_epochs(EpochInstance* in, const int32_t* parent, const double* heig
   in->d_seg_frac = bd + 2 * n + nseg;
   if (in->cfg.flags & EPOCH_GRAD_Q) {
     const size_t KK = (size_t)in->Kp * in->Kp, C = in->C;
-    EPOCH_TRY(ensure(in->qscratch, std::max<size_t>(1, nseg) * C * KK * in->real_size));
+    // prefix products may be formed in double even for FP32 instances (eig_fp64)
+    EPOCH_TRY(ensure(in->qscratch, std::max<size_t>(1, nseg) * C * KK * sizeof(double)));
     EPOCH_TRY(ensure(in->qseg, (nseg * C * KK * 2 + (size_t)in->S * KK * 2) * sizeof(double)));
     std::vector<int32_t> off(in->S + 1, 0), items;
     for (size_t g = 0; g < nseg; ++g) off[plan.seg_process[g] + 1] += (int32_t)C;

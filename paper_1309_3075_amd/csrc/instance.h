@@ -33,13 +33,19 @@ struct EpochInstance {
   std::vector<double> h_V, h_Vinv, h_lre, h_lim;  // padded [S][Kp][Kp], [S][Kp]
   std::vector<char> have_eig;
   bool any_complex = false;
+  std::vector<double> cond;  // infinity-norm condition number of each V
+  // FP32 instances reconstruct exp(tQ) from the eigensystem in FP64 when some
+  // V is ill-conditioned (the FP32 rounding error grows like cond(V) * 2^-24).
+  bool eig_fp64 = false;
   double h_cat_rates[8] = {0}, h_cat_weights[8] = {0};
   bool have_tips = false, have_weights = false, have_cats = false, have_pi = false;
   bool have_tree = false;
   bool P_valid = false, partials_valid = false, logL_valid = false;
   bool eig_dirty = true;
   epochlik::TreePlan plan;
-  int n_chunks = 1;  // pattern chunks of the gradient accumulation
+  int n_chunks = 1;  // pattern chunks of the generic gradient accumulation
+  int path = 0;      // 0 generic, 1 four-state kernels
+  int nuc_R = 8;     // pattern tiles per block in the four-state gradient
 
   // device buffers (compute type T unless noted)
   epochlik::DevBuf eigT;       // V[S][Kp][Kp], Vinv[S][Kp][Kp], lre[S][Kp], lim[S][Kp]
@@ -68,6 +74,13 @@ struct EpochInstance {
   epochlik::DevBuf dQ;         // double [S][Kp][Kp]
   epochlik::DevBuf seglist;    // int32 segments grouped by process: offsets [S+1], items [nseg*C]
 
+  // per-phase timing (epoch_set_timing)
+  bool timing = false;
+  hipEvent_t ev[EPOCH_N_PHASES][2] = {};
+  bool ev_pending[EPOCH_N_PHASES] = {};
+  double phase_ms[EPOCH_N_PHASES] = {};
+  int64_t phase_count[EPOCH_N_PHASES] = {};
+
   // device pointers into tree_i / tree_d
   int32_t *d_parent = nullptr, *d_left = nullptr, *d_right = nullptr, *d_level_nodes = nullptr,
           *d_seg_offset = nullptr, *d_seg_process = nullptr, *d_walk = nullptr;
@@ -75,6 +88,10 @@ struct EpochInstance {
 };
 
 namespace epochlik {
+
+// phase timing brackets (no-ops unless timing is enabled)
+int phase_begin(EpochInstance* in, int phase);
+int phase_end(EpochInstance* in, int phase);
 
 // error helpers (thread-local message)
 int set_error(int code, const char* fmt, ...);
@@ -91,5 +108,13 @@ int launch_root_generic(EpochInstance* in);
 int launch_pre_generic(EpochInstance* in);
 int launch_grad_branch_generic(EpochInstance* in);
 int launch_grad_Q_generic(EpochInstance* in);
+int launch_final_sum(EpochInstance* in, int n_blocks);
+int launch_grad_reduce(EpochInstance* in, int n_chunks);
+
+// 4-state kernels (kernels_nuc.hip)
+int launch_nuc_post(EpochInstance* in);
+int launch_nuc_root(EpochInstance* in);
+int launch_nuc_pre_grad(EpochInstance* in, int R);
+int nuc_chunks(int P, int R);
 
 }  // namespace epochlik

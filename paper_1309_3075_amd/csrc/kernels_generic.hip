@@ -76,13 +76,13 @@ __device__ inline BlockCoef<T> block_coef(const T* lr, const T* li, int j, T tau
 // P stage.  One item = (node v, category c).  For Kp^2 <= 256 several items
 // share a block; otherwise one item per block and EPT elements per thread.
 // ---------------------------------------------------------------------------
-template <typename T, bool GRAD, int EPT>
+template <typename T, typename TO, bool GRAD, int EPT>
 __global__ __launch_bounds__(256) void pstage_generic_kernel(
     int n_nodes, int Kp, int C, const T* __restrict__ eigV, const T* __restrict__ eigVi,
     const T* __restrict__ lre, const T* __restrict__ lim, const int32_t* __restrict__ seg_offset,
     const int32_t* __restrict__ seg_process, const double* __restrict__ seg_time,
     const double* __restrict__ seg_frac, const double* __restrict__ rate,
-    const double* __restrict__ cat_rates, T* __restrict__ Pout, T* __restrict__ dPout) {
+    const double* __restrict__ cat_rates, TO* __restrict__ Pout, TO* __restrict__ dPout) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int KK = Kp * Kp;
   const int ipb = (EPT == 1) ? max(1, 256 / KK) : 1;
@@ -204,8 +204,8 @@ __global__ __launch_bounds__(256) void pstage_generic_kernel(
 #pragma unroll
   for (int e = 0; e < EPT; ++e)
     if (eok[e]) {
-      Pout[base + idx[e]] = sX[idx[e]];
-      if (GRAD) dPout[base + idx[e]] = sD[idx[e]];
+      Pout[base + idx[e]] = TO(sX[idx[e]]);
+      if (GRAD) dPout[base + idx[e]] = TO(sD[idx[e]]);
     }
 }
 
@@ -546,7 +546,9 @@ int lanes_per_pattern(int Kp) {
   return q;
 }
 
-template <typename T>
+// T: arithmetic of the eigen reconstruction and chain products; TO: storage type
+// of the transition matrices handed to pruning.
+template <typename T, typename TO>
 int pstage_dispatch(EpochInstance* in) {
   const int Kp = in->Kp, KK = Kp * Kp, C = in->C, n = in->n_nodes;
   const bool grad = (in->cfg.flags & (EPOCH_GRAD_BRANCH | EPOCH_GRAD_Q)) != 0;
@@ -555,15 +557,17 @@ int pstage_dispatch(EpochInstance* in) {
   const int items = n * C;
   dim3 grid((items + ipb - 1) / ipb);
   const size_t shm = 2 * (size_t)ipb * KK * sizeof(T);
-  const T* V = eigT_ptr<T>(in, 0);
-  const T* Vi = eigT_ptr<T>(in, 1);
-  const T* lr = eigT_ptr<T>(in, 2);
-  const T* li = eigT_ptr<T>(in, 3);
+  const T* base = static_cast<const T*>(sizeof(T) == 8 ? in->eig64.ptr : in->eigT.ptr);
+  const size_t S = in->S;
+  const T* V = base;
+  const T* Vi = base + S * KK;
+  const T* lr = base + 2 * S * KK;
+  const T* li = lr + S * Kp;
   const double* cat = static_cast<const double*>(in->cat.ptr);
-  T* Pout = static_cast<T*>(in->Pm.ptr);
-  T* dPout = static_cast<T*>(in->dPm.ptr);
+  TO* Pout = static_cast<TO*>(in->Pm.ptr);
+  TO* dPout = static_cast<TO*>(in->dPm.ptr);
 #define EPOCH_PSTAGE(G, E)                                                                      \
-  hipLaunchKernelGGL((pstage_generic_kernel<T, G, E>), grid, dim3(256), shm, in->stream, n, Kp, C, \
+  hipLaunchKernelGGL((pstage_generic_kernel<T, TO, G, E>), grid, dim3(256), shm, in->stream, n, Kp, C, \
                      V, Vi, lr, li, in->d_seg_offset, in->d_seg_process, in->d_seg_time,        \
                      in->d_seg_frac, in->d_rate, cat, Pout, dPout)
   if (ept == 1) {
@@ -690,9 +694,15 @@ int grad_branch_dispatch(EpochInstance* in) {
   }
   int rc = hip_check(hipGetLastError(), "grad_G_generic launch");
   if (rc) return rc;
+  return launch_grad_reduce(in, in->n_chunks);
+}
+
+template <typename T>
+int grad_reduce_dispatch(EpochInstance* in, int n_chunks) {
+  const int nG = in->C * in->Kp * in->Kp;
   hipLaunchKernelGGL((grad_reduce_branch_kernel<T>), dim3(in->n_nodes), dim3(256), 0, in->stream,
                      static_cast<const double*>(in->Gpart.ptr), static_cast<const T*>(in->dPm.ptr),
-                     in->n_chunks, in->n_nodes, nG, in->plan.root, static_cast<double*>(in->G.ptr),
+                     n_chunks, in->n_nodes, nG, in->plan.root, static_cast<double*>(in->G.ptr),
                      static_cast<double*>(in->dbranch.ptr));
   return hip_check(hipGetLastError(), "grad_reduce_branch launch");
 }
@@ -711,8 +721,20 @@ int launch_eigen_check(EpochInstance* in, int s, const double* dQ, double* d_out
   return hip_check(hipGetLastError(), "eigen_check launch");
 }
 
+int launch_final_sum(EpochInstance* in, int n_blocks) {
+  hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(256), 0, in->stream,
+                     static_cast<const double*>(in->blocksum.ptr), n_blocks,
+                     static_cast<double*>(in->result.ptr));
+  return hip_check(hipGetLastError(), "final_sum launch");
+}
+
+int launch_grad_reduce(EpochInstance* in, int n_chunks) {
+  return in->fp64 ? grad_reduce_dispatch<double>(in, n_chunks) : grad_reduce_dispatch<float>(in, n_chunks);
+}
+
 int launch_pstage_generic(EpochInstance* in) {
-  return in->fp64 ? pstage_dispatch<double>(in) : pstage_dispatch<float>(in);
+  if (in->fp64) return pstage_dispatch<double, double>(in);
+  return in->eig_fp64 ? pstage_dispatch<double, float>(in) : pstage_dispatch<float, float>(in);
 }
 int launch_post_generic(EpochInstance* in) {
   return in->fp64 ? post_dispatch<double>(in) : post_dispatch<float>(in);

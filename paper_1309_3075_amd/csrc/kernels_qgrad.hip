@@ -347,7 +347,7 @@ int qgrad_dispatch(EpochInstance* in) {
   const int Kp = in->Kp, KK = Kp * Kp, C = in->C;
   const int ept = (KK + 255) / 256;
   const size_t S = in->S;
-  const T* base = static_cast<const T*>(in->eigT.ptr);
+  const T* base = static_cast<const T*>(sizeof(T) == 8 ? in->eig64.ptr : in->eigT.ptr);
   const T* V = base;
   const T* Vi = base + S * KK;
   const T* lr = base + 2 * S * KK;
@@ -388,7 +388,7 @@ int qgrad_dispatch(EpochInstance* in) {
 }  // namespace
 
 int launch_grad_Q_generic(EpochInstance* in) {
-  return in->fp64 ? qgrad_dispatch<double>(in) : qgrad_dispatch<float>(in);
+  return (in->fp64 || in->eig_fp64) ? qgrad_dispatch<double>(in) : qgrad_dispatch<float>(in);
 }
 
 }  // namespace epochlik

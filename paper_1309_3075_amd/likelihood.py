@@ -136,6 +136,17 @@ class EpochLikelihood:
         check(self._lib.epoch_get_transition_matrices(self._h, _dp(out)))
         return out
 
+    def set_timing(self, enable: bool = True):
+        check(self._lib.epoch_set_timing(self._h, 1 if enable else 0))
+
+    def timing(self):
+        """{phase: (milliseconds, launch groups)} accumulated since set_timing(True)."""
+        ms = np.zeros(len(_abi.PHASES))
+        cnt = np.zeros(len(_abi.PHASES), dtype=np.int64)
+        check(self._lib.epoch_get_timing(self._h, _dp(ms),
+                                         cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        return {k: (float(m), int(n)) for k, m, n in zip(_abi.PHASES, ms, cnt)}
+
     def log_likelihood(self, site: bool = False):
         self.update_transition_matrices()
         self.update_partials()

@@ -48,12 +48,15 @@ def _prob(case):
                             branch_rate_spread=0.25)
 
 
+@pytest.mark.parametrize("use_pi", [False, True], ids=["eig", "sym"])
 @pytest.mark.parametrize("kernel", ["generic", "auto"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("case", RANDOM_CASES, ids=[f"K{c[2]}_n{c[1]}_P{c[3]}" for c in RANDOM_CASES])
-def test_random_problem_logL_and_P(case, precision, kernel):
+def test_random_problem_logL_and_P(case, precision, kernel, use_pi):
     prob = _prob(case)
-    with from_problem(prob, precision, kernel=kernel, use_pi=False) as lik:
+    if use_pi and prob.pi_process[0] is None:
+        pytest.skip("asymmetric model: no symmetric form")
+    with from_problem(prob, precision, kernel=kernel, use_pi=use_pi) as lik:
         logL, site = lik.log_likelihood(site=True)
         P = lik.transition_matrices()
     want_site = O.site_log_likelihoods(prob)
