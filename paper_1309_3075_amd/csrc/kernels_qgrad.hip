@@ -22,6 +22,9 @@ namespace epochlik {
 
 namespace {
 
+__device__ inline float dev_expm1(float x) { return expm1f(x); }
+__device__ inline double dev_expm1(double x) { return expm1(x); }
+
 struct cplx {
   double re, im;
 };
@@ -81,15 +84,16 @@ __device__ inline void store_regs(T* s, const T* y, const int* idx, const bool* 
 }
 
 // X <- X F(tau) (transposed = false) or X <- X F(tau)^T (transposed = true), with
-// F = V E V^-1, using sX (LDS) and registers.
+// F = I + V (E - I) V^-1, using sX (LDS) and registers.
 template <typename T, int EPT>
 __device__ void apply_factor(T* sX, const T* V, const T* Vi, const T* lr, const T* li, T tau, int Kp,
                              const int* idx, const bool* ok, bool transposed) {
-  T y[EPT];
+  T y[EPT], xold[EPT];
   // first multiply: X V (plain) or X V^-T (transposed)
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     y[e] = 0;
+    xold[e] = ok[e] ? sX[idx[e]] : T(0);
     if (ok[e]) {
       const int i = idx[e] / Kp, j = idx[e] % Kp;
       for (int l = 0; l < Kp; ++l) y[e] += sX[i * Kp + l] * (transposed ? Vi[j * Kp + l] : V[l * Kp + j]);
@@ -98,7 +102,7 @@ __device__ void apply_factor(T* sX, const T* V, const T* Vi, const T* lr, const 
   __syncthreads();
   store_regs<T, EPT>(sX, y, idx, ok);
   __syncthreads();
-  // middle: E (plain) or E^T (transposed: the rotation angle changes sign)
+  // middle: E - I (plain) or (E - I)^T (transposed: the rotation angle changes sign)
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     y[e] = 0;
@@ -106,26 +110,28 @@ __device__ void apply_factor(T* sX, const T* V, const T* Vi, const T* lr, const 
       const int i = idx[e] / Kp, j = idx[e] % Kp;
       const T b = li[j];
       if (b == T(0)) {
-        y[e] = sX[idx[e]] * dev_exp(lr[j] * tau);
+        y[e] = sX[idx[e]] * dev_expm1(lr[j] * tau);
       } else {
         const bool first = b > T(0);
         const T bb = first ? b : -b;
-        const T ea = dev_exp(lr[j] * tau), cs = dev_cos(bb * tau), sn = dev_sin(bb * tau);
+        const T em1 = dev_expm1(lr[j] * tau);
+        const T ea = em1 + T(1), cs = dev_cos(bb * tau), sn = dev_sin(bb * tau);
+        const T hs = dev_sin(T(0.5) * bb * tau);
         const int jp = first ? j + 1 : j - 1;
         // plain:   first: ea(c x_j - s x_p), second: ea(s x_p + c x_j)
-        // transp.: first: ea(c x_j + s x_p), second: ea(-s x_p + c x_j)
+        // transp.: first: ea(c x_j + s x_p), second: ea(-s x_p + c x_j); minus x_j for E - I
         const T sgn = (first ? T(-1) : T(1)) * (transposed ? T(-1) : T(1));
-        y[e] = ea * (cs * sX[idx[e]] + sgn * sn * sX[i * Kp + jp]);
+        y[e] = (em1 * cs - T(2) * hs * hs) * sX[idx[e]] + sgn * ea * sn * sX[i * Kp + jp];
       }
     }
   }
   __syncthreads();
   store_regs<T, EPT>(sX, y, idx, ok);
   __syncthreads();
-  // last multiply: V^-1 (plain) or V^T (transposed)
+  // last multiply: V^-1 (plain) or V^T (transposed), plus the identity part
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
-    y[e] = 0;
+    y[e] = xold[e];
     if (ok[e]) {
       const int i = idx[e] / Kp, j = idx[e] % Kp;
       for (int l = 0; l < Kp; ++l) y[e] += sX[i * Kp + l] * (transposed ? V[j * Kp + l] : Vi[l * Kp + j]);
