@@ -2,6 +2,7 @@
 // kernels when K == 4 (unless the generic path is forced), the generic any-K
 // kernels otherwise.
 #include <algorithm>
+#include <vector>
 
 #include "fastpath.h"
 
@@ -14,15 +15,25 @@ bool nuc(const EpochInstance* in) { return in->path == 1; }
 int fastpath_init(EpochInstance* in) {
   in->path = (in->K == 4 && in->cfg.kernel_path == EPOCH_KERNEL_AUTO) ? 1 : 0;
   if (nuc(in) && (in->cfg.flags & (EPOCH_GRAD_BRANCH | EPOCH_GRAD_Q))) {
-    const size_t chunks = nuc_chunks(in->P, in->nuc_R);
-    const size_t bytes = chunks * in->n_nodes * in->C * 16 * sizeof(double);
-    return ensure(in->Gpart, std::max(bytes, in->Gpart.bytes));
+    in->nuc_slots = nuc_slots(in->P, in->C, in->nuc_rmin);
+    const size_t bytes = (size_t)in->nuc_slots * in->n_nodes * in->C * 16 * sizeof(double);
+    int rc = ensure(in->Gpart, std::max(bytes, in->Gpart.bytes));
+    if (rc) return rc;
+    return ensure(in->gslots, (size_t)in->n_nodes * sizeof(int32_t));
   }
   return EPOCH_OK;
 }
 void fastpath_release(EpochInstance*) {}
 int fastpath_tips_changed(EpochInstance*) { return EPOCH_OK; }
-int fastpath_tree_changed(EpochInstance*) { return EPOCH_OK; }
+int fastpath_tree_changed(EpochInstance* in) {
+  if (!nuc(in) || !in->gslots.ptr) return EPOCH_OK;
+  std::vector<int32_t> slots;
+  nuc_slots_per_node(in, slots);
+  int rc = hip_check(hipMemcpyAsync(in->gslots.ptr, slots.data(), slots.size() * sizeof(int32_t),
+                                    hipMemcpyHostToDevice, in->stream), "gslots upload");
+  if (rc) return rc;
+  return hip_check(hipStreamSynchronize(in->stream), "gslots sync");
+}
 
 #define EPOCH_PHASE(k, expr)            \
   do {                                  \
@@ -49,8 +60,8 @@ int fastpath_root(EpochInstance* in) {
 
 int fastpath_gradient(EpochInstance* in, bool want_Q) {
   if (nuc(in)) {
-    EPOCH_PHASE(3, launch_nuc_pre_grad(in, in->nuc_R));
-    EPOCH_PHASE(4, launch_grad_reduce(in, nuc_chunks(in->P, in->nuc_R)));
+    EPOCH_PHASE(3, launch_nuc_pre_grad(in));
+    EPOCH_PHASE(4, launch_grad_reduce(in, in->nuc_slots, static_cast<const int32_t*>(in->gslots.ptr)));
   } else {
     EPOCH_PHASE(3, launch_pre_generic(in));
     EPOCH_PHASE(4, launch_grad_branch_generic(in));

@@ -44,8 +44,9 @@ struct EpochInstance {
   bool eig_dirty = true;
   epochlik::TreePlan plan;
   int n_chunks = 1;  // pattern chunks of the generic gradient accumulation
-  int path = 0;      // 0 generic, 1 four-state kernels
-  int nuc_R = 8;     // pattern tiles per block in the four-state gradient
+  int path = 0;        // 0 generic, 1 four-state kernels
+  int nuc_rmin = 8;    // minimum pattern tiles per wavefront in the four-state gradient
+  int nuc_slots = 1;   // partial-sum slots per branch of the four-state gradient
 
   // device buffers (compute type T unless noted)
   epochlik::DevBuf eigT;       // V[S][Kp][Kp], Vinv[S][Kp][Kp], lre[S][Kp], lim[S][Kp]
@@ -73,6 +74,7 @@ struct EpochInstance {
   epochlik::DevBuf qscratch;   // T prefix products [nseg][C][Kp][Kp]
   epochlik::DevBuf dQ;         // double [S][Kp][Kp]
   epochlik::DevBuf seglist;    // int32 segments grouped by process: offsets [S+1], items [nseg*C]
+  epochlik::DevBuf gslots;     // int32 [n]: partial-sum slots written per branch (4-state gradient)
 
   // per-phase timing (epoch_set_timing)
   bool timing = false;
@@ -109,12 +111,13 @@ int launch_pre_generic(EpochInstance* in);
 int launch_grad_branch_generic(EpochInstance* in);
 int launch_grad_Q_generic(EpochInstance* in);
 int launch_final_sum(EpochInstance* in, int n_blocks);
-int launch_grad_reduce(EpochInstance* in, int n_chunks);
+int launch_grad_reduce(EpochInstance* in, int n_chunks, const int32_t* chunks_per_node);
 
 // 4-state kernels (kernels_nuc.hip)
 int launch_nuc_post(EpochInstance* in);
 int launch_nuc_root(EpochInstance* in);
-int launch_nuc_pre_grad(EpochInstance* in, int R);
-int nuc_chunks(int P, int R);
+int launch_nuc_pre_grad(EpochInstance* in);
+int nuc_slots(int P, int C, int rmin);
+void nuc_slots_per_node(const EpochInstance* in, std::vector<int32_t>& out);
 
 }  // namespace epochlik

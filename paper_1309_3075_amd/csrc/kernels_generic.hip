@@ -468,24 +468,39 @@ __global__ __launch_bounds__(256) void grad_G_generic_kernel(
 #pragma unroll
   for (int k = 0; k < GPT; ++k) {
     const int e = threadIdx.x + k * 256;
-    if (e < nG) Gpart[((size_t)blockIdx.y * n_nodes + v) * nG + e] = (double)g[k];
+    if (e < nG) Gpart[((size_t)v * n_chunks + blockIdx.y) * nG + e] = (double)g[k];
   }
 }
 
-// G[v] = ordered FP64 sum over chunks; d_branch[v] = sum_c <G[v][c], dP[v][c]>.
+// G[v] = FP64 sum over chunks in a fixed order; d_branch[v] = sum_c <G[v][c], dP[v][c]>.
+// Partial sums are laid out [v][chunk][nG]; thread (e, g) of the block sums
+// chunks g, g + NG, ... of element e, then the NG groups are combined in order.
 template <typename T>
 __global__ __launch_bounds__(256) void grad_reduce_branch_kernel(
-    const double* __restrict__ Gpart, const T* __restrict__ dP, int n_chunks, int n_nodes, int nG,
-    int root, double* __restrict__ G, double* __restrict__ dbranch) {
+    const double* __restrict__ Gpart, const T* __restrict__ dP, int n_slots,
+    const int32_t* __restrict__ chunks_per_node, int n_nodes, int nG, int root, double* __restrict__ G,
+    double* __restrict__ dbranch) {
   __shared__ double sm[256];
   const int v = blockIdx.x;
+  const double* src = Gpart + (size_t)v * n_slots * nG;
+  const int n_chunks = chunks_per_node ? chunks_per_node[v] : n_slots;
+  const int groups = nG >= 256 ? 1 : 256 / nG;  // nG is a multiple of 16
   double d = 0.0;
-  for (int e = threadIdx.x; e < nG; e += 256) {
+  for (int e0 = 0; e0 < nG; e0 += 256 / groups) {
+    const int e = e0 + threadIdx.x % (256 / groups);
+    const int g = threadIdx.x / (256 / groups);
     double s = 0.0;
-    if (v != root)
-      for (int k = 0; k < n_chunks; ++k) s += Gpart[((size_t)k * n_nodes + v) * nG + e];
-    G[(size_t)v * nG + e] = s;
-    d += s * (double)dP[(size_t)v * nG + e];
+    if (v != root && e < nG && g < groups)
+      for (int k = g; k < n_chunks; k += groups) s += src[(size_t)k * nG + e];
+    sm[threadIdx.x] = s;
+    __syncthreads();
+    if (g == 0 && e < nG) {
+      double tot = 0.0;
+      for (int q = 0; q < groups; ++q) tot += sm[q * (256 / groups) + threadIdx.x];
+      G[(size_t)v * nG + e] = tot;
+      d += tot * (double)dP[(size_t)v * nG + e];
+    }
+    __syncthreads();
   }
   const double tot = block_sum<256>(d, sm);
   if (threadIdx.x == 0) dbranch[v] = (v == root) ? 0.0 : tot;
@@ -702,16 +717,16 @@ int grad_branch_dispatch(EpochInstance* in) {
   }
   int rc = hip_check(hipGetLastError(), "grad_G_generic launch");
   if (rc) return rc;
-  return launch_grad_reduce(in, in->n_chunks);
+  return launch_grad_reduce(in, in->n_chunks, nullptr);
 }
 
 template <typename T>
-int grad_reduce_dispatch(EpochInstance* in, int n_chunks) {
+int grad_reduce_dispatch(EpochInstance* in, int n_slots, const int32_t* chunks_per_node) {
   const int nG = in->C * in->Kp * in->Kp;
   hipLaunchKernelGGL((grad_reduce_branch_kernel<T>), dim3(in->n_nodes), dim3(256), 0, in->stream,
                      static_cast<const double*>(in->Gpart.ptr), static_cast<const T*>(in->dPm.ptr),
-                     n_chunks, in->n_nodes, nG, in->plan.root, static_cast<double*>(in->G.ptr),
-                     static_cast<double*>(in->dbranch.ptr));
+                     n_slots, chunks_per_node, in->n_nodes, nG, in->plan.root,
+                     static_cast<double*>(in->G.ptr), static_cast<double*>(in->dbranch.ptr));
   return hip_check(hipGetLastError(), "grad_reduce_branch launch");
 }
 
@@ -736,8 +751,9 @@ int launch_final_sum(EpochInstance* in, int n_blocks) {
   return hip_check(hipGetLastError(), "final_sum launch");
 }
 
-int launch_grad_reduce(EpochInstance* in, int n_chunks) {
-  return in->fp64 ? grad_reduce_dispatch<double>(in, n_chunks) : grad_reduce_dispatch<float>(in, n_chunks);
+int launch_grad_reduce(EpochInstance* in, int n_slots, const int32_t* chunks_per_node) {
+  return in->fp64 ? grad_reduce_dispatch<double>(in, n_slots, chunks_per_node)
+                  : grad_reduce_dispatch<float>(in, n_slots, chunks_per_node);
 }
 
 int launch_pstage_generic(EpochInstance* in) {

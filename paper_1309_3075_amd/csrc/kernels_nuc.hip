@@ -1,18 +1,21 @@
 // Specialised 4-state (nucleotide) kernels, FP32 or FP64.
 //
-// Layout (shared with the generic kernels): partials [slot][c][P][4] with
-// slot = node - N; transition matrices [node][c][4][4] row-major.
+// Layout (shared with the generic kernels): partials and outside vectors
+// [slot][c][P][4] with slot = node - N; transition matrices [node][c][4][4]
+// row-major; cumulative scale exponents [slot][P].
 //
-// A block covers one internal node and 64 patterns; wavefront c of the block
-// handles rate category c, so the 4x4 matrices it multiplies by are uniform
-// across the wavefront and live in scalar registers.  The categories of a
-// pattern share one power-of-two scale factor; they agree on it through LDS.
-//   nuc_post_level : Felsenstein pruning for one tree level (Eq. 4), with the
-//                    cumulative scale exponent of each node's subtree.
+// Lane mapping: lane = (pattern, category) with the CP (power of two >= C)
+// categories of a pattern in adjacent lanes, so the per-pattern scale factor
+// (shared by all categories) and the category sums are in-group shuffles:
+// no LDS and no barriers on the hot path.  Each lane keeps its category's
+// two 4x4 matrices in registers for the whole node.  A wavefront walks R
+// consecutive tiles of 64/CP patterns and loads tile r+1 while computing
+// tile r.
+//   nuc_post_level : Felsenstein pruning for one tree level (Eq. 4) with the
+//                    cumulative power-of-two scale of every node's subtree.
 //   nuc_root       : root sum over pi and categories (text after Eq. 4), FP64.
-//   nuc_pre_level  : outside vectors of one level plus the per-branch
-//                    accumulation of dlogL/dP over R pattern tiles, reduced
-//                    across the wavefront with a reduce-scatter butterfly.
+//   nuc_pre_level  : outside vectors of one level plus the accumulation of
+//                    dlogL/dP for the two child branches of each node.
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
@@ -28,6 +31,11 @@ struct alignas(4 * sizeof(T)) V4 {
 };
 
 template <typename T>
+struct M4 {
+  T m[16];
+};
+
+template <typename T>
 __device__ inline V4<T> onehot(int st) {
   V4<T> r;
 #pragma unroll
@@ -35,29 +43,27 @@ __device__ inline V4<T> onehot(int st) {
   return r;
 }
 
-// y = M x with M row-major 4x4 at a wavefront-uniform address
 template <typename T>
-__device__ inline V4<T> matvec(const T* __restrict__ M, const V4<T>& x) {
+__device__ inline V4<T> matvec(const M4<T>& M, const V4<T>& x) {
   V4<T> y;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    T s = M[4 * i] * x.v[0];
+    T s = M.m[4 * i] * x.v[0];
 #pragma unroll
-    for (int j = 1; j < 4; ++j) s += M[4 * i + j] * x.v[j];
+    for (int j = 1; j < 4; ++j) s += M.m[4 * i + j] * x.v[j];
     y.v[i] = s;
   }
   return y;
 }
 
-// y = M^T x
 template <typename T>
-__device__ inline V4<T> matvec_t(const T* __restrict__ M, const V4<T>& x) {
+__device__ inline V4<T> matvec_t(const M4<T>& M, const V4<T>& x) {
   V4<T> y;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    T s = M[j] * x.v[0];
+    T s = M.m[j] * x.v[0];
 #pragma unroll
-    for (int i = 1; i < 4; ++i) s += M[4 * i + j] * x.v[i];
+    for (int i = 1; i < 4; ++i) s += M.m[4 * i + j] * x.v[i];
     y.v[j] = s;
   }
   return y;
@@ -71,244 +77,325 @@ __device__ inline T max4(const V4<T>& x) {
 }
 
 template <typename T>
-__device__ inline V4<T> load_child(int child, int N, int c, int C, int P, int pc, const uint8_t* __restrict__ tips,
-                                   const V4<T>* __restrict__ part) {
+__device__ inline M4<T> load_matrix(const T* __restrict__ p) {
+  M4<T> M;
+  const V4<T>* q = reinterpret_cast<const V4<T>*>(p);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const V4<T> row = q[r];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) M.m[4 * r + j] = row.v[j];
+  }
+  return M;
+}
+
+// Child vector for one (pattern, category): tip indicator or stored partial.
+template <typename T>
+__device__ inline V4<T> load_child(int child, int N, int c, int P, int pc, const uint8_t* __restrict__ tips,
+                                   const V4<T>* __restrict__ part, int C) {
   if (child < N) return onehot<T>(tips[(size_t)child * P + pc]);
   return part[((size_t)(child - N) * C + c) * P + pc];
 }
 
-__device__ inline int wave_uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+template <int CP, typename T>
+__device__ inline T group_max_cp(T v) {
+#pragma unroll
+  for (int o = 1; o < CP; o <<= 1) {
+    const T u = __shfl_xor(v, o, 64);
+    v = u > v ? u : v;
+  }
+  return v;
+}
+template <int CP, typename T>
+__device__ inline T group_sum_cp(T v) {
+#pragma unroll
+  for (int o = 1; o < CP; o <<= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum of 16 values over the lanes of a wavefront that share a category
+// (lanes differing in bits log2(CP)..5), as a reduce-scatter: halving steps
+// over lane bits 5, 4, 3, 2 (as far as they are pattern bits), then plain sums
+// over the remaining pattern bits.  On return lane l holds the total of element
+// (l >> 2) & 15 in out[0] when CP <= 4, and of elements 2 * ((l >> 3) & 7) +
+// {0, 1} in out[0..1] when CP == 8.
+template <int CP, typename T>
+__device__ inline void reduce16(const T (&v)[16], int lane, T (&out)[2]) {
+  constexpr int LOG_CP = CP == 1 ? 0 : (CP == 2 ? 1 : (CP == 4 ? 2 : 3));
+  constexpr int PB = 6 - LOG_CP;          // pattern bits of the lane index
+  constexpr int HALVE = PB < 4 ? PB : 4;  // halving steps
+  T buf[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) buf[k] = v[k];
+  int n = 16;
+#pragma unroll
+  for (int s = 0; s < HALVE; ++s) {
+    const int bit = 5 - s;  // highest pattern bit first
+    const bool hi = (lane >> bit) & 1;
+    n >>= 1;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (j < n) {
+        const T keep = hi ? buf[n + j] : buf[j];
+        const T give = hi ? buf[j] : buf[n + j];
+        buf[j] = keep + __shfl_xor(give, 1 << bit, 64);
+      }
+    }
+  }
+#pragma unroll
+  for (int s = HALVE; s < PB; ++s) {
+    const int bit = 5 - s;
+    buf[0] += __shfl_xor(buf[0], 1 << bit, 64);
+  }
+  out[0] = buf[0];
+  out[1] = (CP == 8) ? buf[1] : T(0);
+}
 
 // ---------------------------------------------------------------------------
-template <typename T, int C>
-__global__ __launch_bounds__(C * 64) void nuc_post_level_kernel(
+template <typename T, int CP>
+__global__ __launch_bounds__(256) void nuc_post_level_kernel(
     const int32_t* __restrict__ nodes, const int32_t* __restrict__ left, const int32_t* __restrict__ right,
-    const T* __restrict__ Pm, const uint8_t* __restrict__ tips, V4<T>* __restrict__ part,
-    int32_t* __restrict__ scale_cum, int N, int P) {
-  __shared__ T smax[C][64];
-  const int c = wave_uniform(threadIdx.x >> 6);
+    const T* __restrict__ Pm, const uint8_t* __restrict__ tips, const V4<T>* __restrict__ part_in,
+    V4<T>* __restrict__ part_out, const int32_t* __restrict__ scale_in, int32_t* __restrict__ scale_out,
+    int N, int P, int C, int R) {
+  constexpr int TPW = 64 / CP;  // patterns per wavefront tile
   const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int cl = lane & (CP - 1);
+  const bool cat_ok = cl < C;
+  const int c = cat_ok ? cl : 0;
   const int u = nodes[blockIdx.y];
   const int a = left[u], b = right[u];
-  const int p = blockIdx.x * 64 + lane;
-  const bool pok = p < P;
-  const int pc = pok ? p : P - 1;
-  const V4<T> xa = load_child<T>(a, N, c, C, P, pc, tips, part);
-  const V4<T> xb = load_child<T>(b, N, c, C, P, pc, tips, part);
-  const V4<T> va = matvec(Pm + ((size_t)a * C + c) * 16, xa);
-  const V4<T> vb = matvec(Pm + ((size_t)b * C + c) * 16, xb);
-  V4<T> x;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) x.v[i] = va.v[i] * vb.v[i];
-  T m = max4(x);
-  if constexpr (C > 1) {
-    smax[c][lane] = m;
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < C; ++k) m = smax[k][lane] > m ? smax[k][lane] : m;
+  const int first = (blockIdx.x * 4 + wave) * R * TPW;  // first pattern of the wavefront
+  if (first >= P) return;                                // uniform across the wavefront
+  const M4<T> Pa = load_matrix(Pm + ((size_t)a * C + c) * 16);
+  const M4<T> Pb = load_matrix(Pm + ((size_t)b * C + c) * 16);
+  const int pbase = first + lane / CP;
+  V4<T> xa, xb;
+  int sa = 0, sb = 0;
+  {
+    const int pc = pbase < P ? pbase : P - 1;
+    xa = load_child<T>(a, N, c, P, pc, tips, part_in, C);
+    xb = load_child<T>(b, N, c, P, pc, tips, part_in, C);
+    if (a >= N) sa = scale_in[(size_t)(a - N) * P + pc];
+    if (b >= N) sb = scale_in[(size_t)(b - N) * P + pc];
   }
-  const int e = scale_exponent(m);
-#pragma unroll
-  for (int i = 0; i < 4; ++i) x.v[i] = scale_by_pow2(x.v[i], e);
-  if (pok) {
-    part[((size_t)(u - N) * C + c) * P + p] = x;
-    if (c == 0) {
-      int s = e;
-      if (a >= N) s += scale_cum[(size_t)(a - N) * P + p];
-      if (b >= N) s += scale_cum[(size_t)(b - N) * P + p];
-      scale_cum[(size_t)(u - N) * P + p] = s;
+  for (int r = 0; r < R; ++r) {
+    if (first + r * TPW >= P) break;  // uniform
+    const int p = pbase + r * TPW;
+    V4<T> na = xa, nb = xb;
+    int nsa = 0, nsb = 0;
+    if (r + 1 < R) {
+      const int pn = p + TPW;
+      const int pc = pn < P ? pn : P - 1;
+      na = load_child<T>(a, N, c, P, pc, tips, part_in, C);
+      nb = load_child<T>(b, N, c, P, pc, tips, part_in, C);
+      if (a >= N) nsa = scale_in[(size_t)(a - N) * P + pc];
+      if (b >= N) nsb = scale_in[(size_t)(b - N) * P + pc];
     }
+    const V4<T> va = matvec(Pa, xa);
+    const V4<T> vb = matvec(Pb, xb);
+    V4<T> x;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x.v[i] = va.v[i] * vb.v[i];
+    T m = cat_ok ? max4(x) : T(0);
+    m = group_max_cp<CP>(m);
+    const int e = scale_exponent(m);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x.v[i] = scale_by_pow2(x.v[i], e);
+    if (p < P && cat_ok) {
+      part_out[((size_t)(u - N) * C + c) * P + p] = x;
+      if (cl == 0) scale_out[(size_t)(u - N) * P + p] = e + sa + sb;
+    }
+    xa = na;
+    xb = nb;
+    sa = nsa;
+    sb = nsb;
   }
 }
 
 // ---------------------------------------------------------------------------
-template <typename T, int C>
-__global__ __launch_bounds__(C * 64) void nuc_root_kernel(
+template <typename T, int CP>
+__global__ __launch_bounds__(256) void nuc_root_kernel(
     const V4<T>* __restrict__ rootp, const int32_t* __restrict__ scale_root, const double* __restrict__ pi,
     const double* __restrict__ cat, const double* __restrict__ weights, double* __restrict__ site,
-    double* __restrict__ block_out, int P) {
-  __shared__ double sl[C][64];
-  const int c = wave_uniform(threadIdx.x >> 6);
+    double* __restrict__ block_out, int P, int C) {
+  __shared__ double sm[4];
+  constexpr int TPW = 64 / CP;
   const int lane = threadIdx.x & 63;
-  const int p = blockIdx.x * 64 + lane;
-  const bool pok = p < P;
-  const int pc = pok ? p : P - 1;
+  const int wave = threadIdx.x >> 6;
+  const int cl = lane & (CP - 1);
+  const bool cat_ok = cl < C;
+  const int c = cat_ok ? cl : 0;
+  const int p = (blockIdx.x * 4 + wave) * TPW + lane / CP;
+  const int pc = p < P ? p : P - 1;
   const V4<T> x = rootp[(size_t)c * P + pc];
   double l = 0.0;
 #pragma unroll
   for (int i = 0; i < 4; ++i) l += pi[i] * (double)x.v[i];
-  sl[c][lane] = cat[kMaxCategories + c] * l;
-  __syncthreads();
-  if (c == 0) {
-    double L = 0.0;
-#pragma unroll
-    for (int k = 0; k < C; ++k) L += sl[k][lane];
-    double contrib = 0.0;
-    if (pok) {
-      const double s = log(L) + (double)scale_root[p] * kLn2;
-      site[p] = s;
-      contrib = weights[p] * s;
-    }
-    // wavefront sum in a fixed order
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) contrib += __shfl_xor(contrib, o, 64);
-    if (lane == 0) block_out[blockIdx.x] = contrib;
+  l = cat_ok ? cat[kMaxCategories + c] * l : 0.0;
+  const double L = group_sum_cp<CP>(l);
+  double contrib = 0.0;
+  if (p < P && cl == 0) {
+    const double s = log(L) + (double)scale_root[p] * kLn2;
+    site[p] = s;
+    contrib = weights[p] * s;
   }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) contrib += __shfl_xor(contrib, o, 64);
+  if (lane == 0) sm[wave] = contrib;
+  __syncthreads();
+  if (threadIdx.x == 0) block_out[blockIdx.x] = ((sm[0] + sm[1]) + sm[2]) + sm[3];
 }
 
 // ---------------------------------------------------------------------------
-// Reduce-scatter of 16 values over the 64 lanes: afterwards lane l holds the
-// wavefront total of element (l >> 2) & 15 (replicated on 4 lanes).
-template <typename T>
-__device__ inline T butterfly16(T (&v)[16], int lane) {
-  T w8[8];
-  {
-    const bool hi = lane & 32;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const T keep = hi ? v[8 + j] : v[j];
-      const T give = hi ? v[j] : v[8 + j];
-      w8[j] = keep + __shfl_xor(give, 32, 64);
-    }
-  }
-  T w4[4];
-  {
-    const bool hi = lane & 16;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const T keep = hi ? w8[4 + j] : w8[j];
-      const T give = hi ? w8[j] : w8[4 + j];
-      w4[j] = keep + __shfl_xor(give, 16, 64);
-    }
-  }
-  T w2[2];
-  {
-    const bool hi = lane & 8;
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const T keep = hi ? w4[2 + j] : w4[j];
-      const T give = hi ? w4[j] : w4[2 + j];
-      w2[j] = keep + __shfl_xor(give, 8, 64);
-    }
-  }
-  T w1;
-  {
-    const bool hi = lane & 4;
-    const T keep = hi ? w2[1] : w2[0];
-    const T give = hi ? w2[0] : w2[1];
-    w1 = keep + __shfl_xor(give, 4, 64);
-  }
-  w1 += __shfl_xor(w1, 2, 64);
-  w1 += __shfl_xor(w1, 1, 64);
-  return w1;
-}
-
-template <typename T, int C, int R>
-__global__ __launch_bounds__(C * 64) void nuc_pre_level_kernel(
+template <typename T, int CP>
+__global__ __launch_bounds__(256) void nuc_pre_level_kernel(
     const int32_t* __restrict__ nodes, const int32_t* __restrict__ left, const int32_t* __restrict__ right,
     const T* __restrict__ Pm, const uint8_t* __restrict__ tips, const V4<T>* __restrict__ part,
-    V4<T>* __restrict__ pre, const double* __restrict__ pi, const double* __restrict__ cat,
-    const T* __restrict__ weights, int root, int N, int P, int n_nodes, double* __restrict__ Gpart) {
-  __shared__ T sx[2][C][64];
-  __shared__ T sm[2][C][2][64];
-  const int c = wave_uniform(threadIdx.x >> 6);
+    const V4<T>* __restrict__ pre_in, V4<T>* __restrict__ pre_out, const double* __restrict__ pi,
+    const double* __restrict__ cat, const T* __restrict__ weights, int root, int N, int P, int C, int R,
+    int n_slots, double* __restrict__ Gpart) {
+  constexpr int TPW = 64 / CP;
+  __shared__ T sG[4][2][CP][16];
   const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int cl = lane & (CP - 1);
+  const bool cat_ok = cl < C;
+  const int c = cat_ok ? cl : 0;
   const int u = nodes[blockIdx.y];
   const int a = left[u], b = right[u];
-  const T* Pa = Pm + ((size_t)a * C + c) * 16;
-  const T* Pb = Pm + ((size_t)b * C + c) * 16;
-  const T wc = T(cat[kMaxCategories + c]);
-  V4<T> qroot;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) qroot.v[i] = T(pi[i]);
   T ga[16], gb[16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
     ga[k] = 0;
     gb[k] = 0;
   }
-  int buf = 0;
-  for (int r = 0; r < R; ++r) {
-    const int tile = blockIdx.x * R + r;
-    if (tile * 64 >= P) break;  // uniform across the block
-    const int p = tile * 64 + lane;
-    const bool pok = p < P;
-    const int pc = pok ? p : P - 1;
-    const V4<T> q = (u == root) ? qroot : pre[((size_t)(u - N) * C + c) * P + pc];
-    const V4<T> xa = load_child<T>(a, N, c, C, P, pc, tips, part);
-    const V4<T> xb = load_child<T>(b, N, c, C, P, pc, tips, part);
-    const V4<T> sa = matvec(Pa, xa);
-    const V4<T> sb = matvec(Pb, xb);
-    T l = 0;
+  const int first = (blockIdx.x * 4 + wave) * R * TPW;
+  if (first < P) {  // uniform across the wavefront
+    const M4<T> Pa = load_matrix(Pm + ((size_t)a * C + c) * 16);
+    const M4<T> Pb = load_matrix(Pm + ((size_t)b * C + c) * 16);
+    const T wc = cat_ok ? T(cat[kMaxCategories + c]) : T(0);
+    V4<T> qroot;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) l += q.v[i] * sa.v[i] * sb.v[i];
-    l *= wc;
-    if constexpr (C > 1) {
-      sx[buf][c][lane] = l;
-      __syncthreads();
-      l = 0;
-#pragma unroll
-      for (int k = 0; k < C; ++k) l += sx[buf][k][lane];
+    for (int i = 0; i < 4; ++i) qroot.v[i] = T(pi[i]);
+    const int pbase = first + lane / CP;
+    V4<T> q, xa, xb;
+    T w;
+    {
+      const int pc = pbase < P ? pbase : P - 1;
+      q = (u == root) ? qroot : pre_in[((size_t)(u - N) * C + c) * P + pc];
+      xa = load_child<T>(a, N, c, P, pc, tips, part, C);
+      xb = load_child<T>(b, N, c, P, pc, tips, part, C);
+      w = (pbase < P && cat_ok) ? weights[pc] : T(0);
     }
-    const T coef = (pok && l > T(0)) ? weights[p] / l : T(0);
-    const T f = coef * wc;
-    V4<T> ta, tb;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      ta.v[i] = q.v[i] * sb.v[i];
-      tb.v[i] = q.v[i] * sa.v[i];
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const T fa = f * ta.v[i], fb = f * tb.v[i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        ga[4 * i + j] += fa * xa.v[j];
-        gb[4 * i + j] += fb * xb.v[j];
+    for (int r = 0; r < R; ++r) {
+      if (first + r * TPW >= P) break;  // uniform
+      const int p = pbase + r * TPW;
+      V4<T> nq = q, na = xa, nb = xb;
+      T nw = 0;
+      if (r + 1 < R) {
+        const int pn = p + TPW;
+        const int pc = pn < P ? pn : P - 1;
+        nq = (u == root) ? qroot : pre_in[((size_t)(u - N) * C + c) * P + pc];
+        na = load_child<T>(a, N, c, P, pc, tips, part, C);
+        nb = load_child<T>(b, N, c, P, pc, tips, part, C);
+        nw = (pn < P && cat_ok) ? weights[pc] : T(0);
       }
-    }
-    V4<T> qa = matvec_t(Pa, ta);
-    V4<T> qb = matvec_t(Pb, tb);
-    T ma = max4(qa), mb = max4(qb);
-    if constexpr (C > 1) {
-      sm[buf][c][0][lane] = ma;
-      sm[buf][c][1][lane] = mb;
-      __syncthreads();
+      const V4<T> sa = matvec(Pa, xa);
+      const V4<T> sb = matvec(Pb, xb);
+      T l = 0;
 #pragma unroll
-      for (int k = 0; k < C; ++k) {
-        ma = sm[buf][k][0][lane] > ma ? sm[buf][k][0][lane] : ma;
-        mb = sm[buf][k][1][lane] > mb ? sm[buf][k][1][lane] : mb;
+      for (int i = 0; i < 4; ++i) l += q.v[i] * sa.v[i] * sb.v[i];
+      l = group_sum_cp<CP>(l * wc);
+      const T f = (l > T(0) ? w / l : T(0)) * wc;
+      V4<T> ta, tb;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        ta.v[i] = q.v[i] * sb.v[i];
+        tb.v[i] = q.v[i] * sa.v[i];
       }
-    }
-    buf ^= 1;
-    const int ea = scale_exponent(ma), eb = scale_exponent(mb);
-    if (pok) {
-      if (a >= N) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const T fa = f * ta.v[i], fb = f * tb.v[i];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          ga[4 * i + j] += fa * xa.v[j];
+          gb[4 * i + j] += fb * xb.v[j];
+        }
+      }
+      if (a >= N) {  // uniform
+        V4<T> qa = matvec_t(Pa, ta);
+        const T ma = group_max_cp<CP>(cat_ok ? max4(qa) : T(0));
+        const int ea = scale_exponent(ma);
 #pragma unroll
         for (int i = 0; i < 4; ++i) qa.v[i] = scale_by_pow2(qa.v[i], ea);
-        pre[((size_t)(a - N) * C + c) * P + p] = qa;
+        if (p < P && cat_ok) pre_out[((size_t)(a - N) * C + c) * P + p] = qa;
       }
       if (b >= N) {
+        V4<T> qb = matvec_t(Pb, tb);
+        const T mb = group_max_cp<CP>(cat_ok ? max4(qb) : T(0));
+        const int eb = scale_exponent(mb);
 #pragma unroll
         for (int i = 0; i < 4; ++i) qb.v[i] = scale_by_pow2(qb.v[i], eb);
-        pre[((size_t)(b - N) * C + c) * P + p] = qb;
+        if (p < P && cat_ok) pre_out[((size_t)(b - N) * C + c) * P + p] = qb;
       }
+      q = nq;
+      xa = na;
+      xb = nb;
+      w = nw;
     }
   }
-  const T ra = butterfly16(ga, lane);
-  const T rb = butterfly16(gb, lane);
-  if ((lane & 3) == 0) {
+  // wavefront reduce-scatter, then the four wavefronts of the block in order
+  T ra[2], rb[2];
+  reduce16<CP>(ga, lane, ra);
+  reduce16<CP>(gb, lane, rb);
+  if constexpr (CP == 8) {
+    const int e0 = 2 * ((lane >> 3) & 7);
+    sG[wave][0][cl][e0] = ra[0];
+    sG[wave][0][cl][e0 + 1] = ra[1];
+    sG[wave][1][cl][e0] = rb[0];
+    sG[wave][1][cl][e0 + 1] = rb[1];
+  } else {
+    // the halving steps run over lane bits 5..2, so lane l holds element
+    // (l >> 2) & 15; lane bits below 2 that are pattern bits were summed and
+    // replicate it: only the lane with those bits clear stores
     const int e = (lane >> 2) & 15;
-    const size_t nG = (size_t)C * 16;
-    Gpart[((size_t)blockIdx.x * n_nodes + a) * nG + c * 16 + e] = (double)ra;
-    Gpart[((size_t)blockIdx.x * n_nodes + b) * nG + c * 16 + e] = (double)rb;
+    if ((lane & 3 & ~(CP - 1)) == 0) {
+      sG[wave][0][cl][e] = ra[0];
+      sG[wave][1][cl][e] = rb[0];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * CP * 16) {
+    const int side = threadIdx.x / (CP * 16);
+    const int rem = threadIdx.x % (CP * 16);
+    const int cc = rem / 16, e = rem % 16;
+    if (cc < C) {
+      const T s = ((sG[0][side][cc][e] + sG[1][side][cc][e]) + sG[2][side][cc][e]) + sG[3][side][cc][e];
+      const int v = side == 0 ? a : b;
+      Gpart[((size_t)v * n_slots + blockIdx.x) * ((size_t)C * 16) + cc * 16 + e] = (double)s;
+    }
   }
 }
 
-template <typename T, int C>
-int nuc_post_dispatch_c(EpochInstance* in) {
+int cp_of(int C) { return C <= 1 ? 1 : (C <= 2 ? 2 : (C <= 4 ? 4 : 8)); }
+
+// tiles per wavefront for a level with n_l nodes: enough wavefronts to fill the chip
+int tiles_per_wave(int tiles, int n_l, int r_min, int r_max) {
+  const long target_waves = 8192;
+  const long waves_per_node = (target_waves + n_l - 1) / n_l;
+  long R = (tiles + waves_per_node - 1) / waves_per_node;
+  if (R < r_min) R = r_min;
+  if (R > r_max) R = r_max;
+  return (int)R;
+}
+
+template <typename T, int CP>
+int post_dispatch_cp(EpochInstance* in) {
   const auto& pl = in->plan;
-  const int tiles = (in->P + 63) / 64;
+  constexpr int TPW = 64 / CP;
+  const int tiles = (in->P + TPW - 1) / TPW;
   const T* Pm = static_cast<const T*>(in->Pm.ptr);
   const uint8_t* tips = static_cast<const uint8_t*>(in->tips.ptr);
   V4<T>* part = static_cast<V4<T>*>(in->partials.ptr);
@@ -316,33 +403,45 @@ int nuc_post_dispatch_c(EpochInstance* in) {
   for (int l = 1; l <= pl.n_levels; ++l) {
     const int n_l = pl.level_offset[l + 1] - pl.level_offset[l];
     if (!n_l) continue;
-    hipLaunchKernelGGL((nuc_post_level_kernel<T, C>), dim3(tiles, n_l), dim3(C * 64), 0, in->stream,
-                       in->d_level_nodes + pl.level_offset[l], in->d_left, in->d_right, Pm, tips, part, sc,
-                       in->N, in->P);
+    const int R = tiles_per_wave(tiles, n_l, 1, 16);
+    const int blocks = (tiles + 4 * R - 1) / (4 * R);
+    hipLaunchKernelGGL((nuc_post_level_kernel<T, CP>), dim3(blocks, n_l), dim3(256), 0, in->stream,
+                       in->d_level_nodes + pl.level_offset[l], in->d_left, in->d_right, Pm, tips, part, part,
+                       sc, sc, in->N, in->P, in->C, R);
   }
   return hip_check(hipGetLastError(), "nuc_post_level launch");
 }
 
-template <typename T, int C>
-int nuc_root_dispatch_c(EpochInstance* in) {
+template <typename T, int CP>
+int root_dispatch_cp(EpochInstance* in) {
   const auto& pl = in->plan;
-  const int tiles = (in->P + 63) / 64;
+  constexpr int TPW = 64 / CP;
+  const int blocks = (in->P + 4 * TPW - 1) / (4 * TPW);
   const V4<T>* part = static_cast<const V4<T>*>(in->partials.ptr);
   const int32_t* sc = static_cast<const int32_t*>(in->scales.ptr);
   const size_t slot = pl.root - in->N;
-  hipLaunchKernelGGL((nuc_root_kernel<T, C>), dim3(tiles), dim3(C * 64), 0, in->stream,
-                     part + slot * C * (size_t)in->P, sc + slot * (size_t)in->P,
+  hipLaunchKernelGGL((nuc_root_kernel<T, CP>), dim3(blocks), dim3(256), 0, in->stream,
+                     part + slot * in->C * (size_t)in->P, sc + slot * (size_t)in->P,
                      static_cast<const double*>(in->pi.ptr), static_cast<const double*>(in->cat.ptr),
                      static_cast<const double*>(in->weights.ptr), static_cast<double*>(in->site.ptr),
-                     static_cast<double*>(in->blocksum.ptr), in->P);
-  return hip_check(hipGetLastError(), "nuc_root launch");
+                     static_cast<double*>(in->blocksum.ptr), in->P, in->C);
+  int rc = hip_check(hipGetLastError(), "nuc_root launch");
+  if (rc) return rc;
+  return launch_final_sum(in, blocks);
 }
 
-template <typename T, int C>
-int nuc_pre_dispatch_c(EpochInstance* in, int R) {
+int pre_blocks(const EpochInstance* in, int n_l) {
+  const int TPW = 64 / cp_of(in->C);
+  const int tiles = (in->P + TPW - 1) / TPW;
+  const int R = tiles_per_wave(tiles, n_l, in->nuc_rmin, 64);
+  return (tiles + 4 * R - 1) / (4 * R);
+}
+
+template <typename T, int CP>
+int pre_dispatch_cp(EpochInstance* in) {
   const auto& pl = in->plan;
-  const int tiles = (in->P + 63) / 64;
-  const int chunks = (tiles + R - 1) / R;
+  constexpr int TPW = 64 / CP;
+  const int tiles = (in->P + TPW - 1) / TPW;
   const T* Pm = static_cast<const T*>(in->Pm.ptr);
   const uint8_t* tips = static_cast<const uint8_t*>(in->tips.ptr);
   const V4<T>* part = static_cast<const V4<T>*>(in->partials.ptr);
@@ -351,81 +450,68 @@ int nuc_pre_dispatch_c(EpochInstance* in, int R) {
   for (int l = pl.n_levels; l >= 1; --l) {
     const int n_l = pl.level_offset[l + 1] - pl.level_offset[l];
     if (!n_l) continue;
-#define EPOCH_NUC_PRE(RR)                                                                                  \
-  hipLaunchKernelGGL((nuc_pre_level_kernel<T, C, RR>), dim3(chunks, n_l), dim3(C * 64), 0, in->stream,        \
-                     in->d_level_nodes + pl.level_offset[l], in->d_left, in->d_right, Pm, tips, part, pre,      \
-                     static_cast<const double*>(in->pi.ptr), static_cast<const double*>(in->cat.ptr), w,       \
-                     pl.root, in->N, in->P, in->n_nodes, static_cast<double*>(in->Gpart.ptr))
-    switch (R) {
-      case 1: EPOCH_NUC_PRE(1); break;
-      case 2: EPOCH_NUC_PRE(2); break;
-      case 4: EPOCH_NUC_PRE(4); break;
-      case 8: EPOCH_NUC_PRE(8); break;
-      default: EPOCH_NUC_PRE(16); break;
-    }
-#undef EPOCH_NUC_PRE
+    const int R = tiles_per_wave(tiles, n_l, in->nuc_rmin, 64);
+    const int blocks = pre_blocks(in, n_l);
+    hipLaunchKernelGGL((nuc_pre_level_kernel<T, CP>), dim3(blocks, n_l), dim3(256), 0, in->stream,
+                       in->d_level_nodes + pl.level_offset[l], in->d_left, in->d_right, Pm, tips, part, pre, pre,
+                       static_cast<const double*>(in->pi.ptr), static_cast<const double*>(in->cat.ptr), w,
+                       pl.root, in->N, in->P, in->C, R, in->nuc_slots, static_cast<double*>(in->Gpart.ptr));
   }
   return hip_check(hipGetLastError(), "nuc_pre_level launch");
 }
 
-template <typename T>
-int nuc_post_dispatch(EpochInstance* in) {
-  switch (in->C) {
-    case 1: return nuc_post_dispatch_c<T, 1>(in);
-    case 2: return nuc_post_dispatch_c<T, 2>(in);
-    case 3: return nuc_post_dispatch_c<T, 3>(in);
-    case 4: return nuc_post_dispatch_c<T, 4>(in);
-    case 5: return nuc_post_dispatch_c<T, 5>(in);
-    case 6: return nuc_post_dispatch_c<T, 6>(in);
-    case 7: return nuc_post_dispatch_c<T, 7>(in);
-    default: return nuc_post_dispatch_c<T, 8>(in);
-  }
-}
-
-template <typename T>
-int nuc_root_dispatch(EpochInstance* in) {
-  switch (in->C) {
-    case 1: return nuc_root_dispatch_c<T, 1>(in);
-    case 2: return nuc_root_dispatch_c<T, 2>(in);
-    case 3: return nuc_root_dispatch_c<T, 3>(in);
-    case 4: return nuc_root_dispatch_c<T, 4>(in);
-    case 5: return nuc_root_dispatch_c<T, 5>(in);
-    case 6: return nuc_root_dispatch_c<T, 6>(in);
-    case 7: return nuc_root_dispatch_c<T, 7>(in);
-    default: return nuc_root_dispatch_c<T, 8>(in);
-  }
-}
-
-template <typename T>
-int nuc_pre_dispatch(EpochInstance* in, int R) {
-  switch (in->C) {
-    case 1: return nuc_pre_dispatch_c<T, 1>(in, R);
-    case 2: return nuc_pre_dispatch_c<T, 2>(in, R);
-    case 3: return nuc_pre_dispatch_c<T, 3>(in, R);
-    case 4: return nuc_pre_dispatch_c<T, 4>(in, R);
-    case 5: return nuc_pre_dispatch_c<T, 5>(in, R);
-    case 6: return nuc_pre_dispatch_c<T, 6>(in, R);
-    case 7: return nuc_pre_dispatch_c<T, 7>(in, R);
-    default: return nuc_pre_dispatch_c<T, 8>(in, R);
-  }
-}
-
 }  // namespace
 
+// Partial-sum slots per branch of the 4-state gradient: the block count of a
+// level launched with the smallest tile count per wavefront.
+int nuc_slots(int P, int C, int rmin) {
+  const int TPW = 64 / cp_of(C);
+  const int tiles = (P + TPW - 1) / TPW;
+  return (tiles + 4 * rmin - 1) / (4 * rmin);
+}
+
+// Number of partial-sum slots each branch receives from the gradient pass
+// (the block count of its parent's level), host [n_nodes].
+void nuc_slots_per_node(const EpochInstance* in, std::vector<int32_t>& out) {
+  const auto& pl = in->plan;
+  out.assign(in->n_nodes, 0);
+  for (int l = 1; l <= pl.n_levels; ++l) {
+    const int n_l = pl.level_offset[l + 1] - pl.level_offset[l];
+    if (!n_l) continue;
+    const int blocks = pre_blocks(in, n_l);
+    for (int k = pl.level_offset[l]; k < pl.level_offset[l + 1]; ++k) {
+      const int u = pl.level_nodes[k];
+      out[pl.left[u]] = blocks;
+      out[pl.right[u]] = blocks;
+    }
+  }
+}
+
 int launch_nuc_post(EpochInstance* in) {
-  return in->fp64 ? nuc_post_dispatch<double>(in) : nuc_post_dispatch<float>(in);
+  switch (cp_of(in->C)) {
+    case 1: return in->fp64 ? post_dispatch_cp<double, 1>(in) : post_dispatch_cp<float, 1>(in);
+    case 2: return in->fp64 ? post_dispatch_cp<double, 2>(in) : post_dispatch_cp<float, 2>(in);
+    case 4: return in->fp64 ? post_dispatch_cp<double, 4>(in) : post_dispatch_cp<float, 4>(in);
+    default: return in->fp64 ? post_dispatch_cp<double, 8>(in) : post_dispatch_cp<float, 8>(in);
+  }
 }
 
 int launch_nuc_root(EpochInstance* in) {
-  int rc = in->fp64 ? nuc_root_dispatch<double>(in) : nuc_root_dispatch<float>(in);
-  if (rc) return rc;
-  return launch_final_sum(in, (in->P + 63) / 64);
+  switch (cp_of(in->C)) {
+    case 1: return in->fp64 ? root_dispatch_cp<double, 1>(in) : root_dispatch_cp<float, 1>(in);
+    case 2: return in->fp64 ? root_dispatch_cp<double, 2>(in) : root_dispatch_cp<float, 2>(in);
+    case 4: return in->fp64 ? root_dispatch_cp<double, 4>(in) : root_dispatch_cp<float, 4>(in);
+    default: return in->fp64 ? root_dispatch_cp<double, 8>(in) : root_dispatch_cp<float, 8>(in);
+  }
 }
 
-int launch_nuc_pre_grad(EpochInstance* in, int R) {
-  return in->fp64 ? nuc_pre_dispatch<double>(in, R) : nuc_pre_dispatch<float>(in, R);
+int launch_nuc_pre_grad(EpochInstance* in) {
+  switch (cp_of(in->C)) {
+    case 1: return in->fp64 ? pre_dispatch_cp<double, 1>(in) : pre_dispatch_cp<float, 1>(in);
+    case 2: return in->fp64 ? pre_dispatch_cp<double, 2>(in) : pre_dispatch_cp<float, 2>(in);
+    case 4: return in->fp64 ? pre_dispatch_cp<double, 4>(in) : pre_dispatch_cp<float, 4>(in);
+    default: return in->fp64 ? pre_dispatch_cp<double, 8>(in) : pre_dispatch_cp<float, 8>(in);
+  }
 }
-
-int nuc_chunks(int P, int R) { return ((P + 63) / 64 + R - 1) / R; }
 
 }  // namespace epochlik

@@ -37,7 +37,14 @@ RANDOM_CASES = [
     (106, 11, 40, 19, 1, 6, 4, False, 0.0, 0.0),
     (107, 10, 61, 70, 1, 4, 4, True, 0.0, 0.0),
     (108, 6, 64, 33, 2, 2, 1, True, 0.0, 0.1),
+    # 4-state cases for every category-group width of the specialised kernels
+    (109, 17, 4, 200, 1, 2, 2, True, 0.1, 0.0),
+    (110, 8, 4, 150, 2, 3, 2, False, 0.0, 0.05),
+    (111, 12, 4, 333, 3, 2, 2, True, 0.2, 0.0),
+    (112, 10, 4, 70, 5, 3, 3, True, 0.0, 0.0),
+    (113, 9, 4, 90, 8, 2, 2, False, 0.1, 0.1),
 ]
+GRAD_CASES = RANDOM_CASES[:6] + RANDOM_CASES[8:]
 
 
 def _prob(case):
@@ -81,7 +88,7 @@ def test_C1_full_size(precision, kernel):
 
 @pytest.mark.parametrize("kernel", ["generic", "auto"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("case", RANDOM_CASES[:6], ids=[f"K{c[2]}_n{c[1]}" for c in RANDOM_CASES[:6]])
+@pytest.mark.parametrize("case", GRAD_CASES, ids=[f"K{c[2]}_n{c[1]}_C{c[4]}" for c in GRAD_CASES])
 def test_gradients_against_oracle(case, precision, kernel):
     prob = _prob(case)
     with from_problem(prob, precision, grad_branch=True, grad_Q=True, kernel=kernel, use_pi=False) as lik:
@@ -132,3 +139,32 @@ def test_eigensystem_residual_warning():
         wrong[0] += 0.1
         res_bad = lik.set_eigensystem(0, e.V, e.Vinv, wrong, None, prob.Q[0])
         assert res_bad > 1e-3
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_C2_tree_reduced_patterns(precision):
+    """The full 512-taxon C2 tree and model, 3000 simulated patterns, logL + branch gradients."""
+    prob = W.make_config(2, n_patterns=3000)
+    with from_problem(prob, precision, grad_branch=True) as lik:
+        logL = lik.log_likelihood()
+        db, _ = lik.gradient()
+    want = O.log_likelihood(prob)
+    ref_b, _ = O.gradient(prob, wrt=("branch",))
+    assert rel(logL, want) <= TOL_LOGL[precision], rel(logL, want)
+    assert grad_rel(db, ref_b) <= TOL_GRAD[precision], grad_rel(db, ref_b)
+
+
+def test_repeat_evaluations_are_bitwise_identical():
+    """No float atomics: the same inputs give the same bits on every evaluation."""
+    prob = W.make_config(2, n_tips=64, n_patterns=5000)
+    with from_problem(prob, "fp32", grad_branch=True) as lik:
+        out = []
+        for _ in range(3):
+            lik.update_transition_matrices()
+            lik.update_partials()
+            logL = lik.root_log_likelihood()
+            db, _ = lik.gradient()
+            out.append((logL, db.copy()))
+    for logL, db in out[1:]:
+        assert logL == out[0][0]
+        assert np.array_equal(db, out[0][1])
