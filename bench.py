@@ -164,6 +164,12 @@ def main():
         "logL": logL,
     }
 
+    from paper_1309_3075_amd import _abi
+    probe = {k: round(_abi.bandwidth_probe(1 << 31, k, 20), 1) for k in ("copy", "read", "write")}
+    result["measured_hbm_GBps"] = probe
+    result["roofline"]["frac_of_measured_copy"] = round(achieved / probe["copy"], 4)
+    log(f"bench: bandwidth probe {probe}")
+
     if not args.no_cpu_baseline:
         sample = args.cpu_sample or min(prob.n_patterns, {1: 1000, 2: 2000, 3: 500, 4: 1}.get(args.config, 1000))
         log(f"bench: cpu baseline on {sample} patterns ...")

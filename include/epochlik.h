@@ -183,6 +183,13 @@ int epoch_set_timing(EpochInstance* inst, int32_t enable);
  * each (either may be NULL).  Synchronises the stream. */
 int epoch_get_timing(EpochInstance* inst, double* ms_out, int64_t* counts_out);
 
+/* Attainable HBM bandwidth on the current device: a plain stream over a
+ * library-allocated buffer of `bytes` (1 MiB .. 64 GiB), repeated `iters`
+ * times on the default stream and timed with HIP events.  kind: 0 = copy
+ * (counts read + write bytes), 1 = read-only, 2 = write-only.  *gbs receives
+ * GB/s (1e9 bytes per second).  Allocates and frees its own buffers. */
+int epoch_bandwidth_probe(int64_t bytes, int32_t kind, int32_t iters, double* gbs);
+
 /* Host planner only (no device work, usable without a GPU): the per-interval
  * segments of every branch, parent side first.
  *   seg_offset: host [2N] out (CSR offsets indexed by child node);

@@ -35,7 +35,7 @@ EXPORTED = [
     "epoch_set_pattern_weights", "epoch_set_categories", "epoch_set_root_frequencies",
     "set_epoch_eigensystems", "set_tree_epochs", "update_transition_matrices", "update_partials",
     "root_log_likelihood", "log_likelihood_gradient", "epoch_get_transition_matrices",
-    "epoch_plan_segments", "epoch_set_timing", "epoch_get_timing",
+    "epoch_plan_segments", "epoch_set_timing", "epoch_get_timing", "epoch_bandwidth_probe",
 ]
 PHASES = ["transition_matrices", "post_order", "root", "pre_order_dP", "grad_reduce", "grad_Q"]
 
@@ -98,6 +98,7 @@ def load() -> ctypes.CDLL:
         "epoch_get_transition_matrices": (i32, [P, dp]),
         "epoch_plan_segments": (i32, [i32, ip, dp, i32, dp, ip, i32, i32, ip, ip, dp, ip]),
         "epoch_set_timing": (i32, [P, i32]),
+        "epoch_bandwidth_probe": (i32, [ctypes.c_int64, i32, i32, dp]),
         "epoch_get_timing": (i32, [P, dp, ctypes.POINTER(ctypes.c_int64)]),
     }
     for name, (res, args) in sig.items():
@@ -160,3 +161,12 @@ def plan_segments(parent, height, boundaries, interval_process, n_processes):
                                   n_processes, cap, _ip(off), _ip(proc), _dp(tim), ctypes.byref(nseg)))
     n = nseg.value
     return off, proc[:n].copy(), tim[:n].copy()
+
+
+def bandwidth_probe(nbytes: int = 1 << 31, kind: str = "copy", iters: int = 20) -> float:
+    """Measured GB/s of a plain copy / read / write stream on the current device."""
+    lib = load()
+    out = ctypes.c_double(0.0)
+    check(lib.epoch_bandwidth_probe(int(nbytes), {"copy": 0, "read": 1, "write": 2}[kind], iters,
+                                    ctypes.byref(out)))
+    return out.value

@@ -97,19 +97,42 @@ __device__ inline V4<T> load_child(int child, int N, int c, int P, int pc, const
   return part[((size_t)(child - N) * C + c) * P + pc];
 }
 
+// Lane exchange inside groups of CP adjacent lanes.  Offsets 1 and 2 use DPP
+// quad permutations (no LDS traffic); offset 4 (CP = 8 only) uses ds_bpermute.
+template <int OFF>
+__device__ inline float xor_lanes(float v) {
+  if constexpr (OFF == 1)
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+  else if constexpr (OFF == 2)
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
+  else
+    return __shfl_xor(v, OFF, 64);
+}
+template <int OFF>
+__device__ inline double xor_lanes(double v) {
+  if constexpr (OFF == 1 || OFF == 2) {
+    const long long b = __double_as_longlong(v);
+    const int ctrl = OFF == 1 ? 0xB1 : 0x4E;
+    const int l = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), ctrl, 0xF, 0xF, false);
+    const int h = __builtin_amdgcn_mov_dpp((int)(b >> 32), ctrl, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)h << 32) | (unsigned int)l);
+  } else {
+    return __shfl_xor(v, OFF, 64);
+  }
+}
+
 template <int CP, typename T>
 __device__ inline T group_max_cp(T v) {
-#pragma unroll
-  for (int o = 1; o < CP; o <<= 1) {
-    const T u = __shfl_xor(v, o, 64);
-    v = u > v ? u : v;
-  }
+  if constexpr (CP >= 2) { const T u = xor_lanes<1>(v); v = u > v ? u : v; }
+  if constexpr (CP >= 4) { const T u = xor_lanes<2>(v); v = u > v ? u : v; }
+  if constexpr (CP >= 8) { const T u = xor_lanes<4>(v); v = u > v ? u : v; }
   return v;
 }
 template <int CP, typename T>
 __device__ inline T group_sum_cp(T v) {
-#pragma unroll
-  for (int o = 1; o < CP; o <<= 1) v += __shfl_xor(v, o, 64);
+  if constexpr (CP >= 2) v += xor_lanes<1>(v);
+  if constexpr (CP >= 4) v += xor_lanes<2>(v);
+  if constexpr (CP >= 8) v += xor_lanes<4>(v);
   return v;
 }
 
@@ -151,7 +174,96 @@ __device__ inline void reduce16(const T (&v)[16], int lane, T (&out)[2]) {
   out[1] = (CP == 8) ? buf[1] : T(0);
 }
 
+// Raw per-lane data of one child for one tile: the tip state byte, or the
+// stored partial (and its cumulative scale for the post-order pass).  The
+// conversion of a tip state to its indicator vector happens at use, so loads
+// prefetched for the next tile stay in flight.
+template <typename T, bool TIP>
+struct ChildBuf;
+template <typename T>
+struct ChildBuf<T, true> {
+  int st;
+};
+template <typename T>
+struct ChildBuf<T, false> {
+  V4<T> x;
+  int sc;
+};
+
+template <typename T, bool TIP, bool SCALE>
+__device__ inline void fetch_child(ChildBuf<T, TIP>& cb, int child, int N, int c, int C, int P, int pc,
+                                   const uint8_t* __restrict__ tips, const V4<T>* __restrict__ part,
+                                   const int32_t* __restrict__ scale_in) {
+  if constexpr (TIP) {
+    cb.st = tips[(size_t)child * P + pc];
+  } else {
+    cb.x = part[((size_t)(child - N) * C + c) * P + pc];
+    if constexpr (SCALE) cb.sc = scale_in[(size_t)(child - N) * P + pc];
+  }
+}
+
+template <typename T, bool TIP>
+__device__ inline V4<T> child_vec(const ChildBuf<T, TIP>& cb) {
+  if constexpr (TIP)
+    return onehot<T>(cb.st);
+  else
+    return cb.x;
+}
+
+template <typename T, bool TIP>
+__device__ inline int child_scale(const ChildBuf<T, TIP>& cb) {
+  if constexpr (TIP)
+    return 0;
+  else
+    return cb.sc;
+}
+
 // ---------------------------------------------------------------------------
+template <typename T, int CP, bool TA, bool TB>
+__device__ inline void post_tiles(int u, int a, int b, int N, int P, int C, int c, int cl, bool cat_ok,
+                                  int first, int R, const M4<T>& Pa, const M4<T>& Pb,
+                                  const uint8_t* __restrict__ tips, const V4<T>* __restrict__ part_in,
+                                  V4<T>* __restrict__ part_out, const int32_t* __restrict__ scale_in,
+                                  int32_t* __restrict__ scale_out) {
+  constexpr int TPW = 64 / CP;
+  const int pbase = first + (int)(threadIdx.x & 63) / CP;
+  ChildBuf<T, TA> ca;
+  ChildBuf<T, TB> cb;
+  {
+    const int pc = pbase < P ? pbase : P - 1;
+    fetch_child<T, TA, true>(ca, a, N, c, C, P, pc, tips, part_in, scale_in);
+    fetch_child<T, TB, true>(cb, b, N, c, C, P, pc, tips, part_in, scale_in);
+  }
+  for (int r = 0; r < R; ++r) {
+    if (first + r * TPW >= P) break;  // uniform
+    const int p = pbase + r * TPW;
+    ChildBuf<T, TA> na = ca;
+    ChildBuf<T, TB> nb = cb;
+    if (r + 1 < R) {
+      const int pn = p + TPW;
+      const int pc = pn < P ? pn : P - 1;
+      fetch_child<T, TA, true>(na, a, N, c, C, P, pc, tips, part_in, scale_in);
+      fetch_child<T, TB, true>(nb, b, N, c, C, P, pc, tips, part_in, scale_in);
+    }
+    const V4<T> va = matvec(Pa, child_vec(ca));
+    const V4<T> vb = matvec(Pb, child_vec(cb));
+    V4<T> x;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x.v[i] = va.v[i] * vb.v[i];
+    T m = cat_ok ? max4(x) : T(0);
+    m = group_max_cp<CP>(m);
+    const int e = scale_exponent(m);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x.v[i] = scale_by_pow2(x.v[i], e);
+    if (p < P && cat_ok) {
+      part_out[((size_t)(u - N) * C + c) * P + p] = x;
+      if (cl == 0) scale_out[(size_t)(u - N) * P + p] = e + child_scale(ca) + child_scale(cb);
+    }
+    ca = na;
+    cb = nb;
+  }
+}
+
 template <typename T, int CP>
 __global__ __launch_bounds__(256) void nuc_post_level_kernel(
     const int32_t* __restrict__ nodes, const int32_t* __restrict__ left, const int32_t* __restrict__ right,
@@ -170,48 +282,15 @@ __global__ __launch_bounds__(256) void nuc_post_level_kernel(
   if (first >= P) return;                                // uniform across the wavefront
   const M4<T> Pa = load_matrix(Pm + ((size_t)a * C + c) * 16);
   const M4<T> Pb = load_matrix(Pm + ((size_t)b * C + c) * 16);
-  const int pbase = first + lane / CP;
-  V4<T> xa, xb;
-  int sa = 0, sb = 0;
-  {
-    const int pc = pbase < P ? pbase : P - 1;
-    xa = load_child<T>(a, N, c, P, pc, tips, part_in, C);
-    xb = load_child<T>(b, N, c, P, pc, tips, part_in, C);
-    if (a >= N) sa = scale_in[(size_t)(a - N) * P + pc];
-    if (b >= N) sb = scale_in[(size_t)(b - N) * P + pc];
-  }
-  for (int r = 0; r < R; ++r) {
-    if (first + r * TPW >= P) break;  // uniform
-    const int p = pbase + r * TPW;
-    V4<T> na = xa, nb = xb;
-    int nsa = 0, nsb = 0;
-    if (r + 1 < R) {
-      const int pn = p + TPW;
-      const int pc = pn < P ? pn : P - 1;
-      na = load_child<T>(a, N, c, P, pc, tips, part_in, C);
-      nb = load_child<T>(b, N, c, P, pc, tips, part_in, C);
-      if (a >= N) nsa = scale_in[(size_t)(a - N) * P + pc];
-      if (b >= N) nsb = scale_in[(size_t)(b - N) * P + pc];
-    }
-    const V4<T> va = matvec(Pa, xa);
-    const V4<T> vb = matvec(Pb, xb);
-    V4<T> x;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) x.v[i] = va.v[i] * vb.v[i];
-    T m = cat_ok ? max4(x) : T(0);
-    m = group_max_cp<CP>(m);
-    const int e = scale_exponent(m);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) x.v[i] = scale_by_pow2(x.v[i], e);
-    if (p < P && cat_ok) {
-      part_out[((size_t)(u - N) * C + c) * P + p] = x;
-      if (cl == 0) scale_out[(size_t)(u - N) * P + p] = e + sa + sb;
-    }
-    xa = na;
-    xb = nb;
-    sa = nsa;
-    sb = nsb;
-  }
+  const bool ta = a < N, tb = b < N;  // uniform
+  if (ta && tb)
+    post_tiles<T, CP, true, true>(u, a, b, N, P, C, c, cl, cat_ok, first, R, Pa, Pb, tips, part_in, part_out, scale_in, scale_out);
+  else if (ta)
+    post_tiles<T, CP, true, false>(u, a, b, N, P, C, c, cl, cat_ok, first, R, Pa, Pb, tips, part_in, part_out, scale_in, scale_out);
+  else if (tb)
+    post_tiles<T, CP, false, true>(u, a, b, N, P, C, c, cl, cat_ok, first, R, Pa, Pb, tips, part_in, part_out, scale_in, scale_out);
+  else
+    post_tiles<T, CP, false, false>(u, a, b, N, P, C, c, cl, cat_ok, first, R, Pa, Pb, tips, part_in, part_out, scale_in, scale_out);
 }
 
 // ---------------------------------------------------------------------------
@@ -249,6 +328,105 @@ __global__ __launch_bounds__(256) void nuc_root_kernel(
 }
 
 // ---------------------------------------------------------------------------
+template <typename T, int CP, bool TA, bool TB, bool ROOT>
+__device__ inline void pre_tiles(int u, int a, int b, int N, int P, int C, int c, bool cat_ok, int first,
+                                 int R, const M4<T>& Pa, const M4<T>& Pb, T wc, const V4<T>& qroot,
+                                 const uint8_t* __restrict__ tips, const V4<T>* __restrict__ part,
+                                 const V4<T>* __restrict__ pre_in, V4<T>* __restrict__ pre_out,
+                                 const T* __restrict__ weights, T (&ga)[16], T (&gb)[16]) {
+  constexpr int TPW = 64 / CP;
+  const int pbase = first + (int)(threadIdx.x & 63) / CP;
+  ChildBuf<T, TA> ca;
+  ChildBuf<T, TB> cb;
+  V4<T> q = qroot;
+  T w;
+  {
+    const int pc = pbase < P ? pbase : P - 1;
+    if constexpr (!ROOT) q = pre_in[((size_t)(u - N) * C + c) * P + pc];
+    fetch_child<T, TA, false>(ca, a, N, c, C, P, pc, tips, part, nullptr);
+    fetch_child<T, TB, false>(cb, b, N, c, C, P, pc, tips, part, nullptr);
+    w = weights[pc];
+  }
+  for (int r = 0; r < R; ++r) {
+    if (first + r * TPW >= P) break;  // uniform
+    const int p = pbase + r * TPW;
+    ChildBuf<T, TA> na = ca;
+    ChildBuf<T, TB> nb = cb;
+    V4<T> nq = q;
+    T nw = w;
+    if (r + 1 < R) {
+      const int pn = p + TPW;
+      const int pc = pn < P ? pn : P - 1;
+      if constexpr (!ROOT) nq = pre_in[((size_t)(u - N) * C + c) * P + pc];
+      fetch_child<T, TA, false>(na, a, N, c, C, P, pc, tips, part, nullptr);
+      fetch_child<T, TB, false>(nb, b, N, c, C, P, pc, tips, part, nullptr);
+      nw = weights[pc];
+    }
+    const V4<T> xa = child_vec(ca);
+    const V4<T> xb = child_vec(cb);
+    const V4<T> sa = matvec(Pa, xa);
+    const V4<T> sb = matvec(Pb, xb);
+    T l = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) l += q.v[i] * sa.v[i] * sb.v[i];
+    l = group_sum_cp<CP>(l * wc);
+    const T wt = (p < P && cat_ok) ? w : T(0);
+    const T f = (l > T(0) ? wt / l : T(0)) * wc;
+    V4<T> ta, tb;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      ta.v[i] = q.v[i] * sb.v[i];
+      tb.v[i] = q.v[i] * sa.v[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const T fa = f * ta.v[i], fb = f * tb.v[i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        ga[4 * i + j] += fa * xa.v[j];
+        gb[4 * i + j] += fb * xb.v[j];
+      }
+    }
+    if constexpr (!TA) {
+      V4<T> qa = matvec_t(Pa, ta);
+      const T ma = group_max_cp<CP>(cat_ok ? max4(qa) : T(0));
+      const int ea = scale_exponent(ma);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) qa.v[i] = scale_by_pow2(qa.v[i], ea);
+      if (p < P && cat_ok) pre_out[((size_t)(a - N) * C + c) * P + p] = qa;
+    }
+    if constexpr (!TB) {
+      V4<T> qb = matvec_t(Pb, tb);
+      const T mb = group_max_cp<CP>(cat_ok ? max4(qb) : T(0));
+      const int eb = scale_exponent(mb);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) qb.v[i] = scale_by_pow2(qb.v[i], eb);
+      if (p < P && cat_ok) pre_out[((size_t)(b - N) * C + c) * P + p] = qb;
+    }
+    ca = na;
+    cb = nb;
+    q = nq;
+    w = nw;
+  }
+}
+
+template <typename T, int CP, bool ROOT>
+__device__ inline void pre_dispatch_kind(int u, int a, int b, int N, int P, int C, int c, bool cat_ok, int first,
+                                         int R, const M4<T>& Pa, const M4<T>& Pb, T wc, const V4<T>& qroot,
+                                         const uint8_t* __restrict__ tips, const V4<T>* __restrict__ part,
+                                         const V4<T>* __restrict__ pre_in, V4<T>* __restrict__ pre_out,
+                                         const T* __restrict__ weights, T (&ga)[16], T (&gb)[16]) {
+  const bool ta = a < N, tb = b < N;  // uniform
+  if (ta && tb)
+    pre_tiles<T, CP, true, true, ROOT>(u, a, b, N, P, C, c, cat_ok, first, R, Pa, Pb, wc, qroot, tips, part, pre_in, pre_out, weights, ga, gb);
+  else if (ta)
+    pre_tiles<T, CP, true, false, ROOT>(u, a, b, N, P, C, c, cat_ok, first, R, Pa, Pb, wc, qroot, tips, part, pre_in, pre_out, weights, ga, gb);
+  else if (tb)
+    pre_tiles<T, CP, false, true, ROOT>(u, a, b, N, P, C, c, cat_ok, first, R, Pa, Pb, wc, qroot, tips, part, pre_in, pre_out, weights, ga, gb);
+  else
+    pre_tiles<T, CP, false, false, ROOT>(u, a, b, N, P, C, c, cat_ok, first, R, Pa, Pb, wc, qroot, tips, part, pre_in, pre_out, weights, ga, gb);
+}
+
 template <typename T, int CP>
 __global__ __launch_bounds__(256) void nuc_pre_level_kernel(
     const int32_t* __restrict__ nodes, const int32_t* __restrict__ left, const int32_t* __restrict__ right,
@@ -279,72 +457,10 @@ __global__ __launch_bounds__(256) void nuc_pre_level_kernel(
     V4<T> qroot;
 #pragma unroll
     for (int i = 0; i < 4; ++i) qroot.v[i] = T(pi[i]);
-    const int pbase = first + lane / CP;
-    V4<T> q, xa, xb;
-    T w;
-    {
-      const int pc = pbase < P ? pbase : P - 1;
-      q = (u == root) ? qroot : pre_in[((size_t)(u - N) * C + c) * P + pc];
-      xa = load_child<T>(a, N, c, P, pc, tips, part, C);
-      xb = load_child<T>(b, N, c, P, pc, tips, part, C);
-      w = (pbase < P && cat_ok) ? weights[pc] : T(0);
-    }
-    for (int r = 0; r < R; ++r) {
-      if (first + r * TPW >= P) break;  // uniform
-      const int p = pbase + r * TPW;
-      V4<T> nq = q, na = xa, nb = xb;
-      T nw = 0;
-      if (r + 1 < R) {
-        const int pn = p + TPW;
-        const int pc = pn < P ? pn : P - 1;
-        nq = (u == root) ? qroot : pre_in[((size_t)(u - N) * C + c) * P + pc];
-        na = load_child<T>(a, N, c, P, pc, tips, part, C);
-        nb = load_child<T>(b, N, c, P, pc, tips, part, C);
-        nw = (pn < P && cat_ok) ? weights[pc] : T(0);
-      }
-      const V4<T> sa = matvec(Pa, xa);
-      const V4<T> sb = matvec(Pb, xb);
-      T l = 0;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) l += q.v[i] * sa.v[i] * sb.v[i];
-      l = group_sum_cp<CP>(l * wc);
-      const T f = (l > T(0) ? w / l : T(0)) * wc;
-      V4<T> ta, tb;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        ta.v[i] = q.v[i] * sb.v[i];
-        tb.v[i] = q.v[i] * sa.v[i];
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const T fa = f * ta.v[i], fb = f * tb.v[i];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          ga[4 * i + j] += fa * xa.v[j];
-          gb[4 * i + j] += fb * xb.v[j];
-        }
-      }
-      if (a >= N) {  // uniform
-        V4<T> qa = matvec_t(Pa, ta);
-        const T ma = group_max_cp<CP>(cat_ok ? max4(qa) : T(0));
-        const int ea = scale_exponent(ma);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) qa.v[i] = scale_by_pow2(qa.v[i], ea);
-        if (p < P && cat_ok) pre_out[((size_t)(a - N) * C + c) * P + p] = qa;
-      }
-      if (b >= N) {
-        V4<T> qb = matvec_t(Pb, tb);
-        const T mb = group_max_cp<CP>(cat_ok ? max4(qb) : T(0));
-        const int eb = scale_exponent(mb);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) qb.v[i] = scale_by_pow2(qb.v[i], eb);
-        if (p < P && cat_ok) pre_out[((size_t)(b - N) * C + c) * P + p] = qb;
-      }
-      q = nq;
-      xa = na;
-      xb = nb;
-      w = nw;
-    }
+    if (u == root)
+      pre_dispatch_kind<T, CP, true>(u, a, b, N, P, C, c, cat_ok, first, R, Pa, Pb, wc, qroot, tips, part, pre_in, pre_out, weights, ga, gb);
+    else
+      pre_dispatch_kind<T, CP, false>(u, a, b, N, P, C, c, cat_ok, first, R, Pa, Pb, wc, qroot, tips, part, pre_in, pre_out, weights, ga, gb);
   }
   // wavefront reduce-scatter, then the four wavefronts of the block in order
   T ra[2], rb[2];
