@@ -10,13 +10,25 @@ namespace epochlik {
 
 namespace {
 bool nuc(const EpochInstance* in) { return in->path == 1; }
+bool codon(const EpochInstance* in) { return in->path == 2; }
 }  // namespace
 
 int fastpath_init(EpochInstance* in) {
-  in->path = (in->K == 4 && in->cfg.kernel_path == EPOCH_KERNEL_AUTO) ? 1 : 0;
-  if (nuc(in) && (in->cfg.flags & (EPOCH_GRAD_BRANCH | EPOCH_GRAD_Q))) {
+  in->path = 0;
+  if (in->cfg.kernel_path == EPOCH_KERNEL_AUTO) {
+    if (in->K == 4) in->path = 1;
+    else if (in->Kp == 64 && in->K > 48 && !in->fp64 && in->C == 1) in->path = 2;
+  }
+  const bool grad = (in->cfg.flags & (EPOCH_GRAD_BRANCH | EPOCH_GRAD_Q)) != 0;
+  if (nuc(in) && grad) {
     in->nuc_slots = nuc_slots(in->P, in->C, in->nuc_rmin);
     const size_t bytes = (size_t)in->nuc_slots * in->n_nodes * in->C * 16 * sizeof(double);
+    int rc = ensure(in->Gpart, std::max(bytes, in->Gpart.bytes));
+    if (rc) return rc;
+    return ensure(in->gslots, (size_t)in->n_nodes * sizeof(int32_t));
+  }
+  if (codon(in) && grad) {
+    const size_t bytes = (size_t)codon_max_slots(in->P) * in->n_nodes * 64 * 64 * sizeof(float);
     int rc = ensure(in->Gpart, std::max(bytes, in->Gpart.bytes));
     if (rc) return rc;
     return ensure(in->gslots, (size_t)in->n_nodes * sizeof(int32_t));
@@ -26,9 +38,12 @@ int fastpath_init(EpochInstance* in) {
 void fastpath_release(EpochInstance*) {}
 int fastpath_tips_changed(EpochInstance*) { return EPOCH_OK; }
 int fastpath_tree_changed(EpochInstance* in) {
-  if (!nuc(in) || !in->gslots.ptr) return EPOCH_OK;
+  if ((!nuc(in) && !codon(in)) || !in->gslots.ptr) return EPOCH_OK;
   std::vector<int32_t> slots;
-  nuc_slots_per_node(in, slots);
+  if (nuc(in))
+    nuc_slots_per_node(in, slots);
+  else
+    codon_slots_per_node(in, slots);
   int rc = hip_check(hipMemcpyAsync(in->gslots.ptr, slots.data(), slots.size() * sizeof(int32_t),
                                     hipMemcpyHostToDevice, in->stream), "gslots upload");
   if (rc) return rc;
@@ -49,12 +64,12 @@ int fastpath_pstage(EpochInstance* in) {
 }
 
 int fastpath_post(EpochInstance* in) {
-  EPOCH_PHASE(1, nuc(in) ? launch_nuc_post(in) : launch_post_generic(in));
+  EPOCH_PHASE(1, nuc(in) ? launch_nuc_post(in) : (codon(in) ? launch_codon_post(in) : launch_post_generic(in)));
   return EPOCH_OK;
 }
 
 int fastpath_root(EpochInstance* in) {
-  EPOCH_PHASE(2, nuc(in) ? launch_nuc_root(in) : launch_root_generic(in));
+  EPOCH_PHASE(2, nuc(in) ? launch_nuc_root(in) : (codon(in) ? launch_codon_root(in) : launch_root_generic(in)));
   return EPOCH_OK;
 }
 
@@ -62,6 +77,8 @@ int fastpath_gradient(EpochInstance* in, bool want_Q) {
   if (nuc(in)) {
     EPOCH_PHASE(3, launch_nuc_pre_grad(in));
     EPOCH_PHASE(4, launch_grad_reduce(in, in->nuc_slots, static_cast<const int32_t*>(in->gslots.ptr)));
+  } else if (codon(in)) {
+    EPOCH_PHASE(3, launch_codon_pre_grad(in));
   } else {
     EPOCH_PHASE(3, launch_pre_generic(in));
     EPOCH_PHASE(4, launch_grad_branch_generic(in));

@@ -44,7 +44,7 @@ struct EpochInstance {
   bool eig_dirty = true;
   epochlik::TreePlan plan;
   int n_chunks = 1;  // pattern chunks of the generic gradient accumulation
-  int path = 0;        // 0 generic, 1 four-state kernels
+  int path = 0;        // 0 generic, 1 four-state kernels, 2 64-state MFMA kernels
   int nuc_rmin = 8;    // minimum pattern tiles per wavefront in the four-state gradient
   int nuc_slots = 1;   // partial-sum slots per branch of the four-state gradient
 
@@ -119,5 +119,12 @@ int launch_nuc_root(EpochInstance* in);
 int launch_nuc_pre_grad(EpochInstance* in);
 int nuc_slots(int P, int C, int rmin);
 void nuc_slots_per_node(const EpochInstance* in, std::vector<int32_t>& out);
+
+// 64-state MFMA kernels (kernels_codon.hip)
+int launch_codon_post(EpochInstance* in);
+int launch_codon_root(EpochInstance* in);
+int launch_codon_pre_grad(EpochInstance* in);
+int codon_max_slots(int P);
+void codon_slots_per_node(const EpochInstance* in, std::vector<int32_t>& out);
 
 }  // namespace epochlik

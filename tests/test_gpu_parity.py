@@ -44,7 +44,7 @@ RANDOM_CASES = [
     (112, 10, 4, 70, 5, 3, 3, True, 0.0, 0.0),
     (113, 9, 4, 90, 8, 2, 2, False, 0.1, 0.1),
 ]
-GRAD_CASES = RANDOM_CASES[:6] + RANDOM_CASES[8:]
+GRAD_CASES = RANDOM_CASES[:7] + RANDOM_CASES[8:]
 
 
 def _prob(case):
@@ -168,3 +168,28 @@ def test_repeat_evaluations_are_bitwise_identical():
     for logL, db in out[1:]:
         assert logL == out[0][0]
         assert np.array_equal(db, out[0][1])
+
+
+@pytest.mark.parametrize("kernel", ["auto", "generic"])
+def test_codon_C3_tree(kernel):
+    """GY94 61-state (padded to 64), 4 epochs, the full 128-taxon tree, 700 patterns
+    (11 tiles of 64 with a ragged tail): logL, branch and rate-matrix gradients in FP32."""
+    prob = W.make_config(3, n_patterns=700)
+    with from_problem(prob, "fp32", grad_branch=True, grad_Q=True, kernel=kernel) as lik:
+        logL = lik.log_likelihood()
+        db, dq = lik.gradient(branch=True, Q=True)
+    want = O.log_likelihood(prob)
+    ref_b, ref_q = O.gradient(prob)
+    assert rel(logL, want) <= TOL_LOGL["fp32"], rel(logL, want)
+    assert grad_rel(db, ref_b) <= TOL_GRAD["fp32"], grad_rel(db, ref_b)
+    assert grad_rel(dq, ref_q) <= TOL_GRAD["fp32"], grad_rel(dq, ref_q)
+
+
+def test_codon_fp64_generic_C3_tree():
+    prob = W.make_config(3, n_patterns=300)
+    with from_problem(prob, "fp64", grad_branch=True) as lik:
+        logL = lik.log_likelihood()
+        db, _ = lik.gradient()
+    assert rel(logL, O.log_likelihood(prob)) <= TOL_LOGL["fp64"]
+    ref_b, _ = O.gradient(prob, wrt=("branch",))
+    assert grad_rel(db, ref_b) <= TOL_GRAD["fp64"]
