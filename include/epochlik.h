@@ -183,6 +183,36 @@ int epoch_set_timing(EpochInstance* inst, int32_t enable);
  * each (either may be NULL).  Synchronises the stream. */
 int epoch_get_timing(EpochInstance* inst, double* ms_out, int64_t* counts_out);
 
+/* ---- Batched evaluation (an addition to the paper: many independent
+ * evaluations in one replayed HIP graph).
+ * A batch references n distinct, fully set-up instances (eigensystems, tree,
+ * tips, weights, categories, root frequencies); it does not own them and they
+ * must outlive it.  Members on the 64-state path share merged per-level
+ * launches; the graph is captured at the first evaluation and replayed, and
+ * captured again when a member's tree or eigen-reconstruction precision
+ * changes.  tune_cache_path (or NULL) names a text file caching the tuned
+ * launch shape per device and batch shape; it is read, and written after
+ * tuning on the first evaluation. */
+typedef struct EpochBatch EpochBatch;
+#define EPOCH_EVAL_LOGL 0x1u
+#define EPOCH_EVAL_GRAD_BRANCH 0x2u
+#define EPOCH_EVAL_GRAD_Q 0x4u
+int epoch_batch_create(EpochInstance* const* insts, int32_t n, const char* tune_cache_path, EpochBatch** out);
+
+/* Evaluate every member: logL: host [n] out.  what: EPOCH_EVAL_* bits (logL
+ * is always computed).  Gradients stay on the device; read them with
+ * epoch_batch_gradients.  Synchronises the batch's own stream. */
+int epoch_batch_evaluate(EpochBatch* batch, uint32_t what, double* logL);
+
+/* Gradients of member i from the last evaluation (host arrays as in
+ * log_likelihood_gradient; either may be NULL). */
+int epoch_batch_gradients(EpochBatch* batch, int32_t i, double* d_branch, double* d_Q);
+
+/* Tuned number of blocks per pre-order launch in use (for reporting). */
+int epoch_batch_target_blocks(EpochBatch* batch, int32_t* out);
+
+int epoch_batch_destroy(EpochBatch* batch);
+
 /* Attainable HBM bandwidth on the current device: a plain stream over a
  * library-allocated buffer of `bytes` (1 MiB .. 64 GiB), repeated `iters`
  * times on the default stream and timed with HIP events.  kind: 0 = copy

@@ -36,7 +36,12 @@ EXPORTED = [
     "set_epoch_eigensystems", "set_tree_epochs", "update_transition_matrices", "update_partials",
     "root_log_likelihood", "log_likelihood_gradient", "epoch_get_transition_matrices",
     "epoch_plan_segments", "epoch_set_timing", "epoch_get_timing", "epoch_bandwidth_probe",
+    "epoch_batch_create", "epoch_batch_evaluate", "epoch_batch_gradients", "epoch_batch_target_blocks",
+    "epoch_batch_destroy",
 ]
+EPOCH_EVAL_LOGL = 0x1
+EPOCH_EVAL_GRAD_BRANCH = 0x2
+EPOCH_EVAL_GRAD_Q = 0x4
 PHASES = ["transition_matrices", "post_order", "root", "pre_order_dP", "grad_reduce", "grad_Q"]
 
 
@@ -99,6 +104,11 @@ def load() -> ctypes.CDLL:
         "epoch_plan_segments": (i32, [i32, ip, dp, i32, dp, ip, i32, i32, ip, ip, dp, ip]),
         "epoch_set_timing": (i32, [P, i32]),
         "epoch_bandwidth_probe": (i32, [ctypes.c_int64, i32, i32, dp]),
+        "epoch_batch_create": (i32, [ctypes.POINTER(P), i32, ctypes.c_char_p, ctypes.POINTER(P)]),
+        "epoch_batch_evaluate": (i32, [P, u32, dp]),
+        "epoch_batch_gradients": (i32, [P, i32, dp, dp]),
+        "epoch_batch_target_blocks": (i32, [P, ctypes.POINTER(i32)]),
+        "epoch_batch_destroy": (i32, [P]),
         "epoch_get_timing": (i32, [P, dp, ctypes.POINTER(ctypes.c_int64)]),
     }
     for name, (res, args) in sig.items():

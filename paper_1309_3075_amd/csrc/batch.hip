@@ -1,0 +1,394 @@
+// Batched evaluation: many independent likelihood problems in one replayed
+// HIP graph.
+//
+// Problems on the 64-state MFMA path share merged launches: one launch per
+// tree level (counted from the tips) carries the nodes of that level of every
+// problem as (problem, node) work items, so small problems do not leave the
+// chip idle.  Transition matrices and dlogL/dQ are launched per problem inside
+// the same graph.  The graph is captured on the first evaluation and replayed
+// afterwards; it is captured again when a tree topology (level structure) or
+// the precision of the eigen reconstruction of a member changes.  The number
+// of blocks each pre-order launch aims for is tuned on the device the first
+// time a shape is seen and kept in a JSON cache file.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "fastpath.h"
+#include "instance.h"
+
+using namespace epochlik;
+
+struct EpochBatch {
+  std::vector<EpochInstance*> insts;
+  hipStream_t stream = nullptr;
+  bool merged = false;  // every member is on the 64-state path
+  int target_blocks = 1024;
+  std::string tune_path;
+  CodonSchedule sched;
+  DevBuf dev;                  // descriptors + items + reduce items
+  std::vector<DevBuf> gslots;  // per member
+  DevBuf results;              // double [n]
+  std::vector<uint64_t> signature;
+  hipGraph_t graph[8] = {};
+  hipGraphExec_t exec[8] = {};
+  bool tuned = false;
+  bool own_stream = false;
+};
+
+namespace {
+
+constexpr uint32_t kLogL = 1u, kGradBranch = 2u, kGradQ = 4u;
+
+__global__ __launch_bounds__(64) void gather_results(const double* const* __restrict__ src, int n,
+                                                     double* __restrict__ dst) {
+  for (int i = threadIdx.x; i < n; i += 64) dst[i] = *src[i];
+}
+
+uint64_t member_signature(const EpochInstance* in) {
+  uint64_t h = (uint64_t)in->tree_generation * 1000003ull + (in->eig_fp64 ? 7 : 0);
+  return h;
+}
+
+void release_buf(DevBuf& b) {
+  if (b.ptr) (void)hipFree(b.ptr);
+  b.ptr = nullptr;
+  b.bytes = 0;
+}
+
+void drop_graphs(EpochBatch* b) {
+  for (int k = 0; k < 8; ++k) {
+    if (b->exec[k]) (void)hipGraphExecDestroy(b->exec[k]);
+    if (b->graph[k]) (void)hipGraphDestroy(b->graph[k]);
+    b->exec[k] = nullptr;
+    b->graph[k] = nullptr;
+  }
+}
+
+int build_schedule(EpochBatch* b) {
+  std::vector<const EpochInstance*> cin(b->insts.begin(), b->insts.end());
+  std::vector<std::vector<int32_t>> gs;
+  codon_build_schedule(cin, b->target_blocks, b->sched, gs);
+  const size_t n = b->insts.size();
+  b->gslots.resize(n);
+  std::vector<CodonProblem> desc(n);
+  for (size_t q = 0; q < n; ++q) {
+    int rc = ensure(b->gslots[q], gs[q].size() * sizeof(int32_t));
+    if (rc) return rc;
+    rc = hip_check(hipMemcpy(b->gslots[q].ptr, gs[q].data(), gs[q].size() * sizeof(int32_t), hipMemcpyHostToDevice),
+                   "batch gslots upload");
+    if (rc) return rc;
+    desc[q] = codon_descriptor(b->insts[q], static_cast<const int32_t*>(b->gslots[q].ptr));
+  }
+  const auto& sc = b->sched;
+  const size_t bytes = sizeof(CodonProblem) * n + sizeof(int2) * (sc.items.size() + sc.reduce_items.size());
+  int rc = ensure(b->dev, bytes);
+  if (rc) return rc;
+  std::vector<char> h(bytes);
+  memcpy(h.data(), desc.data(), sizeof(CodonProblem) * n);
+  memcpy(h.data() + sizeof(CodonProblem) * n, sc.items.data(), sizeof(int2) * sc.items.size());
+  memcpy(h.data() + sizeof(CodonProblem) * n + sizeof(int2) * sc.items.size(), sc.reduce_items.data(),
+         sizeof(int2) * sc.reduce_items.size());
+  return hip_check(hipMemcpy(b->dev.ptr, h.data(), bytes, hipMemcpyHostToDevice), "batch schedule upload");
+}
+
+// Enqueue one evaluation of every member on b->stream (no host synchronisation).
+int enqueue(EpochBatch* b, uint32_t what, const double* const* d_result_ptrs) {
+  const size_t n = b->insts.size();
+  for (auto* in : b->insts) {
+    int rc = launch_pstage_generic(in);
+    if (rc) return rc;
+  }
+  if (b->merged) {
+    const CodonProblem* probs = static_cast<const CodonProblem*>(b->dev.ptr);
+    const int2* items = reinterpret_cast<const int2*>(static_cast<const char*>(b->dev.ptr) + sizeof(CodonProblem) * n);
+    const int2* red = items + b->sched.items.size();
+    int rc = codon_launch_post(b->sched, probs, items, b->stream);
+    if (!rc) rc = codon_launch_root(b->sched, probs, b->stream);
+    if (!rc && (what & (kGradBranch | kGradQ))) rc = codon_launch_pre_grad(b->sched, probs, items, red, b->stream);
+    if (rc) return rc;
+  } else {
+    for (auto* in : b->insts) {
+      int rc = fastpath_post(in);
+      if (!rc) rc = fastpath_root(in);
+      if (!rc && (what & (kGradBranch | kGradQ))) rc = fastpath_gradient(in, false);
+      if (rc) return rc;
+    }
+  }
+  if (what & kGradQ)
+    for (auto* in : b->insts) {
+      int rc = launch_grad_Q_generic(in);
+      if (rc) return rc;
+    }
+  hipLaunchKernelGGL(gather_results, dim3(1), dim3(64), 0, b->stream, d_result_ptrs, (int)n,
+                     static_cast<double*>(b->results.ptr));
+  return hip_check(hipGetLastError(), "batch gather launch");
+}
+
+int check_members(EpochBatch* b, uint32_t what) {
+  for (size_t q = 0; q < b->insts.size(); ++q) {
+    EpochInstance* in = b->insts[q];
+    if (!in->have_tree || !in->have_cats || !in->have_tips || !in->have_weights || !in->have_pi)
+      return set_error(EPOCH_ERR_STATE, "batch member %zu is missing inputs", q);
+    for (int s = 0; s < in->S; ++s)
+      if (!in->have_eig[s]) return set_error(EPOCH_ERR_STATE, "batch member %zu: eigensystem %d not set", q, s);
+    if ((what & kGradBranch) && !(in->cfg.flags & EPOCH_GRAD_BRANCH))
+      return set_error(EPOCH_ERR_STATE, "batch member %zu created without EPOCH_GRAD_BRANCH", q);
+    if ((what & kGradQ) && !(in->cfg.flags & EPOCH_GRAD_Q))
+      return set_error(EPOCH_ERR_STATE, "batch member %zu created without EPOCH_GRAD_Q", q);
+  }
+  return EPOCH_OK;
+}
+
+int capture(EpochBatch* b, uint32_t what) {
+  const size_t n = b->insts.size();
+  // pointers to every member's result[0], kept after the results array
+  int rc = ensure(b->results, n * sizeof(double) + n * sizeof(double*));
+  if (rc) return rc;
+  std::vector<const double*> ptrs(n);
+  for (size_t q = 0; q < n; ++q) ptrs[q] = static_cast<const double*>(b->insts[q]->result.ptr);
+  const double** d_ptrs = reinterpret_cast<const double**>(static_cast<char*>(b->results.ptr) + n * sizeof(double));
+  rc = hip_check(hipMemcpy(d_ptrs, ptrs.data(), n * sizeof(double*), hipMemcpyHostToDevice), "batch pointers");
+  if (rc) return rc;
+  // members launch on the batch stream while captured, without phase timing
+  std::vector<hipStream_t> saved(n);
+  std::vector<bool> timing(n);
+  for (size_t q = 0; q < n; ++q) {
+    saved[q] = b->insts[q]->stream;
+    timing[q] = b->insts[q]->timing;
+    b->insts[q]->stream = b->stream;
+    b->insts[q]->timing = false;
+  }
+  rc = hip_check(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "begin capture");
+  if (!rc) {
+    int erc = enqueue(b, what, d_ptrs);
+    hipGraph_t g = nullptr;
+    int crc = hip_check(hipStreamEndCapture(b->stream, &g), "end capture");
+    rc = erc ? erc : crc;
+    if (!rc) {
+      rc = hip_check(hipGraphInstantiate(&b->exec[what], g, nullptr, nullptr, 0), "graph instantiate");
+      b->graph[what] = g;
+    } else if (g) {
+      (void)hipGraphDestroy(g);
+    }
+  }
+  for (size_t q = 0; q < n; ++q) {
+    b->insts[q]->stream = saved[q];
+    b->insts[q]->timing = timing[q];
+  }
+  return rc;
+}
+
+int replay(EpochBatch* b, uint32_t what) {
+  std::vector<uint64_t> sig;
+  for (auto* in : b->insts) sig.push_back(member_signature(in));
+  if (sig != b->signature) {
+    drop_graphs(b);
+    if (b->merged) {
+      int rc = build_schedule(b);
+      if (rc) return rc;
+    }
+    b->signature = sig;
+  }
+  if (!b->exec[what]) {
+    int rc = capture(b, what);
+    if (rc) return rc;
+  }
+  return hip_check(hipGraphLaunch(b->exec[what], b->stream), "graph launch");
+}
+
+// ---- tuning cache: lines "key value" in a small text/JSON-like file
+std::string tune_key(EpochBatch* b) {
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, b->insts[0]->device) == hipSuccess) arch = prop.gcnArchName;
+  long tot_p = 0;
+  for (auto* in : b->insts) tot_p += in->P;
+  std::ostringstream k;
+  k << arch.substr(0, arch.find(':')) << "/codon/n" << b->insts.size() << "/P" << (tot_p / (long)b->insts.size() / 1000);
+  return k.str();
+}
+
+bool tune_lookup(const std::string& path, const std::string& key, int& value) {
+  std::ifstream f(path);
+  if (!f) return false;
+  std::string line;
+  while (std::getline(f, line)) {
+    // format: "key": value,
+    const size_t q1 = line.find('"'), q2 = line.find('"', q1 + 1);
+    if (q1 == std::string::npos || q2 == std::string::npos) continue;
+    if (line.substr(q1 + 1, q2 - q1 - 1) != key) continue;
+    const size_t c = line.find(':', q2);
+    if (c == std::string::npos) continue;
+    value = atoi(line.c_str() + c + 1);
+    return value > 0;
+  }
+  return false;
+}
+
+void tune_store(const std::string& path, const std::string& key, int value) {
+  std::vector<std::string> entries;
+  {
+    std::ifstream f(path);
+    std::string line;
+    while (f && std::getline(f, line)) {
+      const size_t q1 = line.find('"'), q2 = line.find('"', q1 + 1);
+      if (q1 == std::string::npos || q2 == std::string::npos) continue;
+      if (line.substr(q1 + 1, q2 - q1 - 1) == key) continue;
+      std::string e = line;
+      while (!e.empty() && (e.back() == ',' || e.back() == ' ')) e.pop_back();
+      entries.push_back(e);
+    }
+  }
+  std::ostringstream e;
+  e << "  \"" << key << "\": " << value;
+  entries.push_back(e.str());
+  std::ofstream f(path);
+  f << "{\n";
+  for (size_t i = 0; i < entries.size(); ++i) f << entries[i] << (i + 1 < entries.size() ? ",\n" : "\n");
+  f << "}\n";
+}
+
+int autotune(EpochBatch* b) {
+  const std::string key = tune_key(b);
+  int v = 0;
+  if (!b->tune_path.empty() && tune_lookup(b->tune_path, key, v)) {
+    b->target_blocks = v;
+    return EPOCH_OK;
+  }
+  const uint32_t what = kLogL | kGradBranch;
+  hipEvent_t e0, e1;
+  int rc = hip_check(hipEventCreate(&e0), "tune event");
+  if (!rc) rc = hip_check(hipEventCreate(&e1), "tune event");
+  if (rc) return rc;
+  float best = 1e30f;
+  int best_t = b->target_blocks;
+  for (int t : {256, 512, 1024, 2048, 4096}) {
+    b->target_blocks = t;
+    b->signature.clear();  // forces a new schedule and capture
+    rc = replay(b, what);  // warm-up (and capture)
+    if (!rc) rc = hip_check(hipEventRecord(e0, b->stream), "tune record");
+    for (int k = 0; k < 3 && !rc; ++k) rc = replay(b, what);
+    if (!rc) rc = hip_check(hipEventRecord(e1, b->stream), "tune record");
+    if (!rc) rc = hip_check(hipEventSynchronize(e1), "tune sync");
+    float ms = 0.f;
+    if (!rc) rc = hip_check(hipEventElapsedTime(&ms, e0, e1), "tune elapsed");
+    if (rc) break;
+    if (ms < best) {
+      best = ms;
+      best_t = t;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  b->target_blocks = best_t;
+  b->signature.clear();
+  if (!b->tune_path.empty()) tune_store(b->tune_path, key, best_t);
+  return EPOCH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int epoch_batch_create(EpochInstance* const* insts, int32_t n, const char* tune_cache_path, EpochBatch** out) {
+  if (!insts || !out || n < 1) return set_error(EPOCH_ERR_ARG, "batch needs n >= 1 instances and an output");
+  *out = nullptr;
+  for (int i = 0; i < n; ++i)
+    if (!insts[i]) return set_error(EPOCH_ERR_ARG, "batch member %d is NULL", i);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < i; ++j)
+      if (insts[i] == insts[j]) return set_error(EPOCH_ERR_ARG, "batch member %d repeats member %d", i, j);
+  auto* b = new EpochBatch();
+  b->insts.assign(insts, insts + n);
+  // graph capture needs a stream of its own (the legacy default stream cannot be captured)
+  if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete b;
+    return set_error(EPOCH_ERR_HIP, "batch stream creation failed");
+  }
+  b->own_stream = true;
+  b->merged = true;
+  for (int i = 0; i < n; ++i) {
+    if (insts[i]->path != 2) b->merged = false;
+    if (insts[i]->device != insts[0]->device) {
+      (void)hipStreamDestroy(b->stream);
+      delete b;
+      return set_error(EPOCH_ERR_ARG, "batch members must share one device");
+    }
+  }
+  if (tune_cache_path) b->tune_path = tune_cache_path;
+  *out = b;
+  return EPOCH_OK;
+}
+
+int epoch_batch_evaluate(EpochBatch* b, uint32_t what, double* logL) {
+  if (!b || !logL) return set_error(EPOCH_ERR_ARG, "batch and logL must not be NULL");
+  if (what & ~(kLogL | kGradBranch | kGradQ)) return set_error(EPOCH_ERR_ARG, "unknown evaluation flags");
+  what |= kLogL;
+  int rc = check_members(b, what);
+  if (rc) return rc;
+  if (b->merged && !b->tuned) {
+    rc = autotune(b);
+    if (rc) return rc;
+    b->tuned = true;
+  }
+  rc = replay(b, what);
+  if (rc) return rc;
+  const size_t n = b->insts.size();
+  rc = hip_check(hipMemcpyAsync(logL, b->results.ptr, n * sizeof(double), hipMemcpyDeviceToHost, b->stream), "batch logL");
+  if (!rc) rc = hip_check(hipStreamSynchronize(b->stream), "batch sync");
+  if (rc) return rc;
+  for (size_t q = 0; q < n; ++q) {
+    EpochInstance* in = b->insts[q];
+    in->P_valid = in->partials_valid = true;
+    in->logL_valid = std::isfinite(logL[q]);
+    in->grad_ready = (what & (kGradBranch | kGradQ)) != 0;
+    in->gradQ_ready = (what & kGradQ) != 0;
+  }
+  for (size_t q = 0; q < n; ++q)
+    if (!std::isfinite(logL[q])) return set_error(EPOCH_ERR_NUMERIC, "batch member %zu: log-likelihood not finite", q);
+  return EPOCH_OK;
+}
+
+int epoch_batch_gradients(EpochBatch* b, int32_t i, double* d_branch, double* d_Q) {
+  if (!b || i < 0 || i >= (int)b->insts.size()) return set_error(EPOCH_ERR_ARG, "bad batch member index");
+  EpochInstance* in = b->insts[i];
+  if (d_branch && !in->grad_ready) return set_error(EPOCH_ERR_STATE, "the last batch evaluation had no gradient");
+  if (d_Q && !in->gradQ_ready) return set_error(EPOCH_ERR_STATE, "the last batch evaluation had no dlogL/dQ");
+  int rc = EPOCH_OK;
+  if (d_branch)
+    rc = hip_check(hipMemcpyAsync(d_branch, in->dbranch.ptr, (size_t)in->n_nodes * sizeof(double), hipMemcpyDeviceToHost,
+                                  b->stream), "batch gradient copy");
+  if (!rc && d_Q)
+    rc = hip_check(hipMemcpyAsync(d_Q, in->dQ.ptr, (size_t)in->S * in->K * in->K * sizeof(double), hipMemcpyDeviceToHost,
+                                  b->stream), "batch gradient copy");
+  if (!rc) rc = hip_check(hipStreamSynchronize(b->stream), "batch sync");
+  return rc;
+}
+
+int epoch_batch_target_blocks(EpochBatch* b, int32_t* out) {
+  if (!b || !out) return set_error(EPOCH_ERR_ARG, "NULL argument");
+  *out = b->target_blocks;
+  return EPOCH_OK;
+}
+
+int epoch_batch_destroy(EpochBatch* b) {
+  if (!b) return EPOCH_OK;
+  drop_graphs(b);
+  release_buf(b->dev);
+  release_buf(b->results);
+  for (auto& g : b->gslots) release_buf(g);
+  if (b->own_stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+  return EPOCH_OK;
+}
+
+}  // extern "C"

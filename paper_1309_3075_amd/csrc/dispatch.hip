@@ -38,12 +38,10 @@ int fastpath_init(EpochInstance* in) {
 void fastpath_release(EpochInstance*) {}
 int fastpath_tips_changed(EpochInstance*) { return EPOCH_OK; }
 int fastpath_tree_changed(EpochInstance* in) {
-  if ((!nuc(in) && !codon(in)) || !in->gslots.ptr) return EPOCH_OK;
+  if (codon(in)) return codon_prepare(in);
+  if (!nuc(in) || !in->gslots.ptr) return EPOCH_OK;
   std::vector<int32_t> slots;
-  if (nuc(in))
-    nuc_slots_per_node(in, slots);
-  else
-    codon_slots_per_node(in, slots);
+  nuc_slots_per_node(in, slots);
   int rc = hip_check(hipMemcpyAsync(in->gslots.ptr, slots.data(), slots.size() * sizeof(int32_t),
                                     hipMemcpyHostToDevice, in->stream), "gslots upload");
   if (rc) return rc;

@@ -297,7 +297,7 @@ int epoch_destroy(EpochInstance* in) {
   for (DevBuf* b : {&in->eigT, &in->eig64, &in->check, &in->tips, &in->weights, &in->weightsT, &in->pi,
                     &in->cat, &in->tree_i, &in->tree_d, &in->Pm, &in->dPm, &in->partials, &in->scales,
                     &in->pre, &in->site, &in->blocksum, &in->result, &in->Gpart, &in->G, &in->dbranch,
-                    &in->qseg, &in->qscratch, &in->dQ, &in->seglist})
+                    &in->qseg, &in->qscratch, &in->dQ, &in->seglist, &in->gslots, &in->codon_dev})
     release(*b);
   delete in;
   return EPOCH_OK;
@@ -536,6 +536,7 @@ int set_tree_epochs(EpochInstance* in, const int32_t* parent, const double* heig
   }
   in->plan = std::move(plan);
   in->have_tree = true;
+  in->tree_generation++;
   invalidate_downstream(in);
   return fastpath_tree_changed(in);
 }

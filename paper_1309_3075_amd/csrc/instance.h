@@ -17,7 +17,38 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
-struct EpochInstanceImpl;
+// Device-visible description of one problem for the 64-state kernels (one
+// instance, or one member of a batch).
+struct CodonProblem {
+  const float* Pm;
+  const uint8_t* tips;
+  float* part;
+  float* pre;
+  int32_t* scales;
+  const float* weightsT;
+  const double* weights;
+  const double* pi;
+  float* Gpart;
+  const float* dPm;
+  double* G;
+  double* dbranch;
+  double* site;
+  double* blocksum;
+  double* result;
+  const int32_t* left;
+  const int32_t* right;
+  const int32_t* gslots;
+  int N, P, K, root, n_slots, n_nodes;
+};
+
+// Merged level schedule: work items (problem, internal node) grouped by level.
+struct CodonSchedule {
+  std::vector<int2> items;         // level l (1-based) occupies [level_off[l-1], level_off[l])
+  std::vector<int> level_off;
+  std::vector<int> level_R;        // pattern tiles per block of the pre-order launch of each level
+  std::vector<int2> reduce_items;  // every (problem, node)
+  int n_levels = 0, max_tiles = 0, max_pattern_blocks = 0, n_problems = 0;
+};
 
 }  // namespace epochlik
 
@@ -41,6 +72,8 @@ struct EpochInstance {
   bool have_tips = false, have_weights = false, have_cats = false, have_pi = false;
   bool have_tree = false;
   bool P_valid = false, partials_valid = false, logL_valid = false;
+  bool grad_ready = false, gradQ_ready = false;  // gradients left on the device by a batch evaluation
+  uint64_t tree_generation = 0;                   // bumped by set_tree_epochs
   bool eig_dirty = true;
   epochlik::TreePlan plan;
   int n_chunks = 1;  // pattern chunks of the generic gradient accumulation
@@ -74,7 +107,10 @@ struct EpochInstance {
   epochlik::DevBuf qscratch;   // T prefix products [nseg][C][Kp][Kp]
   epochlik::DevBuf dQ;         // double [S][Kp][Kp]
   epochlik::DevBuf seglist;    // int32 segments grouped by process: offsets [S+1], items [nseg*C]
-  epochlik::DevBuf gslots;     // int32 [n]: partial-sum slots written per branch (4-state gradient)
+  epochlik::DevBuf gslots;     // int32 [n]: partial-sum slots written per branch (4-state / 64-state gradient)
+  epochlik::DevBuf codon_dev;  // 64-state path: descriptor + work items
+  epochlik::CodonSchedule codon_sched;
+  int codon_target_blocks = 1024;  // blocks per pre-order launch the 64-state schedule aims for
 
   // per-phase timing (epoch_set_timing)
   bool timing = false;
@@ -125,6 +161,13 @@ int launch_codon_post(EpochInstance* in);
 int launch_codon_root(EpochInstance* in);
 int launch_codon_pre_grad(EpochInstance* in);
 int codon_max_slots(int P);
-void codon_slots_per_node(const EpochInstance* in, std::vector<int32_t>& out);
+int codon_prepare(EpochInstance* in);
+CodonProblem codon_descriptor(const EpochInstance* in, const int32_t* gslots);
+void codon_build_schedule(const std::vector<const EpochInstance*>& insts, int target_blocks, CodonSchedule& out,
+                          std::vector<std::vector<int32_t>>& gslots);
+int codon_launch_post(const CodonSchedule& sc, const CodonProblem* d_probs, const int2* d_items, hipStream_t st);
+int codon_launch_root(const CodonSchedule& sc, const CodonProblem* d_probs, hipStream_t st);
+int codon_launch_pre_grad(const CodonSchedule& sc, const CodonProblem* d_probs, const int2* d_items,
+                          const int2* d_reduce_items, hipStream_t st);
 
 }  // namespace epochlik

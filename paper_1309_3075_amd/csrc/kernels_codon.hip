@@ -20,6 +20,9 @@
 //                      outer products; rows 16 w .. 16 w + 15 of G per wavefront.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstring>
+
 #include "device_common.h"
 #include "instance.h"
 
@@ -32,6 +35,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 constexpr int KP = 64;
 constexpr int LDP = 68;  // padded LDS row stride (floats) against bank conflicts
 constexpr int TILE = 64;
+constexpr int kMaxSlots = 64;  // partial-sum slots per branch (blocks sharing one node)
 
 __device__ inline f4 mfma(float a, float b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 
@@ -105,18 +109,25 @@ __device__ inline void tip_lookup(f4 (&S)[4], const uint8_t* __restrict__ tipst,
 }
 
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void codon_post_level_kernel(
-    const int32_t* __restrict__ nodes, const int32_t* __restrict__ left, const int32_t* __restrict__ right,
-    const float* __restrict__ Pm, const uint8_t* __restrict__ tips, const float* __restrict__ part_in,
-    float* __restrict__ part_out, const int32_t* __restrict__ scale_in, int32_t* __restrict__ scale_out,
-    int N, int P, int K) {
+__global__ __launch_bounds__(256) void codon_post_level_kernel(const CodonProblem* __restrict__ probs,
+                                                                const int2* __restrict__ items) {
   __shared__ __align__(16) float sPa[KP * LDP];
   __shared__ __align__(16) float sPb[KP * LDP];
   __shared__ float smax[4][TILE];
-  const int u = nodes[blockIdx.y];
-  const int a = left[u], b = right[u];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
+  const int2 it = items[blockIdx.y];
+  const CodonProblem& pr = probs[it.x];
+  const int N = pr.N, P = pr.P, K = pr.K;
   const int p0 = blockIdx.x * TILE;
+  if (p0 >= P) return;  // uniform: this problem has fewer tiles
+  const float* __restrict__ Pm = pr.Pm;
+  const uint8_t* __restrict__ tips = pr.tips;
+  const float* __restrict__ part_in = pr.part;
+  float* __restrict__ part_out = pr.part;
+  const int32_t* __restrict__ scale_in = pr.scales;
+  int32_t* __restrict__ scale_out = pr.scales;
+  const int u = it.y;
+  const int a = pr.left[u], b = pr.right[u];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
   stage_matrix(sPa, Pm + (size_t)a * KP * KP);
   stage_matrix(sPb, Pm + (size_t)b * KP * KP);
   __syncthreads();
@@ -165,27 +176,37 @@ __global__ __launch_bounds__(256) void codon_post_level_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// Root: L_p = sum_i pi_i x_root(p, i); one wavefront per 64 patterns? no: one
-// thread per pattern, 64 states read as float4.
-__global__ __launch_bounds__(256) void codon_root_kernel(const float* __restrict__ rootp,
-                                                         const int32_t* __restrict__ scale_root,
-                                                         const double* __restrict__ pi,
-                                                         const double* __restrict__ weights,
-                                                         double* __restrict__ site, double* __restrict__ block_out,
-                                                         int P, int K) {
+// Root: one thread per pattern, L_p = sum_i pi_i x_root(p, i) in FP64; block
+// partial sums of w_p log L_p per problem (blockIdx.y).
+__global__ __launch_bounds__(256) void codon_root_kernel(const CodonProblem* __restrict__ probs) {
   __shared__ double sm[256];
+  const CodonProblem& pr = probs[blockIdx.y];
+  const int P = pr.P, K = pr.K;
+  if ((int)blockIdx.x * 256 >= P) return;  // uniform
   const int p = blockIdx.x * 256 + threadIdx.x;
+  const size_t slot = pr.root - pr.N;
   double contrib = 0.0;
   if (p < P) {
     double L = 0.0;
-    const float* x = rootp + (size_t)p * KP;
-    for (int i = 0; i < K; ++i) L += pi[i] * (double)x[i];
-    const double s = log(L) + (double)scale_root[p] * kLn2;
-    site[p] = s;
-    contrib = weights[p] * s;
+    const float* x = pr.part + (slot * P + p) * KP;
+    for (int i = 0; i < K; ++i) L += pr.pi[i] * (double)x[i];
+    const double s = log(L) + (double)pr.scales[slot * P + p] * kLn2;
+    pr.site[p] = s;
+    contrib = pr.weights[p] * s;
   }
   const double tot = block_sum<256>(contrib, sm);
-  if (threadIdx.x == 0) block_out[blockIdx.x] = tot;
+  if (threadIdx.x == 0) pr.blocksum[blockIdx.x] = tot;
+}
+
+// Ordered sum of each problem's block partial sums into its result[0].
+__global__ __launch_bounds__(256) void codon_final_kernel(const CodonProblem* __restrict__ probs) {
+  __shared__ double sm[256];
+  const CodonProblem& pr = probs[blockIdx.x];
+  const int nb = (pr.P + 255) / 256;
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < nb; k += 256) acc += pr.blocksum[k];
+  const double tot = block_sum<256>(acc, sm);
+  if (threadIdx.x == 0) pr.result[0] = tot;
 }
 
 // ---------------------------------------------------------------------------
@@ -195,18 +216,26 @@ __device__ inline float dval_partial(const float* __restrict__ Lg, int P, int p,
   return p < P ? Lg[(size_t)p * KP + col] : 0.f;
 }
 
-__global__ __launch_bounds__(256) void codon_pre_level_kernel(
-    const int32_t* __restrict__ nodes, const int32_t* __restrict__ left, const int32_t* __restrict__ right,
-    const float* __restrict__ Pm, const uint8_t* __restrict__ tips, const float* __restrict__ part,
-    const float* __restrict__ pre_in, float* __restrict__ pre_out, const double* __restrict__ pi,
-    const float* __restrict__ weights, int root, int N, int P, int K, int R, int n_slots,
-    float* __restrict__ Gpart) {
+__global__ __launch_bounds__(256) void codon_pre_level_kernel(const CodonProblem* __restrict__ probs,
+                                                               const int2* __restrict__ items, int R) {
   __shared__ __align__(16) float sPa[KP * LDP];
   __shared__ __align__(16) float sPb[KP * LDP];
   __shared__ __align__(16) float sT[TILE * LDP];  // t_a or t_b tile [pattern][state]
   __shared__ float sx[4][TILE];
-  const int u = nodes[blockIdx.y];
-  const int a = left[u], b = right[u];
+  const int2 it = items[blockIdx.y];
+  const CodonProblem& pr = probs[it.x];
+  const int N = pr.N, P = pr.P, K = pr.K, root = pr.root, n_slots = pr.n_slots;
+  if ((int)blockIdx.x * R * TILE >= P) return;  // uniform: this problem has fewer tiles
+  const float* __restrict__ Pm = pr.Pm;
+  const uint8_t* __restrict__ tips = pr.tips;
+  const float* __restrict__ part = pr.part;
+  const float* __restrict__ pre_in = pr.pre;
+  float* __restrict__ pre_out = pr.pre;
+  const double* __restrict__ pi = pr.pi;
+  const float* __restrict__ weights = pr.weightsT;
+  float* __restrict__ Gpart = pr.Gpart;
+  const int u = it.y;
+  const int a = pr.left[u], b = pr.right[u];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
   stage_matrix(sPa, Pm + (size_t)a * KP * KP);
   stage_matrix(sPb, Pm + (size_t)b * KP * KP);
@@ -361,30 +390,28 @@ __global__ __launch_bounds__(256) void codon_pre_level_kernel(
 }
 
 // G[v] = sum of the FP32 slot partials in FP64 (fixed order), then dlogL/dl.
-__global__ __launch_bounds__(256) void codon_grad_reduce_kernel(const float* __restrict__ Gpart,
-                                                                const float* __restrict__ dP,
-                                                                const int32_t* __restrict__ slots_per_node,
-                                                                int n_slots, int root, double* __restrict__ G,
-                                                                double* __restrict__ dbranch) {
+__global__ __launch_bounds__(256) void codon_grad_reduce_kernel(const CodonProblem* __restrict__ probs,
+                                                                const int2* __restrict__ items) {
   __shared__ double sm[256];
-  const int v = blockIdx.x;
-  const int ns = v == root ? 0 : slots_per_node[v];
-  const float* src = Gpart + (size_t)v * n_slots * (KP * KP);
+  const int2 it = items[blockIdx.x];
+  const CodonProblem& pr = probs[it.x];
+  const int v = it.y;
+  const int ns = v == pr.root ? 0 : pr.gslots[v];
+  const float* src = pr.Gpart + (size_t)v * pr.n_slots * (KP * KP);
   double d = 0.0;
   for (int e = threadIdx.x; e < KP * KP; e += 256) {
     double s = 0.0;
     for (int k = 0; k < ns; ++k) s += (double)src[(size_t)k * (KP * KP) + e];
-    G[(size_t)v * KP * KP + e] = s;
-    d += s * (double)dP[(size_t)v * KP * KP + e];
+    pr.G[(size_t)v * KP * KP + e] = s;
+    d += s * (double)pr.dPm[(size_t)v * KP * KP + e];
   }
   const double tot = block_sum<256>(d, sm);
-  if (threadIdx.x == 0) dbranch[v] = (v == root) ? 0.0 : tot;
+  if (threadIdx.x == 0) pr.dbranch[v] = (v == pr.root) ? 0.0 : tot;
 }
 
-int codon_tiles_per_block(int tiles, int n_l, int r_max) {
-  const long target_blocks = 1024;
-  const long per_node = (target_blocks + n_l - 1) / n_l;
-  long R = (tiles + per_node - 1) / per_node;
+int codon_tiles_per_block(int tiles, int n_items, int target_blocks, int r_max) {
+  const long per_item = ((long)target_blocks + n_items - 1) / n_items;
+  long R = (tiles + per_item - 1) / per_item;
   if (R < 1) R = 1;
   if (R > r_max) R = r_max;
   return (int)R;
@@ -392,83 +419,148 @@ int codon_tiles_per_block(int tiles, int n_l, int r_max) {
 
 }  // namespace
 
-int codon_blocks(const EpochInstance* in, int n_l) {
-  const int tiles = (in->P + TILE - 1) / TILE;
-  const int R = codon_tiles_per_block(tiles, n_l, 64);
-  return (tiles + R - 1) / R;
+// Partial-sum slots per branch: at most kMaxSlots blocks share a node, so the
+// dlogL/dP partials of a branch take at most kMaxSlots x 16 KB.
+int codon_max_slots(int P) { return std::min((P + TILE - 1) / TILE, kMaxSlots); }
+
+CodonProblem codon_descriptor(const EpochInstance* in, const int32_t* gslots) {
+  CodonProblem d{};
+  d.Pm = static_cast<const float*>(in->Pm.ptr);
+  d.tips = static_cast<const uint8_t*>(in->tips.ptr);
+  d.part = static_cast<float*>(in->partials.ptr);
+  d.pre = static_cast<float*>(in->pre.ptr);
+  d.scales = static_cast<int32_t*>(in->scales.ptr);
+  d.weightsT = static_cast<const float*>(in->weightsT.ptr);
+  d.weights = static_cast<const double*>(in->weights.ptr);
+  d.pi = static_cast<const double*>(in->pi.ptr);
+  d.Gpart = static_cast<float*>(in->Gpart.ptr);
+  d.dPm = static_cast<const float*>(in->dPm.ptr);
+  d.G = static_cast<double*>(in->G.ptr);
+  d.dbranch = static_cast<double*>(in->dbranch.ptr);
+  d.site = static_cast<double*>(in->site.ptr);
+  d.blocksum = static_cast<double*>(in->blocksum.ptr);
+  d.result = static_cast<double*>(in->result.ptr);
+  d.left = in->d_left;
+  d.right = in->d_right;
+  d.gslots = gslots;
+  d.N = in->N;
+  d.P = in->P;
+  d.K = in->K;
+  d.root = in->plan.root;
+  d.n_slots = codon_max_slots(in->P);
+  d.n_nodes = in->n_nodes;
+  return d;
 }
 
-int codon_max_slots(int P) { return (P + TILE - 1) / TILE; }
+// Merged level schedule over one or more problems (levels counted from the tips).
+void codon_build_schedule(const std::vector<const EpochInstance*>& insts, int target_blocks, CodonSchedule& out,
+                          std::vector<std::vector<int32_t>>& gslots) {
+  out.items.clear();
+  out.level_off.assign(1, 0);
+  out.level_R.clear();
+  out.reduce_items.clear();
+  int n_levels = 0, max_tiles = 0, max_pblocks = 0;
+  for (auto* in : insts) {
+    n_levels = std::max(n_levels, in->plan.n_levels);
+    max_tiles = std::max(max_tiles, (in->P + TILE - 1) / TILE);
+    max_pblocks = std::max(max_pblocks, (in->P + 255) / 256);
+  }
+  gslots.assign(insts.size(), {});
+  for (size_t q = 0; q < insts.size(); ++q) gslots[q].assign(insts[q]->n_nodes, 0);
+  for (int l = 1; l <= n_levels; ++l) {
+    const size_t begin = out.items.size();
+    for (size_t q = 0; q < insts.size(); ++q) {
+      const auto& pl = insts[q]->plan;
+      if (l > pl.n_levels) continue;
+      for (int k = pl.level_offset[l]; k < pl.level_offset[l + 1]; ++k) out.items.push_back(make_int2((int)q, pl.level_nodes[k]));
+    }
+    const int n_items = (int)(out.items.size() - begin);
+    int R = codon_tiles_per_block(max_tiles, std::max(1, n_items), target_blocks, 64);
+    R = std::max(R, (max_tiles + kMaxSlots - 1) / kMaxSlots);  // at most kMaxSlots blocks per node
+    out.level_off.push_back((int)out.items.size());
+    out.level_R.push_back(R);
+    for (size_t k = begin; k < out.items.size(); ++k) {
+      const int q = out.items[k].x, u = out.items[k].y;
+      const auto& pl = insts[q]->plan;
+      const int tiles = (insts[q]->P + TILE - 1) / TILE;
+      const int used = (tiles + R - 1) / R;
+      gslots[q][pl.left[u]] = used;
+      gslots[q][pl.right[u]] = used;
+    }
+  }
+  for (size_t q = 0; q < insts.size(); ++q)
+    for (int v = 0; v < insts[q]->n_nodes; ++v) out.reduce_items.push_back(make_int2((int)q, v));
+  out.n_levels = n_levels;
+  out.max_tiles = max_tiles;
+  out.max_pattern_blocks = max_pblocks;
+  out.n_problems = (int)insts.size();
+}
 
-int launch_codon_post(EpochInstance* in) {
-  const auto& pl = in->plan;
-  const int tiles = (in->P + TILE - 1) / TILE;
-  for (int l = 1; l <= pl.n_levels; ++l) {
-    const int n_l = pl.level_offset[l + 1] - pl.level_offset[l];
-    if (!n_l) continue;
-    hipLaunchKernelGGL(codon_post_level_kernel, dim3(tiles, n_l), dim3(256), 0, in->stream,
-                       in->d_level_nodes + pl.level_offset[l], in->d_left, in->d_right,
-                       static_cast<const float*>(in->Pm.ptr), static_cast<const uint8_t*>(in->tips.ptr),
-                       static_cast<const float*>(in->partials.ptr), static_cast<float*>(in->partials.ptr),
-                       static_cast<const int32_t*>(in->scales.ptr), static_cast<int32_t*>(in->scales.ptr),
-                       in->N, in->P, in->K);
+int codon_launch_post(const CodonSchedule& sc, const CodonProblem* d_probs, const int2* d_items, hipStream_t st) {
+  for (int l = 1; l <= sc.n_levels; ++l) {
+    const int b = sc.level_off[l - 1], n = sc.level_off[l] - b;
+    if (!n) continue;
+    hipLaunchKernelGGL(codon_post_level_kernel, dim3(sc.max_tiles, n), dim3(256), 0, st, d_probs, d_items + b);
   }
   return hip_check(hipGetLastError(), "codon_post_level launch");
 }
 
-int launch_codon_root(EpochInstance* in) {
-  const int nb = (in->P + 255) / 256;
-  const size_t slot = in->plan.root - in->N;
-  hipLaunchKernelGGL(codon_root_kernel, dim3(nb), dim3(256), 0, in->stream,
-                     static_cast<const float*>(in->partials.ptr) + slot * (size_t)in->P * KP,
-                     static_cast<const int32_t*>(in->scales.ptr) + slot * (size_t)in->P,
-                     static_cast<const double*>(in->pi.ptr), static_cast<const double*>(in->weights.ptr),
-                     static_cast<double*>(in->site.ptr), static_cast<double*>(in->blocksum.ptr), in->P, in->K);
-  int rc = hip_check(hipGetLastError(), "codon_root launch");
-  if (rc) return rc;
-  return launch_final_sum(in, nb);
+int codon_launch_root(const CodonSchedule& sc, const CodonProblem* d_probs, hipStream_t st) {
+  hipLaunchKernelGGL(codon_root_kernel, dim3(sc.max_pattern_blocks, sc.n_problems), dim3(256), 0, st, d_probs);
+  hipLaunchKernelGGL(codon_final_kernel, dim3(sc.n_problems), dim3(256), 0, st, d_probs);
+  return hip_check(hipGetLastError(), "codon_root launch");
 }
 
-int launch_codon_pre_grad(EpochInstance* in) {
-  const auto& pl = in->plan;
-  const int tiles = (in->P + TILE - 1) / TILE;
-  const int n_slots = codon_max_slots(in->P);
-  for (int l = pl.n_levels; l >= 1; --l) {
-    const int n_l = pl.level_offset[l + 1] - pl.level_offset[l];
-    if (!n_l) continue;
-    const int R = codon_tiles_per_block(tiles, n_l, 64);
-    const int blocks = (tiles + R - 1) / R;
-    hipLaunchKernelGGL(codon_pre_level_kernel, dim3(blocks, n_l), dim3(256), 0, in->stream,
-                       in->d_level_nodes + pl.level_offset[l], in->d_left, in->d_right,
-                       static_cast<const float*>(in->Pm.ptr), static_cast<const uint8_t*>(in->tips.ptr),
-                       static_cast<const float*>(in->partials.ptr), static_cast<const float*>(in->pre.ptr),
-                       static_cast<float*>(in->pre.ptr), static_cast<const double*>(in->pi.ptr),
-                       static_cast<const float*>(in->weightsT.ptr), pl.root, in->N, in->P, in->K, R, n_slots,
-                       static_cast<float*>(in->Gpart.ptr));
+int codon_launch_pre_grad(const CodonSchedule& sc, const CodonProblem* d_probs, const int2* d_items,
+                          const int2* d_reduce_items, hipStream_t st) {
+  for (int l = sc.n_levels; l >= 1; --l) {
+    const int b = sc.level_off[l - 1], n = sc.level_off[l] - b;
+    if (!n) continue;
+    const int R = sc.level_R[l - 1];
+    const int blocks = (sc.max_tiles + R - 1) / R;
+    hipLaunchKernelGGL(codon_pre_level_kernel, dim3(blocks, n), dim3(256), 0, st, d_probs, d_items + b, R);
   }
   int rc = hip_check(hipGetLastError(), "codon_pre_level launch");
   if (rc) return rc;
-  hipLaunchKernelGGL(codon_grad_reduce_kernel, dim3(in->n_nodes), dim3(256), 0, in->stream,
-                     static_cast<const float*>(in->Gpart.ptr), static_cast<const float*>(in->dPm.ptr),
-                     static_cast<const int32_t*>(in->gslots.ptr), n_slots, pl.root,
-                     static_cast<double*>(in->G.ptr), static_cast<double*>(in->dbranch.ptr));
+  hipLaunchKernelGGL(codon_grad_reduce_kernel, dim3((unsigned)sc.reduce_items.size()), dim3(256), 0, st, d_probs,
+                     d_reduce_items);
   return hip_check(hipGetLastError(), "codon_grad_reduce launch");
 }
 
-// slots written per branch (the block count of its parent's level)
-void codon_slots_per_node(const EpochInstance* in, std::vector<int32_t>& out) {
-  const auto& pl = in->plan;
-  out.assign(in->n_nodes, 0);
-  for (int l = 1; l <= pl.n_levels; ++l) {
-    const int n_l = pl.level_offset[l + 1] - pl.level_offset[l];
-    if (!n_l) continue;
-    const int blocks = codon_blocks(in, n_l);
-    for (int k = pl.level_offset[l]; k < pl.level_offset[l + 1]; ++k) {
-      const int u = pl.level_nodes[k];
-      out[pl.left[u]] = blocks;
-      out[pl.right[u]] = blocks;
-    }
-  }
+// ---- single-instance entry points (schedule built when the tree changes)
+int codon_prepare(EpochInstance* in) {
+  std::vector<std::vector<int32_t>> gslots;
+  codon_build_schedule({in}, in->codon_target_blocks, in->codon_sched, gslots);
+  const CodonProblem d = codon_descriptor(in, static_cast<const int32_t*>(in->gslots.ptr));
+  const auto& sc = in->codon_sched;
+  const size_t bytes = sizeof(CodonProblem) + sizeof(int2) * (sc.items.size() + sc.reduce_items.size());
+  int rc = ensure(in->codon_dev, bytes);
+  if (rc) return rc;
+  std::vector<char> h(bytes);
+  memcpy(h.data(), &d, sizeof(d));
+  memcpy(h.data() + sizeof(d), sc.items.data(), sizeof(int2) * sc.items.size());
+  memcpy(h.data() + sizeof(d) + sizeof(int2) * sc.items.size(), sc.reduce_items.data(),
+         sizeof(int2) * sc.reduce_items.size());
+  rc = hip_check(hipMemcpyAsync(in->codon_dev.ptr, h.data(), bytes, hipMemcpyHostToDevice, in->stream), "codon schedule upload");
+  if (!rc && in->gslots.ptr)
+    rc = hip_check(hipMemcpyAsync(in->gslots.ptr, gslots[0].data(), gslots[0].size() * sizeof(int32_t),
+                                  hipMemcpyHostToDevice, in->stream), "gslots upload");
+  if (!rc) rc = hip_check(hipStreamSynchronize(in->stream), "codon schedule sync");
+  return rc;
+}
+
+namespace {
+const CodonProblem* dev_probs(EpochInstance* in) { return static_cast<const CodonProblem*>(in->codon_dev.ptr); }
+const int2* dev_items(EpochInstance* in) {
+  return reinterpret_cast<const int2*>(static_cast<const char*>(in->codon_dev.ptr) + sizeof(CodonProblem));
+}
+const int2* dev_reduce_items(EpochInstance* in) { return dev_items(in) + in->codon_sched.items.size(); }
+}  // namespace
+
+int launch_codon_post(EpochInstance* in) { return codon_launch_post(in->codon_sched, dev_probs(in), dev_items(in), in->stream); }
+int launch_codon_root(EpochInstance* in) { return codon_launch_root(in->codon_sched, dev_probs(in), in->stream); }
+int launch_codon_pre_grad(EpochInstance* in) {
+  return codon_launch_pre_grad(in->codon_sched, dev_probs(in), dev_items(in), dev_reduce_items(in), in->stream);
 }
 
 }  // namespace epochlik

@@ -167,3 +167,46 @@ def from_problem(prob, precision: str = "fp64", grad_branch: bool = False, grad_
         lik.set_rate_matrix(s, Q, pi)
     lik.set_tree(prob.parent, prob.height, prob.branch_rate, prob.boundaries, prob.interval_process)
     return lik
+
+
+class EpochBatchEvaluator:
+    """Many instances evaluated together in one replayed HIP graph (C ABI epoch_batch_*)."""
+
+    def __init__(self, members, tune_cache: Optional[str] = None):
+        self._lib = _abi.load()
+        self.members = list(members)
+        arr = (ctypes.c_void_p * len(self.members))(*[m._h.value for m in self.members])
+        h = ctypes.c_void_p()
+        check(self._lib.epoch_batch_create(arr, len(self.members),
+                                           tune_cache.encode() if tune_cache else None, ctypes.byref(h)))
+        self._h = h
+
+    def evaluate(self, grad_branch: bool = True, grad_Q: bool = False) -> np.ndarray:
+        what = _abi.EPOCH_EVAL_LOGL | (_abi.EPOCH_EVAL_GRAD_BRANCH if grad_branch else 0) | \
+            (_abi.EPOCH_EVAL_GRAD_Q if grad_Q else 0)
+        out = np.zeros(len(self.members))
+        check(self._lib.epoch_batch_evaluate(self._h, what, _dp(out)))
+        return out
+
+    def gradients(self, i: int, branch: bool = True, Q: bool = False):
+        m = self.members[i]
+        db = np.zeros(m.n_nodes) if branch else None
+        dq = np.zeros((m.n_processes, m.n_states, m.n_states)) if Q else None
+        check(self._lib.epoch_batch_gradients(self._h, i, _dp(db), _dp(dq)))
+        return db, dq
+
+    def target_blocks(self) -> int:
+        v = ctypes.c_int32(0)
+        check(self._lib.epoch_batch_target_blocks(self._h, ctypes.byref(v)))
+        return v.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.epoch_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
