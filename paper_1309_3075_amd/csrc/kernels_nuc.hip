@@ -174,90 +174,161 @@ __device__ inline void reduce16(const T (&v)[16], int lane, T (&out)[2]) {
   out[1] = (CP == 8) ? buf[1] : T(0);
 }
 
-// Raw per-lane data of one child for one tile: the tip state byte, or the
-// stored partial (and its cumulative scale for the post-order pass).  The
-// conversion of a tip state to its indicator vector happens at use, so loads
-// prefetched for the next tile stay in flight.
-template <typename T, bool TIP>
+// Child kinds: a tip (state byte), an internal node whose partial is stored, or
+// a cherry (an internal node whose two children are tips).  Cherries are never
+// stored: their partial is the product of two tip lookups, recomputed by the
+// parent in both passes from the cherry's tip states and transposed tip
+// matrices staged in LDS (row 4 holds the row sums used for missing data).
+enum ChildKind { kTip = 0, kInternal = 1, kCherry = 2 };
+
+template <typename T, int KIND>
 struct ChildBuf;
 template <typename T>
-struct ChildBuf<T, true> {
+struct ChildBuf<T, kTip> {
   int st;
 };
 template <typename T>
-struct ChildBuf<T, false> {
+struct ChildBuf<T, kInternal> {
   V4<T> x;
   int sc;
 };
+template <typename T>
+struct ChildBuf<T, kCherry> {
+  int st1, st2;
+};
 
-template <typename T, bool TIP, bool SCALE>
-__device__ inline void fetch_child(ChildBuf<T, TIP>& cb, int child, int N, int c, int C, int P, int pc,
-                                   const uint8_t* __restrict__ tips, const V4<T>* __restrict__ part,
-                                   const int32_t* __restrict__ scale_in) {
-  if constexpr (TIP) {
-    cb.st = tips[(size_t)child * P + pc];
+template <typename T>
+struct NucCtx {
+  int N, P, C, c, cl;
+  bool cat_ok;
+  const uint8_t* __restrict__ tips;
+  const V4<T>* __restrict__ part;
+  const int32_t* __restrict__ scale_in;
+  const int32_t* __restrict__ left;
+  const int32_t* __restrict__ right;
+  const V4<T>* sTip;  // LDS [4 slots][8 categories][5 rows]
+};
+
+template <typename T, int KIND, bool SCALE>
+__device__ inline void fetch_child(ChildBuf<T, KIND>& cb, const NucCtx<T>& x, int child, int pc) {
+  if constexpr (KIND == kTip) {
+    cb.st = x.tips[(size_t)child * x.P + pc];
+  } else if constexpr (KIND == kInternal) {
+    cb.x = x.part[((size_t)(child - x.N) * x.C + x.c) * x.P + pc];
+    if constexpr (SCALE) cb.sc = x.scale_in[(size_t)(child - x.N) * x.P + pc];
   } else {
-    cb.x = part[((size_t)(child - N) * C + c) * P + pc];
-    if constexpr (SCALE) cb.sc = scale_in[(size_t)(child - N) * P + pc];
+    cb.st1 = x.tips[(size_t)x.left[child] * x.P + pc];
+    cb.st2 = x.tips[(size_t)x.right[child] * x.P + pc];
   }
 }
 
-template <typename T, bool TIP>
-__device__ inline V4<T> child_vec(const ChildBuf<T, TIP>& cb) {
-  if constexpr (TIP)
+// Child vector; for a cherry the raw product of its two tip lookups (slots s0, s0+1).
+template <typename T, int KIND>
+__device__ inline V4<T> child_vec(const ChildBuf<T, KIND>& cb, const NucCtx<T>& x, int s0) {
+  if constexpr (KIND == kTip) {
     return onehot<T>(cb.st);
-  else
+  } else if constexpr (KIND == kInternal) {
     return cb.x;
+  } else {
+    const V4<T> u = x.sTip[(s0 * 8 + x.c) * 5 + (cb.st1 < 4 ? cb.st1 : 4)];
+    const V4<T> w = x.sTip[((s0 + 1) * 8 + x.c) * 5 + (cb.st2 < 4 ? cb.st2 : 4)];
+    V4<T> r;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) r.v[i] = u.v[i] * w.v[i];
+    return r;
+  }
 }
 
-template <typename T, bool TIP>
-__device__ inline int child_scale(const ChildBuf<T, TIP>& cb) {
-  if constexpr (TIP)
+// Post-order only: a cherry's partial is rescaled exactly like a stored one
+// (power of two shared by the categories of the pattern); returns its exponent.
+template <int CP, typename T, int KIND>
+__device__ inline int child_normalise(V4<T>& v, const ChildBuf<T, KIND>& cb, bool cat_ok) {
+  if constexpr (KIND == kTip) {
     return 0;
-  else
+  } else if constexpr (KIND == kInternal) {
     return cb.sc;
+  } else {
+    const T m = group_max_cp<CP>(cat_ok ? max4(v) : T(0));
+    const int e = scale_exponent(m);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v.v[i] = scale_by_pow2(v.v[i], e);
+    return e;
+  }
+}
+
+// Stage the transposed tip matrices of cherry children: slots 0-1 for child a,
+// 2-3 for child b.  Called by every thread of the block before a barrier.
+template <typename T>
+__device__ inline void stage_cherry_tips(V4<T>* sTip, const T* __restrict__ Pm, const int32_t* __restrict__ left,
+                                         const int32_t* __restrict__ right, int N, int C, int a, int b, bool ca,
+                                         bool cb) {
+  for (int t = threadIdx.x; t < 4 * C * 5; t += blockDim.x) {
+    const int slot = t / (C * 5), c = (t / 5) % C, j = t % 5;
+    const int owner = slot < 2 ? a : b;
+    if (!(slot < 2 ? ca : cb)) continue;
+    const int tip = (slot & 1) ? right[owner] : left[owner];
+    const T* M = Pm + ((size_t)tip * C + c) * 16;
+    V4<T> col;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (j < 4) {
+        col.v[i] = M[4 * i + j];
+      } else {
+        col.v[i] = (M[4 * i] + M[4 * i + 1]) + (M[4 * i + 2] + M[4 * i + 3]);
+      }
+    }
+    sTip[(slot * 8 + c) * 5 + j] = col;
+  }
+}
+
+template <typename T>
+__device__ inline int kind_of(int v, int N, const int32_t* __restrict__ left, const int32_t* __restrict__ right) {
+  if (v < N) return kTip;
+  return (left[v] < N && right[v] < N) ? kCherry : kInternal;
 }
 
 // ---------------------------------------------------------------------------
-template <typename T, int CP, bool TA, bool TB>
-__device__ inline void post_tiles(int u, int a, int b, int N, int P, int C, int c, int cl, bool cat_ok,
-                                  int first, int R, const M4<T>& Pa, const M4<T>& Pb,
-                                  const uint8_t* __restrict__ tips, const V4<T>* __restrict__ part_in,
-                                  V4<T>* __restrict__ part_out, const int32_t* __restrict__ scale_in,
-                                  int32_t* __restrict__ scale_out) {
+template <typename T, int CP, int KA, int KB>
+__device__ inline void post_tiles(const NucCtx<T>& x, int u, int a, int b, int first, int R, const M4<T>& Pa,
+                                  const M4<T>& Pb, V4<T>* __restrict__ part_out, int32_t* __restrict__ scale_out) {
   constexpr int TPW = 64 / CP;
+  const int N = x.N, P = x.P, C = x.C, c = x.c;
   const int pbase = first + (int)(threadIdx.x & 63) / CP;
-  ChildBuf<T, TA> ca;
-  ChildBuf<T, TB> cb;
+  ChildBuf<T, KA> ca;
+  ChildBuf<T, KB> cb;
   {
     const int pc = pbase < P ? pbase : P - 1;
-    fetch_child<T, TA, true>(ca, a, N, c, C, P, pc, tips, part_in, scale_in);
-    fetch_child<T, TB, true>(cb, b, N, c, C, P, pc, tips, part_in, scale_in);
+    fetch_child<T, KA, true>(ca, x, a, pc);
+    fetch_child<T, KB, true>(cb, x, b, pc);
   }
   for (int r = 0; r < R; ++r) {
     if (first + r * TPW >= P) break;  // uniform
     const int p = pbase + r * TPW;
-    ChildBuf<T, TA> na = ca;
-    ChildBuf<T, TB> nb = cb;
+    ChildBuf<T, KA> na = ca;
+    ChildBuf<T, KB> nb = cb;
     if (r + 1 < R) {
       const int pn = p + TPW;
       const int pc = pn < P ? pn : P - 1;
-      fetch_child<T, TA, true>(na, a, N, c, C, P, pc, tips, part_in, scale_in);
-      fetch_child<T, TB, true>(nb, b, N, c, C, P, pc, tips, part_in, scale_in);
+      fetch_child<T, KA, true>(na, x, a, pc);
+      fetch_child<T, KB, true>(nb, x, b, pc);
     }
-    const V4<T> va = matvec(Pa, child_vec(ca));
-    const V4<T> vb = matvec(Pb, child_vec(cb));
-    V4<T> x;
+    V4<T> xa = child_vec<T, KA>(ca, x, 0);
+    V4<T> xb = child_vec<T, KB>(cb, x, 2);
+    const int sa = child_normalise<CP, T, KA>(xa, ca, x.cat_ok);
+    const int sb = child_normalise<CP, T, KB>(xb, cb, x.cat_ok);
+    const V4<T> va = matvec(Pa, xa);
+    const V4<T> vb = matvec(Pb, xb);
+    V4<T> y;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) x.v[i] = va.v[i] * vb.v[i];
-    T m = cat_ok ? max4(x) : T(0);
+    for (int i = 0; i < 4; ++i) y.v[i] = va.v[i] * vb.v[i];
+    T m = x.cat_ok ? max4(y) : T(0);
     m = group_max_cp<CP>(m);
     const int e = scale_exponent(m);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) x.v[i] = scale_by_pow2(x.v[i], e);
-    if (p < P && cat_ok) {
-      part_out[((size_t)(u - N) * C + c) * P + p] = x;
-      if (cl == 0) scale_out[(size_t)(u - N) * P + p] = e + child_scale(ca) + child_scale(cb);
+    for (int i = 0; i < 4; ++i) y.v[i] = scale_by_pow2(y.v[i], e);
+    if (p < P && x.cat_ok) {
+      part_out[((size_t)(u - N) * C + c) * P + p] = y;
+      if (x.cl == 0) scale_out[(size_t)(u - N) * P + p] = e + sa + sb;
     }
     ca = na;
     cb = nb;
@@ -271,26 +342,35 @@ __global__ __launch_bounds__(256) void nuc_post_level_kernel(
     V4<T>* __restrict__ part_out, const int32_t* __restrict__ scale_in, int32_t* __restrict__ scale_out,
     int N, int P, int C, int R) {
   constexpr int TPW = 64 / CP;  // patterns per wavefront tile
+  __shared__ V4<T> sTip[4 * 8 * 5];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int cl = lane & (CP - 1);
   const bool cat_ok = cl < C;
   const int c = cat_ok ? cl : 0;
   const int u = nodes[blockIdx.y];
-  const int a = left[u], b = right[u];
+  int a = left[u], b = right[u];
+  int ka = kind_of<T>(a, N, left, right), kb = kind_of<T>(b, N, left, right);
+  if (ka > kb) {  // canonical order: the smaller kind first (the product is symmetric)
+    const int t = a; a = b; b = t;
+    const int k = ka; ka = kb; kb = k;
+  }
+  stage_cherry_tips<T>(sTip, Pm, left, right, N, C, a, b, ka == kCherry, kb == kCherry);
+  __syncthreads();
   const int first = (blockIdx.x * 4 + wave) * R * TPW;  // first pattern of the wavefront
-  if (first >= P) return;                                // uniform across the wavefront
+  if (first >= P) return;                                // uniform across the wavefront (after the barrier)
   const M4<T> Pa = load_matrix(Pm + ((size_t)a * C + c) * 16);
   const M4<T> Pb = load_matrix(Pm + ((size_t)b * C + c) * 16);
-  const bool ta = a < N, tb = b < N;  // uniform
-  if (ta && tb)
-    post_tiles<T, CP, true, true>(u, a, b, N, P, C, c, cl, cat_ok, first, R, Pa, Pb, tips, part_in, part_out, scale_in, scale_out);
-  else if (ta)
-    post_tiles<T, CP, true, false>(u, a, b, N, P, C, c, cl, cat_ok, first, R, Pa, Pb, tips, part_in, part_out, scale_in, scale_out);
-  else if (tb)
-    post_tiles<T, CP, false, true>(u, a, b, N, P, C, c, cl, cat_ok, first, R, Pa, Pb, tips, part_in, part_out, scale_in, scale_out);
-  else
-    post_tiles<T, CP, false, false>(u, a, b, N, P, C, c, cl, cat_ok, first, R, Pa, Pb, tips, part_in, part_out, scale_in, scale_out);
+  const NucCtx<T> x{N, P, C, c, cl, cat_ok, tips, part_in, scale_in, left, right, sTip};
+#define EPOCH_POST_CASE(A, B) \
+  if (ka == A && kb == B) return post_tiles<T, CP, A, B>(x, u, a, b, first, R, Pa, Pb, part_out, scale_out)
+  EPOCH_POST_CASE(kTip, kTip);
+  EPOCH_POST_CASE(kTip, kInternal);
+  EPOCH_POST_CASE(kTip, kCherry);
+  EPOCH_POST_CASE(kInternal, kInternal);
+  EPOCH_POST_CASE(kInternal, kCherry);
+  EPOCH_POST_CASE(kCherry, kCherry);
+#undef EPOCH_POST_CASE
 }
 
 // ---------------------------------------------------------------------------
@@ -328,42 +408,44 @@ __global__ __launch_bounds__(256) void nuc_root_kernel(
 }
 
 // ---------------------------------------------------------------------------
-template <typename T, int CP, bool TA, bool TB, bool ROOT>
-__device__ inline void pre_tiles(int u, int a, int b, int N, int P, int C, int c, bool cat_ok, int first,
-                                 int R, const M4<T>& Pa, const M4<T>& Pb, T wc, const V4<T>& qroot,
-                                 const uint8_t* __restrict__ tips, const V4<T>* __restrict__ part,
-                                 const V4<T>* __restrict__ pre_in, V4<T>* __restrict__ pre_out,
-                                 const T* __restrict__ weights, T (&ga)[16], T (&gb)[16]) {
+template <typename T, int CP, int KA, int KB, bool ROOT>
+__device__ inline void pre_tiles(const NucCtx<T>& x, int u, int a, int b, int first, int R, const M4<T>& Pa,
+                                 const M4<T>& Pb, T wc, const V4<T>& qroot, const V4<T>* __restrict__ pre_in,
+                                 V4<T>* __restrict__ pre_out, const T* __restrict__ weights, T (&ga)[16],
+                                 T (&gb)[16]) {
   constexpr int TPW = 64 / CP;
+  const int N = x.N, P = x.P, C = x.C, c = x.c;
+  const bool cat_ok = x.cat_ok;
   const int pbase = first + (int)(threadIdx.x & 63) / CP;
-  ChildBuf<T, TA> ca;
-  ChildBuf<T, TB> cb;
+  ChildBuf<T, KA> ca;
+  ChildBuf<T, KB> cb;
   V4<T> q = qroot;
   T w;
   {
     const int pc = pbase < P ? pbase : P - 1;
     if constexpr (!ROOT) q = pre_in[((size_t)(u - N) * C + c) * P + pc];
-    fetch_child<T, TA, false>(ca, a, N, c, C, P, pc, tips, part, nullptr);
-    fetch_child<T, TB, false>(cb, b, N, c, C, P, pc, tips, part, nullptr);
+    fetch_child<T, KA, false>(ca, x, a, pc);
+    fetch_child<T, KB, false>(cb, x, b, pc);
     w = weights[pc];
   }
   for (int r = 0; r < R; ++r) {
     if (first + r * TPW >= P) break;  // uniform
     const int p = pbase + r * TPW;
-    ChildBuf<T, TA> na = ca;
-    ChildBuf<T, TB> nb = cb;
+    ChildBuf<T, KA> na = ca;
+    ChildBuf<T, KB> nb = cb;
     V4<T> nq = q;
     T nw = w;
     if (r + 1 < R) {
       const int pn = p + TPW;
       const int pc = pn < P ? pn : P - 1;
       if constexpr (!ROOT) nq = pre_in[((size_t)(u - N) * C + c) * P + pc];
-      fetch_child<T, TA, false>(na, a, N, c, C, P, pc, tips, part, nullptr);
-      fetch_child<T, TB, false>(nb, b, N, c, C, P, pc, tips, part, nullptr);
+      fetch_child<T, KA, false>(na, x, a, pc);
+      fetch_child<T, KB, false>(nb, x, b, pc);
       nw = weights[pc];
     }
-    const V4<T> xa = child_vec(ca);
-    const V4<T> xb = child_vec(cb);
+    // a cherry's recomputed partial is left unscaled: its scale cancels in the ratios
+    const V4<T> xa = child_vec<T, KA>(ca, x, 0);
+    const V4<T> xb = child_vec<T, KB>(cb, x, 2);
     const V4<T> sa = matvec(Pa, xa);
     const V4<T> sb = matvec(Pb, xb);
     T l = 0;
@@ -387,7 +469,7 @@ __device__ inline void pre_tiles(int u, int a, int b, int N, int P, int C, int c
         gb[4 * i + j] += fb * xb.v[j];
       }
     }
-    if constexpr (!TA) {
+    if constexpr (KA != kTip) {
       V4<T> qa = matvec_t(Pa, ta);
       const T ma = group_max_cp<CP>(cat_ok ? max4(qa) : T(0));
       const int ea = scale_exponent(ma);
@@ -395,7 +477,7 @@ __device__ inline void pre_tiles(int u, int a, int b, int N, int P, int C, int c
       for (int i = 0; i < 4; ++i) qa.v[i] = scale_by_pow2(qa.v[i], ea);
       if (p < P && cat_ok) pre_out[((size_t)(a - N) * C + c) * P + p] = qa;
     }
-    if constexpr (!TB) {
+    if constexpr (KB != kTip) {
       V4<T> qb = matvec_t(Pb, tb);
       const T mb = group_max_cp<CP>(cat_ok ? max4(qb) : T(0));
       const int eb = scale_exponent(mb);
@@ -411,20 +493,21 @@ __device__ inline void pre_tiles(int u, int a, int b, int N, int P, int C, int c
 }
 
 template <typename T, int CP, bool ROOT>
-__device__ inline void pre_dispatch_kind(int u, int a, int b, int N, int P, int C, int c, bool cat_ok, int first,
-                                         int R, const M4<T>& Pa, const M4<T>& Pb, T wc, const V4<T>& qroot,
-                                         const uint8_t* __restrict__ tips, const V4<T>* __restrict__ part,
+__device__ inline void pre_dispatch_kind(const NucCtx<T>& x, int ka, int kb, int u, int a, int b, int first, int R,
+                                         const M4<T>& Pa, const M4<T>& Pb, T wc, const V4<T>& qroot,
                                          const V4<T>* __restrict__ pre_in, V4<T>* __restrict__ pre_out,
                                          const T* __restrict__ weights, T (&ga)[16], T (&gb)[16]) {
-  const bool ta = a < N, tb = b < N;  // uniform
-  if (ta && tb)
-    pre_tiles<T, CP, true, true, ROOT>(u, a, b, N, P, C, c, cat_ok, first, R, Pa, Pb, wc, qroot, tips, part, pre_in, pre_out, weights, ga, gb);
-  else if (ta)
-    pre_tiles<T, CP, true, false, ROOT>(u, a, b, N, P, C, c, cat_ok, first, R, Pa, Pb, wc, qroot, tips, part, pre_in, pre_out, weights, ga, gb);
-  else if (tb)
-    pre_tiles<T, CP, false, true, ROOT>(u, a, b, N, P, C, c, cat_ok, first, R, Pa, Pb, wc, qroot, tips, part, pre_in, pre_out, weights, ga, gb);
-  else
-    pre_tiles<T, CP, false, false, ROOT>(u, a, b, N, P, C, c, cat_ok, first, R, Pa, Pb, wc, qroot, tips, part, pre_in, pre_out, weights, ga, gb);
+#define EPOCH_PRE_CASE(A, B)                                                                              \
+  if (ka == A && kb == B)                                                                                 \
+    return pre_tiles<T, CP, A, B, ROOT>(x, u, a, b, first, R, Pa, Pb, wc, qroot, pre_in, pre_out, weights, \
+                                        ga, gb)
+  EPOCH_PRE_CASE(kTip, kTip);
+  EPOCH_PRE_CASE(kTip, kInternal);
+  EPOCH_PRE_CASE(kTip, kCherry);
+  EPOCH_PRE_CASE(kInternal, kInternal);
+  EPOCH_PRE_CASE(kInternal, kCherry);
+  EPOCH_PRE_CASE(kCherry, kCherry);
+#undef EPOCH_PRE_CASE
 }
 
 template <typename T, int CP>
@@ -436,13 +519,21 @@ __global__ __launch_bounds__(256) void nuc_pre_level_kernel(
     int n_slots, double* __restrict__ Gpart) {
   constexpr int TPW = 64 / CP;
   __shared__ T sG[4][2][CP][16];
+  __shared__ V4<T> sTip[4 * 8 * 5];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int cl = lane & (CP - 1);
   const bool cat_ok = cl < C;
   const int c = cat_ok ? cl : 0;
   const int u = nodes[blockIdx.y];
-  const int a = left[u], b = right[u];
+  int a = left[u], b = right[u];
+  int ka = kind_of<T>(a, N, left, right), kb = kind_of<T>(b, N, left, right);
+  if (ka > kb) {  // canonical order; each child's gradient still goes to its own branch
+    const int t = a; a = b; b = t;
+    const int k = ka; ka = kb; kb = k;
+  }
+  stage_cherry_tips<T>(sTip, Pm, left, right, N, C, a, b, ka == kCherry, kb == kCherry);
+  __syncthreads();
   T ga[16], gb[16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
@@ -457,10 +548,11 @@ __global__ __launch_bounds__(256) void nuc_pre_level_kernel(
     V4<T> qroot;
 #pragma unroll
     for (int i = 0; i < 4; ++i) qroot.v[i] = T(pi[i]);
+    const NucCtx<T> x{N, P, C, c, cl, cat_ok, tips, part, nullptr, left, right, sTip};
     if (u == root)
-      pre_dispatch_kind<T, CP, true>(u, a, b, N, P, C, c, cat_ok, first, R, Pa, Pb, wc, qroot, tips, part, pre_in, pre_out, weights, ga, gb);
+      pre_dispatch_kind<T, CP, true>(x, ka, kb, u, a, b, first, R, Pa, Pb, wc, qroot, pre_in, pre_out, weights, ga, gb);
     else
-      pre_dispatch_kind<T, CP, false>(u, a, b, N, P, C, c, cat_ok, first, R, Pa, Pb, wc, qroot, tips, part, pre_in, pre_out, weights, ga, gb);
+      pre_dispatch_kind<T, CP, false>(x, ka, kb, u, a, b, first, R, Pa, Pb, wc, qroot, pre_in, pre_out, weights, ga, gb);
   }
   // wavefront reduce-scatter, then the four wavefronts of the block in order
   T ra[2], rb[2];
@@ -516,7 +608,9 @@ int post_dispatch_cp(EpochInstance* in) {
   const uint8_t* tips = static_cast<const uint8_t*>(in->tips.ptr);
   V4<T>* part = static_cast<V4<T>*>(in->partials.ptr);
   int32_t* sc = static_cast<int32_t*>(in->scales.ptr);
-  for (int l = 1; l <= pl.n_levels; ++l) {
+  // level 1 holds exactly the cherries, which are recomputed by their parents;
+  // it is launched only when the root itself is a cherry (two tips)
+  for (int l = (pl.n_levels == 1 ? 1 : 2); l <= pl.n_levels; ++l) {
     const int n_l = pl.level_offset[l + 1] - pl.level_offset[l];
     if (!n_l) continue;
     const int R = tiles_per_wave(tiles, n_l, 1, 16);
