@@ -103,7 +103,7 @@ int build_schedule(EpochBatch* b) {
 int enqueue(EpochBatch* b, uint32_t what, const double* const* d_result_ptrs) {
   const size_t n = b->insts.size();
   for (auto* in : b->insts) {
-    int rc = launch_pstage_generic(in);
+    int rc = launch_pstage(in);
     if (rc) return rc;
   }
   if (b->merged) {

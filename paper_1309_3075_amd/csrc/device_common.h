@@ -28,6 +28,8 @@ __device__ inline double scale_by_pow2(double x, int e) { return ldexp(x, -e); }
 
 __device__ inline float dev_exp(float x) { return expf(x); }
 __device__ inline double dev_exp(double x) { return exp(x); }
+__device__ inline float dev_expm1(float x) { return expm1f(x); }
+__device__ inline double dev_expm1(double x) { return expm1(x); }
 __device__ inline float dev_cos(float x) { return cosf(x); }
 __device__ inline double dev_cos(double x) { return cos(x); }
 __device__ inline float dev_sin(float x) { return sinf(x); }

@@ -56,8 +56,13 @@ int fastpath_tree_changed(EpochInstance* in) {
     if (_rc) return _rc;                \
   } while (0)
 
+int launch_pstage(EpochInstance* in) {
+  if (in->cfg.kernel_path == EPOCH_KERNEL_AUTO && pstage_mfma_supported(in)) return launch_pstage_mfma(in);
+  return launch_pstage_generic(in);
+}
+
 int fastpath_pstage(EpochInstance* in) {
-  EPOCH_PHASE(0, launch_pstage_generic(in));
+  EPOCH_PHASE(0, launch_pstage(in));
   return EPOCH_OK;
 }
 

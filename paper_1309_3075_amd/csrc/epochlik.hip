@@ -405,13 +405,28 @@ int set_epoch_eigensystems(EpochInstance* in, int32_t s, const double* V, const 
   std::fill(hVi, hVi + KK, 0.0);
   std::fill(hr, hr + Kp, 0.0);
   std::fill(hi, hi + Kp, 0.0);
-  for (int i = 0; i < K; ++i) {
-    for (int j = 0; j < K; ++j) {
-      hV[i * Kp + j] = V[i * K + j];
-      hVi[i * Kp + j] = Vinv[i * K + j];
+  // Device column order: complex pairs first, so that every pair occupies an
+  // (even, odd) column couple, then the real eigenvalues.  Permuting the
+  // columns of V, the rows of V^-1 and the eigenvalues together leaves
+  // V diag(.) V^-1 unchanged.
+  std::vector<int> order;
+  order.reserve(K);
+  for (int j = 0; j < K; ++j)
+    if (lambda_im && lambda_im[j] > 0) {
+      order.push_back(j);
+      order.push_back(j + 1);
     }
-    hr[i] = lambda_re[i];
-    hi[i] = lambda_im ? lambda_im[i] : 0.0;
+  for (int j = 0; j < K; ++j)
+    if (!lambda_im || lambda_im[j] == 0) order.push_back(j);
+  for (int i = 0; i < K; ++i) {
+    for (int q = 0; q < K; ++q) {
+      hV[i * Kp + q] = V[i * K + order[q]];
+      hVi[q * Kp + i] = Vinv[order[q] * K + i];
+    }
+  }
+  for (int q = 0; q < K; ++q) {
+    hr[q] = lambda_re[order[q]];
+    hi[q] = lambda_im ? lambda_im[order[q]] : 0.0;
   }
   in->any_complex = false;
   for (double x : in->h_lim)

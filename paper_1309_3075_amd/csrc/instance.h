@@ -141,6 +141,9 @@ int ensure(DevBuf& b, size_t bytes);
 // kernel launchers (kernels_generic.hip); all return EPOCH_OK or an error code
 int launch_eigen_check(EpochInstance* in, int s, const double* dQ, double* d_out);
 int launch_pstage_generic(EpochInstance* in);
+int launch_pstage_mfma(EpochInstance* in);
+bool pstage_mfma_supported(const EpochInstance* in);
+int launch_pstage(EpochInstance* in);  // matrix-core kernel where it applies, else generic
 int launch_post_generic(EpochInstance* in);
 int launch_root_generic(EpochInstance* in);
 int launch_pre_generic(EpochInstance* in);

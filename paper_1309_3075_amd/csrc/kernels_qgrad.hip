@@ -22,9 +22,6 @@ namespace epochlik {
 
 namespace {
 
-__device__ inline float dev_expm1(float x) { return expm1f(x); }
-__device__ inline double dev_expm1(double x) { return expm1(x); }
-
 struct cplx {
   double re, im;
 };
