@@ -35,6 +35,8 @@ struct EpochBatch {
   CodonSchedule sched;
   DevBuf dev;                  // descriptors + items + reduce items
   std::vector<DevBuf> gslots;  // per member
+  DevBuf gpart;                // dlogL/dP slot partials of every member
+  DevBuf dpart;                // per-chunk shares of dlogL/dl
   DevBuf results;              // double [n]
   std::vector<uint64_t> signature;
   hipGraph_t graph[8] = {};
@@ -77,17 +79,25 @@ int build_schedule(EpochBatch* b) {
   std::vector<std::vector<int32_t>> gs;
   codon_build_schedule(cin, b->target_blocks, b->sched, gs);
   const size_t n = b->insts.size();
+  const auto& sc = b->sched;
+  size_t total = 0;
+  for (size_t q = 0; q < n; ++q) total += sc.slot_total[q];
+  int rc0 = ensure(b->gpart, std::max<size_t>(1, total) * kCodonSlotBytes);
+  if (!rc0) rc0 = ensure(b->dpart, codon_dpart_bytes(sc));
+  if (rc0) return rc0;
   b->gslots.resize(n);
   std::vector<CodonProblem> desc(n);
+  size_t off = 0;
   for (size_t q = 0; q < n; ++q) {
     int rc = ensure(b->gslots[q], gs[q].size() * sizeof(int32_t));
     if (rc) return rc;
     rc = hip_check(hipMemcpy(b->gslots[q].ptr, gs[q].data(), gs[q].size() * sizeof(int32_t), hipMemcpyHostToDevice),
                    "batch gslots upload");
     if (rc) return rc;
-    desc[q] = codon_descriptor(b->insts[q], static_cast<const int32_t*>(b->gslots[q].ptr));
+    float* region = static_cast<float*>(b->gpart.ptr) + off * (kCodonSlotBytes / sizeof(float));
+    desc[q] = codon_descriptor(b->insts[q], static_cast<const int32_t*>(b->gslots[q].ptr), region);
+    off += sc.slot_total[q];
   }
-  const auto& sc = b->sched;
   const size_t bytes = sizeof(CodonProblem) * n + sizeof(int2) * (sc.items.size() + sc.reduce_items.size());
   int rc = ensure(b->dev, bytes);
   if (rc) return rc;
@@ -112,7 +122,7 @@ int enqueue(EpochBatch* b, uint32_t what, const double* const* d_result_ptrs) {
     const int2* red = items + b->sched.items.size();
     int rc = codon_launch_post(b->sched, probs, items, b->stream);
     if (!rc) rc = codon_launch_root(b->sched, probs, b->stream);
-    if (!rc && (what & (kGradBranch | kGradQ))) rc = codon_launch_pre_grad(b->sched, probs, items, red, b->stream);
+    if (!rc && (what & (kGradBranch | kGradQ))) rc = codon_launch_pre_grad(b->sched, probs, items, red, static_cast<double*>(b->dpart.ptr), b->stream);
     if (rc) return rc;
   } else {
     for (auto* in : b->insts) {
@@ -384,6 +394,8 @@ int epoch_batch_destroy(EpochBatch* b) {
   if (!b) return EPOCH_OK;
   drop_graphs(b);
   release_buf(b->dev);
+  release_buf(b->gpart);
+  release_buf(b->dpart);
   release_buf(b->results);
   for (auto& g : b->gslots) release_buf(g);
   if (b->own_stream) (void)hipStreamDestroy(b->stream);

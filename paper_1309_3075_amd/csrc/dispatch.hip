@@ -27,12 +27,6 @@ int fastpath_init(EpochInstance* in) {
     if (rc) return rc;
     return ensure(in->gslots, (size_t)in->n_nodes * sizeof(int32_t));
   }
-  if (codon(in) && grad) {
-    const size_t bytes = (size_t)codon_max_slots(in->P) * in->n_nodes * 64 * 64 * sizeof(float);
-    int rc = ensure(in->Gpart, std::max(bytes, in->Gpart.bytes));
-    if (rc) return rc;
-    return ensure(in->gslots, (size_t)in->n_nodes * sizeof(int32_t));
-  }
   return EPOCH_OK;
 }
 void fastpath_release(EpochInstance*) {}

@@ -297,7 +297,7 @@ int epoch_destroy(EpochInstance* in) {
   for (DevBuf* b : {&in->eigT, &in->eig64, &in->check, &in->tips, &in->weights, &in->weightsT, &in->pi,
                     &in->cat, &in->tree_i, &in->tree_d, &in->Pm, &in->dPm, &in->partials, &in->scales,
                     &in->pre, &in->site, &in->blocksum, &in->result, &in->Gpart, &in->G, &in->dbranch,
-                    &in->qseg, &in->qscratch, &in->dQ, &in->seglist, &in->gslots, &in->codon_dev})
+                    &in->qseg, &in->qscratch, &in->dQ, &in->seglist, &in->gslots, &in->codon_dev, &in->codon_aux})
     release(*b);
   delete in;
   return EPOCH_OK;

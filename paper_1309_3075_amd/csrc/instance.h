@@ -37,16 +37,17 @@ struct CodonProblem {
   double* result;
   const int32_t* left;
   const int32_t* right;
-  const int32_t* gslots;
-  int N, P, K, root, n_slots, n_nodes;
+  const int32_t* gslots;  // [2 n_nodes]: dlogL/dP partial slots written per branch, then each branch's first slot
+  int N, P, K, root, n_nodes;
 };
 
 // Merged level schedule: work items (problem, internal node) grouped by level.
 struct CodonSchedule {
   std::vector<int2> items;         // level l (1-based) occupies [level_off[l-1], level_off[l])
   std::vector<int> level_off;
-  std::vector<int> level_R;        // pattern tiles per block of the pre-order launch of each level
+  std::vector<int> level_R;        // 64-pattern tiles per block of the launches of each level
   std::vector<int2> reduce_items;  // every (problem, node)
+  std::vector<size_t> slot_total;  // dlogL/dP partial slots of each problem
   int n_levels = 0, max_tiles = 0, max_pattern_blocks = 0, n_problems = 0;
 };
 
@@ -109,6 +110,7 @@ struct EpochInstance {
   epochlik::DevBuf seglist;    // int32 segments grouped by process: offsets [S+1], items [nseg*C]
   epochlik::DevBuf gslots;     // int32 [n]: partial-sum slots written per branch (4-state / 64-state gradient)
   epochlik::DevBuf codon_dev;  // 64-state path: descriptor + work items
+  epochlik::DevBuf codon_aux;  // 64-state path: per-chunk shares of dlogL/dl (double)
   epochlik::CodonSchedule codon_sched;
   int codon_target_blocks = 1024;  // blocks per pre-order launch the 64-state schedule aims for
 
@@ -163,14 +165,15 @@ void nuc_slots_per_node(const EpochInstance* in, std::vector<int32_t>& out);
 int launch_codon_post(EpochInstance* in);
 int launch_codon_root(EpochInstance* in);
 int launch_codon_pre_grad(EpochInstance* in);
-int codon_max_slots(int P);
 int codon_prepare(EpochInstance* in);
-CodonProblem codon_descriptor(const EpochInstance* in, const int32_t* gslots);
+CodonProblem codon_descriptor(const EpochInstance* in, const int32_t* gslots, float* gpart);
+constexpr size_t kCodonSlotBytes = 64 * 64 * sizeof(float);  // one FP32 64x64 partial of dlogL/dP
 void codon_build_schedule(const std::vector<const EpochInstance*>& insts, int target_blocks, CodonSchedule& out,
                           std::vector<std::vector<int32_t>>& gslots);
 int codon_launch_post(const CodonSchedule& sc, const CodonProblem* d_probs, const int2* d_items, hipStream_t st);
 int codon_launch_root(const CodonSchedule& sc, const CodonProblem* d_probs, hipStream_t st);
+size_t codon_dpart_bytes(const CodonSchedule& sc);
 int codon_launch_pre_grad(const CodonSchedule& sc, const CodonProblem* d_probs, const int2* d_items,
-                          const int2* d_reduce_items, hipStream_t st);
+                          const int2* d_reduce_items, double* dpart, hipStream_t st);
 
 }  // namespace epochlik

@@ -8,16 +8,19 @@
 // r = lane % 16):  A[m][k]: m = r, k = g;  B[k][n]: k = g, n = r;
 // D[m][n] (4 registers v): m = 4 g + v, n = r.
 //
-// Block = 4 wavefronts = one node and one tile of 64 patterns; wavefront w
-// produces output states 16 w .. 16 w + 15 for all 64 patterns (four 16x16
-// blocks along the patterns).  The contraction index k runs over states; its
-// order inside a 16-wide group is permuted (k = 16 t + 4 g + e) so that both
-// operands come from 16-byte loads.
-//   codon_post_level : Eq. 4 for one level, per-pattern power-of-two scale
-//                      agreed across the four wavefronts through LDS.
-//   codon_pre_level  : outside vectors of one level and dlogL/dP of the two
-//                      child branches, accumulated over R tiles as MFMA
-//                      outer products; rows 16 w .. 16 w + 15 of G per wavefront.
+// Work split.  A block takes one internal node and R tiles of 64 patterns;
+// it stages the two child transition matrices in LDS (row sums in the
+// padding column, so a missing tip state is one more column), and each of
+// its four wavefronts then works alone on 16-pattern tiles: D-layout
+// registers hold pattern 4 g + v, state 16 nt + r of each 16x16 block nt.
+//   child vectors   S = L P^T     A = child partial rows (16-byte loads), B = P rows (LDS)
+//   post-order      x = S_a o S_b, per-pattern power-of-two scale (row reduction by DPP)
+//   dlogL/dP        G += sum_p (w_p / L_p) t_p L_p^T, contraction over the 16
+//                   patterns: A = t (registers), B = child partials in the D layout
+//   outside vector  q_c = t P_c    A = t through a wave-private LDS transpose, B = P (LDS)
+// with t = q_u o S_sibling.  The four wavefronts' dlogL/dP partials are
+// summed in LDS in a fixed order and written to one slot per block; a last
+// kernel sums the slots of each branch in FP64.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,6 +29,8 @@
 #include "device_common.h"
 #include "instance.h"
 
+#define EPOCH_GLOBAL __attribute__((address_space(1)))
+
 namespace epochlik {
 
 namespace {
@@ -33,19 +38,46 @@ namespace {
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int KP = 64;
-constexpr int LDP = 68;  // padded LDS row stride (floats) against bank conflicts
-constexpr int TILE = 64;
-constexpr int kMaxSlots = 64;  // partial-sum slots per branch (blocks sharing one node)
+constexpr int KK = KP * KP;
+constexpr int LDP = 68;  // LDS row stride (floats): 64 states, the row sum, padding
+constexpr int TILE = 64;  // patterns per block tile
+constexpr int WT = 16;    // patterns per wavefront tile
 
 __device__ inline f4 mfma(float a, float b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 
+template <typename T>
+__device__ inline const EPOCH_GLOBAL T* gptr(const T* p) {
+  return (const EPOCH_GLOBAL T*)p;
+}
+template <typename T>
+__device__ inline EPOCH_GLOBAL T* gptr(T* p) {
+  return (EPOCH_GLOBAL T*)p;
+}
+
+// Orders LDS accesses of one wavefront (write, then read by other lanes).
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Stage a 64x64 row-major matrix into LDS with row stride LDP.
 __device__ inline void stage_matrix(float* __restrict__ s, const float* __restrict__ g) {
-  for (int e = threadIdx.x; e < KP * KP / 4; e += 256) {
-    const int row = e / 16, c4 = e % 16;
-    const float4 v = reinterpret_cast<const float4*>(g)[e];
-    *reinterpret_cast<float4*>(s + row * LDP + 4 * c4) = v;
+  const EPOCH_GLOBAL f4* src = gptr(reinterpret_cast<const f4*>(g));
+  for (int e = threadIdx.x; e < KK / 4; e += 256) {
+    const int row = e >> 4, c4 = e & 15;
+    *reinterpret_cast<f4*>(s + row * LDP + 4 * c4) = src[e];
   }
+}
+// Row sums over the first K columns into column 64 (needs the staged matrix).
+__device__ inline void stage_row_sums(float* __restrict__ s, int K) {
+  const int row = threadIdx.x >> 2, q = threadIdx.x & 3;
+  float acc = 0.f;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) acc += (16 * q + j < K) ? s[row * LDP + 16 * q + j] : 0.f;
+  acc += __shfl_xor(acc, 1, 4);
+  acc += __shfl_xor(acc, 2, 4);
+  if (q == 0) s[row * LDP + 64] = acc;
 }
 
 // Row-max / row-sum over the 16 lanes of a DPP row (lanes sharing g).
@@ -64,115 +96,119 @@ __device__ inline float row16_sum(float v) {
   return v;
 }
 
-// S[mb] (D layout: pattern 16 mb + 4 g + v, state 16 w + r) = sum_j L[p][j] P[i][j]
-// for an internal child whose 64x64 partial tile starts at Lg (row stride 64).
+// S[nt] (D layout) = sum_j L[p][j] P[16 nt + r][j] for an internal child whose
+// partials start at Lg.  Pattern rows past the end are clamped (their results
+// are never stored).
 __device__ inline void child_gemm(f4 (&S)[4], const float* __restrict__ Lg, int P, int p0,
-                                  const float* __restrict__ sP, int w, int g, int r) {
+                                  const float* __restrict__ sP, int g, int r) {
 #pragma unroll
-  for (int mb = 0; mb < 4; ++mb) S[mb] = f4{0.f, 0.f, 0.f, 0.f};
-  const float* prow = sP + (16 * w + r) * LDP;  // B[k][n] = P[n][k], n = 16 w + r
+  for (int nt = 0; nt < 4; ++nt) S[nt] = f4{0.f, 0.f, 0.f, 0.f};
+  const int pa = min(p0 + r, P - 1);
+  const EPOCH_GLOBAL f4* arow = gptr(reinterpret_cast<const f4*>(Lg + (size_t)pa * KP)) + g;
+  f4 a[4];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const float4 b4 = *reinterpret_cast<const float4*>(prow + 16 * t + 4 * g);
+  for (int t = 0; t < 4; ++t) a[t] = arow[4 * t];  // L[pa][16 t + 4 g .. 16 t + 4 g + 3]
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb) {
-      const int p = p0 + 16 * mb + r;  // A[m][k]: m = r (pattern), k over states
-      float4 a4 = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (p < P) a4 = *reinterpret_cast<const float4*>(Lg + (size_t)p * KP + 16 * t + 4 * g);
-      S[mb] = mfma(a4.x, b4.x, S[mb]);
-      S[mb] = mfma(a4.y, b4.y, S[mb]);
-      S[mb] = mfma(a4.z, b4.z, S[mb]);
-      S[mb] = mfma(a4.w, b4.w, S[mb]);
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const f4 b = *reinterpret_cast<const f4*>(sP + (16 * nt + r) * LDP + 16 * t + 4 * g);
+      S[nt] = mfma(a[t].x, b.x, S[nt]);
+      S[nt] = mfma(a[t].y, b.y, S[nt]);
+      S[nt] = mfma(a[t].z, b.z, S[nt]);
+      S[nt] = mfma(a[t].w, b.w, S[nt]);
     }
-  }
 }
 
-// Tip child: S = P[i][state_p] looked up from LDS (missing state K: row sum).
-__device__ inline void tip_lookup(f4 (&S)[4], const uint8_t* __restrict__ tipst, int P, int p0, int K,
-                                  const float* __restrict__ sP, int w, int g, int r) {
-  const float* prow = sP + (16 * w + r) * LDP;
+// Tip states of patterns p0 + 4 g + v as LDS columns (missing state: column 64).
+__device__ inline void tip_columns(int (&col)[4], const uint8_t* __restrict__ tipst, int P, int p0, int K, int g) {
 #pragma unroll
-  for (int mb = 0; mb < 4; ++mb)
+  for (int v = 0; v < 4; ++v) {
+    const int st = gptr(tipst)[min(p0 + 4 * g + v, P - 1)];
+    col[v] = st < K ? st : 64;
+  }
+}
+// Tip child: S = P[i][state_p].
+__device__ inline void tip_lookup(f4 (&S)[4], const int (&col)[4], const float* __restrict__ sP, int r) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int p = p0 + 16 * mb + 4 * g + v;
-      const int st = p < P ? tipst[p] : 0;
-      float val;
-      if (st < K) {
-        val = prow[st];
-      } else {
-        val = 0.f;
-        for (int j = 0; j < K; ++j) val += prow[j];
-      }
-      S[mb][v] = val;
-    }
+  for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) S[nt][v] = sP[(16 * nt + r) * LDP + col[v]];
+}
+
+// D-layout load of a [P][64] array: value at pattern p0 + 4 g + v, state 16 nt + r.
+__device__ inline void load_dlayout(f4 (&X)[4], const float* __restrict__ base, int P, int p0, int g, int r) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const EPOCH_GLOBAL float* row = gptr(base + (size_t)min(p0 + 4 * g + v, P - 1) * KP) + r;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) X[nt][v] = row[16 * nt];
+  }
 }
 
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void codon_post_level_kernel(const CodonProblem* __restrict__ probs,
-                                                                const int2* __restrict__ items) {
+                                                                const int2* __restrict__ items, int R) {
   __shared__ __align__(16) float sPa[KP * LDP];
   __shared__ __align__(16) float sPb[KP * LDP];
-  __shared__ float smax[4][TILE];
   const int2 it = items[blockIdx.y];
   const CodonProblem& pr = probs[it.x];
   const int N = pr.N, P = pr.P, K = pr.K;
-  const int p0 = blockIdx.x * TILE;
-  if (p0 >= P) return;  // uniform: this problem has fewer tiles
-  const float* __restrict__ Pm = pr.Pm;
-  const uint8_t* __restrict__ tips = pr.tips;
-  const float* __restrict__ part_in = pr.part;
-  float* __restrict__ part_out = pr.part;
-  const int32_t* __restrict__ scale_in = pr.scales;
-  int32_t* __restrict__ scale_out = pr.scales;
+  const int base = blockIdx.x * R * TILE;
+  if (base >= P) return;  // uniform: this problem has fewer tiles
+  const int end = min(P, base + R * TILE);
   const int u = it.y;
   const int a = pr.left[u], b = pr.right[u];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
-  stage_matrix(sPa, Pm + (size_t)a * KP * KP);
-  stage_matrix(sPb, Pm + (size_t)b * KP * KP);
+  stage_matrix(sPa, pr.Pm + (size_t)a * KK);
+  stage_matrix(sPb, pr.Pm + (size_t)b * KK);
   __syncthreads();
-  f4 Sa[4], Sb[4];
-  if (a < N)
-    tip_lookup(Sa, tips + (size_t)a * P, P, p0, K, sPa, w, g, r);
-  else
-    child_gemm(Sa, part_in + (size_t)(a - N) * P * KP, P, p0, sPa, w, g, r);
-  if (b < N)
-    tip_lookup(Sb, tips + (size_t)b * P, P, p0, K, sPb, w, g, r);
-  else
-    child_gemm(Sb, part_in + (size_t)(b - N) * P * KP, P, p0, sPb, w, g, r);
-  // x = Sa * Sb; per-pattern max over this wavefront's 16 states, then over wavefronts
-  float m[4][4];
-#pragma unroll
-  for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      Sa[mb][v] *= Sb[mb][v];
-      m[mb][v] = row16_max(Sa[mb][v]);
+  stage_row_sums(sPa, K);
+  stage_row_sums(sPb, K);
+  __syncthreads();
+  const float* La = a >= N ? pr.part + (size_t)(a - N) * P * KP : nullptr;
+  const float* Lb = b >= N ? pr.part + (size_t)(b - N) * P * KP : nullptr;
+  const int32_t* sca = a >= N ? pr.scales + (size_t)(a - N) * P : nullptr;
+  const int32_t* scb = b >= N ? pr.scales + (size_t)(b - N) * P : nullptr;
+  EPOCH_GLOBAL float* out = gptr(pr.part + (size_t)(u - N) * P * KP);
+  EPOCH_GLOBAL int32_t* sout = gptr(pr.scales + (size_t)(u - N) * P);
+  for (int p0 = base + WT * w; p0 < end; p0 += 4 * WT) {
+    f4 Sa[4], Sb[4];
+    if (La) {
+      child_gemm(Sa, La, P, p0, sPa, g, r);
+    } else {
+      int col[4];
+      tip_columns(col, pr.tips + (size_t)a * P, P, p0, K, g);
+      tip_lookup(Sa, col, sPa, r);
     }
-  if (r == 0)
-#pragma unroll
-    for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) smax[w][16 * mb + 4 * g + v] = m[mb][v];
-  __syncthreads();
-#pragma unroll
-  for (int mb = 0; mb < 4; ++mb)
+    if (Lb) {
+      child_gemm(Sb, Lb, P, p0, sPb, g, r);
+    } else {
+      int col[4];
+      tip_columns(col, pr.tips + (size_t)b * P, P, p0, K, g);
+      tip_lookup(Sb, col, sPb, r);
+    }
+    int e[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int pl = 16 * mb + 4 * g + v;
-      const float mm = fmaxf(fmaxf(smax[0][pl], smax[1][pl]), fmaxf(smax[2][pl], smax[3][pl]));
-      const int e = scale_exponent(mm);
-      const int p = p0 + pl;
+      float m = 0.f;
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) {
+        Sa[nt][v] *= Sb[nt][v];
+        m = fmaxf(m, Sa[nt][v]);
+      }
+      e[v] = scale_exponent(row16_max(m));
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int p = p0 + 4 * g + v;
       if (p < P) {
-        part_out[((size_t)(u - N) * P + p) * KP + 16 * w + r] = ldexpf(Sa[mb][v], -e);
-        if (w == 0 && r == 0) {
-          int s = e;
-          if (a >= N) s += scale_in[(size_t)(a - N) * P + p];
-          if (b >= N) s += scale_in[(size_t)(b - N) * P + p];
-          scale_out[(size_t)(u - N) * P + p] = s;
-        }
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) out[(size_t)p * KP + 16 * nt + r] = ldexpf(Sa[nt][v], -e[v]);
+        if (r == 0) sout[p] = e[v] + (sca ? gptr(sca)[p] : 0) + (scb ? gptr(scb)[p] : 0);
       }
     }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -210,203 +246,222 @@ __global__ __launch_bounds__(256) void codon_final_kernel(const CodonProblem* __
 }
 
 // ---------------------------------------------------------------------------
-// Loads of one pattern block in the D layout (pattern 16 mb + 4 g + v, state
-// 16 nb + r): outside vector q, or a stored partial, or a tip indicator.
-__device__ inline float dval_partial(const float* __restrict__ Lg, int P, int p, int col) {
-  return p < P ? Lg[(size_t)p * KP + col] : 0.f;
-}
-
+// Pre-order of one level fused with dlogL/dP of the two child branches.
 __global__ __launch_bounds__(256) void codon_pre_level_kernel(const CodonProblem* __restrict__ probs,
                                                                const int2* __restrict__ items, int R) {
   __shared__ __align__(16) float sPa[KP * LDP];
   __shared__ __align__(16) float sPb[KP * LDP];
-  __shared__ __align__(16) float sT[TILE * LDP];  // t_a or t_b tile [pattern][state]
-  __shared__ float sx[4][TILE];
+  __shared__ __align__(16) float sT[4][WT * LDP];  // per-wavefront transpose of t
   const int2 it = items[blockIdx.y];
   const CodonProblem& pr = probs[it.x];
-  const int N = pr.N, P = pr.P, K = pr.K, root = pr.root, n_slots = pr.n_slots;
-  if ((int)blockIdx.x * R * TILE >= P) return;  // uniform: this problem has fewer tiles
-  const float* __restrict__ Pm = pr.Pm;
-  const uint8_t* __restrict__ tips = pr.tips;
-  const float* __restrict__ part = pr.part;
-  const float* __restrict__ pre_in = pr.pre;
-  float* __restrict__ pre_out = pr.pre;
-  const double* __restrict__ pi = pr.pi;
-  const float* __restrict__ weights = pr.weightsT;
-  float* __restrict__ Gpart = pr.Gpart;
+  const int N = pr.N, P = pr.P, K = pr.K;
+  const int base = blockIdx.x * R * TILE;
+  if (base >= P) return;  // uniform: this problem has fewer tiles
+  const int end = min(P, base + R * TILE);
   const int u = it.y;
   const int a = pr.left[u], b = pr.right[u];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
-  stage_matrix(sPa, Pm + (size_t)a * KP * KP);
-  stage_matrix(sPb, Pm + (size_t)b * KP * KP);
+  stage_matrix(sPa, pr.Pm + (size_t)a * KK);
+  stage_matrix(sPb, pr.Pm + (size_t)b * KK);
   __syncthreads();
-  // G accumulators: rows 16 w + (4 g + v), columns 16 nb + r, per child
-  f4 Ga[4], Gb[4];
+  stage_row_sums(sPa, K);
+  stage_row_sums(sPb, K);
+  __syncthreads();
+  const float* La = a >= N ? pr.part + (size_t)(a - N) * P * KP : nullptr;
+  const float* Lb = b >= N ? pr.part + (size_t)(b - N) * P * KP : nullptr;
+  const float* Qu = u == pr.root ? nullptr : pr.pre + (size_t)(u - N) * P * KP;
+  float piv[4];
 #pragma unroll
-  for (int nb = 0; nb < 4; ++nb) {
-    Ga[nb] = f4{0.f, 0.f, 0.f, 0.f};
-    Gb[nb] = f4{0.f, 0.f, 0.f, 0.f};
-  }
-  const float* La = a >= N ? part + (size_t)(a - N) * P * KP : nullptr;
-  const float* Lb = b >= N ? part + (size_t)(b - N) * P * KP : nullptr;
-  const float* Qu = u == root ? nullptr : pre_in + (size_t)(u - N) * P * KP;
-  const int my_state = 16 * w + r;
-  const float piv = my_state < K ? (float)pi[my_state] : 0.f;
-  for (int rr = 0; rr < R; ++rr) {
-    const int p0 = (blockIdx.x * R + rr) * TILE;
-    if (p0 >= P) break;  // uniform
+  for (int nt = 0; nt < 4; ++nt) piv[nt] = 16 * nt + r < K ? (float)pr.pi[16 * nt + r] : 0.f;
+  float* tw = sT[w];
+  // dlogL/dP accumulators: row 16 mt + 4 g + v, column 16 nt + r
+  f4 Ga[4][4], Gb[4][4];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      Ga[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
+      Gb[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+  for (int p0 = base + WT * w; p0 < end; p0 += 4 * WT) {
     f4 Sa[4], Sb[4];
-    if (a < N)
-      tip_lookup(Sa, tips + (size_t)a * P, P, p0, K, sPa, w, g, r);
-    else
-      child_gemm(Sa, La, P, p0, sPa, w, g, r);
-    if (b < N)
-      tip_lookup(Sb, tips + (size_t)b * P, P, p0, K, sPb, w, g, r);
-    else
-      child_gemm(Sb, Lb, P, p0, sPb, w, g, r);
-    // q in the D layout and the per-pattern likelihood contributions
+    int cola[4], colb[4];
+    if (La) {
+      child_gemm(Sa, La, P, p0, sPa, g, r);
+    } else {
+      tip_columns(cola, pr.tips + (size_t)a * P, P, p0, K, g);
+      tip_lookup(Sa, cola, sPa, r);
+    }
+    if (Lb) {
+      child_gemm(Sb, Lb, P, p0, sPb, g, r);
+    } else {
+      tip_columns(colb, pr.tips + (size_t)b * P, P, p0, K, g);
+      tip_lookup(Sb, colb, sPb, r);
+    }
     f4 Q[4];
-    float lsum[4][4];
+    if (Qu) {
+      load_dlayout(Q, Qu, P, p0, g, r);
+    } else {
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb)
+      for (int nt = 0; nt < 4; ++nt) Q[nt] = f4{piv[nt], piv[nt], piv[nt], piv[nt]};
+    }
+    // w_p / L_p with L_p = sum_i q_i S_a,i S_b,i (the scales of q, L_a and L_b cancel)
+    float cf[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int p = p0 + 16 * mb + 4 * g + v;
-        Q[mb][v] = Qu ? dval_partial(Qu, P, p, my_state) : piv;
-        lsum[mb][v] = row16_sum(Q[mb][v] * Sa[mb][v] * Sb[mb][v]);
-      }
-    if (r == 0)
+    for (int v = 0; v < 4; ++v) {
+      float s = 0.f;
 #pragma unroll
-      for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) sx[w][16 * mb + 4 * g + v] = lsum[mb][v];
-    __syncthreads();
-    float coef[4][4];
-#pragma unroll
-    for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int pl = 16 * mb + 4 * g + v;
-        const float L = (sx[0][pl] + sx[1][pl]) + (sx[2][pl] + sx[3][pl]);
-        const int p = p0 + pl;
-        coef[mb][v] = (p < P && L > 0.f) ? weights[p] / L : 0.f;
-      }
-    // G_a[i][j] += sum_p coef_p t_a[p][i] L_a[p][j] with t_a = q * S_b:
-    // A[m = i][k = p] is the D-layout register (k-step v), B[k = p][n = j] the child vector.
+      for (int nt = 0; nt < 4; ++nt) s += Q[nt][v] * Sa[nt][v] * Sb[nt][v];
+      s = row16_sum(s);
+      const int p = p0 + 4 * g + v;
+      cf[v] = (p < P && s > 0.f) ? gptr(pr.weightsT)[p] / s : 0.f;
+    }
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
       const int child = side == 0 ? a : b;
       const float* Lc = side == 0 ? La : Lb;
-      f4* G = side == 0 ? Ga : Gb;
-      const uint8_t* tipst = child < N ? tips + (size_t)child * P : nullptr;
-#pragma unroll
-      for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const float t = Q[mb][v] * (side == 0 ? Sb[mb][v] : Sa[mb][v]);
-          const float av = coef[mb][v] * t;
-          const int p = p0 + 16 * mb + 4 * g + v;
-          int st = 0;
-          if (tipst) st = p < P ? tipst[p] : K;
-#pragma unroll
-          for (int nb = 0; nb < 4; ++nb) {
-            const int col = 16 * nb + r;
-            float bv;
-            if (tipst)
-              bv = (p < P && (st == col || (st >= K && col < K))) ? 1.f : 0.f;
-            else
-              bv = dval_partial(Lc, P, p, col);
-            G[nb] = mfma(av, bv, G[nb]);
-          }
-        }
-    }
-    // outside vectors of internal children: q_c[p][j] = sum_i t_c[p][i] P_c[i][j]
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      const int child = side == 0 ? a : b;
-      if (child < N) continue;  // uniform
-      __syncthreads();  // sT is free
-#pragma unroll
-      for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          sT[(16 * mb + 4 * g + v) * LDP + my_state] = Q[mb][v] * (side == 0 ? Sb[mb][v] : Sa[mb][v]);
-      __syncthreads();
+      const f4* So = side == 0 ? Sb : Sa;
+      f4(&G)[4][4] = side == 0 ? Ga : Gb;
       const float* sP = side == 0 ? sPa : sPb;
-      // D[m = p][n = j], j = 16 w + r: A[m = p][k = i] from sT, B[k = i][n = j] = P[i][j]
+      f4 t[4];
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) t[nt] = Q[nt] * So[nt];
+      // G[i][j] += sum_p cf_p t[p][i] L[p][j]: A = cf t (registers), B = child vector
+      f4 B[4];
+      if (Lc) {
+        load_dlayout(B, Lc, P, p0, g, r);
+      } else {
+        const int* col = side == 0 ? cola : colb;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int j = 16 * nt + r;
+            B[nt][v] = (col[v] == j || (col[v] == 64 && j < K)) ? 1.f : 0.f;
+          }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+          const float av = cf[v] * t[mt][v];
+#pragma unroll
+          for (int nt = 0; nt < 4; ++nt) G[mt][nt] = mfma(av, B[nt][v], G[mt][nt]);
+        }
+      if (!Lc) continue;  // tips carry no outside vector
+      // q_c[p][j] = sum_i t[p][i] P_c[i][j]: A = t rows (LDS transpose), B = P_c (LDS)
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) tw[(4 * g + v) * LDP + 16 * nt + r] = t[nt][v];
+      wave_lds_sync();
+      f4 ta[4];
+#pragma unroll
+      for (int tt = 0; tt < 4; ++tt) ta[tt] = *reinterpret_cast<const f4*>(tw + r * LDP + 16 * tt + 4 * g);
+      wave_lds_sync();
       f4 Qo[4];
 #pragma unroll
-      for (int mb = 0; mb < 4; ++mb) Qo[mb] = f4{0.f, 0.f, 0.f, 0.f};
+      for (int nt = 0; nt < 4; ++nt) Qo[nt] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        float b4[4];
+      for (int tt = 0; tt < 4; ++tt)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) b4[e] = sP[(16 * t + 4 * g + e) * LDP + my_state];
-#pragma unroll
-        for (int mb = 0; mb < 4; ++mb) {
-          const float4 a4 = *reinterpret_cast<const float4*>(sT + (16 * mb + r) * LDP + 16 * t + 4 * g);
-          Qo[mb] = mfma(a4.x, b4[0], Qo[mb]);
-          Qo[mb] = mfma(a4.y, b4[1], Qo[mb]);
-          Qo[mb] = mfma(a4.z, b4[2], Qo[mb]);
-          Qo[mb] = mfma(a4.w, b4[3], Qo[mb]);
+        for (int nt = 0; nt < 4; ++nt) {
+          const float* prow = sP + (16 * tt + 4 * g) * LDP + 16 * nt + r;
+          Qo[nt] = mfma(ta[tt].x, prow[0], Qo[nt]);
+          Qo[nt] = mfma(ta[tt].y, prow[LDP], Qo[nt]);
+          Qo[nt] = mfma(ta[tt].z, prow[2 * LDP], Qo[nt]);
+          Qo[nt] = mfma(ta[tt].w, prow[3 * LDP], Qo[nt]);
         }
+      EPOCH_GLOBAL float* out = gptr(pr.pre + (size_t)(child - N) * P * KP);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        float m = 0.f;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) m = fmaxf(m, Qo[nt][v]);
+        const int e = scale_exponent(row16_max(m));
+        const int p = p0 + 4 * g + v;
+        if (p < P)
+#pragma unroll
+          for (int nt = 0; nt < 4; ++nt) out[(size_t)p * KP + 16 * nt + r] = ldexpf(Qo[nt][v], -e);
       }
-      float mx[4][4];
-#pragma unroll
-      for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) mx[mb][v] = row16_max(Qo[mb][v]);
-      __syncthreads();  // every wavefront is done reading sx
-      if (r == 0)
-#pragma unroll
-        for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) sx[w][16 * mb + 4 * g + v] = mx[mb][v];
-      __syncthreads();
-#pragma unroll
-      for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int pl = 16 * mb + 4 * g + v;
-          const float mm = fmaxf(fmaxf(sx[0][pl], sx[1][pl]), fmaxf(sx[2][pl], sx[3][pl]));
-          const int e = scale_exponent(mm);
-          const int p = p0 + pl;
-          if (p < P) pre_out[((size_t)(child - N) * P + p) * KP + my_state] = ldexpf(Qo[mb][v], -e);
-        }
     }
-    __syncthreads();  // sx and sT reuse by the next tile
   }
-  // partial G of this block: rows 16 w + 4 g + v, columns 16 nb + r
+  // Sum the four wavefronts' partials in a fixed order ((w0 + w2) + (w1 + w3))
+  // in LDS, then write this block's slot of each child branch.
+  __syncthreads();  // every wavefront is done with the staged matrices
+  float* red0 = sPa;
+  float* red1 = sPb;
 #pragma unroll
   for (int side = 0; side < 2; ++side) {
     const int child = side == 0 ? a : b;
-    const f4* G = side == 0 ? Ga : Gb;
-    float* dst = Gpart + ((size_t)child * n_slots + blockIdx.x) * (KP * KP);
+    const f4(&G)[4][4] = side == 0 ? Ga : Gb;
+    float* mine = (w & 1) ? red1 : red0;
+    if (w < 2) {
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb)
+      for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) dst[(16 * w + 4 * g + v) * KP + 16 * nb + r] = G[nb][v];
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) mine[(16 * mt + 4 * g + v) * KP + 16 * nt + r] = G[mt][nt][v];
+    }
+    __syncthreads();
+    if (w >= 2) {
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) mine[(16 * mt + 4 * g + v) * KP + 16 * nt + r] += G[mt][nt][v];
+    }
+    __syncthreads();
+    EPOCH_GLOBAL f4* dst =
+        gptr(reinterpret_cast<f4*>(pr.Gpart + ((size_t)pr.gslots[pr.n_nodes + child] + blockIdx.x) * KK));
+    for (int e = threadIdx.x; e < KK / 4; e += 256)
+      dst[e] = reinterpret_cast<const f4*>(red0)[e] + reinterpret_cast<const f4*>(red1)[e];
+    __syncthreads();
   }
 }
 
-// G[v] = sum of the FP32 slot partials in FP64 (fixed order), then dlogL/dl.
+// G[v] = sum of the FP32 slot partials in FP64 (fixed order): one block per
+// (branch, 256 entries); also the block's share of <G, dP/dl>.
+constexpr int kReduceChunks = KK / 256;
 __global__ __launch_bounds__(256) void codon_grad_reduce_kernel(const CodonProblem* __restrict__ probs,
-                                                                const int2* __restrict__ items) {
+                                                                const int2* __restrict__ items,
+                                                                double* __restrict__ dpart) {
   __shared__ double sm[256];
-  const int2 it = items[blockIdx.x];
+  const int2 it = items[blockIdx.x / kReduceChunks];
+  const int chunk = blockIdx.x % kReduceChunks;
   const CodonProblem& pr = probs[it.x];
   const int v = it.y;
   const int ns = v == pr.root ? 0 : pr.gslots[v];
-  const float* src = pr.Gpart + (size_t)v * pr.n_slots * (KP * KP);
-  double d = 0.0;
-  for (int e = threadIdx.x; e < KP * KP; e += 256) {
-    double s = 0.0;
-    for (int k = 0; k < ns; ++k) s += (double)src[(size_t)k * (KP * KP) + e];
-    pr.G[(size_t)v * KP * KP + e] = s;
-    d += s * (double)pr.dPm[(size_t)v * KP * KP + e];
+  const int e = chunk * 256 + threadIdx.x;
+  const EPOCH_GLOBAL float* src = gptr(pr.Gpart + (size_t)(v == pr.root ? 0 : pr.gslots[pr.n_nodes + v]) * KK) + e;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int k = 0;
+  for (; k + 4 <= ns; k += 4) {
+    s0 += (double)src[(size_t)k * KK];
+    s1 += (double)src[(size_t)(k + 1) * KK];
+    s2 += (double)src[(size_t)(k + 2) * KK];
+    s3 += (double)src[(size_t)(k + 3) * KK];
   }
-  const double tot = block_sum<256>(d, sm);
-  if (threadIdx.x == 0) pr.dbranch[v] = (v == pr.root) ? 0.0 : tot;
+  for (; k < ns; ++k) s0 += (double)src[(size_t)k * KK];
+  const double s = (s0 + s1) + (s2 + s3);
+  pr.G[(size_t)v * KK + e] = s;
+  const double d = block_sum<256>(s * (double)pr.dPm[(size_t)v * KK + e], sm);
+  if (threadIdx.x == 0) dpart[blockIdx.x] = d;
+}
+
+// dlogL/dl of each branch from the chunk shares, in a fixed order.
+__global__ __launch_bounds__(256) void codon_dbranch_kernel(const CodonProblem* __restrict__ probs,
+                                                            const int2* __restrict__ items, int n_items,
+                                                            const double* __restrict__ dpart) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n_items) return;
+  const int2 it = items[i];
+  const CodonProblem& pr = probs[it.x];
+  double d = 0.0;
+  for (int c = 0; c < kReduceChunks; ++c) d += dpart[(size_t)i * kReduceChunks + c];
+  pr.dbranch[it.y] = it.y == pr.root ? 0.0 : d;
 }
 
 int codon_tiles_per_block(int tiles, int n_items, int target_blocks, int r_max) {
@@ -419,11 +474,7 @@ int codon_tiles_per_block(int tiles, int n_items, int target_blocks, int r_max) 
 
 }  // namespace
 
-// Partial-sum slots per branch: at most kMaxSlots blocks share a node, so the
-// dlogL/dP partials of a branch take at most kMaxSlots x 16 KB.
-int codon_max_slots(int P) { return std::min((P + TILE - 1) / TILE, kMaxSlots); }
-
-CodonProblem codon_descriptor(const EpochInstance* in, const int32_t* gslots) {
+CodonProblem codon_descriptor(const EpochInstance* in, const int32_t* gslots, float* gpart) {
   CodonProblem d{};
   d.Pm = static_cast<const float*>(in->Pm.ptr);
   d.tips = static_cast<const uint8_t*>(in->tips.ptr);
@@ -433,7 +484,7 @@ CodonProblem codon_descriptor(const EpochInstance* in, const int32_t* gslots) {
   d.weightsT = static_cast<const float*>(in->weightsT.ptr);
   d.weights = static_cast<const double*>(in->weights.ptr);
   d.pi = static_cast<const double*>(in->pi.ptr);
-  d.Gpart = static_cast<float*>(in->Gpart.ptr);
+  d.Gpart = gpart;
   d.dPm = static_cast<const float*>(in->dPm.ptr);
   d.G = static_cast<double*>(in->G.ptr);
   d.dbranch = static_cast<double*>(in->dbranch.ptr);
@@ -447,12 +498,16 @@ CodonProblem codon_descriptor(const EpochInstance* in, const int32_t* gslots) {
   d.P = in->P;
   d.K = in->K;
   d.root = in->plan.root;
-  d.n_slots = codon_max_slots(in->P);
   d.n_nodes = in->n_nodes;
   return d;
 }
 
-// Merged level schedule over one or more problems (levels counted from the tips).
+// Merged level schedule over one or more problems (levels counted from the
+// tips).  Each level gets R 64-pattern tiles per block, with R chosen so that
+// the level's launch has about target_blocks blocks; every block of a node
+// writes one dlogL/dP slot for each of the node's two child branches.
+// gslots[q] holds, per node, the number of slots of its branch and then the
+// index of its first slot in problem q's slot array.
 void codon_build_schedule(const std::vector<const EpochInstance*>& insts, int target_blocks, CodonSchedule& out,
                           std::vector<std::vector<int32_t>>& gslots) {
   out.items.clear();
@@ -466,7 +521,8 @@ void codon_build_schedule(const std::vector<const EpochInstance*>& insts, int ta
     max_pblocks = std::max(max_pblocks, (in->P + 255) / 256);
   }
   gslots.assign(insts.size(), {});
-  for (size_t q = 0; q < insts.size(); ++q) gslots[q].assign(insts[q]->n_nodes, 0);
+  out.slot_total.assign(insts.size(), 0);
+  for (size_t q = 0; q < insts.size(); ++q) gslots[q].assign(2 * (size_t)insts[q]->n_nodes, 0);
   for (int l = 1; l <= n_levels; ++l) {
     const size_t begin = out.items.size();
     for (size_t q = 0; q < insts.size(); ++q) {
@@ -475,8 +531,7 @@ void codon_build_schedule(const std::vector<const EpochInstance*>& insts, int ta
       for (int k = pl.level_offset[l]; k < pl.level_offset[l + 1]; ++k) out.items.push_back(make_int2((int)q, pl.level_nodes[k]));
     }
     const int n_items = (int)(out.items.size() - begin);
-    int R = codon_tiles_per_block(max_tiles, std::max(1, n_items), target_blocks, 64);
-    R = std::max(R, (max_tiles + kMaxSlots - 1) / kMaxSlots);  // at most kMaxSlots blocks per node
+    const int R = codon_tiles_per_block(max_tiles, std::max(1, n_items), target_blocks, max_tiles);
     out.level_off.push_back((int)out.items.size());
     out.level_R.push_back(R);
     for (size_t k = begin; k < out.items.size(); ++k) {
@@ -484,8 +539,12 @@ void codon_build_schedule(const std::vector<const EpochInstance*>& insts, int ta
       const auto& pl = insts[q]->plan;
       const int tiles = (insts[q]->P + TILE - 1) / TILE;
       const int used = (tiles + R - 1) / R;
-      gslots[q][pl.left[u]] = used;
-      gslots[q][pl.right[u]] = used;
+      const int n = insts[q]->n_nodes;
+      for (int child : {pl.left[u], pl.right[u]}) {
+        gslots[q][child] = used;
+        gslots[q][n + child] = (int32_t)out.slot_total[q];
+        out.slot_total[q] += used;
+      }
     }
   }
   for (size_t q = 0; q < insts.size(); ++q)
@@ -500,7 +559,9 @@ int codon_launch_post(const CodonSchedule& sc, const CodonProblem* d_probs, cons
   for (int l = 1; l <= sc.n_levels; ++l) {
     const int b = sc.level_off[l - 1], n = sc.level_off[l] - b;
     if (!n) continue;
-    hipLaunchKernelGGL(codon_post_level_kernel, dim3(sc.max_tiles, n), dim3(256), 0, st, d_probs, d_items + b);
+    const int R = sc.level_R[l - 1];
+    const int blocks = (sc.max_tiles + R - 1) / R;
+    hipLaunchKernelGGL(codon_post_level_kernel, dim3(blocks, n), dim3(256), 0, st, d_probs, d_items + b, R);
   }
   return hip_check(hipGetLastError(), "codon_post_level launch");
 }
@@ -511,8 +572,10 @@ int codon_launch_root(const CodonSchedule& sc, const CodonProblem* d_probs, hipS
   return hip_check(hipGetLastError(), "codon_root launch");
 }
 
+size_t codon_dpart_bytes(const CodonSchedule& sc) { return sc.reduce_items.size() * kReduceChunks * sizeof(double); }
+
 int codon_launch_pre_grad(const CodonSchedule& sc, const CodonProblem* d_probs, const int2* d_items,
-                          const int2* d_reduce_items, hipStream_t st) {
+                          const int2* d_reduce_items, double* dpart, hipStream_t st) {
   for (int l = sc.n_levels; l >= 1; --l) {
     const int b = sc.level_off[l - 1], n = sc.level_off[l] - b;
     if (!n) continue;
@@ -522,8 +585,11 @@ int codon_launch_pre_grad(const CodonSchedule& sc, const CodonProblem* d_probs, 
   }
   int rc = hip_check(hipGetLastError(), "codon_pre_level launch");
   if (rc) return rc;
-  hipLaunchKernelGGL(codon_grad_reduce_kernel, dim3((unsigned)sc.reduce_items.size()), dim3(256), 0, st, d_probs,
-                     d_reduce_items);
+  const int n_items = (int)sc.reduce_items.size();
+  hipLaunchKernelGGL(codon_grad_reduce_kernel, dim3((unsigned)(n_items * kReduceChunks)), dim3(256), 0, st, d_probs,
+                     d_reduce_items, dpart);
+  hipLaunchKernelGGL(codon_dbranch_kernel, dim3((unsigned)((n_items + 255) / 256)), dim3(256), 0, st, d_probs,
+                     d_reduce_items, n_items, static_cast<const double*>(dpart));
   return hip_check(hipGetLastError(), "codon_grad_reduce launch");
 }
 
@@ -531,10 +597,15 @@ int codon_launch_pre_grad(const CodonSchedule& sc, const CodonProblem* d_probs, 
 int codon_prepare(EpochInstance* in) {
   std::vector<std::vector<int32_t>> gslots;
   codon_build_schedule({in}, in->codon_target_blocks, in->codon_sched, gslots);
-  const CodonProblem d = codon_descriptor(in, static_cast<const int32_t*>(in->gslots.ptr));
   const auto& sc = in->codon_sched;
+  const bool grad = (in->cfg.flags & (EPOCH_GRAD_BRANCH | EPOCH_GRAD_Q)) != 0;
+  int rc = ensure(in->gslots, gslots[0].size() * sizeof(int32_t));
+  if (!rc && grad) rc = ensure(in->Gpart, std::max<size_t>(1, sc.slot_total[0]) * kCodonSlotBytes);
+  if (!rc && grad) rc = ensure(in->codon_aux, codon_dpart_bytes(sc));
+  if (rc) return rc;
+  const CodonProblem d = codon_descriptor(in, static_cast<const int32_t*>(in->gslots.ptr), static_cast<float*>(in->Gpart.ptr));
   const size_t bytes = sizeof(CodonProblem) + sizeof(int2) * (sc.items.size() + sc.reduce_items.size());
-  int rc = ensure(in->codon_dev, bytes);
+  rc = ensure(in->codon_dev, bytes);
   if (rc) return rc;
   std::vector<char> h(bytes);
   memcpy(h.data(), &d, sizeof(d));
@@ -542,7 +613,7 @@ int codon_prepare(EpochInstance* in) {
   memcpy(h.data() + sizeof(d) + sizeof(int2) * sc.items.size(), sc.reduce_items.data(),
          sizeof(int2) * sc.reduce_items.size());
   rc = hip_check(hipMemcpyAsync(in->codon_dev.ptr, h.data(), bytes, hipMemcpyHostToDevice, in->stream), "codon schedule upload");
-  if (!rc && in->gslots.ptr)
+  if (!rc)
     rc = hip_check(hipMemcpyAsync(in->gslots.ptr, gslots[0].data(), gslots[0].size() * sizeof(int32_t),
                                   hipMemcpyHostToDevice, in->stream), "gslots upload");
   if (!rc) rc = hip_check(hipStreamSynchronize(in->stream), "codon schedule sync");
@@ -560,7 +631,8 @@ const int2* dev_reduce_items(EpochInstance* in) { return dev_items(in) + in->cod
 int launch_codon_post(EpochInstance* in) { return codon_launch_post(in->codon_sched, dev_probs(in), dev_items(in), in->stream); }
 int launch_codon_root(EpochInstance* in) { return codon_launch_root(in->codon_sched, dev_probs(in), in->stream); }
 int launch_codon_pre_grad(EpochInstance* in) {
-  return codon_launch_pre_grad(in->codon_sched, dev_probs(in), dev_items(in), dev_reduce_items(in), in->stream);
+  return codon_launch_pre_grad(in->codon_sched, dev_probs(in), dev_items(in), dev_reduce_items(in),
+                               static_cast<double*>(in->codon_aux.ptr), in->stream);
 }
 
 }  // namespace epochlik
