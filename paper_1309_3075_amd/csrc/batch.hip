@@ -134,7 +134,7 @@ int enqueue(EpochBatch* b, uint32_t what, const double* const* d_result_ptrs) {
   }
   if (what & kGradQ)
     for (auto* in : b->insts) {
-      int rc = launch_grad_Q_generic(in);
+      int rc = launch_grad_Q(in);
       if (rc) return rc;
     }
   hipLaunchKernelGGL(gather_results, dim3(1), dim3(64), 0, b->stream, d_result_ptrs, (int)n,

@@ -55,6 +55,11 @@ int launch_pstage(EpochInstance* in) {
   return launch_pstage_generic(in);
 }
 
+int launch_grad_Q(EpochInstance* in) {
+  if (in->cfg.kernel_path == EPOCH_KERNEL_AUTO && grad_Q_mfma_supported(in)) return launch_grad_Q_mfma(in);
+  return launch_grad_Q_generic(in);
+}
+
 int fastpath_pstage(EpochInstance* in) {
   EPOCH_PHASE(0, launch_pstage(in));
   return EPOCH_OK;
@@ -80,7 +85,7 @@ int fastpath_gradient(EpochInstance* in, bool want_Q) {
     EPOCH_PHASE(3, launch_pre_generic(in));
     EPOCH_PHASE(4, launch_grad_branch_generic(in));
   }
-  if (want_Q) EPOCH_PHASE(5, launch_grad_Q_generic(in));
+  if (want_Q) EPOCH_PHASE(5, launch_grad_Q(in));
   return EPOCH_OK;
 }
 

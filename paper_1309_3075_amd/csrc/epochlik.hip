@@ -210,6 +210,8 @@ int epoch_create(const EpochConfig* cfg, EpochInstance** out) {
   };
   A(in->eigT, (2 * S * KK + 2 * S * Kp) * R);
   A(in->eig64, (2 * S * KK + 2 * S * Kp) * sizeof(double));
+  A(in->eigTT, 2 * S * KK * R);
+  A(in->eig64T, 2 * S * KK * sizeof(double));
   A(in->check, (KK + 8) * sizeof(double));
   A(in->tips, N * P);
   A(in->weights, P * sizeof(double));
@@ -240,6 +242,8 @@ int epoch_create(const EpochConfig* cfg, EpochInstance** out) {
   // zero the eigen buffers so padding is well defined
   rc = hip_check(hipMemsetAsync(in->eigT.ptr, 0, in->eigT.bytes, in->stream), "memset");
   if (rc == EPOCH_OK) rc = hip_check(hipMemsetAsync(in->eig64.ptr, 0, in->eig64.bytes, in->stream), "memset");
+  if (rc == EPOCH_OK) rc = hip_check(hipMemsetAsync(in->eigTT.ptr, 0, in->eigTT.bytes, in->stream), "memset");
+  if (rc == EPOCH_OK) rc = hip_check(hipMemsetAsync(in->eig64T.ptr, 0, in->eig64T.bytes, in->stream), "memset");
   if (rc == EPOCH_OK) rc = hip_check(hipStreamSynchronize(in->stream), "create sync");
   if (rc != EPOCH_OK) {
     std::string keep = g_error;
@@ -297,7 +301,8 @@ int epoch_destroy(EpochInstance* in) {
   for (DevBuf* b : {&in->eigT, &in->eig64, &in->check, &in->tips, &in->weights, &in->weightsT, &in->pi,
                     &in->cat, &in->tree_i, &in->tree_d, &in->Pm, &in->dPm, &in->partials, &in->scales,
                     &in->pre, &in->site, &in->blocksum, &in->result, &in->Gpart, &in->G, &in->dbranch,
-                    &in->qseg, &in->qscratch, &in->dQ, &in->seglist, &in->gslots, &in->codon_dev, &in->codon_aux})
+                    &in->qseg, &in->qscratch, &in->dQ, &in->seglist, &in->gslots, &in->codon_dev, &in->codon_aux,
+                    &in->eigTT, &in->eig64T, &in->qtau})
     release(*b);
   delete in;
   return EPOCH_OK;
@@ -467,6 +472,27 @@ int set_epoch_eigensystems(EpochInstance* in, int32_t s, const double* V, const 
   };
   EPOCH_TRY(up_slice(in->eig64, sizeof(double), false));
   EPOCH_TRY(up_slice(in->eigT, in->real_size, !in->fp64));
+  {
+    // transposed copies: rows of V^T and V^-T feed the adjoint chain
+    std::vector<double> tV(KK), tVi(KK);
+    for (int i = 0; i < Kp; ++i)
+      for (int j = 0; j < Kp; ++j) {
+        tV[(size_t)j * Kp + i] = hV[(size_t)i * Kp + j];
+        tVi[(size_t)j * Kp + i] = hVi[(size_t)i * Kp + j];
+      }
+    char* b64 = static_cast<char*>(in->eig64T.ptr);
+    EPOCH_TRY(upload(in, b64 + s * KK * sizeof(double), tV.data(), KK * sizeof(double)));
+    EPOCH_TRY(upload(in, b64 + (S * KK + s * KK) * sizeof(double), tVi.data(), KK * sizeof(double)));
+    char* bT = static_cast<char*>(in->eigTT.ptr);
+    if (in->fp64) {
+      EPOCH_TRY(upload(in, bT + s * KK * 8, tV.data(), KK * 8));
+      EPOCH_TRY(upload(in, bT + (S * KK + s * KK) * 8, tVi.data(), KK * 8));
+    } else {
+      std::vector<float> fV(tV.begin(), tV.end()), fVi(tVi.begin(), tVi.end());
+      EPOCH_TRY(upload(in, bT + s * KK * 4, fV.data(), KK * 4));
+      EPOCH_TRY(upload(in, bT + (S * KK + s * KK) * 4, fVi.data(), KK * 4));
+    }
+  }
   in->have_eig[s] = 1;
   invalidate_downstream(in);
   int ret = EPOCH_OK;
@@ -536,10 +562,20 @@ int set_tree_epochs(EpochInstance* in, const int32_t* parent, const double* heig
     const size_t KK = (size_t)in->Kp * in->Kp, C = in->C;
     // prefix products may be formed in double even for FP32 instances (eig_fp64)
     EPOCH_TRY(ensure(in->qscratch, std::max<size_t>(1, nseg) * C * KK * sizeof(double)));
-    EPOCH_TRY(ensure(in->qseg, (nseg * C * KK * 2 + (size_t)in->S * KK * 2) * sizeof(double)));
     std::vector<int32_t> off(in->S + 1, 0), items;
     for (size_t g = 0; g < nseg; ++g) off[plan.seg_process[g] + 1] += (int32_t)C;
+    int max_items = 1;
+    for (int s = 0; s < in->S; ++s) max_items = std::max(max_items, off[s + 1]);
     for (int s = 0; s < in->S; ++s) off[s + 1] += off[s];
+    in->q_chunks = (max_items + in->q_chunk_items - 1) / in->q_chunk_items;
+    // generic form: per-segment complex terms + per-process sums; matrix-core form:
+    // per-segment real adjoints + chunk partials + per-process sums (complex)
+    const size_t S2 = (size_t)in->S * KK * 2;
+    const size_t generic_doubles = nseg * C * KK * 2 + S2;
+    const size_t mfma_doubles = nseg * C * KK + S2 * in->q_chunks + S2;
+    EPOCH_TRY(ensure(in->qseg, std::max(generic_doubles, mfma_doubles) * sizeof(double)));
+    // tau of each segment term, then e^{tau lambda} of each eigenvalue (complex)
+    EPOCH_TRY(ensure(in->qtau, std::max<size_t>(1, nseg * C) * (1 + 2 * (size_t)in->Kp) * sizeof(double)));
     items.assign(off[in->S], 0);
     std::vector<int32_t> fill(off.begin(), off.end());
     for (size_t g = 0; g < nseg; ++g)

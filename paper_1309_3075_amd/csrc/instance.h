@@ -85,6 +85,8 @@ struct EpochInstance {
   // device buffers (compute type T unless noted)
   epochlik::DevBuf eigT;       // V[S][Kp][Kp], Vinv[S][Kp][Kp], lre[S][Kp], lim[S][Kp]
   epochlik::DevBuf eig64;      // the same in double
+  epochlik::DevBuf eigTT;      // V^T[S][Kp][Kp], (V^-1)^T[S][Kp][Kp] in the compute type
+  epochlik::DevBuf eig64T;     // the same in double
   epochlik::DevBuf check;      // double scratch for the eigen check
   epochlik::DevBuf tips;       // uint8 [N][P]
   epochlik::DevBuf weights;    // double [P]
@@ -107,6 +109,9 @@ struct EpochInstance {
   epochlik::DevBuf qseg;       // double complex per segment [nseg][C][Kp][Kp][2]
   epochlik::DevBuf qscratch;   // T prefix products [nseg][C][Kp][Kp]
   epochlik::DevBuf dQ;         // double [S][Kp][Kp]
+  epochlik::DevBuf qtau;       // double [nseg][C] tau of each segment term of dlogL/dQ, then complex [nseg][C][Kp] e^{tau lambda}
+  int q_chunks = 1;            // segment chunks per process of the dlogL/dQ sums
+  int q_chunk_items = 32;      // segment terms per chunk
   epochlik::DevBuf seglist;    // int32 segments grouped by process: offsets [S+1], items [nseg*C]
   epochlik::DevBuf gslots;     // int32 [n]: partial-sum slots written per branch (4-state / 64-state gradient)
   epochlik::DevBuf codon_dev;  // 64-state path: descriptor + work items
@@ -146,6 +151,9 @@ int launch_pstage_generic(EpochInstance* in);
 int launch_pstage_mfma(EpochInstance* in);
 bool pstage_mfma_supported(const EpochInstance* in);
 int launch_pstage(EpochInstance* in);  // matrix-core kernel where it applies, else generic
+int launch_grad_Q_mfma(EpochInstance* in);
+bool grad_Q_mfma_supported(const EpochInstance* in);
+int launch_grad_Q(EpochInstance* in);  // matrix-core kernels where they apply, else generic
 int launch_post_generic(EpochInstance* in);
 int launch_root_generic(EpochInstance* in);
 int launch_pre_generic(EpochInstance* in);

@@ -247,7 +247,7 @@ __global__ __launch_bounds__(256) void codon_final_kernel(const CodonProblem* __
 
 // ---------------------------------------------------------------------------
 // Pre-order of one level fused with dlogL/dP of the two child branches.
-__global__ __launch_bounds__(256) void codon_pre_level_kernel(const CodonProblem* __restrict__ probs,
+__global__ __launch_bounds__(256, 2) void codon_pre_level_kernel(const CodonProblem* __restrict__ probs,
                                                                const int2* __restrict__ items, int R) {
   __shared__ __align__(16) float sPa[KP * LDP];
   __shared__ __align__(16) float sPb[KP * LDP];

@@ -216,7 +216,10 @@ __global__ __launch_bounds__(256) void post_level_generic_kernel(
   if (pok && i < Kp)
     for (int c = 0; c < C; ++c)
       partials[((size_t)(u - N) * C + c) * stride_c + (size_t)p * Kp + i] = (i < K) ? scale_by_pow2(x[c], e) : T(0);
-  if (pok && i == 0) scales[(size_t)(u - N) * P + p] = e;
+  // cumulative exponent of the subtree, so the root needs only its own
+  if (pok && i == 0)
+    scales[(size_t)(u - N) * P + p] = e + (a >= N ? scales[(size_t)(a - N) * P + p] : 0) +
+                                     (b >= N ? scales[(size_t)(b - N) * P + p] : 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -225,7 +228,7 @@ __global__ __launch_bounds__(256) void post_level_generic_kernel(
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void root_generic_kernel(
-    const T* __restrict__ root_part, const int32_t* __restrict__ scales, int n_int,
+    const T* __restrict__ root_part, const int32_t* __restrict__ root_scales,
     const double* __restrict__ pi, const double* __restrict__ cat, const double* __restrict__ weights,
     double* __restrict__ site, double* __restrict__ block_out, int P, int K, int Kp, int C) {
   __shared__ double sm[256];
@@ -239,9 +242,7 @@ __global__ __launch_bounds__(256) void root_generic_kernel(
       for (int i = 0; i < K; ++i) lc += pi[i] * (double)x[i];
       L += cat[kMaxCategories + c] * lc;
     }
-    long long E = 0;
-    for (int u = 0; u < n_int; ++u) E += scales[(size_t)u * P + p];
-    const double s = log(L) + (double)E * kLn2;
+    const double s = log(L) + (double)root_scales[p] * kLn2;
     site[p] = s;
     contrib = weights[p] * s;
   }
@@ -586,7 +587,7 @@ int root_dispatch(EpochInstance* in) {
                    (size_t)(in->plan.root - in->N) * in->C * (size_t)in->P * in->Kp;
   double* blk = static_cast<double*>(in->blocksum.ptr);
   hipLaunchKernelGGL((root_generic_kernel<T>), dim3(nb), dim3(256), 0, in->stream, rootp,
-                     static_cast<const int32_t*>(in->scales.ptr), in->n_int,
+                     static_cast<const int32_t*>(in->scales.ptr) + (size_t)(in->plan.root - in->N) * in->P,
                      static_cast<const double*>(in->pi.ptr), static_cast<const double*>(in->cat.ptr),
                      static_cast<const double*>(in->weights.ptr), static_cast<double*>(in->site.ptr),
                      blk, in->P, in->K, in->Kp, in->C);

@@ -16,7 +16,9 @@
 #include <cmath>
 
 #include "device_common.h"
+#include "eigen_block.h"
 #include "instance.h"
+#include "mfma_chain.h"
 
 namespace epochlik {
 
@@ -345,6 +347,372 @@ __global__ __launch_bounds__(256) void qgrad_reduce_kernel(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Matrix-core form (padded K a multiple of 16).  With U_k = A_k V_s and
+// W_k = R_k V_s^-T, where R_k = G B_k^T, the real-basis adjoint of segment k is
+//   Y_k = V_s^T G_k V_s^-T = U_k^T W_k.
+// One block per (branch, category), one wavefront per 16-row stripe.  The
+// forward chain A_{k+1} = A_k + (U_k (E_k - I)) V^-1 and the backward chain
+// R_{k-1} = R_k + (W_k (E_k - I)^T) V^T keep their stripes in registers (the
+// layout of the P-stage kernel); U_k is parked in a global scratch buffer
+// between the two passes; Y_k contracts over all rows, so U_k and W_k meet in
+// LDS and each wavefront writes 16 rows of Y_k.  The transposed factors V^T and
+// V^-T are read as rows of host-transposed copies.
+template <typename T, int NT>
+__global__ __launch_bounds__(256) void qgrad_chain_kernel(
+    int C, int root, const T* __restrict__ eigV, const T* __restrict__ eigVi, const T* __restrict__ eigVT,
+    const T* __restrict__ eigViT, const T* __restrict__ lre, const T* __restrict__ lim,
+    const int32_t* __restrict__ seg_offset, const int32_t* __restrict__ seg_process,
+    const double* __restrict__ seg_time, const double* __restrict__ rate, const double* __restrict__ cat_rates,
+    const double* __restrict__ G, T* __restrict__ Ubuf, double* __restrict__ Yseg, double* __restrict__ qtau,
+    const double* __restrict__ lr64, const double* __restrict__ li64, double* __restrict__ qexp) {
+  using acc = typename Mfma<T>::acc;
+  constexpr int Kp = 16 * NT, KK = Kp * Kp, LD = Kp + 1;
+  __shared__ T sU[Kp * LD];
+  __shared__ T sW[Kp * LD];
+  __shared__ T s_coef[NT][64][2];
+  const int v = blockIdx.x / C, c = blockIdx.x - (blockIdx.x / C) * C;
+  if (v == root) return;
+  const int seg0 = seg_offset[v], m = seg_offset[v + 1] - seg0;
+  if (m == 0) return;  // uniform over the block
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int g = lane >> 4, n = lane & 15;
+  const int row = 16 * w + n;
+  const int arow = Mfma<T>::a_row(n);
+  const double scale = cat_rates[c] * rate[v];
+  T(*coef)[2] = s_coef[w];
+
+  // forward pass
+  acc x[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) x[t][q] = (16 * t + 4 * g + q == row) ? T(1) : T(0);
+  for (int k = 0; k < m; ++k) {
+    const int s = seg_process[seg0 + k];
+    const double tau_d = scale * seg_time[seg0 + k];
+    const T* V = eigV + (size_t)s * KK;
+    const T* Vi = eigVi + (size_t)s * KK;
+    if (lane < Kp) {
+      const BlockCoef<T> bc = block_coef(lre + (size_t)s * Kp, lim + (size_t)s * Kp, lane, T(tau_d));
+      coef[lane][0] = bc.m_self;
+      coef[lane][1] = bc.m_other;
+    }
+    if (threadIdx.x == 0) qtau[(size_t)(seg0 + k) * C + c] = tau_d;
+    if (w == 0 && lane < Kp) {
+      // e^{tau lambda} of every eigenvalue, for the divided differences of the sums
+      const double ea = exp(tau_d * lr64[(size_t)s * Kp + lane]);
+      const double th = tau_d * li64[(size_t)s * Kp + lane];
+      reinterpret_cast<double2*>(qexp)[((size_t)(seg0 + k) * C + c) * Kp + lane] = make_double2(ea * cos(th), ea * sin(th));
+    }
+    wave_lds_sync();
+    acc y[NT];
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt) y[mt] = acc{0, 0, 0, 0};
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const T* vrow = V + (16 * t + 4 * g + q) * Kp + arow;
+#pragma unroll
+        for (int mt = 0; mt < NT; ++mt) y[mt] = Mfma<T>::mma(vrow[16 * mt], x[t][q], y[mt]);
+      }
+    T* U = Ubuf + ((size_t)(seg0 + k) * C + c) * KK + (size_t)row * Kp + 4 * g;
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt) store4<T, T>(U + 16 * mt, y[mt]);
+    if (k + 1 < m) {
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt)
+#pragma unroll
+        for (int q = 0; q < 4; q += 2) {
+          const int j = 16 * mt + 4 * g + q;
+          const T y0 = y[mt][q], y1 = y[mt][q + 1];
+          y[mt][q] = coef[j][0] * y0 + coef[j][1] * y1;
+          y[mt][q + 1] = coef[j + 1][0] * y1 + coef[j + 1][1] * y0;
+        }
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const T* vrow = Vi + (16 * t + 4 * g + q) * Kp + arow;
+#pragma unroll
+          for (int mt = 0; mt < NT; ++mt) x[mt] = Mfma<T>::mma(vrow[16 * mt], y[t][q], x[mt]);
+        }
+    }
+    wave_lds_sync();
+  }
+
+  // backward pass, R_{m-1} = G (rows of this stripe)
+  acc R[NT];
+  {
+    const double* Gr = G + ((size_t)v * C + c) * KK + (size_t)row * Kp + 4 * g;
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) R[mt][q] = T(Gr[16 * mt + q]);
+  }
+  for (int k = m - 1; k >= 0; --k) {
+    const int s = seg_process[seg0 + k];
+    const T* VT = eigVT + (size_t)s * KK;
+    const T* ViT = eigViT + (size_t)s * KK;
+    // W = R V^-T
+    acc wk[NT];
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt) wk[mt] = acc{0, 0, 0, 0};
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const T* vrow = ViT + (16 * t + 4 * g + q) * Kp + arow;
+#pragma unroll
+        for (int mt = 0; mt < NT; ++mt) wk[mt] = Mfma<T>::mma(vrow[16 * mt], R[t][q], wk[mt]);
+      }
+    // stage this stripe's rows of W_k and U_k
+    const T* U = Ubuf + ((size_t)(seg0 + k) * C + c) * KK + (size_t)row * Kp + 4 * g;
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        sW[row * LD + 16 * mt + 4 * g + q] = wk[mt][q];
+        sU[row * LD + 16 * mt + 4 * g + q] = U[16 * mt + q];
+      }
+    __syncthreads();
+    // rows 16 w .. 16 w + 15 of Y_k = U_k^T W_k (contraction over every row i)
+    acc yv[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) yv[nt] = acc{0, 0, 0, 0};
+    for (int kk = 0; kk < Kp / 4; ++kk) {
+      const int i = 4 * kk + g;
+      const T a = sU[i * LD + 16 * w + arow];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) yv[nt] = Mfma<T>::mma(a, sW[i * LD + 16 * nt + n], yv[nt]);
+    }
+    double* Y = Yseg + ((size_t)(seg0 + k) * C + c) * KK;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Y[(size_t)(16 * w + 4 * g + q) * Kp + 16 * nt + n] = (double)yv[nt][q];
+    __syncthreads();
+    if (k > 0) {
+      // R <- R + (W (E_k - I)^T) V^T; the transposed rotation flips the partner sign
+      const double tau_d = scale * seg_time[seg0 + k];
+      if (lane < Kp) {
+        const BlockCoef<T> bc = block_coef(lre + (size_t)s * Kp, lim + (size_t)s * Kp, lane, T(tau_d));
+        coef[lane][0] = bc.m_self;
+        coef[lane][1] = -bc.m_other;
+      }
+      wave_lds_sync();
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt)
+#pragma unroll
+        for (int q = 0; q < 4; q += 2) {
+          const int j = 16 * mt + 4 * g + q;
+          const T y0 = wk[mt][q], y1 = wk[mt][q + 1];
+          wk[mt][q] = coef[j][0] * y0 + coef[j][1] * y1;
+          wk[mt][q + 1] = coef[j + 1][0] * y1 + coef[j + 1][1] * y0;
+        }
+      wave_lds_sync();
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const T* vrow = VT + (16 * t + 4 * g + q) * Kp + arow;
+#pragma unroll
+          for (int mt = 0; mt < NT; ++mt) R[mt] = Mfma<T>::mma(vrow[16 * mt], wk[t][q], R[mt]);
+        }
+    }
+  }
+}
+
+// (e^{x_a} - e^{x_b}) / (x_a - x_b) from E_a = e^{x_a}, E_b = e^{x_b} and
+// d = x_a - x_b: the quotient where |d| is large, E_b (e^d - 1)/d by its Taylor
+// series where it is small (no cancellation; exact limit E_b at d = 0).
+__device__ inline cplx divided_difference_from_exp(cplx Ea, cplx Eb, cplx d) {
+  const double ad = fabs(d.re) + fabs(d.im);
+  if (ad > 0.25) return cdiv(cplx{Ea.re - Eb.re, Ea.im - Eb.im}, d);
+  // (e^d - 1)/d = sum_{k>=0} d^k / (k+1)! = 1 + d/2 (1 + d/3 (1 + ... (1 + d/15))),
+  // terms through d^14/15!: the remainder is below 0.25^15 / 16! ~ 4e-23
+  cplx s = {1.0, 0.0};
+#pragma unroll
+  for (int k = 15; k >= 2; --k) {
+    s = cmul(s, d);
+    s.re = 1.0 + s.re / (double)k;
+    s.im = s.im / (double)k;
+  }
+  return cmul(Eb, s);
+}
+
+// H_s partial sums: for every segment term of process s in this block's chunk,
+// tau Phi(tau lambda) o (T^T Y T^-T) in FP64 complex, one entry per thread.
+__global__ __launch_bounds__(256) void qgrad_h_kernel(int Kp, int n_chunks, int chunk,
+                                                      const int32_t* __restrict__ list_off,
+                                                      const int32_t* __restrict__ list, const double* __restrict__ Yseg,
+                                                      const double* __restrict__ qtau, const double* __restrict__ qexp,
+                                                      const double* __restrict__ lr_all,
+                                                      const double* __restrict__ li_all, double* __restrict__ Hpart) {
+  const int KK = Kp * Kp;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  const int ch = blockIdx.y, s = blockIdx.z;
+  if (e >= KK) return;
+  const int a = e / Kp, b = e - (e / Kp) * Kp;
+  const double* lr = lr_all + (size_t)s * Kp;
+  const double* li = li_all + (size_t)s * Kp;
+  const PairIdx pa = pair_of(li, a), pb = pair_of(li, b);
+  const int na = pa.pair ? 2 : 1, nb = pb.pair ? 2 : 1;
+  cplx tt[2][2];
+  for (int ci = 0; ci < na; ++ci)
+    for (int di = 0; di < nb; ++di)
+      tt[ci][di] = cmul(T_entry(pa.first + ci, a, pa.first, pa.pair), Tinv_entry(b, pb.first + di, pb.first, pb.pair));
+  const cplx dl = {lr[a] - lr[b], li[a] - li[b]};
+  const int q0 = list_off[s] + ch * chunk;
+  const int q1 = min(list_off[s + 1], q0 + chunk);
+  double re = 0.0, im = 0.0;
+  const double2* E = reinterpret_cast<const double2*>(qexp);
+  for (int qi = q0; qi < q1; ++qi) {
+    const int item = list[qi];
+    const double tau = qtau[item];
+    const double* Y = Yseg + (size_t)item * KK;
+    cplx z = {0.0, 0.0};
+    for (int ci = 0; ci < na; ++ci)
+      for (int di = 0; di < nb; ++di) {
+        const double yv = Y[(pa.first + ci) * Kp + pb.first + di];
+        z.re += tt[ci][di].re * yv;
+        z.im += tt[ci][di].im * yv;
+      }
+    const double2 ea = E[(size_t)item * Kp + a], eb = E[(size_t)item * Kp + b];
+    const cplx phi = divided_difference_from_exp(cplx{ea.x, ea.y}, cplx{eb.x, eb.y}, cplx{tau * dl.re, tau * dl.im});
+    const cplx wv = cmul(phi, z);
+    re += tau * wv.re;
+    im += tau * wv.im;
+  }
+  reinterpret_cast<double2*>(Hpart)[((size_t)s * n_chunks + ch) * KK + e] = make_double2(re, im);
+}
+
+// H_s = fixed-order sum of the chunk partials, one entry per thread.
+__global__ __launch_bounds__(256) void qgrad_hsum_kernel(int KK, int n_chunks, const double* __restrict__ Hpart,
+                                                         double* __restrict__ Hsum) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  const int s = blockIdx.y;
+  if (e >= KK) return;
+  const double2* src = reinterpret_cast<const double2*>(Hpart) + (size_t)s * n_chunks * KK + e;
+  double2 a0 = make_double2(0.0, 0.0), a1 = a0;
+  int ch = 0;
+  for (; ch + 2 <= n_chunks; ch += 2) {
+    const double2 h0 = src[(size_t)ch * KK], h1 = src[(size_t)(ch + 1) * KK];
+    a0.x += h0.x;
+    a0.y += h0.y;
+    a1.x += h1.x;
+    a1.y += h1.y;
+  }
+  if (ch < n_chunks) {
+    const double2 h0 = src[(size_t)ch * KK];
+    a0.x += h0.x;
+    a0.y += h0.y;
+  }
+  reinterpret_cast<double2*>(Hsum)[(size_t)s * KK + e] = make_double2(a0.x + a1.x, a0.y + a1.y);
+}
+
+// dQ_s = V^-T Re(T^-T H_s T^T) V^T.  Block (s, band) forms rows 16 band ..
+// 16 band + 15: X = Re(T^-T H T^T) in LDS, then those rows of Y = V^-T X
+// (columns of V^-1 from global), then dQ rows = Y_rows V^T with V replacing X
+// in LDS (Kp^2 + 16 Kp doubles).
+__global__ __launch_bounds__(256) void qgrad_final_kernel(int K, int Kp, const double* __restrict__ Hsum,
+                                                          const double* __restrict__ V, const double* __restrict__ Vi,
+                                                          const double* __restrict__ li_all, double* __restrict__ dQ) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int s = blockIdx.x, r0 = 16 * blockIdx.y;
+  const int KK = Kp * Kp;
+  double* sX = reinterpret_cast<double*>(smem_raw);
+  double* sY = sX + KK;  // 16 x Kp
+  const double* li = li_all + (size_t)s * Kp;
+  const double2* H = reinterpret_cast<const double2*>(Hsum) + (size_t)s * KK;
+  for (int e = threadIdx.x; e < KK; e += 256) {
+    const int a = e / Kp, b = e % Kp;
+    const PairIdx pa = pair_of(li, a), pb = pair_of(li, b);
+    const int na = pa.pair ? 2 : 1, nb = pb.pair ? 2 : 1;
+    double re = 0.0;
+    for (int ci = 0; ci < na; ++ci) {
+      const int cc = pa.first + ci;
+      const cplx t1 = Tinv_entry(cc, a, pa.first, pa.pair);
+      for (int di = 0; di < nb; ++di) {
+        const int dd = pb.first + di;
+        const cplx t2 = T_entry(b, dd, pb.first, pb.pair);
+        const double2 h = H[cc * Kp + dd];
+        re += cmul(cmul(t1, cplx{h.x, h.y}), t2).re;
+      }
+    }
+    sX[e] = re;
+  }
+  __syncthreads();
+  const double* Vis = Vi + (size_t)s * KK;
+  for (int e = threadIdx.x; e < 16 * Kp; e += 256) {
+    const int i = r0 + e / Kp, j = e % Kp;
+    double r = 0.0;
+    for (int l = 0; l < Kp; ++l) r += Vis[l * Kp + i] * sX[l * Kp + j];
+    sY[e] = r;
+  }
+  __syncthreads();
+  double* sV = sX;
+  for (int e = threadIdx.x; e < KK; e += 256) sV[e] = V[(size_t)s * KK + e];
+  __syncthreads();
+  for (int e = threadIdx.x; e < 16 * Kp; e += 256) {
+    const int i = r0 + e / Kp, j = e % Kp;
+    if (i < K && j < K) {
+      double r = 0.0;
+      for (int l = 0; l < Kp; ++l) r += sY[(i - r0) * Kp + l] * sV[j * Kp + l];
+      dQ[((size_t)s * K + i) * K + j] = r;
+    }
+  }
+}
+
+template <typename T, int NT>
+int qgrad_mfma_launch(EpochInstance* in) {
+  const int Kp = in->Kp, C = in->C;
+  const size_t KK = (size_t)Kp * Kp, S = in->S;
+  const T* base = static_cast<const T*>(sizeof(T) == 8 ? in->eig64.ptr : in->eigT.ptr);
+  const T* baseT = static_cast<const T*>(sizeof(T) == 8 ? in->eig64T.ptr : in->eigTT.ptr);
+  const T* lr = base + 2 * S * KK;
+  double* qexp = static_cast<double*>(in->qtau.ptr) + in->plan.seg_process.size() * C;
+  hipLaunchKernelGGL((qgrad_chain_kernel<T, NT>), dim3(in->n_nodes * C), dim3(64 * NT), 0, in->stream, C,
+                     in->plan.root, base, base + S * KK, baseT, baseT + S * KK, lr, lr + S * Kp, in->d_seg_offset,
+                     in->d_seg_process, in->d_seg_time, in->d_rate, static_cast<const double*>(in->cat.ptr),
+                     static_cast<const double*>(in->G.ptr), static_cast<T*>(in->qscratch.ptr),
+                     static_cast<double*>(in->qseg.ptr), static_cast<double*>(in->qtau.ptr),
+                     static_cast<const double*>(in->eig64.ptr) + 2 * S * KK,
+                     static_cast<const double*>(in->eig64.ptr) + 2 * S * KK + S * Kp, qexp);
+  int rc = hip_check(hipGetLastError(), "qgrad_chain launch");
+  if (rc) return rc;
+  const double* b64 = static_cast<const double*>(in->eig64.ptr);
+  const int32_t* lo = static_cast<const int32_t*>(in->seglist.ptr);
+  const int32_t* items = lo + in->S + 1;
+  const size_t nseg = in->plan.seg_process.size();
+  double* Hpart = static_cast<double*>(in->qseg.ptr) + nseg * C * KK;
+  double* Hsum = Hpart + 2 * S * in->q_chunks * KK;
+  dim3 grid((unsigned)((KK + 255) / 256), (unsigned)in->q_chunks, (unsigned)S);
+  hipLaunchKernelGGL(qgrad_h_kernel, grid, dim3(256), 0, in->stream, Kp, in->q_chunks, in->q_chunk_items, lo, items,
+                     static_cast<const double*>(in->qseg.ptr), static_cast<const double*>(in->qtau.ptr), qexp,
+                     b64 + 2 * S * KK, b64 + 2 * S * KK + S * Kp, Hpart);
+  hipLaunchKernelGGL(qgrad_hsum_kernel, dim3((unsigned)((KK + 255) / 256), (unsigned)S), dim3(256), 0, in->stream,
+                     (int)KK, in->q_chunks, static_cast<const double*>(Hpart), Hsum);
+  rc = hip_check(hipGetLastError(), "qgrad_h launch");
+  if (rc) return rc;
+  hipLaunchKernelGGL(qgrad_final_kernel, dim3(in->S, Kp / 16), dim3(256), (KK + 16 * Kp) * sizeof(double),
+                     in->stream, in->K, Kp, static_cast<const double*>(Hsum), b64, b64 + S * KK,
+                     b64 + 2 * S * KK + S * Kp, static_cast<double*>(in->dQ.ptr));
+  return hip_check(hipGetLastError(), "qgrad_final launch");
+}
+
+template <typename T>
+int qgrad_mfma_dispatch(EpochInstance* in) {
+  switch (in->Kp) {
+    case 16: return qgrad_mfma_launch<T, 1>(in);
+    case 32: return qgrad_mfma_launch<T, 2>(in);
+    case 48: return qgrad_mfma_launch<T, 3>(in);
+    case 64: return qgrad_mfma_launch<T, 4>(in);
+    default: return set_error(EPOCH_ERR_STATE, "matrix-core dlogL/dQ needs Kp in {16, 32, 48, 64}, got %d", in->Kp);
+  }
+}
+
 template <typename T>
 int qgrad_dispatch(EpochInstance* in) {
   const int Kp = in->Kp, KK = Kp * Kp, C = in->C;
@@ -392,6 +760,12 @@ int qgrad_dispatch(EpochInstance* in) {
 
 int launch_grad_Q_generic(EpochInstance* in) {
   return (in->fp64 || in->eig_fp64) ? qgrad_dispatch<double>(in) : qgrad_dispatch<float>(in);
+}
+
+bool grad_Q_mfma_supported(const EpochInstance* in) { return in->Kp >= 16 && in->Kp <= 64 && in->Kp % 16 == 0; }
+
+int launch_grad_Q_mfma(EpochInstance* in) {
+  return (in->fp64 || in->eig_fp64) ? qgrad_mfma_dispatch<double>(in) : qgrad_mfma_dispatch<float>(in);
 }
 
 }  // namespace epochlik

@@ -193,3 +193,81 @@ def test_codon_fp64_generic_C3_tree():
     assert rel(logL, O.log_likelihood(prob)) <= TOL_LOGL["fp64"]
     ref_b, _ = O.gradient(prob, wrt=("branch",))
     assert grad_rel(db, ref_b) <= TOL_GRAD["fp64"]
+
+
+@pytest.mark.parametrize("kernel", ["auto", "generic"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_trait_C4_shape(precision, kernel):
+    """40-state asymmetric CTMC (padded to 48), 12 processes cycled over 48 intervals,
+    160-taxon tree: branches near the root cross up to dozens of intervals, so the
+    epoch-product chains and their adjoints are long; logL, branch and Q gradients."""
+    prob = W.make_config(4, n_tips=160)
+    with from_problem(prob, precision, grad_branch=True, grad_Q=True, kernel=kernel, use_pi=False) as lik:
+        logL = lik.log_likelihood()
+        db, dq = lik.gradient(branch=True, Q=True)
+    want = O.log_likelihood(prob)
+    ref_b, ref_q = O.gradient(prob)
+    assert rel(logL, want) <= TOL_LOGL[precision], rel(logL, want)
+    assert grad_rel(db, ref_b) <= TOL_GRAD[precision], grad_rel(db, ref_b)
+    assert grad_rel(dq, ref_q) <= TOL_GRAD[precision], grad_rel(dq, ref_q)
+
+
+def test_trait_C4_full_size():
+    """The full 2000-taxon 40-state workload in the benchmarked configuration (FP32,
+    automatic kernels): logL and every gradient against the oracle."""
+    prob = W.make_config(4)
+    with from_problem(prob, "fp32", grad_branch=True, grad_Q=True, use_pi=False) as lik:
+        logL = lik.log_likelihood()
+        db, dq = lik.gradient(branch=True, Q=True)
+    assert rel(logL, O.log_likelihood(prob)) <= TOL_LOGL["fp32"]
+    ref_b, ref_q = O.gradient(prob)
+    assert grad_rel(db, ref_b) <= TOL_GRAD["fp32"], grad_rel(db, ref_b)
+    assert grad_rel(dq, ref_q) <= TOL_GRAD["fp32"], grad_rel(dq, ref_q)
+
+
+def _pattern_subset(prob, idx):
+    import dataclasses
+    return dataclasses.replace(prob, tips=prob.tips[:, idx], weights=prob.weights[idx])
+
+
+@pytest.mark.parametrize("config", [2, 3])
+def test_full_size_sampled_sites(config):
+    """Full-size workloads in the benchmarked configuration (FP32, automatic kernels):
+    site log-likelihoods of a sample of patterns (first, last and random ones, so the
+    ragged last tile is included) against the oracle on those patterns alone."""
+    prob = W.make_config(config)
+    with from_problem(prob, "fp32", grad_branch=True, grad_Q=config == 3) as lik:
+        _, site = lik.log_likelihood(site=True)
+    rng = np.random.default_rng(7)
+    idx = np.unique(np.concatenate([[0, prob.n_patterns - 1],
+                                    rng.choice(prob.n_patterns, 150, replace=False)]))
+    want = O.site_log_likelihoods(_pattern_subset(prob, idx))
+    np.testing.assert_allclose(site[idx], want, rtol=TOL_LOGL["fp32"] * 10, atol=0)
+
+
+@pytest.mark.parametrize("config", [2, 3])
+def test_full_size_gradient_directional(config):
+    """Full-size gradients checked by a property that holds at any size: the FP64 library
+    logL along a random branch-length direction has central difference <dlogL/dl, d>."""
+    prob = W.make_config(config)
+    n = prob.parent.shape[0]
+    tau = np.zeros(n)
+    for v in range(n):
+        if prob.parent[v] >= 0:
+            tau[v] = prob.height[prob.parent[v]] - prob.height[v]
+    rng = np.random.default_rng(11)
+    # relative perturbations: coalescent tip branches can be ~1e-5 long
+    d = prob.branch_rate * tau * rng.standard_normal(n)
+    d[prob.parent < 0] = 0.0
+    with from_problem(prob, "fp64", grad_branch=True) as lik:
+        lik.log_likelihood()
+        db, _ = lik.gradient()
+        h = 1e-6
+        vals = []
+        for sgn in (1.0, -1.0):
+            # l_v = r_v tau_v, so l + s h d is the rate r_v + s h d_v / tau_v
+            rate = prob.branch_rate + np.where(tau > 0, sgn * h * d / np.where(tau > 0, tau, 1.0), 0.0)
+            lik.set_tree(prob.parent, prob.height, rate, prob.boundaries, prob.interval_process)
+            vals.append(lik.log_likelihood())
+    fd = (vals[0] - vals[1]) / (2 * h)
+    assert abs(fd - float(np.dot(db, d))) <= 1e-6 * abs(fd) + 1e-9 * np.linalg.norm(db * d), (fd, np.dot(db, d))
