@@ -73,6 +73,41 @@ def algorithmic_flops(prob):
     return {"post_order": post, "pre_order_dP": pre, "transition_matrices": chain}
 
 
+def fp64_reconstruction(prob, use_pi):
+    """Whether the library forms exp(tQ) in FP64 for this problem: it does so in FP32 instances when
+    some eigenvector matrix has infinity-norm condition number above 32 (the same rule, evaluated here
+    on the eigensystems the binding hands over)."""
+    from paper_1309_3075_amd.eigen import eigensystem
+    for s, Q in enumerate(prob.Q):
+        e = eigensystem(Q, prob.pi_process[s] if use_pi else None)
+        cond = np.abs(e.V).sum(axis=1).max() * np.abs(e.Vinv).sum(axis=1).max()
+        if cond > 32.0:
+            return True
+    return False
+
+
+def committed_traffic(name, kernel):
+    """HBM bytes per evaluation of `kernel` from a committed counter summary under profiles/,
+    or None when the summary is missing or the kernel source has changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        k, v = line.split(None, 1)
+        vals[k] = v.strip()
+    src = os.path.join(ROOT, vals.get("source", ""))
+    if not os.path.isfile(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != vals.get("source_sha256"):
+        return None
+    try:
+        return int(vals[f"{kernel}_read_bytes_per_eval"]) + int(vals[f"{kernel}_write_bytes_per_eval"])
+    except KeyError:
+        return None
+
+
 def run_cpu_baseline(prob, sample_patterns, want_Q):
     """The FP64 oracle on a pattern subsample, scaled to evaluations/s of the full problem."""
     import copy
@@ -217,10 +252,13 @@ def main():
     names = {"nuc": {"post_order": "nuc_post_level", "pre_order_dP": "nuc_pre_level"},
              "codon": {"post_order": "codon_post_level", "pre_order_dP": "codon_pre_level"},
              "generic": {"post_order": "post_level_generic", "pre_order_dP": "pre_level_generic + grad_G_generic"}}
-    kname = names[path].get(dom, "pstage_generic")
+    Kp = 4 if prob.n_states <= 4 else (8 if prob.n_states <= 8 else (prob.n_states + 15) // 16 * 16)
+    mfma_pstage = args.kernel == "auto" and Kp >= 16
+    kname = names[path].get(dom, "pstage_mfma" if mfma_pstage else "pstage_generic")
     if path == "codon" or dom == "transition_matrices":
         achieved = aflops[dom] / (dom_ms * 1e-3) / 1e12
-        peak = FP64_PEAK_TFLOPS if (args.precision == "fp64" or dom == "transition_matrices" and args.config == 4) \
+        peak = FP64_PEAK_TFLOPS if (args.precision == "fp64" or
+                                    dom == "transition_matrices" and fp64_reconstruction(prob, args.config != 4)) \
             else FP32_PEAK_TFLOPS
         roofline = {"bound": "mfma", "kernel": kname, "achieved": round(achieved, 3), "peak": peak,
                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
@@ -228,8 +266,12 @@ def main():
                     "hbm_GBps_same_kernel": round(abytes.get(dom, 0) / (dom_ms * 1e-3) / 1e9, 1)}
     else:
         achieved = abytes[dom] / (dom_ms * 1e-3) / 1e9
+        traffic = None
+        if path == "nuc" and args.precision == "fp32" and args.config == 2 and args.patterns is None:
+            traffic = committed_traffic("nuc_C2_hbm_traffic.txt", kname)
         roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                    "traffic_unit": "bytes per evaluation (all launches of the kernel)",
                     "algorithmic_bytes_per_eval": abytes[dom], "ms_per_eval": round(dom_ms, 4)}
     total_bytes = sum(abytes.values())
     result = {
@@ -257,7 +299,7 @@ def main():
     log(f"bench: bandwidth probe {probe}")
 
     if not args.no_cpu_baseline:
-        sample = args.cpu_sample or min(prob.n_patterns, {1: 1000, 2: 2000, 3: 500, 4: 1}.get(args.config, 1000))
+        sample = args.cpu_sample or min(prob.n_patterns, {1: 1000, 2: 30000, 3: 3000, 4: 1}.get(args.config, 1000))
         log(f"bench: cpu baseline on {sample} patterns ...")
         sub, ref_logL, ref_b, ref_q, cpu = run_cpu_baseline(prob, sample, want_Q)
         result["cpu_baseline"] = cpu
