@@ -38,6 +38,15 @@ struct EpochBatch {
   DevBuf gpart;                // dlogL/dP slot partials of every member
   DevBuf dpart;                // per-chunk shares of dlogL/dl
   DevBuf results;              // double [n]
+  // P-stage groups: members sharing Kp, precision, eigen arithmetic and gradient flag run in one launch
+  struct PGroup {
+    std::vector<size_t> members;
+    int max_items = 0;
+    size_t desc_offset = 0;  // index of the group's first descriptor in pdescs
+  };
+  std::vector<PGroup> pgroups;
+  std::vector<size_t> p_single;  // members on the generic P stage
+  DevBuf pdescs;
   std::vector<uint64_t> signature;
   hipGraph_t graph[8] = {};
   hipGraphExec_t exec[8] = {};
@@ -72,6 +81,41 @@ void drop_graphs(EpochBatch* b) {
     b->exec[k] = nullptr;
     b->graph[k] = nullptr;
   }
+}
+
+// Group the members' P stages by kernel instantiation and upload their descriptors.
+int build_pstage_groups(EpochBatch* b) {
+  b->pgroups.clear();
+  b->p_single.clear();
+  std::vector<int> key_of(b->insts.size(), -1);
+  std::vector<std::vector<int>> keys;  // Kp, fp64, eig_fp64, grad
+  for (size_t q = 0; q < b->insts.size(); ++q) {
+    const EpochInstance* in = b->insts[q];
+    if (in->cfg.kernel_path != EPOCH_KERNEL_AUTO || !pstage_mfma_supported(in)) {
+      b->p_single.push_back(q);
+      continue;
+    }
+    const std::vector<int> k = {in->Kp, in->fp64 ? 1 : 0, in->eig_fp64 ? 1 : 0,
+                                (in->cfg.flags & (EPOCH_GRAD_BRANCH | EPOCH_GRAD_Q)) ? 1 : 0};
+    size_t g = 0;
+    while (g < keys.size() && keys[g] != k) ++g;
+    if (g == keys.size()) {
+      keys.push_back(k);
+      b->pgroups.emplace_back();
+    }
+    b->pgroups[g].members.push_back(q);
+    b->pgroups[g].max_items = std::max(b->pgroups[g].max_items, in->n_nodes * in->C);
+  }
+  std::vector<PStageDesc> descs;
+  for (auto& g : b->pgroups) {
+    g.desc_offset = descs.size();
+    for (size_t q : g.members) descs.push_back(pstage_descriptor(b->insts[q]));
+  }
+  if (descs.empty()) return EPOCH_OK;
+  int rc = ensure(b->pdescs, descs.size() * sizeof(PStageDesc));
+  if (rc) return rc;
+  return hip_check(hipMemcpy(b->pdescs.ptr, descs.data(), descs.size() * sizeof(PStageDesc), hipMemcpyHostToDevice),
+                   "batch P-stage descriptors");
 }
 
 int build_schedule(EpochBatch* b) {
@@ -112,8 +156,13 @@ int build_schedule(EpochBatch* b) {
 // Enqueue one evaluation of every member on b->stream (no host synchronisation).
 int enqueue(EpochBatch* b, uint32_t what, const double* const* d_result_ptrs) {
   const size_t n = b->insts.size();
-  for (auto* in : b->insts) {
-    int rc = launch_pstage(in);
+  for (const auto& g : b->pgroups) {
+    int rc = launch_pstage_mfma_multi(b->insts[g.members[0]], static_cast<const PStageDesc*>(b->pdescs.ptr) + g.desc_offset,
+                                      (int)g.members.size(), g.max_items, b->stream);
+    if (rc) return rc;
+  }
+  for (size_t q : b->p_single) {
+    int rc = launch_pstage(b->insts[q]);
     if (rc) return rc;
   }
   if (b->merged) {
@@ -201,8 +250,10 @@ int replay(EpochBatch* b, uint32_t what) {
   for (auto* in : b->insts) sig.push_back(member_signature(in));
   if (sig != b->signature) {
     drop_graphs(b);
+    int rc = build_pstage_groups(b);
+    if (rc) return rc;
     if (b->merged) {
-      int rc = build_schedule(b);
+      rc = build_schedule(b);
       if (rc) return rc;
     }
     b->signature = sig;
@@ -396,6 +447,7 @@ int epoch_batch_destroy(EpochBatch* b) {
   release_buf(b->dev);
   release_buf(b->gpart);
   release_buf(b->dpart);
+  release_buf(b->pdescs);
   release_buf(b->results);
   for (auto& g : b->gslots) release_buf(g);
   if (b->own_stream) (void)hipStreamDestroy(b->stream);

@@ -41,6 +41,25 @@ struct CodonProblem {
   int N, P, K, root, n_nodes;
 };
 
+// Device pointers of one problem's P stage (one instance, or one member of a batch).
+struct PStageDesc {
+  const void* V;
+  const void* Vi;
+  const void* lr;
+  const void* li;
+  const int32_t* seg_offset;
+  const int32_t* seg_process;
+  const double* seg_time;
+  const double* seg_frac;
+  const double* rate;
+  const double* cat_rates;
+  void* Pout;
+  void* dPout;
+  int n_items;  // nodes x categories
+  int C;
+  bool grad;
+};
+
 // Merged level schedule: work items (problem, internal node) grouped by level.
 struct CodonSchedule {
   std::vector<int2> items;         // level l (1-based) occupies [level_off[l-1], level_off[l])
@@ -151,6 +170,9 @@ int launch_pstage_generic(EpochInstance* in);
 int launch_pstage_mfma(EpochInstance* in);
 bool pstage_mfma_supported(const EpochInstance* in);
 int launch_pstage(EpochInstance* in);  // matrix-core kernel where it applies, else generic
+PStageDesc pstage_descriptor(const EpochInstance* in);
+int launch_pstage_mfma_multi(const EpochInstance* like, const PStageDesc* d_descs, int n, int max_items,
+                             hipStream_t st);
 int launch_grad_Q_mfma(EpochInstance* in);
 bool grad_Q_mfma_supported(const EpochInstance* in);
 int launch_grad_Q(EpochInstance* in);  // matrix-core kernels where they apply, else generic

@@ -35,47 +35,51 @@ namespace epochlik {
 
 namespace {
 
-// One wavefront = one 16-row stripe of one (node, category) item.
+// One wavefront = one 16-row stripe of one (node, category) item of one problem.
 template <typename T, typename TO, bool GRAD, int NT>
-__global__ __launch_bounds__(256) void pstage_mfma_kernel(
-    int n_items, int C, const T* __restrict__ eigV, const T* __restrict__ eigVi,
-    const T* __restrict__ lre, const T* __restrict__ lim, const int32_t* __restrict__ seg_offset,
-    const int32_t* __restrict__ seg_process, const double* __restrict__ seg_time,
-    const double* __restrict__ seg_frac, const double* __restrict__ rate,
-    const double* __restrict__ cat_rates, TO* __restrict__ Pout, TO* __restrict__ dPout) {
+__device__ inline void pstage_stripe(const PStageDesc& pd, int gw, ColCoef<T>* coef) {
   using acc = typename Mfma<T>::acc;
   constexpr int Kp = 16 * NT;
   constexpr int KK = Kp * Kp;
-  __shared__ ColCoef<T> s_coef[4][64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int gw = blockIdx.x * 4 + wave;
   const int item = gw / NT, stripe = gw - item * NT;
-  if (item >= n_items) return;  // whole wavefronts only: no barrier follows
+  if (item >= pd.n_items) return;  // whole wavefronts only: no barrier follows
+  const int C = pd.C;
+  const T* __restrict__ eigV = static_cast<const T*>(pd.V);
+  const T* __restrict__ eigVi = static_cast<const T*>(pd.Vi);
+  const T* __restrict__ lre = static_cast<const T*>(pd.lr);
+  const T* __restrict__ lim = static_cast<const T*>(pd.li);
+  const int32_t* __restrict__ seg_offset = pd.seg_offset;
+  const int32_t* __restrict__ seg_process = pd.seg_process;
+  const double* __restrict__ seg_time = pd.seg_time;
+  const double* __restrict__ seg_frac = pd.seg_frac;
+  const double* __restrict__ rate = pd.rate;
+  const double* __restrict__ cat_rates = pd.cat_rates;
+  TO* __restrict__ Pout = static_cast<TO*>(pd.Pout);
+  TO* __restrict__ dPout = static_cast<TO*>(pd.dPout);
+  const int lane = threadIdx.x & 63;
   const int v = item / C, c = item - v * C;
   const int g = lane >> 4, n = lane & 15;
   const int row = 16 * stripe + n;  // row of P this lane's column of X^T belongs to
   const int arow = Mfma<T>::a_row(n);
 
-  acc x[NT], d[NT];
+  constexpr int NB = GRAD ? 2 : 1;  // the running product X and, with GRAD, its derivative D
+  acc xd[NB][NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      x[t][q] = (16 * t + 4 * g + q == row) ? T(1) : T(0);
-      d[t][q] = T(0);
+      xd[0][t][q] = (16 * t + 4 * g + q == row) ? T(1) : T(0);
+      if (GRAD) xd[NB - 1][t][q] = T(0);
     }
 
   const int seg0 = seg_offset[v];
   const int m = seg_offset[v + 1] - seg0;
   const double rho = cat_rates[c];
   const double scale = rho * rate[v];
-  ColCoef<T>* coef = s_coef[wave];
   for (int k = 0; k < m; ++k) {
     const int s = seg_process[seg0 + k];
     const T tau = T(scale * seg_time[seg0 + k]);
     const T dsc = T(rho * seg_frac[seg0 + k]);
-    const T* V = eigV + (size_t)s * KK;
-    const T* Vi = eigVi + (size_t)s * KK;
     if (lane < Kp) {
       const BlockCoef<T> bc = block_coef(lre + (size_t)s * Kp, lim + (size_t)s * Kp, lane, tau);
       coef[lane] = ColCoef<T>{bc.m_self, bc.m_other, dsc * bc.dm_self, dsc * bc.dm_other};
@@ -83,24 +87,12 @@ __global__ __launch_bounds__(256) void pstage_mfma_kernel(
     __builtin_amdgcn_wave_barrier();
 
     // Y^T = V^T X^T (and V^T D^T)
-    acc y[NT], yd[NT];
+    acc y[NB][NT];
 #pragma unroll
-    for (int mt = 0; mt < NT; ++mt) {
-      y[mt] = acc{0, 0, 0, 0};
-      if (GRAD) yd[mt] = acc{0, 0, 0, 0};
-    }
+    for (int b = 0; b < NB; ++b)
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const T* vrow = V + (16 * t + 4 * g + q) * Kp + arow;
-#pragma unroll
-        for (int mt = 0; mt < NT; ++mt) {
-          const T a = vrow[16 * mt];
-          y[mt] = Mfma<T>::mma(a, x[t][q], y[mt]);
-          if (GRAD) yd[mt] = Mfma<T>::mma(a, d[t][q], yd[mt]);
-        }
-      }
+      for (int mt = 0; mt < NT; ++mt) y[b][mt] = acc{0, 0, 0, 0};
+    stripe_gemm<T, NT, NB>(eigV + (size_t)s * KK, g, arow, xd, y);
 
     // column operator on rows j = 16 mt + 4 g + q of Y^T
 #pragma unroll
@@ -109,64 +101,55 @@ __global__ __launch_bounds__(256) void pstage_mfma_kernel(
       for (int q = 0; q < 4; q += 2) {
         const ColCoef<T> c0 = coef[16 * mt + 4 * g + q];
         const ColCoef<T> c1 = coef[16 * mt + 4 * g + q + 1];
-        const T y0 = y[mt][q], y1 = y[mt][q + 1];
-        y[mt][q] = c0.ms * y0 + c0.mo * y1;
-        y[mt][q + 1] = c1.ms * y1 + c1.mo * y0;
+        const T y0 = y[0][mt][q], y1 = y[0][mt][q + 1];
+        y[0][mt][q] = c0.ms * y0 + c0.mo * y1;
+        y[0][mt][q + 1] = c1.ms * y1 + c1.mo * y0;
         if (GRAD) {
-          const T d0 = yd[mt][q], d1 = yd[mt][q + 1];
-          yd[mt][q] = c0.ms * d0 + c0.mo * d1 + c0.dms * y0 + c0.dmo * y1;
-          yd[mt][q + 1] = c1.ms * d1 + c1.mo * d0 + c1.dms * y1 + c1.dmo * y0;
+          const T d0 = y[NB - 1][mt][q], d1 = y[NB - 1][mt][q + 1];
+          y[NB - 1][mt][q] = c0.ms * d0 + c0.mo * d1 + c0.dms * y0 + c0.dmo * y1;
+          y[NB - 1][mt][q + 1] = c1.ms * d1 + c1.mo * d0 + c1.dms * y1 + c1.dmo * y0;
         }
       }
     __builtin_amdgcn_wave_barrier();
 
     // X^T += V^-T Y'^T (and D^T += V^-T YD'^T)
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const T* vrow = Vi + (16 * t + 4 * g + q) * Kp + arow;
-#pragma unroll
-        for (int mt = 0; mt < NT; ++mt) {
-          const T a = vrow[16 * mt];
-          x[mt] = Mfma<T>::mma(a, y[t][q], x[mt]);
-          if (GRAD) d[mt] = Mfma<T>::mma(a, yd[t][q], d[mt]);
-        }
-      }
+    stripe_gemm<T, NT, NB>(eigVi + (size_t)s * KK, g, arow, y, xd);
   }
 
   const size_t base = ((size_t)v * C + c) * KK + (size_t)row * Kp + 4 * g;
 #pragma unroll
   for (int mt = 0; mt < NT; ++mt) {
-    store4<T, TO>(Pout + base + 16 * mt, x[mt]);
-    if (GRAD) store4<T, TO>(dPout + base + 16 * mt, d[mt]);
+    store4<T, TO>(Pout + base + 16 * mt, xd[0][mt]);
+    if (GRAD) store4<T, TO>(dPout + base + 16 * mt, xd[NB - 1][mt]);
   }
+}
+
+// One problem (descriptor passed by value).
+template <typename T, typename TO, bool GRAD, int NT>
+__global__ __launch_bounds__(256) void pstage_mfma_kernel(PStageDesc pd) {
+  __shared__ ColCoef<T> s_coef[4][64];
+  const int wave = threadIdx.x >> 6;
+  pstage_stripe<T, TO, GRAD, NT>(pd, blockIdx.x * 4 + wave, s_coef[wave]);
+}
+
+// Several problems of one batch in one launch: blockIdx.y selects the problem.
+template <typename T, typename TO, bool GRAD, int NT>
+__global__ __launch_bounds__(256) void pstage_mfma_multi_kernel(const PStageDesc* __restrict__ descs) {
+  __shared__ ColCoef<T> s_coef[4][64];
+  const int wave = threadIdx.x >> 6;
+  const PStageDesc pd = descs[blockIdx.y];
+  pstage_stripe<T, TO, GRAD, NT>(pd, blockIdx.x * 4 + wave, s_coef[wave]);
 }
 
 template <typename T, typename TO, int NT>
 int pstage_mfma_launch(EpochInstance* in) {
-  const int Kp = in->Kp, C = in->C;
-  const size_t KK = (size_t)Kp * Kp, S = in->S;
-  const bool grad = (in->cfg.flags & (EPOCH_GRAD_BRANCH | EPOCH_GRAD_Q)) != 0;
-  const int items = in->n_nodes * C;
-  const long waves = (long)items * NT;
+  const PStageDesc pd = pstage_descriptor(in);
+  const long waves = (long)pd.n_items * NT;
   dim3 grid((unsigned)((waves + 3) / 4));
-  const T* base = static_cast<const T*>(sizeof(T) == 8 ? in->eig64.ptr : in->eigT.ptr);
-  const T* V = base;
-  const T* Vi = base + S * KK;
-  const T* lr = base + 2 * S * KK;
-  const T* li = lr + S * Kp;
-  const double* cat = static_cast<const double*>(in->cat.ptr);
-  TO* Pout = static_cast<TO*>(in->Pm.ptr);
-  TO* dPout = static_cast<TO*>(in->dPm.ptr);
-  if (grad)
-    hipLaunchKernelGGL((pstage_mfma_kernel<T, TO, true, NT>), grid, dim3(256), 0, in->stream, items, C, V, Vi,
-                       lr, li, in->d_seg_offset, in->d_seg_process, in->d_seg_time, in->d_seg_frac, in->d_rate,
-                       cat, Pout, dPout);
+  if (pd.grad)
+    hipLaunchKernelGGL((pstage_mfma_kernel<T, TO, true, NT>), grid, dim3(256), 0, in->stream, pd);
   else
-    hipLaunchKernelGGL((pstage_mfma_kernel<T, TO, false, NT>), grid, dim3(256), 0, in->stream, items, C, V, Vi,
-                       lr, li, in->d_seg_offset, in->d_seg_process, in->d_seg_time, in->d_seg_frac, in->d_rate,
-                       cat, Pout, dPout);
+    hipLaunchKernelGGL((pstage_mfma_kernel<T, TO, false, NT>), grid, dim3(256), 0, in->stream, pd);
   return hip_check(hipGetLastError(), "pstage_mfma launch");
 }
 
@@ -181,6 +164,27 @@ int pstage_mfma_dispatch(EpochInstance* in) {
   }
 }
 
+template <typename T, typename TO, int NT>
+int pstage_multi_launch(const PStageDesc* d_descs, int n, int max_items, bool grad, hipStream_t st) {
+  dim3 grid((unsigned)(((long)max_items * NT + 3) / 4), (unsigned)n);
+  if (grad)
+    hipLaunchKernelGGL((pstage_mfma_multi_kernel<T, TO, true, NT>), grid, dim3(256), 0, st, d_descs);
+  else
+    hipLaunchKernelGGL((pstage_mfma_multi_kernel<T, TO, false, NT>), grid, dim3(256), 0, st, d_descs);
+  return hip_check(hipGetLastError(), "pstage_mfma_multi launch");
+}
+
+template <typename T, typename TO>
+int pstage_multi_dispatch(int Kp, const PStageDesc* d_descs, int n, int max_items, bool grad, hipStream_t st) {
+  switch (Kp) {
+    case 16: return pstage_multi_launch<T, TO, 1>(d_descs, n, max_items, grad, st);
+    case 32: return pstage_multi_launch<T, TO, 2>(d_descs, n, max_items, grad, st);
+    case 48: return pstage_multi_launch<T, TO, 3>(d_descs, n, max_items, grad, st);
+    case 64: return pstage_multi_launch<T, TO, 4>(d_descs, n, max_items, grad, st);
+    default: return set_error(EPOCH_ERR_STATE, "matrix-core P stage needs Kp in {16, 32, 48, 64}, got %d", Kp);
+  }
+}
+
 }  // namespace
 
 bool pstage_mfma_supported(const EpochInstance* in) {
@@ -190,6 +194,42 @@ bool pstage_mfma_supported(const EpochInstance* in) {
 int launch_pstage_mfma(EpochInstance* in) {
   if (in->fp64) return pstage_mfma_dispatch<double, double>(in);
   return in->eig_fp64 ? pstage_mfma_dispatch<double, float>(in) : pstage_mfma_dispatch<float, float>(in);
+}
+
+// The device pointers and sizes one problem's P stage reads and writes, in the
+// arithmetic type the instance uses (FP64 eigensystems when fp64 or eig_fp64).
+PStageDesc pstage_descriptor(const EpochInstance* in) {
+  PStageDesc d{};
+  const size_t KK = (size_t)in->Kp * in->Kp, S = in->S;
+  const bool dbl = in->fp64 || in->eig_fp64;
+  const size_t es = dbl ? sizeof(double) : sizeof(float);
+  const char* base = static_cast<const char*>(dbl ? in->eig64.ptr : in->eigT.ptr);
+  d.V = base;
+  d.Vi = base + S * KK * es;
+  d.lr = base + 2 * S * KK * es;
+  d.li = base + (2 * S * KK + S * in->Kp) * es;
+  d.seg_offset = in->d_seg_offset;
+  d.seg_process = in->d_seg_process;
+  d.seg_time = in->d_seg_time;
+  d.seg_frac = in->d_seg_frac;
+  d.rate = in->d_rate;
+  d.cat_rates = static_cast<const double*>(in->cat.ptr);
+  d.Pout = in->Pm.ptr;
+  d.dPout = in->dPm.ptr;
+  d.n_items = in->n_nodes * in->C;
+  d.C = in->C;
+  d.grad = (in->cfg.flags & (EPOCH_GRAD_BRANCH | EPOCH_GRAD_Q)) != 0;
+  return d;
+}
+
+// One launch for a group of problems that share Kp, precision, eigen arithmetic
+// and gradient flag (their descriptors already on the device).
+int launch_pstage_mfma_multi(const EpochInstance* like, const PStageDesc* d_descs, int n, int max_items,
+                             hipStream_t st) {
+  const bool grad = (like->cfg.flags & (EPOCH_GRAD_BRANCH | EPOCH_GRAD_Q)) != 0;
+  if (like->fp64) return pstage_multi_dispatch<double, double>(like->Kp, d_descs, n, max_items, grad, st);
+  if (like->eig_fp64) return pstage_multi_dispatch<double, float>(like->Kp, d_descs, n, max_items, grad, st);
+  return pstage_multi_dispatch<float, float>(like->Kp, d_descs, n, max_items, grad, st);
 }
 
 }  // namespace epochlik

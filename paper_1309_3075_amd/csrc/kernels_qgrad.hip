@@ -383,11 +383,11 @@ __global__ __launch_bounds__(256) void qgrad_chain_kernel(
   T(*coef)[2] = s_coef[w];
 
   // forward pass
-  acc x[NT];
+  acc x[1][NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) x[t][q] = (16 * t + 4 * g + q == row) ? T(1) : T(0);
+    for (int q = 0; q < 4; ++q) x[0][t][q] = (16 * t + 4 * g + q == row) ? T(1) : T(0);
   for (int k = 0; k < m; ++k) {
     const int s = seg_process[seg0 + k];
     const double tau_d = scale * seg_time[seg0 + k];
@@ -406,74 +406,53 @@ __global__ __launch_bounds__(256) void qgrad_chain_kernel(
       reinterpret_cast<double2*>(qexp)[((size_t)(seg0 + k) * C + c) * Kp + lane] = make_double2(ea * cos(th), ea * sin(th));
     }
     wave_lds_sync();
-    acc y[NT];
+    acc y[1][NT];
 #pragma unroll
-    for (int mt = 0; mt < NT; ++mt) y[mt] = acc{0, 0, 0, 0};
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const T* vrow = V + (16 * t + 4 * g + q) * Kp + arow;
-#pragma unroll
-        for (int mt = 0; mt < NT; ++mt) y[mt] = Mfma<T>::mma(vrow[16 * mt], x[t][q], y[mt]);
-      }
+    for (int mt = 0; mt < NT; ++mt) y[0][mt] = acc{0, 0, 0, 0};
+    stripe_gemm<T, NT, 1>(V, g, arow, x, y);
     T* U = Ubuf + ((size_t)(seg0 + k) * C + c) * KK + (size_t)row * Kp + 4 * g;
 #pragma unroll
-    for (int mt = 0; mt < NT; ++mt) store4<T, T>(U + 16 * mt, y[mt]);
+    for (int mt = 0; mt < NT; ++mt) store4<T, T>(U + 16 * mt, y[0][mt]);
     if (k + 1 < m) {
 #pragma unroll
       for (int mt = 0; mt < NT; ++mt)
 #pragma unroll
         for (int q = 0; q < 4; q += 2) {
           const int j = 16 * mt + 4 * g + q;
-          const T y0 = y[mt][q], y1 = y[mt][q + 1];
-          y[mt][q] = coef[j][0] * y0 + coef[j][1] * y1;
-          y[mt][q + 1] = coef[j + 1][0] * y1 + coef[j + 1][1] * y0;
+          const T y0 = y[0][mt][q], y1 = y[0][mt][q + 1];
+          y[0][mt][q] = coef[j][0] * y0 + coef[j][1] * y1;
+          y[0][mt][q + 1] = coef[j + 1][0] * y1 + coef[j + 1][1] * y0;
         }
-#pragma unroll
-      for (int t = 0; t < NT; ++t)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const T* vrow = Vi + (16 * t + 4 * g + q) * Kp + arow;
-#pragma unroll
-          for (int mt = 0; mt < NT; ++mt) x[mt] = Mfma<T>::mma(vrow[16 * mt], y[t][q], x[mt]);
-        }
+      stripe_gemm<T, NT, 1>(Vi, g, arow, y, x);
     }
     wave_lds_sync();
   }
 
   // backward pass, R_{m-1} = G (rows of this stripe)
-  acc R[NT];
+  acc R[1][NT];
   {
     const double* Gr = G + ((size_t)v * C + c) * KK + (size_t)row * Kp + 4 * g;
 #pragma unroll
     for (int mt = 0; mt < NT; ++mt)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) R[mt][q] = T(Gr[16 * mt + q]);
+      for (int q = 0; q < 4; ++q) R[0][mt][q] = T(Gr[16 * mt + q]);
   }
   for (int k = m - 1; k >= 0; --k) {
     const int s = seg_process[seg0 + k];
     const T* VT = eigVT + (size_t)s * KK;
     const T* ViT = eigViT + (size_t)s * KK;
     // W = R V^-T
-    acc wk[NT];
+    acc wk[1][NT];
 #pragma unroll
-    for (int mt = 0; mt < NT; ++mt) wk[mt] = acc{0, 0, 0, 0};
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const T* vrow = ViT + (16 * t + 4 * g + q) * Kp + arow;
-#pragma unroll
-        for (int mt = 0; mt < NT; ++mt) wk[mt] = Mfma<T>::mma(vrow[16 * mt], R[t][q], wk[mt]);
-      }
+    for (int mt = 0; mt < NT; ++mt) wk[0][mt] = acc{0, 0, 0, 0};
+    stripe_gemm<T, NT, 1>(ViT, g, arow, R, wk);
     // stage this stripe's rows of W_k and U_k
     const T* U = Ubuf + ((size_t)(seg0 + k) * C + c) * KK + (size_t)row * Kp + 4 * g;
 #pragma unroll
     for (int mt = 0; mt < NT; ++mt)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        sW[row * LD + 16 * mt + 4 * g + q] = wk[mt][q];
+        sW[row * LD + 16 * mt + 4 * g + q] = wk[0][mt][q];
         sU[row * LD + 16 * mt + 4 * g + q] = U[16 * mt + q];
       }
     __syncthreads();
@@ -507,19 +486,12 @@ __global__ __launch_bounds__(256) void qgrad_chain_kernel(
 #pragma unroll
         for (int q = 0; q < 4; q += 2) {
           const int j = 16 * mt + 4 * g + q;
-          const T y0 = wk[mt][q], y1 = wk[mt][q + 1];
-          wk[mt][q] = coef[j][0] * y0 + coef[j][1] * y1;
-          wk[mt][q + 1] = coef[j + 1][0] * y1 + coef[j + 1][1] * y0;
+          const T y0 = wk[0][mt][q], y1 = wk[0][mt][q + 1];
+          wk[0][mt][q] = coef[j][0] * y0 + coef[j][1] * y1;
+          wk[0][mt][q + 1] = coef[j + 1][0] * y1 + coef[j + 1][1] * y0;
         }
       wave_lds_sync();
-#pragma unroll
-      for (int t = 0; t < NT; ++t)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const T* vrow = VT + (16 * t + 4 * g + q) * Kp + arow;
-#pragma unroll
-          for (int mt = 0; mt < NT; ++mt) R[mt] = Mfma<T>::mma(vrow[16 * mt], wk[t][q], R[mt]);
-        }
+      stripe_gemm<T, NT, 1>(VT, g, arow, wk, R);
     }
   }
 }

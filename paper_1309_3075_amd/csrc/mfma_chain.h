@@ -53,6 +53,38 @@ __device__ inline void store4<double, float>(float* dst, const f64x4& x) {
   *reinterpret_cast<float4*>(dst) = make_float4(float(x[0]), float(x[1]), float(x[2]), float(x[3]));
 }
 
+// out[b] (+)= (in[b] M) for NB stripes held transposed (see the chain kernels):
+// the A operand of k-step (t, q) is row 16 t + 4 g + q of the Kp x Kp matrix M
+// at column 16 mt + arow.  The 4 NT operands of tile t + 1 are loaded while the
+// MFMAs of tile t run, so a step waits on memory about once instead of once per
+// instruction.
+template <typename T, int NT, int NB>
+__device__ inline void stripe_gemm(const T* __restrict__ M, int g, int arow,
+                                   const typename Mfma<T>::acc (&in)[NB][NT],
+                                   typename Mfma<T>::acc (&out)[NB][NT]) {
+  constexpr int Kp = 16 * NT;
+  T a[2][4][NT];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt) a[0][q][mt] = M[(4 * g + q) * Kp + 16 * mt + arow];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    if (t + 1 < NT) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int mt = 0; mt < NT; ++mt) a[(t + 1) & 1][q][mt] = M[(16 * (t + 1) + 4 * g + q) * Kp + 16 * mt + arow];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) out[b][mt] = Mfma<T>::mma(a[t & 1][q][mt], in[b][t][q], out[b][mt]);
+  }
+}
+
 // Orders the LDS accesses of one wavefront (a write, then reads by other lanes).
 __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
