@@ -331,7 +331,7 @@ int autotune(EpochBatch* b) {
   if (rc) return rc;
   float best = 1e30f;
   int best_t = b->target_blocks;
-  for (int t : {256, 512, 1024, 2048, 4096}) {
+  for (int t : {512, 1024, 2048, 4096, 8192, 16384}) {
     b->target_blocks = t;
     b->signature.clear();  // forces a new schedule and capture
     rc = replay(b, what);  // warm-up (and capture)

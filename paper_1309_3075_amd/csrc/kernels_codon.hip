@@ -247,17 +247,74 @@ __global__ __launch_bounds__(256) void codon_final_kernel(const CodonProblem* __
 
 // ---------------------------------------------------------------------------
 // Pre-order of one level fused with dlogL/dP of the two child branches.
+//
+// The block's four wavefronts walk its R tiles of 64 patterns together.  For
+// each tile, wavefront w first works on patterns 16 w .. 16 w + 15: child
+// vectors, q_u, the weights w_p / L_p, t_a = q o S_b and t_b = q o S_a (kept in
+// LDS for the whole block), and the outside vectors of internal children.
+// After a barrier, wavefront w accumulates rows 16 w .. 16 w + 15 of both
+// children's dlogL/dP over all 64 patterns (A = t from LDS times w_p/L_p,
+// B = child partials from L2, or the tip indicator), so each wavefront holds
+// only 2 x 16 accumulator registers; the loads of its next tile are issued
+// before that second phase and arrive while it runs.
+struct PreTileLoads {
+  f4 La[4], Lb[4];  // 16-byte rows of internal children's partials (child product A operand)
+  f4 Q[4];          // q_u in the D layout
+  int cola[4], colb[4];
+};
+
+__device__ inline void pre_load_tile(PreTileLoads& ld, const CodonProblem& pr, const float* La, const float* Lb,
+                                     const float* Qu, int a, int b, int p0, int g, int r) {
+  const int P = pr.P, K = pr.K, N = pr.N;
+  const int pa = min(p0 + r, P - 1);
+  if (La) {
+    const EPOCH_GLOBAL f4* row = gptr(reinterpret_cast<const f4*>(La + (size_t)pa * KP)) + g;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) ld.La[t] = row[4 * t];
+  } else {
+    tip_columns(ld.cola, pr.tips + (size_t)a * P, P, p0, K, g);
+  }
+  if (Lb) {
+    const EPOCH_GLOBAL f4* row = gptr(reinterpret_cast<const f4*>(Lb + (size_t)pa * KP)) + g;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) ld.Lb[t] = row[4 * t];
+  } else {
+    tip_columns(ld.colb, pr.tips + (size_t)b * P, P, p0, K, g);
+  }
+  if (Qu) load_dlayout(ld.Q, Qu, P, p0, g, r);
+  (void)N;
+}
+
+// S[nt] (D layout) from 16-byte A-operand rows already in registers.
+__device__ inline void child_gemm_regs(f4 (&S)[4], const f4 (&a)[4], const float* __restrict__ sP, int g, int r) {
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) S[nt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const f4 bv = *reinterpret_cast<const f4*>(sP + (16 * nt + r) * LDP + 16 * t + 4 * g);
+      S[nt] = mfma(a[t].x, bv.x, S[nt]);
+      S[nt] = mfma(a[t].y, bv.y, S[nt]);
+      S[nt] = mfma(a[t].z, bv.z, S[nt]);
+      S[nt] = mfma(a[t].w, bv.w, S[nt]);
+    }
+}
+
 __global__ __launch_bounds__(256, 2) void codon_pre_level_kernel(const CodonProblem* __restrict__ probs,
                                                                const int2* __restrict__ items, int R) {
   __shared__ __align__(16) float sPa[KP * LDP];
   __shared__ __align__(16) float sPb[KP * LDP];
-  __shared__ __align__(16) float sT[4][WT * LDP];  // per-wavefront transpose of t
+  __shared__ __align__(16) float sT[TILE * LDP];  // t of one side for the block tile, pattern-major
+  __shared__ __align__(16) float sL[TILE * LDP];  // that side's child partials for the block tile
+  __shared__ float sCF[TILE];                     // w_p / L_p of the block tile
+  __shared__ int sCol[2][TILE];                    // tip columns of the block tile
   const int2 it = items[blockIdx.y];
   const CodonProblem& pr = probs[it.x];
   const int N = pr.N, P = pr.P, K = pr.K;
   const int base = blockIdx.x * R * TILE;
   if (base >= P) return;  // uniform: this problem has fewer tiles
-  const int end = min(P, base + R * TILE);
+  const int n_tiles = min(R, (P - base + TILE - 1) / TILE);  // uniform over the block
   const int u = it.y;
   const int a = pr.left[u], b = pr.right[u];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
@@ -273,152 +330,133 @@ __global__ __launch_bounds__(256, 2) void codon_pre_level_kernel(const CodonProb
   float piv[4];
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt) piv[nt] = 16 * nt + r < K ? (float)pr.pi[16 * nt + r] : 0.f;
-  float* tw = sT[w];
-  // dlogL/dP accumulators: row 16 mt + 4 g + v, column 16 nt + r
-  f4 Ga[4][4], Gb[4][4];
+  // dlogL/dP accumulators: rows 16 w + 4 g + v, columns 16 nt + r
+  f4 Ga[4], Gb[4];
 #pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-      Ga[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
-      Gb[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
-    }
-  for (int p0 = base + WT * w; p0 < end; p0 += 4 * WT) {
+  for (int nt = 0; nt < 4; ++nt) {
+    Ga[nt] = f4{0.f, 0.f, 0.f, 0.f};
+    Gb[nt] = f4{0.f, 0.f, 0.f, 0.f};
+  }
+  PreTileLoads cur, nxt;
+  pre_load_tile(cur, pr, La, Lb, Qu, a, b, base + WT * w, g, r);
+  float* trows = sT + (WT * w) * LDP;  // this wavefront's 16 pattern rows
+  float* lrows = sL + (WT * w) * LDP;
+  for (int bt = 0; bt < n_tiles; ++bt) {
+    const int p0 = base + bt * TILE + WT * w;  // first pattern of this wavefront's part
+    // ---- this wavefront's 16 patterns: child vectors, q_u, w_p / L_p
     f4 Sa[4], Sb[4];
-    int cola[4], colb[4];
-    if (La) {
-      child_gemm(Sa, La, P, p0, sPa, g, r);
-    } else {
-      tip_columns(cola, pr.tips + (size_t)a * P, P, p0, K, g);
-      tip_lookup(Sa, cola, sPa, r);
-    }
-    if (Lb) {
-      child_gemm(Sb, Lb, P, p0, sPb, g, r);
-    } else {
-      tip_columns(colb, pr.tips + (size_t)b * P, P, p0, K, g);
-      tip_lookup(Sb, colb, sPb, r);
-    }
+    if (La)
+      child_gemm_regs(Sa, cur.La, sPa, g, r);
+    else
+      tip_lookup(Sa, cur.cola, sPa, r);
+    if (Lb)
+      child_gemm_regs(Sb, cur.Lb, sPb, g, r);
+    else
+      tip_lookup(Sb, cur.colb, sPb, r);
     f4 Q[4];
-    if (Qu) {
-      load_dlayout(Q, Qu, P, p0, g, r);
-    } else {
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt) Q[nt] = f4{piv[nt], piv[nt], piv[nt], piv[nt]};
-    }
-    // w_p / L_p with L_p = sum_i q_i S_a,i S_b,i (the scales of q, L_a and L_b cancel)
-    float cf[4];
+    for (int nt = 0; nt < 4; ++nt) Q[nt] = Qu ? cur.Q[nt] : f4{piv[nt], piv[nt], piv[nt], piv[nt]};
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      float s = 0.f;
+      float sum = 0.f;
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt) s += Q[nt][v] * Sa[nt][v] * Sb[nt][v];
-      s = row16_sum(s);
+      for (int nt = 0; nt < 4; ++nt) sum += Q[nt][v] * Sa[nt][v] * Sb[nt][v];
+      sum = row16_sum(sum);
       const int p = p0 + 4 * g + v;
-      cf[v] = (p < P && s > 0.f) ? gptr(pr.weightsT)[p] / s : 0.f;
+      if (r == 0) {
+        sCF[WT * w + 4 * g + v] = (p < P && sum > 0.f) ? gptr(pr.weightsT)[p] / sum : 0.f;
+        if (!La) sCol[0][WT * w + 4 * g + v] = cur.cola[v];
+        if (!Lb) sCol[1][WT * w + 4 * g + v] = cur.colb[v];
+      }
     }
+    // loads of this wavefront's part of the next tile, in flight during the rest
+    if (bt + 1 < n_tiles) pre_load_tile(nxt, pr, La, Lb, Qu, a, b, p0 + TILE, g, r);
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
       const int child = side == 0 ? a : b;
       const float* Lc = side == 0 ? La : Lb;
       const f4* So = side == 0 ? Sb : Sa;
-      f4(&G)[4][4] = side == 0 ? Ga : Gb;
+      f4* G = side == 0 ? Ga : Gb;
       const float* sP = side == 0 ? sPa : sPb;
-      f4 t[4];
-#pragma unroll
-      for (int nt = 0; nt < 4; ++nt) t[nt] = Q[nt] * So[nt];
-      // G[i][j] += sum_p cf_p t[p][i] L[p][j]: A = cf t (registers), B = child vector
-      f4 B[4];
-      if (Lc) {
-        load_dlayout(B, Lc, P, p0, g, r);
-      } else {
-        const int* col = side == 0 ? cola : colb;
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int j = 16 * nt + r;
-            B[nt][v] = (col[v] == j || (col[v] == 64 && j < K)) ? 1.f : 0.f;
-          }
-      }
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-          const float av = cf[v] * t[mt][v];
-#pragma unroll
-          for (int nt = 0; nt < 4; ++nt) G[mt][nt] = mfma(av, B[nt][v], G[mt][nt]);
-        }
-      if (!Lc) continue;  // tips carry no outside vector
-      // q_c[p][j] = sum_i t[p][i] P_c[i][j]: A = t rows (LDS transpose), B = P_c (LDS)
+      if (side == 1) __syncthreads();  // every wavefront is done with side a's t and L
+      // t = q o S_sibling rows, and the child's partial rows, into LDS
 #pragma unroll
       for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) tw[(4 * g + v) * LDP + 16 * nt + r] = t[nt][v];
+        for (int v = 0; v < 4; ++v) trows[(4 * g + v) * LDP + 16 * nt + r] = Q[nt][v] * So[nt][v];
+      if (Lc) {
+        const f4* lr = side == 0 ? cur.La : cur.Lb;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) *reinterpret_cast<f4*>(lrows + r * LDP + 16 * t + 4 * g) = lr[t];
+      }
       wave_lds_sync();
-      f4 ta[4];
+      if (Lc) {
+        // outside vector q_c[p][j] = sum_i t[p][i] P_c[i][j] of this wavefront's patterns
+        f4 ta[4];
 #pragma unroll
-      for (int tt = 0; tt < 4; ++tt) ta[tt] = *reinterpret_cast<const f4*>(tw + r * LDP + 16 * tt + 4 * g);
-      wave_lds_sync();
-      f4 Qo[4];
+        for (int tt = 0; tt < 4; ++tt) ta[tt] = *reinterpret_cast<const f4*>(trows + r * LDP + 16 * tt + 4 * g);
+        f4 Qo[4];
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt) Qo[nt] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int nt = 0; nt < 4; ++nt) Qo[nt] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int tt = 0; tt < 4; ++tt)
+        for (int tt = 0; tt < 4; ++tt)
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-          const float* prow = sP + (16 * tt + 4 * g) * LDP + 16 * nt + r;
-          Qo[nt] = mfma(ta[tt].x, prow[0], Qo[nt]);
-          Qo[nt] = mfma(ta[tt].y, prow[LDP], Qo[nt]);
-          Qo[nt] = mfma(ta[tt].z, prow[2 * LDP], Qo[nt]);
-          Qo[nt] = mfma(ta[tt].w, prow[3 * LDP], Qo[nt]);
+          for (int nt = 0; nt < 4; ++nt) {
+            const float* prow = sP + (16 * tt + 4 * g) * LDP + 16 * nt + r;
+            Qo[nt] = mfma(ta[tt].x, prow[0], Qo[nt]);
+            Qo[nt] = mfma(ta[tt].y, prow[LDP], Qo[nt]);
+            Qo[nt] = mfma(ta[tt].z, prow[2 * LDP], Qo[nt]);
+            Qo[nt] = mfma(ta[tt].w, prow[3 * LDP], Qo[nt]);
+          }
+        EPOCH_GLOBAL float* out = gptr(pr.pre + (size_t)(child - N) * P * KP);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          float m = 0.f;
+#pragma unroll
+          for (int nt = 0; nt < 4; ++nt) m = fmaxf(m, Qo[nt][v]);
+          const int e = scale_exponent(row16_max(m));
+          const int p = p0 + 4 * g + v;
+          if (p < P)
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) out[(size_t)p * KP + 16 * nt + r] = ldexpf(Qo[nt][v], -e);
         }
-      EPOCH_GLOBAL float* out = gptr(pr.pre + (size_t)(child - N) * P * KP);
+      }
+      __syncthreads();  // t, L, w_p / L_p and tip columns of every wavefront are in LDS
+      // rows 16 w .. 16 w + 15 of dlogL/dP over the 64 patterns of the tile
+      const float* tcol = sT + WT * w + r;  // column i = 16 w + r of t
+#pragma unroll 8
+      for (int ks = 0; ks < TILE / 4; ++ks) {
+        const int pl = 4 * ks + g;  // pattern of the tile this lane feeds into k-step ks
+        const float av = tcol[pl * LDP] * sCF[pl];
+        f4 B;
+        if (Lc) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        float m = 0.f;
+          for (int nt = 0; nt < 4; ++nt) B[nt] = sL[pl * LDP + 16 * nt + r];
+        } else {
+          const int col = sCol[side][pl];
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) m = fmaxf(m, Qo[nt][v]);
-        const int e = scale_exponent(row16_max(m));
-        const int p = p0 + 4 * g + v;
-        if (p < P)
+          for (int nt = 0; nt < 4; ++nt) {
+            const int j = 16 * nt + r;
+            B[nt] = (col == j || (col == 64 && j < K)) ? 1.f : 0.f;
+          }
+        }
 #pragma unroll
-          for (int nt = 0; nt < 4; ++nt) out[(size_t)p * KP + 16 * nt + r] = ldexpf(Qo[nt][v], -e);
+        for (int nt = 0; nt < 4; ++nt) G[nt] = mfma(av, B[nt], G[nt]);
       }
     }
+    __syncthreads();  // the next tile overwrites t, L, w_p / L_p and tip columns
+    if (bt + 1 < n_tiles) cur = nxt;
   }
-  // Sum the four wavefronts' partials in a fixed order ((w0 + w2) + (w1 + w3))
-  // in LDS, then write this block's slot of each child branch.
-  __syncthreads();  // every wavefront is done with the staged matrices
-  float* red0 = sPa;
-  float* red1 = sPb;
+  // this wavefront's rows of the block's slot of each child branch
 #pragma unroll
   for (int side = 0; side < 2; ++side) {
     const int child = side == 0 ? a : b;
-    const f4(&G)[4][4] = side == 0 ? Ga : Gb;
-    float* mine = (w & 1) ? red1 : red0;
-    if (w < 2) {
+    const f4* G = side == 0 ? Ga : Gb;
+    EPOCH_GLOBAL float* dst = gptr(pr.Gpart + ((size_t)pr.gslots[pr.n_nodes + child] + blockIdx.x) * KK);
 #pragma unroll
-      for (int mt = 0; mt < 4; ++mt)
+    for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) mine[(16 * mt + 4 * g + v) * KP + 16 * nt + r] = G[mt][nt][v];
-    }
-    __syncthreads();
-    if (w >= 2) {
-#pragma unroll
-      for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) mine[(16 * mt + 4 * g + v) * KP + 16 * nt + r] += G[mt][nt][v];
-    }
-    __syncthreads();
-    EPOCH_GLOBAL f4* dst =
-        gptr(reinterpret_cast<f4*>(pr.Gpart + ((size_t)pr.gslots[pr.n_nodes + child] + blockIdx.x) * KK));
-    for (int e = threadIdx.x; e < KK / 4; e += 256)
-      dst[e] = reinterpret_cast<const f4*>(red0)[e] + reinterpret_cast<const f4*>(red1)[e];
-    __syncthreads();
+      for (int v = 0; v < 4; ++v) dst[(WT * w + 4 * g + v) * KP + 16 * nt + r] = G[nt][v];
   }
 }
 
