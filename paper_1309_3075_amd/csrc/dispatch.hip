@@ -34,10 +34,15 @@ int fastpath_tips_changed(EpochInstance*) { return EPOCH_OK; }
 int fastpath_tree_changed(EpochInstance* in) {
   if (codon(in)) return codon_prepare(in);
   if (!nuc(in) || !in->gslots.ptr) return EPOCH_OK;
-  std::vector<int32_t> slots;
+  std::vector<int32_t> slots, nodes;
   nuc_slots_per_node(in, slots);
-  int rc = hip_check(hipMemcpyAsync(in->gslots.ptr, slots.data(), slots.size() * sizeof(int32_t),
-                                    hipMemcpyHostToDevice, in->stream), "gslots upload");
+  nuc_pre_order_nodes(in, nodes, in->nuc_fuse);
+  int rc = ensure(in->nuc_nodes, std::max<size_t>(1, nodes.size()) * sizeof(int32_t));
+  if (!rc) rc = hip_check(hipMemcpyAsync(in->gslots.ptr, slots.data(), slots.size() * sizeof(int32_t),
+                                         hipMemcpyHostToDevice, in->stream), "gslots upload");
+  if (!rc && !nodes.empty())
+    rc = hip_check(hipMemcpyAsync(in->nuc_nodes.ptr, nodes.data(), nodes.size() * sizeof(int32_t),
+                                  hipMemcpyHostToDevice, in->stream), "pre-order node upload");
   if (rc) return rc;
   return hip_check(hipStreamSynchronize(in->stream), "gslots sync");
 }

@@ -302,7 +302,7 @@ int epoch_destroy(EpochInstance* in) {
                     &in->cat, &in->tree_i, &in->tree_d, &in->Pm, &in->dPm, &in->partials, &in->scales,
                     &in->pre, &in->site, &in->blocksum, &in->result, &in->Gpart, &in->G, &in->dbranch,
                     &in->qseg, &in->qscratch, &in->dQ, &in->seglist, &in->gslots, &in->codon_dev, &in->codon_aux,
-                    &in->eigTT, &in->eig64T, &in->qtau})
+                    &in->eigTT, &in->eig64T, &in->qtau, &in->nuc_nodes})
     release(*b);
   delete in;
   return EPOCH_OK;

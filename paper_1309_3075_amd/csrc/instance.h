@@ -100,6 +100,8 @@ struct EpochInstance {
   int path = 0;        // 0 generic, 1 four-state kernels, 2 64-state MFMA kernels
   int nuc_rmin = 8;    // minimum pattern tiles per wavefront in the four-state gradient
   int nuc_slots = 1;   // partial-sum slots per branch of the four-state gradient
+  std::vector<int> nuc_fuse;   // per level: pre-order nodes with a cherry child (listed first in nuc_nodes)
+  epochlik::DevBuf nuc_nodes;  // int32 [N-1]: level order of the four-state pre-order launches
 
   // device buffers (compute type T unless noted)
   epochlik::DevBuf eigT;       // V[S][Kp][Kp], Vinv[S][Kp][Kp], lre[S][Kp], lim[S][Kp]
@@ -189,6 +191,7 @@ int launch_nuc_post(EpochInstance* in);
 int launch_nuc_root(EpochInstance* in);
 int launch_nuc_pre_grad(EpochInstance* in);
 int nuc_slots(int P, int C, int rmin);
+void nuc_pre_order_nodes(const EpochInstance* in, std::vector<int32_t>& nodes, std::vector<int>& fuse);
 void nuc_slots_per_node(const EpochInstance* in, std::vector<int32_t>& out);
 
 // 64-state MFMA kernels (kernels_codon.hip)

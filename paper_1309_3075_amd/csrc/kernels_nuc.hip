@@ -408,11 +408,31 @@ __global__ __launch_bounds__(256) void nuc_root_kernel(
 }
 
 // ---------------------------------------------------------------------------
-template <typename T, int CP, int KA, int KB, bool ROOT>
+// Outer product of a cherry's tip branches.  At the cherry's parent the cherry's
+// outside vector q_c = P_c^T t_c is already in registers (unscaled: it shares the
+// scale of t_c and of the pattern likelihood l behind f), so the dlogL/dP of the
+// cherry's two tip branches is formed there, and q_c is never stored: its tip
+// children get f (q_c o S_other) (x) onehot(state).
+template <typename T>
+__device__ inline void cherry_tip_grads(const V4<T>& qc, const V4<T>& s1, const V4<T>& s2, int st1, int st2, T f,
+                                        T (&g1)[16], T (&g2)[16]) {
+  const V4<T> o1 = onehot<T>(st1), o2 = onehot<T>(st2);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const T f1 = f * qc.v[i] * s2.v[i], f2 = f * qc.v[i] * s1.v[i];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      g1[4 * i + j] += f1 * o1.v[j];
+      g2[4 * i + j] += f2 * o2.v[j];
+    }
+  }
+}
+
+template <typename T, int CP, int KA, int KB, bool ROOT, bool FUSE>
 __device__ inline void pre_tiles(const NucCtx<T>& x, int u, int a, int b, int first, int R, const M4<T>& Pa,
                                  const M4<T>& Pb, T wc, const V4<T>& qroot, const V4<T>* __restrict__ pre_in,
                                  V4<T>* __restrict__ pre_out, const T* __restrict__ weights, T (&ga)[16],
-                                 T (&gb)[16]) {
+                                 T (&gb)[16], T (&gx)[4][16]) {
   constexpr int TPW = 64 / CP;
   const int N = x.N, P = x.P, C = x.C, c = x.c;
   const bool cat_ok = x.cat_ok;
@@ -469,7 +489,11 @@ __device__ inline void pre_tiles(const NucCtx<T>& x, int u, int a, int b, int fi
         gb[4 * i + j] += fb * xb.v[j];
       }
     }
-    if constexpr (KA != kTip) {
+    if constexpr (FUSE && KA == kCherry) {
+      const V4<T> qa = matvec_t(Pa, ta);
+      cherry_tip_grads<T>(qa, x.sTip[(0 * 8 + c) * 5 + (ca.st1 < 4 ? ca.st1 : 4)],
+                          x.sTip[(1 * 8 + c) * 5 + (ca.st2 < 4 ? ca.st2 : 4)], ca.st1, ca.st2, f, gx[0], gx[1]);
+    } else if constexpr (KA != kTip) {
       V4<T> qa = matvec_t(Pa, ta);
       const T ma = group_max_cp<CP>(cat_ok ? max4(qa) : T(0));
       const int ea = scale_exponent(ma);
@@ -477,7 +501,11 @@ __device__ inline void pre_tiles(const NucCtx<T>& x, int u, int a, int b, int fi
       for (int i = 0; i < 4; ++i) qa.v[i] = scale_by_pow2(qa.v[i], ea);
       if (p < P && cat_ok) pre_out[((size_t)(a - N) * C + c) * P + p] = qa;
     }
-    if constexpr (KB != kTip) {
+    if constexpr (FUSE && KB == kCherry) {
+      const V4<T> qb = matvec_t(Pb, tb);
+      cherry_tip_grads<T>(qb, x.sTip[(2 * 8 + c) * 5 + (cb.st1 < 4 ? cb.st1 : 4)],
+                          x.sTip[(3 * 8 + c) * 5 + (cb.st2 < 4 ? cb.st2 : 4)], cb.st1, cb.st2, f, gx[2], gx[3]);
+    } else if constexpr (KB != kTip) {
       V4<T> qb = matvec_t(Pb, tb);
       const T mb = group_max_cp<CP>(cat_ok ? max4(qb) : T(0));
       const int eb = scale_exponent(mb);
@@ -492,25 +520,31 @@ __device__ inline void pre_tiles(const NucCtx<T>& x, int u, int a, int b, int fi
   }
 }
 
-template <typename T, int CP, bool ROOT>
+template <typename T, int CP, bool ROOT, bool FUSE>
 __device__ inline void pre_dispatch_kind(const NucCtx<T>& x, int ka, int kb, int u, int a, int b, int first, int R,
                                          const M4<T>& Pa, const M4<T>& Pb, T wc, const V4<T>& qroot,
                                          const V4<T>* __restrict__ pre_in, V4<T>* __restrict__ pre_out,
-                                         const T* __restrict__ weights, T (&ga)[16], T (&gb)[16]) {
-#define EPOCH_PRE_CASE(A, B)                                                                              \
-  if (ka == A && kb == B)                                                                                 \
-    return pre_tiles<T, CP, A, B, ROOT>(x, u, a, b, first, R, Pa, Pb, wc, qroot, pre_in, pre_out, weights, \
-                                        ga, gb)
-  EPOCH_PRE_CASE(kTip, kTip);
-  EPOCH_PRE_CASE(kTip, kInternal);
-  EPOCH_PRE_CASE(kTip, kCherry);
-  EPOCH_PRE_CASE(kInternal, kInternal);
-  EPOCH_PRE_CASE(kInternal, kCherry);
-  EPOCH_PRE_CASE(kCherry, kCherry);
+                                         const T* __restrict__ weights, T (&ga)[16], T (&gb)[16], T (&gx)[4][16]) {
+#define EPOCH_PRE_CASE(A, B)                                                                                    \
+  if (ka == A && kb == B)                                                                                       \
+    return pre_tiles<T, CP, A, B, ROOT, FUSE>(x, u, a, b, first, R, Pa, Pb, wc, qroot, pre_in, pre_out, weights, \
+                                              ga, gb, gx)
+  if constexpr (FUSE) {  // nodes with at least one cherry child
+    EPOCH_PRE_CASE(kTip, kCherry);
+    EPOCH_PRE_CASE(kInternal, kCherry);
+    EPOCH_PRE_CASE(kCherry, kCherry);
+  } else {
+    EPOCH_PRE_CASE(kTip, kTip);
+    EPOCH_PRE_CASE(kTip, kInternal);
+    EPOCH_PRE_CASE(kInternal, kInternal);
+  }
 #undef EPOCH_PRE_CASE
 }
 
-template <typename T, int CP>
+// FUSE: every node of the launch has at least one cherry child, whose tip
+// branches' dlogL/dP is formed here (see cherry_tip_grads); otherwise no node of
+// the launch has a cherry child.
+template <typename T, int CP, bool FUSE>
 __global__ __launch_bounds__(256) void nuc_pre_level_kernel(
     const int32_t* __restrict__ nodes, const int32_t* __restrict__ left, const int32_t* __restrict__ right,
     const T* __restrict__ Pm, const uint8_t* __restrict__ tips, const V4<T>* __restrict__ part,
@@ -518,7 +552,8 @@ __global__ __launch_bounds__(256) void nuc_pre_level_kernel(
     const double* __restrict__ cat, const T* __restrict__ weights, int root, int N, int P, int C, int R,
     int n_slots, double* __restrict__ Gpart) {
   constexpr int TPW = 64 / CP;
-  __shared__ T sG[4][2][CP][16];
+  constexpr int NG = FUSE ? 6 : 2;  // branches receiving dlogL/dP from this block
+  __shared__ T sG[4][NG][CP][16];
   __shared__ V4<T> sTip[4 * 8 * 5];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -535,10 +570,13 @@ __global__ __launch_bounds__(256) void nuc_pre_level_kernel(
   stage_cherry_tips<T>(sTip, Pm, left, right, N, C, a, b, ka == kCherry, kb == kCherry);
   __syncthreads();
   T ga[16], gb[16];
+  T gx[4][16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
     ga[k] = 0;
     gb[k] = 0;
+#pragma unroll
+    for (int h = 0; h < 4; ++h) gx[h][k] = 0;
   }
   const int first = (blockIdx.x * 4 + wave) * R * TPW;
   if (first < P) {  // uniform across the wavefront
@@ -550,38 +588,47 @@ __global__ __launch_bounds__(256) void nuc_pre_level_kernel(
     for (int i = 0; i < 4; ++i) qroot.v[i] = T(pi[i]);
     const NucCtx<T> x{N, P, C, c, cl, cat_ok, tips, part, nullptr, left, right, sTip};
     if (u == root)
-      pre_dispatch_kind<T, CP, true>(x, ka, kb, u, a, b, first, R, Pa, Pb, wc, qroot, pre_in, pre_out, weights, ga, gb);
+      pre_dispatch_kind<T, CP, true, FUSE>(x, ka, kb, u, a, b, first, R, Pa, Pb, wc, qroot, pre_in, pre_out, weights,
+                                           ga, gb, gx);
     else
-      pre_dispatch_kind<T, CP, false>(x, ka, kb, u, a, b, first, R, Pa, Pb, wc, qroot, pre_in, pre_out, weights, ga, gb);
+      pre_dispatch_kind<T, CP, false, FUSE>(x, ka, kb, u, a, b, first, R, Pa, Pb, wc, qroot, pre_in, pre_out, weights,
+                                            ga, gb, gx);
   }
   // wavefront reduce-scatter, then the four wavefronts of the block in order
-  T ra[2], rb[2];
-  reduce16<CP>(ga, lane, ra);
-  reduce16<CP>(gb, lane, rb);
-  if constexpr (CP == 8) {
-    const int e0 = 2 * ((lane >> 3) & 7);
-    sG[wave][0][cl][e0] = ra[0];
-    sG[wave][0][cl][e0 + 1] = ra[1];
-    sG[wave][1][cl][e0] = rb[0];
-    sG[wave][1][cl][e0 + 1] = rb[1];
-  } else {
-    // the halving steps run over lane bits 5..2, so lane l holds element
-    // (l >> 2) & 15; lane bits below 2 that are pattern bits were summed and
-    // replicate it: only the lane with those bits clear stores
-    const int e = (lane >> 2) & 15;
-    if ((lane & 3 & ~(CP - 1)) == 0) {
-      sG[wave][0][cl][e] = ra[0];
-      sG[wave][1][cl][e] = rb[0];
+  auto scatter = [&](T (&g)[16], int side) {
+    T rg[2];
+    reduce16<CP>(g, lane, rg);
+    if constexpr (CP == 8) {
+      const int e0 = 2 * ((lane >> 3) & 7);
+      sG[wave][side][cl][e0] = rg[0];
+      sG[wave][side][cl][e0 + 1] = rg[1];
+    } else {
+      // the halving steps run over lane bits 5..2, so lane l holds element
+      // (l >> 2) & 15; lane bits below 2 that are pattern bits were summed and
+      // replicate it: only the lane with those bits clear stores
+      const int e = (lane >> 2) & 15;
+      if ((lane & 3 & ~(CP - 1)) == 0) sG[wave][side][cl][e] = rg[0];
     }
+  };
+  scatter(ga, 0);
+  scatter(gb, 1);
+  if constexpr (FUSE) {
+#pragma unroll
+    for (int h = 0; h < 4; ++h) scatter(gx[h], 2 + h);
   }
   __syncthreads();
-  if (threadIdx.x < 2 * CP * 16) {
-    const int side = threadIdx.x / (CP * 16);
-    const int rem = threadIdx.x % (CP * 16);
+  for (int t = threadIdx.x; t < NG * CP * 16; t += 256) {
+    const int side = t / (CP * 16);
+    const int rem = t % (CP * 16);
     const int cc = rem / 16, e = rem % 16;
+    int v = side == 0 ? a : b;
+    if (side >= 2) {
+      const int owner = side < 4 ? a : b;
+      if ((side < 4 ? ka : kb) != kCherry) continue;
+      v = (side & 1) ? right[owner] : left[owner];
+    }
     if (cc < C) {
       const T s = ((sG[0][side][cc][e] + sG[1][side][cc][e]) + sG[2][side][cc][e]) + sG[3][side][cc][e];
-      const int v = side == 0 ? a : b;
       Gpart[((size_t)v * n_slots + blockIdx.x) * ((size_t)C * 16) + cc * 16 + e] = (double)s;
     }
   }
@@ -657,15 +704,27 @@ int pre_dispatch_cp(EpochInstance* in) {
   const V4<T>* part = static_cast<const V4<T>*>(in->partials.ptr);
   V4<T>* pre = static_cast<V4<T>*>(in->pre.ptr);
   const T* w = static_cast<const T*>(in->weightsT.ptr);
-  for (int l = pl.n_levels; l >= 1; --l) {
+  const int32_t* nodes = static_cast<const int32_t*>(in->nuc_nodes.ptr);
+  // level 1 holds exactly the cherries, whose tip branches are handled by their
+  // parents; it is launched only when the root itself is a cherry
+  const int lowest = pl.n_levels == 1 ? 1 : 2;
+  for (int l = pl.n_levels; l >= lowest; --l) {
     const int n_l = pl.level_offset[l + 1] - pl.level_offset[l];
     if (!n_l) continue;
     const int R = tiles_per_wave(tiles, n_l, in->nuc_rmin, 64);
     const int blocks = pre_blocks(in, n_l);
-    hipLaunchKernelGGL((nuc_pre_level_kernel<T, CP>), dim3(blocks, n_l), dim3(256), 0, in->stream,
-                       in->d_level_nodes + pl.level_offset[l], in->d_left, in->d_right, Pm, tips, part, pre, pre,
-                       static_cast<const double*>(in->pi.ptr), static_cast<const double*>(in->cat.ptr), w,
-                       pl.root, in->N, in->P, in->C, R, in->nuc_slots, static_cast<double*>(in->Gpart.ptr));
+    const int nf = in->nuc_fuse[l];  // nodes of the level with a cherry child come first
+    const int32_t* lv = nodes + pl.level_offset[l];
+    if (nf > 0)
+      hipLaunchKernelGGL((nuc_pre_level_kernel<T, CP, true>), dim3(blocks, nf), dim3(256), 0, in->stream, lv,
+                         in->d_left, in->d_right, Pm, tips, part, pre, pre, static_cast<const double*>(in->pi.ptr),
+                         static_cast<const double*>(in->cat.ptr), w, pl.root, in->N, in->P, in->C, R, in->nuc_slots,
+                         static_cast<double*>(in->Gpart.ptr));
+    if (n_l > nf)
+      hipLaunchKernelGGL((nuc_pre_level_kernel<T, CP, false>), dim3(blocks, n_l - nf), dim3(256), 0, in->stream,
+                         lv + nf, in->d_left, in->d_right, Pm, tips, part, pre, pre,
+                         static_cast<const double*>(in->pi.ptr), static_cast<const double*>(in->cat.ptr), w, pl.root,
+                         in->N, in->P, in->C, R, in->nuc_slots, static_cast<double*>(in->Gpart.ptr));
   }
   return hip_check(hipGetLastError(), "nuc_pre_level launch");
 }
@@ -680,20 +739,48 @@ int nuc_slots(int P, int C, int rmin) {
   return (tiles + 4 * rmin - 1) / (4 * rmin);
 }
 
-// Number of partial-sum slots each branch receives from the gradient pass
-// (the block count of its parent's level), host [n_nodes].
+// Number of partial-sum slots each branch receives from the gradient pass, host
+// [n_nodes]: the block count of the level that forms its dlogL/dP (its parent's,
+// or its grandparent's for the tip children of a cherry).
 void nuc_slots_per_node(const EpochInstance* in, std::vector<int32_t>& out) {
   const auto& pl = in->plan;
+  const int N = in->N;
   out.assign(in->n_nodes, 0);
-  for (int l = 1; l <= pl.n_levels; ++l) {
+  const int lowest = pl.n_levels == 1 ? 1 : 2;
+  for (int l = lowest; l <= pl.n_levels; ++l) {
     const int n_l = pl.level_offset[l + 1] - pl.level_offset[l];
     if (!n_l) continue;
     const int blocks = pre_blocks(in, n_l);
     for (int k = pl.level_offset[l]; k < pl.level_offset[l + 1]; ++k) {
       const int u = pl.level_nodes[k];
-      out[pl.left[u]] = blocks;
-      out[pl.right[u]] = blocks;
+      for (int child : {pl.left[u], pl.right[u]}) {
+        out[child] = blocks;
+        if (l > 1 && child >= N && pl.left[child] < N && pl.right[child] < N) {
+          out[pl.left[child]] = blocks;
+          out[pl.right[child]] = blocks;
+        }
+      }
     }
+  }
+}
+
+// Level order of the pre-order launches: within each level, the nodes with a
+// cherry child first (host [N-1] and the count per level).
+void nuc_pre_order_nodes(const EpochInstance* in, std::vector<int32_t>& nodes, std::vector<int>& fuse) {
+  const auto& pl = in->plan;
+  const int N = in->N;
+  nodes.assign(pl.level_nodes.begin(), pl.level_nodes.end());
+  fuse.assign(pl.n_levels + 2, 0);
+  auto is_cherry = [&](int v) { return v >= N && pl.left[v] < N && pl.right[v] < N; };
+  for (int l = 1; l <= pl.n_levels; ++l) {
+    std::vector<int32_t> with, without;
+    for (int k = pl.level_offset[l]; k < pl.level_offset[l + 1]; ++k) {
+      const int u = pl.level_nodes[k];
+      (l > 1 && (is_cherry(pl.left[u]) || is_cherry(pl.right[u])) ? with : without).push_back(u);
+    }
+    fuse[l] = (int)with.size();
+    std::copy(with.begin(), with.end(), nodes.begin() + pl.level_offset[l]);
+    std::copy(without.begin(), without.end(), nodes.begin() + pl.level_offset[l] + with.size());
   }
 }
 
