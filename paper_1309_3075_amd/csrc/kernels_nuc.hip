@@ -428,11 +428,13 @@ __device__ inline void cherry_tip_grads(const V4<T>& qc, const V4<T>& s1, const 
   }
 }
 
-template <typename T, int CP, int KA, int KB, bool ROOT, bool FUSE>
+// NX: cherry children of the node (0, 1 = the second child after the canonical
+// order, 2 = both); gx holds their tip branches' accumulators, 2 per cherry.
+template <typename T, int CP, int KA, int KB, bool ROOT, int NX>
 __device__ inline void pre_tiles(const NucCtx<T>& x, int u, int a, int b, int first, int R, const M4<T>& Pa,
                                  const M4<T>& Pb, T wc, const V4<T>& qroot, const V4<T>* __restrict__ pre_in,
                                  V4<T>* __restrict__ pre_out, const T* __restrict__ weights, T (&ga)[16],
-                                 T (&gb)[16], T (&gx)[4][16]) {
+                                 T (&gb)[16], T (&gx)[2 * NX + (NX == 0)][16]) {
   constexpr int TPW = 64 / CP;
   const int N = x.N, P = x.P, C = x.C, c = x.c;
   const bool cat_ok = x.cat_ok;
@@ -489,7 +491,7 @@ __device__ inline void pre_tiles(const NucCtx<T>& x, int u, int a, int b, int fi
         gb[4 * i + j] += fb * xb.v[j];
       }
     }
-    if constexpr (FUSE && KA == kCherry) {
+    if constexpr (NX == 2 && KA == kCherry) {
       const V4<T> qa = matvec_t(Pa, ta);
       cherry_tip_grads<T>(qa, x.sTip[(0 * 8 + c) * 5 + (ca.st1 < 4 ? ca.st1 : 4)],
                           x.sTip[(1 * 8 + c) * 5 + (ca.st2 < 4 ? ca.st2 : 4)], ca.st1, ca.st2, f, gx[0], gx[1]);
@@ -501,10 +503,11 @@ __device__ inline void pre_tiles(const NucCtx<T>& x, int u, int a, int b, int fi
       for (int i = 0; i < 4; ++i) qa.v[i] = scale_by_pow2(qa.v[i], ea);
       if (p < P && cat_ok) pre_out[((size_t)(a - N) * C + c) * P + p] = qa;
     }
-    if constexpr (FUSE && KB == kCherry) {
+    if constexpr (NX >= 1 && KB == kCherry) {
+      constexpr int h = NX == 2 ? 2 : 0;
       const V4<T> qb = matvec_t(Pb, tb);
       cherry_tip_grads<T>(qb, x.sTip[(2 * 8 + c) * 5 + (cb.st1 < 4 ? cb.st1 : 4)],
-                          x.sTip[(3 * 8 + c) * 5 + (cb.st2 < 4 ? cb.st2 : 4)], cb.st1, cb.st2, f, gx[2], gx[3]);
+                          x.sTip[(3 * 8 + c) * 5 + (cb.st2 < 4 ? cb.st2 : 4)], cb.st1, cb.st2, f, gx[h], gx[h + 1]);
     } else if constexpr (KB != kTip) {
       V4<T> qb = matvec_t(Pb, tb);
       const T mb = group_max_cp<CP>(cat_ok ? max4(qb) : T(0));
@@ -520,19 +523,21 @@ __device__ inline void pre_tiles(const NucCtx<T>& x, int u, int a, int b, int fi
   }
 }
 
-template <typename T, int CP, bool ROOT, bool FUSE>
+template <typename T, int CP, bool ROOT, int NX>
 __device__ inline void pre_dispatch_kind(const NucCtx<T>& x, int ka, int kb, int u, int a, int b, int first, int R,
                                          const M4<T>& Pa, const M4<T>& Pb, T wc, const V4<T>& qroot,
                                          const V4<T>* __restrict__ pre_in, V4<T>* __restrict__ pre_out,
-                                         const T* __restrict__ weights, T (&ga)[16], T (&gb)[16], T (&gx)[4][16]) {
-#define EPOCH_PRE_CASE(A, B)                                                                                    \
-  if (ka == A && kb == B)                                                                                       \
-    return pre_tiles<T, CP, A, B, ROOT, FUSE>(x, u, a, b, first, R, Pa, Pb, wc, qroot, pre_in, pre_out, weights, \
-                                              ga, gb, gx)
-  if constexpr (FUSE) {  // nodes with at least one cherry child
+                                         const T* __restrict__ weights, T (&ga)[16], T (&gb)[16],
+                                         T (&gx)[2 * NX + (NX == 0)][16]) {
+#define EPOCH_PRE_CASE(A, B)                                                                                  \
+  if (ka == A && kb == B)                                                                                     \
+    return pre_tiles<T, CP, A, B, ROOT, NX>(x, u, a, b, first, R, Pa, Pb, wc, qroot, pre_in, pre_out, weights, \
+                                            ga, gb, gx)
+  if constexpr (NX == 2) {
+    EPOCH_PRE_CASE(kCherry, kCherry);
+  } else if constexpr (NX == 1) {
     EPOCH_PRE_CASE(kTip, kCherry);
     EPOCH_PRE_CASE(kInternal, kCherry);
-    EPOCH_PRE_CASE(kCherry, kCherry);
   } else {
     EPOCH_PRE_CASE(kTip, kTip);
     EPOCH_PRE_CASE(kTip, kInternal);
@@ -541,10 +546,9 @@ __device__ inline void pre_dispatch_kind(const NucCtx<T>& x, int ka, int kb, int
 #undef EPOCH_PRE_CASE
 }
 
-// FUSE: every node of the launch has at least one cherry child, whose tip
-// branches' dlogL/dP is formed here (see cherry_tip_grads); otherwise no node of
-// the launch has a cherry child.
-template <typename T, int CP, bool FUSE>
+// NX: every node of the launch has exactly NX cherry children, whose tip
+// branches' dlogL/dP is formed here (see cherry_tip_grads).
+template <typename T, int CP, int NX>
 __global__ __launch_bounds__(256) void nuc_pre_level_kernel(
     const int32_t* __restrict__ nodes, const int32_t* __restrict__ left, const int32_t* __restrict__ right,
     const T* __restrict__ Pm, const uint8_t* __restrict__ tips, const V4<T>* __restrict__ part,
@@ -552,7 +556,7 @@ __global__ __launch_bounds__(256) void nuc_pre_level_kernel(
     const double* __restrict__ cat, const T* __restrict__ weights, int root, int N, int P, int C, int R,
     int n_slots, double* __restrict__ Gpart) {
   constexpr int TPW = 64 / CP;
-  constexpr int NG = FUSE ? 6 : 2;  // branches receiving dlogL/dP from this block
+  constexpr int NG = 2 + 2 * NX;  // branches receiving dlogL/dP from this block
   __shared__ T sG[4][NG][CP][16];
   __shared__ V4<T> sTip[4 * 8 * 5];
   const int lane = threadIdx.x & 63;
@@ -570,13 +574,13 @@ __global__ __launch_bounds__(256) void nuc_pre_level_kernel(
   stage_cherry_tips<T>(sTip, Pm, left, right, N, C, a, b, ka == kCherry, kb == kCherry);
   __syncthreads();
   T ga[16], gb[16];
-  T gx[4][16];
+  T gx[2 * NX + (NX == 0)][16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
     ga[k] = 0;
     gb[k] = 0;
 #pragma unroll
-    for (int h = 0; h < 4; ++h) gx[h][k] = 0;
+    for (int h = 0; h < 2 * NX + (NX == 0); ++h) gx[h][k] = 0;
   }
   const int first = (blockIdx.x * 4 + wave) * R * TPW;
   if (first < P) {  // uniform across the wavefront
@@ -588,11 +592,11 @@ __global__ __launch_bounds__(256) void nuc_pre_level_kernel(
     for (int i = 0; i < 4; ++i) qroot.v[i] = T(pi[i]);
     const NucCtx<T> x{N, P, C, c, cl, cat_ok, tips, part, nullptr, left, right, sTip};
     if (u == root)
-      pre_dispatch_kind<T, CP, true, FUSE>(x, ka, kb, u, a, b, first, R, Pa, Pb, wc, qroot, pre_in, pre_out, weights,
-                                           ga, gb, gx);
+      pre_dispatch_kind<T, CP, true, NX>(x, ka, kb, u, a, b, first, R, Pa, Pb, wc, qroot, pre_in, pre_out, weights,
+                                         ga, gb, gx);
     else
-      pre_dispatch_kind<T, CP, false, FUSE>(x, ka, kb, u, a, b, first, R, Pa, Pb, wc, qroot, pre_in, pre_out, weights,
-                                            ga, gb, gx);
+      pre_dispatch_kind<T, CP, false, NX>(x, ka, kb, u, a, b, first, R, Pa, Pb, wc, qroot, pre_in, pre_out, weights,
+                                          ga, gb, gx);
   }
   // wavefront reduce-scatter, then the four wavefronts of the block in order
   auto scatter = [&](T (&g)[16], int side) {
@@ -612,19 +616,16 @@ __global__ __launch_bounds__(256) void nuc_pre_level_kernel(
   };
   scatter(ga, 0);
   scatter(gb, 1);
-  if constexpr (FUSE) {
 #pragma unroll
-    for (int h = 0; h < 4; ++h) scatter(gx[h], 2 + h);
-  }
+  for (int h = 0; h < 2 * NX; ++h) scatter(gx[h], 2 + h);
   __syncthreads();
   for (int t = threadIdx.x; t < NG * CP * 16; t += 256) {
     const int side = t / (CP * 16);
     const int rem = t % (CP * 16);
     const int cc = rem / 16, e = rem % 16;
     int v = side == 0 ? a : b;
-    if (side >= 2) {
-      const int owner = side < 4 ? a : b;
-      if ((side < 4 ? ka : kb) != kCherry) continue;
+    if (side >= 2) {  // tip children of the cherry children (b's when NX == 1)
+      const int owner = (NX == 2 && side < 4) ? a : b;
       v = (side & 1) ? right[owner] : left[owner];
     }
     if (cc < C) {
@@ -713,18 +714,19 @@ int pre_dispatch_cp(EpochInstance* in) {
     if (!n_l) continue;
     const int R = tiles_per_wave(tiles, n_l, in->nuc_rmin, 64);
     const int blocks = pre_blocks(in, n_l);
-    const int nf = in->nuc_fuse[l];  // nodes of the level with a cherry child come first
+    // nodes with two cherry children first, then one, then none
+    const int n2 = in->nuc_fuse[2 * l], n1 = in->nuc_fuse[2 * l + 1];
     const int32_t* lv = nodes + pl.level_offset[l];
-    if (nf > 0)
-      hipLaunchKernelGGL((nuc_pre_level_kernel<T, CP, true>), dim3(blocks, nf), dim3(256), 0, in->stream, lv,
-                         in->d_left, in->d_right, Pm, tips, part, pre, pre, static_cast<const double*>(in->pi.ptr),
-                         static_cast<const double*>(in->cat.ptr), w, pl.root, in->N, in->P, in->C, R, in->nuc_slots,
-                         static_cast<double*>(in->Gpart.ptr));
-    if (n_l > nf)
-      hipLaunchKernelGGL((nuc_pre_level_kernel<T, CP, false>), dim3(blocks, n_l - nf), dim3(256), 0, in->stream,
-                         lv + nf, in->d_left, in->d_right, Pm, tips, part, pre, pre,
-                         static_cast<const double*>(in->pi.ptr), static_cast<const double*>(in->cat.ptr), w, pl.root,
-                         in->N, in->P, in->C, R, in->nuc_slots, static_cast<double*>(in->Gpart.ptr));
+#define EPOCH_PRE_LAUNCH(NXV, first_node, count)                                                              \
+  if ((count) > 0)                                                                                           \
+    hipLaunchKernelGGL((nuc_pre_level_kernel<T, CP, NXV>), dim3(blocks, (count)), dim3(256), 0, in->stream,  \
+                       lv + (first_node), in->d_left, in->d_right, Pm, tips, part, pre, pre,                  \
+                       static_cast<const double*>(in->pi.ptr), static_cast<const double*>(in->cat.ptr), w,   \
+                       pl.root, in->N, in->P, in->C, R, in->nuc_slots, static_cast<double*>(in->Gpart.ptr))
+    EPOCH_PRE_LAUNCH(2, 0, n2);
+    EPOCH_PRE_LAUNCH(1, n2, n1);
+    EPOCH_PRE_LAUNCH(0, n2 + n1, n_l - n2 - n1);
+#undef EPOCH_PRE_LAUNCH
   }
   return hip_check(hipGetLastError(), "nuc_pre_level launch");
 }
@@ -764,23 +766,26 @@ void nuc_slots_per_node(const EpochInstance* in, std::vector<int32_t>& out) {
   }
 }
 
-// Level order of the pre-order launches: within each level, the nodes with a
-// cherry child first (host [N-1] and the count per level).
+// Level order of the pre-order launches: within each level, the nodes with two
+// cherry children, then those with one, then the rest (host [N-1]; fuse[2 l]
+// and fuse[2 l + 1] count the first two groups of level l).
 void nuc_pre_order_nodes(const EpochInstance* in, std::vector<int32_t>& nodes, std::vector<int>& fuse) {
   const auto& pl = in->plan;
   const int N = in->N;
   nodes.assign(pl.level_nodes.begin(), pl.level_nodes.end());
-  fuse.assign(pl.n_levels + 2, 0);
+  fuse.assign(2 * (pl.n_levels + 2), 0);
   auto is_cherry = [&](int v) { return v >= N && pl.left[v] < N && pl.right[v] < N; };
   for (int l = 1; l <= pl.n_levels; ++l) {
-    std::vector<int32_t> with, without;
+    std::vector<int32_t> group[3];
     for (int k = pl.level_offset[l]; k < pl.level_offset[l + 1]; ++k) {
       const int u = pl.level_nodes[k];
-      (l > 1 && (is_cherry(pl.left[u]) || is_cherry(pl.right[u])) ? with : without).push_back(u);
+      const int nc = l > 1 ? (int)is_cherry(pl.left[u]) + (int)is_cherry(pl.right[u]) : 0;
+      group[2 - nc].push_back(u);
     }
-    fuse[l] = (int)with.size();
-    std::copy(with.begin(), with.end(), nodes.begin() + pl.level_offset[l]);
-    std::copy(without.begin(), without.end(), nodes.begin() + pl.level_offset[l] + with.size());
+    fuse[2 * l] = (int)group[0].size();
+    fuse[2 * l + 1] = (int)group[1].size();
+    auto dst = nodes.begin() + pl.level_offset[l];
+    for (auto& gr : group) dst = std::copy(gr.begin(), gr.end(), dst);
   }
 }
 
