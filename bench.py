@@ -215,10 +215,8 @@ def main():
                        use_pi=args.config != 4)
 
     def step():
-        lik.update_transition_matrices()
-        lik.update_partials()
-        lL = lik.root_log_likelihood()
-        db, dq = lik.gradient(branch=True, Q=want_Q)
+        # the whole path (P stage, pruning, root log-likelihood, gradients) with one host sync
+        lL, _, db, dq = lik.evaluate(branch=True, Q=want_Q)
         return lL, db, dq
 
     for _ in range(args.warmup):

@@ -166,6 +166,25 @@ int root_log_likelihood(EpochInstance* inst, double* logL, double* site_logL);
  * Requires root_log_likelihood for the current state. */
 int log_likelihood_gradient(EpochInstance* inst, double* d_branch, double* d_Q);
 
+/* One whole evaluation with a single host synchronisation: the transition
+ * matrices (Eq. 3, 6, 7), the post-order partials (Eq. 4), the root
+ * log-likelihood and, on request, the gradients, enqueued back to back on the
+ * instance's stream; equivalent to update_transition_matrices, update_partials,
+ * root_log_likelihood and log_likelihood_gradient in turn, without the host
+ * round trip between the log-likelihood and the gradient pass.
+ *   what: EPOCH_EVAL_* bits (the log-likelihood is always computed).
+ *   logL: host out; site_logL: host [P] out or NULL;
+ *   d_branch, d_Q: host outs as in log_likelihood_gradient, required when
+ *     EPOCH_EVAL_GRAD_BRANCH / EPOCH_EVAL_GRAD_Q are set (ignored otherwise).
+ * Needs every input set (as the separate calls do) and the instance flags for
+ * the requested gradients (EPOCH_ERR_STATE otherwise).  A non-finite logL
+ * returns EPOCH_ERR_NUMERIC after the outputs are written. */
+#define EPOCH_EVAL_LOGL 0x1u
+#define EPOCH_EVAL_GRAD_BRANCH 0x2u
+#define EPOCH_EVAL_GRAD_Q 0x4u
+int epoch_evaluate(EpochInstance* inst, uint32_t what, double* logL, double* site_logL, double* d_branch,
+                   double* d_Q);
+
 /* Read back the transition matrices: host [2N-1][C][K][K] doubles (row-major,
  * entry v = branch above node v; root block left as zeros).  Requires
  * update_transition_matrices. */
@@ -194,9 +213,6 @@ int epoch_get_timing(EpochInstance* inst, double* ms_out, int64_t* counts_out);
  * launch shape per device and batch shape; it is read, and written after
  * tuning on the first evaluation. */
 typedef struct EpochBatch EpochBatch;
-#define EPOCH_EVAL_LOGL 0x1u
-#define EPOCH_EVAL_GRAD_BRANCH 0x2u
-#define EPOCH_EVAL_GRAD_Q 0x4u
 int epoch_batch_create(EpochInstance* const* insts, int32_t n, const char* tune_cache_path, EpochBatch** out);
 
 /* Evaluate every member: logL: host [n] out.  what: EPOCH_EVAL_* bits (logL

@@ -34,7 +34,7 @@ EXPORTED = [
     "epoch_last_error", "epoch_version", "epoch_create", "epoch_destroy", "epoch_set_tip_states",
     "epoch_set_pattern_weights", "epoch_set_categories", "epoch_set_root_frequencies",
     "set_epoch_eigensystems", "set_tree_epochs", "update_transition_matrices", "update_partials",
-    "root_log_likelihood", "log_likelihood_gradient", "epoch_get_transition_matrices",
+    "root_log_likelihood", "log_likelihood_gradient", "epoch_evaluate", "epoch_get_transition_matrices",
     "epoch_plan_segments", "epoch_set_timing", "epoch_get_timing", "epoch_bandwidth_probe",
     "epoch_batch_create", "epoch_batch_evaluate", "epoch_batch_gradients", "epoch_batch_target_blocks",
     "epoch_batch_destroy",
@@ -100,6 +100,7 @@ def load() -> ctypes.CDLL:
         "update_partials": (i32, [P]),
         "root_log_likelihood": (i32, [P, dp, dp]),
         "log_likelihood_gradient": (i32, [P, dp, dp]),
+        "epoch_evaluate": (i32, [P, u32, dp, dp, dp, dp]),
         "epoch_get_transition_matrices": (i32, [P, dp]),
         "epoch_plan_segments": (i32, [i32, ip, dp, i32, dp, ip, i32, i32, ip, ip, dp, ip]),
         "epoch_set_timing": (i32, [P, i32]),

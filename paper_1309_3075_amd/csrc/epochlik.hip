@@ -645,6 +645,47 @@ int log_likelihood_gradient(EpochInstance* in, double* d_branch, double* d_Q) {
   return EPOCH_OK;
 }
 
+int epoch_evaluate(EpochInstance* in, uint32_t what, double* logL, double* site_logL, double* d_branch,
+                   double* d_Q) {
+  if (!in || !logL) return set_error(EPOCH_ERR_ARG, "instance and logL must not be NULL");
+  if (what & ~(EPOCH_EVAL_LOGL | EPOCH_EVAL_GRAD_BRANCH | EPOCH_EVAL_GRAD_Q))
+    return set_error(EPOCH_ERR_ARG, "unknown evaluation flags");
+  const bool gb = (what & EPOCH_EVAL_GRAD_BRANCH) != 0, gq = (what & EPOCH_EVAL_GRAD_Q) != 0;
+  if (gb && !d_branch) return set_error(EPOCH_ERR_ARG, "d_branch must not be NULL with EPOCH_EVAL_GRAD_BRANCH");
+  if (gq && !d_Q) return set_error(EPOCH_ERR_ARG, "d_Q must not be NULL with EPOCH_EVAL_GRAD_Q");
+  if (gb && !(in->cfg.flags & EPOCH_GRAD_BRANCH))
+    return set_error(EPOCH_ERR_STATE, "instance created without EPOCH_GRAD_BRANCH");
+  if (gq && !(in->cfg.flags & EPOCH_GRAD_Q)) return set_error(EPOCH_ERR_STATE, "instance created without EPOCH_GRAD_Q");
+  if (!in->have_tree) return set_error(EPOCH_ERR_STATE, "set_tree_epochs has not been called");
+  if (!in->have_cats) return set_error(EPOCH_ERR_STATE, "epoch_set_categories has not been called");
+  for (int s = 0; s < in->S; ++s)
+    if (!in->have_eig[s]) return set_error(EPOCH_ERR_STATE, "eigensystem %d has not been set", s);
+  if (!in->have_tips) return set_error(EPOCH_ERR_STATE, "epoch_set_tip_states has not been called");
+  if (!in->have_weights) return set_error(EPOCH_ERR_STATE, "epoch_set_pattern_weights has not been called");
+  if (!in->have_pi) return set_error(EPOCH_ERR_STATE, "epoch_set_root_frequencies has not been called");
+  in->P_valid = in->partials_valid = in->logL_valid = false;
+  EPOCH_TRY(fastpath_pstage(in));
+  EPOCH_TRY(fastpath_post(in));
+  EPOCH_TRY(fastpath_root(in));
+  if (gb || gq) EPOCH_TRY(fastpath_gradient(in, gq));
+  EPOCH_TRY(hip_check(hipMemcpyAsync(logL, in->result.ptr, sizeof(double), hipMemcpyDeviceToHost, in->stream),
+                      "logL download"));
+  if (site_logL)
+    EPOCH_TRY(hip_check(hipMemcpyAsync(site_logL, in->site.ptr, (size_t)in->P * sizeof(double),
+                                       hipMemcpyDeviceToHost, in->stream), "site download"));
+  if (gb)
+    EPOCH_TRY(hip_check(hipMemcpyAsync(d_branch, in->dbranch.ptr, (size_t)in->n_nodes * sizeof(double),
+                                       hipMemcpyDeviceToHost, in->stream), "gradient download"));
+  if (gq)
+    EPOCH_TRY(hip_check(hipMemcpyAsync(d_Q, in->dQ.ptr, (size_t)in->S * in->K * in->K * sizeof(double),
+                                       hipMemcpyDeviceToHost, in->stream), "gradient download"));
+  EPOCH_TRY(hip_check(hipStreamSynchronize(in->stream), "evaluation sync"));
+  in->P_valid = in->partials_valid = true;
+  if (!std::isfinite(*logL)) return set_error(EPOCH_ERR_NUMERIC, "log-likelihood is not finite (%g)", *logL);
+  in->logL_valid = true;
+  return EPOCH_OK;
+}
+
 int epoch_get_transition_matrices(EpochInstance* in, double* out) {
   if (!in || !out) return set_error(EPOCH_ERR_ARG, "NULL argument");
   if (!in->P_valid) return set_error(EPOCH_ERR_STATE, "update_transition_matrices has not been called");

@@ -131,6 +131,18 @@ class EpochLikelihood:
         check(self._lib.log_likelihood_gradient(self._h, _dp(db), _dp(dq)))
         return db, dq
 
+    def evaluate(self, branch: bool = False, Q: bool = False, site: bool = False):
+        """One whole evaluation with one host synchronisation (epoch_evaluate):
+        returns (logL, site logL or None, dlogL/dl or None, dlogL/dQ or None)."""
+        out = ctypes.c_double(0.0)
+        s = np.zeros(self.n_patterns) if site else None
+        db = np.zeros(self.n_nodes) if branch else None
+        dq = np.zeros((self.n_processes, self.n_states, self.n_states)) if Q else None
+        what = _abi.EPOCH_EVAL_LOGL | (_abi.EPOCH_EVAL_GRAD_BRANCH if branch else 0) | \
+            (_abi.EPOCH_EVAL_GRAD_Q if Q else 0)
+        check(self._lib.epoch_evaluate(self._h, what, ctypes.byref(out), _dp(s), _dp(db), _dp(dq)))
+        return out.value, s, db, dq
+
     def transition_matrices(self):
         out = np.zeros((self.n_nodes, self.n_categories, self.n_states, self.n_states))
         check(self._lib.epoch_get_transition_matrices(self._h, _dp(out)))

@@ -271,3 +271,25 @@ def test_full_size_gradient_directional(config):
             vals.append(lik.log_likelihood())
     fd = (vals[0] - vals[1]) / (2 * h)
     assert abs(fd - float(np.dot(db, d))) <= 1e-6 * abs(fd) + 1e-9 * np.linalg.norm(db * d), (fd, np.dot(db, d))
+
+
+@pytest.mark.parametrize("case", [RANDOM_CASES[2], RANDOM_CASES[6], RANDOM_CASES[10]],
+                         ids=lambda c: f"K{c[2]}_n{c[1]}")
+def test_single_call_evaluation_matches_separate_calls(case):
+    """epoch_evaluate (one host synchronisation) gives the same bits as the four
+    separate calls, and its errors follow the same rules."""
+    prob = _prob(case)
+    with from_problem(prob, "fp32", grad_branch=True, grad_Q=True, use_pi=False) as lik:
+        lik.update_transition_matrices()
+        lik.update_partials()
+        logL, site = lik.root_log_likelihood(site=True)
+        db, dq = lik.gradient(branch=True, Q=True)
+        l2, s2, db2, dq2 = lik.evaluate(branch=True, Q=True, site=True)
+        l3, _, db3, dq3 = lik.evaluate()
+    assert l2 == logL and l3 == logL
+    assert np.array_equal(s2, site) and np.array_equal(db2, db) and np.array_equal(dq2, dq)
+    assert db3 is None and dq3 is None
+    with from_problem(prob, "fp32", grad_branch=True, use_pi=False) as lik:
+        with pytest.raises(_abi.EpochError) as e:
+            lik.evaluate(branch=True, Q=True)
+        assert e.value.code == _abi.EPOCH_ERR_STATE
