@@ -55,6 +55,7 @@ struct PStageDesc {
   const double* cat_rates;
   void* Pout;
   void* dPout;
+  void* Ubuf;   // or null: A_k V of every segment term, kept for the dlogL/dQ adjoint chain
   int n_items;  // nodes x categories
   int C;
   bool grad;

@@ -93,6 +93,13 @@ __device__ inline void pstage_stripe(const PStageDesc& pd, int gw, ColCoef<T>* c
 #pragma unroll
       for (int mt = 0; mt < NT; ++mt) y[b][mt] = acc{0, 0, 0, 0};
     stripe_gemm<T, NT, NB>(eigV + (size_t)s * KK, g, arow, xd, y);
+    if (pd.Ubuf) {
+      // A_k V (the running product times V before the column operator), the forward
+      // half of the dlogL/dQ adjoint chain
+      T* U = static_cast<T*>(pd.Ubuf) + ((size_t)(seg0 + k) * C + c) * KK + (size_t)row * Kp + 4 * g;
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt) store4<T, T>(U + 16 * mt, y[0][mt]);
+    }
 
     // column operator on rows j = 16 mt + 4 g + q of Y^T
 #pragma unroll
@@ -216,6 +223,11 @@ PStageDesc pstage_descriptor(const EpochInstance* in) {
   d.cat_rates = static_cast<const double*>(in->cat.ptr);
   d.Pout = in->Pm.ptr;
   d.dPout = in->dPm.ptr;
+  // the matrix-core dlogL/dQ chain reads A_k V from the P stage
+  d.Ubuf = ((in->cfg.flags & EPOCH_GRAD_Q) && in->qscratch.ptr && grad_Q_mfma_supported(in) &&
+            in->cfg.kernel_path == EPOCH_KERNEL_AUTO)
+               ? in->qscratch.ptr
+               : nullptr;
   d.n_items = in->n_nodes * in->C;
   d.C = in->C;
   d.grad = (in->cfg.flags & (EPOCH_GRAD_BRANCH | EPOCH_GRAD_Q)) != 0;

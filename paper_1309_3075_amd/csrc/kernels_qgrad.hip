@@ -352,11 +352,11 @@ __global__ __launch_bounds__(256) void qgrad_reduce_kernel(
 // W_k = R_k V_s^-T, where R_k = G B_k^T, the real-basis adjoint of segment k is
 //   Y_k = V_s^T G_k V_s^-T = U_k^T W_k.
 // One block per (branch, category), one wavefront per 16-row stripe.  The
-// forward chain A_{k+1} = A_k + (U_k (E_k - I)) V^-1 and the backward chain
-// R_{k-1} = R_k + (W_k (E_k - I)^T) V^T keep their stripes in registers (the
-// layout of the P-stage kernel); U_k is parked in a global scratch buffer
-// between the two passes; Y_k contracts over all rows, so U_k and W_k meet in
-// LDS and each wavefront writes 16 rows of Y_k.  The transposed factors V^T and
+// forward chain is the P stage's: it stores U_k = A_k V (its first product of
+// each step) in a global scratch buffer.  The backward chain
+// R_{k-1} = R_k + (W_k (E_k - I)^T) V^T keeps its stripes in registers (the
+// layout of the P-stage kernel); Y_k contracts over all rows, so U_k and W_k
+// meet in LDS and each wavefront writes 16 rows of Y_k.  The transposed factors V^T and
 // V^-T are read as rows of host-transposed copies.
 template <typename T, int NT>
 __global__ __launch_bounds__(256) void qgrad_chain_kernel(
@@ -382,50 +382,17 @@ __global__ __launch_bounds__(256) void qgrad_chain_kernel(
   const double scale = cat_rates[c] * rate[v];
   T(*coef)[2] = s_coef[w];
 
-  // forward pass
-  acc x[1][NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) x[0][t][q] = (16 * t + 4 * g + q == row) ? T(1) : T(0);
+  // tau and e^{tau lambda} of every segment term, for the divided differences of the sums;
+  // the forward products A_k V were stored by the P stage
   for (int k = 0; k < m; ++k) {
     const int s = seg_process[seg0 + k];
     const double tau_d = scale * seg_time[seg0 + k];
-    const T* V = eigV + (size_t)s * KK;
-    const T* Vi = eigVi + (size_t)s * KK;
-    if (lane < Kp) {
-      const BlockCoef<T> bc = block_coef(lre + (size_t)s * Kp, lim + (size_t)s * Kp, lane, T(tau_d));
-      coef[lane][0] = bc.m_self;
-      coef[lane][1] = bc.m_other;
-    }
     if (threadIdx.x == 0) qtau[(size_t)(seg0 + k) * C + c] = tau_d;
     if (w == 0 && lane < Kp) {
-      // e^{tau lambda} of every eigenvalue, for the divided differences of the sums
       const double ea = exp(tau_d * lr64[(size_t)s * Kp + lane]);
       const double th = tau_d * li64[(size_t)s * Kp + lane];
       reinterpret_cast<double2*>(qexp)[((size_t)(seg0 + k) * C + c) * Kp + lane] = make_double2(ea * cos(th), ea * sin(th));
     }
-    wave_lds_sync();
-    acc y[1][NT];
-#pragma unroll
-    for (int mt = 0; mt < NT; ++mt) y[0][mt] = acc{0, 0, 0, 0};
-    stripe_gemm<T, NT, 1>(V, g, arow, x, y);
-    T* U = Ubuf + ((size_t)(seg0 + k) * C + c) * KK + (size_t)row * Kp + 4 * g;
-#pragma unroll
-    for (int mt = 0; mt < NT; ++mt) store4<T, T>(U + 16 * mt, y[0][mt]);
-    if (k + 1 < m) {
-#pragma unroll
-      for (int mt = 0; mt < NT; ++mt)
-#pragma unroll
-        for (int q = 0; q < 4; q += 2) {
-          const int j = 16 * mt + 4 * g + q;
-          const T y0 = y[0][mt][q], y1 = y[0][mt][q + 1];
-          y[0][mt][q] = coef[j][0] * y0 + coef[j][1] * y1;
-          y[0][mt][q + 1] = coef[j + 1][0] * y1 + coef[j + 1][1] * y0;
-        }
-      stripe_gemm<T, NT, 1>(Vi, g, arow, y, x);
-    }
-    wave_lds_sync();
   }
 
   // backward pass, R_{m-1} = G (rows of this stripe)
