@@ -507,6 +507,7 @@ __global__ __launch_bounds__(256) void qgrad_h_kernel(int Kp, int n_chunks, int 
   const int q1 = min(list_off[s + 1], q0 + chunk);
   double re = 0.0, im = 0.0;
   const double2* E = reinterpret_cast<const double2*>(qexp);
+#pragma unroll 4
   for (int qi = q0; qi < q1; ++qi) {
     const int item = list[qi];
     const double tau = qtau[item];
