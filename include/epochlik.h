@@ -202,6 +202,31 @@ int epoch_set_timing(EpochInstance* inst, int32_t enable);
  * each (either may be NULL).  Synchronises the stream. */
 int epoch_get_timing(EpochInstance* inst, double* ms_out, int64_t* counts_out);
 
+/* Kernel-selection options of an instance (performance only: every setting
+ * computes the same quantities).  Takes effect for the next evaluation; a key
+ * that changes the schedule re-plans the current tree.
+ *   EPOCH_OPT_TREE_WALK: 1 = 4-state pruning and branch gradients as one
+ *     traversal of the whole tree per tile of patterns; 0 (default) = one
+ *     launch per tree level.  dlogL/dQ always uses the level kernels.
+ *   EPOCH_OPT_WALK_RECOMPUTE: value >= 2 (default 2): in the tree walk,
+ *     internal nodes whose subtree holds at most this many tips are recomputed
+ *     from tip states in the pre-order pass instead of being stored (2 when the
+ *     instance has EPOCH_GRAD_Q).
+ *   EPOCH_OPT_WALK_BLOCKS: value >= 0: cap on the blocks of a tree-walk launch
+ *     (0 = one group of tiles per wavefront).
+ *   EPOCH_OPT_WALK_TILES: 1 or 2 (default 2): FP32 pattern tiles carried
+ *     together by one wavefront of the tree walk.
+ *   EPOCH_OPT_LEVEL_MIN_TILES: 1..64 (default 8): fewest pattern tiles a
+ *     wavefront of the 4-state pre-order level kernels walks; smaller values
+ *     give narrow levels more wavefronts and more dlogL/dP partial sums.
+ * Returns EPOCH_ERR_ARG for an unknown key or a value out of range. */
+#define EPOCH_OPT_TREE_WALK 1
+#define EPOCH_OPT_WALK_RECOMPUTE 2
+#define EPOCH_OPT_WALK_BLOCKS 3
+#define EPOCH_OPT_WALK_TILES 4
+#define EPOCH_OPT_LEVEL_MIN_TILES 5
+int epoch_set_option(EpochInstance* inst, int32_t key, int64_t value);
+
 /* ---- Batched evaluation (an addition to the paper: many independent
  * evaluations in one replayed HIP graph).
  * A batch references n distinct, fully set-up instances (eigensystems, tree,
@@ -246,6 +271,23 @@ int epoch_plan_segments(int32_t n_tips, const int32_t* parent, const double* hei
                         const int32_t* interval_process, int32_t n_processes,
                         int32_t capacity, int32_t* seg_offset, int32_t* seg_process,
                         double* seg_time, int32_t* n_segments);
+
+/* Host planner only (no device work, usable without a GPU): the two programs
+ * of the 4-state tree walk for a tree (the pre-order pass that follows
+ * Felsenstein's recursion, Eq. 4, down from the root).  parent/height as in
+ * set_tree_epochs; recompute_tips >= 2.  ops: host [capacity][4] int32 out,
+ * the post-order program followed by the pre-order program; counts: host [4]
+ * out = {post ops, pre ops, post stack slots, pre stack slots}.  Each
+ * operation is {info, a, b, u}: info bit 0 = pre-order operation, bit 1 =
+ * root, bit 2 = store the partial, bits 3-4 / 5-6 = source of child a / b
+ * (0 tip, 1 stored partial, 2 stack slot), bits 8-13 / 14-19 = stack slots of
+ * a / b, bits 20-25 = output slot (post) or outside-vector slot (pre), bits
+ * 26-31 = slot of q_b (pre); an output that nothing reads (the root's partial,
+ * the outside vector of a tip) names the slot just past the program's slot
+ * count.  Returns EPOCH_ERR_ARG if capacity is too small (counts still set) or
+ * the tree needs more than 62 stack slots. */
+int epoch_plan_walk(int32_t n_tips, const int32_t* parent, const double* height, int32_t recompute_tips,
+                    int32_t capacity, int32_t* ops, int32_t* counts);
 
 #ifdef __cplusplus
 }

@@ -37,7 +37,7 @@ EXPORTED = [
     "root_log_likelihood", "log_likelihood_gradient", "epoch_evaluate", "epoch_get_transition_matrices",
     "epoch_plan_segments", "epoch_set_timing", "epoch_get_timing", "epoch_bandwidth_probe",
     "epoch_batch_create", "epoch_batch_evaluate", "epoch_batch_gradients", "epoch_batch_target_blocks",
-    "epoch_batch_destroy",
+    "epoch_batch_destroy", "epoch_set_option", "epoch_plan_walk",
 ]
 EPOCH_EVAL_LOGL = 0x1
 EPOCH_EVAL_GRAD_BRANCH = 0x2
@@ -111,6 +111,8 @@ def load() -> ctypes.CDLL:
         "epoch_batch_target_blocks": (i32, [P, ctypes.POINTER(i32)]),
         "epoch_batch_destroy": (i32, [P]),
         "epoch_get_timing": (i32, [P, dp, ctypes.POINTER(ctypes.c_int64)]),
+        "epoch_set_option": (i32, [P, i32, ctypes.c_int64]),
+        "epoch_plan_walk": (i32, [i32, ip, dp, i32, i32, ip, ip]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -172,6 +174,29 @@ def plan_segments(parent, height, boundaries, interval_process, n_processes):
                                   n_processes, cap, _ip(off), _ip(proc), _dp(tim), ctypes.byref(nseg)))
     n = nseg.value
     return off, proc[:n].copy(), tim[:n].copy()
+
+
+EPOCH_OPT_TREE_WALK = 1
+EPOCH_OPT_WALK_RECOMPUTE = 2
+EPOCH_OPT_WALK_BLOCKS = 3
+EPOCH_OPT_WALK_TILES = 4
+EPOCH_OPT_LEVEL_MIN_TILES = 5
+
+
+def plan_walk(parent, height, recompute_tips: int = 2):
+    """Host planner (no GPU needed): the 4-state tree-walk programs.
+    Returns (post ops [n,4], pre ops [m,4], post stack slots, pre stack slots)."""
+    lib = load()
+    parent = _i32(parent)
+    height = _f64(height)
+    n_nodes = parent.shape[0]
+    n_tips = (n_nodes + 1) // 2
+    counts = np.zeros(4, np.int32)
+    cap = 8 * n_nodes + 16
+    ops = np.zeros((cap, 4), np.int32)
+    check(lib.epoch_plan_walk(n_tips, _ip(parent), _dp(height), int(recompute_tips), cap, _ip(ops), _ip(counts)))
+    n_post, n_pre = int(counts[0]), int(counts[1])
+    return ops[:n_post].copy(), ops[n_post:n_post + n_pre].copy(), int(counts[2]), int(counts[3])
 
 
 def bandwidth_probe(nbytes: int = 1 << 31, kind: str = "copy", iters: int = 20) -> float:

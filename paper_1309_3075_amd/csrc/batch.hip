@@ -163,6 +163,7 @@ int enqueue(EpochBatch* b, uint32_t what, const double* const* d_result_ptrs) {
   }
   for (size_t q : b->p_single) {
     int rc = launch_pstage(b->insts[q]);
+    if (!rc) rc = fastpath_after_pstage(b->insts[q]);
     if (rc) return rc;
   }
   if (b->merged) {
@@ -177,11 +178,11 @@ int enqueue(EpochBatch* b, uint32_t what, const double* const* d_result_ptrs) {
     for (auto* in : b->insts) {
       int rc = fastpath_post(in);
       if (!rc) rc = fastpath_root(in);
-      if (!rc && (what & (kGradBranch | kGradQ))) rc = fastpath_gradient(in, false);
+      if (!rc && (what & (kGradBranch | kGradQ))) rc = fastpath_gradient(in, (what & kGradQ) != 0);
       if (rc) return rc;
     }
   }
-  if (what & kGradQ)
+  if (b->merged && (what & kGradQ))
     for (auto* in : b->insts) {
       int rc = launch_grad_Q(in);
       if (rc) return rc;

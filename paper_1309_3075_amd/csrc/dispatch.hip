@@ -33,10 +33,14 @@ void fastpath_release(EpochInstance*) {}
 int fastpath_tips_changed(EpochInstance*) { return EPOCH_OK; }
 int fastpath_tree_changed(EpochInstance* in) {
   if (codon(in)) return codon_prepare(in);
+  if (nuc(in)) {
+    int rc = walk_prepare(in);
+    if (rc) return rc;
+  }
   if (!nuc(in) || !in->gslots.ptr) return EPOCH_OK;
   std::vector<int32_t> slots, nodes;
-  nuc_slots_per_node(in, slots);
   nuc_pre_order_nodes(in, nodes, in->nuc_fuse);
+  nuc_slots_per_node(in, nodes, in->nuc_fuse, slots);
   int rc = ensure(in->nuc_nodes, std::max<size_t>(1, nodes.size()) * sizeof(int32_t));
   if (!rc) rc = hip_check(hipMemcpyAsync(in->gslots.ptr, slots.data(), slots.size() * sizeof(int32_t),
                                          hipMemcpyHostToDevice, in->stream), "gslots upload");
@@ -65,13 +69,20 @@ int launch_grad_Q(EpochInstance* in) {
   return launch_grad_Q_generic(in);
 }
 
+int fastpath_after_pstage(EpochInstance* in) { return (nuc(in) && in->walk_ok) ? launch_walk_tipcol(in) : EPOCH_OK; }
+
 int fastpath_pstage(EpochInstance* in) {
-  EPOCH_PHASE(0, launch_pstage(in));
+  EPOCH_PHASE(0, launch_pstage(in) || fastpath_after_pstage(in));
   return EPOCH_OK;
 }
 
+int launch_post(EpochInstance* in) {
+  if (nuc(in)) return in->walk_ok ? launch_walk_post(in) : launch_nuc_post(in);
+  return codon(in) ? launch_codon_post(in) : launch_post_generic(in);
+}
+
 int fastpath_post(EpochInstance* in) {
-  EPOCH_PHASE(1, nuc(in) ? launch_nuc_post(in) : (codon(in) ? launch_codon_post(in) : launch_post_generic(in)));
+  EPOCH_PHASE(1, launch_post(in));
   return EPOCH_OK;
 }
 
@@ -81,7 +92,9 @@ int fastpath_root(EpochInstance* in) {
 }
 
 int fastpath_gradient(EpochInstance* in, bool want_Q) {
-  if (nuc(in)) {
+  if (nuc(in) && in->walk_ok && in->walk_pre_ok && !want_Q) {
+    EPOCH_PHASE(3, launch_walk_pre_grad(in));
+  } else if (nuc(in)) {
     EPOCH_PHASE(3, launch_nuc_pre_grad(in));
     EPOCH_PHASE(4, launch_grad_reduce(in, in->nuc_slots, static_cast<const int32_t*>(in->gslots.ptr)));
   } else if (codon(in)) {

@@ -302,7 +302,8 @@ int epoch_destroy(EpochInstance* in) {
                     &in->cat, &in->tree_i, &in->tree_d, &in->Pm, &in->dPm, &in->partials, &in->scales,
                     &in->pre, &in->site, &in->blocksum, &in->result, &in->Gpart, &in->G, &in->dbranch,
                     &in->qseg, &in->qscratch, &in->dQ, &in->seglist, &in->gslots, &in->codon_dev, &in->codon_aux,
-                    &in->eigTT, &in->eig64T, &in->qtau, &in->nuc_nodes})
+                    &in->eigTT, &in->eig64T, &in->qtau, &in->nuc_nodes, &in->walk_ops,
+                    &in->walk_tcol, &in->walk_dpart, &in->walk_dummy})
     release(*b);
   delete in;
   return EPOCH_OK;
@@ -720,6 +721,61 @@ int epoch_plan_segments(int32_t n_tips, const int32_t* parent, const double* hei
   if (nseg > capacity) return set_error(EPOCH_ERR_ARG, "capacity %d < %d segments", capacity, nseg);
   std::copy(plan.seg_process.begin(), plan.seg_process.end(), seg_process);
   std::copy(plan.seg_time.begin(), plan.seg_time.end(), seg_time);
+  return EPOCH_OK;
+}
+
+int epoch_set_option(EpochInstance* in, int32_t key, int64_t value) {
+  if (!in) return set_error(EPOCH_ERR_ARG, "NULL instance");
+  switch (key) {
+    case EPOCH_OPT_TREE_WALK:
+      if (value != 0 && value != 1) return set_error(EPOCH_ERR_ARG, "EPOCH_OPT_TREE_WALK takes 0 or 1");
+      in->walk_enable = (int)value;
+      break;
+    case EPOCH_OPT_WALK_RECOMPUTE:
+      if (value < 2 || value > in->N) return set_error(EPOCH_ERR_ARG, "EPOCH_OPT_WALK_RECOMPUTE takes 2..N");
+      in->walk_recompute = (int)value;
+      break;
+    case EPOCH_OPT_WALK_BLOCKS:
+      if (value < 0 || value > (1 << 30)) return set_error(EPOCH_ERR_ARG, "EPOCH_OPT_WALK_BLOCKS out of range");
+      in->walk_blocks = (int)value;
+      return EPOCH_OK;
+    case EPOCH_OPT_WALK_TILES:
+      if (value != 1 && value != 2) return set_error(EPOCH_ERR_ARG, "EPOCH_OPT_WALK_TILES takes 1 or 2");
+      in->walk_nt = (int)value;
+      break;
+    case EPOCH_OPT_LEVEL_MIN_TILES:
+      if (value < 1 || value > 64) return set_error(EPOCH_ERR_ARG, "EPOCH_OPT_LEVEL_MIN_TILES takes 1..64");
+      in->nuc_rmin = (int)value;
+      if (int rc = fastpath_init(in)) return rc;
+      break;
+    default:
+      return set_error(EPOCH_ERR_ARG, "unknown option %d", key);
+  }
+  in->partials_valid = in->logL_valid = false;
+  return in->have_tree ? fastpath_tree_changed(in) : EPOCH_OK;
+}
+
+int epoch_plan_walk(int32_t n_tips, const int32_t* parent, const double* height, int32_t recompute_tips,
+                    int32_t capacity, int32_t* ops, int32_t* counts) {
+  g_error.clear();
+  if (!counts || (capacity > 0 && !ops)) return set_error(EPOCH_ERR_ARG, "NULL output");
+  if (recompute_tips < 2) return set_error(EPOCH_ERR_ARG, "recompute_tips must be >= 2");
+  TreePlan plan;
+  std::string err;
+  const int32_t phi = 0;
+  if (plan_tree(n_tips, parent, height, nullptr, 1, nullptr, &phi, 1, plan, err))
+    return set_error(EPOCH_ERR_ARG, "%s", err.c_str());
+  WalkProgram w;
+  const int rc = build_walk_programs(plan, recompute_tips, w);
+  counts[0] = (int32_t)(w.post.size() / 4);
+  counts[1] = (int32_t)(w.pre.size() / 4);
+  counts[2] = w.post_slots;
+  counts[3] = w.pre_slots;
+  if (rc) return set_error(EPOCH_ERR_ARG, "tree needs more than %d stack slots", kWalkMaxSlots);
+  const int n_ops = counts[0] + counts[1];
+  if (n_ops > capacity) return set_error(EPOCH_ERR_ARG, "capacity %d < %d operations", capacity, n_ops);
+  std::copy(w.post.begin(), w.post.end(), ops);
+  std::copy(w.pre.begin(), w.pre.end(), ops + w.post.size());
   return EPOCH_OK;
 }
 

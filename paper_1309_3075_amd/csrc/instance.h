@@ -103,6 +103,18 @@ struct EpochInstance {
   int nuc_slots = 1;   // partial-sum slots per branch of the four-state gradient
   std::vector<int> nuc_fuse;   // per level: pre-order nodes with a cherry child (listed first in nuc_nodes)
   epochlik::DevBuf nuc_nodes;  // int32 [N-1]: level order of the four-state pre-order launches
+  // four-state tree-walk kernels (kernels_walk.hip)
+  int walk_enable = 0;         // 1: tree-walk kernels for the 4-state pruning and branch gradients
+  int walk_recompute = 2;      // subtrees with at most this many tips are recomputed, not stored
+  int walk_blocks = 0;         // > 0: cap on the blocks of a walk launch (tiles are then strided)
+  int walk_nt = 2;             // FP32: pattern tiles per wavefront (1 or 2)
+  bool walk_ok = false;        // programs built for the current tree
+  bool walk_pre_ok = false;    // the pre-order program's LDS fits (else the level kernels take the gradient)
+  epochlik::WalkProgram walk;
+  epochlik::DevBuf walk_ops;   // int4 post-order program, then pre-order program
+  epochlik::DevBuf walk_tcol;  // T [2][N][C][5][4] columns of the tip branches' P and dP/dl
+  epochlik::DevBuf walk_dpart; // T [tile groups][n_nodes] shares of dlogL/dl, then double [32][n_nodes]
+  epochlik::DevBuf walk_dummy; // stand-in operands of the walk kernels (never read back)
 
   // device buffers (compute type T unless noted)
   epochlik::DevBuf eigT;       // V[S][Kp][Kp], Vinv[S][Kp][Kp], lre[S][Kp], lim[S][Kp]
@@ -193,7 +205,17 @@ int launch_nuc_root(EpochInstance* in);
 int launch_nuc_pre_grad(EpochInstance* in);
 int nuc_slots(int P, int C, int rmin);
 void nuc_pre_order_nodes(const EpochInstance* in, std::vector<int32_t>& nodes, std::vector<int>& fuse);
-void nuc_slots_per_node(const EpochInstance* in, std::vector<int32_t>& out);
+void nuc_slots_per_node(const EpochInstance* in, const std::vector<int32_t>& nodes, const std::vector<int>& fuse,
+                        std::vector<int32_t>& out);
+
+// 4-state tree-walk kernels (kernels_walk.hip)
+int walk_prepare(EpochInstance* in);  // builds and uploads the programs (walk_ok)
+int walk_tiles(const EpochInstance* in);
+size_t walk_tcol_bytes(const EpochInstance* in);
+size_t walk_dpart_rows_bytes(const EpochInstance* in);
+int launch_walk_tipcol(EpochInstance* in);
+int launch_walk_post(EpochInstance* in);
+int launch_walk_pre_grad(EpochInstance* in);
 
 // 64-state MFMA kernels (kernels_codon.hip)
 int launch_codon_post(EpochInstance* in);

@@ -20,121 +20,12 @@
 
 #include "device_common.h"
 #include "instance.h"
+#include "nuc_common.h"
 
 namespace epochlik {
 
 namespace {
-
-template <typename T>
-struct alignas(4 * sizeof(T)) V4 {
-  T v[4];
-};
-
-template <typename T>
-struct M4 {
-  T m[16];
-};
-
-template <typename T>
-__device__ inline V4<T> onehot(int st) {
-  V4<T> r;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) r.v[i] = (st >= 4 || st == i) ? T(1) : T(0);
-  return r;
-}
-
-template <typename T>
-__device__ inline V4<T> matvec(const M4<T>& M, const V4<T>& x) {
-  V4<T> y;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    T s = M.m[4 * i] * x.v[0];
-#pragma unroll
-    for (int j = 1; j < 4; ++j) s += M.m[4 * i + j] * x.v[j];
-    y.v[i] = s;
-  }
-  return y;
-}
-
-template <typename T>
-__device__ inline V4<T> matvec_t(const M4<T>& M, const V4<T>& x) {
-  V4<T> y;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    T s = M.m[j] * x.v[0];
-#pragma unroll
-    for (int i = 1; i < 4; ++i) s += M.m[4 * i + j] * x.v[i];
-    y.v[j] = s;
-  }
-  return y;
-}
-
-template <typename T>
-__device__ inline T max4(const V4<T>& x) {
-  T a = x.v[0] > x.v[1] ? x.v[0] : x.v[1];
-  T b = x.v[2] > x.v[3] ? x.v[2] : x.v[3];
-  return a > b ? a : b;
-}
-
-template <typename T>
-__device__ inline M4<T> load_matrix(const T* __restrict__ p) {
-  M4<T> M;
-  const V4<T>* q = reinterpret_cast<const V4<T>*>(p);
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const V4<T> row = q[r];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) M.m[4 * r + j] = row.v[j];
-  }
-  return M;
-}
-
-// Child vector for one (pattern, category): tip indicator or stored partial.
-template <typename T>
-__device__ inline V4<T> load_child(int child, int N, int c, int P, int pc, const uint8_t* __restrict__ tips,
-                                   const V4<T>* __restrict__ part, int C) {
-  if (child < N) return onehot<T>(tips[(size_t)child * P + pc]);
-  return part[((size_t)(child - N) * C + c) * P + pc];
-}
-
-// Lane exchange inside groups of CP adjacent lanes.  Offsets 1 and 2 use DPP
-// quad permutations (no LDS traffic); offset 4 (CP = 8 only) uses ds_bpermute.
-template <int OFF>
-__device__ inline float xor_lanes(float v) {
-  if constexpr (OFF == 1)
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
-  else if constexpr (OFF == 2)
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
-  else
-    return __shfl_xor(v, OFF, 64);
-}
-template <int OFF>
-__device__ inline double xor_lanes(double v) {
-  if constexpr (OFF == 1 || OFF == 2) {
-    const long long b = __double_as_longlong(v);
-    const int ctrl = OFF == 1 ? 0xB1 : 0x4E;
-    const int l = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), ctrl, 0xF, 0xF, false);
-    const int h = __builtin_amdgcn_mov_dpp((int)(b >> 32), ctrl, 0xF, 0xF, false);
-    return __longlong_as_double(((long long)h << 32) | (unsigned int)l);
-  } else {
-    return __shfl_xor(v, OFF, 64);
-  }
-}
-
-template <int CP, typename T>
-__device__ inline T group_max_cp(T v) {
-  if constexpr (CP >= 2) { const T u = xor_lanes<1>(v); v = u > v ? u : v; }
-  if constexpr (CP >= 4) { const T u = xor_lanes<2>(v); v = u > v ? u : v; }
-  if constexpr (CP >= 8) { const T u = xor_lanes<4>(v); v = u > v ? u : v; }
-  return v;
-}
-template <int CP, typename T>
-__device__ inline T group_sum_cp(T v) {
-  if constexpr (CP >= 2) v += xor_lanes<1>(v);
-  if constexpr (CP >= 4) v += xor_lanes<2>(v);
-  if constexpr (CP >= 8) v += xor_lanes<4>(v);
-  return v;
-}
+using namespace nuc;
 
 // Sum of 16 values over the lanes of a wavefront that share a category
 // (lanes differing in bits log2(CP)..5), as a reduce-scatter: halving steps
@@ -712,17 +603,17 @@ int pre_dispatch_cp(EpochInstance* in) {
   for (int l = pl.n_levels; l >= lowest; --l) {
     const int n_l = pl.level_offset[l + 1] - pl.level_offset[l];
     if (!n_l) continue;
-    const int R = tiles_per_wave(tiles, n_l, in->nuc_rmin, 64);
-    const int blocks = pre_blocks(in, n_l);
-    // nodes with two cherry children first, then one, then none
+    // nodes with two cherry children first, then one, then none; each group's
+    // launch picks its own tiles per wavefront for its node count
     const int n2 = in->nuc_fuse[2 * l], n1 = in->nuc_fuse[2 * l + 1];
     const int32_t* lv = nodes + pl.level_offset[l];
 #define EPOCH_PRE_LAUNCH(NXV, first_node, count)                                                              \
   if ((count) > 0)                                                                                           \
-    hipLaunchKernelGGL((nuc_pre_level_kernel<T, CP, NXV>), dim3(blocks, (count)), dim3(256), 0, in->stream,  \
-                       lv + (first_node), in->d_left, in->d_right, Pm, tips, part, pre, pre,                  \
+    hipLaunchKernelGGL((nuc_pre_level_kernel<T, CP, NXV>), dim3(pre_blocks(in, (count)), (count)), dim3(256), 0, \
+                       in->stream, lv + (first_node), in->d_left, in->d_right, Pm, tips, part, pre, pre,      \
                        static_cast<const double*>(in->pi.ptr), static_cast<const double*>(in->cat.ptr), w,   \
-                       pl.root, in->N, in->P, in->C, R, in->nuc_slots, static_cast<double*>(in->Gpart.ptr))
+                       pl.root, in->N, in->P, in->C, tiles_per_wave(tiles, (count), in->nuc_rmin, 64),        \
+                       in->nuc_slots, static_cast<double*>(in->Gpart.ptr))
     EPOCH_PRE_LAUNCH(2, 0, n2);
     EPOCH_PRE_LAUNCH(1, n2, n1);
     EPOCH_PRE_LAUNCH(0, n2 + n1, n_l - n2 - n1);
@@ -742,9 +633,11 @@ int nuc_slots(int P, int C, int rmin) {
 }
 
 // Number of partial-sum slots each branch receives from the gradient pass, host
-// [n_nodes]: the block count of the level that forms its dlogL/dP (its parent's,
-// or its grandparent's for the tip children of a cherry).
-void nuc_slots_per_node(const EpochInstance* in, std::vector<int32_t>& out) {
+// [n_nodes]: the block count of the launch that forms its dlogL/dP (its parent's
+// group within its level, or its grandparent's for the tip children of a
+// cherry).  nodes / fuse: the pre-order launch order (nuc_pre_order_nodes).
+void nuc_slots_per_node(const EpochInstance* in, const std::vector<int32_t>& nodes, const std::vector<int>& fuse,
+                        std::vector<int32_t>& out) {
   const auto& pl = in->plan;
   const int N = in->N;
   out.assign(in->n_nodes, 0);
@@ -752,9 +645,11 @@ void nuc_slots_per_node(const EpochInstance* in, std::vector<int32_t>& out) {
   for (int l = lowest; l <= pl.n_levels; ++l) {
     const int n_l = pl.level_offset[l + 1] - pl.level_offset[l];
     if (!n_l) continue;
-    const int blocks = pre_blocks(in, n_l);
+    const int n2 = fuse[2 * l], n1 = fuse[2 * l + 1];
     for (int k = pl.level_offset[l]; k < pl.level_offset[l + 1]; ++k) {
-      const int u = pl.level_nodes[k];
+      const int u = nodes[k];
+      const int r = k - pl.level_offset[l];
+      const int blocks = pre_blocks(in, r < n2 ? n2 : (r < n2 + n1 ? n1 : n_l - n2 - n1));
       for (int child : {pl.left[u], pl.right[u]}) {
         out[child] = blocks;
         if (l > 1 && child >= N && pl.left[child] < N && pl.right[child] < N) {

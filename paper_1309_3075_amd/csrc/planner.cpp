@@ -201,4 +201,152 @@ int plan_tree(int n_tips, const int32_t* parent, const double* height, const dou
   return 0;
 }
 
+namespace {
+
+struct SlotPool {
+  std::vector<char> used;
+  int peak = 0;
+  int get() {
+    for (int s = 0;; ++s) {
+      if (s == (int)used.size()) used.push_back(0);
+      if (!used[s]) {
+        used[s] = 1;
+        peak = std::max(peak, s + 1);
+        return s;
+      }
+    }
+  }
+  void put(int s) {
+    if (s >= 0) used[s] = 0;
+  }
+};
+
+int32_t encode(int flags, int src_a, int src_b, int s0, int s1, int s2, int s3) {
+  const uint32_t v = (uint32_t)flags | ((uint32_t)src_a << 3) | ((uint32_t)src_b << 5) |
+                     ((uint32_t)(s0 & 63) << 8) | ((uint32_t)(s1 & 63) << 14) | ((uint32_t)(s2 & 63) << 20) |
+                     ((uint32_t)(s3 & 63) << 26);
+  return (int32_t)v;
+}
+
+void emit(std::vector<int32_t>& prog, int32_t info, int a, int b, int u) {
+  prog.push_back(info);
+  prog.push_back(a);
+  prog.push_back(b);
+  prog.push_back(u);
+}
+
+}  // namespace
+
+int build_walk_programs(const TreePlan& P, int recompute_tips, WalkProgram& out) {
+  const int N = P.n_tips, n = P.n_nodes;
+  out = WalkProgram{};
+  std::vector<int32_t> tipcount(n, 1), need(n, 0);
+  for (int u : P.post) {
+    tipcount[u] = tipcount[P.left[u]] + tipcount[P.right[u]];
+    const int a = need[P.left[u]], b = need[P.right[u]];
+    need[u] = (a == b) ? a + 1 : std::max(a, b);
+  }
+  // children in visiting order: the one needing more stack slots first
+  auto first = [&](int u) { return need[P.right[u]] > need[P.left[u]] ? P.right[u] : P.left[u]; };
+  auto second = [&](int u) { return need[P.right[u]] > need[P.left[u]] ? P.left[u] : P.right[u]; };
+  out.stored.assign(n, 0);
+  for (int u = N; u < n; ++u) out.stored[u] = (u == P.root || tipcount[u] > recompute_tips) ? 1 : 0;
+
+  // Post-order over the subtree of v (children before parents, first child
+  // first); calls f(u) for every internal node.
+  auto post_walk = [&](int v, auto&& f) {
+    std::vector<std::pair<int, int>> st{{v, 0}};
+    while (!st.empty()) {
+      auto& top = st.back();
+      const int u = top.first;
+      if (top.second) {
+        st.pop_back();
+        f(u);
+        continue;
+      }
+      top.second = 1;
+      const int a = first(u), b = second(u);
+      if (b >= N) st.push_back({b, 0});
+      if (a >= N) st.push_back({a, 0});
+    }
+  };
+  // POST operations for the subtree of v; returns the slot holding x_v (-1 for the root).
+  auto emit_post = [&](std::vector<int32_t>& prog, SlotPool& pool, std::vector<int>& slot, int v, bool main) {
+    post_walk(v, [&](int u) {
+      const int a = first(u), b = second(u);
+      const int sa = a >= N ? slot[a] : -1, sb = b >= N ? slot[b] : -1;
+      pool.put(sa);
+      pool.put(sb);
+      int flags = 0, so = kWalkTrash;
+      if (main && u == P.root) {
+        flags = kWalkRoot | kWalkStore;
+      } else {
+        so = pool.get();
+        slot[u] = so;
+        if (main && out.stored[u]) flags = kWalkStore;
+      }
+      emit(prog, encode(flags, a >= N ? kWalkStack : kWalkTip, b >= N ? kWalkStack : kWalkTip, sa, sb, so, 0), a, b,
+           u);
+    });
+    return slot[v];
+  };
+
+  {
+    SlotPool pool;
+    std::vector<int> slot(n, -1);
+    emit_post(out.post, pool, slot, P.root, true);
+    out.post_slots = pool.peak;
+  }
+  {
+    SlotPool pool;
+    std::vector<int> slot(n, -1);
+    std::vector<std::pair<int, int>> st{{P.root, -1}};  // (node, slot holding its outside vector)
+    while (!st.empty()) {
+      const int u = st.back().first, qs = st.back().second;
+      st.pop_back();
+      // the child needing fewer slots first: the other's outside vector waits meanwhile
+      const int a = second(u), b = first(u);
+      int src[2], s[2] = {-1, -1};
+      const int ch[2] = {a, b};
+      for (int k = 0; k < 2; ++k) {
+        if (ch[k] < N) {
+          src[k] = kWalkTip;
+        } else if (out.stored[ch[k]]) {
+          src[k] = kWalkHbm;
+        } else {
+          src[k] = kWalkStack;
+          s[k] = emit_post(out.pre, pool, slot, ch[k], false);
+        }
+      }
+      int sqa = qs;
+      if (a >= N && sqa < 0) sqa = pool.get();
+      const int sqb = b >= N ? pool.get() : -1;
+      const int flags = kWalkPre | (u == P.root ? kWalkRoot : 0);
+      // q_u is read from, and q_a written to, the same slot; for a tip a the write
+      // lands in q_u's slot, free after this operation (at the root: the discard slot)
+      emit(out.pre, encode(flags, src[0], src[1], s[0], s[1], sqa >= 0 ? sqa : kWalkTrash, b >= N ? sqb : kWalkTrash),
+           a, b, u);
+      pool.put(s[0]);
+      pool.put(s[1]);
+      if (a < N) pool.put(sqa);
+      if (b >= N) st.push_back({b, sqb});
+      if (a >= N) st.push_back({a, sqa});
+    }
+    out.pre_slots = pool.peak;
+  }
+  if (out.post_slots > kWalkMaxSlots || out.pre_slots > kWalkMaxSlots) return -1;
+  // unused outputs go to the slot just past the last one (every write is then unconditional)
+  auto patch = [](std::vector<int32_t>& prog, int trash) {
+    for (size_t k = 0; k < prog.size(); k += 4) {
+      uint32_t v = (uint32_t)prog[k];
+      for (int sh : {20, 26})
+        if (((v >> sh) & 63u) == (uint32_t)kWalkTrash) v = (v & ~(63u << sh)) | ((uint32_t)trash << sh);
+      prog[k] = (int32_t)v;
+    }
+  };
+  patch(out.post, out.post_slots);
+  patch(out.pre, out.pre_slots);
+  return 0;
+}
+
 }  // namespace epochlik

@@ -148,6 +148,14 @@ class EpochLikelihood:
         check(self._lib.epoch_get_transition_matrices(self._h, _dp(out)))
         return out
 
+    def set_option(self, key: str, value: int):
+        """Kernel-selection option (epoch_set_option): 'tree_walk', 'walk_recompute', 'walk_blocks',
+        'walk_tiles', 'level_min_tiles'."""
+        k = {"tree_walk": _abi.EPOCH_OPT_TREE_WALK, "walk_recompute": _abi.EPOCH_OPT_WALK_RECOMPUTE,
+             "walk_blocks": _abi.EPOCH_OPT_WALK_BLOCKS, "walk_tiles": _abi.EPOCH_OPT_WALK_TILES,
+             "level_min_tiles": _abi.EPOCH_OPT_LEVEL_MIN_TILES}[key]
+        check(self._lib.epoch_set_option(self._h, k, int(value)))
+
     def set_timing(self, enable: bool = True):
         check(self._lib.epoch_set_timing(self._h, 1 if enable else 0))
 
@@ -166,10 +174,12 @@ class EpochLikelihood:
 
 
 def from_problem(prob, precision: str = "fp64", grad_branch: bool = False, grad_Q: bool = False,
-                 kernel: str = "auto", use_pi: bool = True) -> EpochLikelihood:
-    """Instance loaded with every input of a generated problem."""
+                 kernel: str = "auto", use_pi: bool = True, options: Optional[dict] = None) -> EpochLikelihood:
+    """Instance loaded with every input of a generated problem (options: see set_option)."""
     lik = EpochLikelihood(prob.n_tips, prob.n_patterns, prob.n_states, len(prob.cat_rates),
                           prob.n_processes, prob.n_intervals, precision, grad_branch, grad_Q, kernel)
+    for k, v in (options or {}).items():
+        lik.set_option(k, v)
     lik.set_tip_states(prob.tips)
     lik.set_pattern_weights(prob.weights)
     lik.set_categories(prob.cat_rates, prob.cat_weights)

@@ -1,0 +1,129 @@
+"""4-state tree-walk kernels (an opt-in alternative to the level kernels)
+against the FP64 oracle, through the C ABI: every category packing, ragged
+pattern tiles, recomputation thresholds, strided tiles, deep (caterpillar) and
+balanced trees; and the level kernels under their tiling option."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import epoch_oracle as O
+from paper_1309_3075_amd import workloads as W
+from paper_1309_3075_amd.likelihood import from_problem
+
+pytestmark = pytest.mark.gpu
+
+TOL_LOGL = {"fp64": 1e-12, "fp32": 1e-5}
+TOL_GRAD = {"fp64": 1e-6, "fp32": 1e-3}
+
+
+def _check(prob, precision, options=None, grad_Q=False):
+    options = {"tree_walk": 1, **(options or {})}
+    with from_problem(prob, precision, grad_branch=True, grad_Q=grad_Q, options=options) as lik:
+        logL, site, db, dq = lik.evaluate(branch=True, Q=grad_Q, site=True)
+    want_site = O.site_log_likelihoods(prob)
+    want = float(np.dot(prob.weights, want_site))
+    assert abs(logL - want) <= TOL_LOGL[precision] * abs(want), (logL, want)
+    assert np.max(np.abs(site - want_site)) <= TOL_LOGL[precision] * 10 * np.max(np.abs(want_site))
+    ref_b, ref_q = O.gradient(prob, wrt=("branch", "Q") if grad_Q else ("branch",))
+    assert np.linalg.norm(db - ref_b) <= TOL_GRAD[precision] * np.linalg.norm(ref_b), \
+        np.linalg.norm(db - ref_b) / np.linalg.norm(ref_b)
+    if grad_Q:
+        assert np.linalg.norm(dq - ref_q) <= TOL_GRAD[precision] * np.linalg.norm(ref_q)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("C", [1, 2, 4, 5])
+@pytest.mark.parametrize("P", [1, 17, 100])
+def test_walk_categories_and_tiles(C, P, precision):
+    rng = np.random.default_rng(5000 + 10 * C + P)
+    prob = W.random_problem(rng, 19, 4, P, n_categories=C, n_intervals=3, reversible=False, missing_frac=0.05)
+    _check(prob, precision)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("recompute", [3, 8, 40])
+def test_walk_recompute_thresholds(recompute, precision):
+    rng = np.random.default_rng(5100 + recompute)
+    prob = W.random_problem(rng, 40, 4, 70, n_categories=4, n_intervals=3, reversible=True,
+                            tip_height_max=0.2, missing_frac=0.05)
+    _check(prob, precision, options={"walk_recompute": recompute})
+
+
+@pytest.mark.parametrize("tiles", [1, 2])
+@pytest.mark.parametrize("blocks", [1, 3])
+def test_walk_strided_tiles(blocks, tiles):
+    """Fewer blocks than tiles: each wavefront walks several groups of tiles in turn."""
+    rng = np.random.default_rng(5200 + blocks)
+    prob = W.random_problem(rng, 25, 4, 300, n_categories=4, n_intervals=2)
+    _check(prob, "fp32", options={"walk_blocks": blocks, "walk_tiles": tiles})
+
+
+@pytest.mark.parametrize("C", [1, 3, 8])
+def test_walk_one_tile_per_wavefront(C):
+    rng = np.random.default_rng(5250 + C)
+    prob = W.random_problem(rng, 33, 4, 150, n_categories=C, n_intervals=3, reversible=False, missing_frac=0.05)
+    _check(prob, "fp32", options={"walk_tiles": 1})
+
+
+def _shaped(parent, seed, P=60, C=4):
+    rng = np.random.default_rng(seed)
+    n = len(parent)
+    N = (n + 1) // 2
+    prob = W.random_problem(rng, N, 4, P, n_categories=C, n_intervals=3, reversible=False)
+    height = np.zeros(n)
+    for u in range(N, n):
+        height[u] = 1.0 + max(height[v] for v in range(n) if parent[v] == u)
+    return dataclasses.replace(prob, parent=np.asarray(parent, np.int32), height=height / height[-1])
+
+
+def test_walk_caterpillar_tree():
+    N = 60
+    parent = [-1] * (2 * N - 1)
+    parent[0] = parent[1] = N
+    for k in range(2, N):
+        parent[k] = N + k - 1
+        parent[N + k - 2] = N + k - 1
+    _check(_shaped(parent, 5300), "fp32")
+    _check(_shaped(parent, 5301), "fp64")
+
+
+def test_walk_balanced_tree():
+    N = 64
+    parent = [-1] * (2 * N - 1)
+    level, nxt = list(range(N)), N
+    while len(level) > 1:
+        new = []
+        for i in range(0, len(level), 2):
+            parent[level[i]] = parent[level[i + 1]] = nxt
+            new.append(nxt)
+            nxt += 1
+        level = new
+    _check(_shaped(parent, 5400), "fp32")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("min_tiles", [1, 8, 64])
+def test_level_kernels_still_match(precision, min_tiles):
+    rng = np.random.default_rng(5500)
+    prob = W.random_problem(rng, 30, 4, 2000, n_categories=4, n_intervals=3, reversible=False, missing_frac=0.05)
+    _check(prob, precision, options={"tree_walk": 0, "level_min_tiles": min_tiles})
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_walk_post_with_rate_matrix_gradient(precision):
+    """dlogL/dQ takes the level pre-order kernels on the walk's stored partials."""
+    rng = np.random.default_rng(5600)
+    prob = W.random_problem(rng, 30, 4, 90, n_categories=4, n_intervals=3, reversible=False)
+    _check(prob, precision, grad_Q=True)
+
+
+def test_walk_and_level_agree_at_c2_shape():
+    """The same 512-taxon problem through both 4-state paths (FP32)."""
+    prob = W.make_config(2, n_patterns=3000)
+    with from_problem(prob, "fp32", grad_branch=True, options={"tree_walk": 1}) as lik:
+        a = lik.evaluate(branch=True)
+    with from_problem(prob, "fp32", grad_branch=True, options={"tree_walk": 0}) as lik:
+        b = lik.evaluate(branch=True)
+    assert abs(a[0] - b[0]) <= 1e-5 * abs(b[0])
+    assert np.linalg.norm(a[2] - b[2]) <= 1e-3 * np.linalg.norm(b[2])
