@@ -206,15 +206,17 @@ int epoch_get_timing(EpochInstance* inst, double* ms_out, int64_t* counts_out);
  * computes the same quantities).  Takes effect for the next evaluation; a key
  * that changes the schedule re-plans the current tree.
  *   EPOCH_OPT_TREE_WALK: 1 = 4-state pruning and branch gradients as one
- *     traversal of the whole tree per tile of patterns; 0 (default) = one
- *     launch per tree level.  dlogL/dQ always uses the level kernels.
+ *     traversal of the whole tree per tile of patterns; 0 = one launch per
+ *     tree level; -1 (default) = the traversal for FP32 instances with at
+ *     most 1024 tiles of 16 patterns (where per-level launches cannot fill the
+ *     GPU), else per level.  dlogL/dQ always uses the level kernels.
  *   EPOCH_OPT_WALK_RECOMPUTE: value >= 2 (default 2): in the tree walk,
  *     internal nodes whose subtree holds at most this many tips are recomputed
  *     from tip states in the pre-order pass instead of being stored (2 when the
  *     instance has EPOCH_GRAD_Q).
  *   EPOCH_OPT_WALK_BLOCKS: value >= 0: cap on the blocks of a tree-walk launch
  *     (0 = one group of tiles per wavefront).
- *   EPOCH_OPT_WALK_TILES: 1 or 2 (default 2): FP32 pattern tiles carried
+ *   EPOCH_OPT_WALK_TILES: 1 (default) or 2: FP32 pattern tiles carried
  *     together by one wavefront of the tree walk.
  *   EPOCH_OPT_LEVEL_MIN_TILES: 1..64 (default 8): fewest pattern tiles a
  *     wavefront of the 4-state pre-order level kernels walks; smaller values

@@ -728,7 +728,7 @@ int epoch_set_option(EpochInstance* in, int32_t key, int64_t value) {
   if (!in) return set_error(EPOCH_ERR_ARG, "NULL instance");
   switch (key) {
     case EPOCH_OPT_TREE_WALK:
-      if (value != 0 && value != 1) return set_error(EPOCH_ERR_ARG, "EPOCH_OPT_TREE_WALK takes 0 or 1");
+      if (value < -1 || value > 1) return set_error(EPOCH_ERR_ARG, "EPOCH_OPT_TREE_WALK takes -1, 0 or 1");
       in->walk_enable = (int)value;
       break;
     case EPOCH_OPT_WALK_RECOMPUTE:

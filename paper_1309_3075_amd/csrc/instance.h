@@ -104,10 +104,11 @@ struct EpochInstance {
   std::vector<int> nuc_fuse;   // per level: pre-order nodes with a cherry child (listed first in nuc_nodes)
   epochlik::DevBuf nuc_nodes;  // int32 [N-1]: level order of the four-state pre-order launches
   // four-state tree-walk kernels (kernels_walk.hip)
-  int walk_enable = 0;         // 1: tree-walk kernels for the 4-state pruning and branch gradients
+  int walk_enable = -1;        // tree-walk kernels for the 4-state pruning and branch gradients: 1 on, 0 off,
+                               // -1 when the level kernels cannot fill the GPU (FP32, at most kWalkAutoTiles tiles)
   int walk_recompute = 2;      // subtrees with at most this many tips are recomputed, not stored
   int walk_blocks = 0;         // > 0: cap on the blocks of a walk launch (tiles are then strided)
-  int walk_nt = 2;             // FP32: pattern tiles per wavefront (1 or 2)
+  int walk_nt = 1;             // FP32: pattern tiles per wavefront (1 or 2)
   bool walk_ok = false;        // programs built for the current tree
   bool walk_pre_ok = false;    // the pre-order program's LDS fits (else the level kernels take the gradient)
   epochlik::WalkProgram walk;

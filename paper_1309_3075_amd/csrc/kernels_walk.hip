@@ -755,9 +755,14 @@ bool walk_fits(const EpochInstance* in, int slots) {
   return per_wave <= kWalkMaxLds;
 }
 
+// Automatic choice: the walk where the level kernels cannot fill the chip (a
+// launch per level, each with fewer 16-pattern tiles than there are SIMDs).
+constexpr int kWalkAutoTiles = 1024;
+
 int walk_prepare(EpochInstance* in) {
   in->walk_ok = false;
-  if (in->path != 1 || !in->walk_enable) return EPOCH_OK;
+  if (in->path != 1 || in->walk_enable == 0) return EPOCH_OK;
+  if (in->walk_enable < 0 && (in->fp64 || walk_tiles(in) > kWalkAutoTiles)) return EPOCH_OK;
   const int rt = (in->cfg.flags & EPOCH_GRAD_Q) ? 2 : std::max(2, in->walk_recompute);
   if (build_walk_programs(in->plan, rt, in->walk) || !walk_fits(in, in->walk.post_slots))
     return EPOCH_OK;  // too deep for the stack: level kernels
