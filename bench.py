@@ -108,7 +108,7 @@ def committed_traffic(name, kernel):
         return None
 
 
-def run_cpu_baseline(prob, sample_patterns, want_Q):
+def run_cpu_baseline(prob, sample_patterns, want_Q, want_grad=True):
     """The FP64 oracle on a pattern subsample, scaled to evaluations/s of the full problem."""
     import copy
     from threadpoolctl import threadpool_limits
@@ -120,7 +120,8 @@ def run_cpu_baseline(prob, sample_patterns, want_Q):
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         logL = O.log_likelihood(sub)
-        d_branch, d_Q = O.gradient(sub, wrt=("branch", "Q") if want_Q else ("branch",))
+        d_branch, d_Q = (O.gradient(sub, wrt=("branch", "Q") if want_Q else ("branch",)) if want_grad
+                         else (None, None))
         dt = time.perf_counter() - t0
     full = dt * prob.n_patterns / sample_patterns
     return sub, logL, d_branch, d_Q, {
@@ -206,17 +207,18 @@ def main():
     if args.config == 5:
         return run_batch(args)
     want_Q = args.grad_q or args.config in (3, 4)
+    want_grad = args.config != 1  # the 16-taxon workload is a plain log-likelihood
     log(f"bench: generating config C{args.config} ...")
     t0 = time.perf_counter()
     prob = W.make_config(args.config, n_patterns=args.patterns)
     log(f"bench: generated in {time.perf_counter() - t0:.1f} s: N={prob.n_tips} P={prob.n_patterns} "
         f"K={prob.n_states} C={len(prob.cat_rates)} S={prob.n_processes} M={prob.n_intervals}")
-    lik = from_problem(prob, args.precision, grad_branch=True, grad_Q=want_Q, kernel=args.kernel,
+    lik = from_problem(prob, args.precision, grad_branch=want_grad, grad_Q=want_Q, kernel=args.kernel,
                        use_pi=args.config != 4)
 
     def step():
         # the whole path (P stage, pruning, root log-likelihood, gradients) with one host sync
-        lL, _, db, dq = lik.evaluate(branch=True, Q=want_Q)
+        lL, _, db, dq = lik.evaluate(branch=want_grad, Q=want_Q)
         return lL, db, dq
 
     for _ in range(args.warmup):
@@ -247,7 +249,11 @@ def main():
                                                and len(prob.cat_rates) == 1 else "generic"))
     if args.kernel == "generic":
         path = "generic"
-    names = {"nuc": {"post_order": "nuc_post_level", "pre_order_dP": "nuc_pre_level"},
+    # the library takes the tree walk for FP32 4-state instances of at most 1024 tiles of 16 patterns
+    cp = 1 if len(prob.cat_rates) <= 1 else (2 if len(prob.cat_rates) <= 2 else (4 if len(prob.cat_rates) <= 4 else 8))
+    walk = args.precision == "fp32" and -(-prob.n_patterns // (64 // cp)) <= 1024
+    names = {"nuc": {"post_order": "nuc_walk_mfma (post-order program)" if walk else "nuc_post_level",
+                     "pre_order_dP": "nuc_walk_mfma (pre-order program)" if walk else "nuc_pre_level"},
              "codon": {"post_order": "codon_post_level", "pre_order_dP": "codon_pre_level"},
              "generic": {"post_order": "post_level_generic", "pre_order_dP": "pre_level_generic + grad_G_generic"}}
     Kp = 4 if prob.n_states <= 4 else (8 if prob.n_states <= 8 else (prob.n_states + 15) // 16 * 16)
@@ -273,7 +279,8 @@ def main():
                     "algorithmic_bytes_per_eval": abytes[dom], "ms_per_eval": round(dom_ms, 4)}
     total_bytes = sum(abytes.values())
     result = {
-        "metric": "logL+gradient evals/sec", "value": round(value, 3), "unit": "evals/s", "n_gpus": 1,
+        "metric": "logL+gradient evals/sec" if want_grad else "logL evals/sec", "value": round(value, 3),
+        "unit": "evals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if args.precision == "fp32" else "f64",
@@ -299,15 +306,17 @@ def main():
     if not args.no_cpu_baseline:
         sample = args.cpu_sample or min(prob.n_patterns, {1: 1000, 2: 30000, 3: 3000, 4: 1}.get(args.config, 1000))
         log(f"bench: cpu baseline on {sample} patterns ...")
-        sub, ref_logL, ref_b, ref_q, cpu = run_cpu_baseline(prob, sample, want_Q)
+        sub, ref_logL, ref_b, ref_q, cpu = run_cpu_baseline(prob, sample, want_Q, want_grad)
         result["cpu_baseline"] = cpu
         # parity of the same GPU path on the same subsample
-        with from_problem(sub, args.precision, grad_branch=True, grad_Q=want_Q, kernel=args.kernel,
+        with from_problem(sub, args.precision, grad_branch=want_grad, grad_Q=want_Q, kernel=args.kernel,
                           use_pi=args.config != 4) as small:
             g_logL = small.log_likelihood()
-            g_b, g_q = small.gradient(branch=True, Q=want_Q)
-        parity = {"sample_patterns": sample, "logL_rel_err": abs(g_logL - ref_logL) / abs(ref_logL),
-                  "grad_branch_rel_err": float(np.linalg.norm(g_b - ref_b) / np.linalg.norm(ref_b))}
+            if want_grad:
+                g_b, g_q = small.gradient(branch=True, Q=want_Q)
+        parity = {"sample_patterns": sample, "logL_rel_err": abs(g_logL - ref_logL) / abs(ref_logL)}
+        if want_grad:
+            parity["grad_branch_rel_err"] = float(np.linalg.norm(g_b - ref_b) / np.linalg.norm(ref_b))
         if want_Q:
             parity["grad_Q_rel_err"] = float(np.linalg.norm(g_q - ref_q) / np.linalg.norm(ref_q))
         result["parity_vs_oracle"] = parity
