@@ -80,6 +80,13 @@ typedef struct EpochConfig {
   uint32_t flags;          /* EPOCH_GRAD_* */
   int32_t kernel_path;     /* EPOCH_KERNEL_AUTO or EPOCH_KERNEL_GENERIC */
   int32_t reserved;        /* must be 0 */
+  int64_t hbm_budget_bytes; /* 0 = unlimited.  > 0: device bytes allowed for intermediate
+                             * partials (and their scale row and gradient rows); the 4-state
+                             * tree walk then stores only the partials of the largest subtrees
+                             * that fit and recomputes the others from the tip states in the
+                             * gradient pass.  Needs n_states == 4, EPOCH_KERNEL_AUTO and no
+                             * EPOCH_GRAD_Q (dlogL/dQ reads every partial); set_tree_epochs
+                             * returns EPOCH_ERR_OOM when even the root alone does not fit. */
   void* stream;            /* hipStream_t to run on, or NULL for the default stream */
 } EpochConfig;
 
@@ -205,7 +212,7 @@ int epoch_get_timing(EpochInstance* inst, double* ms_out, int64_t* counts_out);
 /* Kernel-selection options of an instance (performance only: every setting
  * computes the same quantities).  Takes effect for the next evaluation; a key
  * that changes the schedule re-plans the current tree.
- *   EPOCH_OPT_TREE_WALK: 1 = 4-state pruning and branch gradients as one
+ *   EPOCH_OPT_TREE_WALK (fixed at 1 under hbm_budget_bytes): 1 = 4-state pruning and branch gradients as one
  *     traversal of the whole tree per tile of patterns; 0 = one launch per
  *     tree level; -1 (default) = the traversal for FP32 instances with at
  *     most 1024 tiles of 16 patterns (where per-level launches cannot fill the

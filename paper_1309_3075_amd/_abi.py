@@ -57,6 +57,7 @@ class EpochConfig(ctypes.Structure):
         ("flags", ctypes.c_uint32),
         ("kernel_path", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
+        ("hbm_budget_bytes", ctypes.c_int64),
         ("stream", ctypes.c_void_p),
     ]
 

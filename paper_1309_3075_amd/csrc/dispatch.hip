@@ -20,7 +20,8 @@ int fastpath_init(EpochInstance* in) {
     else if (in->Kp == 64 && in->K > 48 && !in->fp64 && in->C == 1) in->path = 2;
   }
   const bool grad = (in->cfg.flags & (EPOCH_GRAD_BRANCH | EPOCH_GRAD_Q)) != 0;
-  if (nuc(in) && grad) {
+  in->root_slot = 0;
+  if (nuc(in) && grad && in->budget == 0) {
     in->nuc_slots = nuc_slots(in->P, in->C, in->nuc_rmin);
     const size_t bytes = (size_t)in->nuc_slots * in->n_nodes * in->C * 16 * sizeof(double);
     int rc = ensure(in->Gpart, std::max(bytes, in->Gpart.bytes));
@@ -77,6 +78,7 @@ int fastpath_pstage(EpochInstance* in) {
 }
 
 int launch_post(EpochInstance* in) {
+  if (in->budget > 0 && !in->walk_ok) return set_error(EPOCH_ERR_STATE, "no tree-walk schedule for the HBM budget");
   if (nuc(in)) return in->walk_ok ? launch_walk_post(in) : launch_nuc_post(in);
   return codon(in) ? launch_codon_post(in) : launch_post_generic(in);
 }

@@ -171,6 +171,11 @@ int epoch_create(const EpochConfig* cfg, EpochInstance** out) {
   if (c.kernel_path != EPOCH_KERNEL_AUTO && c.kernel_path != EPOCH_KERNEL_GENERIC)
     return set_error(EPOCH_ERR_ARG, "unknown kernel_path");
   if (c.reserved != 0) return set_error(EPOCH_ERR_ARG, "reserved must be 0");
+  if (c.hbm_budget_bytes < 0) return set_error(EPOCH_ERR_ARG, "hbm_budget_bytes must be >= 0");
+  if (c.hbm_budget_bytes > 0 && (c.n_states != 4 || c.kernel_path != EPOCH_KERNEL_AUTO))
+    return set_error(EPOCH_ERR_ARG, "hbm_budget_bytes needs the 4-state kernels (n_states 4, EPOCH_KERNEL_AUTO)");
+  if (c.hbm_budget_bytes > 0 && (c.flags & EPOCH_GRAD_Q))
+    return set_error(EPOCH_ERR_ARG, "hbm_budget_bytes cannot be combined with EPOCH_GRAD_Q");
   const size_t N = c.n_tips, P = c.n_patterns;
   if ((N - 1) * P > ((size_t)1 << 40)) return set_error(EPOCH_ERR_ARG, "problem too large");
 
@@ -220,9 +225,14 @@ int epoch_create(const EpochConfig* cfg, EpochInstance** out) {
   A(in->cat, 2 * kMaxCategories * sizeof(double));
   A(in->Pm, n * C * KK * R);
   if (grad) A(in->dPm, n * C * KK * R);
-  A(in->partials, (N - 1) * C * P * Kp * R);
-  A(in->scales, (N - 1) * P * sizeof(int32_t));
-  if (grad) A(in->pre, (N - 1) * C * P * Kp * R);
+  in->budget = c.hbm_budget_bytes;
+  if (in->budget > 0) {
+    in->walk_enable = 1;  // partials are sized at set_tree_epochs, within the budget
+  } else {
+    A(in->partials, (N - 1) * C * P * Kp * R);
+    A(in->scales, (N - 1) * P * sizeof(int32_t));
+    if (grad) A(in->pre, (N - 1) * C * P * Kp * R);
+  }
   A(in->site, P * sizeof(double));
   A(in->blocksum, ((P + 63) / 64 + 1) * sizeof(double));
   A(in->result, 8 * sizeof(double));
@@ -303,7 +313,7 @@ int epoch_destroy(EpochInstance* in) {
                     &in->pre, &in->site, &in->blocksum, &in->result, &in->Gpart, &in->G, &in->dbranch,
                     &in->qseg, &in->qscratch, &in->dQ, &in->seglist, &in->gslots, &in->codon_dev, &in->codon_aux,
                     &in->eigTT, &in->eig64T, &in->qtau, &in->nuc_nodes, &in->walk_ops,
-                    &in->walk_tcol, &in->walk_dpart, &in->walk_dummy})
+                    &in->walk_tcol, &in->walk_dpart, &in->walk_dummy, &in->walk_slots})
     release(*b);
   delete in;
   return EPOCH_OK;
@@ -590,7 +600,9 @@ int set_tree_epochs(EpochInstance* in, const int32_t* parent, const double* heig
   in->have_tree = true;
   in->tree_generation++;
   invalidate_downstream(in);
-  return fastpath_tree_changed(in);
+  const int rc = fastpath_tree_changed(in);
+  if (rc) in->have_tree = false;  // no evaluation on a half-prepared schedule
+  return rc;
 }
 
 int update_transition_matrices(EpochInstance* in) {
@@ -729,10 +741,12 @@ int epoch_set_option(EpochInstance* in, int32_t key, int64_t value) {
   switch (key) {
     case EPOCH_OPT_TREE_WALK:
       if (value < -1 || value > 1) return set_error(EPOCH_ERR_ARG, "EPOCH_OPT_TREE_WALK takes -1, 0 or 1");
+      if (in->budget > 0 && value != 1) return set_error(EPOCH_ERR_ARG, "an HBM budget needs the tree walk");
       in->walk_enable = (int)value;
       break;
     case EPOCH_OPT_WALK_RECOMPUTE:
       if (value < 2 || value > in->N) return set_error(EPOCH_ERR_ARG, "EPOCH_OPT_WALK_RECOMPUTE takes 2..N");
+      if (in->budget > 0) return set_error(EPOCH_ERR_ARG, "under an HBM budget the budget sets the recomputation");
       in->walk_recompute = (int)value;
       break;
     case EPOCH_OPT_WALK_BLOCKS:
@@ -752,7 +766,10 @@ int epoch_set_option(EpochInstance* in, int32_t key, int64_t value) {
       return set_error(EPOCH_ERR_ARG, "unknown option %d", key);
   }
   in->partials_valid = in->logL_valid = false;
-  return in->have_tree ? fastpath_tree_changed(in) : EPOCH_OK;
+  if (!in->have_tree) return EPOCH_OK;
+  const int rc = fastpath_tree_changed(in);
+  if (rc) in->have_tree = false;
+  return rc;
 }
 
 int epoch_plan_walk(int32_t n_tips, const int32_t* parent, const double* height, int32_t recompute_tips,

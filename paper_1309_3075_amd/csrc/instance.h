@@ -116,6 +116,9 @@ struct EpochInstance {
   epochlik::DevBuf walk_tcol;  // T [2][N][C][5][4] columns of the tip branches' P and dP/dl
   epochlik::DevBuf walk_dpart; // T [tile groups][n_nodes] shares of dlogL/dl, then double [32][n_nodes]
   epochlik::DevBuf walk_dummy; // stand-in operands of the walk kernels (never read back)
+  epochlik::DevBuf walk_slots; // int32 [n_nodes]: partial slot of each stored node (-1: not stored)
+  int64_t budget = 0;          // hbm_budget_bytes (0: every internal node has a slot, slot = node - N)
+  int root_slot = 0;           // partial slot of the root; its scale exponents are scales row root_slot
 
   // device buffers (compute type T unless noted)
   epochlik::DevBuf eigT;       // V[S][Kp][Kp], Vinv[S][Kp][Kp], lre[S][Kp], lim[S][Kp]

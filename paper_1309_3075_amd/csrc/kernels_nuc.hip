@@ -568,7 +568,8 @@ int root_dispatch_cp(EpochInstance* in) {
   const int blocks = (in->P + 4 * TPW - 1) / (4 * TPW);
   const V4<T>* part = static_cast<const V4<T>*>(in->partials.ptr);
   const int32_t* sc = static_cast<const int32_t*>(in->scales.ptr);
-  const size_t slot = pl.root - in->N;
+  const size_t slot = in->root_slot;  // pl.root - N, or its compact slot under an HBM budget
+  (void)pl;
   hipLaunchKernelGGL((nuc_root_kernel<T, CP>), dim3(blocks), dim3(256), 0, in->stream,
                      part + slot * in->C * (size_t)in->P, sc + slot * (size_t)in->P,
                      static_cast<const double*>(in->pi.ptr), static_cast<const double*>(in->cat.ptr),

@@ -48,7 +48,8 @@ struct WalkArgs {
   const T* PmT;           // FP32 walk: [n][C][4][4] transposed transition matrices
   const uint8_t* tips;    // [N][P]
   V4<T>* part;            // [N-1][C][P]
-  int32_t* scales;        // [N-1][P]: the root's row receives each pattern's total exponent
+  int32_t* root_scales;   // [P]: each pattern's total exponent (the root's row of the scales)
+  const int32_t* slot_of; // [n_nodes]: partial slot of each stored node, -1 otherwise
   const double* pi;       // [4]
   const double* cat;      // rates[8], weights[8]
   const T* weightsT;      // [P]
@@ -127,8 +128,8 @@ template <typename T, int NT>
 __device__ inline void fetch_op(const WalkArgs<T>& g, const Lane<T, NT>& L, const Op& op, Fetch<T> (&f)[NT]) {
   const int ka = (op.info >> 3) & 3, kb = (op.info >> 5) & 3;
   const int ta = op.a < g.N ? op.a : g.N - 1, tb = op.b < g.N ? op.b : g.N - 1;
-  const size_t ra = ka == kWalkHbm ? (size_t)(op.a - g.N) * g.C + L.c : 0;
-  const size_t rb = kb == kWalkHbm ? (size_t)(op.b - g.N) * g.C + L.c : 0;
+  const size_t ra = ka == kWalkHbm ? (size_t)g.slot_of[op.a] * g.C + L.c : 0;
+  const size_t rb = kb == kWalkHbm ? (size_t)g.slot_of[op.b] * g.C + L.c : 0;
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     f[t].sta = g.tips[(size_t)ta * g.P + L.pc[t]];
@@ -210,8 +211,8 @@ __device__ inline void walk_step(const WalkArgs<T>& g, const Lane<T, NT>& L, con
       if constexpr (!PRE) {
         E[t] += e[t];
         const bool st = (info & kWalkStore) && L.valid[t];
-        *(st ? g.part + ((size_t)(u - g.N) * g.C + c) * g.P + L.p[t] : L.wdummy + L.lane) = y[t];
-        int32_t* sp = ((info & kWalkRoot) && L.cl == 0 && L.valid[t]) ? g.scales + (size_t)(u - g.N) * g.P + L.p[t]
+        *(st ? g.part + ((size_t)g.slot_of[u] * g.C + c) * g.P + L.p[t] : L.wdummy + L.lane) = y[t];
+        int32_t* sp = ((info & kWalkRoot) && L.cl == 0 && L.valid[t]) ? g.root_scales + L.p[t]
                                                                        : reinterpret_cast<int32_t*>(L.wdummy + 64) + L.lane;
         *sp = E[t];
       }
@@ -437,8 +438,8 @@ __device__ inline void fetch_op_m(const WalkArgs<float>& g, const LaneM<NT>& L, 
   const uint32_t tb_bytes = (uint32_t)g.P, nb = (uint32_t)g.C * g.P * 16;
   const auto rta = rsrc(g.tips + (size_t)(ka == kWalkTip ? op.a : 0) * g.P, tb_bytes);
   const auto rtb = rsrc(g.tips + (size_t)(kb == kWalkTip ? op.b : 0) * g.P, tb_bytes);
-  const auto rxa = rsrc(g.part + (size_t)(ka == kWalkHbm ? op.a - g.N : 0) * g.C * g.P, nb);
-  const auto rxb = rsrc(g.part + (size_t)(kb == kWalkHbm ? op.b - g.N : 0) * g.C * g.P, nb);
+  const auto rxa = rsrc(g.part + (size_t)(ka == kWalkHbm ? g.slot_of[op.a] : 0) * g.C * g.P, nb);
+  const auto rxb = rsrc(g.part + (size_t)(kb == kWalkHbm ? g.slot_of[op.b] : 0) * g.C * g.P, nb);
   const uint32_t mta = ka == kWalkTip ? 0u : kAbsent, mtb = kb == kWalkTip ? 0u : kAbsent;
   const uint32_t mxa = ka == kWalkHbm ? 0u : kAbsent, mxb = kb == kWalkHbm ? 0u : kAbsent;
 #pragma unroll
@@ -487,7 +488,8 @@ __device__ inline void walk_step_m(const WalkArgs<float>& g, const LaneM<NT>& L,
 
   if (!(info & kWalkPre)) {
     const uint32_t nb = (uint32_t)g.C * g.P * 16;
-    const auto rS = rsrc(g.part + (size_t)(u - g.N) * g.C * g.P, nb);
+    const int su = g.slot_of[u];  // -1 for a node the post-order program does not store
+    const auto rS = rsrc(g.part + (size_t)(su < 0 ? 0 : su) * g.C * g.P, nb);
     const uint32_t mS = (!PRE && (info & kWalkStore)) ? 0u : kAbsent;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -594,7 +596,7 @@ __global__ __launch_bounds__(256) void nuc_walk_mfma_kernel(const WalkArgs<float
     } else {  // the pattern's total exponent, with the root's partial
 #pragma unroll
       for (int t = 0; t < NT; ++t)
-        if (L.valid[t] && L.c == 0) g.scales[(size_t)(g.root - g.N) * g.P + L.p[t]] = E[t];
+        if (L.valid[t] && L.c == 0) g.root_scales[L.p[t]] = E[t];
     }
   }
 }
@@ -665,7 +667,8 @@ WalkArgs<T> walk_args(EpochInstance* in, bool pre) {
   g.PmT = static_cast<const T*>(in->walk_tcol.ptr);
   g.tips = static_cast<const uint8_t*>(in->tips.ptr);
   g.part = static_cast<V4<T>*>(in->partials.ptr);
-  g.scales = static_cast<int32_t*>(in->scales.ptr);
+  g.root_scales = static_cast<int32_t*>(in->scales.ptr) + (size_t)in->root_slot * in->P;
+  g.slot_of = static_cast<const int32_t*>(in->walk_slots.ptr);
   g.pi = static_cast<const double*>(in->pi.ptr);
   g.cat = static_cast<const double*>(in->cat.ptr);
   g.weightsT = static_cast<const T*>(in->weightsT.ptr);
@@ -759,22 +762,83 @@ bool walk_fits(const EpochInstance* in, int slots) {
 // launch per level, each with fewer 16-pattern tiles than there are SIMDs).
 constexpr int kWalkAutoTiles = 1024;
 
+// Bytes an HBM budget must hold for a walk that stores n_stored partials: the
+// partials, the root's scale row and (with gradients) the rows of dlogL/dl shares.
+size_t walk_budget_bytes(const EpochInstance* in, size_t n_stored) {
+  const size_t V = (size_t)in->C * in->P * in->Kp * in->real_size;
+  size_t b = n_stored * V + (size_t)in->P * sizeof(int32_t);
+  if (in->cfg.flags & (EPOCH_GRAD_BRANCH | EPOCH_GRAD_Q))
+    b += walk_dpart_rows_bytes(in) + (size_t)kWalkRowGroups * in->n_nodes * sizeof(double);
+  return b;
+}
+
+// Under an HBM budget: the smallest recomputation threshold (tips per subtree)
+// whose stored partials fit, or -1.
+int walk_budget_threshold(const EpochInstance* in) {
+  const auto& pl = in->plan;
+  const int N = in->N, n = in->n_nodes;
+  std::vector<int> tips(n, 1);
+  for (int u : pl.post) tips[u] = tips[pl.left[u]] + tips[pl.right[u]];
+  std::vector<int> sizes(tips.begin() + N, tips.end());
+  std::sort(sizes.begin(), sizes.end());
+  sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
+  for (int T : sizes) {  // nodes with more than T tips are stored, and the root always
+    if (T < 2) continue;
+    size_t stored = 1;
+    for (int u = N; u < n; ++u) stored += (u != pl.root && tips[u] > T) ? 1 : 0;
+    if (walk_budget_bytes(in, stored) <= (size_t)in->budget) return T;
+  }
+  return -1;
+}
+
 int walk_prepare(EpochInstance* in) {
   in->walk_ok = false;
+  in->root_slot = in->plan.root - in->N;
   if (in->path != 1 || in->walk_enable == 0) return EPOCH_OK;
   if (in->walk_enable < 0 && (in->fp64 || walk_tiles(in) > kWalkAutoTiles)) return EPOCH_OK;
-  const int rt = (in->cfg.flags & EPOCH_GRAD_Q) ? 2 : std::max(2, in->walk_recompute);
-  if (build_walk_programs(in->plan, rt, in->walk) || !walk_fits(in, in->walk.post_slots))
+  int rt = (in->cfg.flags & EPOCH_GRAD_Q) ? 2 : std::max(2, in->walk_recompute);
+  if (in->budget > 0) {
+    rt = walk_budget_threshold(in);
+    if (rt < 0)
+      return set_error(EPOCH_ERR_OOM, "hbm_budget_bytes %lld is below the %zu bytes the root's partial needs",
+                       (long long)in->budget, walk_budget_bytes(in, 1));
+  }
+  const bool built = !build_walk_programs(in->plan, rt, in->walk) && walk_fits(in, in->walk.post_slots);
+  if (!built) {
+    if (in->budget > 0) return set_error(EPOCH_ERR_ARG, "the tree is too deep for the tree walk an HBM budget needs");
     return EPOCH_OK;  // too deep for the stack: level kernels
+  }
+  // partial slots: node - N without a budget (the level kernels' layout); under a
+  // budget, compact slots for the stored nodes, the root first
+  std::vector<int32_t> slot(in->n_nodes, -1);
+  size_t n_stored = 0;
+  if (in->budget > 0) {
+    slot[in->plan.root] = (int32_t)n_stored++;
+    for (int u = in->N; u < in->n_nodes; ++u)
+      if (u != in->plan.root && in->walk.stored[u]) slot[u] = (int32_t)n_stored++;
+    in->root_slot = 0;
+  } else {
+    for (int u = in->N; u < in->n_nodes; ++u) slot[u] = u - in->N;
+  }
   if (!in->fp64) {    // the FP32 walk addresses each node's partials and the gradient rows as buffers below 2^31 bytes
     const size_t groups = ((size_t)walk_tiles(in) + walk_nt_of(in) - 1) / walk_nt_of(in);
-    if ((size_t)in->C * in->P * 16 >= (size_t(1) << 31) || groups * in->n_nodes * 4 >= (size_t(1) << 31))
+    if ((size_t)in->C * in->P * 16 >= (size_t(1) << 31) || groups * in->n_nodes * 4 >= (size_t(1) << 31)) {
+      if (in->budget > 0) return set_error(EPOCH_ERR_ARG, "too many patterns for the FP32 tree walk an HBM budget needs");
       return EPOCH_OK;
+    }
   }
   std::vector<int32_t> ops(in->walk.post);
   ops.insert(ops.end(), in->walk.pre.begin(), in->walk.pre.end());
   int rc = ensure(in->walk_ops, ops.size() * sizeof(int32_t));
   if (!rc) rc = ensure(in->walk_tcol, walk_tcol_bytes(in));
+  if (!rc) rc = ensure(in->walk_slots, slot.size() * sizeof(int32_t));
+  if (!rc && in->budget > 0) {
+    rc = ensure(in->partials, n_stored * (size_t)in->C * in->P * in->Kp * in->real_size);
+    if (!rc) rc = ensure(in->scales, (size_t)in->P * sizeof(int32_t));
+  }
+  if (!rc)
+    rc = hip_check(hipMemcpyAsync(in->walk_slots.ptr, slot.data(), slot.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                  in->stream), "walk slot upload");
   if (!rc && !in->walk_dummy.ptr) {
     rc = ensure(in->walk_dummy, kWalkDummyBytes);
     if (!rc) rc = hip_check(hipMemsetAsync(in->walk_dummy.ptr, 0, kWalkDummyBytes, in->stream), "walk dummy clear");
@@ -788,6 +852,10 @@ int walk_prepare(EpochInstance* in) {
   if (rc) return rc;
   in->walk_ok = true;
   in->walk_pre_ok = walk_fits(in, in->walk.pre_slots);
+  if (in->budget > 0 && !in->walk_pre_ok && (in->cfg.flags & EPOCH_GRAD_BRANCH)) {
+    in->walk_ok = false;
+    return set_error(EPOCH_ERR_ARG, "the tree is too deep for the pre-order walk an HBM budget needs");
+  }
   return EPOCH_OK;
 }
 

@@ -32,7 +32,7 @@ class EpochLikelihood:
     def __init__(self, n_tips: int, n_patterns: int, n_states: int, n_categories: int = 1,
                  n_processes: int = 1, max_intervals: int = 1, precision: str = "fp64",
                  grad_branch: bool = False, grad_Q: bool = False, kernel: str = "auto",
-                 stream=None):
+                 stream=None, hbm_budget_bytes: int = 0):
         lib = _abi.load()
         cfg = _abi.EpochConfig()
         cfg.n_tips = n_tips
@@ -45,6 +45,7 @@ class EpochLikelihood:
         cfg.flags = (_abi.EPOCH_GRAD_BRANCH if grad_branch else 0) | (_abi.EPOCH_GRAD_Q if grad_Q else 0)
         cfg.kernel_path = {"auto": _abi.EPOCH_KERNEL_AUTO, "generic": _abi.EPOCH_KERNEL_GENERIC}[kernel]
         cfg.reserved = 0
+        cfg.hbm_budget_bytes = int(hbm_budget_bytes)
         cfg.stream = stream if stream is not None else _current_stream()
         self._cfg = cfg
         h = ctypes.c_void_p()
@@ -174,10 +175,12 @@ class EpochLikelihood:
 
 
 def from_problem(prob, precision: str = "fp64", grad_branch: bool = False, grad_Q: bool = False,
-                 kernel: str = "auto", use_pi: bool = True, options: Optional[dict] = None) -> EpochLikelihood:
+                 kernel: str = "auto", use_pi: bool = True, options: Optional[dict] = None,
+                 hbm_budget_bytes: int = 0) -> EpochLikelihood:
     """Instance loaded with every input of a generated problem (options: see set_option)."""
     lik = EpochLikelihood(prob.n_tips, prob.n_patterns, prob.n_states, len(prob.cat_rates),
-                          prob.n_processes, prob.n_intervals, precision, grad_branch, grad_Q, kernel)
+                          prob.n_processes, prob.n_intervals, precision, grad_branch, grad_Q, kernel,
+                          hbm_budget_bytes=hbm_budget_bytes)
     for k, v in (options or {}).items():
         lik.set_option(k, v)
     lik.set_tip_states(prob.tips)

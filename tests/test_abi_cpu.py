@@ -46,7 +46,10 @@ def _cfg(**kw):
 @pytest.mark.parametrize("bad", [dict(n_tips=1), dict(n_patterns=0), dict(n_states=1), dict(n_states=65),
                                  dict(n_categories=0), dict(n_categories=9), dict(n_processes=0),
                                  dict(max_intervals=0), dict(precision=3), dict(flags=0x10),
-                                 dict(kernel_path=7), dict(reserved=1)])
+                                 dict(kernel_path=7), dict(reserved=1), dict(hbm_budget_bytes=-1),
+                                 dict(hbm_budget_bytes=1 << 20, n_states=20),
+                                 dict(hbm_budget_bytes=1 << 20, kernel_path=1),
+                                 dict(hbm_budget_bytes=1 << 20, flags=0x2)])
 def test_create_rejects_bad_config_before_touching_the_device(bad):
     lib = _abi.load()
     h = ctypes.c_void_p()

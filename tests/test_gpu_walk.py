@@ -127,3 +127,44 @@ def test_walk_and_level_agree_at_c2_shape():
         b = lik.evaluate(branch=True)
     assert abs(a[0] - b[0]) <= 1e-5 * abs(b[0])
     assert np.linalg.norm(a[2] - b[2]) <= 1e-3 * np.linalg.norm(b[2])
+
+
+def _budget_for(prob, precision, n_stored):
+    """Bytes the library needs to store n_stored partials (plus its root scale row and gradient rows)."""
+    P, C = prob.n_patterns, len(prob.cat_rates)
+    R = 8 if precision == "fp64" else 4
+    n_nodes = 2 * prob.n_tips - 1
+    cp = 1 if C <= 1 else (2 if C <= 2 else (4 if C <= 4 else 8))
+    tiles = -(-P // (64 // cp))
+    rows = -(-(tiles * n_nodes * R) // 256) * 256 + 32 * n_nodes * 8
+    return n_stored * P * C * 4 * R + 4 * P + rows
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("n_stored", [1, 4, 12])
+def test_hbm_budget_recomputes_partials(n_stored, precision):
+    """Under an HBM budget only the partials of the largest subtrees are stored; the
+    gradient pass recomputes the rest from the tip states.  Results match the oracle
+    and the unbudgeted instance."""
+    rng = np.random.default_rng(5700 + n_stored)
+    prob = W.random_problem(rng, 48, 4, 400, n_categories=4, n_intervals=3, reversible=False, missing_frac=0.05)
+    budget = _budget_for(prob, precision, n_stored)
+    with from_problem(prob, precision, grad_branch=True, hbm_budget_bytes=budget) as lik:
+        logL, site, db, _ = lik.evaluate(branch=True, site=True)
+        logL2, _, db2, _ = lik.evaluate(branch=True)  # a second evaluation reuses the compact slots
+    with from_problem(prob, precision, grad_branch=True, options={"tree_walk": 1}) as lik:
+        ref_logL, _, ref_db, _ = lik.evaluate(branch=True)
+    want = O.log_likelihood(prob)
+    assert abs(logL - want) <= TOL_LOGL[precision] * abs(want)
+    assert logL2 == logL and np.array_equal(db, db2)
+    ob, _ = O.gradient(prob, wrt=("branch",))
+    assert np.linalg.norm(db - ob) <= TOL_GRAD[precision] * np.linalg.norm(ob)
+    assert abs(logL - ref_logL) <= TOL_LOGL[precision] * abs(want)
+    assert np.linalg.norm(db - ref_db) <= TOL_GRAD[precision] * np.linalg.norm(ob)
+
+
+def test_hbm_budget_too_small_is_refused():
+    rng = np.random.default_rng(5800)
+    prob = W.random_problem(rng, 20, 4, 300, n_categories=4, n_intervals=2)
+    with pytest.raises(Exception, match="hbm_budget_bytes"):
+        from_problem(prob, "fp32", grad_branch=True, hbm_budget_bytes=_budget_for(prob, "fp32", 1) - 1)
