@@ -88,6 +88,12 @@ typedef struct EpochConfig {
                              * EPOCH_GRAD_Q (dlogL/dQ reads every partial); set_tree_epochs
                              * returns EPOCH_ERR_OOM when even the root alone does not fit. */
   void* stream;            /* hipStream_t to run on, or NULL for the default stream */
+  void* workspace;         /* NULL, or caller-owned device memory (e.g. a torch tensor) of
+                            * workspace_bytes bytes that holds the pattern-sized buffers (tip
+                            * states, weights, partials, outside vectors, scale exponents,
+                            * per-pattern log-likelihoods); it must stay allocated until
+                            * epoch_destroy.  Not combinable with hbm_budget_bytes. */
+  int64_t workspace_bytes; /* >= epoch_workspace_bytes(cfg) when workspace is set */
 } EpochConfig;
 
 /* Message for the last non-zero return on this thread ("" if none). */
@@ -96,8 +102,13 @@ const char* epoch_last_error(void);
 /* Library version string. */
 const char* epoch_version(void);
 
+/* Bytes of caller-owned device memory (EpochConfig.workspace) that hold this
+ * configuration's pattern-sized buffers; *out receives it.  No device work. */
+int epoch_workspace_bytes(const EpochConfig* cfg, int64_t* out);
+
 /* Create an instance: validates cfg (before any HIP call), then allocates the
- * device buffers whose size depends only on cfg.  *out receives the handle. */
+ * device buffers whose size depends only on cfg (the pattern-sized ones inside
+ * cfg->workspace when it is set).  *out receives the handle. */
 int epoch_create(const EpochConfig* cfg, EpochInstance** out);
 
 /* Free every device buffer of the instance (NULL is accepted). */

@@ -37,7 +37,7 @@ EXPORTED = [
     "root_log_likelihood", "log_likelihood_gradient", "epoch_evaluate", "epoch_get_transition_matrices",
     "epoch_plan_segments", "epoch_set_timing", "epoch_get_timing", "epoch_bandwidth_probe",
     "epoch_batch_create", "epoch_batch_evaluate", "epoch_batch_gradients", "epoch_batch_target_blocks",
-    "epoch_batch_destroy", "epoch_set_option", "epoch_plan_walk",
+    "epoch_batch_destroy", "epoch_set_option", "epoch_plan_walk", "epoch_workspace_bytes",
 ]
 EPOCH_EVAL_LOGL = 0x1
 EPOCH_EVAL_GRAD_BRANCH = 0x2
@@ -59,6 +59,8 @@ class EpochConfig(ctypes.Structure):
         ("reserved", ctypes.c_int32),
         ("hbm_budget_bytes", ctypes.c_int64),
         ("stream", ctypes.c_void_p),
+        ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_int64),
     ]
 
 
@@ -113,6 +115,7 @@ def load() -> ctypes.CDLL:
         "epoch_batch_destroy": (i32, [P]),
         "epoch_get_timing": (i32, [P, dp, ctypes.POINTER(ctypes.c_int64)]),
         "epoch_set_option": (i32, [P, i32, ctypes.c_int64]),
+        "epoch_workspace_bytes": (i32, [ctypes.POINTER(EpochConfig), ctypes.POINTER(ctypes.c_int64)]),
         "epoch_plan_walk": (i32, [i32, ip, dp, i32, i32, ip, ip]),
     }
     for name, (res, args) in sig.items():

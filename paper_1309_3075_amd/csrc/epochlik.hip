@@ -39,6 +39,7 @@ int hip_check(hipError_t e, const char* what) {
 int ensure(DevBuf& b, size_t bytes) {
   if (bytes == 0) bytes = 256;
   if (b.ptr && b.bytes >= bytes) return EPOCH_OK;
+  if (b.borrowed) return set_error(EPOCH_ERR_OOM, "a workspace buffer of %zu bytes cannot grow to %zu", b.bytes, bytes);
   if (b.ptr) {
     (void)hipFree(b.ptr);
     b.ptr = nullptr;
@@ -91,9 +92,34 @@ namespace {
 constexpr double kCondFP32 = 32.0;
 
 void release(DevBuf& b) {
-  if (b.ptr) (void)hipFree(b.ptr);
+  if (b.ptr && !b.borrowed) (void)hipFree(b.ptr);
+  b.borrowed = false;
   b.ptr = nullptr;
   b.bytes = 0;
+}
+
+// The pattern-sized buffers a caller-owned workspace holds, in order, with their sizes.
+struct WorkspaceItem {
+  DevBuf EpochInstance::*buf;
+  size_t bytes;
+};
+std::vector<WorkspaceItem> workspace_items(const EpochConfig& c, int Kp) {
+  const size_t N = c.n_tips, P = c.n_patterns, C = c.n_categories, R = c.precision == EPOCH_FP64 ? 8 : 4;
+  const bool grad = (c.flags & (EPOCH_GRAD_BRANCH | EPOCH_GRAD_Q)) != 0;
+  std::vector<WorkspaceItem> v = {{&EpochInstance::tips, N * P},
+                                  {&EpochInstance::weights, P * sizeof(double)},
+                                  {&EpochInstance::weightsT, P * R},
+                                  {&EpochInstance::partials, (N - 1) * C * P * Kp * R},
+                                  {&EpochInstance::scales, (N - 1) * P * sizeof(int32_t)},
+                                  {&EpochInstance::site, P * sizeof(double)}};
+  if (grad) v.push_back({&EpochInstance::pre, (N - 1) * C * P * Kp * R});
+  return v;
+}
+size_t aligned256(size_t b) { return (b + 255) / 256 * 256; }
+size_t workspace_total(const EpochConfig& c, int Kp) {
+  size_t t = 0;
+  for (const auto& it : workspace_items(c, Kp)) t += aligned256(it.bytes);
+  return t;
 }
 
 int padded_states(int K) {
@@ -176,6 +202,13 @@ int epoch_create(const EpochConfig* cfg, EpochInstance** out) {
     return set_error(EPOCH_ERR_ARG, "hbm_budget_bytes needs the 4-state kernels (n_states 4, EPOCH_KERNEL_AUTO)");
   if (c.hbm_budget_bytes > 0 && (c.flags & EPOCH_GRAD_Q))
     return set_error(EPOCH_ERR_ARG, "hbm_budget_bytes cannot be combined with EPOCH_GRAD_Q");
+  if (c.workspace && c.hbm_budget_bytes > 0)
+    return set_error(EPOCH_ERR_ARG, "a workspace cannot be combined with hbm_budget_bytes");
+  if (c.workspace && (c.workspace_bytes < 0 || (size_t)c.workspace_bytes < workspace_total(c, padded_states(c.n_states))))
+    return set_error(EPOCH_ERR_ARG, "workspace_bytes %lld is below the %zu bytes epoch_workspace_bytes asks for",
+                     (long long)c.workspace_bytes, workspace_total(c, padded_states(c.n_states)));
+  if (c.workspace && (reinterpret_cast<uintptr_t>(c.workspace) & 255))
+    return set_error(EPOCH_ERR_ARG, "workspace must be 256-byte aligned");
   const size_t N = c.n_tips, P = c.n_patterns;
   if ((N - 1) * P > ((size_t)1 << 40)) return set_error(EPOCH_ERR_ARG, "problem too large");
 
@@ -210,6 +243,16 @@ int epoch_create(const EpochConfig* cfg, EpochInstance** out) {
   in->cond.assign(S, 1.0);
   in->n_chunks = choose_chunks(in);
   int rc = EPOCH_OK;
+  if (c.workspace) {  // pattern-sized buffers inside the caller's memory
+    size_t off = 0;
+    for (const auto& it : workspace_items(c, (int)Kp)) {
+      DevBuf& b = in->*(it.buf);
+      b.ptr = static_cast<char*>(c.workspace) + off;
+      b.bytes = std::max<size_t>(it.bytes, 256);
+      b.borrowed = true;
+      off += aligned256(it.bytes);
+    }
+  }
   auto A = [&](DevBuf& b, size_t bytes) {
     if (rc == EPOCH_OK) rc = ensure(b, bytes);
   };
@@ -733,6 +776,16 @@ int epoch_plan_segments(int32_t n_tips, const int32_t* parent, const double* hei
   if (nseg > capacity) return set_error(EPOCH_ERR_ARG, "capacity %d < %d segments", capacity, nseg);
   std::copy(plan.seg_process.begin(), plan.seg_process.end(), seg_process);
   std::copy(plan.seg_time.begin(), plan.seg_time.end(), seg_time);
+  return EPOCH_OK;
+}
+
+int epoch_workspace_bytes(const EpochConfig* cfg, int64_t* out) {
+  g_error.clear();
+  if (!cfg || !out) return set_error(EPOCH_ERR_ARG, "cfg and out must not be NULL");
+  if (cfg->n_tips < 2 || cfg->n_patterns < 1 || cfg->n_states < 2 || cfg->n_states > 64 || cfg->n_categories < 1 ||
+      cfg->n_categories > kMaxCategories || (cfg->precision != EPOCH_FP32 && cfg->precision != EPOCH_FP64))
+    return set_error(EPOCH_ERR_ARG, "invalid configuration");
+  *out = (int64_t)workspace_total(*cfg, padded_states(cfg->n_states));
   return EPOCH_OK;
 }
 

@@ -15,6 +15,7 @@ namespace epochlik {
 struct DevBuf {
   void* ptr = nullptr;
   size_t bytes = 0;
+  bool borrowed = false;  // part of a caller-owned workspace: never freed or reallocated
 };
 
 // Device-visible description of one problem for the 64-state kernels (one

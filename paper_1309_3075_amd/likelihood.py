@@ -32,7 +32,7 @@ class EpochLikelihood:
     def __init__(self, n_tips: int, n_patterns: int, n_states: int, n_categories: int = 1,
                  n_processes: int = 1, max_intervals: int = 1, precision: str = "fp64",
                  grad_branch: bool = False, grad_Q: bool = False, kernel: str = "auto",
-                 stream=None, hbm_budget_bytes: int = 0):
+                 stream=None, hbm_budget_bytes: int = 0, workspace=None):
         lib = _abi.load()
         cfg = _abi.EpochConfig()
         cfg.n_tips = n_tips
@@ -47,6 +47,11 @@ class EpochLikelihood:
         cfg.reserved = 0
         cfg.hbm_budget_bytes = int(hbm_budget_bytes)
         cfg.stream = stream if stream is not None else _current_stream()
+        # caller-owned device memory for the pattern-sized buffers: a torch tensor (kept alive here)
+        self._workspace = workspace
+        if workspace is not None:
+            cfg.workspace = workspace.data_ptr()
+            cfg.workspace_bytes = workspace.numel() * workspace.element_size()
         self._cfg = cfg
         h = ctypes.c_void_p()
         check(lib.epoch_create(ctypes.byref(cfg), ctypes.byref(h)))
@@ -55,6 +60,19 @@ class EpochLikelihood:
         self.n_tips, self.n_patterns, self.n_states = n_tips, n_patterns, n_states
         self.n_categories, self.n_processes = n_categories, n_processes
         self.n_nodes = 2 * n_tips - 1
+
+    @staticmethod
+    def workspace_bytes(n_tips: int, n_patterns: int, n_states: int, n_categories: int = 1,
+                        precision: str = "fp64", grad_branch: bool = False, grad_Q: bool = False) -> int:
+        """Bytes of the optional caller-owned workspace (epoch_workspace_bytes)."""
+        cfg = _abi.EpochConfig()
+        cfg.n_tips, cfg.n_patterns, cfg.n_states, cfg.n_categories = n_tips, n_patterns, n_states, n_categories
+        cfg.n_processes, cfg.max_intervals = 1, 1
+        cfg.precision = {"fp32": _abi.EPOCH_FP32, "fp64": _abi.EPOCH_FP64}[precision]
+        cfg.flags = (_abi.EPOCH_GRAD_BRANCH if grad_branch else 0) | (_abi.EPOCH_GRAD_Q if grad_Q else 0)
+        out = ctypes.c_int64(0)
+        check(_abi.load().epoch_workspace_bytes(ctypes.byref(cfg), ctypes.byref(out)))
+        return out.value
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -176,11 +194,11 @@ class EpochLikelihood:
 
 def from_problem(prob, precision: str = "fp64", grad_branch: bool = False, grad_Q: bool = False,
                  kernel: str = "auto", use_pi: bool = True, options: Optional[dict] = None,
-                 hbm_budget_bytes: int = 0) -> EpochLikelihood:
+                 hbm_budget_bytes: int = 0, workspace=None) -> EpochLikelihood:
     """Instance loaded with every input of a generated problem (options: see set_option)."""
     lik = EpochLikelihood(prob.n_tips, prob.n_patterns, prob.n_states, len(prob.cat_rates),
                           prob.n_processes, prob.n_intervals, precision, grad_branch, grad_Q, kernel,
-                          hbm_budget_bytes=hbm_budget_bytes)
+                          hbm_budget_bytes=hbm_budget_bytes, workspace=workspace)
     for k, v in (options or {}).items():
         lik.set_option(k, v)
     lik.set_tip_states(prob.tips)

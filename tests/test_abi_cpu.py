@@ -162,3 +162,31 @@ def test_host_eigensystem_real_form():
     Q2 = W.gtr(rng.dirichlet(np.ones(6)), pi)
     e2 = eigensystem(Q2, pi)
     np.testing.assert_allclose(e2.V @ np.diag(e2.lambda_re) @ e2.Vinv, Q2, atol=1e-13)
+
+
+def test_workspace_bytes_covers_the_pattern_sized_buffers():
+    lib = _abi.load()
+    out = ctypes.c_int64(0)
+    c = _cfg(n_tips=10, n_patterns=1000, n_states=4, n_categories=4, flags=_abi.EPOCH_GRAD_BRANCH)
+    assert lib.epoch_workspace_bytes(ctypes.byref(c), ctypes.byref(out)) == _abi.EPOCH_OK
+    N, P, C, R = 10, 1000, 4, 8
+    need = N * P + 8 * P + R * P + 2 * (N - 1) * C * P * 4 * R + 4 * (N - 1) * P + 8 * P
+    assert need <= out.value <= need + 7 * 256
+    c.flags = 0
+    small = ctypes.c_int64(0)
+    assert lib.epoch_workspace_bytes(ctypes.byref(c), ctypes.byref(small)) == _abi.EPOCH_OK
+    assert small.value < out.value  # no outside vectors without gradients
+    assert lib.epoch_workspace_bytes(ctypes.byref(_cfg(n_states=65)), ctypes.byref(out)) == _abi.EPOCH_ERR_ARG
+
+
+def test_workspace_too_small_or_misaligned_is_refused_before_the_device():
+    lib = _abi.load()
+    c = _cfg(n_tips=6, n_patterns=100)
+    need = ctypes.c_int64(0)
+    assert lib.epoch_workspace_bytes(ctypes.byref(c), ctypes.byref(need)) == _abi.EPOCH_OK
+    h = ctypes.c_void_p()
+    for ws, nbytes in [(1 << 20, need.value - 1), ((1 << 20) + 8, need.value), (1 << 20, need.value)]:
+        c.workspace, c.workspace_bytes = ws, nbytes
+        c.hbm_budget_bytes = 1 << 30 if nbytes == need.value and ws == 1 << 20 else 0
+        assert lib.epoch_create(ctypes.byref(c), ctypes.byref(h)) == _abi.EPOCH_ERR_ARG
+        assert not h.value

@@ -168,3 +168,20 @@ def test_hbm_budget_too_small_is_refused():
     prob = W.random_problem(rng, 20, 4, 300, n_categories=4, n_intervals=2)
     with pytest.raises(Exception, match="hbm_budget_bytes"):
         from_problem(prob, "fp32", grad_branch=True, hbm_budget_bytes=_budget_for(prob, "fp32", 1) - 1)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_caller_owned_workspace(precision):
+    """Pattern-sized buffers inside a torch tensor give the same results as library-owned ones."""
+    import torch
+    from paper_1309_3075_amd.likelihood import EpochLikelihood
+    rng = np.random.default_rng(5900)
+    prob = W.random_problem(rng, 30, 4, 700, n_categories=4, n_intervals=3, reversible=False)
+    nbytes = EpochLikelihood.workspace_bytes(prob.n_tips, prob.n_patterns, 4, 4, precision, grad_branch=True)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    with from_problem(prob, precision, grad_branch=True, workspace=ws) as lik:
+        a = lik.evaluate(branch=True, site=True)
+    torch.cuda.synchronize()
+    with from_problem(prob, precision, grad_branch=True) as lik:
+        b = lik.evaluate(branch=True, site=True)
+    assert a[0] == b[0] and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
