@@ -132,7 +132,7 @@ struct EpochInstance {
   epochlik::DevBuf weightsT;   // T [P]
   epochlik::DevBuf pi;         // double [Kp]
   epochlik::DevBuf cat;        // double rates[8], weights[8]
-  epochlik::DevBuf tree_i;     // int32: parent, left, right [n], level_nodes [N-1], seg_offset [n+1], seg_process [nseg], walk [N-1]
+  epochlik::DevBuf tree_i;     // int32: parent, left, right [n], level_nodes [N-1], seg_offset [n+1], seg_process [nseg]
   epochlik::DevBuf tree_d;     // double: rate [n], tau [n], seg_time [nseg], seg_frac [nseg]
   epochlik::DevBuf Pm;         // T [n][C][Kp][Kp]
   epochlik::DevBuf dPm;        // T [n][C][Kp][Kp]
@@ -167,7 +167,7 @@ struct EpochInstance {
 
   // device pointers into tree_i / tree_d
   int32_t *d_parent = nullptr, *d_left = nullptr, *d_right = nullptr, *d_level_nodes = nullptr,
-          *d_seg_offset = nullptr, *d_seg_process = nullptr, *d_walk = nullptr;
+          *d_seg_offset = nullptr, *d_seg_process = nullptr;
   double *d_rate = nullptr, *d_tau = nullptr, *d_seg_time = nullptr, *d_seg_frac = nullptr;
 };
 

@@ -168,35 +168,6 @@ int plan_tree(int n_tips, const int32_t* parent, const double* height, const dou
     P.max_segments = std::max<int>(P.max_segments, (int)(P.seg_process.size() - before));
   }
   P.seg_offset[n] = (int32_t)P.seg_process.size();
-  // Strahler-ordered walk: visit the child needing more stack slots first.
-  {
-    std::vector<int32_t> need(n, 0);
-    for (int u : P.post) {
-      int a = need[P.left[u]], b = need[P.right[u]];
-      if (P.left[u] < N && P.right[u] < N)
-        need[u] = 1;
-      else
-        need[u] = (a == b) ? a + 1 : std::max(a, b);
-    }
-    P.stack_depth = need[P.root];
-    std::vector<std::pair<int, int>> st;  // (node, expanded)
-    st.push_back({P.root, 0});
-    while (!st.empty()) {
-      auto& top = st.back();
-      int u = top.first;
-      if (top.second) {
-        P.walk.push_back(u);
-        st.pop_back();
-        continue;
-      }
-      top.second = 1;
-      int a = P.left[u], b = P.right[u];
-      if (need[b] > need[a]) std::swap(a, b);
-      // push second child first so the first child is processed first
-      if (b >= N) st.push_back({b, 0});
-      if (a >= N) st.push_back({a, 0});
-    }
-  }
   out = std::move(P);
   return 0;
 }

@@ -31,10 +31,6 @@ struct TreePlan {
   std::vector<double> seg_time;      // [n_seg] duration in height units
   std::vector<double> seg_frac;      // [n_seg] duration / tau (0 when tau == 0)
   int max_segments = 0;              // longest segment list of any branch
-  // Strahler-ordered post-order walk for the register-stack kernels:
-  // for every internal node in walk order, which child is visited first
-  std::vector<int32_t> walk;          // internal nodes, children before parents
-  int stack_depth = 0;                // max simultaneously pending partials
 };
 
 // Programs of the four-state tree-walk kernels (one wavefront carries a tile of
