@@ -185,6 +185,7 @@ EPOCH_OPT_WALK_RECOMPUTE = 2
 EPOCH_OPT_WALK_BLOCKS = 3
 EPOCH_OPT_WALK_TILES = 4
 EPOCH_OPT_LEVEL_MIN_TILES = 5
+EPOCH_OPT_SPLIT_BLOCKS = 6
 
 
 def plan_walk(parent, height, recompute_tips: int = 2):

@@ -31,6 +31,7 @@ struct EpochBatch {
   hipStream_t stream = nullptr;
   bool merged = false;  // every member is on the 64-state path
   int target_blocks = 1024;
+  int split_blocks = 256;  // narrow pre-order levels use the side-split kernel
   std::string tune_path;
   CodonSchedule sched;
   DevBuf dev;                  // descriptors + items + reduce items
@@ -122,6 +123,7 @@ int build_schedule(EpochBatch* b) {
   std::vector<const EpochInstance*> cin(b->insts.begin(), b->insts.end());
   std::vector<std::vector<int32_t>> gs;
   codon_build_schedule(cin, b->target_blocks, b->sched, gs);
+  b->sched.split_blocks = b->split_blocks;
   const size_t n = b->insts.size();
   const auto& sc = b->sched;
   size_t total = 0;

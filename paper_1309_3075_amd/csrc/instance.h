@@ -70,6 +70,7 @@ struct CodonSchedule {
   std::vector<int2> reduce_items;  // every (problem, node)
   std::vector<size_t> slot_total;  // dlogL/dP partial slots of each problem
   int n_levels = 0, max_tiles = 0, max_pattern_blocks = 0, n_problems = 0;
+  int split_blocks = 0;  // pre-order levels of at most this many blocks put each child branch on its own wavefronts
 };
 
 }  // namespace epochlik
@@ -157,6 +158,7 @@ struct EpochInstance {
   epochlik::DevBuf codon_aux;  // 64-state path: per-chunk shares of dlogL/dl (double)
   epochlik::CodonSchedule codon_sched;
   int codon_target_blocks = 1024;  // blocks per pre-order launch the 64-state schedule aims for
+  int codon_split_blocks = 256;    // narrow pre-order levels (at most this many blocks) use the side-split kernel
 
   // per-phase timing (epoch_set_timing)
   bool timing = false;

@@ -61,17 +61,22 @@ __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Stage a 64x64 row-major matrix into LDS with row stride LDP.
-__device__ inline void stage_matrix(float* __restrict__ s, const float* __restrict__ g) {
+// Stage a 64x64 row-major matrix into LDS with row stride LDP (256 threads,
+// t = 0 .. 255).
+__device__ inline void stage_matrix(float* __restrict__ s, const float* __restrict__ g, int t) {
   const EPOCH_GLOBAL f4* src = gptr(reinterpret_cast<const f4*>(g));
-  for (int e = threadIdx.x; e < KK / 4; e += 256) {
+  for (int e = t; e < KK / 4; e += 256) {
     const int row = e >> 4, c4 = e & 15;
     *reinterpret_cast<f4*>(s + row * LDP + 4 * c4) = src[e];
   }
 }
-// Row sums over the first K columns into column 64 (needs the staged matrix).
-__device__ inline void stage_row_sums(float* __restrict__ s, int K) {
-  const int row = threadIdx.x >> 2, q = threadIdx.x & 3;
+__device__ inline void stage_matrix(float* __restrict__ s, const float* __restrict__ g) {
+  stage_matrix(s, g, threadIdx.x);
+}
+// Row sums over the first K columns into column 64 (needs the staged matrix;
+// 256 threads, t = 0 .. 255).
+__device__ inline void stage_row_sums(float* __restrict__ s, int K, int t) {
+  const int row = t >> 2, q = t & 3;
   float acc = 0.f;
 #pragma unroll
   for (int j = 0; j < 16; ++j) acc += (16 * q + j < K) ? s[row * LDP + 16 * q + j] : 0.f;
@@ -79,6 +84,7 @@ __device__ inline void stage_row_sums(float* __restrict__ s, int K) {
   acc += __shfl_xor(acc, 2, 4);
   if (q == 0) s[row * LDP + 64] = acc;
 }
+__device__ inline void stage_row_sums(float* __restrict__ s, int K) { stage_row_sums(s, K, threadIdx.x); }
 
 // Row-max / row-sum over the 16 lanes of a DPP row (lanes sharing g).
 __device__ inline float row16_max(float v) {
@@ -460,6 +466,182 @@ __global__ __launch_bounds__(256, 2) void codon_pre_level_kernel(const CodonProb
   }
 }
 
+// The same step with the two child branches on separate wavefronts, for
+// levels too narrow to fill the GPU.  Eight wavefronts per block: wavefront
+// 4 s + w takes side s (0: left child, 1: right child) of patterns 16 w ..
+// 16 w + 15 of each 64-pattern tile.  The child vectors are swapped through
+// LDS, so each wavefront runs one child product, one outside-vector product
+// and its side's dlogL/dP rows per tile, half the serial work of the kernel
+// above.  Tiles, slots and the order of every sum are those of the kernel
+// above, so both give the same bits.
+struct PreSplitShared {
+  __align__(16) float sP[2][KP * LDP];    // P_left, P_right with row sums
+  __align__(16) float sS[2][TILE * LDP];  // each side's child vectors for the block tile
+  __align__(16) float sT[2][TILE * LDP];  // each side's t = q o S_sibling
+  __align__(16) float sL[2][TILE * LDP];  // each side's child partials
+  float sCF[TILE];
+  int sCol[2][TILE];
+};
+
+struct SplitTileLoads {
+  f4 L[4];  // 16-byte rows of this side's child partials (internal child)
+  f4 Q[4];  // q_u in the D layout
+  int col[4];
+};
+
+__device__ inline void split_load_tile(SplitTileLoads& ld, const CodonProblem& pr, const float* Lc, const float* Qu,
+                                       int c, int p0, int g, int r) {
+  const int P = pr.P;
+  if (Lc) {
+    const EPOCH_GLOBAL f4* row = gptr(reinterpret_cast<const f4*>(Lc + (size_t)min(p0 + r, P - 1) * KP)) + g;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) ld.L[t] = row[4 * t];
+  } else {
+    tip_columns(ld.col, pr.tips + (size_t)c * P, P, p0, pr.K, g);
+  }
+  if (Qu) load_dlayout(ld.Q, Qu, P, p0, g, r);
+}
+
+__global__ __launch_bounds__(512, 1) void codon_pre_split_kernel(const CodonProblem* __restrict__ probs,
+                                                                const int2* __restrict__ items, int R) {
+  __shared__ PreSplitShared sh;
+  const int2 it = items[blockIdx.y];
+  const CodonProblem& pr = probs[it.x];
+  const int N = pr.N, P = pr.P, K = pr.K;
+  const int base = blockIdx.x * R * TILE;
+  if (base >= P) return;  // uniform: this problem has fewer tiles
+  const int n_tiles = min(R, (P - base + TILE - 1) / TILE);  // uniform over the block
+  const int u = it.y;
+  const int a = pr.left[u], b = pr.right[u];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, w = wave & 3, s = wave >> 2;
+  const int g = lane >> 4, r = lane & 15;
+  const int c = s ? b : a;
+  {  // threads 0..255 stage P_left, 256..511 P_right
+    const int h = threadIdx.x >> 8;
+    stage_matrix(sh.sP[h], pr.Pm + (size_t)(h ? b : a) * KK, threadIdx.x & 255);
+    __syncthreads();
+    stage_row_sums(sh.sP[h], K, threadIdx.x & 255);
+    __syncthreads();
+  }
+  const float* sPc = sh.sP[s];
+  const float* Lc = c >= N ? pr.part + (size_t)(c - N) * P * KP : nullptr;
+  const float* Qu = u == pr.root ? nullptr : pr.pre + (size_t)(u - N) * P * KP;
+  float piv[4];
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) piv[nt] = 16 * nt + r < K ? (float)pr.pi[16 * nt + r] : 0.f;
+  f4 G[4];
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) G[nt] = f4{0.f, 0.f, 0.f, 0.f};
+  SplitTileLoads cur, nxt;
+  split_load_tile(cur, pr, Lc, Qu, c, base + WT * w, g, r);
+  float* srows = sh.sS[s] + (WT * w) * LDP;
+  const float* sibrows = sh.sS[1 - s] + (WT * w) * LDP;
+  float* trows = sh.sT[s] + (WT * w) * LDP;
+  float* lrows = sh.sL[s] + (WT * w) * LDP;
+  for (int bt = 0; bt < n_tiles; ++bt) {
+    const int p0 = base + bt * TILE + WT * w;
+    f4 S[4];
+    if (Lc)
+      child_gemm_regs(S, cur.L, sPc, g, r);
+    else
+      tip_lookup(S, cur.col, sPc, r);
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) srows[(4 * g + v) * LDP + 16 * nt + r] = S[nt][v];
+    // the other side's child vectors of the same patterns are in LDS after this
+    // barrier; every wavefront has also finished the previous tile's dlogL/dP
+    __syncthreads();
+    f4 So[4], Q[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) So[nt][v] = sibrows[(4 * g + v) * LDP + 16 * nt + r];
+      Q[nt] = Qu ? cur.Q[nt] : f4{piv[nt], piv[nt], piv[nt], piv[nt]};
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      if (s == 0) {  // uniform; S is the left child's vector, So the right child's
+        float sum = 0.f;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) sum += Q[nt][v] * S[nt][v] * So[nt][v];
+        sum = row16_sum(sum);
+        const int p = p0 + 4 * g + v;
+        if (r == 0) sh.sCF[WT * w + 4 * g + v] = (p < P && sum > 0.f) ? gptr(pr.weightsT)[p] / sum : 0.f;
+      }
+      if (r == 0 && !Lc) sh.sCol[s][WT * w + 4 * g + v] = cur.col[v];
+    }
+    if (bt + 1 < n_tiles) split_load_tile(nxt, pr, Lc, Qu, c, p0 + TILE, g, r);
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) trows[(4 * g + v) * LDP + 16 * nt + r] = Q[nt][v] * So[nt][v];
+    if (Lc) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) *reinterpret_cast<f4*>(lrows + r * LDP + 16 * t + 4 * g) = cur.L[t];
+    }
+    wave_lds_sync();
+    if (Lc) {
+      f4 ta[4];
+#pragma unroll
+      for (int tt = 0; tt < 4; ++tt) ta[tt] = *reinterpret_cast<const f4*>(trows + r * LDP + 16 * tt + 4 * g);
+      f4 Qo[4];
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) Qo[nt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+          const float* prow = sPc + (16 * tt + 4 * g) * LDP + 16 * nt + r;
+          Qo[nt] = mfma(ta[tt].x, prow[0], Qo[nt]);
+          Qo[nt] = mfma(ta[tt].y, prow[LDP], Qo[nt]);
+          Qo[nt] = mfma(ta[tt].z, prow[2 * LDP], Qo[nt]);
+          Qo[nt] = mfma(ta[tt].w, prow[3 * LDP], Qo[nt]);
+        }
+      EPOCH_GLOBAL float* out = gptr(pr.pre + (size_t)(c - N) * P * KP);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        float m = 0.f;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) m = fmaxf(m, Qo[nt][v]);
+        const int e = scale_exponent(row16_max(m));
+        const int p = p0 + 4 * g + v;
+        if (p < P)
+#pragma unroll
+          for (int nt = 0; nt < 4; ++nt) out[(size_t)p * KP + 16 * nt + r] = ldexpf(Qo[nt][v], -e);
+      }
+    }
+    __syncthreads();  // t, L, w_p / L_p and tip columns of the whole tile are in LDS
+    const float* tcol = sh.sT[s] + WT * w + r;
+    const float* sL = sh.sL[s];
+#pragma unroll 8
+    for (int ks = 0; ks < TILE / 4; ++ks) {
+      const int pl = 4 * ks + g;
+      const float av = tcol[pl * LDP] * sh.sCF[pl];
+      f4 B;
+      if (Lc) {
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) B[nt] = sL[pl * LDP + 16 * nt + r];
+      } else {
+        const int col = sh.sCol[s][pl];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+          const int j = 16 * nt + r;
+          B[nt] = (col == j || (col == 64 && j < K)) ? 1.f : 0.f;
+        }
+      }
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) G[nt] = mfma(av, B[nt], G[nt]);
+    }
+    if (bt + 1 < n_tiles) cur = nxt;
+  }
+  EPOCH_GLOBAL float* dst = gptr(pr.Gpart + ((size_t)pr.gslots[pr.n_nodes + c] + blockIdx.x) * KK);
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) dst[(WT * w + 4 * g + v) * KP + 16 * nt + r] = G[nt][v];
+}
+
 // G[v] = sum of the FP32 slot partials in FP64 (fixed order): one block per
 // (branch, 256 entries); also the block's share of <G, dP/dl>.
 constexpr int kReduceChunks = KK / 256;
@@ -619,7 +801,10 @@ int codon_launch_pre_grad(const CodonSchedule& sc, const CodonProblem* d_probs, 
     if (!n) continue;
     const int R = sc.level_R[l - 1];
     const int blocks = (sc.max_tiles + R - 1) / R;
-    hipLaunchKernelGGL(codon_pre_level_kernel, dim3(blocks, n), dim3(256), 0, st, d_probs, d_items + b, R);
+    if ((long)blocks * n <= sc.split_blocks)
+      hipLaunchKernelGGL(codon_pre_split_kernel, dim3(blocks, n), dim3(512), 0, st, d_probs, d_items + b, R);
+    else
+      hipLaunchKernelGGL(codon_pre_level_kernel, dim3(blocks, n), dim3(256), 0, st, d_probs, d_items + b, R);
   }
   int rc = hip_check(hipGetLastError(), "codon_pre_level launch");
   if (rc) return rc;
@@ -635,6 +820,7 @@ int codon_launch_pre_grad(const CodonSchedule& sc, const CodonProblem* d_probs, 
 int codon_prepare(EpochInstance* in) {
   std::vector<std::vector<int32_t>> gslots;
   codon_build_schedule({in}, in->codon_target_blocks, in->codon_sched, gslots);
+  in->codon_sched.split_blocks = in->codon_split_blocks;
   const auto& sc = in->codon_sched;
   const bool grad = (in->cfg.flags & (EPOCH_GRAD_BRANCH | EPOCH_GRAD_Q)) != 0;
   int rc = ensure(in->gslots, gslots[0].size() * sizeof(int32_t));

@@ -29,8 +29,8 @@ struct cplx {
 };
 __device__ inline cplx cmul(cplx a, cplx b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
 __device__ inline cplx cdiv(cplx a, cplx b) {
-  const double d = b.re * b.re + b.im * b.im;
-  return {(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
+  const double inv = 1.0 / (b.re * b.re + b.im * b.im);
+  return {(a.re * b.re + a.im * b.im) * inv, (a.im * b.re - a.re * b.im) * inv};
 }
 // e^z - 1 without cancellation for small |z|
 __device__ inline cplx cexpm1(cplx z) {
@@ -470,13 +470,16 @@ __device__ inline cplx divided_difference_from_exp(cplx Ea, cplx Eb, cplx d) {
   const double ad = fabs(d.re) + fabs(d.im);
   if (ad > 0.25) return cdiv(cplx{Ea.re - Eb.re, Ea.im - Eb.im}, d);
   // (e^d - 1)/d = sum_{k>=0} d^k / (k+1)! = 1 + d/2 (1 + d/3 (1 + ... (1 + d/15))),
-  // terms through d^14/15!: the remainder is below 0.25^15 / 16! ~ 4e-23
+  // terms through d^14/15!: the remainder is below 0.25^15 / 16! ~ 4e-23.  Each
+  // step multiplies by the correctly rounded constant 1/k (no division).
   cplx s = {1.0, 0.0};
 #pragma unroll
   for (int k = 15; k >= 2; --k) {
+    constexpr double one = 1.0;
+    const double inv_k = one / (double)k;  // folded to a constant once the loop is unrolled
     s = cmul(s, d);
-    s.re = 1.0 + s.re / (double)k;
-    s.im = s.im / (double)k;
+    s.re = 1.0 + s.re * inv_k;
+    s.im = s.im * inv_k;
   }
   return cmul(Eb, s);
 }
@@ -554,8 +557,8 @@ __global__ __launch_bounds__(256) void qgrad_hsum_kernel(int KK, int n_chunks, c
 
 // dQ_s = V^-T Re(T^-T H_s T^T) V^T.  Block (s, band) forms rows 16 band ..
 // 16 band + 15: X = Re(T^-T H T^T) in LDS, then those rows of Y = V^-T X
-// (columns of V^-1 from global), then dQ rows = Y_rows V^T with V replacing X
-// in LDS (Kp^2 + 16 Kp doubles).
+// (the 16 columns of V^-1 staged in LDS), then dQ rows = Y_rows V^T with V
+// replacing X in LDS (Kp^2 + 32 Kp doubles).
 __global__ __launch_bounds__(256) void qgrad_final_kernel(int K, int Kp, const double* __restrict__ Hsum,
                                                           const double* __restrict__ V, const double* __restrict__ Vi,
                                                           const double* __restrict__ li_all, double* __restrict__ dQ) {
@@ -563,9 +566,12 @@ __global__ __launch_bounds__(256) void qgrad_final_kernel(int K, int Kp, const d
   const int s = blockIdx.x, r0 = 16 * blockIdx.y;
   const int KK = Kp * Kp;
   double* sX = reinterpret_cast<double*>(smem_raw);
-  double* sY = sX + KK;  // 16 x Kp
+  double* sY = sX + KK;        // 16 x Kp
+  double* sVi = sY + 16 * Kp;  // Kp x 16: columns r0 .. r0 + 15 of V^-1
   const double* li = li_all + (size_t)s * Kp;
   const double2* H = reinterpret_cast<const double2*>(Hsum) + (size_t)s * KK;
+  const double* Vis = Vi + (size_t)s * KK;
+  for (int e = threadIdx.x; e < 16 * Kp; e += 256) sVi[e] = Vis[(e >> 4) * Kp + r0 + (e & 15)];
   for (int e = threadIdx.x; e < KK; e += 256) {
     const int a = e / Kp, b = e % Kp;
     const PairIdx pa = pair_of(li, a), pb = pair_of(li, b);
@@ -584,11 +590,10 @@ __global__ __launch_bounds__(256) void qgrad_final_kernel(int K, int Kp, const d
     sX[e] = re;
   }
   __syncthreads();
-  const double* Vis = Vi + (size_t)s * KK;
   for (int e = threadIdx.x; e < 16 * Kp; e += 256) {
-    const int i = r0 + e / Kp, j = e % Kp;
+    const int ii = e / Kp, j = e % Kp;
     double r = 0.0;
-    for (int l = 0; l < Kp; ++l) r += Vis[l * Kp + i] * sX[l * Kp + j];
+    for (int l = 0; l < Kp; ++l) r += sVi[l * 16 + ii] * sX[l * Kp + j];
     sY[e] = r;
   }
   __syncthreads();
@@ -636,7 +641,7 @@ int qgrad_mfma_launch(EpochInstance* in) {
                      (int)KK, in->q_chunks, static_cast<const double*>(Hpart), Hsum);
   rc = hip_check(hipGetLastError(), "qgrad_h launch");
   if (rc) return rc;
-  hipLaunchKernelGGL(qgrad_final_kernel, dim3(in->S, Kp / 16), dim3(256), (KK + 16 * Kp) * sizeof(double),
+  hipLaunchKernelGGL(qgrad_final_kernel, dim3(in->S, Kp / 16), dim3(256), (KK + 32 * Kp) * sizeof(double),
                      in->stream, in->K, Kp, static_cast<const double*>(Hsum), b64, b64 + S * KK,
                      b64 + 2 * S * KK + S * Kp, static_cast<double*>(in->dQ.ptr));
   return hip_check(hipGetLastError(), "qgrad_final launch");

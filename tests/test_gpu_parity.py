@@ -185,6 +185,38 @@ def test_codon_C3_tree(kernel):
     assert grad_rel(dq, ref_q) <= TOL_GRAD["fp32"], grad_rel(dq, ref_q)
 
 
+def _codon_eval(prob, options):
+    with from_problem(prob, "fp32", grad_branch=True, grad_Q=True, options=options) as lik:
+        logL = lik.log_likelihood()
+        db, dq = lik.gradient(branch=True, Q=True)
+    return logL, db, dq
+
+
+@pytest.mark.parametrize("n_patterns", [20, 700])
+def test_codon_side_split_pre_order_matches_oracle(n_patterns):
+    """Pre-order levels with each child branch on its own wavefronts (all levels, the
+    default narrow ones, none) match the oracle and give the same bits."""
+    prob = W.make_config(3, n_patterns=n_patterns)
+    want = O.log_likelihood(prob)
+    ref_b, ref_q = O.gradient(prob)
+    out = [_codon_eval(prob, {"split_blocks": v}) for v in (0, 256, 1 << 30)]
+    for logL, db, dq in out:
+        assert rel(logL, want) <= TOL_LOGL["fp32"], rel(logL, want)
+        assert grad_rel(db, ref_b) <= TOL_GRAD["fp32"], grad_rel(db, ref_b)
+        assert grad_rel(dq, ref_q) <= TOL_GRAD["fp32"], grad_rel(dq, ref_q)
+    for logL, db, dq in out[1:]:
+        assert logL == out[0][0] and np.array_equal(db, out[0][1]) and np.array_equal(dq, out[0][2])
+
+
+def test_codon_side_split_several_tiles_per_block():
+    """5000 patterns put several 64-pattern tiles on each block of the wide levels; the
+    side-split kernel on every level gives the bits of the four-wavefront kernel."""
+    prob = W.make_config(3, n_patterns=5000)
+    a = _codon_eval(prob, {"split_blocks": 0})
+    b = _codon_eval(prob, {"split_blocks": 1 << 30})
+    assert a[0] == b[0] and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+
+
 def test_codon_fp64_generic_C3_tree():
     prob = W.make_config(3, n_patterns=300)
     with from_problem(prob, "fp64", grad_branch=True) as lik:
