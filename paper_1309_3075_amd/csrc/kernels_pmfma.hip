@@ -76,15 +76,28 @@ __device__ inline void pstage_stripe(const PStageDesc& pd, int gw, ColCoef<T>* c
   const int m = seg_offset[v + 1] - seg0;
   const double rho = cat_rates[c];
   const double scale = rho * rate[v];
+  // Column coefficients of segment k (double-buffered by k parity).  Those of
+  // segment k + 1, and the first operands of its V product, are produced while
+  // the matrix cores run segment k's products.
+  auto make_coef = [&](int k, ColCoef<T>* dst) {
+    const int s = seg_process[seg0 + k];
+    if (lane < Kp) {
+      const T tau = T(scale * seg_time[seg0 + k]);
+      const T dsc = T(rho * seg_frac[seg0 + k]);
+      const BlockCoef<T> bc = block_coef(lre + (size_t)s * Kp, lim + (size_t)s * Kp, lane, tau);
+      dst[lane] = ColCoef<T>{bc.m_self, bc.m_other, dsc * bc.dm_self, dsc * bc.dm_other};
+    }
+  };
+  T av[2][4][NT], ai[2][4][NT];
+  if (m > 0) {
+    make_coef(0, coef);
+    stripe_load<T, NT>(eigV + (size_t)seg_process[seg0] * KK, 0, g, arow, av[0]);
+  }
   for (int k = 0; k < m; ++k) {
     const int s = seg_process[seg0 + k];
-    const T tau = T(scale * seg_time[seg0 + k]);
-    const T dsc = T(rho * seg_frac[seg0 + k]);
-    if (lane < Kp) {
-      const BlockCoef<T> bc = block_coef(lre + (size_t)s * Kp, lim + (size_t)s * Kp, lane, tau);
-      coef[lane] = ColCoef<T>{bc.m_self, bc.m_other, dsc * bc.dm_self, dsc * bc.dm_other};
-    }
-    __builtin_amdgcn_wave_barrier();
+    const ColCoef<T>* ck = coef + 64 * (k & 1);
+    wave_lds_sync();  // segment k's coefficients are in LDS
+    stripe_load<T, NT>(eigVi + (size_t)s * KK, 0, g, arow, ai[0]);
 
     // Y^T = V^T X^T (and V^T D^T)
     acc y[NB][NT];
@@ -92,7 +105,11 @@ __device__ inline void pstage_stripe(const PStageDesc& pd, int gw, ColCoef<T>* c
     for (int b = 0; b < NB; ++b)
 #pragma unroll
       for (int mt = 0; mt < NT; ++mt) y[b][mt] = acc{0, 0, 0, 0};
-    stripe_gemm<T, NT, NB>(eigV + (size_t)s * KK, g, arow, xd, y);
+    stripe_gemm_from<T, NT, NB>(eigV + (size_t)s * KK, g, arow, av, xd, y);
+    if (k + 1 < m) {
+      make_coef(k + 1, coef + 64 * ((k + 1) & 1));
+      stripe_load<T, NT>(eigV + (size_t)seg_process[seg0 + k + 1] * KK, 0, g, arow, av[0]);
+    }
     if (pd.Ubuf) {
       // A_k V (the running product times V before the column operator), the forward
       // half of the dlogL/dQ adjoint chain
@@ -106,8 +123,8 @@ __device__ inline void pstage_stripe(const PStageDesc& pd, int gw, ColCoef<T>* c
     for (int mt = 0; mt < NT; ++mt)
 #pragma unroll
       for (int q = 0; q < 4; q += 2) {
-        const ColCoef<T> c0 = coef[16 * mt + 4 * g + q];
-        const ColCoef<T> c1 = coef[16 * mt + 4 * g + q + 1];
+        const ColCoef<T> c0 = ck[16 * mt + 4 * g + q];
+        const ColCoef<T> c1 = ck[16 * mt + 4 * g + q + 1];
         const T y0 = y[0][mt][q], y1 = y[0][mt][q + 1];
         y[0][mt][q] = c0.ms * y0 + c0.mo * y1;
         y[0][mt][q + 1] = c1.ms * y1 + c1.mo * y0;
@@ -117,10 +134,9 @@ __device__ inline void pstage_stripe(const PStageDesc& pd, int gw, ColCoef<T>* c
           y[NB - 1][mt][q + 1] = c1.ms * d1 + c1.mo * d0 + c1.dms * y1 + c1.dmo * y0;
         }
       }
-    __builtin_amdgcn_wave_barrier();
 
     // X^T += V^-T Y'^T (and D^T += V^-T YD'^T)
-    stripe_gemm<T, NT, NB>(eigVi + (size_t)s * KK, g, arow, y, xd);
+    stripe_gemm_from<T, NT, NB>(eigVi + (size_t)s * KK, g, arow, ai, y, xd);
   }
 
   const size_t base = ((size_t)v * C + c) * KK + (size_t)row * Kp + 4 * g;
@@ -134,7 +150,7 @@ __device__ inline void pstage_stripe(const PStageDesc& pd, int gw, ColCoef<T>* c
 // One problem (descriptor passed by value).
 template <typename T, typename TO, bool GRAD, int NT>
 __global__ __launch_bounds__(256) void pstage_mfma_kernel(PStageDesc pd) {
-  __shared__ ColCoef<T> s_coef[4][64];
+  __shared__ ColCoef<T> s_coef[4][2 * 64];
   const int wave = threadIdx.x >> 6;
   pstage_stripe<T, TO, GRAD, NT>(pd, blockIdx.x * 4 + wave, s_coef[wave]);
 }
@@ -142,7 +158,7 @@ __global__ __launch_bounds__(256) void pstage_mfma_kernel(PStageDesc pd) {
 // Several problems of one batch in one launch: blockIdx.y selects the problem.
 template <typename T, typename TO, bool GRAD, int NT>
 __global__ __launch_bounds__(256) void pstage_mfma_multi_kernel(const PStageDesc* __restrict__ descs) {
-  __shared__ ColCoef<T> s_coef[4][64];
+  __shared__ ColCoef<T> s_coef[4][2 * 64];
   const int wave = threadIdx.x >> 6;
   const PStageDesc pd = descs[blockIdx.y];
   pstage_stripe<T, TO, GRAD, NT>(pd, blockIdx.x * 4 + wave, s_coef[wave]);

@@ -58,24 +58,25 @@ __device__ inline void store4<double, float>(float* dst, const f64x4& x) {
 // at column 16 mt + arow.  The 4 NT operands of tile t + 1 are loaded while the
 // MFMAs of tile t run, so a step waits on memory about once instead of once per
 // instruction.
-template <typename T, int NT, int NB>
-__device__ inline void stripe_gemm(const T* __restrict__ M, int g, int arow,
-                                   const typename Mfma<T>::acc (&in)[NB][NT],
-                                   typename Mfma<T>::acc (&out)[NB][NT]) {
+// Operands of k-step tile t of a stripe product by M (see stripe_gemm).
+template <typename T, int NT>
+__device__ inline void stripe_load(const T* __restrict__ M, int t, int g, int arow, T (&a)[4][NT]) {
   constexpr int Kp = 16 * NT;
-  T a[2][4][NT];
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll
-    for (int mt = 0; mt < NT; ++mt) a[0][q][mt] = M[(4 * g + q) * Kp + 16 * mt + arow];
+    for (int mt = 0; mt < NT; ++mt) a[q][mt] = M[(16 * t + 4 * g + q) * Kp + 16 * mt + arow];
+}
+
+// stripe_gemm with the operands of tile 0 already in a[0] (loaded earlier by
+// stripe_load, so that their latency overlaps other work).
+template <typename T, int NT, int NB>
+__device__ inline void stripe_gemm_from(const T* __restrict__ M, int g, int arow, T (&a)[2][4][NT],
+                                        const typename Mfma<T>::acc (&in)[NB][NT],
+                                        typename Mfma<T>::acc (&out)[NB][NT]) {
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    if (t + 1 < NT) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int mt = 0; mt < NT; ++mt) a[(t + 1) & 1][q][mt] = M[(16 * (t + 1) + 4 * g + q) * Kp + 16 * mt + arow];
-    }
+    if (t + 1 < NT) stripe_load<T, NT>(M, t + 1, g, arow, a[(t + 1) & 1]);
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -83,6 +84,15 @@ __device__ inline void stripe_gemm(const T* __restrict__ M, int g, int arow,
 #pragma unroll
         for (int b = 0; b < NB; ++b) out[b][mt] = Mfma<T>::mma(a[t & 1][q][mt], in[b][t][q], out[b][mt]);
   }
+}
+
+template <typename T, int NT, int NB>
+__device__ inline void stripe_gemm(const T* __restrict__ M, int g, int arow,
+                                   const typename Mfma<T>::acc (&in)[NB][NT],
+                                   typename Mfma<T>::acc (&out)[NB][NT]) {
+  T a[2][4][NT];
+  stripe_load<T, NT>(M, 0, g, arow, a[0]);
+  stripe_gemm_from<T, NT, NB>(M, g, arow, a, in, out);
 }
 
 // Orders the LDS accesses of one wavefront (a write, then reads by other lanes).
