@@ -174,7 +174,7 @@ int enqueue(EpochBatch* b, uint32_t what, const double* const* d_result_ptrs) {
     const int2* red = items + b->sched.items.size();
     int rc = codon_launch_post(b->sched, probs, items, b->stream);
     if (!rc) rc = codon_launch_root(b->sched, probs, b->stream);
-    if (!rc && (what & (kGradBranch | kGradQ))) rc = codon_launch_pre_grad(b->sched, probs, items, red, static_cast<double*>(b->dpart.ptr), b->stream);
+    if (!rc && (what & (kGradBranch | kGradQ))) rc = codon_launch_pre_grad(b->sched, probs, items, red, static_cast<double*>(b->dpart.ptr), b->stream, false, true);
     if (rc) return rc;
   } else {
     for (auto* in : b->insts) {
@@ -381,7 +381,7 @@ int epoch_batch_create(EpochInstance* const* insts, int32_t n, const char* tune_
   b->own_stream = true;
   b->merged = true;
   for (int i = 0; i < n; ++i) {
-    if (insts[i]->path != 2) b->merged = false;
+    if (insts[i]->path != 2 || insts[i]->codon_nchunks > 1) b->merged = false;
     if (insts[i]->device != insts[0]->device) {
       (void)hipStreamDestroy(b->stream);
       delete b;

@@ -78,7 +78,8 @@ int fastpath_pstage(EpochInstance* in) {
 }
 
 int launch_post(EpochInstance* in) {
-  if (in->budget > 0 && !in->walk_ok) return set_error(EPOCH_ERR_STATE, "no tree-walk schedule for the HBM budget");
+  if (nuc(in) && in->budget > 0 && !in->walk_ok)
+    return set_error(EPOCH_ERR_STATE, "no tree-walk schedule for the HBM budget");
   if (nuc(in)) return in->walk_ok ? launch_walk_post(in) : launch_nuc_post(in);
   return codon(in) ? launch_codon_post(in) : launch_post_generic(in);
 }

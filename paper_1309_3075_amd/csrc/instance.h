@@ -40,6 +40,7 @@ struct CodonProblem {
   const int32_t* right;
   const int32_t* gslots;  // [2 n_nodes]: dlogL/dP partial slots written per branch, then each branch's first slot
   int N, P, K, root, n_nodes;
+  int tip_stride;         // row stride of tips (the instance's pattern count; P is this chunk's)
 };
 
 // Device pointers of one problem's P stage (one instance, or one member of a batch).
@@ -158,6 +159,8 @@ struct EpochInstance {
   epochlik::DevBuf codon_aux;  // 64-state path: per-chunk shares of dlogL/dl (double)
   epochlik::CodonSchedule codon_sched;
   int codon_target_blocks = 1024;  // blocks per pre-order launch the 64-state schedule aims for
+  int codon_pc = 0;                // 64-state path under an HBM budget: patterns per chunk (0: all at once)
+  int codon_nchunks = 1;           // pattern chunks evaluated one after another
   int codon_split_blocks = 256;    // narrow pre-order levels (at most this many blocks) use the side-split kernel
 
   // per-phase timing (epoch_set_timing)
@@ -237,6 +240,6 @@ int codon_launch_post(const CodonSchedule& sc, const CodonProblem* d_probs, cons
 int codon_launch_root(const CodonSchedule& sc, const CodonProblem* d_probs, hipStream_t st);
 size_t codon_dpart_bytes(const CodonSchedule& sc);
 int codon_launch_pre_grad(const CodonSchedule& sc, const CodonProblem* d_probs, const int2* d_items,
-                          const int2* d_reduce_items, double* dpart, hipStream_t st);
+                          const int2* d_reduce_items, double* dpart, hipStream_t st, bool accumulate, bool finish);
 
 }  // namespace epochlik

@@ -184,14 +184,14 @@ __global__ __launch_bounds__(256) void codon_post_level_kernel(const CodonProble
       child_gemm(Sa, La, P, p0, sPa, g, r);
     } else {
       int col[4];
-      tip_columns(col, pr.tips + (size_t)a * P, P, p0, K, g);
+      tip_columns(col, pr.tips + (size_t)a * pr.tip_stride, P, p0, K, g);
       tip_lookup(Sa, col, sPa, r);
     }
     if (Lb) {
       child_gemm(Sb, Lb, P, p0, sPb, g, r);
     } else {
       int col[4];
-      tip_columns(col, pr.tips + (size_t)b * P, P, p0, K, g);
+      tip_columns(col, pr.tips + (size_t)b * pr.tip_stride, P, p0, K, g);
       tip_lookup(Sb, col, sPb, r);
     }
     int e[4];
@@ -251,6 +251,15 @@ __global__ __launch_bounds__(256) void codon_final_kernel(const CodonProblem* __
   if (threadIdx.x == 0) pr.result[0] = tot;
 }
 
+// logL of pattern chunks 1 .. n (in result[1 .. n]) summed in order into result[0].
+__global__ void codon_chunk_sum_kernel(double* __restrict__ result, int n) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double acc = 0.0;
+    for (int j = 1; j <= n; ++j) acc += result[j];
+    result[0] = acc;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Pre-order of one level fused with dlogL/dP of the two child branches.
 //
@@ -263,6 +272,16 @@ __global__ __launch_bounds__(256) void codon_final_kernel(const CodonProblem* __
 // B = child partials from L2, or the tip indicator), so each wavefront holds
 // only 2 x 16 accumulator registers; the loads of its next tile are issued
 // before that second phase and arrive while it runs.
+// A block past the last tile of a pattern chunk shorter than the one the
+// schedule was built for still owns a dlogL/dP slot of each child branch (the
+// slot count covers the longest chunk): it writes zeros there.  Blocks past a
+// batch member's own tiles own no slot and write nothing.
+__device__ inline void zero_unused_slot(const CodonProblem& pr, int child, int nthreads) {
+  if ((int)blockIdx.x >= pr.gslots[child]) return;
+  EPOCH_GLOBAL float* dst = gptr(pr.Gpart + ((size_t)pr.gslots[pr.n_nodes + child] + blockIdx.x) * KK);
+  for (int e = threadIdx.x; e < KK / 4; e += nthreads) reinterpret_cast<EPOCH_GLOBAL f4*>(dst)[e] = f4{0.f, 0.f, 0.f, 0.f};
+}
+
 struct PreTileLoads {
   f4 La[4], Lb[4];  // 16-byte rows of internal children's partials (child product A operand)
   f4 Q[4];          // q_u in the D layout
@@ -278,14 +297,14 @@ __device__ inline void pre_load_tile(PreTileLoads& ld, const CodonProblem& pr, c
 #pragma unroll
     for (int t = 0; t < 4; ++t) ld.La[t] = row[4 * t];
   } else {
-    tip_columns(ld.cola, pr.tips + (size_t)a * P, P, p0, K, g);
+    tip_columns(ld.cola, pr.tips + (size_t)a * pr.tip_stride, P, p0, K, g);
   }
   if (Lb) {
     const EPOCH_GLOBAL f4* row = gptr(reinterpret_cast<const f4*>(Lb + (size_t)pa * KP)) + g;
 #pragma unroll
     for (int t = 0; t < 4; ++t) ld.Lb[t] = row[4 * t];
   } else {
-    tip_columns(ld.colb, pr.tips + (size_t)b * P, P, p0, K, g);
+    tip_columns(ld.colb, pr.tips + (size_t)b * pr.tip_stride, P, p0, K, g);
   }
   if (Qu) load_dlayout(ld.Q, Qu, P, p0, g, r);
   (void)N;
@@ -319,10 +338,14 @@ __global__ __launch_bounds__(256, 2) void codon_pre_level_kernel(const CodonProb
   const CodonProblem& pr = probs[it.x];
   const int N = pr.N, P = pr.P, K = pr.K;
   const int base = blockIdx.x * R * TILE;
-  if (base >= P) return;  // uniform: this problem has fewer tiles
-  const int n_tiles = min(R, (P - base + TILE - 1) / TILE);  // uniform over the block
   const int u = it.y;
   const int a = pr.left[u], b = pr.right[u];
+  if (base >= P) {  // uniform: this problem (or pattern chunk) has fewer tiles
+    zero_unused_slot(pr, a, 256);
+    zero_unused_slot(pr, b, 256);
+    return;
+  }
+  const int n_tiles = min(R, (P - base + TILE - 1) / TILE);  // uniform over the block
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
   stage_matrix(sPa, pr.Pm + (size_t)a * KK);
   stage_matrix(sPb, pr.Pm + (size_t)b * KK);
@@ -497,7 +520,7 @@ __device__ inline void split_load_tile(SplitTileLoads& ld, const CodonProblem& p
 #pragma unroll
     for (int t = 0; t < 4; ++t) ld.L[t] = row[4 * t];
   } else {
-    tip_columns(ld.col, pr.tips + (size_t)c * P, P, p0, pr.K, g);
+    tip_columns(ld.col, pr.tips + (size_t)c * pr.tip_stride, P, p0, pr.K, g);
   }
   if (Qu) load_dlayout(ld.Q, Qu, P, p0, g, r);
 }
@@ -509,10 +532,14 @@ __global__ __launch_bounds__(512, 1) void codon_pre_split_kernel(const CodonProb
   const CodonProblem& pr = probs[it.x];
   const int N = pr.N, P = pr.P, K = pr.K;
   const int base = blockIdx.x * R * TILE;
-  if (base >= P) return;  // uniform: this problem has fewer tiles
-  const int n_tiles = min(R, (P - base + TILE - 1) / TILE);  // uniform over the block
   const int u = it.y;
   const int a = pr.left[u], b = pr.right[u];
+  if (base >= P) {  // uniform: this problem (or pattern chunk) has fewer tiles
+    zero_unused_slot(pr, a, 512);
+    zero_unused_slot(pr, b, 512);
+    return;
+  }
+  const int n_tiles = min(R, (P - base + TILE - 1) / TILE);  // uniform over the block
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, w = wave & 3, s = wave >> 2;
   const int g = lane >> 4, r = lane & 15;
   const int c = s ? b : a;
@@ -647,7 +674,7 @@ __global__ __launch_bounds__(512, 1) void codon_pre_split_kernel(const CodonProb
 constexpr int kReduceChunks = KK / 256;
 __global__ __launch_bounds__(256) void codon_grad_reduce_kernel(const CodonProblem* __restrict__ probs,
                                                                 const int2* __restrict__ items,
-                                                                double* __restrict__ dpart) {
+                                                                double* __restrict__ dpart, int accumulate) {
   __shared__ double sm[256];
   const int2 it = items[blockIdx.x / kReduceChunks];
   const int chunk = blockIdx.x % kReduceChunks;
@@ -665,7 +692,8 @@ __global__ __launch_bounds__(256) void codon_grad_reduce_kernel(const CodonProbl
     s3 += (double)src[(size_t)(k + 3) * KK];
   }
   for (; k < ns; ++k) s0 += (double)src[(size_t)k * KK];
-  const double s = (s0 + s1) + (s2 + s3);
+  double s = (s0 + s1) + (s2 + s3);
+  if (accumulate) s += pr.G[(size_t)v * KK + e];  // earlier pattern chunks
   pr.G[(size_t)v * KK + e] = s;
   const double d = block_sum<256>(s * (double)pr.dPm[(size_t)v * KK + e], sm);
   if (threadIdx.x == 0) dpart[blockIdx.x] = d;
@@ -683,6 +711,10 @@ __global__ __launch_bounds__(256) void codon_dbranch_kernel(const CodonProblem* 
   for (int c = 0; c < kReduceChunks; ++c) d += dpart[(size_t)i * kReduceChunks + c];
   pr.dbranch[it.y] = it.y == pr.root ? 0.0 : d;
 }
+
+// Patterns the buffers and the launch schedule of an instance are sized for:
+// all of them, or one chunk under an HBM budget.
+int codon_chunk_patterns(const EpochInstance* in) { return in->codon_pc > 0 ? in->codon_pc : in->P; }
 
 int codon_tiles_per_block(int tiles, int n_items, int target_blocks, int r_max) {
   const long per_item = ((long)target_blocks + n_items - 1) / n_items;
@@ -716,6 +748,7 @@ CodonProblem codon_descriptor(const EpochInstance* in, const int32_t* gslots, fl
   d.gslots = gslots;
   d.N = in->N;
   d.P = in->P;
+  d.tip_stride = in->P;
   d.K = in->K;
   d.root = in->plan.root;
   d.n_nodes = in->n_nodes;
@@ -737,8 +770,8 @@ void codon_build_schedule(const std::vector<const EpochInstance*>& insts, int ta
   int n_levels = 0, max_tiles = 0, max_pblocks = 0;
   for (auto* in : insts) {
     n_levels = std::max(n_levels, in->plan.n_levels);
-    max_tiles = std::max(max_tiles, (in->P + TILE - 1) / TILE);
-    max_pblocks = std::max(max_pblocks, (in->P + 255) / 256);
+    max_tiles = std::max(max_tiles, (codon_chunk_patterns(in) + TILE - 1) / TILE);
+    max_pblocks = std::max(max_pblocks, (codon_chunk_patterns(in) + 255) / 256);
   }
   gslots.assign(insts.size(), {});
   out.slot_total.assign(insts.size(), 0);
@@ -757,7 +790,7 @@ void codon_build_schedule(const std::vector<const EpochInstance*>& insts, int ta
     for (size_t k = begin; k < out.items.size(); ++k) {
       const int q = out.items[k].x, u = out.items[k].y;
       const auto& pl = insts[q]->plan;
-      const int tiles = (insts[q]->P + TILE - 1) / TILE;
+      const int tiles = (codon_chunk_patterns(insts[q]) + TILE - 1) / TILE;
       const int used = (tiles + R - 1) / R;
       const int n = insts[q]->n_nodes;
       for (int child : {pl.left[u], pl.right[u]}) {
@@ -795,7 +828,7 @@ int codon_launch_root(const CodonSchedule& sc, const CodonProblem* d_probs, hipS
 size_t codon_dpart_bytes(const CodonSchedule& sc) { return sc.reduce_items.size() * kReduceChunks * sizeof(double); }
 
 int codon_launch_pre_grad(const CodonSchedule& sc, const CodonProblem* d_probs, const int2* d_items,
-                          const int2* d_reduce_items, double* dpart, hipStream_t st) {
+                          const int2* d_reduce_items, double* dpart, hipStream_t st, bool accumulate, bool finish) {
   for (int l = sc.n_levels; l >= 1; --l) {
     const int b = sc.level_off[l - 1], n = sc.level_off[l] - b;
     if (!n) continue;
@@ -810,13 +843,17 @@ int codon_launch_pre_grad(const CodonSchedule& sc, const CodonProblem* d_probs, 
   if (rc) return rc;
   const int n_items = (int)sc.reduce_items.size();
   hipLaunchKernelGGL(codon_grad_reduce_kernel, dim3((unsigned)(n_items * kReduceChunks)), dim3(256), 0, st, d_probs,
-                     d_reduce_items, dpart);
-  hipLaunchKernelGGL(codon_dbranch_kernel, dim3((unsigned)((n_items + 255) / 256)), dim3(256), 0, st, d_probs,
-                     d_reduce_items, n_items, static_cast<const double*>(dpart));
+                     d_reduce_items, dpart, accumulate ? 1 : 0);
+  if (finish)
+    hipLaunchKernelGGL(codon_dbranch_kernel, dim3((unsigned)((n_items + 255) / 256)), dim3(256), 0, st, d_probs,
+                       d_reduce_items, n_items, static_cast<const double*>(dpart));
   return hip_check(hipGetLastError(), "codon_grad_reduce launch");
 }
 
-// ---- single-instance entry points (schedule built when the tree changes)
+// ---- single-instance entry points (schedule built when the tree changes).
+// Under an HBM budget the patterns run in chunks of codon_pc: chunk j has its
+// own descriptor (pattern count, and tips, weights and per-pattern outputs
+// offset to its first pattern) over the shared chunk-sized buffers.
 int codon_prepare(EpochInstance* in) {
   std::vector<std::vector<int32_t>> gslots;
   codon_build_schedule({in}, in->codon_target_blocks, in->codon_sched, gslots);
@@ -827,14 +864,27 @@ int codon_prepare(EpochInstance* in) {
   if (!rc && grad) rc = ensure(in->Gpart, std::max<size_t>(1, sc.slot_total[0]) * kCodonSlotBytes);
   if (!rc && grad) rc = ensure(in->codon_aux, codon_dpart_bytes(sc));
   if (rc) return rc;
+  const int nc = in->codon_nchunks;
+  std::vector<CodonProblem> desc(nc);
   const CodonProblem d = codon_descriptor(in, static_cast<const int32_t*>(in->gslots.ptr), static_cast<float*>(in->Gpart.ptr));
-  const size_t bytes = sizeof(CodonProblem) + sizeof(int2) * (sc.items.size() + sc.reduce_items.size());
+  for (int j = 0; j < nc; ++j) {
+    const int p0 = j * codon_chunk_patterns(in);
+    desc[j] = d;
+    desc[j].P = std::min(in->P - p0, codon_chunk_patterns(in));
+    desc[j].tips = d.tips + p0;
+    desc[j].weightsT = d.weightsT + p0;
+    desc[j].weights = d.weights + p0;
+    desc[j].site = d.site + p0;
+    desc[j].result = nc > 1 ? d.result + 1 + j : d.result;
+  }
+  const size_t dbytes = sizeof(CodonProblem) * nc;
+  const size_t bytes = dbytes + sizeof(int2) * (sc.items.size() + sc.reduce_items.size());
   rc = ensure(in->codon_dev, bytes);
   if (rc) return rc;
   std::vector<char> h(bytes);
-  memcpy(h.data(), &d, sizeof(d));
-  memcpy(h.data() + sizeof(d), sc.items.data(), sizeof(int2) * sc.items.size());
-  memcpy(h.data() + sizeof(d) + sizeof(int2) * sc.items.size(), sc.reduce_items.data(),
+  memcpy(h.data(), desc.data(), dbytes);
+  memcpy(h.data() + dbytes, sc.items.data(), sizeof(int2) * sc.items.size());
+  memcpy(h.data() + dbytes + sizeof(int2) * sc.items.size(), sc.reduce_items.data(),
          sizeof(int2) * sc.reduce_items.size());
   rc = hip_check(hipMemcpyAsync(in->codon_dev.ptr, h.data(), bytes, hipMemcpyHostToDevice, in->stream), "codon schedule upload");
   if (!rc)
@@ -847,16 +897,44 @@ int codon_prepare(EpochInstance* in) {
 namespace {
 const CodonProblem* dev_probs(EpochInstance* in) { return static_cast<const CodonProblem*>(in->codon_dev.ptr); }
 const int2* dev_items(EpochInstance* in) {
-  return reinterpret_cast<const int2*>(static_cast<const char*>(in->codon_dev.ptr) + sizeof(CodonProblem));
+  return reinterpret_cast<const int2*>(static_cast<const char*>(in->codon_dev.ptr) +
+                                       sizeof(CodonProblem) * in->codon_nchunks);
 }
 const int2* dev_reduce_items(EpochInstance* in) { return dev_items(in) + in->codon_sched.items.size(); }
 }  // namespace
 
-int launch_codon_post(EpochInstance* in) { return codon_launch_post(in->codon_sched, dev_probs(in), dev_items(in), in->stream); }
-int launch_codon_root(EpochInstance* in) { return codon_launch_root(in->codon_sched, dev_probs(in), in->stream); }
+// Post-order pass.  In chunks, each chunk's root reduction follows its partials
+// (the next chunk overwrites them), and the chunk log-likelihoods are summed.
+int launch_codon_post(EpochInstance* in) {
+  const int nc = in->codon_nchunks;
+  if (nc == 1) return codon_launch_post(in->codon_sched, dev_probs(in), dev_items(in), in->stream);
+  for (int j = 0; j < nc; ++j) {
+    int rc = codon_launch_post(in->codon_sched, dev_probs(in) + j, dev_items(in), in->stream);
+    if (!rc) rc = codon_launch_root(in->codon_sched, dev_probs(in) + j, in->stream);
+    if (rc) return rc;
+  }
+  hipLaunchKernelGGL(codon_chunk_sum_kernel, dim3(1), dim3(64), 0, in->stream, static_cast<double*>(in->result.ptr), nc);
+  return hip_check(hipGetLastError(), "codon_chunk_sum launch");
+}
+
+int launch_codon_root(EpochInstance* in) {
+  if (in->codon_nchunks > 1) return EPOCH_OK;  // formed with the chunks' partials
+  return codon_launch_root(in->codon_sched, dev_probs(in), in->stream);
+}
+
+// Pre-order pass and dlogL/dP.  In chunks, each chunk's partials are formed
+// again first (only one chunk's fit), and dlogL/dP accumulates over chunks.
 int launch_codon_pre_grad(EpochInstance* in) {
-  return codon_launch_pre_grad(in->codon_sched, dev_probs(in), dev_items(in), dev_reduce_items(in),
-                               static_cast<double*>(in->codon_aux.ptr), in->stream);
+  const int nc = in->codon_nchunks;
+  double* dpart = static_cast<double*>(in->codon_aux.ptr);
+  for (int j = 0; j < nc; ++j) {
+    int rc = nc > 1 ? codon_launch_post(in->codon_sched, dev_probs(in) + j, dev_items(in), in->stream) : EPOCH_OK;
+    if (!rc)
+      rc = codon_launch_pre_grad(in->codon_sched, dev_probs(in) + j, dev_items(in), dev_reduce_items(in), dpart,
+                                 in->stream, j > 0, j == nc - 1);
+    if (rc) return rc;
+  }
+  return EPOCH_OK;
 }
 
 }  // namespace epochlik

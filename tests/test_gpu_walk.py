@@ -1,7 +1,8 @@
 """4-state tree-walk kernels (an opt-in alternative to the level kernels)
 against the FP64 oracle, through the C ABI: every category packing, ragged
 pattern tiles, recomputation thresholds, strided tiles, deep (caterpillar) and
-balanced trees; and the level kernels under their tiling option."""
+balanced trees; the level kernels under their tiling option; and evaluation
+under an HBM budget (4-state recomputation, 64-state pattern chunks)."""
 import dataclasses
 
 import numpy as np
@@ -185,3 +186,55 @@ def test_caller_owned_workspace(precision):
     with from_problem(prob, precision, grad_branch=True) as lik:
         b = lik.evaluate(branch=True, site=True)
     assert a[0] == b[0] and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+
+
+def _codon_budget(prob, patterns_per_chunk, grad=True):
+    """Budget that gives the 64-state path chunks of patterns_per_chunk patterns (a multiple of 64)."""
+    nm1 = prob.n_tips - 1
+    per = nm1 * (64 * 4 + 4) + (nm1 * 64 * 4 + 2 * nm1 * 64 * 64 * 4 // 64 if grad else 0)
+    return per * patterns_per_chunk
+
+
+@pytest.mark.parametrize("chunk", [64, 192])
+def test_codon_hbm_budget_streams_pattern_chunks(chunk):
+    """Under a budget the 64-state path evaluates the patterns in chunks (the last one
+    ragged); the gradient call forms each chunk's partials again.  Results match the
+    oracle and the unbudgeted instance, through the separate calls and the single call."""
+    prob = W.make_config(3, n_patterns=700)
+    budget = _codon_budget(prob, chunk)
+    with from_problem(prob, "fp32", grad_branch=True, grad_Q=True, hbm_budget_bytes=budget) as lik:
+        logL, site = lik.log_likelihood(site=True)
+        db, dq = lik.gradient(branch=True, Q=True)
+        one = lik.evaluate(branch=True, Q=True, site=True)
+        again = lik.evaluate(branch=True, Q=True, site=True)
+    with from_problem(prob, "fp32", grad_branch=True, grad_Q=True) as lik:
+        ref = lik.evaluate(branch=True, Q=True, site=True)
+    want = O.log_likelihood(prob)
+    ob, oq = O.gradient(prob)
+    assert abs(logL - want) <= TOL_LOGL["fp32"] * abs(want)
+    assert np.linalg.norm(db - ob) <= TOL_GRAD["fp32"] * np.linalg.norm(ob)
+    assert np.linalg.norm(dq - oq) <= TOL_GRAD["fp32"] * np.linalg.norm(oq)
+    # the same FP32 partials; only the FP64 sums over chunks are ordered differently
+    assert abs(logL - ref[0]) <= 1e-13 * abs(want) and abs(one[0] - logL) <= 1e-13 * abs(want)
+    assert np.array_equal(site, ref[1]) and np.array_equal(one[1], ref[1])
+    assert np.linalg.norm(db - ref[2]) <= 1e-12 * np.linalg.norm(ob)
+    assert np.linalg.norm(dq - ref[3]) <= 1e-12 * np.linalg.norm(oq)
+    assert np.linalg.norm(one[2] - db) <= 1e-12 * np.linalg.norm(ob)
+    assert again[0] == one[0] and np.array_equal(again[2], one[2]) and np.array_equal(again[3], one[3])
+
+
+def test_codon_hbm_budget_logL_only_and_large_budget():
+    prob = W.make_config(3, n_patterns=300)
+    with from_problem(prob, "fp32", hbm_budget_bytes=_codon_budget(prob, 128, grad=False)) as lik:
+        logL = lik.log_likelihood()
+    with from_problem(prob, "fp32", grad_branch=True, hbm_budget_bytes=1 << 40) as lik:  # one chunk
+        big = lik.evaluate(branch=True)
+    want = O.log_likelihood(prob)
+    assert abs(logL - want) <= TOL_LOGL["fp32"] * abs(want)
+    assert abs(big[0] - want) <= TOL_LOGL["fp32"] * abs(want)
+
+
+def test_codon_hbm_budget_too_small_is_refused():
+    prob = W.make_config(3, n_patterns=300)
+    with pytest.raises(Exception, match="hbm_budget_bytes"):
+        from_problem(prob, "fp32", grad_branch=True, hbm_budget_bytes=_codon_budget(prob, 64) - 1)
