@@ -272,6 +272,42 @@ __global__ void codon_chunk_sum_kernel(double* __restrict__ result, int n) {
 // B = child partials from L2, or the tip indicator), so each wavefront holds
 // only 2 x 16 accumulator registers; the loads of its next tile are issued
 // before that second phase and arrive while it runs.
+// Rows 16 w .. 16 w + 15 of one child's dlogL/dP over the 64 patterns of a
+// block tile (contraction over patterns: k-step ks takes pattern 4 ks + g):
+// A = t[p][16 w + r] w_p / L_p, B = the child's partials (internal child) or
+// its tip-state indicator.  One loop per kind of child, with no branch inside,
+// so the LDS reads of later k-steps are issued ahead of the matrix-core work.
+__device__ inline void grad_rows_internal(f4* G, const float* __restrict__ tcol, const float* __restrict__ sCF,
+                                          const float* __restrict__ sL, int g, int r) {
+#pragma unroll 8
+  for (int ks = 0; ks < TILE / 4; ++ks) {
+    const int pl = 4 * ks + g;
+    const float av = tcol[pl * LDP] * sCF[pl];
+    f4 B;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) B[nt] = sL[pl * LDP + 16 * nt + r];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) G[nt] = mfma(av, B[nt], G[nt]);
+  }
+}
+__device__ inline void grad_rows_tip(f4* G, const float* __restrict__ tcol, const float* __restrict__ sCF,
+                                     const int* __restrict__ sCol, int K, int g, int r) {
+#pragma unroll 8
+  for (int ks = 0; ks < TILE / 4; ++ks) {
+    const int pl = 4 * ks + g;
+    const float av = tcol[pl * LDP] * sCF[pl];
+    const int col = sCol[pl];
+    f4 B;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const int j = 16 * nt + r;
+      B[nt] = (col == j || (col == 64 && j < K)) ? 1.f : 0.f;
+    }
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) G[nt] = mfma(av, B[nt], G[nt]);
+  }
+}
+
 // A block past the last tile of a pattern chunk shorter than the one the
 // schedule was built for still owns a dlogL/dP slot of each child branch (the
 // slot count covers the longest chunk): it writes zeros there.  Blocks past a
@@ -453,25 +489,10 @@ __global__ __launch_bounds__(256, 2) void codon_pre_level_kernel(const CodonProb
       __syncthreads();  // t, L, w_p / L_p and tip columns of every wavefront are in LDS
       // rows 16 w .. 16 w + 15 of dlogL/dP over the 64 patterns of the tile
       const float* tcol = sT + WT * w + r;  // column i = 16 w + r of t
-#pragma unroll 8
-      for (int ks = 0; ks < TILE / 4; ++ks) {
-        const int pl = 4 * ks + g;  // pattern of the tile this lane feeds into k-step ks
-        const float av = tcol[pl * LDP] * sCF[pl];
-        f4 B;
-        if (Lc) {
-#pragma unroll
-          for (int nt = 0; nt < 4; ++nt) B[nt] = sL[pl * LDP + 16 * nt + r];
-        } else {
-          const int col = sCol[side][pl];
-#pragma unroll
-          for (int nt = 0; nt < 4; ++nt) {
-            const int j = 16 * nt + r;
-            B[nt] = (col == j || (col == 64 && j < K)) ? 1.f : 0.f;
-          }
-        }
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) G[nt] = mfma(av, B[nt], G[nt]);
-      }
+      if (Lc)
+        grad_rows_internal(G, tcol, sCF, sL, g, r);
+      else
+        grad_rows_tip(G, tcol, sCF, sCol[side], K, g, r);
     }
     __syncthreads();  // the next tile overwrites t, L, w_p / L_p and tip columns
     if (bt + 1 < n_tiles) cur = nxt;
@@ -640,26 +661,10 @@ __global__ __launch_bounds__(512, 1) void codon_pre_split_kernel(const CodonProb
     }
     __syncthreads();  // t, L, w_p / L_p and tip columns of the whole tile are in LDS
     const float* tcol = sh.sT[s] + WT * w + r;
-    const float* sL = sh.sL[s];
-#pragma unroll 8
-    for (int ks = 0; ks < TILE / 4; ++ks) {
-      const int pl = 4 * ks + g;
-      const float av = tcol[pl * LDP] * sh.sCF[pl];
-      f4 B;
-      if (Lc) {
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) B[nt] = sL[pl * LDP + 16 * nt + r];
-      } else {
-        const int col = sh.sCol[s][pl];
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-          const int j = 16 * nt + r;
-          B[nt] = (col == j || (col == 64 && j < K)) ? 1.f : 0.f;
-        }
-      }
-#pragma unroll
-      for (int nt = 0; nt < 4; ++nt) G[nt] = mfma(av, B[nt], G[nt]);
-    }
+    if (Lc)
+      grad_rows_internal(G, tcol, sh.sCF, sh.sL[s], g, r);
+    else
+      grad_rows_tip(G, tcol, sh.sCF, sh.sCol[s], K, g, r);
     if (bt + 1 < n_tiles) cur = nxt;
   }
   EPOCH_GLOBAL float* dst = gptr(pr.Gpart + ((size_t)pr.gslots[pr.n_nodes + c] + blockIdx.x) * KK);
