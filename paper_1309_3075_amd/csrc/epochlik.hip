@@ -610,15 +610,25 @@ int set_tree_epochs(EpochInstance* in, const int32_t* parent, const double* heig
   if (plan_tree(in->N, parent, height, branch_rate, n_intervals, boundaries, interval_process, in->S, plan, err))
     return set_error(EPOCH_ERR_ARG, "set_tree_epochs: %s", err.c_str());
   const size_t n = in->n_nodes, nseg = plan.seg_process.size(), Nm1 = in->N - 1;
-  // int32 block: parent, left, right [n], level_nodes [N-1], seg_offset [n+1], seg_process [nseg]
+  // int32 block: parent, left, right [n], level_nodes [N-1], seg_offset [n+1], seg_process [nseg],
+  // chain_order [n] (nodes by descending segment count, so that the matrix-core chain kernels
+  // start the longest products first)
   std::vector<int32_t> hi;
-  hi.reserve(3 * n + Nm1 + n + 1 + nseg);
+  hi.reserve(3 * n + Nm1 + n + 1 + nseg + n);
   hi.insert(hi.end(), plan.parent.begin(), plan.parent.end());
   hi.insert(hi.end(), plan.left.begin(), plan.left.end());
   hi.insert(hi.end(), plan.right.begin(), plan.right.end());
   hi.insert(hi.end(), plan.level_nodes.begin(), plan.level_nodes.end());
   hi.insert(hi.end(), plan.seg_offset.begin(), plan.seg_offset.end());
   hi.insert(hi.end(), plan.seg_process.begin(), plan.seg_process.end());
+  {
+    std::vector<int32_t> order(n);
+    for (size_t v = 0; v < n; ++v) order[v] = (int32_t)v;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+      return plan.seg_offset[a + 1] - plan.seg_offset[a] > plan.seg_offset[b + 1] - plan.seg_offset[b];
+    });
+    hi.insert(hi.end(), order.begin(), order.end());
+  }
   std::vector<double> hd;
   hd.reserve(2 * n + 2 * nseg);
   hd.insert(hd.end(), plan.rate.begin(), plan.rate.end());
@@ -636,6 +646,7 @@ int set_tree_epochs(EpochInstance* in, const int32_t* parent, const double* heig
   in->d_level_nodes = bi + 3 * n;
   in->d_seg_offset = bi + 3 * n + Nm1;
   in->d_seg_process = in->d_seg_offset + n + 1;
+  in->d_chain_order = in->d_seg_process + nseg;
   double* bd = static_cast<double*>(in->tree_d.ptr);
   in->d_rate = bd;
   in->d_tau = bd + n;

@@ -51,6 +51,7 @@ struct PStageDesc {
   const void* li;
   const int32_t* seg_offset;
   const int32_t* seg_process;
+  const int32_t* chain_order;  // nodes by descending segment count (work item i takes node chain_order[i / C])
   const double* seg_time;
   const double* seg_frac;
   const double* rate;
@@ -172,7 +173,7 @@ struct EpochInstance {
 
   // device pointers into tree_i / tree_d
   int32_t *d_parent = nullptr, *d_left = nullptr, *d_right = nullptr, *d_level_nodes = nullptr,
-          *d_seg_offset = nullptr, *d_seg_process = nullptr;
+          *d_seg_offset = nullptr, *d_seg_process = nullptr, *d_chain_order = nullptr;
   double *d_rate = nullptr, *d_tau = nullptr, *d_seg_time = nullptr, *d_seg_frac = nullptr;
 };
 

@@ -57,7 +57,7 @@ __device__ inline void pstage_stripe(const PStageDesc& pd, int gw, ColCoef<T>* c
   TO* __restrict__ Pout = static_cast<TO*>(pd.Pout);
   TO* __restrict__ dPout = static_cast<TO*>(pd.dPout);
   const int lane = threadIdx.x & 63;
-  const int v = item / C, c = item - v * C;
+  const int v = pd.chain_order[item / C], c = item - (item / C) * C;
   const int g = lane >> 4, n = lane & 15;
   const int row = 16 * stripe + n;  // row of P this lane's column of X^T belongs to
   const int arow = Mfma<T>::a_row(n);
@@ -233,6 +233,7 @@ PStageDesc pstage_descriptor(const EpochInstance* in) {
   d.li = base + (2 * S * KK + S * in->Kp) * es;
   d.seg_offset = in->d_seg_offset;
   d.seg_process = in->d_seg_process;
+  d.chain_order = in->d_chain_order;
   d.seg_time = in->d_seg_time;
   d.seg_frac = in->d_seg_frac;
   d.rate = in->d_rate;

@@ -363,15 +363,16 @@ __global__ __launch_bounds__(256) void qgrad_chain_kernel(
     int C, int root, const T* __restrict__ eigV, const T* __restrict__ eigVi, const T* __restrict__ eigVT,
     const T* __restrict__ eigViT, const T* __restrict__ lre, const T* __restrict__ lim,
     const int32_t* __restrict__ seg_offset, const int32_t* __restrict__ seg_process,
-    const double* __restrict__ seg_time, const double* __restrict__ rate, const double* __restrict__ cat_rates,
-    const double* __restrict__ G, T* __restrict__ Ubuf, double* __restrict__ Yseg, double* __restrict__ qtau,
+    const int32_t* __restrict__ chain_order, const double* __restrict__ seg_time, const double* __restrict__ rate,
+    const double* __restrict__ cat_rates, const double* __restrict__ G, T* __restrict__ Ubuf,
+    double* __restrict__ Yseg, double* __restrict__ qtau,
     const double* __restrict__ lr64, const double* __restrict__ li64, double* __restrict__ qexp) {
   using acc = typename Mfma<T>::acc;
   constexpr int Kp = 16 * NT, KK = Kp * Kp, LD = Kp + 1;
   __shared__ T sU[Kp * LD];
   __shared__ T sW[Kp * LD];
-  __shared__ T s_coef[NT][64][2];
-  const int v = blockIdx.x / C, c = blockIdx.x - (blockIdx.x / C) * C;
+  __shared__ T s_coef[NT][2 * 64][2];
+  const int v = chain_order[blockIdx.x / C], c = blockIdx.x - (blockIdx.x / C) * C;  // longest chains first
   if (v == root) return;
   const int seg0 = seg_offset[v], m = seg_offset[v + 1] - seg0;
   if (m == 0) return;  // uniform over the block
@@ -404,6 +405,28 @@ __global__ __launch_bounds__(256) void qgrad_chain_kernel(
 #pragma unroll
       for (int q = 0; q < 4; ++q) R[0][mt][q] = T(Gr[16 * mt + q]);
   }
+  // Segment k - 1's column coefficients, U rows and first V^-T operands are
+  // produced while the matrix cores run segment k (coefficients double-buffered
+  // by k parity).
+  auto make_coef = [&](int k) {
+    if (k > 0 && lane < Kp) {
+      const int s = seg_process[seg0 + k];
+      const BlockCoef<T> bc = block_coef(lre + (size_t)s * Kp, lim + (size_t)s * Kp, lane, T(scale * seg_time[seg0 + k]));
+      coef[64 * (k & 1) + lane][0] = bc.m_self;
+      coef[64 * (k & 1) + lane][1] = -bc.m_other;
+    }
+  };
+  auto load_u = [&](int k, T (&u)[NT][4]) {
+    const T* U = Ubuf + ((size_t)(seg0 + k) * C + c) * KK + (size_t)row * Kp + 4 * g;
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) u[mt][q] = U[16 * mt + q];
+  };
+  T aw[2][4][NT], av[2][4][NT], u[NT][4], un[NT][4];
+  make_coef(m - 1);
+  load_u(m - 1, u);
+  stripe_load<T, NT>(eigViT + (size_t)seg_process[seg0 + m - 1] * KK, 0, g, arow, aw[0]);
   for (int k = m - 1; k >= 0; --k) {
     const int s = seg_process[seg0 + k];
     const T* VT = eigVT + (size_t)s * KK;
@@ -412,21 +435,27 @@ __global__ __launch_bounds__(256) void qgrad_chain_kernel(
     acc wk[1][NT];
 #pragma unroll
     for (int mt = 0; mt < NT; ++mt) wk[0][mt] = acc{0, 0, 0, 0};
-    stripe_gemm<T, NT, 1>(ViT, g, arow, R, wk);
+    stripe_gemm_from<T, NT, 1>(ViT, g, arow, aw, R, wk);
+    if (k > 0) {  // while those MFMAs run
+      stripe_load<T, NT>(VT, 0, g, arow, av[0]);
+      stripe_load<T, NT>(eigViT + (size_t)seg_process[seg0 + k - 1] * KK, 0, g, arow, aw[0]);
+      load_u(k - 1, un);
+      make_coef(k - 1);
+    }
     // stage this stripe's rows of W_k and U_k
-    const T* U = Ubuf + ((size_t)(seg0 + k) * C + c) * KK + (size_t)row * Kp + 4 * g;
 #pragma unroll
     for (int mt = 0; mt < NT; ++mt)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         sW[row * LD + 16 * mt + 4 * g + q] = wk[0][mt][q];
-        sU[row * LD + 16 * mt + 4 * g + q] = U[16 * mt + q];
+        sU[row * LD + 16 * mt + 4 * g + q] = u[mt][q];
       }
     __syncthreads();
     // rows 16 w .. 16 w + 15 of Y_k = U_k^T W_k (contraction over every row i)
     acc yv[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) yv[nt] = acc{0, 0, 0, 0};
+#pragma unroll
     for (int kk = 0; kk < Kp / 4; ++kk) {
       const int i = 4 * kk + g;
       const T a = sU[i * LD + 16 * w + arow];
@@ -438,27 +467,24 @@ __global__ __launch_bounds__(256) void qgrad_chain_kernel(
     for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
       for (int q = 0; q < 4; ++q) Y[(size_t)(16 * w + 4 * g + q) * Kp + 16 * nt + n] = (double)yv[nt][q];
-    __syncthreads();
+    __syncthreads();  // also orders this wavefront's coefficient writes before the reads below
     if (k > 0) {
       // R <- R + (W (E_k - I)^T) V^T; the transposed rotation flips the partner sign
-      const double tau_d = scale * seg_time[seg0 + k];
-      if (lane < Kp) {
-        const BlockCoef<T> bc = block_coef(lre + (size_t)s * Kp, lim + (size_t)s * Kp, lane, T(tau_d));
-        coef[lane][0] = bc.m_self;
-        coef[lane][1] = -bc.m_other;
-      }
-      wave_lds_sync();
+      const T(*ck)[2] = coef + 64 * (k & 1);
 #pragma unroll
       for (int mt = 0; mt < NT; ++mt)
 #pragma unroll
         for (int q = 0; q < 4; q += 2) {
           const int j = 16 * mt + 4 * g + q;
           const T y0 = wk[0][mt][q], y1 = wk[0][mt][q + 1];
-          wk[0][mt][q] = coef[j][0] * y0 + coef[j][1] * y1;
-          wk[0][mt][q + 1] = coef[j + 1][0] * y1 + coef[j + 1][1] * y0;
+          wk[0][mt][q] = ck[j][0] * y0 + ck[j][1] * y1;
+          wk[0][mt][q + 1] = ck[j + 1][0] * y1 + ck[j + 1][1] * y0;
         }
-      wave_lds_sync();
-      stripe_gemm<T, NT, 1>(VT, g, arow, wk, R);
+      stripe_gemm_from<T, NT, 1>(VT, g, arow, av, wk, R);
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) u[mt][q] = un[mt][q];
     }
   }
 }
@@ -620,7 +646,8 @@ int qgrad_mfma_launch(EpochInstance* in) {
   double* qexp = static_cast<double*>(in->qtau.ptr) + in->plan.seg_process.size() * C;
   hipLaunchKernelGGL((qgrad_chain_kernel<T, NT>), dim3(in->n_nodes * C), dim3(64 * NT), 0, in->stream, C,
                      in->plan.root, base, base + S * KK, baseT, baseT + S * KK, lr, lr + S * Kp, in->d_seg_offset,
-                     in->d_seg_process, in->d_seg_time, in->d_rate, static_cast<const double*>(in->cat.ptr),
+                     in->d_seg_process, in->d_chain_order, in->d_seg_time, in->d_rate,
+                     static_cast<const double*>(in->cat.ptr),
                      static_cast<const double*>(in->G.ptr), static_cast<T*>(in->qscratch.ptr),
                      static_cast<double*>(in->qseg.ptr), static_cast<double*>(in->qtau.ptr),
                      static_cast<const double*>(in->eig64.ptr) + 2 * S * KK,
