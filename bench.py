@@ -254,7 +254,7 @@ def main():
     walk = args.precision == "fp32" and -(-prob.n_patterns // (64 // cp)) <= 1024
     names = {"nuc": {"post_order": "nuc_walk_mfma (post-order program)" if walk else "nuc_post_level",
                      "pre_order_dP": "nuc_walk_mfma (pre-order program)" if walk else "nuc_pre_level"},
-             "codon": {"post_order": "codon_post_level", "pre_order_dP": "codon_pre_level"},
+             "codon": {"post_order": "codon_post_level", "pre_order_dP": "codon_pre_level + codon_pre_split"},
              "generic": {"post_order": "post_level_generic", "pre_order_dP": "pre_level_generic + grad_G_generic"}}
     Kp = 4 if prob.n_states <= 4 else (8 if prob.n_states <= 8 else (prob.n_states + 15) // 16 * 16)
     mfma_pstage = args.kernel == "auto" and Kp >= 16
