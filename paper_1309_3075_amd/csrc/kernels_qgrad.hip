@@ -584,7 +584,9 @@ __global__ __launch_bounds__(256) void qgrad_hsum_kernel(int KK, int n_chunks, c
 // dQ_s = V^-T Re(T^-T H_s T^T) V^T.  Block (s, band) forms rows 16 band ..
 // 16 band + 15: X = Re(T^-T H T^T) in LDS, then those rows of Y = V^-T X
 // (the 16 columns of V^-1 staged in LDS), then dQ rows = Y_rows V^T with V
-// replacing X in LDS (Kp^2 + 32 Kp doubles).
+// replacing X in LDS, its rows padded to Kp + 1 doubles so that lanes reading
+// one column of different rows fall in different banks (Kp (Kp + 1) + 32 Kp
+// doubles).
 __global__ __launch_bounds__(256) void qgrad_final_kernel(int K, int Kp, const double* __restrict__ Hsum,
                                                           const double* __restrict__ V, const double* __restrict__ Vi,
                                                           const double* __restrict__ li_all, double* __restrict__ dQ) {
@@ -592,8 +594,8 @@ __global__ __launch_bounds__(256) void qgrad_final_kernel(int K, int Kp, const d
   const int s = blockIdx.x, r0 = 16 * blockIdx.y;
   const int KK = Kp * Kp;
   double* sX = reinterpret_cast<double*>(smem_raw);
-  double* sY = sX + KK;        // 16 x Kp
-  double* sVi = sY + 16 * Kp;  // Kp x 16: columns r0 .. r0 + 15 of V^-1
+  double* sY = sX + Kp * (Kp + 1);  // 16 x Kp
+  double* sVi = sY + 16 * Kp;       // Kp x 16: columns r0 .. r0 + 15 of V^-1
   const double* li = li_all + (size_t)s * Kp;
   const double2* H = reinterpret_cast<const double2*>(Hsum) + (size_t)s * KK;
   const double* Vis = Vi + (size_t)s * KK;
@@ -623,14 +625,14 @@ __global__ __launch_bounds__(256) void qgrad_final_kernel(int K, int Kp, const d
     sY[e] = r;
   }
   __syncthreads();
-  double* sV = sX;
-  for (int e = threadIdx.x; e < KK; e += 256) sV[e] = V[(size_t)s * KK + e];
+  double* sV = sX;  // row stride Kp + 1
+  for (int e = threadIdx.x; e < KK; e += 256) sV[(e / Kp) * (Kp + 1) + e % Kp] = V[(size_t)s * KK + e];
   __syncthreads();
   for (int e = threadIdx.x; e < 16 * Kp; e += 256) {
     const int i = r0 + e / Kp, j = e % Kp;
     if (i < K && j < K) {
       double r = 0.0;
-      for (int l = 0; l < Kp; ++l) r += sY[(i - r0) * Kp + l] * sV[j * Kp + l];
+      for (int l = 0; l < Kp; ++l) r += sY[(i - r0) * Kp + l] * sV[j * (Kp + 1) + l];
       dQ[((size_t)s * K + i) * K + j] = r;
     }
   }
@@ -664,11 +666,12 @@ int qgrad_mfma_launch(EpochInstance* in) {
   hipLaunchKernelGGL(qgrad_h_kernel, grid, dim3(256), 0, in->stream, Kp, in->q_chunks, in->q_chunk_items, lo, items,
                      static_cast<const double*>(in->qseg.ptr), static_cast<const double*>(in->qtau.ptr), qexp,
                      b64 + 2 * S * KK, b64 + 2 * S * KK + S * Kp, Hpart);
+
   hipLaunchKernelGGL(qgrad_hsum_kernel, dim3((unsigned)((KK + 255) / 256), (unsigned)S), dim3(256), 0, in->stream,
                      (int)KK, in->q_chunks, static_cast<const double*>(Hpart), Hsum);
   rc = hip_check(hipGetLastError(), "qgrad_h launch");
   if (rc) return rc;
-  hipLaunchKernelGGL(qgrad_final_kernel, dim3(in->S, Kp / 16), dim3(256), (KK + 32 * Kp) * sizeof(double),
+  hipLaunchKernelGGL(qgrad_final_kernel, dim3(in->S, Kp / 16), dim3(256), (KK + 33 * Kp) * sizeof(double),
                      in->stream, in->K, Kp, static_cast<const double*>(Hsum), b64, b64 + S * KK,
                      b64 + 2 * S * KK + S * Kp, static_cast<double*>(in->dQ.ptr));
   return hip_check(hipGetLastError(), "qgrad_final launch");
