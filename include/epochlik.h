@@ -81,20 +81,20 @@ typedef struct EpochConfig {
   int32_t kernel_path;     /* EPOCH_KERNEL_AUTO or EPOCH_KERNEL_GENERIC */
   int32_t reserved;        /* must be 0 */
   int64_t hbm_budget_bytes; /* 0 = unlimited.  > 0: device bytes allowed for intermediate
-                             * partials (and their scale rows and gradient partial sums), with
-                             * EPOCH_KERNEL_AUTO on one of two paths:
-                             * - n_states == 4, no EPOCH_GRAD_Q: the tree walk stores only the
-                             *   partials of the largest subtrees that fit and recomputes the
-                             *   others from the tip states in the gradient pass; set_tree_epochs
-                             *   returns EPOCH_ERR_OOM when even the root alone does not fit.
-                             * - 48 < n_states <= 64, EPOCH_FP32, one category: the patterns are
-                             *   evaluated in chunks (a multiple of 64 patterns) whose partials,
-                             *   outside vectors, scale exponents and dlogL/dP partial sums fit;
-                             *   update_partials forms each chunk's partials and its share of
-                             *   logL, and the gradient call forms them again chunk by chunk.
+                             * partials (and their scale rows and gradient partial sums):
+                             * - n_states == 4 with EPOCH_KERNEL_AUTO, no EPOCH_GRAD_Q: the tree
+                             *   walk stores only the partials of the largest subtrees that fit
+                             *   and recomputes the others from the tip states in the gradient
+                             *   pass; set_tree_epochs returns EPOCH_ERR_OOM when even the root
+                             *   alone does not fit.
+                             * - every other configuration (the 64-state kernels and the generic
+                             *   kernels, EPOCH_GRAD_Q allowed): the patterns are evaluated in
+                             *   chunks (a multiple of 64 patterns) whose partials, outside
+                             *   vectors, scale exponents (and 64-state dlogL/dP partial sums)
+                             *   fit; update_partials forms each chunk's partials and its share
+                             *   of logL, and the gradient call forms them again chunk by chunk.
                              *   epoch_create returns EPOCH_ERR_ARG when one chunk of
-                             *   min(64, n_patterns) patterns does not fit.
-                             * Other configurations return EPOCH_ERR_ARG. */
+                             *   min(64, n_patterns) patterns does not fit. */
   void* stream;            /* hipStream_t to run on, or NULL for the default stream */
   void* workspace;         /* NULL, or caller-owned device memory (e.g. a torch tensor) of
                             * workspace_bytes bytes that holds the pattern-sized buffers (tip

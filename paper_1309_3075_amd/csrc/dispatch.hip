@@ -77,11 +77,61 @@ int fastpath_pstage(EpochInstance* in) {
   return EPOCH_OK;
 }
 
+namespace {
+// Generic path under an HBM budget: select pattern chunk j (or all patterns, j < 0).
+void set_view(EpochInstance* in, int j, bool accumulate) {
+  if (j < 0) {
+    in->view_P = in->view_p0 = in->view_j = 0;
+    in->view_accumulate = false;
+    return;
+  }
+  in->view_p0 = j * in->gen_pc;
+  in->view_P = std::min(in->P - in->view_p0, in->gen_pc);
+  in->view_j = j;
+  in->view_accumulate = accumulate;
+}
+
+// Post-order pass of the generic path; in pattern chunks, each chunk's share of
+// logL follows its partials (the next chunk overwrites them), then the shares
+// are summed in order.
+int launch_post_generic_chunks(EpochInstance* in) {
+  if (in->gen_nchunks == 1) return launch_post_generic(in);
+  for (int j = 0; j < in->gen_nchunks; ++j) {
+    set_view(in, j, false);
+    int rc = launch_post_generic(in);
+    if (!rc) rc = launch_root_generic(in);
+    if (rc) {
+      set_view(in, -1, false);
+      return rc;
+    }
+  }
+  set_view(in, -1, false);
+  return launch_chunk_sum(in, in->gen_nchunks);
+}
+
+// Pre-order pass and dlogL/dP of the generic path; in pattern chunks, each
+// chunk's partials are formed again first and dlogL/dP accumulates over chunks.
+int launch_pre_grad_generic_chunks(EpochInstance* in) {
+  for (int j = 0; j < in->gen_nchunks; ++j) {
+    if (in->gen_nchunks > 1) set_view(in, j, j > 0);
+    int rc = in->gen_nchunks > 1 ? launch_post_generic(in) : EPOCH_OK;
+    if (!rc) rc = launch_pre_generic(in);
+    if (!rc) rc = launch_grad_branch_generic(in);
+    if (rc) {
+      set_view(in, -1, false);
+      return rc;
+    }
+  }
+  set_view(in, -1, false);
+  return EPOCH_OK;
+}
+}  // namespace
+
 int launch_post(EpochInstance* in) {
   if (nuc(in) && in->budget > 0 && !in->walk_ok)
     return set_error(EPOCH_ERR_STATE, "no tree-walk schedule for the HBM budget");
   if (nuc(in)) return in->walk_ok ? launch_walk_post(in) : launch_nuc_post(in);
-  return codon(in) ? launch_codon_post(in) : launch_post_generic(in);
+  return codon(in) ? launch_codon_post(in) : launch_post_generic_chunks(in);
 }
 
 int fastpath_post(EpochInstance* in) {
@@ -90,6 +140,7 @@ int fastpath_post(EpochInstance* in) {
 }
 
 int fastpath_root(EpochInstance* in) {
+  if (!nuc(in) && !codon(in) && in->gen_nchunks > 1) return EPOCH_OK;  // formed with the chunks' partials
   EPOCH_PHASE(2, nuc(in) ? launch_nuc_root(in) : (codon(in) ? launch_codon_root(in) : launch_root_generic(in)));
   return EPOCH_OK;
 }
@@ -102,6 +153,8 @@ int fastpath_gradient(EpochInstance* in, bool want_Q) {
     EPOCH_PHASE(4, launch_grad_reduce(in, in->nuc_slots, static_cast<const int32_t*>(in->gslots.ptr)));
   } else if (codon(in)) {
     EPOCH_PHASE(3, launch_codon_pre_grad(in));
+  } else if (in->gen_nchunks > 1) {
+    EPOCH_PHASE(3, launch_pre_grad_generic_chunks(in));
   } else {
     EPOCH_PHASE(3, launch_pre_generic(in));
     EPOCH_PHASE(4, launch_grad_branch_generic(in));

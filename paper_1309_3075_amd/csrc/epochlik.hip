@@ -179,6 +179,15 @@ size_t codon_bytes_per_pattern(const EpochConfig& c) {
          (grad ? Nm1 * 64 * sizeof(float) + 2 * Nm1 * kCodonSlotBytes / 64 : 0);
 }
 
+// Device bytes one pattern of a chunk costs on the generic path: partials and
+// scale exponents of every internal node, and outside vectors with a gradient.
+size_t generic_bytes_per_pattern(const EpochConfig& c) {
+  const bool grad = (c.flags & (EPOCH_GRAD_BRANCH | EPOCH_GRAD_Q)) != 0;
+  const size_t Nm1 = (size_t)c.n_tips - 1, R = c.precision == EPOCH_FP64 ? 8 : 4;
+  const size_t row = (size_t)c.n_categories * padded_states(c.n_states) * R;
+  return Nm1 * (row * (grad ? 2 : 1) + sizeof(int32_t));
+}
+
 void invalidate_downstream(EpochInstance* in) {
   in->P_valid = false;
   in->partials_valid = false;
@@ -214,16 +223,18 @@ int epoch_create(const EpochConfig* cfg, EpochInstance** out) {
     return set_error(EPOCH_ERR_ARG, "unknown kernel_path");
   if (c.reserved != 0) return set_error(EPOCH_ERR_ARG, "reserved must be 0");
   if (c.hbm_budget_bytes < 0) return set_error(EPOCH_ERR_ARG, "hbm_budget_bytes must be >= 0");
+  // HBM budgets: the 4-state tree walk recomputes subtrees; the 64-state and generic
+  // paths evaluate the patterns in chunks
+  const bool nuc_budget = c.hbm_budget_bytes > 0 && c.n_states == 4 && c.kernel_path == EPOCH_KERNEL_AUTO;
   const bool codon_budget = c.hbm_budget_bytes > 0 && codon_budget_config(c);
-  if (c.hbm_budget_bytes > 0 && ((c.n_states != 4 && !codon_budget) || c.kernel_path != EPOCH_KERNEL_AUTO))
-    return set_error(EPOCH_ERR_ARG,
-                     "hbm_budget_bytes needs the 4-state kernels (n_states 4) or the 64-state FP32 kernels "
-                     "(48 < n_states <= 64, one category), with EPOCH_KERNEL_AUTO");
-  if (c.hbm_budget_bytes > 0 && !codon_budget && (c.flags & EPOCH_GRAD_Q))
+  const bool gen_budget = c.hbm_budget_bytes > 0 && !nuc_budget && !codon_budget;
+  if (nuc_budget && (c.flags & EPOCH_GRAD_Q))
     return set_error(EPOCH_ERR_ARG, "hbm_budget_bytes on 4-state instances cannot be combined with EPOCH_GRAD_Q");
-  if (codon_budget && (size_t)c.hbm_budget_bytes < codon_bytes_per_pattern(c) * (size_t)std::min(c.n_patterns, 64))
-    return set_error(EPOCH_ERR_ARG, "hbm_budget_bytes %lld is below the %zu bytes one tile of 64 patterns needs",
-                     (long long)c.hbm_budget_bytes, codon_bytes_per_pattern(c) * (size_t)std::min(c.n_patterns, 64));
+  const size_t chunk_pattern_bytes = codon_budget ? codon_bytes_per_pattern(c) : generic_bytes_per_pattern(c);
+  if ((codon_budget || gen_budget) &&
+      (size_t)c.hbm_budget_bytes < chunk_pattern_bytes * (size_t)std::min(c.n_patterns, 64))
+    return set_error(EPOCH_ERR_ARG, "hbm_budget_bytes %lld is below the %zu bytes one chunk of 64 patterns needs",
+                     (long long)c.hbm_budget_bytes, chunk_pattern_bytes * (size_t)std::min(c.n_patterns, 64));
   if (c.workspace && c.hbm_budget_bytes > 0)
     return set_error(EPOCH_ERR_ARG, "a workspace cannot be combined with hbm_budget_bytes");
   if (c.workspace && (c.workspace_bytes < 0 || (size_t)c.workspace_bytes < workspace_total(c, padded_states(c.n_states))))
@@ -291,15 +302,21 @@ int epoch_create(const EpochConfig* cfg, EpochInstance** out) {
   A(in->Pm, n * C * KK * R);
   if (grad) A(in->dPm, n * C * KK * R);
   in->budget = c.hbm_budget_bytes;
-  if (codon_budget) {
-    // 64-state path: the patterns run in chunks whose partials, outside vectors,
-    // scale exponents and dlogL/dP slots fit the budget
-    const size_t pc = std::min<size_t>(P, (size_t)in->budget / codon_bytes_per_pattern(c) / 64 * 64);
-    in->codon_pc = (int)pc;
-    in->codon_nchunks = (int)((P + pc - 1) / pc);
-    A(in->partials, (N - 1) * pc * Kp * R);
+  if (codon_budget || gen_budget) {
+    // 64-state and generic paths: the patterns run in chunks whose partials, outside
+    // vectors, scale exponents (and 64-state dlogL/dP slots) fit the budget
+    const size_t pc = std::min<size_t>(P, (size_t)in->budget / chunk_pattern_bytes / 64 * 64);
+    const int nc = (int)((P + pc - 1) / pc);
+    if (codon_budget) {
+      in->codon_pc = (int)pc;
+      in->codon_nchunks = nc;
+    } else {
+      in->gen_pc = (int)pc;
+      in->gen_nchunks = nc;
+    }
+    A(in->partials, (N - 1) * C * pc * Kp * R);
     A(in->scales, (N - 1) * pc * sizeof(int32_t));
-    if (grad) A(in->pre, (N - 1) * pc * Kp * R);
+    if (grad) A(in->pre, (N - 1) * C * pc * Kp * R);
   } else if (in->budget > 0) {
     in->walk_enable = 1;  // partials are sized at set_tree_epochs, within the budget
   } else {
@@ -309,7 +326,7 @@ int epoch_create(const EpochConfig* cfg, EpochInstance** out) {
   }
   A(in->site, P * sizeof(double));
   A(in->blocksum, ((P + 63) / 64 + 1) * sizeof(double));
-  A(in->result, std::max<size_t>(8, in->codon_nchunks + 1) * sizeof(double));
+  A(in->result, std::max<size_t>(8, std::max(in->codon_nchunks, in->gen_nchunks) + 1) * sizeof(double));
   if (grad) {
     A(in->Gpart, (size_t)in->n_chunks * n * C * KK * sizeof(double));
     A(in->G, n * C * KK * sizeof(double));
@@ -834,13 +851,13 @@ int epoch_set_option(EpochInstance* in, int32_t key, int64_t value) {
   switch (key) {
     case EPOCH_OPT_TREE_WALK:
       if (value < -1 || value > 1) return set_error(EPOCH_ERR_ARG, "EPOCH_OPT_TREE_WALK takes -1, 0 or 1");
-      if (in->budget > 0 && in->K == 4 && value != 1)
+      if (in->budget > 0 && in->path == 1 && value != 1)
         return set_error(EPOCH_ERR_ARG, "an HBM budget needs the tree walk");
       in->walk_enable = (int)value;
       break;
     case EPOCH_OPT_WALK_RECOMPUTE:
       if (value < 2 || value > in->N) return set_error(EPOCH_ERR_ARG, "EPOCH_OPT_WALK_RECOMPUTE takes 2..N");
-      if (in->budget > 0 && in->K == 4)
+      if (in->budget > 0 && in->path == 1)
         return set_error(EPOCH_ERR_ARG, "under an HBM budget the budget sets the recomputation");
       in->walk_recompute = (int)value;
       break;

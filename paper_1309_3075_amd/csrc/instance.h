@@ -162,6 +162,11 @@ struct EpochInstance {
   int codon_target_blocks = 1024;  // blocks per pre-order launch the 64-state schedule aims for
   int codon_pc = 0;                // 64-state path under an HBM budget: patterns per chunk (0: all at once)
   int codon_nchunks = 1;           // pattern chunks evaluated one after another
+  int gen_pc = 0;                  // generic path under an HBM budget: patterns per chunk (0: all at once)
+  int gen_nchunks = 1;
+  // the pattern chunk the generic launches work on (view_P == 0: all patterns)
+  int view_P = 0, view_p0 = 0, view_j = 0;
+  bool view_accumulate = false;    // dlogL/dP of this chunk adds to the earlier chunks
   int codon_split_blocks = 256;    // narrow pre-order levels (at most this many blocks) use the side-split kernel
 
   // per-phase timing (epoch_set_timing)
@@ -208,6 +213,7 @@ int launch_pre_generic(EpochInstance* in);
 int launch_grad_branch_generic(EpochInstance* in);
 int launch_grad_Q_generic(EpochInstance* in);
 int launch_final_sum(EpochInstance* in, int n_blocks);
+int launch_chunk_sum(EpochInstance* in, int n);  // result[0] = result[1] + ... + result[n], in order
 int launch_grad_reduce(EpochInstance* in, int n_chunks, const int32_t* chunks_per_node);
 
 // 4-state kernels (kernels_nuc.hip)

@@ -251,15 +251,6 @@ __global__ __launch_bounds__(256) void codon_final_kernel(const CodonProblem* __
   if (threadIdx.x == 0) pr.result[0] = tot;
 }
 
-// logL of pattern chunks 1 .. n (in result[1 .. n]) summed in order into result[0].
-__global__ void codon_chunk_sum_kernel(double* __restrict__ result, int n) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double acc = 0.0;
-    for (int j = 1; j <= n; ++j) acc += result[j];
-    result[0] = acc;
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Pre-order of one level fused with dlogL/dP of the two child branches.
 //
@@ -918,8 +909,7 @@ int launch_codon_post(EpochInstance* in) {
     if (!rc) rc = codon_launch_root(in->codon_sched, dev_probs(in) + j, in->stream);
     if (rc) return rc;
   }
-  hipLaunchKernelGGL(codon_chunk_sum_kernel, dim3(1), dim3(64), 0, in->stream, static_cast<double*>(in->result.ptr), nc);
-  return hip_check(hipGetLastError(), "codon_chunk_sum launch");
+  return launch_chunk_sum(in, nc);
 }
 
 int launch_codon_root(EpochInstance* in) {

@@ -166,11 +166,12 @@ __global__ __launch_bounds__(256) void pstage_generic_kernel(
 // thread = (pattern, state).  Children tiles staged through LDS per category.
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ inline T child_vector(int child, int N, int p, int P, int K, int Kp, int i, const T* Prow,
+__device__ inline T child_vector(int child, int N, int p, int tstride, int K, int Kp, int i, const T* Prow,
                                  const uint8_t* tips, const T* sL) {
-  // (P_child L_child)(i) for a pattern; Prow points at row i of the child's matrix.
+  // (P_child L_child)(i) for a pattern; Prow points at row i of the child's matrix; tstride is the
+  // row stride of the tip states (the instance's pattern count).
   if (child < N) {
-    const int st = tips[(size_t)child * P + p];
+    const int st = tips[(size_t)child * tstride + p];
     if (st < K) return Prow[st];
     T r = 0;
     for (int j = 0; j < K; ++j) r += Prow[j];
@@ -185,7 +186,7 @@ template <typename T, int KQ>
 __global__ __launch_bounds__(256) void post_level_generic_kernel(
     const int32_t* __restrict__ nodes, const int32_t* __restrict__ left,
     const int32_t* __restrict__ right, const T* __restrict__ Pm, const uint8_t* __restrict__ tips,
-    T* __restrict__ partials, int32_t* __restrict__ scales, int N, int P, int K, int Kp, int C) {
+    T* __restrict__ partials, int32_t* __restrict__ scales, int N, int P, int tstride, int K, int Kp, int C) {
   constexpr int TP = 256 / KQ;
   __shared__ T sA[256], sB[256];
   const int u = nodes[blockIdx.y];
@@ -202,8 +203,8 @@ __global__ __launch_bounds__(256) void post_level_generic_kernel(
     __syncthreads();
     T r = 0;
     if (pok && i < K) {
-      const T va = child_vector(a, N, p, P, K, Kp, i, Pm + ((size_t)a * C + c) * KK + (size_t)i * Kp, tips, sA + pl * KQ);
-      const T vb = child_vector(b, N, p, P, K, Kp, i, Pm + ((size_t)b * C + c) * KK + (size_t)i * Kp, tips, sB + pl * KQ);
+      const T va = child_vector(a, N, p, tstride, K, Kp, i, Pm + ((size_t)a * C + c) * KK + (size_t)i * Kp, tips, sA + pl * KQ);
+      const T vb = child_vector(b, N, p, tstride, K, Kp, i, Pm + ((size_t)b * C + c) * KK + (size_t)i * Kp, tips, sB + pl * KQ);
       r = va * vb;
     }
     x[c] = r;
@@ -260,6 +261,15 @@ __global__ __launch_bounds__(256) void final_sum_kernel(const double* __restrict
   if (threadIdx.x == 0) out[0] = tot;
 }
 
+// Log-likelihoods of pattern chunks 1 .. n (in result[1 .. n]) summed in order into result[0].
+__global__ void chunk_sum_kernel(double* __restrict__ result, int n) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double acc = 0.0;
+    for (int j = 1; j <= n; ++j) acc += result[j];
+    result[0] = acc;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Pre-order, one level (root downwards): outside vectors of internal children.
 //   child a of u (sibling b): t_a = q_u * (P_b L_b);  q_a = P_a^T t_a, rescaled.
@@ -269,7 +279,7 @@ __global__ __launch_bounds__(256) void pre_level_generic_kernel(
     const int32_t* __restrict__ nodes, const int32_t* __restrict__ left,
     const int32_t* __restrict__ right, const T* __restrict__ Pm, const uint8_t* __restrict__ tips,
     const T* __restrict__ partials, T* __restrict__ pre, const double* __restrict__ pi, int root,
-    int N, int P, int K, int Kp, int C) {
+    int N, int P, int tstride, int K, int Kp, int C) {
   constexpr int TP = 256 / KQ;
   __shared__ T sQ[256], sA[256], sB[256], sTa[256], sTb[256];
   const int u = nodes[blockIdx.y];
@@ -291,8 +301,8 @@ __global__ __launch_bounds__(256) void pre_level_generic_kernel(
     __syncthreads();
     T ta = 0, tb = 0;
     if (pok && i < K) {
-      const T va = child_vector(a, N, p, P, K, Kp, i, Pm + ((size_t)a * C + c) * KK + (size_t)i * Kp, tips, sA + pl * KQ);
-      const T vb = child_vector(b, N, p, P, K, Kp, i, Pm + ((size_t)b * C + c) * KK + (size_t)i * Kp, tips, sB + pl * KQ);
+      const T va = child_vector(a, N, p, tstride, K, Kp, i, Pm + ((size_t)a * C + c) * KK + (size_t)i * Kp, tips, sA + pl * KQ);
+      const T vb = child_vector(b, N, p, tstride, K, Kp, i, Pm + ((size_t)b * C + c) * KK + (size_t)i * Kp, tips, sB + pl * KQ);
       const T q = sQ[threadIdx.x];
       ta = q * vb;
       tb = q * va;
@@ -341,7 +351,7 @@ __global__ __launch_bounds__(256) void grad_G_generic_kernel(
     const int32_t* __restrict__ right, const T* __restrict__ Pm, const uint8_t* __restrict__ tips,
     const T* __restrict__ partials, const T* __restrict__ pre, const double* __restrict__ pi,
     const double* __restrict__ cat, const double* __restrict__ weights, int root, int N, int n_nodes,
-    int P, int K, int Kp, int C, int n_chunks, double* __restrict__ Gpart) {
+    int P, int tstride, int K, int Kp, int C, int n_chunks, double* __restrict__ Gpart) {
   constexpr int TP = 256 / KQ;
   __shared__ T sQ[256], sV[256], sW[256];
   __shared__ T sAc[kMaxCategories][256];
@@ -373,15 +383,15 @@ __global__ __launch_bounds__(256) void grad_G_generic_kernel(
       T lv = 0;  // L_v(i)
       T tvi = 0;
       if (pok && i < K) {
-        const T sv = child_vector(v, N, p, P, K, Kp, i, Pm + ((size_t)v * C + c) * KK + (size_t)i * Kp, tips, sV + pl * KQ);
-        const T sw = child_vector(w, N, p, P, K, Kp, i, Pm + ((size_t)w * C + c) * KK + (size_t)i * Kp, tips, sW + pl * KQ);
+        const T sv = child_vector(v, N, p, tstride, K, Kp, i, Pm + ((size_t)v * C + c) * KK + (size_t)i * Kp, tips, sV + pl * KQ);
+        const T sw = child_vector(w, N, p, tstride, K, Kp, i, Pm + ((size_t)w * C + c) * KK + (size_t)i * Kp, tips, sW + pl * KQ);
         const T q = sQ[threadIdx.x];
         tvi = q * sw;
         acc += T(cat[kMaxCategories + c]) * tvi * sv;
         if (v >= N) {
           lv = sV[threadIdx.x];
         } else {
-          const int st = tips[(size_t)v * P + p];
+          const int st = tips[(size_t)v * tstride + p];
           lv = (st >= K || st == i) ? T(1) : T(0);
         }
       }
@@ -424,7 +434,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void grad_reduce_branch_kernel(
     const double* __restrict__ Gpart, const T* __restrict__ dP, int n_slots,
     const int32_t* __restrict__ chunks_per_node, int n_nodes, int nG, int root, double* __restrict__ G,
-    double* __restrict__ dbranch) {
+    double* __restrict__ dbranch, int accumulate) {
   __shared__ double sm[256];
   const int v = blockIdx.x;
   const double* src = Gpart + (size_t)v * n_slots * nG;
@@ -442,6 +452,7 @@ __global__ __launch_bounds__(256) void grad_reduce_branch_kernel(
     if (g == 0 && e < nG) {
       double tot = 0.0;
       for (int q = 0; q < groups; ++q) tot += sm[q * (256 / groups) + threadIdx.x];
+      if (accumulate) tot += G[(size_t)v * nG + e];  // earlier pattern chunks
       G[(size_t)v * nG + e] = tot;
       d += tot * (double)dP[(size_t)v * nG + e];
     }
@@ -551,23 +562,31 @@ int pstage_dispatch(EpochInstance* in) {
   return hip_check(hipGetLastError(), "pstage_generic launch");
 }
 
+// The pattern chunk the launches below work on (all patterns unless a chunk
+// is selected under an HBM budget): count, first pattern, and the slot of its
+// log-likelihood in result.
+int view_P(const EpochInstance* in) { return in->view_P > 0 ? in->view_P : in->P; }
+size_t view_p0(const EpochInstance* in) { return in->view_P > 0 ? (size_t)in->view_p0 : 0; }
+size_t view_result(const EpochInstance* in) { return in->view_P > 0 ? 1 + (size_t)in->view_j : 0; }
+
 template <typename T>
 int post_dispatch(EpochInstance* in) {
   const int KQ = lanes_per_pattern(in->Kp);
   const int TP = 256 / KQ;
   const auto& pl = in->plan;
   const T* Pm = static_cast<const T*>(in->Pm.ptr);
-  const uint8_t* tips = static_cast<const uint8_t*>(in->tips.ptr);
+  const uint8_t* tips = static_cast<const uint8_t*>(in->tips.ptr) + view_p0(in);
   T* part = static_cast<T*>(in->partials.ptr);
   int32_t* sc = static_cast<int32_t*>(in->scales.ptr);
+  const int P = view_P(in);
   for (int l = 1; l <= pl.n_levels; ++l) {
     const int n_l = pl.level_offset[l + 1] - pl.level_offset[l];
     if (n_l == 0) continue;
-    dim3 grid((in->P + TP - 1) / TP, n_l);
+    dim3 grid((P + TP - 1) / TP, n_l);
     const int32_t* nodes = in->d_level_nodes + pl.level_offset[l];
 #define EPOCH_POST(Q)                                                                            \
   hipLaunchKernelGGL((post_level_generic_kernel<T, Q>), grid, dim3(256), 0, in->stream, nodes,    \
-                     in->d_left, in->d_right, Pm, tips, part, sc, in->N, in->P, in->K, in->Kp, in->C)
+                     in->d_left, in->d_right, Pm, tips, part, sc, in->N, P, in->P, in->K, in->Kp, in->C)
     switch (KQ) {
       case 4: EPOCH_POST(4); break;
       case 8: EPOCH_POST(8); break;
@@ -582,17 +601,19 @@ int post_dispatch(EpochInstance* in) {
 
 template <typename T>
 int root_dispatch(EpochInstance* in) {
-  const int nb = (in->P + 255) / 256;
+  const int P = view_P(in);
+  const size_t p0 = view_p0(in);
+  const int nb = (P + 255) / 256;
   const T* rootp = static_cast<const T*>(in->partials.ptr) +
-                   (size_t)(in->plan.root - in->N) * in->C * (size_t)in->P * in->Kp;
+                   (size_t)(in->plan.root - in->N) * in->C * (size_t)P * in->Kp;
   double* blk = static_cast<double*>(in->blocksum.ptr);
   hipLaunchKernelGGL((root_generic_kernel<T>), dim3(nb), dim3(256), 0, in->stream, rootp,
-                     static_cast<const int32_t*>(in->scales.ptr) + (size_t)(in->plan.root - in->N) * in->P,
+                     static_cast<const int32_t*>(in->scales.ptr) + (size_t)(in->plan.root - in->N) * P,
                      static_cast<const double*>(in->pi.ptr), static_cast<const double*>(in->cat.ptr),
-                     static_cast<const double*>(in->weights.ptr), static_cast<double*>(in->site.ptr),
-                     blk, in->P, in->K, in->Kp, in->C);
+                     static_cast<const double*>(in->weights.ptr) + p0, static_cast<double*>(in->site.ptr) + p0,
+                     blk, P, in->K, in->Kp, in->C);
   hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(256), 0, in->stream, blk, nb,
-                     static_cast<double*>(in->result.ptr));
+                     static_cast<double*>(in->result.ptr) + view_result(in));
   return hip_check(hipGetLastError(), "root_generic launch");
 }
 
@@ -602,18 +623,19 @@ int pre_dispatch(EpochInstance* in) {
   const int TP = 256 / KQ;
   const auto& pl = in->plan;
   const T* Pm = static_cast<const T*>(in->Pm.ptr);
-  const uint8_t* tips = static_cast<const uint8_t*>(in->tips.ptr);
+  const uint8_t* tips = static_cast<const uint8_t*>(in->tips.ptr) + view_p0(in);
   const T* part = static_cast<const T*>(in->partials.ptr);
   T* pre = static_cast<T*>(in->pre.ptr);
   const double* pi = static_cast<const double*>(in->pi.ptr);
+  const int P = view_P(in);
   for (int l = pl.n_levels; l >= 1; --l) {
     const int n_l = pl.level_offset[l + 1] - pl.level_offset[l];
     if (n_l == 0) continue;
-    dim3 grid((in->P + TP - 1) / TP, n_l);
+    dim3 grid((P + TP - 1) / TP, n_l);
     const int32_t* nodes = in->d_level_nodes + pl.level_offset[l];
 #define EPOCH_PRE(Q)                                                                            \
   hipLaunchKernelGGL((pre_level_generic_kernel<T, Q>), grid, dim3(256), 0, in->stream, nodes,    \
-                     in->d_left, in->d_right, Pm, tips, part, pre, pi, pl.root, in->N, in->P,     \
+                     in->d_left, in->d_right, Pm, tips, part, pre, pi, pl.root, in->N, P, in->P,  \
                      in->K, in->Kp, in->C)
     switch (KQ) {
       case 4: EPOCH_PRE(4); break;
@@ -630,16 +652,16 @@ int pre_dispatch(EpochInstance* in) {
 template <typename T, int KQ, int GP>
 void grad_G_launch(EpochInstance* in, dim3 grid) {
   const T* Pm = static_cast<const T*>(in->Pm.ptr);
-  const uint8_t* tips = static_cast<const uint8_t*>(in->tips.ptr);
+  const uint8_t* tips = static_cast<const uint8_t*>(in->tips.ptr) + view_p0(in);
   const T* part = static_cast<const T*>(in->partials.ptr);
   const T* pre = static_cast<const T*>(in->pre.ptr);
   const double* pi = static_cast<const double*>(in->pi.ptr);
   const double* cat = static_cast<const double*>(in->cat.ptr);
-  const double* wts = static_cast<const double*>(in->weights.ptr);
+  const double* wts = static_cast<const double*>(in->weights.ptr) + view_p0(in);
   double* Gp = static_cast<double*>(in->Gpart.ptr);
   hipLaunchKernelGGL((grad_G_generic_kernel<T, KQ, GP>), grid, dim3(256), 0, in->stream,
                      in->d_parent, in->d_left, in->d_right, Pm, tips, part, pre, pi, cat, wts,
-                     in->plan.root, in->N, in->n_nodes, in->P, in->K, in->Kp, in->C, in->n_chunks, Gp);
+                     in->plan.root, in->N, in->n_nodes, view_P(in), in->P, in->K, in->Kp, in->C, in->n_chunks, Gp);
 }
 
 template <typename T>
@@ -671,7 +693,8 @@ int grad_reduce_dispatch(EpochInstance* in, int n_slots, const int32_t* chunks_p
   hipLaunchKernelGGL((grad_reduce_branch_kernel<T>), dim3(in->n_nodes), dim3(256), 0, in->stream,
                      static_cast<const double*>(in->Gpart.ptr), static_cast<const T*>(in->dPm.ptr),
                      n_slots, chunks_per_node, in->n_nodes, nG, in->plan.root,
-                     static_cast<double*>(in->G.ptr), static_cast<double*>(in->dbranch.ptr));
+                     static_cast<double*>(in->G.ptr), static_cast<double*>(in->dbranch.ptr),
+                     in->view_accumulate ? 1 : 0);
   return hip_check(hipGetLastError(), "grad_reduce_branch launch");
 }
 
@@ -694,6 +717,11 @@ int launch_final_sum(EpochInstance* in, int n_blocks) {
                      static_cast<const double*>(in->blocksum.ptr), n_blocks,
                      static_cast<double*>(in->result.ptr));
   return hip_check(hipGetLastError(), "final_sum launch");
+}
+
+int launch_chunk_sum(EpochInstance* in, int n) {
+  hipLaunchKernelGGL(chunk_sum_kernel, dim3(1), dim3(64), 0, in->stream, static_cast<double*>(in->result.ptr), n);
+  return hip_check(hipGetLastError(), "chunk_sum launch");
 }
 
 int launch_grad_reduce(EpochInstance* in, int n_slots, const int32_t* chunks_per_node) {

@@ -47,13 +47,11 @@ def _cfg(**kw):
                                  dict(n_categories=0), dict(n_categories=9), dict(n_processes=0),
                                  dict(max_intervals=0), dict(precision=3), dict(flags=0x10),
                                  dict(kernel_path=7), dict(reserved=1), dict(hbm_budget_bytes=-1),
-                                 dict(hbm_budget_bytes=1 << 20, n_states=20),
-                                 dict(hbm_budget_bytes=1 << 20, kernel_path=1),
-                                 dict(hbm_budget_bytes=1 << 20, flags=0x2),
-                                 dict(hbm_budget_bytes=1 << 20, n_states=61),  # the 64-state budget needs FP32
-                                 dict(hbm_budget_bytes=1 << 20, n_states=61, precision=_abi.EPOCH_FP32,
-                                      n_categories=2),
-                                 dict(hbm_budget_bytes=7799, n_states=61, precision=_abi.EPOCH_FP32)])
+                                 dict(hbm_budget_bytes=1 << 20, flags=0x2),  # 4-state walk budget without dQ
+                                 # budgets below one chunk of min(64, P) patterns: 64-state, generic paths
+                                 dict(hbm_budget_bytes=7799, n_states=61, precision=_abi.EPOCH_FP32),
+                                 dict(hbm_budget_bytes=7799, n_states=20),
+                                 dict(hbm_budget_bytes=1079, kernel_path=1)])
 def test_create_rejects_bad_config_before_touching_the_device(bad):
     lib = _abi.load()
     h = ctypes.c_void_p()

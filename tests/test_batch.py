@@ -64,3 +64,27 @@ def test_nucleotide_batch_unmerged_path():
     batch.close()
     for m in members:
         m.close()
+
+
+def test_batch_with_a_pattern_chunked_codon_member():
+    """A 64-state member under an HBM budget (pattern chunks) leaves the merged launches and is
+    evaluated on its own inside the batch; every member still matches the oracle."""
+    probs = W.make_batch(3, scale=0.05)
+    p0 = probs[0]
+    nm1 = p0.n_tips - 1
+    budget = (nm1 * (64 * 4 + 4) + nm1 * 64 * 4 + 2 * nm1 * 64 * 64 * 4 // 64) * 64  # chunks of 64 patterns
+    members = [from_problem(p0, "fp32", grad_branch=True, hbm_budget_bytes=budget)] + \
+              [from_problem(p, "fp32", grad_branch=True) for p in probs[1:]]
+    batch = EpochBatchEvaluator(members)
+    logL = batch.evaluate(grad_branch=True)
+    again = batch.evaluate(grad_branch=True)
+    assert np.array_equal(logL, again)
+    for i, p in enumerate(probs):
+        want = O.log_likelihood(p)
+        assert abs(logL[i] - want) / abs(want) <= 1e-5, (i, logL[i], want)
+        db, _ = batch.gradients(i)
+        ref_b, _ = O.gradient(p, wrt=("branch",))
+        assert np.linalg.norm(db - ref_b) / np.linalg.norm(ref_b) <= 1e-3
+    batch.close()
+    for m in members:
+        m.close()

@@ -238,3 +238,48 @@ def test_codon_hbm_budget_too_small_is_refused():
     prob = W.make_config(3, n_patterns=300)
     with pytest.raises(Exception, match="hbm_budget_bytes"):
         from_problem(prob, "fp32", grad_branch=True, hbm_budget_bytes=_codon_budget(prob, 64) - 1)
+
+
+def _generic_budget(prob, precision, patterns_per_chunk, grad=True):
+    """Budget that gives the generic path chunks of patterns_per_chunk patterns (a multiple of 64)."""
+    K = prob.n_states
+    kp = 4 if K <= 4 else (8 if K <= 8 else -(-K // 16) * 16)
+    row = len(prob.cat_rates) * kp * (8 if precision == "fp64" else 4)
+    return (prob.n_tips - 1) * (row * (2 if grad else 1) + 4) * patterns_per_chunk
+
+
+@pytest.mark.parametrize("K,C,kernel,precision", [(20, 2, "auto", "fp64"), (20, 2, "auto", "fp32"),
+                                                  (4, 4, "generic", "fp32"), (61, 1, "auto", "fp64")])
+def test_generic_hbm_budget_streams_pattern_chunks(K, C, kernel, precision):
+    """The generic path under a budget: chunks of 64 patterns (the last one ragged), partials
+    formed again chunk by chunk in the gradient call; logL, site logL and both gradients match
+    the oracle and the unbudgeted instance."""
+    rng = np.random.default_rng(6000 + K + C)
+    prob = W.random_problem(rng, 20, K, 300, n_categories=C, n_intervals=3, reversible=False, missing_frac=0.05)
+    budget = _generic_budget(prob, precision, 64)
+    kw = dict(grad_branch=True, grad_Q=True, kernel=kernel)
+    with from_problem(prob, precision, hbm_budget_bytes=budget, **kw) as lik:
+        logL, site = lik.log_likelihood(site=True)
+        db, dq = lik.gradient(branch=True, Q=True)
+        one = lik.evaluate(branch=True, Q=True, site=True)
+    with from_problem(prob, precision, **kw) as lik:
+        ref = lik.evaluate(branch=True, Q=True, site=True)
+    want = O.log_likelihood(prob)
+    ob, oq = O.gradient(prob)
+    assert abs(logL - want) <= TOL_LOGL[precision] * abs(want)
+    assert np.linalg.norm(db - ob) <= TOL_GRAD[precision] * np.linalg.norm(ob)
+    assert np.linalg.norm(dq - oq) <= TOL_GRAD[precision] * np.linalg.norm(oq)
+    # per-pattern values are those of the unbudgeted instance; only sums over chunks regroup
+    assert np.array_equal(site, ref[1]) and np.array_equal(one[1], ref[1])
+    assert abs(logL - ref[0]) <= 1e-13 * abs(want) and abs(one[0] - logL) <= 1e-13 * abs(want)
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    assert np.linalg.norm(db - ref[2]) <= tol * np.linalg.norm(ob)
+    assert np.linalg.norm(dq - ref[3]) <= tol * np.linalg.norm(oq)
+    assert np.array_equal(one[2], db) and np.array_equal(one[3], dq)
+
+
+def test_generic_hbm_budget_too_small_is_refused():
+    rng = np.random.default_rng(6100)
+    prob = W.random_problem(rng, 12, 20, 200)
+    with pytest.raises(Exception, match="hbm_budget_bytes"):
+        from_problem(prob, "fp64", grad_branch=True, hbm_budget_bytes=_generic_budget(prob, "fp64", 64) - 1)
