@@ -247,6 +247,9 @@ int epoch_get_timing(EpochInstance* inst, double* ms_out, int64_t* counts_out);
  *   EPOCH_OPT_LEVEL_MIN_TILES: 1..64 (default 8): fewest pattern tiles a
  *     wavefront of the 4-state pre-order level kernels walks; smaller values
  *     give narrow levels more wavefronts and more dlogL/dP partial sums.
+ *   EPOCH_OPT_TARGET_BLOCKS: 1..2^30 (default 1024): on the 64-state path,
+ *     the blocks each tree-level launch aims for (it sets how many 64-pattern
+ *     tiles a block walks, and so the number of dlogL/dP partial sums).
  *   EPOCH_OPT_SPLIT_BLOCKS: 0..2^30 (default 256): on the 64-state path, a
  *     pre-order tree level launched with at most this many blocks runs each
  *     child branch on its own wavefronts (same results, shorter per-wavefront
@@ -258,6 +261,7 @@ int epoch_get_timing(EpochInstance* inst, double* ms_out, int64_t* counts_out);
 #define EPOCH_OPT_WALK_TILES 4
 #define EPOCH_OPT_LEVEL_MIN_TILES 5
 #define EPOCH_OPT_SPLIT_BLOCKS 6
+#define EPOCH_OPT_TARGET_BLOCKS 7
 int epoch_set_option(EpochInstance* inst, int32_t key, int64_t value);
 
 /* ---- Batched evaluation (an addition to the paper: many independent

@@ -874,6 +874,10 @@ int epoch_set_option(EpochInstance* in, int32_t key, int64_t value) {
       in->nuc_rmin = (int)value;
       if (int rc = fastpath_init(in)) return rc;
       break;
+    case EPOCH_OPT_TARGET_BLOCKS:
+      if (value < 1 || value > (1 << 30)) return set_error(EPOCH_ERR_ARG, "EPOCH_OPT_TARGET_BLOCKS out of range");
+      in->codon_target_blocks = (int)value;
+      break;
     case EPOCH_OPT_SPLIT_BLOCKS:
       if (value < 0 || value > (1 << 30)) return set_error(EPOCH_ERR_ARG, "EPOCH_OPT_SPLIT_BLOCKS out of range");
       in->codon_split_blocks = (int)value;

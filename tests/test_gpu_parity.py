@@ -208,6 +208,18 @@ def test_codon_side_split_pre_order_matches_oracle(n_patterns):
         assert logL == out[0][0] and np.array_equal(db, out[0][1]) and np.array_equal(dq, out[0][2])
 
 
+@pytest.mark.parametrize("target_blocks", [64, 4096])
+def test_codon_target_blocks_option(target_blocks):
+    """Fewer or more blocks per 64-state level launch (more or fewer tiles per block) still
+    match the oracle."""
+    prob = W.make_config(3, n_patterns=2000)
+    logL, db, dq = _codon_eval(prob, {"target_blocks": target_blocks})
+    want = O.log_likelihood(prob)
+    ref_b, ref_q = O.gradient(prob)
+    assert rel(logL, want) <= TOL_LOGL["fp32"]
+    assert grad_rel(db, ref_b) <= TOL_GRAD["fp32"] and grad_rel(dq, ref_q) <= TOL_GRAD["fp32"]
+
+
 def test_codon_side_split_several_tiles_per_block():
     """5000 patterns put several 64-pattern tiles on each block of the wide levels; the
     side-split kernel on every level gives the bits of the four-wavefront kernel."""
