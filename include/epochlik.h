@@ -247,6 +247,10 @@ int epoch_get_timing(EpochInstance* inst, double* ms_out, int64_t* counts_out);
  *   EPOCH_OPT_LEVEL_MIN_TILES: 1..64 (default 8): fewest pattern tiles a
  *     wavefront of the 4-state pre-order level kernels walks; smaller values
  *     give narrow levels more wavefronts and more dlogL/dP partial sums.
+ *   EPOCH_OPT_CHAIN_SPLIT: 0..2^30 (default 16): on the matrix-core P stage
+ *     and dlogL/dQ chain, a branch whose ordered product has at least this many
+ *     segments is computed as two halves in parallel and combined (the same
+ *     quantities, rounded differently); 0 = never.
  *   EPOCH_OPT_TARGET_BLOCKS: 1..2^30 (default 1024): on the 64-state path,
  *     the blocks each tree-level launch aims for (it sets how many 64-pattern
  *     tiles a block walks, and so the number of dlogL/dP partial sums).
@@ -262,6 +266,7 @@ int epoch_get_timing(EpochInstance* inst, double* ms_out, int64_t* counts_out);
 #define EPOCH_OPT_LEVEL_MIN_TILES 5
 #define EPOCH_OPT_SPLIT_BLOCKS 6
 #define EPOCH_OPT_TARGET_BLOCKS 7
+#define EPOCH_OPT_CHAIN_SPLIT 8
 int epoch_set_option(EpochInstance* inst, int32_t key, int64_t value);
 
 /* ---- Batched evaluation (an addition to the paper: many independent

@@ -187,6 +187,7 @@ EPOCH_OPT_WALK_TILES = 4
 EPOCH_OPT_LEVEL_MIN_TILES = 5
 EPOCH_OPT_SPLIT_BLOCKS = 6
 EPOCH_OPT_TARGET_BLOCKS = 7
+EPOCH_OPT_CHAIN_SPLIT = 8
 
 
 def plan_walk(parent, height, recompute_tips: int = 2):

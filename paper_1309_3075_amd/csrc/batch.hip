@@ -162,6 +162,7 @@ int enqueue(EpochBatch* b, uint32_t what, const double* const* d_result_ptrs) {
     int rc = launch_pstage_mfma_multi(b->insts[g.members[0]], static_cast<const PStageDesc*>(b->pdescs.ptr) + g.desc_offset,
                                       (int)g.members.size(), g.max_items, b->stream);
     if (rc) return rc;
+    for (size_t q : g.members) b->insts[q]->pstage_split = false;  // whole chains: the dQ chains follow suit
   }
   for (size_t q : b->p_single) {
     int rc = launch_pstage(b->insts[q]);

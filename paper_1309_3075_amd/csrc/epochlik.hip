@@ -402,7 +402,7 @@ int epoch_destroy(EpochInstance* in) {
   for (DevBuf* b : {&in->eigT, &in->eig64, &in->check, &in->tips, &in->weights, &in->weightsT, &in->pi,
                     &in->cat, &in->tree_i, &in->tree_d, &in->Pm, &in->dPm, &in->partials, &in->scales,
                     &in->pre, &in->site, &in->blocksum, &in->result, &in->Gpart, &in->G, &in->dbranch,
-                    &in->qseg, &in->qscratch, &in->dQ, &in->seglist, &in->gslots, &in->codon_dev, &in->codon_aux,
+                    &in->qseg, &in->qscratch, &in->chain_items, &in->chain_scratch, &in->dQ, &in->seglist, &in->gslots, &in->codon_dev, &in->codon_aux,
                     &in->eigTT, &in->eig64T, &in->qtau, &in->nuc_nodes, &in->walk_ops,
                     &in->walk_tcol, &in->walk_dpart, &in->walk_dummy, &in->walk_slots})
     release(*b);
@@ -617,6 +617,44 @@ int set_epoch_eigensystems(EpochInstance* in, int32_t s, const double* V, const 
   return ret;
 }
 
+namespace {
+// Work items of the matrix-core chain kernels (P stage, dlogL/dQ chain): one per
+// node, longest segment chain first; and the same with every chain of at least
+// chain_split_min segments cut into a head [0, h) and a tail [h, m), h = m / 2,
+// whose halves run in parallel and are combined afterwards.
+int build_chain_items(EpochInstance* in, const std::vector<int32_t>& off) {  // off: the tree's segment offsets
+  const int n = in->n_nodes;
+  std::vector<int32_t> order(n);
+  for (int v = 0; v < n; ++v) order[v] = v;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t a, int32_t b) { return off[a + 1] - off[a] > off[b + 1] - off[b]; });
+  std::vector<int4> whole, split, info;
+  for (int v : order) {
+    const int m = off[v + 1] - off[v];
+    whole.push_back(make_int4(v, 0, m, 0));
+    if (in->chain_split_min > 0 && m >= std::max(2, in->chain_split_min)) {
+      const int slot = (int)info.size(), h = m / 2;
+      split.push_back(make_int4(v, 0, h, 1 | (slot << 2)));
+      split.push_back(make_int4(v, h, m, 2 | (slot << 2)));
+      info.push_back(make_int4(v, h, m, slot));
+    } else {
+      split.push_back(make_int4(v, 0, m, 0));
+    }
+  }
+  std::stable_sort(split.begin(), split.end(), [](const int4& a, const int4& b) { return a.z - a.y > b.z - b.y; });
+  in->n_chain_split_items = (int)split.size();
+  in->n_chain_splits = (int)info.size();
+  std::vector<int4> all(whole);
+  all.insert(all.end(), split.begin(), split.end());
+  all.insert(all.end(), info.begin(), info.end());
+  int rc = ensure(in->chain_items, all.size() * sizeof(int4));
+  if (!rc && !info.empty())
+    rc = ensure(in->chain_scratch, info.size() * in->C * 5 * (size_t)in->Kp * in->Kp * sizeof(double));
+  if (!rc) rc = upload(in, in->chain_items.ptr, all.data(), all.size() * sizeof(int4));
+  return rc;
+}
+}  // namespace
+
 int set_tree_epochs(EpochInstance* in, const int32_t* parent, const double* height, const double* branch_rate,
                     int32_t n_intervals, const double* boundaries, const int32_t* interval_process) {
   if (!in) return set_error(EPOCH_ERR_ARG, "NULL instance");
@@ -664,6 +702,7 @@ int set_tree_epochs(EpochInstance* in, const int32_t* parent, const double* heig
   in->d_seg_offset = bi + 3 * n + Nm1;
   in->d_seg_process = in->d_seg_offset + n + 1;
   in->d_chain_order = in->d_seg_process + nseg;
+  EPOCH_TRY(build_chain_items(in, plan.seg_offset));  // in->plan still holds the previous tree here
   double* bd = static_cast<double*>(in->tree_d.ptr);
   in->d_rate = bd;
   in->d_tau = bd + n;
@@ -874,6 +913,13 @@ int epoch_set_option(EpochInstance* in, int32_t key, int64_t value) {
       in->nuc_rmin = (int)value;
       if (int rc = fastpath_init(in)) return rc;
       break;
+    case EPOCH_OPT_CHAIN_SPLIT:
+      if (value < 0 || value > (1 << 30)) return set_error(EPOCH_ERR_ARG, "EPOCH_OPT_CHAIN_SPLIT out of range");
+      in->chain_split_min = (int)value;
+      if (in->have_tree) {
+        if (int rc = build_chain_items(in, in->plan.seg_offset)) return rc;
+      }
+      return EPOCH_OK;
     case EPOCH_OPT_TARGET_BLOCKS:
       if (value < 1 || value > (1 << 30)) return set_error(EPOCH_ERR_ARG, "EPOCH_OPT_TARGET_BLOCKS out of range");
       in->codon_target_blocks = (int)value;

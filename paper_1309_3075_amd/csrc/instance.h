@@ -51,7 +51,9 @@ struct PStageDesc {
   const void* li;
   const int32_t* seg_offset;
   const int32_t* seg_process;
-  const int32_t* chain_order;  // nodes by descending segment count (work item i takes node chain_order[i / C])
+  const int32_t* chain_order;  // nodes by descending segment count
+  const int4* items;           // work items (node, k0, k1, kind | slot << 2) of this launch, longest first
+  void* scratch;               // per split and category: X_A, dX_A, X_B, dX_B, X_B^T
   const double* seg_time;
   const double* seg_frac;
   const double* rate;
@@ -59,7 +61,7 @@ struct PStageDesc {
   void* Pout;
   void* dPout;
   void* Ubuf;   // or null: A_k V of every segment term, kept for the dlogL/dQ adjoint chain
-  int n_items;  // nodes x categories
+  int n_items;  // work items x categories
   int C;
   bool grad;
 };
@@ -150,6 +152,13 @@ struct EpochInstance {
   epochlik::DevBuf dbranch;    // double [n]
   epochlik::DevBuf qseg;       // double complex per segment [nseg][C][Kp][Kp][2]
   epochlik::DevBuf qscratch;   // T prefix products [nseg][C][Kp][Kp]
+  // matrix-core chains: work items (node, first segment, end segment, kind | slot << 2), longest first:
+  // [whole list: one per node][split list: long chains cut in two][per split: node, cut, m, slot]
+  epochlik::DevBuf chain_items;
+  epochlik::DevBuf chain_scratch;  // per split and category: X_A, dX_A, X_B, dX_B, X_B^T [Kp][Kp] (compute type)
+  int n_chain_split_items = 0, n_chain_splits = 0;
+  int chain_split_min = 16;        // chains of at least this many segments are cut in two (0: never)
+  bool pstage_split = false;       // the last P stage launched ran the split items (the dQ chain follows it)
   epochlik::DevBuf dQ;         // double [S][Kp][Kp]
   epochlik::DevBuf qtau;       // double [nseg][C] tau of each segment term of dlogL/dQ, then complex [nseg][C][Kp] e^{tau lambda}
   int q_chunks = 1;            // segment chunks per process of the dlogL/dQ sums

@@ -35,7 +35,9 @@ namespace epochlik {
 
 namespace {
 
-// One wavefront = one 16-row stripe of one (node, category) item of one problem.
+// One wavefront = one 16-row stripe of one (work item, category) of one
+// problem.  A work item is a node's whole chain, or the head or tail half of a
+// long one (written to scratch for pstage_combine_kernel).
 template <typename T, typename TO, bool GRAD, int NT>
 __device__ inline void pstage_stripe(const PStageDesc& pd, int gw, ColCoef<T>* coef) {
   using acc = typename Mfma<T>::acc;
@@ -44,6 +46,8 @@ __device__ inline void pstage_stripe(const PStageDesc& pd, int gw, ColCoef<T>* c
   const int item = gw / NT, stripe = gw - item * NT;
   if (item >= pd.n_items) return;  // whole wavefronts only: no barrier follows
   const int C = pd.C;
+  const int4 wi = pd.items[item / C];
+  const int k0 = wi.y, k1 = wi.z, kind = wi.w & 3, slot = wi.w >> 2;
   const T* __restrict__ eigV = static_cast<const T*>(pd.V);
   const T* __restrict__ eigVi = static_cast<const T*>(pd.Vi);
   const T* __restrict__ lre = static_cast<const T*>(pd.lr);
@@ -57,7 +61,7 @@ __device__ inline void pstage_stripe(const PStageDesc& pd, int gw, ColCoef<T>* c
   TO* __restrict__ Pout = static_cast<TO*>(pd.Pout);
   TO* __restrict__ dPout = static_cast<TO*>(pd.dPout);
   const int lane = threadIdx.x & 63;
-  const int v = pd.chain_order[item / C], c = item - (item / C) * C;
+  const int v = wi.x, c = item - (item / C) * C;
   const int g = lane >> 4, n = lane & 15;
   const int row = 16 * stripe + n;  // row of P this lane's column of X^T belongs to
   const int arow = Mfma<T>::a_row(n);
@@ -73,7 +77,6 @@ __device__ inline void pstage_stripe(const PStageDesc& pd, int gw, ColCoef<T>* c
     }
 
   const int seg0 = seg_offset[v];
-  const int m = seg_offset[v + 1] - seg0;
   const double rho = cat_rates[c];
   const double scale = rho * rate[v];
   // Column coefficients of segment k (double-buffered by k parity).  Those of
@@ -89,11 +92,11 @@ __device__ inline void pstage_stripe(const PStageDesc& pd, int gw, ColCoef<T>* c
     }
   };
   T av[2][4][NT], ai[2][4][NT];
-  if (m > 0) {
-    make_coef(0, coef);
-    stripe_load<T, NT>(eigV + (size_t)seg_process[seg0] * KK, 0, g, arow, av[0]);
+  if (k1 > k0) {
+    make_coef(k0, coef + 64 * (k0 & 1));
+    stripe_load<T, NT>(eigV + (size_t)seg_process[seg0 + k0] * KK, 0, g, arow, av[0]);
   }
-  for (int k = 0; k < m; ++k) {
+  for (int k = k0; k < k1; ++k) {
     const int s = seg_process[seg0 + k];
     const ColCoef<T>* ck = coef + 64 * (k & 1);
     wave_lds_sync();  // segment k's coefficients are in LDS
@@ -106,7 +109,7 @@ __device__ inline void pstage_stripe(const PStageDesc& pd, int gw, ColCoef<T>* c
 #pragma unroll
       for (int mt = 0; mt < NT; ++mt) y[b][mt] = acc{0, 0, 0, 0};
     stripe_gemm_from<T, NT, NB>(eigV + (size_t)s * KK, g, arow, av, xd, y);
-    if (k + 1 < m) {
+    if (k + 1 < k1) {
       make_coef(k + 1, coef + 64 * ((k + 1) & 1));
       stripe_load<T, NT>(eigV + (size_t)seg_process[seg0 + k + 1] * KK, 0, g, arow, av[0]);
     }
@@ -139,11 +142,92 @@ __device__ inline void pstage_stripe(const PStageDesc& pd, int gw, ColCoef<T>* c
     stripe_gemm_from<T, NT, NB>(eigVi + (size_t)s * KK, g, arow, ai, y, xd);
   }
 
+  if (kind == 0) {
+    const size_t base = ((size_t)v * C + c) * KK + (size_t)row * Kp + 4 * g;
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt) {
+      store4<T, TO>(Pout + base + 16 * mt, xd[0][mt]);
+      if (GRAD) store4<T, TO>(dPout + base + 16 * mt, xd[NB - 1][mt]);
+    }
+    return;
+  }
+  // half of a split chain: X and dX/dl of the head (kind 1) or tail (kind 2), and the tail's transpose
+  T* sc = static_cast<T*>(pd.scratch) + ((size_t)slot * C + c) * 5 * KK;
+  T* X = sc + (kind == 1 ? 0 : 2) * KK;
+#pragma unroll
+  for (int mt = 0; mt < NT; ++mt) {
+    store4<T, T>(X + (size_t)row * Kp + 4 * g + 16 * mt, xd[0][mt]);
+    if (GRAD) store4<T, T>(X + KK + (size_t)row * Kp + 4 * g + 16 * mt, xd[NB - 1][mt]);
+    if (kind == 2)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sc[4 * KK + (size_t)(16 * mt + 4 * g + q) * Kp + row] = xd[0][mt][q];
+  }
+}
+
+// A split chain's halves combined: P = X_A X_B and dP/dl = dX_A X_B + X_A dX_B,
+// and with dlogL/dQ the tail's stored products A_k V (formed from the tail's
+// own start) become X_A (A_k V).  One block of NT wavefronts (16-row stripes)
+// per (split, category); the block reads each A_k V whole before any stripe
+// overwrites its rows.
+template <typename T, typename TO, bool GRAD, int NT>
+__global__ __launch_bounds__(256) void pstage_combine_kernel(PStageDesc pd, const int4* __restrict__ splits) {
+  using acc = typename Mfma<T>::acc;
+  constexpr int Kp = 16 * NT;
+  constexpr int KK = Kp * Kp;
+  constexpr int NB = GRAD ? 2 : 1;
+  const int C = pd.C;
+  const int sidx = blockIdx.x / C, c = blockIdx.x - sidx * C;
+  const int4 sp = splits[sidx];  // node, cut, m, slot
+  const int v = sp.x;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int g = lane >> 4, n = lane & 15;
+  const int row = 16 * w + n;
+  const int arow = Mfma<T>::a_row(n);
+  const T* sc = static_cast<const T*>(pd.scratch) + ((size_t)sp.w * C + c) * 5 * KK;
+  acc a[NB][NT], o[NB][NT];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[b][mt][q] = sc[b * KK + (size_t)row * Kp + 16 * mt + 4 * g + q];
+      o[b][mt] = acc{0, 0, 0, 0};
+    }
+  stripe_gemm<T, NT, NB>(sc + 2 * KK, g, arow, a, o);  // X_A X_B (and dX_A X_B)
+  if (GRAD) {
+    acc xa[1][NT], d[1][NT];
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt) {
+      xa[0][mt] = a[0][mt];
+      d[0][mt] = o[NB - 1][mt];
+    }
+    stripe_gemm<T, NT, 1>(sc + 3 * KK, g, arow, xa, d);  // + X_A dX_B
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt) o[NB - 1][mt] = d[0][mt];
+  }
+  TO* Pout = static_cast<TO*>(pd.Pout);
+  TO* dPout = static_cast<TO*>(pd.dPout);
   const size_t base = ((size_t)v * C + c) * KK + (size_t)row * Kp + 4 * g;
 #pragma unroll
   for (int mt = 0; mt < NT; ++mt) {
-    store4<T, TO>(Pout + base + 16 * mt, xd[0][mt]);
-    if (GRAD) store4<T, TO>(dPout + base + 16 * mt, xd[NB - 1][mt]);
+    store4<T, TO>(Pout + base + 16 * mt, o[0][mt]);
+    if (GRAD) store4<T, TO>(dPout + base + 16 * mt, o[NB - 1][mt]);
+  }
+  if (pd.Ubuf) {
+    const int seg0 = pd.seg_offset[v];
+    acc xa[1][NT];
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt) xa[0][mt] = a[0][mt];
+    for (int k = sp.y; k < sp.z; ++k) {
+      T* U = static_cast<T*>(pd.Ubuf) + ((size_t)(seg0 + k) * C + c) * KK;
+      acc u[1][NT];
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt) u[0][mt] = acc{0, 0, 0, 0};
+      stripe_gemm<T, NT, 1>(U, g, arow, xa, u);
+      __syncthreads();  // every stripe has read this A_k V
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt) store4<T, T>(U + (size_t)row * Kp + 4 * g + 16 * mt, u[0][mt]);
+    }
   }
 }
 
@@ -166,13 +250,27 @@ __global__ __launch_bounds__(256) void pstage_mfma_multi_kernel(const PStageDesc
 
 template <typename T, typename TO, int NT>
 int pstage_mfma_launch(EpochInstance* in) {
-  const PStageDesc pd = pstage_descriptor(in);
+  const bool split = in->n_chain_splits > 0;
+  PStageDesc pd = pstage_descriptor(in);
+  if (split) {
+    pd.items = static_cast<const int4*>(in->chain_items.ptr) + in->n_nodes;
+    pd.n_items = in->n_chain_split_items * in->C;
+  }
   const long waves = (long)pd.n_items * NT;
   dim3 grid((unsigned)((waves + 3) / 4));
   if (pd.grad)
     hipLaunchKernelGGL((pstage_mfma_kernel<T, TO, true, NT>), grid, dim3(256), 0, in->stream, pd);
   else
     hipLaunchKernelGGL((pstage_mfma_kernel<T, TO, false, NT>), grid, dim3(256), 0, in->stream, pd);
+  if (split) {
+    const int4* splits = static_cast<const int4*>(in->chain_items.ptr) + in->n_nodes + in->n_chain_split_items;
+    dim3 cgrid((unsigned)(in->n_chain_splits * in->C));
+    if (pd.grad)
+      hipLaunchKernelGGL((pstage_combine_kernel<T, TO, true, NT>), cgrid, dim3(64 * NT), 0, in->stream, pd, splits);
+    else
+      hipLaunchKernelGGL((pstage_combine_kernel<T, TO, false, NT>), cgrid, dim3(64 * NT), 0, in->stream, pd, splits);
+  }
+  in->pstage_split = split;
   return hip_check(hipGetLastError(), "pstage_mfma launch");
 }
 
@@ -234,6 +332,8 @@ PStageDesc pstage_descriptor(const EpochInstance* in) {
   d.seg_offset = in->d_seg_offset;
   d.seg_process = in->d_seg_process;
   d.chain_order = in->d_chain_order;
+  d.items = static_cast<const int4*>(in->chain_items.ptr);  // whole chains; the single-instance launch may split
+  d.scratch = in->chain_scratch.ptr;
   d.seg_time = in->d_seg_time;
   d.seg_frac = in->d_seg_frac;
   d.rate = in->d_rate;

@@ -363,7 +363,8 @@ __global__ __launch_bounds__(256) void qgrad_chain_kernel(
     int C, int root, const T* __restrict__ eigV, const T* __restrict__ eigVi, const T* __restrict__ eigVT,
     const T* __restrict__ eigViT, const T* __restrict__ lre, const T* __restrict__ lim,
     const int32_t* __restrict__ seg_offset, const int32_t* __restrict__ seg_process,
-    const int32_t* __restrict__ chain_order, const double* __restrict__ seg_time, const double* __restrict__ rate,
+    const int4* __restrict__ items, const T* __restrict__ chain_scratch, const double* __restrict__ seg_time,
+    const double* __restrict__ rate,
     const double* __restrict__ cat_rates, const double* __restrict__ G, T* __restrict__ Ubuf,
     double* __restrict__ Yseg, double* __restrict__ qtau,
     const double* __restrict__ lr64, const double* __restrict__ li64, double* __restrict__ qexp) {
@@ -372,10 +373,13 @@ __global__ __launch_bounds__(256) void qgrad_chain_kernel(
   __shared__ T sU[Kp * LD];
   __shared__ T sW[Kp * LD];
   __shared__ T s_coef[NT][2 * 64][2];
-  const int v = chain_order[blockIdx.x / C], c = blockIdx.x - (blockIdx.x / C) * C;  // longest chains first
+  // work item: a node's whole chain, or the head or tail half of a long one, longest first
+  const int4 wi = items[blockIdx.x / C];
+  const int v = wi.x, c = blockIdx.x - (blockIdx.x / C) * C;
+  const int k0 = wi.y, k1 = wi.z, kind = wi.w & 3;
   if (v == root) return;
-  const int seg0 = seg_offset[v], m = seg_offset[v + 1] - seg0;
-  if (m == 0) return;  // uniform over the block
+  const int seg0 = seg_offset[v];
+  if (k1 == k0) return;  // uniform over the block
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int g = lane >> 4, n = lane & 15;
   const int row = 16 * w + n;
@@ -385,7 +389,7 @@ __global__ __launch_bounds__(256) void qgrad_chain_kernel(
 
   // tau and e^{tau lambda} of every segment term, for the divided differences of the sums;
   // the forward products A_k V were stored by the P stage
-  for (int k = 0; k < m; ++k) {
+  for (int k = k0; k < k1; ++k) {
     const int s = seg_process[seg0 + k];
     const double tau_d = scale * seg_time[seg0 + k];
     if (threadIdx.x == 0) qtau[(size_t)(seg0 + k) * C + c] = tau_d;
@@ -396,7 +400,8 @@ __global__ __launch_bounds__(256) void qgrad_chain_kernel(
     }
   }
 
-  // backward pass, R_{m-1} = G (rows of this stripe)
+  // backward pass from R = G (rows of this stripe); the head half of a split chain
+  // starts from G X_B^T, X_B being the product of the tail half's factors
   acc R[1][NT];
   {
     const double* Gr = G + ((size_t)v * C + c) * KK + (size_t)row * Kp + 4 * g;
@@ -404,12 +409,21 @@ __global__ __launch_bounds__(256) void qgrad_chain_kernel(
     for (int mt = 0; mt < NT; ++mt)
 #pragma unroll
       for (int q = 0; q < 4; ++q) R[0][mt][q] = T(Gr[16 * mt + q]);
+    if (kind == 1) {
+      const T* XBT = chain_scratch + ((size_t)(wi.w >> 2) * C + c) * 5 * KK + 4 * KK;
+      acc R1[1][NT];
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt) R1[0][mt] = acc{0, 0, 0, 0};
+      stripe_gemm<T, NT, 1>(XBT, g, arow, R, R1);
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt) R[0][mt] = R1[0][mt];
+    }
   }
   // Segment k - 1's column coefficients, U rows and first V^-T operands are
   // produced while the matrix cores run segment k (coefficients double-buffered
   // by k parity).
   auto make_coef = [&](int k) {
-    if (k > 0 && lane < Kp) {
+    if (k > k0 && lane < Kp) {
       const int s = seg_process[seg0 + k];
       const BlockCoef<T> bc = block_coef(lre + (size_t)s * Kp, lim + (size_t)s * Kp, lane, T(scale * seg_time[seg0 + k]));
       coef[64 * (k & 1) + lane][0] = bc.m_self;
@@ -424,10 +438,10 @@ __global__ __launch_bounds__(256) void qgrad_chain_kernel(
       for (int q = 0; q < 4; ++q) u[mt][q] = U[16 * mt + q];
   };
   T aw[2][4][NT], av[2][4][NT], u[NT][4], un[NT][4];
-  make_coef(m - 1);
-  load_u(m - 1, u);
-  stripe_load<T, NT>(eigViT + (size_t)seg_process[seg0 + m - 1] * KK, 0, g, arow, aw[0]);
-  for (int k = m - 1; k >= 0; --k) {
+  make_coef(k1 - 1);
+  load_u(k1 - 1, u);
+  stripe_load<T, NT>(eigViT + (size_t)seg_process[seg0 + k1 - 1] * KK, 0, g, arow, aw[0]);
+  for (int k = k1 - 1; k >= k0; --k) {
     const int s = seg_process[seg0 + k];
     const T* VT = eigVT + (size_t)s * KK;
     const T* ViT = eigViT + (size_t)s * KK;
@@ -436,7 +450,7 @@ __global__ __launch_bounds__(256) void qgrad_chain_kernel(
 #pragma unroll
     for (int mt = 0; mt < NT; ++mt) wk[0][mt] = acc{0, 0, 0, 0};
     stripe_gemm_from<T, NT, 1>(ViT, g, arow, aw, R, wk);
-    if (k > 0) {  // while those MFMAs run
+    if (k > k0) {  // while those MFMAs run
       stripe_load<T, NT>(VT, 0, g, arow, av[0]);
       stripe_load<T, NT>(eigViT + (size_t)seg_process[seg0 + k - 1] * KK, 0, g, arow, aw[0]);
       load_u(k - 1, un);
@@ -468,7 +482,7 @@ __global__ __launch_bounds__(256) void qgrad_chain_kernel(
 #pragma unroll
       for (int q = 0; q < 4; ++q) Y[(size_t)(16 * w + 4 * g + q) * Kp + 16 * nt + n] = (double)yv[nt][q];
     __syncthreads();  // also orders this wavefront's coefficient writes before the reads below
-    if (k > 0) {
+    if (k > k0) {
       // R <- R + (W (E_k - I)^T) V^T; the transposed rotation flips the partner sign
       const T(*ck)[2] = coef + 64 * (k & 1);
 #pragma unroll
@@ -646,9 +660,12 @@ int qgrad_mfma_launch(EpochInstance* in) {
   const T* baseT = static_cast<const T*>(sizeof(T) == 8 ? in->eig64T.ptr : in->eigTT.ptr);
   const T* lr = base + 2 * S * KK;
   double* qexp = static_cast<double*>(in->qtau.ptr) + in->plan.seg_process.size() * C;
-  hipLaunchKernelGGL((qgrad_chain_kernel<T, NT>), dim3(in->n_nodes * C), dim3(64 * NT), 0, in->stream, C,
+  // the work items of the P stage that formed A_k V: whole chains, or split ones
+  const int4* items4 = static_cast<const int4*>(in->chain_items.ptr) + (in->pstage_split ? in->n_nodes : 0);
+  const int n_work = in->pstage_split ? in->n_chain_split_items : in->n_nodes;
+  hipLaunchKernelGGL((qgrad_chain_kernel<T, NT>), dim3(n_work * C), dim3(64 * NT), 0, in->stream, C,
                      in->plan.root, base, base + S * KK, baseT, baseT + S * KK, lr, lr + S * Kp, in->d_seg_offset,
-                     in->d_seg_process, in->d_chain_order, in->d_seg_time, in->d_rate,
+                     in->d_seg_process, items4, static_cast<const T*>(in->chain_scratch.ptr), in->d_seg_time, in->d_rate,
                      static_cast<const double*>(in->cat.ptr),
                      static_cast<const double*>(in->G.ptr), static_cast<T*>(in->qscratch.ptr),
                      static_cast<double*>(in->qseg.ptr), static_cast<double*>(in->qtau.ptr),

@@ -256,6 +256,28 @@ def test_trait_C4_shape(precision, kernel):
     assert grad_rel(dq, ref_q) <= TOL_GRAD[precision], grad_rel(dq, ref_q)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("chain_split", [0, 2, 7])
+def test_split_epoch_chains(precision, chain_split):
+    """Epoch-product chains cut into two halves that run in parallel (every chain of at least
+    chain_split segments; 0 = none): P, dP/dl (through the branch gradient), the stored forward
+    products of the dlogL/dQ adjoint and its backward chain all match the oracle, and the
+    unsplit evaluation to rounding."""
+    prob = W.make_config(4, n_tips=160)
+    opts = {"chain_split": chain_split}
+    with from_problem(prob, precision, grad_branch=True, grad_Q=True, use_pi=False, options=opts) as lik:
+        logL, _, db, dq = lik.evaluate(branch=True, Q=True)
+        P = lik.transition_matrices()
+    want = O.log_likelihood(prob)
+    ref_b, ref_q = O.gradient(prob)
+    assert rel(logL, want) <= TOL_LOGL[precision], rel(logL, want)
+    assert grad_rel(db, ref_b) <= TOL_GRAD[precision], grad_rel(db, ref_b)
+    assert grad_rel(dq, ref_q) <= TOL_GRAD[precision], grad_rel(dq, ref_q)
+    ref_P = O.transition_matrices(prob)
+    ref_P[-1] = 0.0
+    np.testing.assert_allclose(P, ref_P, rtol=0, atol=TOL_P[precision] * max(1.0, prob.n_states / 8))
+
+
 def test_trait_C4_full_size():
     """The full 2000-taxon 40-state workload in the benchmarked configuration (FP32,
     automatic kernels): logL and every gradient against the oracle."""
