@@ -258,7 +258,7 @@ def main():
              "generic": {"post_order": "post_level_generic", "pre_order_dP": "pre_level_generic + grad_G_generic"}}
     Kp = 4 if prob.n_states <= 4 else (8 if prob.n_states <= 8 else (prob.n_states + 15) // 16 * 16)
     mfma_pstage = args.kernel == "auto" and Kp >= 16
-    kname = names[path].get(dom, "pstage_mfma" if mfma_pstage else "pstage_generic")
+    kname = names[path].get(dom, "pstage_mfma (+ split-chain combine)" if mfma_pstage else "pstage_generic")
     if path == "codon" or dom == "transition_matrices":
         achieved = aflops[dom] / (dom_ms * 1e-3) / 1e12
         peak = FP64_PEAK_TFLOPS if (args.precision == "fp64" or

@@ -629,6 +629,7 @@ int build_chain_items(EpochInstance* in, const std::vector<int32_t>& off) {  // 
   std::stable_sort(order.begin(), order.end(),
                    [&](int32_t a, int32_t b) { return off[a + 1] - off[a] > off[b + 1] - off[b]; });
   std::vector<int4> whole, split, info;
+  int max_tail = 0;
   for (int v : order) {
     const int m = off[v + 1] - off[v];
     whole.push_back(make_int4(v, 0, m, 0));
@@ -637,6 +638,7 @@ int build_chain_items(EpochInstance* in, const std::vector<int32_t>& off) {  // 
       split.push_back(make_int4(v, 0, h, 1 | (slot << 2)));
       split.push_back(make_int4(v, h, m, 2 | (slot << 2)));
       info.push_back(make_int4(v, h, m, slot));
+      max_tail = std::max(max_tail, m - h);
     } else {
       split.push_back(make_int4(v, 0, m, 0));
     }
@@ -644,6 +646,7 @@ int build_chain_items(EpochInstance* in, const std::vector<int32_t>& off) {  // 
   std::stable_sort(split.begin(), split.end(), [](const int4& a, const int4& b) { return a.z - a.y > b.z - b.y; });
   in->n_chain_split_items = (int)split.size();
   in->n_chain_splits = (int)info.size();
+  in->chain_max_tail = max_tail;
   std::vector<int4> all(whole);
   all.insert(all.end(), split.begin(), split.end());
   all.insert(all.end(), info.begin(), info.end());
@@ -665,25 +668,15 @@ int set_tree_epochs(EpochInstance* in, const int32_t* parent, const double* heig
   if (plan_tree(in->N, parent, height, branch_rate, n_intervals, boundaries, interval_process, in->S, plan, err))
     return set_error(EPOCH_ERR_ARG, "set_tree_epochs: %s", err.c_str());
   const size_t n = in->n_nodes, nseg = plan.seg_process.size(), Nm1 = in->N - 1;
-  // int32 block: parent, left, right [n], level_nodes [N-1], seg_offset [n+1], seg_process [nseg],
-  // chain_order [n] (nodes by descending segment count, so that the matrix-core chain kernels
-  // start the longest products first)
+  // int32 block: parent, left, right [n], level_nodes [N-1], seg_offset [n+1], seg_process [nseg]
   std::vector<int32_t> hi;
-  hi.reserve(3 * n + Nm1 + n + 1 + nseg + n);
+  hi.reserve(3 * n + Nm1 + n + 1 + nseg);
   hi.insert(hi.end(), plan.parent.begin(), plan.parent.end());
   hi.insert(hi.end(), plan.left.begin(), plan.left.end());
   hi.insert(hi.end(), plan.right.begin(), plan.right.end());
   hi.insert(hi.end(), plan.level_nodes.begin(), plan.level_nodes.end());
   hi.insert(hi.end(), plan.seg_offset.begin(), plan.seg_offset.end());
   hi.insert(hi.end(), plan.seg_process.begin(), plan.seg_process.end());
-  {
-    std::vector<int32_t> order(n);
-    for (size_t v = 0; v < n; ++v) order[v] = (int32_t)v;
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-      return plan.seg_offset[a + 1] - plan.seg_offset[a] > plan.seg_offset[b + 1] - plan.seg_offset[b];
-    });
-    hi.insert(hi.end(), order.begin(), order.end());
-  }
   std::vector<double> hd;
   hd.reserve(2 * n + 2 * nseg);
   hd.insert(hd.end(), plan.rate.begin(), plan.rate.end());
@@ -701,7 +694,6 @@ int set_tree_epochs(EpochInstance* in, const int32_t* parent, const double* heig
   in->d_level_nodes = bi + 3 * n;
   in->d_seg_offset = bi + 3 * n + Nm1;
   in->d_seg_process = in->d_seg_offset + n + 1;
-  in->d_chain_order = in->d_seg_process + nseg;
   EPOCH_TRY(build_chain_items(in, plan.seg_offset));  // in->plan still holds the previous tree here
   double* bd = static_cast<double*>(in->tree_d.ptr);
   in->d_rate = bd;

@@ -51,7 +51,6 @@ struct PStageDesc {
   const void* li;
   const int32_t* seg_offset;
   const int32_t* seg_process;
-  const int32_t* chain_order;  // nodes by descending segment count
   const int4* items;           // work items (node, k0, k1, kind | slot << 2) of this launch, longest first
   void* scratch;               // per split and category: X_A, dX_A, X_B, dX_B, X_B^T
   const double* seg_time;
@@ -156,7 +155,7 @@ struct EpochInstance {
   // [whole list: one per node][split list: long chains cut in two][per split: node, cut, m, slot]
   epochlik::DevBuf chain_items;
   epochlik::DevBuf chain_scratch;  // per split and category: X_A, dX_A, X_B, dX_B, X_B^T [Kp][Kp] (compute type)
-  int n_chain_split_items = 0, n_chain_splits = 0;
+  int n_chain_split_items = 0, n_chain_splits = 0, chain_max_tail = 0;
   int chain_split_min = 16;        // chains of at least this many segments are cut in two (0: never)
   bool pstage_split = false;       // the last P stage launched ran the split items (the dQ chain follows it)
   epochlik::DevBuf dQ;         // double [S][Kp][Kp]
@@ -187,7 +186,7 @@ struct EpochInstance {
 
   // device pointers into tree_i / tree_d
   int32_t *d_parent = nullptr, *d_left = nullptr, *d_right = nullptr, *d_level_nodes = nullptr,
-          *d_seg_offset = nullptr, *d_seg_process = nullptr, *d_chain_order = nullptr;
+          *d_seg_offset = nullptr, *d_seg_process = nullptr;
   double *d_rate = nullptr, *d_tau = nullptr, *d_seg_time = nullptr, *d_seg_frac = nullptr;
 };
 

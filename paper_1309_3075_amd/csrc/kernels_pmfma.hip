@@ -164,11 +164,8 @@ __device__ inline void pstage_stripe(const PStageDesc& pd, int gw, ColCoef<T>* c
   }
 }
 
-// A split chain's halves combined: P = X_A X_B and dP/dl = dX_A X_B + X_A dX_B,
-// and with dlogL/dQ the tail's stored products A_k V (formed from the tail's
-// own start) become X_A (A_k V).  One block of NT wavefronts (16-row stripes)
-// per (split, category); the block reads each A_k V whole before any stripe
-// overwrites its rows.
+// A split chain's halves combined: P = X_A X_B and dP/dl = dX_A X_B + X_A dX_B.
+// One block of NT wavefronts (16-row stripes) per (split, category).
 template <typename T, typename TO, bool GRAD, int NT>
 __global__ __launch_bounds__(256) void pstage_combine_kernel(PStageDesc pd, const int4* __restrict__ splits) {
   using acc = typename Mfma<T>::acc;
@@ -213,22 +210,39 @@ __global__ __launch_bounds__(256) void pstage_combine_kernel(PStageDesc pd, cons
     store4<T, TO>(Pout + base + 16 * mt, o[0][mt]);
     if (GRAD) store4<T, TO>(dPout + base + 16 * mt, o[NB - 1][mt]);
   }
-  if (pd.Ubuf) {
-    const int seg0 = pd.seg_offset[v];
-    acc xa[1][NT];
+}
+
+// With dlogL/dQ, the tail's stored products A_k V (formed from the tail's own
+// start) become X_A (A_k V).  One block of NT wavefronts per (split, category,
+// tail segment); the block reads its A_k V whole before any stripe overwrites
+// its rows.
+template <typename T, int NT>
+__global__ __launch_bounds__(256) void pstage_tail_fix_kernel(PStageDesc pd, const int4* __restrict__ splits) {
+  using acc = typename Mfma<T>::acc;
+  constexpr int Kp = 16 * NT;
+  constexpr int KK = Kp * Kp;
+  const int C = pd.C;
+  const int sidx = blockIdx.x / C, c = blockIdx.x - sidx * C;
+  const int4 sp = splits[sidx];  // node, cut, m, slot
+  const int k = sp.y + blockIdx.y;
+  if (k >= sp.z) return;  // uniform: this split's tail is shorter
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int g = lane >> 4, n = lane & 15;
+  const int row = 16 * w + n;
+  const int arow = Mfma<T>::a_row(n);
+  const T* XA = static_cast<const T*>(pd.scratch) + ((size_t)sp.w * C + c) * 5 * KK;
+  acc xa[1][NT], u[1][NT];
 #pragma unroll
-    for (int mt = 0; mt < NT; ++mt) xa[0][mt] = a[0][mt];
-    for (int k = sp.y; k < sp.z; ++k) {
-      T* U = static_cast<T*>(pd.Ubuf) + ((size_t)(seg0 + k) * C + c) * KK;
-      acc u[1][NT];
+  for (int mt = 0; mt < NT; ++mt) {
 #pragma unroll
-      for (int mt = 0; mt < NT; ++mt) u[0][mt] = acc{0, 0, 0, 0};
-      stripe_gemm<T, NT, 1>(U, g, arow, xa, u);
-      __syncthreads();  // every stripe has read this A_k V
-#pragma unroll
-      for (int mt = 0; mt < NT; ++mt) store4<T, T>(U + (size_t)row * Kp + 4 * g + 16 * mt, u[0][mt]);
-    }
+    for (int q = 0; q < 4; ++q) xa[0][mt][q] = XA[(size_t)row * Kp + 16 * mt + 4 * g + q];
+    u[0][mt] = acc{0, 0, 0, 0};
   }
+  T* U = static_cast<T*>(pd.Ubuf) + ((size_t)(pd.seg_offset[sp.x] + k) * C + c) * KK;
+  stripe_gemm<T, NT, 1>(U, g, arow, xa, u);
+  __syncthreads();  // every stripe has read this A_k V
+#pragma unroll
+  for (int mt = 0; mt < NT; ++mt) store4<T, T>(U + (size_t)row * Kp + 4 * g + 16 * mt, u[0][mt]);
 }
 
 // One problem (descriptor passed by value).
@@ -269,6 +283,9 @@ int pstage_mfma_launch(EpochInstance* in) {
       hipLaunchKernelGGL((pstage_combine_kernel<T, TO, true, NT>), cgrid, dim3(64 * NT), 0, in->stream, pd, splits);
     else
       hipLaunchKernelGGL((pstage_combine_kernel<T, TO, false, NT>), cgrid, dim3(64 * NT), 0, in->stream, pd, splits);
+    if (pd.Ubuf)
+      hipLaunchKernelGGL((pstage_tail_fix_kernel<T, NT>), dim3(cgrid.x, (unsigned)in->chain_max_tail), dim3(64 * NT),
+                         0, in->stream, pd, splits);
   }
   in->pstage_split = split;
   return hip_check(hipGetLastError(), "pstage_mfma launch");
@@ -331,7 +348,6 @@ PStageDesc pstage_descriptor(const EpochInstance* in) {
   d.li = base + (2 * S * KK + S * in->Kp) * es;
   d.seg_offset = in->d_seg_offset;
   d.seg_process = in->d_seg_process;
-  d.chain_order = in->d_chain_order;
   d.items = static_cast<const int4*>(in->chain_items.ptr);  // whole chains; the single-instance launch may split
   d.scratch = in->chain_scratch.ptr;
   d.seg_time = in->d_seg_time;
