@@ -620,8 +620,9 @@ int set_epoch_eigensystems(EpochInstance* in, int32_t s, const double* V, const 
 namespace {
 // Work items of the matrix-core chain kernels (P stage, dlogL/dQ chain): one per
 // node, longest segment chain first; and the same with every chain of at least
-// chain_split_min segments cut into a head [0, h) and a tail [h, m), h = m / 2,
-// whose halves run in parallel and are combined afterwards.
+// chain_split_min segments cut into J parts of about max(4, chain_split_min / 2)
+// segments (at most kChainMaxParts), which run in parallel and are combined
+// afterwards.
 int build_chain_items(EpochInstance* in, const std::vector<int32_t>& off) {  // off: the tree's segment offsets
   const int n = in->n_nodes;
   std::vector<int32_t> order(n);
@@ -630,15 +631,18 @@ int build_chain_items(EpochInstance* in, const std::vector<int32_t>& off) {  // 
                    [&](int32_t a, int32_t b) { return off[a + 1] - off[a] > off[b + 1] - off[b]; });
   std::vector<int4> whole, split, info;
   int max_tail = 0;
+  const int part_len = std::max(4, in->chain_split_min / 2);
   for (int v : order) {
     const int m = off[v + 1] - off[v];
     whole.push_back(make_int4(v, 0, m, 0));
-    if (in->chain_split_min > 0 && m >= std::max(2, in->chain_split_min)) {
-      const int slot = (int)info.size(), h = m / 2;
-      split.push_back(make_int4(v, 0, h, 1 | (slot << 2)));
-      split.push_back(make_int4(v, h, m, 2 | (slot << 2)));
-      info.push_back(make_int4(v, h, m, slot));
-      max_tail = std::max(max_tail, m - h);
+    const int J = std::min(kChainMaxParts, (m + part_len - 1) / part_len);
+    if (in->chain_split_min > 0 && m >= in->chain_split_min && J >= 2) {
+      // J parts [j m / J, (j + 1) m / J); info word: kind 1 | part << 2 | parts << 5 | slot << 9
+      const int slot = (int)info.size();
+      for (int p = 0; p < J; ++p)
+        split.push_back(make_int4(v, p * m / J, (p + 1) * m / J, 1 | (p << 2) | (J << 5) | (slot << 9)));
+      info.push_back(make_int4(v, m, J, slot));
+      max_tail = std::max(max_tail, m - m / J);
     } else {
       split.push_back(make_int4(v, 0, m, 0));
     }
@@ -652,7 +656,8 @@ int build_chain_items(EpochInstance* in, const std::vector<int32_t>& off) {  // 
   all.insert(all.end(), info.begin(), info.end());
   int rc = ensure(in->chain_items, all.size() * sizeof(int4));
   if (!rc && !info.empty())
-    rc = ensure(in->chain_scratch, info.size() * in->C * 5 * (size_t)in->Kp * in->Kp * sizeof(double));
+    rc = ensure(in->chain_scratch,
+                info.size() * in->C * kChainMaxParts * 5 * (size_t)in->Kp * in->Kp * sizeof(double));
   if (!rc) rc = upload(in, in->chain_items.ptr, all.data(), all.size() * sizeof(int4));
   return rc;
 }

@@ -44,6 +44,8 @@ struct CodonProblem {
 };
 
 // Device pointers of one problem's P stage (one instance, or one member of a batch).
+constexpr int kChainMaxParts = 8;  // parts a long epoch-product chain is cut into, at most
+
 struct PStageDesc {
   const void* V;
   const void* Vi;
@@ -52,7 +54,7 @@ struct PStageDesc {
   const int32_t* seg_offset;
   const int32_t* seg_process;
   const int4* items;           // work items (node, k0, k1, kind | slot << 2) of this launch, longest first
-  void* scratch;               // per split and category: X_A, dX_A, X_B, dX_B, X_B^T
+  void* scratch;               // per split, category and part: X_j, dX_j, prefix, suffix, suffix^T
   const double* seg_time;
   const double* seg_frac;
   const double* rate;
@@ -151,10 +153,13 @@ struct EpochInstance {
   epochlik::DevBuf dbranch;    // double [n]
   epochlik::DevBuf qseg;       // double complex per segment [nseg][C][Kp][Kp][2]
   epochlik::DevBuf qscratch;   // T prefix products [nseg][C][Kp][Kp]
-  // matrix-core chains: work items (node, first segment, end segment, kind | slot << 2), longest first:
-  // [whole list: one per node][split list: long chains cut in two][per split: node, cut, m, slot]
+  // matrix-core chains: work items (node, first segment, end segment, info), longest first:
+  // [whole list: one per node][split list: long chains cut into parts][per split: node, m, parts, slot];
+  // info = kind (0 whole, 1 part) | part << 2 | parts << 5 | slot << 9
   epochlik::DevBuf chain_items;
-  epochlik::DevBuf chain_scratch;  // per split and category: X_A, dX_A, X_B, dX_B, X_B^T [Kp][Kp] (compute type)
+  // per split, category and part: X_j, dX_j, prefix X_0..X_{j-1}, suffix X_{j+1}..X_{J-1} and its
+  // transpose [Kp][Kp] (compute type)
+  epochlik::DevBuf chain_scratch;
   int n_chain_split_items = 0, n_chain_splits = 0, chain_max_tail = 0;
   int chain_split_min = 16;        // chains of at least this many segments are cut in two (0: never)
   bool pstage_split = false;       // the last P stage launched ran the split items (the dQ chain follows it)

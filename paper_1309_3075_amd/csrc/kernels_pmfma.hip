@@ -35,6 +35,13 @@ namespace epochlik {
 
 namespace {
 
+// Matrix `which` (0: X_j, 1: dX_j, 2: prefix, 3: suffix, 4: suffix transposed)
+// of part j of split `slot`, category c, in the chain scratch.
+template <typename T, int KK>
+__device__ inline T* chain_mat(void* scratch, int slot, int C, int c, int part, int which) {
+  return static_cast<T*>(scratch) + ((((size_t)slot * C + c) * kChainMaxParts + part) * 5 + which) * KK;
+}
+
 // One wavefront = one 16-row stripe of one (work item, category) of one
 // problem.  A work item is a node's whole chain, or the head or tail half of a
 // long one (written to scratch for pstage_combine_kernel).
@@ -47,7 +54,7 @@ __device__ inline void pstage_stripe(const PStageDesc& pd, int gw, ColCoef<T>* c
   if (item >= pd.n_items) return;  // whole wavefronts only: no barrier follows
   const int C = pd.C;
   const int4 wi = pd.items[item / C];
-  const int k0 = wi.y, k1 = wi.z, kind = wi.w & 3, slot = wi.w >> 2;
+  const int k0 = wi.y, k1 = wi.z, kind = wi.w & 3, part = (wi.w >> 2) & 7, slot = wi.w >> 9;
   const T* __restrict__ eigV = static_cast<const T*>(pd.V);
   const T* __restrict__ eigVi = static_cast<const T*>(pd.Vi);
   const T* __restrict__ lre = static_cast<const T*>(pd.lr);
@@ -151,21 +158,21 @@ __device__ inline void pstage_stripe(const PStageDesc& pd, int gw, ColCoef<T>* c
     }
     return;
   }
-  // half of a split chain: X and dX/dl of the head (kind 1) or tail (kind 2), and the tail's transpose
-  T* sc = static_cast<T*>(pd.scratch) + ((size_t)slot * C + c) * 5 * KK;
-  T* X = sc + (kind == 1 ? 0 : 2) * KK;
+  // one part of a split chain: its product X_j and dX_j/dl
+  T* X = chain_mat<T, KK>(pd.scratch, slot, C, c, part, 0);
 #pragma unroll
   for (int mt = 0; mt < NT; ++mt) {
     store4<T, T>(X + (size_t)row * Kp + 4 * g + 16 * mt, xd[0][mt]);
     if (GRAD) store4<T, T>(X + KK + (size_t)row * Kp + 4 * g + 16 * mt, xd[NB - 1][mt]);
-    if (kind == 2)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) sc[4 * KK + (size_t)(16 * mt + 4 * g + q) * Kp + row] = xd[0][mt][q];
   }
 }
 
-// A split chain's halves combined: P = X_A X_B and dP/dl = dX_A X_B + X_A dX_B.
-// One block of NT wavefronts (16-row stripes) per (split, category).
+// A split chain's parts combined, in order: (X, D) <- (X X_j, D X_j + X dX_j)
+// from (X_0, dX_0) gives P and dP/dl (the product rule over the parts).  The
+// prefix X_0 .. X_{j-1} of each part j >= 1 is kept for the forward products of
+// the dlogL/dQ adjoint, and with it the suffixes X_{j+1} .. X_{J-1} (and their
+// transposes) that start the parts' backward chains.  One block of NT
+// wavefronts (16-row stripes) per (split, category).
 template <typename T, typename TO, bool GRAD, int NT>
 __global__ __launch_bounds__(256) void pstage_combine_kernel(PStageDesc pd, const int4* __restrict__ splits) {
   using acc = typename Mfma<T>::acc;
@@ -174,48 +181,87 @@ __global__ __launch_bounds__(256) void pstage_combine_kernel(PStageDesc pd, cons
   constexpr int NB = GRAD ? 2 : 1;
   const int C = pd.C;
   const int sidx = blockIdx.x / C, c = blockIdx.x - sidx * C;
-  const int4 sp = splits[sidx];  // node, cut, m, slot
-  const int v = sp.x;
+  const int4 sp = splits[sidx];  // node, m, parts, slot
+  const int v = sp.x, J = sp.z, slot = sp.w;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int g = lane >> 4, n = lane & 15;
   const int row = 16 * w + n;
   const int arow = Mfma<T>::a_row(n);
-  const T* sc = static_cast<const T*>(pd.scratch) + ((size_t)sp.w * C + c) * 5 * KK;
-  acc a[NB][NT], o[NB][NT];
+  const size_t rbase = (size_t)row * Kp + 4 * g;
+  auto load_rows = [&](const T* M, acc (&x)[NT]) {
 #pragma unroll
-  for (int b = 0; b < NB; ++b)
+    for (int mt = 0; mt < NT; ++mt)
 #pragma unroll
-    for (int mt = 0; mt < NT; ++mt) {
+      for (int q = 0; q < 4; ++q) x[mt][q] = M[rbase + 16 * mt + q];
+  };
+  acc x[NB][NT];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) a[b][mt][q] = sc[b * KK + (size_t)row * Kp + 16 * mt + 4 * g + q];
-      o[b][mt] = acc{0, 0, 0, 0};
+  for (int b = 0; b < NB; ++b) load_rows(chain_mat<T, KK>(pd.scratch, slot, C, c, 0, b), x[b]);
+  for (int j = 1; j < J; ++j) {
+    if (pd.Ubuf) {
+      T* pre = chain_mat<T, KK>(pd.scratch, slot, C, c, j, 2);
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt) store4<T, T>(pre + rbase + 16 * mt, x[0][mt]);
     }
-  stripe_gemm<T, NT, NB>(sc + 2 * KK, g, arow, a, o);  // X_A X_B (and dX_A X_B)
-  if (GRAD) {
-    acc xa[1][NT], d[1][NT];
+    acc o[NB][NT];
 #pragma unroll
-    for (int mt = 0; mt < NT; ++mt) {
-      xa[0][mt] = a[0][mt];
-      d[0][mt] = o[NB - 1][mt];
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt) o[b][mt] = acc{0, 0, 0, 0};
+    stripe_gemm<T, NT, NB>(chain_mat<T, KK>(pd.scratch, slot, C, c, j, 0), g, arow, x, o);  // X X_j (and D X_j)
+    if (GRAD) {
+      acc xa[1][NT], d[1][NT];
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt) {
+        xa[0][mt] = x[0][mt];
+        d[0][mt] = o[NB - 1][mt];
+      }
+      stripe_gemm<T, NT, 1>(chain_mat<T, KK>(pd.scratch, slot, C, c, j, 1), g, arow, xa, d);  // + X dX_j
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt) o[NB - 1][mt] = d[0][mt];
     }
-    stripe_gemm<T, NT, 1>(sc + 3 * KK, g, arow, xa, d);  // + X_A dX_B
 #pragma unroll
-    for (int mt = 0; mt < NT; ++mt) o[NB - 1][mt] = d[0][mt];
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt) x[b][mt] = o[b][mt];
   }
   TO* Pout = static_cast<TO*>(pd.Pout);
   TO* dPout = static_cast<TO*>(pd.dPout);
-  const size_t base = ((size_t)v * C + c) * KK + (size_t)row * Kp + 4 * g;
+  const size_t base = ((size_t)v * C + c) * KK + rbase;
 #pragma unroll
   for (int mt = 0; mt < NT; ++mt) {
-    store4<T, TO>(Pout + base + 16 * mt, o[0][mt]);
-    if (GRAD) store4<T, TO>(dPout + base + 16 * mt, o[NB - 1][mt]);
+    store4<T, TO>(Pout + base + 16 * mt, x[0][mt]);
+    if (GRAD) store4<T, TO>(dPout + base + 16 * mt, x[NB - 1][mt]);
+  }
+  if (!pd.Ubuf) return;  // uniform
+  // suffixes, last part first: S_{J-2} = X_{J-1}, S_j = X_{j+1} S_{j+1}
+  for (int j = J - 2; j >= 0; --j) {
+    acc sfx[1][NT];
+    if (j == J - 2) {
+      load_rows(chain_mat<T, KK>(pd.scratch, slot, C, c, J - 1, 0), sfx[0]);
+    } else {
+      acc xr[1][NT];
+      load_rows(chain_mat<T, KK>(pd.scratch, slot, C, c, j + 1, 0), xr[0]);
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt) sfx[0][mt] = acc{0, 0, 0, 0};
+      stripe_gemm<T, NT, 1>(chain_mat<T, KK>(pd.scratch, slot, C, c, j + 1, 3), g, arow, xr, sfx);
+    }
+    T* S = chain_mat<T, KK>(pd.scratch, slot, C, c, j, 3);
+    T* ST = chain_mat<T, KK>(pd.scratch, slot, C, c, j, 4);
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt) {
+      store4<T, T>(S + rbase + 16 * mt, sfx[0][mt]);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) ST[(size_t)(16 * mt + 4 * g + q) * Kp + row] = sfx[0][mt][q];
+    }
+    __syncthreads();  // S_j whole before the next suffix reads it
   }
 }
 
-// With dlogL/dQ, the tail's stored products A_k V (formed from the tail's own
-// start) become X_A (A_k V).  One block of NT wavefronts per (split, category,
-// tail segment); the block reads its A_k V whole before any stripe overwrites
-// its rows.
+// With dlogL/dQ, the stored products A_k V of parts j >= 1 (formed from the
+// part's own start) become (X_0 .. X_{j-1}) (A_k V).  One block of NT
+// wavefronts per (split, category, segment past part 0); the block reads its
+// A_k V whole before any stripe overwrites its rows.
 template <typename T, int NT>
 __global__ __launch_bounds__(256) void pstage_tail_fix_kernel(PStageDesc pd, const int4* __restrict__ splits) {
   using acc = typename Mfma<T>::acc;
@@ -223,14 +269,17 @@ __global__ __launch_bounds__(256) void pstage_tail_fix_kernel(PStageDesc pd, con
   constexpr int KK = Kp * Kp;
   const int C = pd.C;
   const int sidx = blockIdx.x / C, c = blockIdx.x - sidx * C;
-  const int4 sp = splits[sidx];  // node, cut, m, slot
-  const int k = sp.y + blockIdx.y;
-  if (k >= sp.z) return;  // uniform: this split's tail is shorter
+  const int4 sp = splits[sidx];  // node, m, parts, slot
+  const int m = sp.y, J = sp.z;
+  const int k = m / J + blockIdx.y;
+  if (k >= m) return;  // uniform: this chain is shorter
+  int part = 1;
+  while (part + 1 < J && (part + 1) * m / J <= k) ++part;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int g = lane >> 4, n = lane & 15;
   const int row = 16 * w + n;
   const int arow = Mfma<T>::a_row(n);
-  const T* XA = static_cast<const T*>(pd.scratch) + ((size_t)sp.w * C + c) * 5 * KK;
+  const T* XA = chain_mat<T, KK>(pd.scratch, sp.w, C, c, part, 2);  // the prefix of this part
   acc xa[1][NT], u[1][NT];
 #pragma unroll
   for (int mt = 0; mt < NT; ++mt) {

@@ -376,7 +376,7 @@ __global__ __launch_bounds__(256) void qgrad_chain_kernel(
   // work item: a node's whole chain, or the head or tail half of a long one, longest first
   const int4 wi = items[blockIdx.x / C];
   const int v = wi.x, c = blockIdx.x - (blockIdx.x / C) * C;
-  const int k0 = wi.y, k1 = wi.z, kind = wi.w & 3;
+  const int k0 = wi.y, k1 = wi.z, kind = wi.w & 3, part = (wi.w >> 2) & 7, parts = (wi.w >> 5) & 15;
   if (v == root) return;
   const int seg0 = seg_offset[v];
   if (k1 == k0) return;  // uniform over the block
@@ -400,8 +400,8 @@ __global__ __launch_bounds__(256) void qgrad_chain_kernel(
     }
   }
 
-  // backward pass from R = G (rows of this stripe); the head half of a split chain
-  // starts from G X_B^T, X_B being the product of the tail half's factors
+  // backward pass from R = G (rows of this stripe); part j < J - 1 of a split chain
+  // starts from G S_j^T, S_j = X_{j+1} .. X_{J-1} being the product of the later parts' factors
   acc R[1][NT];
   {
     const double* Gr = G + ((size_t)v * C + c) * KK + (size_t)row * Kp + 4 * g;
@@ -409,8 +409,8 @@ __global__ __launch_bounds__(256) void qgrad_chain_kernel(
     for (int mt = 0; mt < NT; ++mt)
 #pragma unroll
       for (int q = 0; q < 4; ++q) R[0][mt][q] = T(Gr[16 * mt + q]);
-    if (kind == 1) {
-      const T* XBT = chain_scratch + ((size_t)(wi.w >> 2) * C + c) * 5 * KK + 4 * KK;
+    if (kind == 1 && part < parts - 1) {
+      const T* XBT = chain_scratch + ((((size_t)(wi.w >> 9) * C + c) * kChainMaxParts + part) * 5 + 4) * KK;
       acc R1[1][NT];
 #pragma unroll
       for (int mt = 0; mt < NT; ++mt) R1[0][mt] = acc{0, 0, 0, 0};
