@@ -60,7 +60,8 @@ def algorithmic_flops(prob):
     """Algorithmic flops of one logL+gradient evaluation: internal-child
     matrix-vector products 2K^2 per (pattern, category); tip children are lookups;
     pre-order products and gradient outer products (N-2) 2K^2 P C each; epoch products
-    (2m-1) 2K^3 per (branch, category); padding never counted."""
+    (2m-1) 2K^3 per (branch, category); the dlogL/dQ adjoint chain three K x K products
+    (6K^3) per segment term (W = R V^-T, Y = U^T W, the update of R); padding never counted."""
     from paper_1309_3075_amd import _abi  # the library's host planner gives the segment counts
     N, P, K, C = prob.n_tips, prob.n_patterns, prob.n_states, len(prob.cat_rates)
     n_int_children = N - 2
@@ -70,7 +71,8 @@ def algorithmic_flops(prob):
                                    prob.n_processes)
     m = np.diff(off)
     chain = int(np.sum(np.maximum(2 * m - 1, 0))) * 2 * K ** 3 * C
-    return {"post_order": post, "pre_order_dP": pre, "transition_matrices": chain}
+    adjoint = int(np.sum(m)) * C * 6 * K ** 3
+    return {"post_order": post, "pre_order_dP": pre, "transition_matrices": chain, "grad_Q": adjoint}
 
 
 def fp64_reconstruction(prob, use_pi):
@@ -243,7 +245,8 @@ def main():
     abytes = algorithmic_bytes(prob, args.precision)
     aflops = algorithmic_flops(prob)
     # dominant kernel: the phase with the largest device time
-    dom = max(("post_order", "pre_order_dP", "transition_matrices"), key=lambda k: phases[k][0])
+    dom = max(("post_order", "pre_order_dP", "transition_matrices") + (("grad_Q",) if want_Q else ()),
+              key=lambda k: phases[k][0])
     dom_ms = phases[dom][0] / args.steps
     path = ("nuc" if prob.n_states == 4 else ("codon" if prob.n_states > 48 and args.precision == "fp32"
                                                and len(prob.cat_rates) == 1 else "generic"))
@@ -258,11 +261,15 @@ def main():
              "generic": {"post_order": "post_level_generic", "pre_order_dP": "pre_level_generic + grad_G_generic"}}
     Kp = 4 if prob.n_states <= 4 else (8 if prob.n_states <= 8 else (prob.n_states + 15) // 16 * 16)
     mfma_pstage = args.kernel == "auto" and Kp >= 16
-    kname = names[path].get(dom, "pstage_mfma (+ split-chain combine)" if mfma_pstage else "pstage_generic")
-    if path == "codon" or dom == "transition_matrices":
+    if dom == "grad_Q":
+        kname = "qgrad_chain + qgrad_h + qgrad_final" if mfma_pstage else "qgrad_segments + qgrad_reduce"
+    else:
+        kname = names[path].get(dom, "pstage_mfma (+ split-chain combine)" if mfma_pstage else "pstage_generic")
+    if path == "codon" or dom in ("transition_matrices", "grad_Q"):
         achieved = aflops[dom] / (dom_ms * 1e-3) / 1e12
-        peak = FP64_PEAK_TFLOPS if (args.precision == "fp64" or
-                                    dom == "transition_matrices" and fp64_reconstruction(prob, args.config != 4)) \
+        # the chains run in FP64 when the instance forms exp(tQ) in FP64 (ill-conditioned eigenvectors)
+        peak = FP64_PEAK_TFLOPS if (args.precision == "fp64" or dom in ("transition_matrices", "grad_Q")
+                                    and fp64_reconstruction(prob, args.config != 4)) \
             else FP32_PEAK_TFLOPS
         roofline = {"bound": "mfma", "kernel": kname, "achieved": round(achieved, 3), "peak": peak,
                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
