@@ -351,13 +351,23 @@ __global__ __launch_bounds__(256) void grad_G_generic_kernel(
     const int32_t* __restrict__ right, const T* __restrict__ Pm, const uint8_t* __restrict__ tips,
     const T* __restrict__ partials, const T* __restrict__ pre, const double* __restrict__ pi,
     const double* __restrict__ cat, const double* __restrict__ weights, int root, int N, int n_nodes,
-    int P, int tstride, int K, int Kp, int C, int n_chunks, double* __restrict__ Gpart) {
+    int P, int tstride, int K, int Kp, int C, int n_chunks, double* __restrict__ Gpart,
+    const T* __restrict__ dP, double* __restrict__ G, double* __restrict__ dbranch) {
+  // With one partial-sum slot per branch (n_chunks == 1, G != nullptr) the block
+  // writes G itself and dlogL/dl = <G, dP/dl> (no separate reduction).
   constexpr int TP = 256 / KQ;
   __shared__ T sQ[256], sV[256], sW[256];
   __shared__ T sAc[kMaxCategories][256];
   __shared__ T sBc[kMaxCategories][256];
+  __shared__ double sRed[256];
   const int v = blockIdx.x;
-  if (v == root) return;
+  if (v == root) {  // uniform
+    if (G) {
+      for (int e = threadIdx.x; e < C * Kp * Kp; e += 256) G[(size_t)v * C * Kp * Kp + e] = 0.0;
+      if (threadIdx.x == 0) dbranch[v] = 0.0;
+    }
+    return;
+  }
   const int u = parent[v];
   const int w = (left[u] == v) ? right[u] : left[u];
   const int pl = threadIdx.x / KQ, i = threadIdx.x % KQ;
@@ -419,6 +429,20 @@ __global__ __launch_bounds__(256) void grad_G_generic_kernel(
       }
     }
     __syncthreads();
+  }
+  if (G) {
+    double d = 0.0;
+#pragma unroll
+    for (int k = 0; k < GPT; ++k) {
+      const int e = threadIdx.x + k * 256;
+      if (e < nG) {
+        G[(size_t)v * nG + e] = (double)g[k];
+        d += (double)g[k] * (double)dP[(size_t)v * nG + e];
+      }
+    }
+    d = block_sum<256>(d, sRed);
+    if (threadIdx.x == 0) dbranch[v] = d;
+    return;
   }
 #pragma unroll
   for (int k = 0; k < GPT; ++k) {
@@ -650,7 +674,7 @@ int pre_dispatch(EpochInstance* in) {
 }
 
 template <typename T, int KQ, int GP>
-void grad_G_launch(EpochInstance* in, dim3 grid) {
+void grad_G_launch(EpochInstance* in, dim3 grid, bool fused) {
   const T* Pm = static_cast<const T*>(in->Pm.ptr);
   const uint8_t* tips = static_cast<const uint8_t*>(in->tips.ptr) + view_p0(in);
   const T* part = static_cast<const T*>(in->partials.ptr);
@@ -661,7 +685,9 @@ void grad_G_launch(EpochInstance* in, dim3 grid) {
   double* Gp = static_cast<double*>(in->Gpart.ptr);
   hipLaunchKernelGGL((grad_G_generic_kernel<T, KQ, GP>), grid, dim3(256), 0, in->stream,
                      in->d_parent, in->d_left, in->d_right, Pm, tips, part, pre, pi, cat, wts,
-                     in->plan.root, in->N, in->n_nodes, view_P(in), in->P, in->K, in->Kp, in->C, in->n_chunks, Gp);
+                     in->plan.root, in->N, in->n_nodes, view_P(in), in->P, in->K, in->Kp, in->C, in->n_chunks, Gp,
+                     static_cast<const T*>(in->dPm.ptr), fused ? static_cast<double*>(in->G.ptr) : nullptr,
+                     static_cast<double*>(in->dbranch.ptr));
 }
 
 template <typename T>
@@ -671,19 +697,21 @@ int grad_branch_dispatch(EpochInstance* in) {
   const int gpt = (nG + 255) / 256;
   if (gpt > 64) return set_error(EPOCH_ERR_ARG, "generic gradient supports C*Kp*Kp <= 16384");
   dim3 grid(in->n_nodes, in->n_chunks);
+  // one slot per branch and nothing to accumulate: the gradient kernel finishes G and dlogL/dl itself
+  const bool fused = in->n_chunks == 1 && !in->view_accumulate;
   // lanes per pattern fix Kp, so only these (KQ, elements per thread) pairs occur
   switch (KQ) {
-    case 4: grad_G_launch<T, 4, 1>(in, grid); break;
-    case 8: grad_G_launch<T, 8, 4>(in, grid); break;
-    case 16: grad_G_launch<T, 16, 16>(in, grid); break;
-    case 32: grad_G_launch<T, 32, 32>(in, grid); break;
+    case 4: grad_G_launch<T, 4, 1>(in, grid, fused); break;
+    case 8: grad_G_launch<T, 8, 4>(in, grid, fused); break;
+    case 16: grad_G_launch<T, 16, 16>(in, grid, fused); break;
+    case 32: grad_G_launch<T, 32, 32>(in, grid, fused); break;
     default:
-      if (gpt <= 16) grad_G_launch<T, 64, 16>(in, grid);
-      else grad_G_launch<T, 64, 64>(in, grid);
+      if (gpt <= 16) grad_G_launch<T, 64, 16>(in, grid, fused);
+      else grad_G_launch<T, 64, 64>(in, grid, fused);
       break;
   }
   int rc = hip_check(hipGetLastError(), "grad_G_generic launch");
-  if (rc) return rc;
+  if (rc || fused) return rc;
   return launch_grad_reduce(in, in->n_chunks, nullptr);
 }
 
