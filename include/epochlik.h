@@ -82,8 +82,9 @@ typedef struct EpochConfig {
   int32_t reserved;        /* must be 0 */
   int64_t hbm_budget_bytes; /* 0 = unlimited.  > 0: device bytes allowed for intermediate
                              * partials (and their scale rows and gradient partial sums):
-                             * - n_states == 4 with EPOCH_KERNEL_AUTO, no EPOCH_GRAD_Q: the tree
-                             *   walk stores only the partials of the largest subtrees that fit
+                             * - n_states == 4 with EPOCH_KERNEL_AUTO, no EPOCH_GRAD_Q (with it,
+                             *   EPOCH_ERR_ARG; EPOCH_KERNEL_GENERIC takes the chunked form below):
+                             *   the tree walk stores only the partials of the largest subtrees that fit
                              *   and recomputes the others from the tip states in the gradient
                              *   pass; set_tree_epochs returns EPOCH_ERR_OOM when even the root
                              *   alone does not fit.

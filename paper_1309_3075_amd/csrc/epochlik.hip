@@ -229,7 +229,9 @@ int epoch_create(const EpochConfig* cfg, EpochInstance** out) {
   const bool codon_budget = c.hbm_budget_bytes > 0 && codon_budget_config(c);
   const bool gen_budget = c.hbm_budget_bytes > 0 && !nuc_budget && !codon_budget;
   if (nuc_budget && (c.flags & EPOCH_GRAD_Q))
-    return set_error(EPOCH_ERR_ARG, "hbm_budget_bytes on 4-state instances cannot be combined with EPOCH_GRAD_Q");
+    return set_error(EPOCH_ERR_ARG,
+                     "hbm_budget_bytes with the 4-state kernels cannot be combined with EPOCH_GRAD_Q "
+                     "(EPOCH_KERNEL_GENERIC evaluates pattern chunks instead)");
   const size_t chunk_pattern_bytes = codon_budget ? codon_bytes_per_pattern(c) : generic_bytes_per_pattern(c);
   if ((codon_budget || gen_budget) &&
       (size_t)c.hbm_budget_bytes < chunk_pattern_bytes * (size_t)std::min(c.n_patterns, 64))
