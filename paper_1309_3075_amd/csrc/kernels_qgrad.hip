@@ -580,6 +580,7 @@ __global__ __launch_bounds__(256) void qgrad_hsum_kernel(int KK, int n_chunks, c
   const double2* src = reinterpret_cast<const double2*>(Hpart) + (size_t)s * n_chunks * KK + e;
   double2 a0 = make_double2(0.0, 0.0), a1 = a0;
   int ch = 0;
+#pragma unroll 8
   for (; ch + 2 <= n_chunks; ch += 2) {
     const double2 h0 = src[(size_t)ch * KK], h1 = src[(size_t)(ch + 1) * KK];
     a0.x += h0.x;
