@@ -915,6 +915,9 @@ int epoch_set_option(EpochInstance* in, int32_t key, int64_t value) {
     case EPOCH_OPT_CHAIN_SPLIT:
       if (value < 0 || value > (1 << 30)) return set_error(EPOCH_ERR_ARG, "EPOCH_OPT_CHAIN_SPLIT out of range");
       in->chain_split_min = (int)value;
+      // the parts' scratch (prefixes, suffixes) belongs to the P stage that formed it: evaluate again
+      in->P_valid = in->partials_valid = in->logL_valid = false;
+      in->pstage_split = false;
       if (in->have_tree) {
         if (int rc = build_chain_items(in, in->plan.seg_offset)) return rc;
       }

@@ -278,6 +278,23 @@ def test_split_epoch_chains(precision, chain_split):
     np.testing.assert_allclose(P, ref_P, rtol=0, atol=TOL_P[precision] * max(1.0, prob.n_states / 8))
 
 
+def test_chain_split_option_between_evaluations():
+    """Changing the chain split invalidates the state: the gradient is refused until the path
+    runs again, and the new evaluation matches the oracle."""
+    prob = W.make_config(4, n_tips=160)
+    want = O.log_likelihood(prob)
+    ref_b, ref_q = O.gradient(prob)
+    with from_problem(prob, "fp64", grad_branch=True, grad_Q=True, use_pi=False, options={"chain_split": 2}) as lik:
+        first = lik.evaluate(branch=True, Q=True)
+        lik.set_option("chain_split", 7)
+        with pytest.raises(Exception):
+            lik.gradient(branch=True, Q=True)
+        logL, _, db, dq = lik.evaluate(branch=True, Q=True)
+    for l, b, q in ((first[0], first[2], first[3]), (logL, db, dq)):
+        assert rel(l, want) <= TOL_LOGL["fp64"]
+        assert grad_rel(b, ref_b) <= TOL_GRAD["fp64"] and grad_rel(q, ref_q) <= TOL_GRAD["fp64"]
+
+
 def test_trait_C4_full_size():
     """The full 2000-taxon 40-state workload in the benchmarked configuration (FP32,
     automatic kernels): logL and every gradient against the oracle."""
