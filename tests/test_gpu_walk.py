@@ -195,14 +195,18 @@ def _codon_budget(prob, patterns_per_chunk, grad=True):
     return per * patterns_per_chunk
 
 
+@pytest.mark.parametrize("split_blocks", [256, 0])
 @pytest.mark.parametrize("chunk", [64, 192])
-def test_codon_hbm_budget_streams_pattern_chunks(chunk):
+def test_codon_hbm_budget_streams_pattern_chunks(chunk, split_blocks):
     """Under a budget the 64-state path evaluates the patterns in chunks (the last one
     ragged); the gradient call forms each chunk's partials again.  Results match the
-    oracle and the unbudgeted instance, through the separate calls and the single call."""
+    oracle and the unbudgeted instance, through the separate calls and the single call,
+    with the pre-order levels on the side-split kernel (the default here) or all on the
+    four-wavefront kernel (split_blocks 0); both zero the slots of blocks past a short chunk."""
     prob = W.make_config(3, n_patterns=700)
     budget = _codon_budget(prob, chunk)
-    with from_problem(prob, "fp32", grad_branch=True, grad_Q=True, hbm_budget_bytes=budget) as lik:
+    with from_problem(prob, "fp32", grad_branch=True, grad_Q=True, hbm_budget_bytes=budget,
+                      options={"split_blocks": split_blocks}) as lik:
         logL, site = lik.log_likelihood(site=True)
         db, dq = lik.gradient(branch=True, Q=True)
         one = lik.evaluate(branch=True, Q=True, site=True)
