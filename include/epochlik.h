@@ -277,7 +277,7 @@ int epoch_set_option(EpochInstance* inst, int32_t key, int64_t value);
  * must outlive it.  Members on the 64-state path share merged per-level
  * launches; the graph is captured at the first evaluation and replayed, and
  * captured again when a member's tree or eigen-reconstruction precision
- * changes.  tune_cache_path (or NULL) names a text file caching the tuned
+ * changes or epoch_set_option is called on a member.  tune_cache_path (or NULL) names a text file caching the tuned
  * launch shape per device and batch shape; it is read, and written after
  * tuning on the first evaluation. */
 typedef struct EpochBatch EpochBatch;

@@ -46,7 +46,7 @@ struct EpochBatch {
     size_t desc_offset = 0;  // index of the group's first descriptor in pdescs
   };
   std::vector<PGroup> pgroups;
-  std::vector<size_t> p_single;  // members on the generic P stage
+  std::vector<size_t> p_single;  // members that run their own P stage (generic, or a matrix-core group of one)
   DevBuf pdescs;
   std::vector<uint64_t> signature;
   hipGraph_t graph[8] = {};
@@ -66,7 +66,7 @@ __global__ __launch_bounds__(64) void gather_results(const double* const* __rest
 
 uint64_t member_signature(const EpochInstance* in) {
   uint64_t h = (uint64_t)in->tree_generation * 1000003ull + (in->eig_fp64 ? 7 : 0);
-  return h;
+  return h ^ (in->option_generation * 0x9E3779B97F4A7C15ull);
 }
 
 void release_buf(DevBuf& b) {
@@ -107,6 +107,13 @@ int build_pstage_groups(EpochBatch* b) {
     b->pgroups[g].members.push_back(q);
     b->pgroups[g].max_items = std::max(b->pgroups[g].max_items, in->n_nodes * in->C);
   }
+  // A group of one gains nothing from the shared launch, which runs whole chains:
+  // that member runs its own P stage, with long epoch chains split into parts.
+  for (size_t g = b->pgroups.size(); g-- > 0;)
+    if (b->pgroups[g].members.size() == 1) {
+      b->p_single.push_back(b->pgroups[g].members[0]);
+      b->pgroups.erase(b->pgroups.begin() + g);
+    }
   std::vector<PStageDesc> descs;
   for (auto& g : b->pgroups) {
     g.desc_offset = descs.size();

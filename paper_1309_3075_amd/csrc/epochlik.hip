@@ -886,6 +886,9 @@ int epoch_workspace_bytes(const EpochConfig* cfg, int64_t* out) {
 
 int epoch_set_option(EpochInstance* in, int32_t key, int64_t value) {
   if (!in) return set_error(EPOCH_ERR_ARG, "NULL instance");
+  // options change launch shapes and may reallocate schedules and work lists:
+  // a batch holding this instance captures its graph again
+  in->option_generation++;
   switch (key) {
     case EPOCH_OPT_TREE_WALK:
       if (value < -1 || value > 1) return set_error(EPOCH_ERR_ARG, "EPOCH_OPT_TREE_WALK takes -1, 0 or 1");

@@ -102,6 +102,7 @@ struct EpochInstance {
   bool P_valid = false, partials_valid = false, logL_valid = false;
   bool grad_ready = false, gradQ_ready = false;  // gradients left on the device by a batch evaluation
   uint64_t tree_generation = 0;                   // bumped by set_tree_epochs
+  uint64_t option_generation = 0;                 // bumped by every epoch_set_option call
   bool eig_dirty = true;
   epochlik::TreePlan plan;
   int n_chunks = 1;  // pattern chunks of the generic gradient accumulation

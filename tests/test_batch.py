@@ -88,3 +88,26 @@ def test_batch_with_a_pattern_chunked_codon_member():
     batch.close()
     for m in members:
         m.close()
+
+
+def test_one_member_batch_splits_chains_and_recaptures_after_an_option():
+    """A batch of one 40-state member runs that member's own P stage inside the graph (long epoch
+    chains cut into parts); changing an option on the member (here the chain split, which rebuilds
+    its chain work lists) makes the batch capture its graph again.  Every evaluation, and its
+    replay, matches the oracle."""
+    prob = W.make_config(4, n_tips=160)
+    want = O.log_likelihood(prob)
+    ref_b, ref_q = O.gradient(prob)
+    with from_problem(prob, "fp64", grad_branch=True, grad_Q=True, use_pi=False,
+                      options={"chain_split": 7}) as lik:
+        batch = EpochBatchEvaluator([lik])
+        for split in (7, 2, 0):
+            lik.set_option("chain_split", split)
+            logL = batch.evaluate(grad_branch=True, grad_Q=True)
+            again = batch.evaluate(grad_branch=True, grad_Q=True)
+            assert np.array_equal(logL, again)
+            db, dq = batch.gradients(0, branch=True, Q=True)
+            assert abs(logL[0] - want) / abs(want) <= 1e-12, (split, logL[0], want)
+            assert np.linalg.norm(db - ref_b) / np.linalg.norm(ref_b) <= 1e-6, split
+            assert np.linalg.norm(dq - ref_q) / np.linalg.norm(ref_q) <= 1e-6, split
+        batch.close()
