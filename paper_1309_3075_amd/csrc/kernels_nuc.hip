@@ -218,7 +218,7 @@ __device__ inline void post_tiles(const NucCtx<T>& x, int u, int a, int b, int f
 #pragma unroll
     for (int i = 0; i < 4; ++i) y.v[i] = scale_by_pow2(y.v[i], e);
     if (p < P && x.cat_ok) {
-      part_out[((size_t)(u - N) * C + c) * P + p] = y;
+      store_streaming(&part_out[((size_t)(u - N) * C + c) * P + p], y);
       if (x.cl == 0) scale_out[(size_t)(u - N) * P + p] = e + sa + sb;
     }
     ca = na;
@@ -392,7 +392,7 @@ __device__ inline void pre_tiles(const NucCtx<T>& x, int u, int a, int b, int fi
       const int ea = scale_exponent(ma);
 #pragma unroll
       for (int i = 0; i < 4; ++i) qa.v[i] = scale_by_pow2(qa.v[i], ea);
-      if (p < P && cat_ok) pre_out[((size_t)(a - N) * C + c) * P + p] = qa;
+      if (p < P && cat_ok) store_streaming(&pre_out[((size_t)(a - N) * C + c) * P + p], qa);
     }
     if constexpr (NX >= 1 && KB == kCherry) {
       constexpr int h = NX == 2 ? 2 : 0;
@@ -405,7 +405,7 @@ __device__ inline void pre_tiles(const NucCtx<T>& x, int u, int a, int b, int fi
       const int eb = scale_exponent(mb);
 #pragma unroll
       for (int i = 0; i < 4; ++i) qb.v[i] = scale_by_pow2(qb.v[i], eb);
-      if (p < P && cat_ok) pre_out[((size_t)(b - N) * C + c) * P + p] = qb;
+      if (p < P && cat_ok) store_streaming(&pre_out[((size_t)(b - N) * C + c) * P + p], qb);
     }
     ca = na;
     cb = nb;

@@ -13,6 +13,20 @@ struct alignas(4 * sizeof(T)) V4 {
   T v[4];
 };
 
+// Store of a pattern's 4-vector that no other block of the launch reads.  In
+// FP32 a non-temporal vector store, so the streamed output does not displace
+// the launch's inputs from L2 (C2: 1.7 % faster); in FP64 the plain store
+// measured faster.
+template <typename T>
+__device__ inline void store_streaming(V4<T>* dst, const V4<T>& x) {
+  if constexpr (sizeof(T) == 4) {
+    typedef T vec4 __attribute__((ext_vector_type(4)));
+    __builtin_nontemporal_store(vec4{x.v[0], x.v[1], x.v[2], x.v[3]}, reinterpret_cast<vec4*>(dst));
+  } else {
+    *dst = x;
+  }
+}
+
 template <typename T>
 struct M4 {
   T m[16];
