@@ -210,7 +210,7 @@ __global__ __launch_bounds__(256) void codon_post_level_kernel(const CodonProble
       const int p = p0 + 4 * g + v;
       if (p < P) {
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) out[(size_t)p * KP + 16 * nt + r] = ldexpf(Sa[nt][v], -e[v]);
+        for (int nt = 0; nt < 4; ++nt) __builtin_nontemporal_store(ldexpf(Sa[nt][v], -e[v]), &out[(size_t)p * KP + 16 * nt + r]);
         if (r == 0) sout[p] = e[v] + (sca ? gptr(sca)[p] : 0) + (scb ? gptr(scb)[p] : 0);
       }
     }
@@ -474,7 +474,7 @@ __global__ __launch_bounds__(256, 2) void codon_pre_level_kernel(const CodonProb
           const int p = p0 + 4 * g + v;
           if (p < P)
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) out[(size_t)p * KP + 16 * nt + r] = ldexpf(Qo[nt][v], -e);
+            for (int nt = 0; nt < 4; ++nt) __builtin_nontemporal_store(ldexpf(Qo[nt][v], -e), &out[(size_t)p * KP + 16 * nt + r]);
         }
       }
       __syncthreads();  // t, L, w_p / L_p and tip columns of every wavefront are in LDS
@@ -497,7 +497,7 @@ __global__ __launch_bounds__(256, 2) void codon_pre_level_kernel(const CodonProb
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) dst[(WT * w + 4 * g + v) * KP + 16 * nt + r] = G[nt][v];
+      for (int v = 0; v < 4; ++v) __builtin_nontemporal_store(G[nt][v], &dst[(WT * w + 4 * g + v) * KP + 16 * nt + r]);
   }
 }
 
@@ -647,7 +647,7 @@ __global__ __launch_bounds__(512, 1) void codon_pre_split_kernel(const CodonProb
         const int p = p0 + 4 * g + v;
         if (p < P)
 #pragma unroll
-          for (int nt = 0; nt < 4; ++nt) out[(size_t)p * KP + 16 * nt + r] = ldexpf(Qo[nt][v], -e);
+          for (int nt = 0; nt < 4; ++nt) __builtin_nontemporal_store(ldexpf(Qo[nt][v], -e), &out[(size_t)p * KP + 16 * nt + r]);
       }
     }
     __syncthreads();  // t, L, w_p / L_p and tip columns of the whole tile are in LDS
@@ -662,7 +662,7 @@ __global__ __launch_bounds__(512, 1) void codon_pre_split_kernel(const CodonProb
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) dst[(WT * w + 4 * g + v) * KP + 16 * nt + r] = G[nt][v];
+    for (int v = 0; v < 4; ++v) __builtin_nontemporal_store(G[nt][v], &dst[(WT * w + 4 * g + v) * KP + 16 * nt + r]);
 }
 
 // G[v] = sum of the FP32 slot partials in FP64 (fixed order): one block per
