@@ -60,15 +60,19 @@ class EpochLogLikelihood(torch.autograd.Function):
         for s, Q in enumerate(Qs):
             model.lik.set_rate_matrix(s, Q.detach().cpu().double().numpy(), model.reversible_pi[s])
         model.lik.set_tree(prob.parent, prob.height, rate, prob.boundaries, prob.interval_process)
-        logL = model.lik.log_likelihood()
-        ctx.model = model
+        # The library instance is shared by every forward on this model, so the gradients of
+        # this forward are formed now (one evaluation, one host synchronisation) and kept with
+        # its context: a later forward cannot overwrite them before this backward runs.
+        want = any(ctx.needs_input_grad[1:])
+        logL, _, db, dq = model.lik.evaluate(branch=want, Q=want)
+        ctx.grads = (db, dq)
         ctx.n_q = len(Qs)
         ctx.devices = [branch_lengths.device] + [Q.device for Q in Qs]
         return torch.tensor(logL, dtype=torch.float64)
 
     @staticmethod
     def backward(ctx, grad_out: torch.Tensor):
-        db, dq = ctx.model.lik.gradient(branch=True, Q=True)
+        db, dq = ctx.grads
         g = float(grad_out)
         grads: List[Optional[torch.Tensor]] = [None]
         grads.append(torch.tensor(g * db, dtype=torch.float64, device=ctx.devices[0]))

@@ -176,6 +176,14 @@ int enqueue(EpochBatch* b, uint32_t what, const double* const* d_result_ptrs) {
     if (!rc) rc = fastpath_after_pstage(b->insts[q]);
     if (rc) return rc;
   }
+  if (b->merged && (what & (kGradBranch | kGradQ))) {
+    // the gradient launches write through these buffers: refuse a capture without them
+    for (size_t q = 0; q < n; ++q) {
+      const EpochInstance* in = b->insts[q];
+      if (!in->pre.ptr || !in->dPm.ptr || !in->G.ptr || !in->dbranch.ptr)
+        return set_error(EPOCH_ERR_STATE, "batch member %zu has no gradient buffers", q);
+    }
+  }
   if (b->merged) {
     const CodonProblem* probs = static_cast<const CodonProblem*>(b->dev.ptr);
     const int2* items = reinterpret_cast<const int2*>(static_cast<const char*>(b->dev.ptr) + sizeof(CodonProblem) * n);
@@ -335,7 +343,14 @@ int autotune(EpochBatch* b) {
     b->target_blocks = v;
     return EPOCH_OK;
   }
-  const uint32_t what = kLogL | kGradBranch;
+  // tune the evaluation every member supports: the branch gradient only when every member keeps
+  // its buffers (a log-likelihood-only member has no outside vectors or dlogL/dP slots)
+  bool all_grad = true;
+  for (auto* in : b->insts)
+    if (!(in->cfg.flags & EPOCH_GRAD_BRANCH)) all_grad = false;
+  const uint32_t what = kLogL | (all_grad ? kGradBranch : 0u);
+  int rc0 = check_members(b, what);
+  if (rc0) return rc0;
   hipEvent_t e0, e1;
   int rc = hip_check(hipEventCreate(&e0), "tune event");
   if (!rc) rc = hip_check(hipEventCreate(&e1), "tune event");

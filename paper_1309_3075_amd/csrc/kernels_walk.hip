@@ -803,7 +803,14 @@ int walk_prepare(EpochInstance* in) {
       return set_error(EPOCH_ERR_OOM, "hbm_budget_bytes %lld is below the %zu bytes the root's partial needs",
                        (long long)in->budget, walk_budget_bytes(in, 1));
   }
-  const bool built = !build_walk_programs(in->plan, rt, in->walk) && walk_fits(in, in->walk.post_slots);
+  bool built = !build_walk_programs(in->plan, rt, in->walk) && walk_fits(in, in->walk.post_slots);
+  // When the pre-order program does not fit, the level kernels take the gradient from the
+  // walk's stored partials; they recompute only cherries, so every larger subtree must be stored.
+  const bool grad = (in->cfg.flags & (EPOCH_GRAD_BRANCH | EPOCH_GRAD_Q)) != 0;
+  if (built && grad && in->budget == 0 && rt > 2 && !walk_fits(in, in->walk.pre_slots)) {
+    rt = 2;
+    built = !build_walk_programs(in->plan, rt, in->walk) && walk_fits(in, in->walk.post_slots);
+  }
   if (!built) {
     if (in->budget > 0) return set_error(EPOCH_ERR_ARG, "the tree is too deep for the tree walk an HBM budget needs");
     return EPOCH_OK;  // too deep for the stack: level kernels

@@ -70,3 +70,25 @@ def test_autograd_omega_and_branch_lengths(precision, tol):
     gb = ell.grad.numpy()
     assert np.linalg.norm(gb - ref_b) / np.linalg.norm(ref_b) < tol
     model.close()
+
+
+@pytest.mark.gpu
+def test_autograd_two_forwards_then_backwards():
+    """Two forwards on one model before either backward (current and proposed state): each
+    backward returns the gradient of its own forward."""
+    prob = W.make_config(1, n_tips=10, n_patterns=120)
+    model = A.EpochModel(prob, precision="fp64")
+    Qs = [torch.tensor(Q, dtype=torch.float64) for Q in prob.Q]
+    ell1 = model.branch_lengths().requires_grad_(True)
+    ell2 = (model.branch_lengths() * 1.5).requires_grad_(True)
+    l1 = A.EpochLogLikelihood.apply(model, ell1, *Qs)
+    l2 = A.EpochLogLikelihood.apply(model, ell2, *Qs)
+    l1.backward()
+    l2.backward()
+    p2 = W.Problem(**{**prob.__dict__})
+    p2.branch_rate = prob.branch_rate * 1.5
+    for lv, ell, p in ((l1, ell1, prob), (l2, ell2, p2)):
+        assert abs(float(lv) - O.log_likelihood(p)) <= 1e-12 * abs(O.log_likelihood(p))
+        ref_b, _ = O.gradient(p, wrt=("branch",))
+        np.testing.assert_allclose(ell.grad.numpy(), ref_b, rtol=1e-6, atol=1e-9 * np.abs(ref_b).max())
+    model.close()

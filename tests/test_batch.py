@@ -7,7 +7,9 @@ import pytest
 
 from oracle import epoch_oracle as O
 from paper_1309_3075_amd import workloads as W
+from paper_1309_3075_amd import _abi
 from paper_1309_3075_amd.likelihood import EpochBatchEvaluator, from_problem
+from tolerances import TOL_GRAD, TOL_LOGL, assert_grad, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -118,3 +120,83 @@ def test_one_member_batch_splits_chains_and_recaptures_after_an_option():
             assert np.linalg.norm(db - ref_b) / np.linalg.norm(ref_b) <= 1e-6, split
             assert np.linalg.norm(dq - ref_q) / np.linalg.norm(ref_q) <= 1e-6, split
         batch.close()
+
+
+def test_logL_only_codon_batch_tunes_and_matches_oracle():
+    """A merged 64-state batch whose members keep no gradient buffers: the first evaluation tunes
+    the launch shape with log-likelihood-only replays, every member matches the oracle, and a
+    gradient request is refused."""
+    probs = W.make_batch(4, scale=0.05)
+    members = [from_problem(p, "fp32") for p in probs]
+    cache = os.path.join(tempfile.mkdtemp(), "tune.json")  # empty cache: the tuner runs
+    batch = EpochBatchEvaluator(members, tune_cache=cache)
+    logL = batch.evaluate(grad_branch=False)
+    assert os.path.exists(cache)
+    for i, p in enumerate(probs):
+        assert rel(logL[i], O.log_likelihood(p)) <= TOL_LOGL["fp32"], i
+    assert np.array_equal(batch.evaluate(grad_branch=False), logL)
+    with pytest.raises(_abi.EpochError) as e:
+        batch.evaluate(grad_branch=True)
+    assert e.value.code == _abi.EPOCH_ERR_STATE
+    batch.close()
+    for m in members:
+        m.close()
+
+
+@pytest.fixture(scope="module")
+def full_c5():
+    """The full batched codon workload (64 GY94 problems, 64-256 taxa, 1,000-20,000 patterns
+    each) in the configuration bench.py times, evaluated once with branch and rate-matrix
+    gradients."""
+    probs = W.make_batch(64)
+    members = [from_problem(p, "fp32", grad_branch=True, grad_Q=True) for p in probs]
+    batch = EpochBatchEvaluator(members, tune_cache=os.path.join(tempfile.mkdtemp(), "tune.json"))
+    logL = batch.evaluate(grad_branch=True, grad_Q=True)
+    grads = [batch.gradients(i, branch=True, Q=True) for i in range(len(probs))]
+    yield probs, members, batch, logL, grads
+    batch.close()
+    for m in members:
+        m.close()
+
+
+def test_full_C5_batch_every_member_sites(full_c5):
+    """Every member of the full batch: its root log-likelihood, formed again from the partials
+    the batched launches left, reproduces the batch's logL, and its per-site log-likelihoods on
+    sampled patterns (first, last and random) match the oracle on those patterns."""
+    import dataclasses
+    probs, members, _, logL, _ = full_c5
+    rng = np.random.default_rng(5)
+    for i, (p, m) in enumerate(zip(probs, members)):
+        again, site = m.root_log_likelihood(site=True)
+        assert again == logL[i], (i, again, logL[i])
+        idx = np.unique(np.concatenate([[0, p.n_patterns - 1], rng.choice(p.n_patterns, 24, replace=False)]))
+        sub = dataclasses.replace(p, tips=p.tips[:, idx], weights=p.weights[idx])
+        want = O.site_log_likelihoods(sub)
+        np.testing.assert_allclose(site[idx], want, rtol=TOL_LOGL["fp32"] * 10, atol=0, err_msg=f"member {i}")
+
+
+def _checked_members(probs):
+    size = [p.n_tips * p.n_patterns for p in probs]
+    order = np.argsort(size)
+    # the largest, the smallest and six spread between them
+    return sorted({int(order[-1]), int(order[0])} | {int(order[k]) for k in np.linspace(1, len(probs) - 2, 6).astype(int)})
+
+
+def test_full_C5_batch_logL_of_eight_members(full_c5):
+    probs, _, _, logL, _ = full_c5
+    for i in _checked_members(probs):
+        want = O.log_likelihood(probs[i])
+        assert rel(logL[i], want) <= TOL_LOGL["fp32"], (i, logL[i], want)
+
+
+@pytest.mark.parametrize("half", [0, 1])
+def test_full_C5_batch_gradients_of_eight_members(full_c5, half):
+    """Branch and per-epoch rate-matrix gradients (through which torch forms the omega
+    gradients) of eight members including the largest, against the oracle."""
+    probs, _, _, _, grads = full_c5
+    chosen = _checked_members(probs)
+    for i in chosen[half::2]:
+        ref_b, ref_q = O.gradient(probs[i])
+        db, dq = grads[i]
+        assert_grad(db, ref_b, TOL_GRAD["fp32"], f"member {i} dlogL/dl")
+        assert_grad(dq, ref_q, TOL_GRAD["fp32"], f"member {i} dlogL/dQ")

@@ -1,7 +1,9 @@
 """Parity of the HIP path (through the C ABI) against the FP64 oracle.
 
-Tolerances: |dlogL|/|logL| <= 1e-12 (FP64) and <= 1e-5 (FP32); gradients
-||dg||_2 / ||g||_2 <= 1e-6 (FP64) and <= 1e-3 (FP32); transition matrices
+Tolerances: |dlogL|/|logL| <= 1e-12 (FP64) and <= 1e-5 (FP32); per-site
+log-likelihoods to 10x that relative bound plus an absolute floor of the bound
+times the largest |site logL|; gradients ||dg||_2 / ||g||_2 <= 1e-6 (FP64) and
+<= 1e-3 (FP32) and componentwise (tests/tolerances.py); transition matrices
 entrywise to 1e-12 (FP64) / 2e-6 (FP32).
 """
 import numpy as np
@@ -11,20 +13,9 @@ from oracle import epoch_oracle as O
 from paper_1309_3075_amd import _abi
 from paper_1309_3075_amd import workloads as W
 from paper_1309_3075_amd.likelihood import EpochLikelihood, from_problem
+from tolerances import TOL_GRAD, TOL_LOGL, TOL_P, assert_grad, grad_rel, rel  # noqa: F401
 
 pytestmark = pytest.mark.gpu
-
-TOL_LOGL = {"fp64": 1e-12, "fp32": 1e-5}
-TOL_GRAD = {"fp64": 1e-6, "fp32": 1e-3}
-TOL_P = {"fp64": 1e-12, "fp32": 2e-6}
-
-
-def rel(a, b):
-    return abs(a - b) / abs(b)
-
-
-def grad_rel(g, ref):
-    return np.linalg.norm(g - ref) / np.linalg.norm(ref)
 
 
 RANDOM_CASES = [
@@ -44,7 +35,7 @@ RANDOM_CASES = [
     (112, 10, 4, 70, 5, 3, 3, True, 0.0, 0.0),
     (113, 9, 4, 90, 8, 2, 2, False, 0.1, 0.1),
 ]
-GRAD_CASES = RANDOM_CASES[:7] + RANDOM_CASES[8:]
+GRAD_CASES = RANDOM_CASES
 
 
 def _prob(case):
@@ -69,7 +60,7 @@ def test_random_problem_logL_and_P(case, precision, kernel, use_pi):
     want_site = O.site_log_likelihoods(prob)
     want = float(np.dot(prob.weights, want_site))
     assert rel(logL, want) <= TOL_LOGL[precision], (logL, want)
-    np.testing.assert_allclose(site, want_site, rtol=TOL_LOGL[precision] * 1000,
+    np.testing.assert_allclose(site, want_site, rtol=TOL_LOGL[precision] * 10,
                                atol=TOL_LOGL[precision] * np.abs(want_site).max())
     Pw = O.transition_matrices(prob)
     Pw[-1] = 0.0
@@ -95,8 +86,8 @@ def test_gradients_against_oracle(case, precision, kernel):
         lik.log_likelihood()
         db, dq = lik.gradient(branch=True, Q=True)
     ref_b, ref_q = O.gradient(prob)
-    assert grad_rel(db, ref_b) <= TOL_GRAD[precision], grad_rel(db, ref_b)
-    assert grad_rel(dq, ref_q) <= TOL_GRAD[precision], grad_rel(dq, ref_q)
+    assert_grad(db, ref_b, TOL_GRAD[precision])
+    assert_grad(dq, ref_q, TOL_GRAD[precision])
     assert db[-1] == 0.0
 
 
@@ -151,7 +142,21 @@ def test_C2_tree_reduced_patterns(precision):
     want = O.log_likelihood(prob)
     ref_b, _ = O.gradient(prob, wrt=("branch",))
     assert rel(logL, want) <= TOL_LOGL[precision], rel(logL, want)
-    assert grad_rel(db, ref_b) <= TOL_GRAD[precision], grad_rel(db, ref_b)
+    assert_grad(db, ref_b, TOL_GRAD[precision])
+
+
+def test_C2_full_tree_fp32_level_kernels_gradient():
+    """The benchmarked 4-state kernels on the full 512-taxon C2 tree and model: FP32, level
+    kernels (more than 1,024 tiles of 16 patterns, so the automatic choice is the level path
+    that bench.py times), 30,000 simulated patterns; logL and all 1,022 branch gradients
+    against the oracle on the same patterns."""
+    prob = W.make_config(2, n_patterns=30000)
+    with from_problem(prob, "fp32", grad_branch=True, options={"tree_walk": 0}) as lik:
+        logL, _, db, _ = lik.evaluate(branch=True)
+    want = O.log_likelihood(prob)
+    ref_b, _ = O.gradient(prob, wrt=("branch",))
+    assert rel(logL, want) <= TOL_LOGL["fp32"], rel(logL, want)
+    assert_grad(db, ref_b, TOL_GRAD["fp32"], "dlogL/dl")
 
 
 def test_repeat_evaluations_are_bitwise_identical():
@@ -181,8 +186,8 @@ def test_codon_C3_tree(kernel):
     want = O.log_likelihood(prob)
     ref_b, ref_q = O.gradient(prob)
     assert rel(logL, want) <= TOL_LOGL["fp32"], rel(logL, want)
-    assert grad_rel(db, ref_b) <= TOL_GRAD["fp32"], grad_rel(db, ref_b)
-    assert grad_rel(dq, ref_q) <= TOL_GRAD["fp32"], grad_rel(dq, ref_q)
+    assert_grad(db, ref_b, TOL_GRAD["fp32"])
+    assert_grad(dq, ref_q, TOL_GRAD["fp32"])
 
 
 def _codon_eval(prob, options):
@@ -202,8 +207,8 @@ def test_codon_side_split_pre_order_matches_oracle(n_patterns):
     out = [_codon_eval(prob, {"split_blocks": v}) for v in (0, 256, 1 << 30)]
     for logL, db, dq in out:
         assert rel(logL, want) <= TOL_LOGL["fp32"], rel(logL, want)
-        assert grad_rel(db, ref_b) <= TOL_GRAD["fp32"], grad_rel(db, ref_b)
-        assert grad_rel(dq, ref_q) <= TOL_GRAD["fp32"], grad_rel(dq, ref_q)
+        assert_grad(db, ref_b, TOL_GRAD["fp32"])
+        assert_grad(dq, ref_q, TOL_GRAD["fp32"])
     for logL, db, dq in out[1:]:
         assert logL == out[0][0] and np.array_equal(db, out[0][1]) and np.array_equal(dq, out[0][2])
 
@@ -217,7 +222,8 @@ def test_codon_target_blocks_option(target_blocks):
     want = O.log_likelihood(prob)
     ref_b, ref_q = O.gradient(prob)
     assert rel(logL, want) <= TOL_LOGL["fp32"]
-    assert grad_rel(db, ref_b) <= TOL_GRAD["fp32"] and grad_rel(dq, ref_q) <= TOL_GRAD["fp32"]
+    assert_grad(db, ref_b, TOL_GRAD["fp32"])
+    assert_grad(dq, ref_q, TOL_GRAD["fp32"])
 
 
 def test_codon_side_split_several_tiles_per_block():
@@ -236,7 +242,7 @@ def test_codon_fp64_generic_C3_tree():
         db, _ = lik.gradient()
     assert rel(logL, O.log_likelihood(prob)) <= TOL_LOGL["fp64"]
     ref_b, _ = O.gradient(prob, wrt=("branch",))
-    assert grad_rel(db, ref_b) <= TOL_GRAD["fp64"]
+    assert_grad(db, ref_b, TOL_GRAD["fp64"])
 
 
 @pytest.mark.parametrize("kernel", ["auto", "generic"])
@@ -252,8 +258,8 @@ def test_trait_C4_shape(precision, kernel):
     want = O.log_likelihood(prob)
     ref_b, ref_q = O.gradient(prob)
     assert rel(logL, want) <= TOL_LOGL[precision], rel(logL, want)
-    assert grad_rel(db, ref_b) <= TOL_GRAD[precision], grad_rel(db, ref_b)
-    assert grad_rel(dq, ref_q) <= TOL_GRAD[precision], grad_rel(dq, ref_q)
+    assert_grad(db, ref_b, TOL_GRAD[precision])
+    assert_grad(dq, ref_q, TOL_GRAD[precision])
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -271,8 +277,8 @@ def test_split_epoch_chains(precision, chain_split):
     want = O.log_likelihood(prob)
     ref_b, ref_q = O.gradient(prob)
     assert rel(logL, want) <= TOL_LOGL[precision], rel(logL, want)
-    assert grad_rel(db, ref_b) <= TOL_GRAD[precision], grad_rel(db, ref_b)
-    assert grad_rel(dq, ref_q) <= TOL_GRAD[precision], grad_rel(dq, ref_q)
+    assert_grad(db, ref_b, TOL_GRAD[precision])
+    assert_grad(dq, ref_q, TOL_GRAD[precision])
     ref_P = O.transition_matrices(prob)
     ref_P[-1] = 0.0
     np.testing.assert_allclose(P, ref_P, rtol=0, atol=TOL_P[precision] * max(1.0, prob.n_states / 8))
@@ -292,7 +298,8 @@ def test_chain_split_option_between_evaluations():
         logL, _, db, dq = lik.evaluate(branch=True, Q=True)
     for l, b, q in ((first[0], first[2], first[3]), (logL, db, dq)):
         assert rel(l, want) <= TOL_LOGL["fp64"]
-        assert grad_rel(b, ref_b) <= TOL_GRAD["fp64"] and grad_rel(q, ref_q) <= TOL_GRAD["fp64"]
+        assert_grad(b, ref_b, TOL_GRAD["fp64"])
+        assert_grad(q, ref_q, TOL_GRAD["fp64"])
 
 
 def test_trait_C4_full_size():
@@ -304,8 +311,8 @@ def test_trait_C4_full_size():
         db, dq = lik.gradient(branch=True, Q=True)
     assert rel(logL, O.log_likelihood(prob)) <= TOL_LOGL["fp32"]
     ref_b, ref_q = O.gradient(prob)
-    assert grad_rel(db, ref_b) <= TOL_GRAD["fp32"], grad_rel(db, ref_b)
-    assert grad_rel(dq, ref_q) <= TOL_GRAD["fp32"], grad_rel(dq, ref_q)
+    assert_grad(db, ref_b, TOL_GRAD["fp32"])
+    assert_grad(dq, ref_q, TOL_GRAD["fp32"])
 
 
 def _pattern_subset(prob, idx):
