@@ -295,7 +295,7 @@ int epoch_create(const EpochConfig* cfg, EpochInstance** out) {
   A(in->eig64, (2 * S * KK + 2 * S * Kp) * sizeof(double));
   A(in->eigTT, 2 * S * KK * R);
   A(in->eig64T, 2 * S * KK * sizeof(double));
-  A(in->check, (KK + 8) * sizeof(double));
+  A(in->check, (KK + 1 + 3 * (size_t)eigen_check_tiles(in->K)) * sizeof(double));  // Q, residual, tile maxima
   A(in->tips, N * P);
   A(in->weights, P * sizeof(double));
   A(in->weightsT, P * R);
@@ -605,9 +605,8 @@ int set_epoch_eigensystems(EpochInstance* in, int32_t s, const double* V, const 
     double* dout = dQ + (size_t)Kp * Kp;
     EPOCH_TRY(upload(in, dQ, Q, (size_t)K * K * sizeof(double)));
     EPOCH_TRY(launch_eigen_check(in, s, dQ, dout));
-    double r[3];
-    EPOCH_TRY(download(in, r, dout, sizeof(r)));
-    const double res = std::max(r[2] > 0 ? r[0] / r[2] : r[0], r[1]);
+    double res = 0.0;
+    EPOCH_TRY(download(in, &res, dout, sizeof(res)));
     if (residual_out) *residual_out = res;
     if (!(res <= 1e-8)) {
       set_error(EPOCH_WARN_EIGEN_RESIDUAL, "eigensystem %d reconstruction residual %.3g", s, res);

@@ -210,7 +210,12 @@ int hip_check(hipError_t e, const char* what);
 int ensure(DevBuf& b, size_t bytes);
 
 // kernel launchers (kernels_generic.hip); all return EPOCH_OK or an error code
+// FP64 eigensystem check (kernels_eigcheck.hip): d_out[0] receives the residual, scratch follows it
 int launch_eigen_check(EpochInstance* in, int s, const double* dQ, double* d_out);
+int eigen_check_tiles(int K);  // scratch rows (3 doubles each) per system
+int launch_eigen_check_n(hipStream_t st, int K, int n, int ld, long mat_stride, int vec_stride, const double* V,
+                         const double* Vi, const double* lr, const double* li, const double* Q, double* part,
+                         double* out);
 int launch_pstage_generic(EpochInstance* in);
 int launch_pstage_mfma(EpochInstance* in);
 bool pstage_mfma_supported(const EpochInstance* in);

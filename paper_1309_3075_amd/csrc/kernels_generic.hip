@@ -489,46 +489,6 @@ __global__ __launch_bounds__(256) void grad_reduce_branch_kernel(
 // ---------------------------------------------------------------------------
 // FP64 eigen check: max|V B V^-1 - Q| / max|Q| and max|V V^-1 - I|.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void eigen_check_kernel(const double* __restrict__ V,
-                                                          const double* __restrict__ Vi,
-                                                          const double* __restrict__ lr,
-                                                          const double* __restrict__ li,
-                                                          const double* __restrict__ Q, int K,
-                                                          int Kp, double* __restrict__ out) {
-  __shared__ double sm[256];
-  double r1 = 0.0, r2 = 0.0, qmax = 0.0;
-  for (int e = threadIdx.x; e < K * K; e += 256) {
-    const int i = e / K, j = e % K;
-    double rec = 0.0, id = 0.0;
-    for (int l = 0; l < K; ++l) {
-      double vb;
-      const double b = li[l];
-      if (b == 0.0)
-        vb = V[i * Kp + l] * lr[l];
-      else if (b > 0.0)
-        vb = V[i * Kp + l] * lr[l] - V[i * Kp + l + 1] * b;   // column l of V B
-      else
-        vb = -V[i * Kp + l - 1] * b + V[i * Kp + l] * lr[l];  // column l (second of the pair)
-      rec += vb * Vi[l * Kp + j];
-      id += V[i * Kp + l] * Vi[l * Kp + j];
-    }
-    r1 = fmax(r1, fabs(rec - Q[i * K + j]));
-    r2 = fmax(r2, fabs(id - (i == j ? 1.0 : 0.0)));
-    qmax = fmax(qmax, fabs(Q[i * K + j]));
-  }
-  // block max reductions (fixed order)
-  double vals[3] = {r1, r2, qmax};
-  for (int q = 0; q < 3; ++q) {
-    sm[threadIdx.x] = vals[q];
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if (threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) out[q] = sm[0];
-    __syncthreads();
-  }
-}
 
 template <typename T>
 const T* eigT_ptr(EpochInstance* in, int which) {
@@ -728,17 +688,6 @@ int grad_reduce_dispatch(EpochInstance* in, int n_slots, const int32_t* chunks_p
 
 }  // namespace
 
-int launch_eigen_check(EpochInstance* in, int s, const double* dQ, double* d_out) {
-  const size_t KK = (size_t)in->Kp * in->Kp;
-  const double* base = static_cast<const double*>(in->eig64.ptr);
-  const double* V = base + s * KK;
-  const double* Vi = base + in->S * KK + s * KK;
-  const double* lr = base + 2 * in->S * KK + (size_t)s * in->Kp;
-  const double* li = base + 2 * in->S * KK + (size_t)in->S * in->Kp + (size_t)s * in->Kp;
-  hipLaunchKernelGGL(eigen_check_kernel, dim3(1), dim3(256), 0, in->stream, V, Vi, lr, li, dQ,
-                     in->K, in->Kp, d_out);
-  return hip_check(hipGetLastError(), "eigen_check launch");
-}
 
 int launch_final_sum(EpochInstance* in, int n_blocks) {
   hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(256), 0, in->stream,
