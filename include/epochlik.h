@@ -32,7 +32,8 @@
  *
  * Ownership: every host pointer is borrowed for the duration of the call and
  * copied; the library owns all device memory it allocates.  Device pointers
- * are never taken or returned.  An instance is
+ * are never taken or returned, except by epoch_eigen_residual_noalloc, which
+ * works on caller-owned device memory only.  An instance is
  * not thread-safe; distinct instances are independent.  All device work runs
  * on the stream given in EpochConfig (NULL = the default stream); calls that
  * return host results synchronise that stream.
@@ -303,6 +304,29 @@ int epoch_batch_destroy(EpochBatch* batch);
  * (counts read + write bytes), 1 = read-only, 2 = write-only.  *gbs receives
  * GB/s (1e9 bytes per second).  Allocates and frees its own buffers. */
 int epoch_bandwidth_probe(int64_t bytes, int32_t kind, int32_t iters, double* gbs);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the FP64 eigensystem
+ * check of set_epoch_eigensystems, for n_systems eigensystems at once, on device
+ * memory the caller owns.  It calls no allocating routine and does not
+ * synchronise: the kernels are enqueued on `stream` (a hipStream_t of the current
+ * device, NULL = the default stream) and the residuals are ready when it completes.
+ *   n_states K in [2, 64]; n_systems >= 1.
+ *   V, Vinv: device [n_systems][K][K] row-major doubles; lambda_re: device
+ *   [n_systems][K]; lambda_im: device [n_systems][K] or NULL (all real), complex
+ *   pairs laid out as in set_epoch_eigensystems; Q: device [n_systems][K][K].
+ *   residual: device [n_systems] out: max(max|V B V^-1 - Q| / max|Q|, max|V V^-1 - I|)
+ *   per system, the value set_epoch_eigensystems reports for the same columns.
+ * Every pointer must be device memory of the current device (EPOCH_ERR_ARG
+ * otherwise, checked before any launch).  The per-tile maxima live in a fixed
+ * 1 MiB device array per GPU (131072 doubles; a system of K states takes
+ * 3 * ceil(K/16)^2 of them): more systems than fit in one call -> EPOCH_ERR_ARG.
+ * Every row of that array a call reads is written by the same call first, so
+ * nothing needs clearing; calls that overlap on one GPU (concurrent streams or
+ * threads) share the array and race. */
+int epoch_eigen_residual_noalloc(int32_t n_states, int32_t n_systems, const double* V, const double* Vinv,
+                                 const double* lambda_re, const double* lambda_im, const double* Q,
+                                 double* residual, void* stream);
 
 /* Host planner only (no device work, usable without a GPU): the per-interval
  * segments of every branch, parent side first.

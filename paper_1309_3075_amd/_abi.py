@@ -38,6 +38,7 @@ EXPORTED = [
     "epoch_plan_segments", "epoch_set_timing", "epoch_get_timing", "epoch_bandwidth_probe",
     "epoch_batch_create", "epoch_batch_evaluate", "epoch_batch_gradients", "epoch_batch_target_blocks",
     "epoch_batch_destroy", "epoch_set_option", "epoch_plan_walk", "epoch_workspace_bytes",
+    "epoch_eigen_residual_noalloc",
 ]
 EPOCH_EVAL_LOGL = 0x1
 EPOCH_EVAL_GRAD_BRANCH = 0x2
@@ -117,6 +118,7 @@ def load() -> ctypes.CDLL:
         "epoch_set_option": (i32, [P, i32, ctypes.c_int64]),
         "epoch_workspace_bytes": (i32, [ctypes.POINTER(EpochConfig), ctypes.POINTER(ctypes.c_int64)]),
         "epoch_plan_walk": (i32, [i32, ip, dp, i32, i32, ip, ip]),
+        "epoch_eigen_residual_noalloc": (i32, [i32, i32, P, P, P, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

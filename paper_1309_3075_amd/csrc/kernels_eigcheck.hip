@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "instance.h"
 
@@ -137,4 +138,82 @@ int launch_eigen_check(EpochInstance* in, int s, const double* dQ, double* d_out
   return launch_eigen_check_n(in->stream, in->K, 1, in->Kp, (long)KK, in->Kp, V, Vi, lr, li, dQ, d_out + 1, d_out);
 }
 
+// ---- The check without allocation (epoch_eigen_residual_noalloc) ---------------------------
+// The tile maxima live in a file-scope device array instead of library-allocated memory.  In
+// host code `scratch` names a host-side stand-in, not device memory: the device address of each
+// GPU's copy comes from hipGetSymbolAddress, taken once per device with that device current,
+// and only that address is handed to kernels.
+namespace {
+
+constexpr size_t kNoAllocScratchDoubles = 131072;  // 1 MiB per device
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
+constexpr int kNoAllocMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+int scratch_address(int device, double** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const int rc = hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (rc) return rc;
+    if (!p) return set_error(EPOCH_ERR_HIP, "hipGetSymbolAddress(scratch) returned a null address");
+    g_scratch_ptr[device] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[device];
+  return EPOCH_OK;
+}
+
+// The pointer must be device memory of the current device (a host pointer would fault the GPU).
+int check_device_pointer(const void* p, int device, const char* name) {
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error(EPOCH_ERR_ARG, "%s is not device memory", name);
+  }
+  if (attr.type != hipMemoryTypeDevice || attr.device != device)
+    return set_error(EPOCH_ERR_ARG, "%s is not device memory of the current device", name);
+  return EPOCH_OK;
+}
+
+}  // namespace
 }  // namespace epochlik
+
+using namespace epochlik;
+
+extern "C" int epoch_eigen_residual_noalloc(int32_t n_states, int32_t n_systems, const double* V,
+                                            const double* Vinv, const double* lambda_re,
+                                            const double* lambda_im, const double* Q, double* residual,
+                                            void* stream) {
+  if (n_states < 2 || n_states > 64) return set_error(EPOCH_ERR_ARG, "n_states must be in [2, 64] (got %d)", n_states);
+  if (n_systems < 1) return set_error(EPOCH_ERR_ARG, "n_systems must be >= 1 (got %d)", n_systems);
+  if (!V || !Vinv || !lambda_re || !Q || !residual)
+    return set_error(EPOCH_ERR_ARG, "V, Vinv, lambda_re, Q and residual must not be NULL");
+  const size_t per_system = 3 * (size_t)eigen_check_tiles(n_states);
+  if ((size_t)n_systems * per_system > kNoAllocScratchDoubles)
+    return set_error(EPOCH_ERR_ARG,
+                     "%d systems of %d states need %zu scratch doubles; the fixed scratch holds %zu "
+                     "(at most %zu systems of this size per call)",
+                     n_systems, n_states, (size_t)n_systems * per_system, kNoAllocScratchDoubles,
+                     kNoAllocScratchDoubles / per_system);
+  int device = 0;
+  int rc = hip_check(hipGetDevice(&device), "hipGetDevice");
+  if (rc) return rc;
+  if (device < 0 || device >= kNoAllocMaxDevices)
+    return set_error(EPOCH_ERR_ARG, "device %d beyond the %d devices this entry point serves", device,
+                     kNoAllocMaxDevices);
+  const void* ptrs[] = {V, Vinv, lambda_re, Q, residual, lambda_im};
+  const char* names[] = {"V", "Vinv", "lambda_re", "Q", "residual", "lambda_im"};
+  for (int k = 0; k < 6; ++k) {
+    if (!ptrs[k]) continue;
+    rc = check_device_pointer(ptrs[k], device, names[k]);
+    if (rc) return rc;
+  }
+  double* part = nullptr;
+  rc = scratch_address(device, &part);
+  if (rc) return rc;
+  const long KK = (long)n_states * n_states;
+  return launch_eigen_check_n(static_cast<hipStream_t>(stream), n_states, n_systems, n_states, KK, n_states, V, Vinv,
+                              lambda_re, lambda_im, Q, part, residual);
+}
