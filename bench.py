@@ -1,17 +1,24 @@
 """Benchmark: logL + gradient evaluations per second on one MI355X.
 
-Default workload: GTR 4-state model, 3 epochs, 512-taxon coalescent tree,
+Headline workload: GTR 4-state model, 3 epochs, 512-taxon coalescent tree,
 100,000 site patterns simulated under the epoch model, 4 discrete-gamma
 categories; one step = transition matrices + post-order partials + root
 log-likelihood + pre-order adjoint with all 1,022 branch-length gradients,
 in FP32 with FP64 reductions.  Inputs are resident on the device before the
 timed region; the step returns logL and the gradient to the host.
 
-Prints one JSON line (see the design doc for the roofline accounting).
+The same JSON line also carries the metric's other legs, each timed here:
+the same workload in FP64 (fast kernels and the plain generic FP64 kernels),
+the 128-taxon GY94 codon workload and the 64-problem batched codon workload,
+each with its own roofline, and the FP64 oracle timed on one host core and on
+all of them.  `--config N` benchmarks one workload alone.
+
+Prints one JSON line (the design doc gives the roofline accounting).
 """
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -40,19 +47,22 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def padded(K):
+    return 4 if K <= 4 else (8 if K <= 8 else (K + 15) // 16 * 16)
+
+
 def algorithmic_bytes(prob, precision):
     """Algorithmic HBM bytes of one evaluation, per phase."""
     N = prob.n_tips
     P = prob.n_patterns
     C = len(prob.cat_rates)
-    K = prob.n_states
-    Kp = 4 if K <= 4 else (8 if K <= 8 else (K + 15) // 16 * 16)
+    Kp = padded(prob.n_states)
     b = 8 if precision == "fp64" else 4
     V = P * C * Kp * b          # one partial (or outside) vector set of a node
     T = P                       # u8 tip states of one tip
     s = 4 * P                   # int32 cumulative scale exponents of one node
-    post = (2 * N - 3) * V + N * T + (2 * N - 3) * s   # write N-1, read N-2 internal children
-    pre = (3 * N - 6) * V + N * T                          # read q_u (N-2), read internal p (N-2), write q (N-2)
+    post = (2 * N - 3) * V + N * T + 2 * (N - 1) * s   # write N-1, read N-2 internal children; scales
+    pre = (3 * N - 6) * V + N * T + 2 * (N - 2) * s     # read q_u, read internal p, write q; scales
     return {"post_order": post, "pre_order_dP": pre}
 
 
@@ -64,8 +74,7 @@ def algorithmic_flops(prob):
     (6K^3) per segment term (W = R V^-T, Y = U^T W, the update of R); padding never counted."""
     from paper_1309_3075_amd import _abi  # the library's host planner gives the segment counts
     N, P, K, C = prob.n_tips, prob.n_patterns, prob.n_states, len(prob.cat_rates)
-    n_int_children = N - 2
-    post = n_int_children * 2 * K * K * P * C
+    post = (N - 2) * 2 * K * K * P * C
     pre = 2 * (N - 2) * 2 * K * K * P * C
     off, _, _ = _abi.plan_segments(prob.parent, prob.height, prob.boundaries, prob.interval_process,
                                    prob.n_processes)
@@ -110,73 +119,256 @@ def committed_traffic(name, kernel):
         return None
 
 
-def run_cpu_baseline(prob, sample_patterns, want_Q, want_grad=True):
-    """The FP64 oracle on a pattern subsample, scaled to evaluations/s of the full problem."""
-    import copy
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def host_threads():
+    """Threads the host offers this process (the GPU machine limits it through OMP_NUM_THREADS)."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS")
+    return min(avail, int(env)) if env and env.isdigit() else avail
+
+
+def oracle_timed(prob, want_grad, want_Q, threads):
     from threadpoolctl import threadpool_limits
 
     from oracle import epoch_oracle as O
-    sub = copy.copy(prob)
-    sub.tips = prob.tips[:, :sample_patterns].copy()
-    sub.weights = prob.weights[:sample_patterns].copy()
-    with threadpool_limits(limits=1):
+    with threadpool_limits(limits=threads):
         t0 = time.perf_counter()
-        logL = O.log_likelihood(sub)
-        d_branch, d_Q = (O.gradient(sub, wrt=("branch", "Q") if want_Q else ("branch",)) if want_grad
+        logL = O.log_likelihood(prob)
+        d_branch, d_Q = (O.gradient(prob, wrt=("branch", "Q") if want_Q else ("branch",)) if want_grad
                          else (None, None))
         dt = time.perf_counter() - t0
-    full = dt * prob.n_patterns / sample_patterns
+    return logL, d_branch, d_Q, dt
+
+
+def pattern_subset(prob, n):
+    import copy
+    sub = copy.copy(prob)
+    sub.tips = prob.tips[:, :n].copy()
+    sub.weights = prob.weights[:n].copy()
+    return sub
+
+
+def _oracle_chunk(job):
+    """One worker's share of the all-cores oracle timing: the oracle, unchanged, on a slice of
+    the patterns (sites are independent given the tree, so the slices' results add up)."""
+    prob, lo, hi, want_grad, want_Q = job
+    import copy
+    sub = copy.copy(prob)
+    sub.tips = prob.tips[:, lo:hi].copy()
+    sub.weights = prob.weights[lo:hi].copy()
+    logL, d_branch, d_Q, _ = oracle_timed(sub, want_grad, want_Q, 1)
+    return logL, d_branch, d_Q
+
+
+def oracle_all_cores(sub, want_grad, want_Q, n_workers):
+    """Wall time of the oracle over the sample split into n_workers pattern slices run by as many
+    processes (one BLAS thread each); the pool is started before the clock."""
+    import multiprocessing
+    from concurrent.futures import ProcessPoolExecutor
+    P = sub.n_patterns
+    cuts = [P * k // n_workers for k in range(n_workers + 1)]
+    jobs = [(sub, cuts[k], cuts[k + 1], want_grad, want_Q) for k in range(n_workers) if cuts[k + 1] > cuts[k]]
+    with ProcessPoolExecutor(max_workers=len(jobs), mp_context=multiprocessing.get_context("spawn")) as ex:
+        list(ex.map(_oracle_chunk, [(pattern_subset(sub, 1), 0, 1, False, False)] * len(jobs)))  # start-up
+        t0 = time.perf_counter()
+        parts = list(ex.map(_oracle_chunk, jobs))
+        dt = time.perf_counter() - t0
+    logL = sum(p[0] for p in parts)
+    return logL, dt
+
+
+def run_cpu_baseline(prob, sample_patterns, want_Q, want_grad=True):
+    """The FP64 oracle on a pattern subsample, on one host thread and on every thread the host
+    offers (one process per pattern slice), scaled to evaluations/s of the full problem (linear
+    in patterns)."""
+    sub = pattern_subset(prob, sample_patterns)
+    logL, d_branch, d_Q, dt1 = oracle_timed(sub, want_grad, want_Q, 1)
+    n_all = host_threads()
+    logL_all, dtn = oracle_all_cores(sub, want_grad, want_Q, n_all)
+    assert abs(logL_all - logL) <= 1e-9 * abs(logL), (logL_all, logL)
+    scale = prob.n_patterns / sample_patterns
+    sample = (f"{sample_patterns} of {prob.n_patterns} patterns, full tree; scaled linearly in patterns "
+              f"(FP64 numpy/scipy oracle)")
     return sub, logL, d_branch, d_Q, {
-        "value": 1.0 / full, "unit": "evals/s", "cores": 1, "kind": "oracle",
-        "sample": f"{sample_patterns} of {prob.n_patterns} patterns, full tree; {dt:.2f} s measured, "
-                  f"scaled linearly in patterns (FP64 numpy/scipy, 1 BLAS thread)"}
+        "value": 1.0 / (dt1 * scale), "unit": "evals/s", "cores": 1, "kind": "oracle",
+        "sample": sample + f"; {dt1:.2f} s measured on 1 thread",
+        "all_cores": {"value": 1.0 / (dtn * scale), "cores": n_all, "seconds_measured": round(dtn, 3),
+                      "how": f"{n_all} processes, one pattern slice and one BLAS thread each"},
+        "nproc": os.cpu_count(), "cpu_model": cpu_model()}
 
 
-def run_batch(args):
+def time_instance(lik, steps, warmup, want_grad, want_Q):
+    """Evaluations/s of one instance through epoch_evaluate, with per-phase device times."""
+    import torch
+
+    def step():
+        lL, _, db, dq = lik.evaluate(branch=want_grad, Q=want_Q)
+        return lL, db, dq
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    lik.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    phases = lik.timing()
+    lik.set_timing(False)
+    return steps / wall, wall * 1000.0 / steps, phases, out
+
+
+def roofline(prob, precision, kernel, phases, steps, want_Q, config, traffic_ok):
+    """Roofline of the phase with the largest device time."""
+    abytes = algorithmic_bytes(prob, precision)
+    aflops = algorithmic_flops(prob)
+    dom = max(("post_order", "pre_order_dP", "transition_matrices") + (("grad_Q",) if want_Q else ()),
+              key=lambda k: phases[k][0])
+    dom_ms = phases[dom][0] / steps
+    path = ("nuc" if prob.n_states == 4 else ("codon" if prob.n_states > 48 and precision == "fp32"
+                                               and len(prob.cat_rates) == 1 else "generic"))
+    if kernel == "generic":
+        path = "generic"
+    cp = 1 if len(prob.cat_rates) <= 1 else (2 if len(prob.cat_rates) <= 2 else (4 if len(prob.cat_rates) <= 4 else 8))
+    walk = precision == "fp32" and -(-prob.n_patterns // (64 // cp)) <= 1024
+    names = {"nuc": {"post_order": "nuc_walk_mfma (post-order program)" if walk else "nuc_post_level",
+                     "pre_order_dP": "nuc_walk_mfma (pre-order program)" if walk else "nuc_pre_level"},
+             "codon": {"post_order": "codon_post_level", "pre_order_dP": "codon_pre_level + codon_pre_split"},
+             "generic": {"post_order": "post_level_generic", "pre_order_dP": "pre_level_generic + grad_G_generic"}}
+    mfma_pstage = kernel == "auto" and padded(prob.n_states) >= 16
+    if dom == "grad_Q":
+        kname = "qgrad_chain + qgrad_h + qgrad_final" if mfma_pstage else "qgrad_segments + qgrad_reduce"
+    else:
+        kname = names[path].get(dom, "pstage_mfma (+ split-chain combine)" if mfma_pstage else "pstage_generic")
+    if path == "codon" or dom in ("transition_matrices", "grad_Q"):
+        achieved = aflops[dom] / (dom_ms * 1e-3) / 1e12
+        # the chains run in FP64 when the instance forms exp(tQ) in FP64 (ill-conditioned eigenvectors)
+        peak = FP64_PEAK_TFLOPS if (precision == "fp64" or dom in ("transition_matrices", "grad_Q")
+                                    and fp64_reconstruction(prob, config != 4)) else FP32_PEAK_TFLOPS
+        return {"bound": "mfma", "kernel": kname, "achieved": round(achieved, 3), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "algorithmic_flops_per_eval": aflops[dom], "ms_per_eval": round(dom_ms, 4),
+                "hbm_GBps_algorithmic_same_kernel": round(abytes.get(dom, 0) / (dom_ms * 1e-3) / 1e9, 1)}
+    achieved = abytes[dom] / (dom_ms * 1e-3) / 1e9
+    traffic = None
+    if traffic_ok and path == "nuc" and precision == "fp32" and config == 2 and not walk:
+        traffic = committed_traffic("nuc_C2_hbm_traffic.txt", kname)
+    r = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+         "traffic_unit": "bytes per evaluation (all launches of the kernel)",
+         "achieved_is": "algorithmic bytes / kernel time",
+         "algorithmic_bytes_per_eval": abytes[dom], "ms_per_eval": round(dom_ms, 4)}
+    if traffic:
+        r["counter_GBps"] = round(traffic / (dom_ms * 1e-3) / 1e9, 1)
+        r["counter_frac"] = round(traffic / (dom_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    return r
+
+
+def gpu_parity(sub, precision, kernel, use_pi, ref_logL, ref_b, ref_q, want_grad, want_Q):
+    from paper_1309_3075_amd.likelihood import from_problem
+    with from_problem(sub, precision, grad_branch=want_grad, grad_Q=want_Q, kernel=kernel, use_pi=use_pi) as small:
+        g_logL, _, g_b, g_q = small.evaluate(branch=want_grad, Q=want_Q)
+    out = {"sample_patterns": sub.n_patterns, "logL_rel_err": abs(g_logL - ref_logL) / abs(ref_logL)}
+    for key, g, r in (("grad_branch", g_b, ref_b), ("grad_Q", g_q, ref_q)):
+        if g is None or r is None:
+            continue
+        err = np.abs(g - r).ravel()
+        floor = 1e-3 * np.abs(r).max()
+        out[f"{key}_rel_err"] = float(np.linalg.norm(g - r) / np.linalg.norm(r))
+        out[f"{key}_max_componentwise"] = float(np.max(err / np.maximum(np.abs(r).ravel(), floor)))
+    return out
+
+
+def run_codon_leg(steps, warmup, with_parity):
+    """The 128-taxon GY94 codon workload (FP32, branch and rate-matrix gradients)."""
+    from paper_1309_3075_amd import workloads as W
+    from paper_1309_3075_amd.likelihood import from_problem
+    prob = W.make_config(3)
+    lik = from_problem(prob, "fp32", grad_branch=True, grad_Q=True)
+    eps, ms, phases, _ = time_instance(lik, steps, warmup, True, True)
+    lik.close()
+    aflops = algorithmic_flops(prob)
+    total = sum(aflops.values())
+    leg = {"workload": WORKLOADS[3], "evals_per_s": round(eps, 2), "ms_per_eval": round(ms, 4),
+           "roofline": roofline(prob, "fp32", "auto", phases, steps, True, 3, False),
+           "whole_eval_TFLOPs": round(total / (ms * 1e-3) / 1e12, 3),
+           "whole_eval_frac_fp32_peak": round(total / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4),
+           "phases_ms_per_eval": {k: round(v[0] / steps, 4) for k, v in phases.items()}}
+    if with_parity:
+        sub = pattern_subset(prob, 1000)
+        ref_logL, ref_b, ref_q, _ = oracle_timed(sub, True, True, host_threads())
+        leg["parity_vs_oracle"] = gpu_parity(sub, "fp32", "auto", True, ref_logL, ref_b, ref_q, True, True)
+    return leg
+
+
+def run_batch_leg(n, scale, steps, warmup, precision="fp32", grad_q=False, tune=None):
     """Batched codon workload: independent 64-state problems in one replayed HIP graph."""
     import torch
-    from paper_1309_3075_amd import _abi
     from paper_1309_3075_amd import workloads as W
     from paper_1309_3075_amd.likelihood import EpochBatchEvaluator, from_problem
 
-    n = args.batch or 64
     log(f"bench: generating {n} batched codon problems ...")
     t0 = time.perf_counter()
-    probs = W.make_batch(n, scale=args.batch_scale)
+    probs = W.make_batch(n, scale=scale)
     log(f"bench: generated in {time.perf_counter() - t0:.1f} s; patterns {sum(p.n_patterns for p in probs)}")
-    members = [from_problem(p, args.precision, grad_branch=True, grad_Q=args.grad_q) for p in probs]
-    tune = os.path.join(ROOT, "paper_1309_3075_amd", "tune_cache.json")
+    members = [from_problem(p, precision, grad_branch=True, grad_Q=grad_q) for p in probs]
     batch = EpochBatchEvaluator(members, tune_cache=tune)
-    for _ in range(args.warmup):
-        batch.evaluate(grad_branch=True, grad_Q=args.grad_q)
+    for _ in range(warmup):
+        batch.evaluate(grad_branch=True, grad_Q=grad_q)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        logL = batch.evaluate(grad_branch=True, grad_Q=args.grad_q)
+    for _ in range(steps):
+        logL = batch.evaluate(grad_branch=True, grad_Q=grad_q)
     wall = time.perf_counter() - t0
-    ms = wall * 1000 / args.steps
-    flops = sum(sum(v for k, v in algorithmic_flops(p).items()) for p in probs)
+    ms = wall * 1000 / steps
+    flops = 0
+    for p in probs:
+        f = algorithmic_flops(p)
+        flops += f["post_order"] + f["pre_order_dP"] + f["transition_matrices"] + (f["grad_Q"] if grad_q else 0)
     achieved = flops / (ms * 1e-3) / 1e12
-    result = {
-        "metric": "logL+gradient evals/sec", "value": round(n * args.steps / wall, 3), "unit": "evals/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp32" else "f64",
-        "data": "synthetic (seeded coalescent trees, codon patterns simulated under the epoch model)",
-        "config": {"workload": f"{n} batched GY94 codon problems (61 states padded to 64, 4 epochs), "
-                               f"64-256 taxa and 1000-20000 patterns each (x{args.batch_scale}), one replayed "
-                               "hipGraph per step, logL + branch gradients",
-                   "config_index": 5, "n_problems": n, "precision": args.precision,
-                   "tuned_target_blocks": batch.target_blocks()},
-        "roofline": {"bound": "mfma", "kernel": "whole batched graph (codon_post/pre_level dominant)",
-                     "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None,
-                     "algorithmic_flops_per_step": flops},
-        "logL_first": float(logL[0]),
-    }
+    leg = {"workload": f"{n} batched GY94 codon problems (61 states padded to 64, 4 epochs), 64-256 taxa and "
+                       f"1000-20000 patterns each (x{scale}), one replayed hipGraph per step, logL + branch gradients"
+                       + (" + rate-matrix gradients" if grad_q else ""),
+           "problems_per_s": round(n * steps / wall, 3), "ms_per_batch": round(ms, 4),
+           "tuned_target_blocks": batch.target_blocks(),
+           "roofline": {"bound": "mfma", "kernel": "whole batched graph (codon_post/pre_level dominant)",
+                        "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                        "algorithmic_flops_per_batch": flops},
+           "logL_first": float(logL[0])}
     batch.close()
     for m in members:
         m.close()
+    return leg
+
+
+def run_batch(args):
+    leg = run_batch_leg(args.batch or 64, args.batch_scale, args.steps, args.warmup, args.precision, args.grad_q,
+                        os.path.join(ROOT, "paper_1309_3075_amd", "tune_cache.json"))
+    result = {
+        "metric": "logL+gradient evals/sec", "value": leg["problems_per_s"], "unit": "evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": leg["ms_per_batch"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "data": "synthetic (seeded coalescent trees, codon patterns simulated under the epoch model)",
+        "config": {"workload": leg["workload"], "config_index": 5, "n_problems": args.batch or 64,
+                   "precision": args.precision, "tuned_target_blocks": leg["tuned_target_blocks"]},
+        "roofline": leg["roofline"], "logL_first": leg["logL_first"],
+    }
     print(json.dumps(result), flush=True)
 
 
@@ -185,7 +377,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--config", type=int, default=None,
+                    help="benchmark one workload alone (1-5); default: the headline workload with every leg")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--kernel", default="auto", choices=["auto", "generic"])
     ap.add_argument("--patterns", type=int, default=None, help="override the pattern count")
@@ -206,85 +399,27 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    if args.config == 5:
+    headline = args.config is None
+    config = 2 if headline else args.config
+    if config == 5:
         return run_batch(args)
-    want_Q = args.grad_q or args.config in (3, 4)
-    want_grad = args.config != 1  # the 16-taxon workload is a plain log-likelihood
-    log(f"bench: generating config C{args.config} ...")
+    want_Q = args.grad_q or config in (3, 4)
+    want_grad = config != 1  # the 16-taxon workload is a plain log-likelihood
+    use_pi = config != 4
+    log(f"bench: generating config C{config} ...")
     t0 = time.perf_counter()
-    prob = W.make_config(args.config, n_patterns=args.patterns)
+    prob = W.make_config(config, n_patterns=args.patterns)
     log(f"bench: generated in {time.perf_counter() - t0:.1f} s: N={prob.n_tips} P={prob.n_patterns} "
         f"K={prob.n_states} C={len(prob.cat_rates)} S={prob.n_processes} M={prob.n_intervals}")
     lik = from_problem(prob, args.precision, grad_branch=want_grad, grad_Q=want_Q, kernel=args.kernel,
-                       use_pi=args.config != 4)
-
-    def step():
-        # the whole path (P stage, pruning, root log-likelihood, gradients) with one host sync
-        lL, _, db, dq = lik.evaluate(branch=want_grad, Q=want_Q)
-        return lL, db, dq
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    log("bench: warmup done")
-    lik.set_timing(True)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record()
-    for _ in range(args.steps):
-        logL, db, dq = step()
-    ev1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    phases = lik.timing()
-    ms_per_step = wall * 1000.0 / args.steps
-    value = args.steps / wall
+                       use_pi=use_pi)
+    # the timed region: K whole evaluations, each with one host synchronisation
+    value, ms_per_step, phases, (logL, _, _) = time_instance(lik, args.steps, args.warmup, want_grad, want_Q)
     log(f"bench: {ms_per_step:.3f} ms/step, phases {phases}")
-
+    lik.close()
+    roof = roofline(prob, args.precision, args.kernel, phases, args.steps, want_Q, config,
+                    args.patterns is None)
     abytes = algorithmic_bytes(prob, args.precision)
-    aflops = algorithmic_flops(prob)
-    # dominant kernel: the phase with the largest device time
-    dom = max(("post_order", "pre_order_dP", "transition_matrices") + (("grad_Q",) if want_Q else ()),
-              key=lambda k: phases[k][0])
-    dom_ms = phases[dom][0] / args.steps
-    path = ("nuc" if prob.n_states == 4 else ("codon" if prob.n_states > 48 and args.precision == "fp32"
-                                               and len(prob.cat_rates) == 1 else "generic"))
-    if args.kernel == "generic":
-        path = "generic"
-    # the library takes the tree walk for FP32 4-state instances of at most 1024 tiles of 16 patterns
-    cp = 1 if len(prob.cat_rates) <= 1 else (2 if len(prob.cat_rates) <= 2 else (4 if len(prob.cat_rates) <= 4 else 8))
-    walk = args.precision == "fp32" and -(-prob.n_patterns // (64 // cp)) <= 1024
-    names = {"nuc": {"post_order": "nuc_walk_mfma (post-order program)" if walk else "nuc_post_level",
-                     "pre_order_dP": "nuc_walk_mfma (pre-order program)" if walk else "nuc_pre_level"},
-             "codon": {"post_order": "codon_post_level", "pre_order_dP": "codon_pre_level + codon_pre_split"},
-             "generic": {"post_order": "post_level_generic", "pre_order_dP": "pre_level_generic + grad_G_generic"}}
-    Kp = 4 if prob.n_states <= 4 else (8 if prob.n_states <= 8 else (prob.n_states + 15) // 16 * 16)
-    mfma_pstage = args.kernel == "auto" and Kp >= 16
-    if dom == "grad_Q":
-        kname = "qgrad_chain + qgrad_h + qgrad_final" if mfma_pstage else "qgrad_segments + qgrad_reduce"
-    else:
-        kname = names[path].get(dom, "pstage_mfma (+ split-chain combine)" if mfma_pstage else "pstage_generic")
-    if path == "codon" or dom in ("transition_matrices", "grad_Q"):
-        achieved = aflops[dom] / (dom_ms * 1e-3) / 1e12
-        # the chains run in FP64 when the instance forms exp(tQ) in FP64 (ill-conditioned eigenvectors)
-        peak = FP64_PEAK_TFLOPS if (args.precision == "fp64" or dom in ("transition_matrices", "grad_Q")
-                                    and fp64_reconstruction(prob, args.config != 4)) \
-            else FP32_PEAK_TFLOPS
-        roofline = {"bound": "mfma", "kernel": kname, "achieved": round(achieved, 3), "peak": peak,
-                    "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
-                    "algorithmic_flops_per_eval": aflops[dom], "ms_per_eval": round(dom_ms, 4),
-                    "hbm_GBps_same_kernel": round(abytes.get(dom, 0) / (dom_ms * 1e-3) / 1e9, 1)}
-    else:
-        achieved = abytes[dom] / (dom_ms * 1e-3) / 1e9
-        traffic = None
-        if path == "nuc" and args.precision == "fp32" and args.config == 2 and args.patterns is None:
-            traffic = committed_traffic("nuc_C2_hbm_traffic.txt", kname)
-        roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                    "traffic_unit": "bytes per evaluation (all launches of the kernel)",
-                    "algorithmic_bytes_per_eval": abytes[dom], "ms_per_eval": round(dom_ms, 4)}
-    total_bytes = sum(abytes.values())
     result = {
         "metric": "logL+gradient evals/sec" if want_grad else "logL evals/sec", "value": round(value, 3),
         "unit": "evals/s", "n_gpus": 1,
@@ -292,12 +427,12 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if args.precision == "fp32" else "f64",
         "data": "synthetic (seeded coalescent tree, patterns simulated under the epoch model)",
-        "config": {"workload": WORKLOADS[args.config], "config_index": args.config, "n_tips": prob.n_tips,
+        "config": {"workload": WORKLOADS[config], "config_index": config, "n_tips": prob.n_tips,
                    "n_patterns": prob.n_patterns, "n_states": prob.n_states,
                    "n_categories": len(prob.cat_rates), "precision": args.precision, "kernel": args.kernel,
                    "grad_Q": want_Q},
-        "roofline": roofline,
-        "whole_step_hbm_fraction": round(total_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "roofline": roof,
+        "whole_step_hbm_fraction": round(sum(abytes.values()) / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "phases_ms_per_eval": {k: round(v[0] / args.steps, 4) for k, v in phases.items()},
         "logL": logL,
     }
@@ -305,29 +440,41 @@ def main():
     from paper_1309_3075_amd import _abi
     probe = {k: round(_abi.bandwidth_probe(1 << 31, k, 20), 1) for k in ("copy", "read", "write")}
     result["measured_hbm_GBps"] = probe
-    if result["roofline"]["unit"] == "GB/s":
-        result["roofline"]["frac_of_measured_copy"] = round(achieved / probe["copy"], 4)
-    result["algorithmic_flops_per_eval"] = aflops
+    if roof["unit"] == "GB/s":
+        roof["frac_of_measured_copy"] = round(roof["achieved"] / probe["copy"], 4)
+    result["algorithmic_flops_per_eval"] = algorithmic_flops(prob)
     log(f"bench: bandwidth probe {probe}")
 
+    sample = None
     if not args.no_cpu_baseline:
-        sample = args.cpu_sample or min(prob.n_patterns, {1: 1000, 2: 30000, 3: 3000, 4: 1}.get(args.config, 1000))
+        sample = args.cpu_sample or min(prob.n_patterns, {1: 1000, 2: 30000, 3: 3000, 4: 1}.get(config, 1000))
         log(f"bench: cpu baseline on {sample} patterns ...")
         sub, ref_logL, ref_b, ref_q, cpu = run_cpu_baseline(prob, sample, want_Q, want_grad)
         result["cpu_baseline"] = cpu
-        # parity of the same GPU path on the same subsample
-        with from_problem(sub, args.precision, grad_branch=want_grad, grad_Q=want_Q, kernel=args.kernel,
-                          use_pi=args.config != 4) as small:
-            g_logL = small.log_likelihood()
-            if want_grad:
-                g_b, g_q = small.gradient(branch=True, Q=want_Q)
-        parity = {"sample_patterns": sample, "logL_rel_err": abs(g_logL - ref_logL) / abs(ref_logL)}
-        if want_grad:
-            parity["grad_branch_rel_err"] = float(np.linalg.norm(g_b - ref_b) / np.linalg.norm(ref_b))
-        if want_Q:
-            parity["grad_Q_rel_err"] = float(np.linalg.norm(g_q - ref_q) / np.linalg.norm(ref_q))
-        result["parity_vs_oracle"] = parity
-    lik.close()
+        result["parity_vs_oracle"] = gpu_parity(sub, args.precision, args.kernel, use_pi, ref_logL, ref_b, ref_q,
+                                                want_grad, want_Q)
+
+    if headline and args.precision == "fp32" and args.kernel == "auto" and args.patterns is None:
+        # the metric's FP64 half on the same workload: the fast kernels and the plain generic FP64 path
+        log("bench: FP64 leg ...")
+        steps64 = max(3, args.steps // 2)
+        with from_problem(prob, "fp64", grad_branch=True) as l64:
+            v64, ms64, ph64, _ = time_instance(l64, steps64, 2, True, False)
+        with from_problem(prob, "fp64", grad_branch=True, kernel="generic") as lg:
+            vg, msg, _, _ = time_instance(lg, 3, 1, True, False)
+        fp64 = {"evals_per_s": round(v64, 3), "ms_per_eval": round(ms64, 4),
+                "roofline": roofline(prob, "fp64", "auto", ph64, steps64, False, 2, False),
+                "generic_fp64_evals_per_s": round(vg, 3), "generic_fp64_ms_per_eval": round(msg, 4),
+                "speedup_fp32_over_fp64": round(value / v64, 3),
+                "speedup_fp32_over_generic_fp64": round(value / vg, 3)}
+        if sample:
+            fp64["parity_vs_oracle"] = gpu_parity(sub, "fp64", "auto", True, ref_logL, ref_b, None, True, False)
+        result["fp64"] = fp64
+        log("bench: codon leg ...")
+        result["codon_C3"] = run_codon_leg(max(5, args.steps), 2, sample is not None)
+        log("bench: batched codon leg ...")
+        result["batch_C5"] = run_batch_leg(64, 1.0, max(3, args.steps // 4), 1,
+                                           tune=os.path.join(ROOT, "paper_1309_3075_amd", "tune_cache.json"))
     print(json.dumps(result), flush=True)
 
 

@@ -10,22 +10,36 @@
 namespace epochlik {
 namespace {
 
-__global__ __launch_bounds__(256) void probe_copy(const float4* __restrict__ src, float4* __restrict__ dst, size_t n) {
-  for (size_t i = blockIdx.x * 256ull + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) dst[i] = src[i];
+typedef float vf4 __attribute__((ext_vector_type(4)));
+
+// Each thread keeps four 16-byte loads in flight before it stores; stores are
+// non-temporal, so the streamed output does not evict what is still to be read.
+__global__ __launch_bounds__(256) void probe_copy(const vf4* __restrict__ src, vf4* __restrict__ dst, size_t n) {
+  const size_t stride = (size_t)gridDim.x * 256;
+  size_t i = blockIdx.x * 256ull + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    const vf4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+    __builtin_nontemporal_store(a, dst + i);
+    __builtin_nontemporal_store(b, dst + i + stride);
+    __builtin_nontemporal_store(c, dst + i + 2 * stride);
+    __builtin_nontemporal_store(d, dst + i + 3 * stride);
+  }
+  for (; i < n; i += stride) __builtin_nontemporal_store(src[i], dst + i);
 }
 
-__global__ __launch_bounds__(256) void probe_read(const float4* __restrict__ src, float* __restrict__ out, size_t n) {
+__global__ __launch_bounds__(256) void probe_read(const vf4* __restrict__ src, float* __restrict__ out, size_t n) {
   float acc = 0.f;
   for (size_t i = blockIdx.x * 256ull + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
-    const float4 v = src[i];
+    const vf4 v = src[i];
     acc += (v.x + v.y) + (v.z + v.w);
   }
   if (acc == 123.456f) out[0] = acc;  // keeps the loads live; never true for the zero-filled input
 }
 
-__global__ __launch_bounds__(256) void probe_write(float4* __restrict__ dst, size_t n) {
+__global__ __launch_bounds__(256) void probe_write(vf4* __restrict__ dst, size_t n) {
+  const vf4 v = {0.f, 1.f, 2.f, 3.f};
   for (size_t i = blockIdx.x * 256ull + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
-    dst[i] = make_float4(0.f, 1.f, 2.f, 3.f);
+    __builtin_nontemporal_store(v, dst + i);
 }
 
 }  // namespace
@@ -50,11 +64,11 @@ extern "C" int epoch_bandwidth_probe(int64_t bytes, int32_t kind, int32_t iters,
   const int grid = 256 * 16;
   auto launch = [&]() {
     if (kind == 0)
-      hipLaunchKernelGGL(probe_copy, dim3(grid), dim3(256), 0, nullptr, (const float4*)a, (float4*)b, n);
+      hipLaunchKernelGGL(probe_copy, dim3(grid), dim3(256), 0, nullptr, (const vf4*)a, (vf4*)b, n);
     else if (kind == 1)
-      hipLaunchKernelGGL(probe_read, dim3(grid), dim3(256), 0, nullptr, (const float4*)a, (float*)a, n);
+      hipLaunchKernelGGL(probe_read, dim3(grid), dim3(256), 0, nullptr, (const vf4*)a, (float*)a, n);
     else
-      hipLaunchKernelGGL(probe_write, dim3(grid), dim3(256), 0, nullptr, (float4*)a, n);
+      hipLaunchKernelGGL(probe_write, dim3(grid), dim3(256), 0, nullptr, (vf4*)a, n);
   };
   if (!rc) {
     launch();  // warm-up
