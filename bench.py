@@ -293,6 +293,40 @@ def gpu_parity(sub, precision, kernel, use_pi, ref_logL, ref_b, ref_q, want_grad
     return out
 
 
+def proposal_leg(prob, steps, use_pi=True):
+    """MCMC-style proposals on an FP32 log-likelihood-only instance: each step moves the rate of one
+    random branch and evaluates the log-likelihood, re-forming only that branch's transition
+    matrices and the partials on its path to the root; timed against full evaluations of the
+    same instance (incremental re-evaluation switched off)."""
+    import torch
+    from paper_1309_3075_amd.likelihood import from_problem
+    rng = np.random.default_rng(17)
+    n = prob.parent.shape[0]
+    branches = [v for v in range(n) if prob.parent[v] >= 0]
+    out = {}
+    with from_problem(prob, "fp32", use_pi=use_pi) as lik:
+        for mode in ("full", "incremental"):
+            lik.set_option("incremental", 1 if mode == "incremental" else 0)
+            lik.log_likelihood()
+            rates = prob.branch_rate.copy()
+            work = []
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(steps):
+                v = int(branches[rng.integers(len(branches))])
+                rates[v] *= 1.01 if k % 2 == 0 else 1 / 1.01
+                lik.set_branch_rates([v], [rates[v]])
+                lik.evaluate()
+                work.append(lik.work_counts()[1])
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            out[mode] = {"proposals_per_s": round(steps / dt, 2), "ms_per_proposal": round(dt * 1000 / steps, 4),
+                         "mean_partials_formed": round(float(np.mean(work)), 2)}
+    out["speedup_incremental_over_full"] = round(out["incremental"]["proposals_per_s"] / out["full"]["proposals_per_s"], 3)
+    out["what"] = "one random branch rate changed per step, then logL (FP32, no gradient)"
+    return out
+
+
 def run_codon_leg(steps, warmup, with_parity):
     """The 128-taxon GY94 codon workload (FP32, branch and rate-matrix gradients)."""
     from paper_1309_3075_amd import workloads as W
@@ -301,13 +335,15 @@ def run_codon_leg(steps, warmup, with_parity):
     lik = from_problem(prob, "fp32", grad_branch=True, grad_Q=True)
     eps, ms, phases, _ = time_instance(lik, steps, warmup, True, True)
     lik.close()
+    proposals = proposal_leg(prob, 4 * steps)
     aflops = algorithmic_flops(prob)
     total = sum(aflops.values())
     leg = {"workload": WORKLOADS[3], "evals_per_s": round(eps, 2), "ms_per_eval": round(ms, 4),
            "roofline": roofline(prob, "fp32", "auto", phases, steps, True, 3, False),
            "whole_eval_TFLOPs": round(total / (ms * 1e-3) / 1e12, 3),
            "whole_eval_frac_fp32_peak": round(total / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4),
-           "phases_ms_per_eval": {k: round(v[0] / steps, 4) for k, v in phases.items()}}
+           "phases_ms_per_eval": {k: round(v[0] / steps, 4) for k, v in phases.items()},
+           "one_branch_proposals": proposals}
     if with_parity:
         sub = pattern_subset(prob, 1000)
         ref_logL, ref_b, ref_q, _ = oracle_timed(sub, True, True, host_threads())
@@ -470,6 +506,8 @@ def main():
         if sample:
             fp64["parity_vs_oracle"] = gpu_parity(sub, "fp64", "auto", True, ref_logL, ref_b, None, True, False)
         result["fp64"] = fp64
+        log("bench: proposal leg ...")
+        result["one_branch_proposals"] = proposal_leg(prob, 100)
         log("bench: codon leg ...")
         result["codon_C3"] = run_codon_leg(max(5, args.steps), 2, sample is not None)
         log("bench: batched codon leg ...")

@@ -256,6 +256,8 @@ int epoch_get_timing(EpochInstance* inst, double* ms_out, int64_t* counts_out);
  *   EPOCH_OPT_TARGET_BLOCKS: 1..2^30 (default 1024): on the 64-state path,
  *     the blocks each tree-level launch aims for (it sets how many 64-pattern
  *     tiles a block walks, and so the number of dlogL/dP partial sums).
+ *   EPOCH_OPT_INCREMENTAL: 0 or 1 (default 1): restricted re-evaluation after
+ *     epoch_set_branch_rates / set_epoch_eigensystems (see below).
  *   EPOCH_OPT_SPLIT_BLOCKS: 0..2^30 (default 256): on the 64-state path, a
  *     pre-order tree level launched with at most this many blocks runs each
  *     child branch on its own wavefronts (same results, shorter per-wavefront
@@ -269,7 +271,39 @@ int epoch_get_timing(EpochInstance* inst, double* ms_out, int64_t* counts_out);
 #define EPOCH_OPT_SPLIT_BLOCKS 6
 #define EPOCH_OPT_TARGET_BLOCKS 7
 #define EPOCH_OPT_CHAIN_SPLIT 8
+#define EPOCH_OPT_INCREMENTAL 9
 int epoch_set_option(EpochInstance* inst, int32_t key, int64_t value);
+
+/* ---- Incremental re-evaluation for MCMC proposals (Introduction: the method
+ * runs inside a Markov chain Monte Carlo sampler that proposes one change at a
+ * time; Methods, "Coarse-grain parallel implementation": the front end tracks
+ * which branches need new transition matrices).  The instance remembers which
+ * branches changed since its last post-order pass: the listed branches of
+ * epoch_set_branch_rates, and every branch with a stretch in an interval of
+ * process s after set_epoch_eigensystems(s) (Eq. 6-7).  The next
+ * update_transition_matrices / update_partials (or epoch_evaluate) then forms
+ * only those branches' transition matrices and the partials of the nodes on
+ * their paths to the root (Eq. 4: a partial depends on its subtree only); the
+ * root log-likelihood and any gradient pass run in full.  Any other setter, a
+ * new tree, an option or a batch evaluation makes the next evaluation full.
+ * Restricted passes are taken by instances without EPOCH_GRAD_Q on the
+ * 4-state level kernels, the 64-state kernels and the generic kernels when all
+ * patterns are evaluated at once (not under an HBM budget, not on the tree
+ * walk); otherwise the evaluation is full.  EPOCH_OPT_INCREMENTAL 0 turns the
+ * restriction off (default 1).  Results equal a full evaluation, except that a
+ * long epoch chain the full matrix-core P stage would cut into parts is formed
+ * whole (different rounding). */
+
+/* New rates r_v for the branches above nodes[0..n) (each > 0 and finite; an
+ * entry for the root is ignored), as set_tree_epochs' branch_rate would give
+ * them, without re-planning the tree.  Host arrays [n].  Needs the tree;
+ * invalidates the transition matrices. */
+int epoch_set_branch_rates(EpochInstance* inst, int32_t n, const int32_t* nodes, const double* rates);
+
+/* Work of the last evaluation: out[0] = transition matrices (branch x category)
+ * formed by the last P stage, out[1] = internal-node partials formed by the
+ * last post-order pass (the 4-state kernels never store cherries).  Host [2]. */
+int epoch_get_work_counts(EpochInstance* inst, int64_t* out);
 
 /* ---- Batched evaluation (an addition to the paper: many independent
  * evaluations in one replayed HIP graph).

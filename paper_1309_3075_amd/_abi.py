@@ -38,7 +38,7 @@ EXPORTED = [
     "epoch_plan_segments", "epoch_set_timing", "epoch_get_timing", "epoch_bandwidth_probe",
     "epoch_batch_create", "epoch_batch_evaluate", "epoch_batch_gradients", "epoch_batch_target_blocks",
     "epoch_batch_destroy", "epoch_set_option", "epoch_plan_walk", "epoch_workspace_bytes",
-    "epoch_eigen_residual_noalloc",
+    "epoch_eigen_residual_noalloc", "epoch_set_branch_rates", "epoch_get_work_counts",
 ]
 EPOCH_EVAL_LOGL = 0x1
 EPOCH_EVAL_GRAD_BRANCH = 0x2
@@ -119,6 +119,8 @@ def load() -> ctypes.CDLL:
         "epoch_workspace_bytes": (i32, [ctypes.POINTER(EpochConfig), ctypes.POINTER(ctypes.c_int64)]),
         "epoch_plan_walk": (i32, [i32, ip, dp, i32, i32, ip, ip]),
         "epoch_eigen_residual_noalloc": (i32, [i32, i32, P, P, P, P, P, P, P]),
+        "epoch_set_branch_rates": (i32, [P, i32, ip, dp]),
+        "epoch_get_work_counts": (i32, [P, ctypes.POINTER(ctypes.c_int64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -190,6 +192,7 @@ EPOCH_OPT_LEVEL_MIN_TILES = 5
 EPOCH_OPT_SPLIT_BLOCKS = 6
 EPOCH_OPT_TARGET_BLOCKS = 7
 EPOCH_OPT_CHAIN_SPLIT = 8
+EPOCH_OPT_INCREMENTAL = 9
 
 
 def plan_walk(parent, height, recompute_tips: int = 2):

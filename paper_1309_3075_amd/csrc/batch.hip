@@ -435,6 +435,7 @@ int epoch_batch_evaluate(EpochBatch* b, uint32_t what, double* logL) {
   if (rc) return rc;
   for (size_t q = 0; q < n; ++q) {
     EpochInstance* in = b->insts[q];
+    mark_dirty_all(in);  // the graph's launches are not tracked: the member's next single evaluation is full
     in->P_valid = in->partials_valid = true;
     in->logL_valid = std::isfinite(logL[q]);
     in->grad_ready = (what & (kGradBranch | kGradQ)) != 0;

@@ -72,8 +72,28 @@ int launch_grad_Q(EpochInstance* in) {
 
 int fastpath_after_pstage(EpochInstance* in) { return (nuc(in) && in->walk_ok) ? launch_walk_tipcol(in) : EPOCH_OK; }
 
+namespace {
+int pstage_then_tip_columns(EpochInstance* in) {
+  const int rc = launch_pstage(in);
+  return rc ? rc : fastpath_after_pstage(in);
+}
+
+// internal-node partials a full post-order pass forms (4-state level kernels recompute cherries)
+int64_t full_post_count(const EpochInstance* in) {
+  const auto& pl = in->plan;
+  if (nuc(in) && !in->walk_ok && pl.n_levels > 1) return (int64_t)(in->N - 1) - (pl.level_offset[2] - pl.level_offset[1]);
+  return in->N - 1;
+}
+}  // namespace
+
 int fastpath_pstage(EpochInstance* in) {
-  EPOCH_PHASE(0, launch_pstage(in) || fastpath_after_pstage(in));
+  if (incremental_eligible(in)) {  // only the branches changed since the last post-order pass
+    EPOCH_PHASE(0, launch_pstage_incremental(in));
+    return EPOCH_OK;
+  }
+  in->inc_active = false;
+  in->work_P = (int64_t)(in->n_nodes - 1) * in->C;
+  EPOCH_PHASE(0, pstage_then_tip_columns(in));
   return EPOCH_OK;
 }
 
@@ -135,7 +155,13 @@ int launch_post(EpochInstance* in) {
 }
 
 int fastpath_post(EpochInstance* in) {
-  EPOCH_PHASE(1, launch_post(in));
+  if (in->inc_active) {
+    EPOCH_PHASE(1, launch_post_incremental(in));
+  } else {
+    in->work_partials = full_post_count(in);
+    EPOCH_PHASE(1, launch_post(in));
+  }
+  incremental_done(in);
   return EPOCH_OK;
 }
 

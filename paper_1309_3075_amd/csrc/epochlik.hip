@@ -424,6 +424,7 @@ int epoch_set_tip_states(EpochInstance* in, const int32_t* states) {
     h[k] = (uint8_t)s;
   }
   EPOCH_TRY(upload(in, in->tips.ptr, h.data(), n));
+  mark_dirty_all(in);
   in->have_tips = true;
   in->partials_valid = false;
   in->logL_valid = false;
@@ -463,6 +464,7 @@ int epoch_set_categories(EpochInstance* in, const double* rates, const double* w
     in->h_cat_weights[c] = weights[c];
   }
   EPOCH_TRY(upload(in, in->cat.ptr, h, sizeof(h)));
+  mark_dirty_all(in);
   in->have_cats = true;
   invalidate_downstream(in);
   return EPOCH_OK;
@@ -552,9 +554,14 @@ int set_epoch_eigensystems(EpochInstance* in, int32_t s, const double* V, const 
       ni = std::max(ni, ri);
     }
     in->cond[s] = nv * ni;
+    const bool was_fp64 = in->eig_fp64;
     in->eig_fp64 = false;
     for (int k = 0; k < in->S; ++k)
       if (in->cond[k] > kCondFP32) in->eig_fp64 = true;
+    // a new eigensystem changes the factors of process s only (Eq. 6-7), unless the
+    // arithmetic of every reconstruction changes with it
+    if (was_fp64 != in->eig_fp64 || !in->have_eig[s]) mark_dirty_all(in);
+    else mark_dirty_process(in, s);
   }
   // upload this process's slices in double and in the compute type
   auto up_slice = [&](DevBuf& buf, size_t elem, bool as_float) -> int {
@@ -734,6 +741,8 @@ int set_tree_epochs(EpochInstance* in, const int32_t* parent, const double* heig
     EPOCH_TRY(upload(in, in->seglist.ptr, all.data(), all.size() * sizeof(int32_t)));
   }
   in->plan = std::move(plan);
+  in->dirty.assign(in->n_nodes, 0);
+  mark_dirty_all(in);
   in->have_tree = true;
   in->tree_generation++;
   invalidate_downstream(in);
@@ -888,7 +897,12 @@ int epoch_set_option(EpochInstance* in, int32_t key, int64_t value) {
   // options change launch shapes and may reallocate schedules and work lists:
   // a batch holding this instance captures its graph again
   in->option_generation++;
+  mark_dirty_all(in);
   switch (key) {
+    case EPOCH_OPT_INCREMENTAL:
+      if (value != 0 && value != 1) return set_error(EPOCH_ERR_ARG, "EPOCH_OPT_INCREMENTAL takes 0 or 1");
+      in->inc_enable = (int)value;
+      return EPOCH_OK;
     case EPOCH_OPT_TREE_WALK:
       if (value < -1 || value > 1) return set_error(EPOCH_ERR_ARG, "EPOCH_OPT_TREE_WALK takes -1, 0 or 1");
       if (in->budget > 0 && in->path == 1 && value != 1)

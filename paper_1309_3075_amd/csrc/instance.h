@@ -78,6 +78,16 @@ struct CodonSchedule {
   int split_blocks = 0;  // pre-order levels of at most this many blocks put each child branch on its own wavefronts
 };
 
+// Incremental re-evaluation (MCMC proposals): the work of one restricted pass.
+struct IncrementalPlan {
+  std::vector<int32_t> pnodes;          // branches (child nodes) whose transition matrices are formed again
+  std::vector<int4> chain_items;        // the same as whole-chain work items of the matrix-core P stage
+  std::vector<int32_t> post_nodes;      // internal nodes whose partials are formed again, grouped by level
+  std::vector<int32_t> post_level_off;  // [n_levels + 2]: level l occupies [off[l], off[l + 1])
+  CodonSchedule codon;                  // the 64-state schedule restricted to post_nodes
+  size_t off_chain = 0, off_post = 0, off_codon = 0;  // byte offsets in the device copy
+};
+
 }  // namespace epochlik
 
 struct EpochInstance {
@@ -183,6 +193,16 @@ struct EpochInstance {
   bool view_accumulate = false;    // dlogL/dP of this chunk adds to the earlier chunks
   int codon_split_blocks = 256;    // narrow pre-order levels (at most this many blocks) use the side-split kernel
 
+  // incremental re-evaluation (epoch_set_branch_rates, set_epoch_eigensystems on one process)
+  int inc_enable = 1;              // EPOCH_OPT_INCREMENTAL
+  bool dirty_all = true;           // every transition matrix and partial must be formed again
+  bool inc_base = false;           // the partials hold a complete post-order pass (the state changes apply to)
+  bool inc_active = false;         // the last P stage was restricted: the post-order pass follows it
+  std::vector<uint8_t> dirty;      // [n_nodes]: the branch above the node changed since the last post-order pass
+  epochlik::IncrementalPlan inc;
+  epochlik::DevBuf inc_dev;        // device copy of the restricted lists
+  int64_t work_P = 0, work_partials = 0;  // matrices and node partials formed by the last P stage / post-order pass
+
   // per-phase timing (epoch_set_timing)
   bool timing = false;
   hipEvent_t ev[EPOCH_N_PHASES][2] = {};
@@ -197,6 +217,14 @@ struct EpochInstance {
 };
 
 namespace epochlik {
+
+// incremental re-evaluation (incremental.hip)
+void mark_dirty_all(EpochInstance* in);
+void mark_dirty_process(EpochInstance* in, int s);
+bool incremental_eligible(const EpochInstance* in);
+int launch_pstage_incremental(EpochInstance* in);  // builds the restricted lists, forms the dirty branches' P
+int launch_post_incremental(EpochInstance* in);    // partials of the dirty branches' ancestors
+void incremental_done(EpochInstance* in);           // after a complete post-order pass
 
 // phase timing brackets (no-ops unless timing is enabled)
 int phase_begin(EpochInstance* in, int phase);
@@ -217,6 +245,9 @@ int launch_eigen_check_n(hipStream_t st, int K, int n, int ld, long mat_stride, 
                          const double* Vi, const double* lr, const double* li, const double* Q, double* part,
                          double* out);
 int launch_pstage_generic(EpochInstance* in);
+int launch_pstage_generic_nodes(EpochInstance* in, const int32_t* d_nodes, int n);  // listed branches only
+int launch_post_generic_nodes(EpochInstance* in, const int32_t* d_nodes, const int32_t* level_off);
+int launch_pstage_mfma_items(EpochInstance* in, const int4* d_items, int n_items);  // whole chains listed
 int launch_pstage_mfma(EpochInstance* in);
 bool pstage_mfma_supported(const EpochInstance* in);
 int launch_pstage(EpochInstance* in);  // matrix-core kernel where it applies, else generic
@@ -237,6 +268,7 @@ int launch_grad_reduce(EpochInstance* in, int n_chunks, const int32_t* chunks_pe
 
 // 4-state kernels (kernels_nuc.hip)
 int launch_nuc_post(EpochInstance* in);
+int launch_nuc_post_nodes(EpochInstance* in, const int32_t* d_nodes, const int32_t* level_off);
 int launch_nuc_root(EpochInstance* in);
 int launch_nuc_pre_grad(EpochInstance* in);
 int nuc_slots(int P, int C, int rmin);
@@ -255,6 +287,7 @@ int launch_walk_pre_grad(EpochInstance* in);
 
 // 64-state MFMA kernels (kernels_codon.hip)
 int launch_codon_post(EpochInstance* in);
+int launch_codon_post_schedule(EpochInstance* in, const CodonSchedule& sc, const int2* d_items);
 int launch_codon_root(EpochInstance* in);
 int launch_codon_pre_grad(EpochInstance* in);
 int codon_prepare(EpochInstance* in);

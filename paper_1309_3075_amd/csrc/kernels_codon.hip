@@ -912,6 +912,10 @@ int launch_codon_post(EpochInstance* in) {
   return launch_chunk_sum(in, nc);
 }
 
+int launch_codon_post_schedule(EpochInstance* in, const CodonSchedule& sc, const int2* d_items) {
+  return codon_launch_post(sc, dev_probs(in), d_items, in->stream);
+}
+
 int launch_codon_root(EpochInstance* in) {
   if (in->codon_nchunks > 1) return EPOCH_OK;  // formed with the chunks' partials
   return codon_launch_root(in->codon_sched, dev_probs(in), in->stream);

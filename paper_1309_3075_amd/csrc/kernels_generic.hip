@@ -28,7 +28,8 @@ namespace {
 // ---------------------------------------------------------------------------
 template <typename T, typename TO, bool GRAD, int EPT>
 __global__ __launch_bounds__(256) void pstage_generic_kernel(
-    int n_nodes, int Kp, int C, const T* __restrict__ eigV, const T* __restrict__ eigVi,
+    int n_nodes, const int32_t* __restrict__ node_list, int Kp, int C, const T* __restrict__ eigV,
+    const T* __restrict__ eigVi,
     const T* __restrict__ lre, const T* __restrict__ lim, const int32_t* __restrict__ seg_offset,
     const int32_t* __restrict__ seg_process, const double* __restrict__ seg_time,
     const double* __restrict__ seg_frac, const double* __restrict__ rate,
@@ -41,7 +42,8 @@ __global__ __launch_bounds__(256) void pstage_generic_kernel(
   const bool in_slot = slot < ipb;
   const int item = blockIdx.x * ipb + slot;
   const bool valid = in_slot && item < n_nodes * C;
-  const int v = valid ? item / C : 0;
+  // node_list (or null: every node) names the branches whose matrices are formed
+  const int v = valid ? (node_list ? node_list[item / C] : item / C) : 0;
   const int c = valid ? item % C : 0;
   T* sX = reinterpret_cast<T*>(smem_raw) + (in_slot ? slot : 0) * KK;
   T* sD = reinterpret_cast<T*>(smem_raw) + ipb * KK + (in_slot ? slot : 0) * KK;
@@ -512,8 +514,8 @@ int lanes_per_pattern(int Kp) {
 // T: arithmetic of the eigen reconstruction and chain products; TO: storage type
 // of the transition matrices handed to pruning.
 template <typename T, typename TO>
-int pstage_dispatch(EpochInstance* in) {
-  const int Kp = in->Kp, KK = Kp * Kp, C = in->C, n = in->n_nodes;
+int pstage_dispatch(EpochInstance* in, const int32_t* d_nodes, int n_list) {
+  const int Kp = in->Kp, KK = Kp * Kp, C = in->C, n = d_nodes ? n_list : in->n_nodes;
   const bool grad = (in->cfg.flags & (EPOCH_GRAD_BRANCH | EPOCH_GRAD_Q)) != 0;
   const int ept = KK <= 256 ? 1 : (KK + 255) / 256;
   const int ipb = ept == 1 ? std::max(1, 256 / KK) : 1;
@@ -530,7 +532,7 @@ int pstage_dispatch(EpochInstance* in) {
   TO* Pout = static_cast<TO*>(in->Pm.ptr);
   TO* dPout = static_cast<TO*>(in->dPm.ptr);
 #define EPOCH_PSTAGE(G, E)                                                                      \
-  hipLaunchKernelGGL((pstage_generic_kernel<T, TO, G, E>), grid, dim3(256), shm, in->stream, n, Kp, C, \
+  hipLaunchKernelGGL((pstage_generic_kernel<T, TO, G, E>), grid, dim3(256), shm, in->stream, n, d_nodes, Kp, C, \
                      V, Vi, lr, li, in->d_seg_offset, in->d_seg_process, in->d_seg_time,        \
                      in->d_seg_frac, in->d_rate, cat, Pout, dPout)
   if (ept == 1) {
@@ -553,8 +555,10 @@ int view_P(const EpochInstance* in) { return in->view_P > 0 ? in->view_P : in->P
 size_t view_p0(const EpochInstance* in) { return in->view_P > 0 ? (size_t)in->view_p0 : 0; }
 size_t view_result(const EpochInstance* in) { return in->view_P > 0 ? 1 + (size_t)in->view_j : 0; }
 
+// level l's nodes are nodes[level_off[l] .. level_off[l + 1]) (the plan's level lists, or a
+// restricted list of the same layout)
 template <typename T>
-int post_dispatch(EpochInstance* in) {
+int post_dispatch(EpochInstance* in, const int32_t* d_nodes, const int32_t* level_off) {
   const int KQ = lanes_per_pattern(in->Kp);
   const int TP = 256 / KQ;
   const auto& pl = in->plan;
@@ -564,10 +568,10 @@ int post_dispatch(EpochInstance* in) {
   int32_t* sc = static_cast<int32_t*>(in->scales.ptr);
   const int P = view_P(in);
   for (int l = 1; l <= pl.n_levels; ++l) {
-    const int n_l = pl.level_offset[l + 1] - pl.level_offset[l];
+    const int n_l = level_off[l + 1] - level_off[l];
     if (n_l == 0) continue;
     dim3 grid((P + TP - 1) / TP, n_l);
-    const int32_t* nodes = in->d_level_nodes + pl.level_offset[l];
+    const int32_t* nodes = d_nodes + level_off[l];
 #define EPOCH_POST(Q)                                                                            \
   hipLaunchKernelGGL((post_level_generic_kernel<T, Q>), grid, dim3(256), 0, in->stream, nodes,    \
                      in->d_left, in->d_right, Pm, tips, part, sc, in->N, P, in->P, in->K, in->Kp, in->C)
@@ -706,12 +710,16 @@ int launch_grad_reduce(EpochInstance* in, int n_slots, const int32_t* chunks_per
                   : grad_reduce_dispatch<float>(in, n_slots, chunks_per_node);
 }
 
-int launch_pstage_generic(EpochInstance* in) {
-  if (in->fp64) return pstage_dispatch<double, double>(in);
-  return in->eig_fp64 ? pstage_dispatch<double, float>(in) : pstage_dispatch<float, float>(in);
+int launch_pstage_generic(EpochInstance* in) { return launch_pstage_generic_nodes(in, nullptr, 0); }
+int launch_pstage_generic_nodes(EpochInstance* in, const int32_t* d_nodes, int n) {
+  if (in->fp64) return pstage_dispatch<double, double>(in, d_nodes, n);
+  return in->eig_fp64 ? pstage_dispatch<double, float>(in, d_nodes, n) : pstage_dispatch<float, float>(in, d_nodes, n);
 }
 int launch_post_generic(EpochInstance* in) {
-  return in->fp64 ? post_dispatch<double>(in) : post_dispatch<float>(in);
+  return launch_post_generic_nodes(in, in->d_level_nodes, in->plan.level_offset.data());
+}
+int launch_post_generic_nodes(EpochInstance* in, const int32_t* d_nodes, const int32_t* level_off) {
+  return in->fp64 ? post_dispatch<double>(in, d_nodes, level_off) : post_dispatch<float>(in, d_nodes, level_off);
 }
 int launch_root_generic(EpochInstance* in) {
   return in->fp64 ? root_dispatch<double>(in) : root_dispatch<float>(in);

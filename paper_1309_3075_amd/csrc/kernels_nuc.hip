@@ -545,7 +545,7 @@ int tiles_per_wave(int tiles, int n_l, int r_min, int r_max, long target_waves) 
 }
 
 template <typename T, int CP>
-int post_dispatch_cp(EpochInstance* in) {
+int post_dispatch_cp(EpochInstance* in, const int32_t* d_nodes, const int32_t* level_off) {
   const auto& pl = in->plan;
   constexpr int TPW = 64 / CP;
   const int tiles = (in->P + TPW - 1) / TPW;
@@ -556,12 +556,12 @@ int post_dispatch_cp(EpochInstance* in) {
   // level 1 holds exactly the cherries, which are recomputed by their parents;
   // it is launched only when the root itself is a cherry (two tips)
   for (int l = (pl.n_levels == 1 ? 1 : 2); l <= pl.n_levels; ++l) {
-    const int n_l = pl.level_offset[l + 1] - pl.level_offset[l];
+    const int n_l = level_off[l + 1] - level_off[l];
     if (!n_l) continue;
     const int R = tiles_per_wave(tiles, n_l, 1, 16, post_target_waves(sizeof(T) == 8));
     const int blocks = (tiles + 4 * R - 1) / (4 * R);
     hipLaunchKernelGGL((nuc_post_level_kernel<T, CP>), dim3(blocks, n_l), dim3(256), 0, in->stream,
-                       in->d_level_nodes + pl.level_offset[l], in->d_left, in->d_right, Pm, tips, part, part,
+                       d_nodes + level_off[l], in->d_left, in->d_right, Pm, tips, part, part,
                        sc, sc, in->N, in->P, in->C, R);
   }
   return hip_check(hipGetLastError(), "nuc_post_level launch");
@@ -692,11 +692,17 @@ void nuc_pre_order_nodes(const EpochInstance* in, std::vector<int32_t>& nodes, s
 }
 
 int launch_nuc_post(EpochInstance* in) {
+  return launch_nuc_post_nodes(in, in->d_level_nodes, in->plan.level_offset.data());
+}
+
+// Level l's nodes are d_nodes[level_off[l] .. level_off[l + 1]): the plan's level lists, or a
+// restricted list of the same layout (incremental re-evaluation).
+int launch_nuc_post_nodes(EpochInstance* in, const int32_t* d_nodes, const int32_t* level_off) {
   switch (cp_of(in->C)) {
-    case 1: return in->fp64 ? post_dispatch_cp<double, 1>(in) : post_dispatch_cp<float, 1>(in);
-    case 2: return in->fp64 ? post_dispatch_cp<double, 2>(in) : post_dispatch_cp<float, 2>(in);
-    case 4: return in->fp64 ? post_dispatch_cp<double, 4>(in) : post_dispatch_cp<float, 4>(in);
-    default: return in->fp64 ? post_dispatch_cp<double, 8>(in) : post_dispatch_cp<float, 8>(in);
+    case 1: return in->fp64 ? post_dispatch_cp<double, 1>(in, d_nodes, level_off) : post_dispatch_cp<float, 1>(in, d_nodes, level_off);
+    case 2: return in->fp64 ? post_dispatch_cp<double, 2>(in, d_nodes, level_off) : post_dispatch_cp<float, 2>(in, d_nodes, level_off);
+    case 4: return in->fp64 ? post_dispatch_cp<double, 4>(in, d_nodes, level_off) : post_dispatch_cp<float, 4>(in, d_nodes, level_off);
+    default: return in->fp64 ? post_dispatch_cp<double, 8>(in, d_nodes, level_off) : post_dispatch_cp<float, 8>(in, d_nodes, level_off);
   }
 }
 

@@ -312,10 +312,13 @@ __global__ __launch_bounds__(256) void pstage_mfma_multi_kernel(const PStageDesc
 }
 
 template <typename T, typename TO, int NT>
-int pstage_mfma_launch(EpochInstance* in) {
-  const bool split = in->n_chain_splits > 0;
+int pstage_mfma_launch(EpochInstance* in, const int4* d_items, int n_items) {
+  const bool split = !d_items && in->n_chain_splits > 0;
   PStageDesc pd = pstage_descriptor(in);
-  if (split) {
+  if (d_items) {  // whole chains of the listed nodes only
+    pd.items = d_items;
+    pd.n_items = n_items * in->C;
+  } else if (split) {
     pd.items = static_cast<const int4*>(in->chain_items.ptr) + in->n_nodes;
     pd.n_items = in->n_chain_split_items * in->C;
   }
@@ -336,17 +339,17 @@ int pstage_mfma_launch(EpochInstance* in) {
       hipLaunchKernelGGL((pstage_tail_fix_kernel<T, NT>), dim3(cgrid.x, (unsigned)in->chain_max_tail), dim3(64 * NT),
                          0, in->stream, pd, splits);
   }
-  in->pstage_split = split;
+  if (!d_items) in->pstage_split = split;  // a restricted launch leaves the other chains as they were
   return hip_check(hipGetLastError(), "pstage_mfma launch");
 }
 
 template <typename T, typename TO>
-int pstage_mfma_dispatch(EpochInstance* in) {
+int pstage_mfma_dispatch(EpochInstance* in, const int4* d_items, int n_items) {
   switch (in->Kp) {
-    case 16: return pstage_mfma_launch<T, TO, 1>(in);
-    case 32: return pstage_mfma_launch<T, TO, 2>(in);
-    case 48: return pstage_mfma_launch<T, TO, 3>(in);
-    case 64: return pstage_mfma_launch<T, TO, 4>(in);
+    case 16: return pstage_mfma_launch<T, TO, 1>(in, d_items, n_items);
+    case 32: return pstage_mfma_launch<T, TO, 2>(in, d_items, n_items);
+    case 48: return pstage_mfma_launch<T, TO, 3>(in, d_items, n_items);
+    case 64: return pstage_mfma_launch<T, TO, 4>(in, d_items, n_items);
     default: return set_error(EPOCH_ERR_STATE, "matrix-core P stage needs Kp in {16, 32, 48, 64}, got %d", in->Kp);
   }
 }
@@ -378,9 +381,12 @@ bool pstage_mfma_supported(const EpochInstance* in) {
   return in->Kp >= 16 && in->Kp <= 64 && in->Kp % 16 == 0;
 }
 
-int launch_pstage_mfma(EpochInstance* in) {
-  if (in->fp64) return pstage_mfma_dispatch<double, double>(in);
-  return in->eig_fp64 ? pstage_mfma_dispatch<double, float>(in) : pstage_mfma_dispatch<float, float>(in);
+int launch_pstage_mfma(EpochInstance* in) { return launch_pstage_mfma_items(in, nullptr, 0); }
+
+int launch_pstage_mfma_items(EpochInstance* in, const int4* d_items, int n_items) {
+  if (in->fp64) return pstage_mfma_dispatch<double, double>(in, d_items, n_items);
+  return in->eig_fp64 ? pstage_mfma_dispatch<double, float>(in, d_items, n_items)
+                      : pstage_mfma_dispatch<float, float>(in, d_items, n_items);
 }
 
 // The device pointers and sizes one problem's P stage reads and writes, in the

@@ -131,6 +131,18 @@ class EpochLikelihood:
         phi = _i32(interval_process)
         check(self._lib.set_tree_epochs(self._h, _ip(par), _dp(h), _dp(r), len(phi), _dp(b), _ip(phi)))
 
+    def set_branch_rates(self, nodes, rates):
+        """New rates for the branches above `nodes` (epoch_set_branch_rates): the next
+        evaluation re-forms only those branches' matrices and their ancestors' partials."""
+        n, r = _i32(nodes), _f64(rates)
+        check(self._lib.epoch_set_branch_rates(self._h, int(n.shape[0]), _ip(n), _dp(r)))
+
+    def work_counts(self):
+        """(transition matrices, internal-node partials) formed by the last evaluation."""
+        out = np.zeros(2, dtype=np.int64)
+        check(self._lib.epoch_get_work_counts(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        return int(out[0]), int(out[1])
+
     # -- the path -----------------------------------------------------------
     def update_transition_matrices(self):
         check(self._lib.update_transition_matrices(self._h))
@@ -169,12 +181,12 @@ class EpochLikelihood:
 
     def set_option(self, key: str, value: int):
         """Kernel-selection option (epoch_set_option): 'tree_walk', 'walk_recompute', 'walk_blocks',
-        'walk_tiles', 'level_min_tiles', 'split_blocks', 'target_blocks', 'chain_split'."""
+        'walk_tiles', 'level_min_tiles', 'split_blocks', 'target_blocks', 'chain_split', 'incremental'."""
         k = {"tree_walk": _abi.EPOCH_OPT_TREE_WALK, "walk_recompute": _abi.EPOCH_OPT_WALK_RECOMPUTE,
              "walk_blocks": _abi.EPOCH_OPT_WALK_BLOCKS, "walk_tiles": _abi.EPOCH_OPT_WALK_TILES,
              "level_min_tiles": _abi.EPOCH_OPT_LEVEL_MIN_TILES,
              "split_blocks": _abi.EPOCH_OPT_SPLIT_BLOCKS, "target_blocks": _abi.EPOCH_OPT_TARGET_BLOCKS,
-             "chain_split": _abi.EPOCH_OPT_CHAIN_SPLIT}[key]
+             "chain_split": _abi.EPOCH_OPT_CHAIN_SPLIT, "incremental": _abi.EPOCH_OPT_INCREMENTAL}[key]
         check(self._lib.epoch_set_option(self._h, k, int(value)))
 
     def set_timing(self, enable: bool = True):

@@ -1,0 +1,152 @@
+"""Incremental re-evaluation for MCMC proposals (epoch_set_branch_rates, set_epoch_eigensystems on
+one process): a proposal that moves one branch or one rate matrix re-forms only the affected
+transition matrices and the partials on their paths to the root, and the result equals a full
+evaluation of the proposed state (bit for bit: the same kernels on the same inputs) and the oracle."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import epoch_oracle as O
+from paper_1309_3075_amd import workloads as W
+from paper_1309_3075_amd.likelihood import from_problem
+from tolerances import TOL_GRAD, TOL_LOGL, assert_grad, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _path_to_root(prob, v):
+    """Internal nodes above node v."""
+    out, u = [], prob.parent[v]
+    while u >= 0:
+        out.append(int(u))
+        u = prob.parent[u]
+    return out
+
+
+def _cherries(prob):
+    n = prob.parent.shape[0]
+    N = prob.n_tips
+    kids = {}
+    for v in range(n):
+        if prob.parent[v] >= 0:
+            kids.setdefault(int(prob.parent[v]), []).append(v)
+    return {u for u, c in kids.items() if all(x < N for x in c)}
+
+
+def _expected_partials(prob, nodes, path):
+    """Internal nodes a restricted post-order pass forms: the ancestors of the changed branches
+    (on the 4-state path cherries are recomputed by their parents, never stored)."""
+    up = set()
+    for v in nodes:
+        up.update(_path_to_root(prob, v))
+    if path == "nuc":
+        up -= _cherries(prob)
+    return len(up)
+
+
+CASES = {
+    # name: (problem factory, precision, kernel, options, path)
+    "nuc_fp32": (lambda: W.make_config(2, n_tips=64, n_patterns=3000), "fp32", "auto", {"tree_walk": 0}, "nuc"),
+    "nuc_fp64": (lambda: W.make_config(2, n_tips=40, n_patterns=1500), "fp64", "auto", {"tree_walk": 0}, "nuc"),
+    "codon_fp32": (lambda: W.make_config(3, n_patterns=700), "fp32", "auto", {}, "codon"),
+    "generic_K20": (lambda: W.random_problem(np.random.default_rng(77), 21, 20, 300, n_categories=2, n_intervals=3,
+                                              n_processes=3, reversible=True, tip_height_max=0.1),
+                    "fp32", "auto", {}, "generic"),
+    "generic_K4_fp64": (lambda: W.make_config(2, n_tips=30, n_patterns=800), "fp64", "generic", {}, "generic"),
+}
+
+
+def _perturbed_reversible(Q, pi, rng):
+    """Q with its exchangeabilities scaled by symmetric random factors (same pi, still
+    reversible, zero rates stay zero), normalised to sum_i pi_i q_ii = -1."""
+    R = Q / pi[None, :]
+    F = np.triu(rng.uniform(0.7, 1.4, size=Q.shape), 1)
+    Q1 = R * (F + F.T) * pi[None, :]
+    np.fill_diagonal(Q1, 0.0)
+    Q1 -= np.diag(Q1.sum(axis=1))
+    return Q1 / -(pi * np.diag(Q1)).sum()
+
+
+def _fresh(prob, precision, kernel, options):
+    lik = from_problem(prob, precision, grad_branch=True, kernel=kernel, options=options)
+    logL, _, db, _ = lik.evaluate(branch=True)
+    lik.close()
+    return logL, db
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_one_branch_and_one_process_proposals(name):
+    factory, precision, kernel, options, path = CASES[name]
+    prob = factory()
+    C = len(prob.cat_rates)
+    n = prob.parent.shape[0]
+    lik = from_problem(prob, precision, grad_branch=True, kernel=kernel, options=options)
+    logL0, _, db0, _ = lik.evaluate(branch=True)
+    assert lik.work_counts()[0] == (n - 1) * C  # the first evaluation is full
+
+    # -- one branch: a tip branch and an internal branch, one after the other
+    tip = int(np.argmax(prob.height[:prob.n_tips] == prob.height[:prob.n_tips].min()))
+    internal = next(v for v in range(prob.n_tips, n) if prob.parent[v] >= 0 and prob.parent[prob.parent[v]] >= 0)
+    cur = dataclasses.replace(prob, branch_rate=prob.branch_rate.copy())
+    for v, factor in ((tip, 1.7), (internal, 0.6)):
+        cur.branch_rate[v] *= factor
+        lik.set_branch_rates([v], [cur.branch_rate[v]])
+        logL, _, db, _ = lik.evaluate(branch=True)
+        assert lik.work_counts() == (C, _expected_partials(prob, [v], path)), (v, lik.work_counts())
+        want_logL, want_db = _fresh(cur, precision, kernel, options)
+        assert logL == want_logL, (v, logL, want_logL)
+        assert np.array_equal(db, want_db), v
+        ref = O.log_likelihood(cur)
+        assert rel(logL, ref) <= TOL_LOGL[precision]
+
+    # -- one process: new rates for process 1 (every branch with a stretch in its intervals)
+    Q1 = _perturbed_reversible(prob.Q[1], prob.pi_process[1], np.random.default_rng(3))
+    cur.Q = list(prob.Q)
+    cur.Q[1] = Q1
+    lik.set_rate_matrix(1, Q1, prob.pi_process[1])
+    logL, _, db, _ = lik.evaluate(branch=True)
+    from paper_1309_3075_amd import _abi
+    off_, proc, _ = _abi.plan_segments(prob.parent, prob.height, prob.boundaries, prob.interval_process,
+                                       prob.n_processes)
+    touched = [v for v in range(n) if prob.parent[v] >= 0 and np.any(proc[off_[v]:off_[v + 1]] == 1)]
+    assert lik.work_counts() == (len(touched) * C, _expected_partials(prob, touched, path))
+    want_logL, want_db = _fresh(cur, precision, kernel, options)
+    assert logL == want_logL and np.array_equal(db, want_db)
+    assert rel(logL, O.log_likelihood(cur)) <= TOL_LOGL[precision]
+    ref_b, _ = O.gradient(cur, wrt=("branch",))
+    assert_grad(db, ref_b, TOL_GRAD[precision], "dlogL/dl after the proposal")
+
+    # -- rejecting the proposals restores the original state and its bits
+    lik.set_rate_matrix(1, prob.Q[1], prob.pi_process[1])
+    lik.set_branch_rates([tip, internal], [prob.branch_rate[tip], prob.branch_rate[internal]])
+    logL, _, db, _ = lik.evaluate(branch=True)
+    assert logL == logL0 and np.array_equal(db, db0)
+    lik.close()
+
+
+def test_separate_calls_and_the_option_switch():
+    """The restricted pass through update_transition_matrices / update_partials /
+    root_log_likelihood; EPOCH_OPT_INCREMENTAL 0 evaluates in full with the same result; an
+    instance with dlogL/dQ evaluates in full."""
+    prob = W.make_config(2, n_tips=48, n_patterns=2000)
+    n = prob.parent.shape[0]
+    with from_problem(prob, "fp32", options={"tree_walk": 0}) as lik:
+        lik.log_likelihood()
+        v = 5
+        cur = dataclasses.replace(prob, branch_rate=prob.branch_rate.copy())
+        cur.branch_rate[v] = 2.0
+        lik.set_branch_rates([v], [2.0])
+        a = lik.log_likelihood()
+        assert lik.work_counts()[0] == 4
+        lik.set_option("incremental", 0)
+        lik.set_option("tree_walk", 0)
+        b = lik.log_likelihood()
+        assert lik.work_counts()[0] == (n - 1) * 4
+        assert a == b
+        assert rel(a, O.log_likelihood(cur)) <= TOL_LOGL["fp32"]
+    with from_problem(prob, "fp32", grad_branch=True, grad_Q=True, options={"tree_walk": 0}) as lik:
+        lik.evaluate(branch=True, Q=True)
+        lik.set_branch_rates([3], [1.5])
+        lik.evaluate(branch=True, Q=True)
+        assert lik.work_counts()[0] == (n - 1) * 4
