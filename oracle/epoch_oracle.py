@@ -30,6 +30,13 @@ What it computes, with the passage each step follows (Bielejec et al.,
   pre-order ("outside") pass gives dlogL/dP_b; the chain rule through the
   ordered product and the exponential uses the Van Loan block-matrix identity
   for the adjoint Frechet derivative of exp.
+* Time gradient (an addition; the paper fixes the transition times and names
+  estimating them as the next step, Discussion): derivatives with respect to
+  every node height and every epoch boundary, branch rates held fixed.  Heights
+  and boundaries enter only through the stretch durations of Eq. 7.  At a tie
+  (a node exactly on a boundary) the stretch structure changes, and the
+  derivative given is the one-sided derivative for an increasing height or
+  boundary, which is the side the half-open intervals assign the tie to.
 
 Times are heights (time before the youngest tip); interval k covers heights
 [b_k, b_{k+1}) with b_0 = -inf, b_M = +inf, interval 0 the youngest.
@@ -288,3 +295,57 @@ def gradient(prob, wrt=("branch", "Q")):
                 if "Q" in wrt:
                     d_Q[s] += scale * dt * adjoint_frechet_exp(scale * dt * prob.Q[s], Gk)
     return d_branch, d_Q
+
+
+# ---------------------------------------------------------------------------
+# Time gradient (an addition; Methods, "Relaxing time-homogeneity", Eq. 7)
+# ---------------------------------------------------------------------------
+
+
+def interval_of(h, boundaries):
+    """Index of the interval holding height h.  Intervals are half-open,
+    [b_{k-1}, b_k), so a height exactly on a boundary belongs to the interval
+    above it, and the stretch just above any height h lies in this interval."""
+    return int(np.searchsorted(np.asarray(boundaries, dtype=np.float64), h, side="right"))
+
+
+def time_gradient(prob):
+    """(dlogL/dh [2N-1] for every node height, dlogL/db [M-1] for every boundary).
+
+    Branch rates stay fixed.  With G = dlogL/dP from the outside pass and
+    x = r_b * rho_c:
+    * raising the parent height h_u lengthens the branch at its top by a stretch
+      of the interval holding h_u: dP/dh_u = x Q_top P;
+    * raising the child height h_v shortens it at its bottom, in the interval
+      holding h_v: dP/dh_v = -x P Q_bottom;
+    * raising boundary b_m (between interval m below and m + 1 above) moves
+      time of every branch spanning it (h_v <= b_m < h_u) from interval m + 1 to
+      interval m: with X the product of the factors above b_m and Y of those
+      below, dP/db_m = x X (Q_phi(m) - Q_phi(m+1)) Y.
+    """
+    P = transition_matrices(prob)
+    G = branch_adjoints(prob, P)
+    n_nodes = prob.parent.shape[0]
+    C = len(prob.cat_rates)
+    b = np.asarray(prob.boundaries, dtype=np.float64)
+    phi = prob.interval_process
+    d_h = np.zeros(n_nodes)
+    d_b = np.zeros(len(b))
+    for v in range(n_nodes):
+        u = prob.parent[v]
+        if u < 0:
+            continue
+        hu, hv = prob.height[u], prob.height[v]
+        Q_top = prob.Q[phi[interval_of(hu, b)]]
+        Q_bot = prob.Q[phi[interval_of(hv, b)]]
+        for c in range(C):
+            x = prob.branch_rate[v] * prob.cat_rates[c]
+            d_h[u] += x * float(np.sum(G[v, c] * (Q_top @ P[v, c])))
+            d_h[v] -= x * float(np.sum(G[v, c] * (P[v, c] @ Q_bot)))
+            for m, bm in enumerate(b):
+                if hv <= bm < hu:
+                    X = epoch_P(prob.Q, branch_segments(hu, bm, b, phi), x)
+                    Y = epoch_P(prob.Q, branch_segments(bm, hv, b, phi), x)
+                    D = prob.Q[phi[m]] - prob.Q[phi[m + 1]]
+                    d_b[m] += x * float(np.sum(G[v, c] * (X @ D @ Y)))
+    return d_h, d_b

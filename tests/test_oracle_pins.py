@@ -349,3 +349,109 @@ def test_two_taxon_jc69_branch_derivative():
     want = same + diff + same
     np.testing.assert_allclose(d_branch[0], want, rtol=1e-12)
     np.testing.assert_allclose(d_branch[1], want, rtol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Time gradient: node heights and epoch boundaries
+# ---------------------------------------------------------------------------
+
+
+def _shifted(prob, node=None, boundary=None, delta=0.0):
+    p = copy.deepcopy(prob)
+    if node is not None:
+        p.height = p.height.copy()
+        p.height[node] += delta
+    if boundary is not None:
+        p.boundaries = np.asarray(p.boundaries, float).copy()
+        p.boundaries[boundary] += delta
+    return p
+
+
+def _central(prob, h=1e-6, **where):
+    return (O.log_likelihood(_shifted(prob, delta=h, **where)) -
+            O.log_likelihood(_shifted(prob, delta=-h, **where))) / (2 * h)
+
+
+def _one_sided(prob, sign, h=1e-4, **where):
+    """Richardson-extrapolated one-sided difference (error O(h^2)) towards sign."""
+    f0 = O.log_likelihood(prob)
+    d = lambda s: sign * (O.log_likelihood(_shifted(prob, delta=sign * s, **where)) - f0) / s
+    return 2 * d(h / 2) - d(h)
+
+
+def _time_problem(seed, reversible):
+    rng = np.random.default_rng(seed)
+    prob = W.random_problem(rng, 6, 4, 9, n_categories=2, n_intervals=3, n_processes=2,
+                            reversible=reversible, tip_height_max=0.3, branch_rate_spread=0.2,
+                            missing_frac=0.05)
+    prob.interval_process = np.array([0, 1, 0], np.int32)  # every boundary separates different processes
+    gap = min(abs(h - b) for h in prob.height for b in prob.boundaries)
+    assert gap > 1e-4, "nodes must sit away from the boundaries for central differences"
+    return prob
+
+
+@pytest.mark.parametrize("seed,reversible", [(31, True), (32, False)])
+def test_time_gradient_against_central_differences(seed, reversible):
+    prob = _time_problem(seed, reversible)
+    d_h, d_b = O.time_gradient(prob)
+    scale = np.abs(d_h).max()
+    for x in range(prob.parent.shape[0]):
+        np.testing.assert_allclose(d_h[x], _central(prob, node=x), rtol=1e-6, atol=1e-7 * scale)
+    for m in range(len(prob.boundaries)):
+        np.testing.assert_allclose(d_b[m], _central(prob, boundary=m), rtol=1e-6, atol=1e-7 * scale)
+    assert np.all(d_b != 0.0)
+
+
+def test_time_gradient_translation_and_scaling_identities():
+    """Moving every height and boundary by the same amount changes no stretch, so the
+    derivatives sum to zero; scaling them all by c equals scaling every Q by c (Euler)."""
+    prob = _time_problem(33, False)
+    d_h, d_b = O.time_gradient(prob)
+    total = np.abs(d_h).sum() + np.abs(d_b).sum()
+    assert abs(d_h.sum() + d_b.sum()) <= 1e-11 * total
+    _, d_Q = O.gradient(prob, wrt=("Q",))
+    lhs = float(d_h @ prob.height + d_b @ prob.boundaries)
+    rhs = float(sum(np.sum(dq * q) for dq, q in zip(d_Q, prob.Q)))
+    np.testing.assert_allclose(lhs, rhs, rtol=1e-10)
+
+
+def test_time_gradient_single_epoch_is_the_branch_gradient_chained():
+    """One interval: l_v = r_v (h_parent - h_v), so dlogL/dh_u = sum over u's children of
+    r_v dlogL/dl_v minus r_u dlogL/dl_u, with the branch gradient pinned above."""
+    rng = np.random.default_rng(34)
+    prob = W.random_problem(rng, 7, 3, 6, n_categories=2, n_intervals=1, reversible=True,
+                            tip_height_max=0.2, branch_rate_spread=0.3)
+    d_h, d_b = O.time_gradient(prob)
+    g, _ = O.gradient(prob, wrt=("branch",))
+    want = np.zeros_like(d_h)
+    for v, u in enumerate(prob.parent):
+        if u >= 0:
+            want[u] += prob.branch_rate[v] * g[v]
+            want[v] -= prob.branch_rate[v] * g[v]
+    np.testing.assert_allclose(d_h, want, rtol=1e-11, atol=1e-11 * np.abs(want).max())
+    assert d_b.shape == (0,)
+
+
+def test_time_gradient_at_ties_is_the_upward_one_sided_derivative():
+    """A tip and an internal node exactly on boundaries: the derivative is the one-sided
+    derivative for an increasing height or boundary (the side the half-open intervals give
+    the tie to), and it differs from the downward one."""
+    Q0 = np.array([[-1.0, 0.6, 0.4], [0.3, -0.5, 0.2], [0.5, 0.5, -1.0]])
+    Q1 = np.array([[-0.4, 0.1, 0.3], [1.2, -1.5, 0.3], [0.2, 0.9, -1.1]])
+    # tips 0..3, node 4 = (0, 1) on boundary 1 (0.6), node 5 = (4, 2), root 6 = (5, 3);
+    # tip 2 on boundary 0 (0.25)
+    parent = [4, 4, 5, 6, 5, 6, -1]
+    height = [0.0, 0.1, 0.25, 0.0, 0.6, 0.8, 1.0]
+    tips = np.array([[0, 1, 2, 0, 1, 3], [1, 1, 0, 2, 2, 0], [2, 0, 1, 1, 3, 2], [0, 2, 2, 1, 0, 1]])
+    prob = make_problem(parent, height, [Q0, Q1], [0.25, 0.6], [0, 1, 0], tips, [0.3, 0.3, 0.4],
+                        cat_rates=(0.5, 1.5), cat_weights=(0.5, 0.5), branch_rate=[1.1, 0.9, 1.0, 1.2, 0.8, 1.0, 1.0])
+    d_h, d_b = O.time_gradient(prob)
+    for where, got in ((dict(node=2), d_h[2]), (dict(node=4), d_h[4]), (dict(boundary=0), d_b[0]),
+                       (dict(boundary=1), d_b[1])):
+        up = _one_sided(prob, +1, **where)
+        down = _one_sided(prob, -1, **where)
+        np.testing.assert_allclose(got, up, rtol=1e-6, err_msg=str(where))
+        assert abs(up - down) > 1e-3 * abs(up), where
+    # nodes away from the boundaries keep their two-sided derivative
+    for x in (0, 1, 3, 5, 6):
+        np.testing.assert_allclose(d_h[x], _central(prob, node=x), rtol=1e-6, atol=1e-9)
