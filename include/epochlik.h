@@ -64,6 +64,9 @@ extern "C" {
 
 #define EPOCH_GRAD_BRANCH 0x1u   /* keep what log_likelihood_gradient needs for dlogL/dl_b */
 #define EPOCH_GRAD_Q 0x2u        /* ... and for dlogL/dQ_s */
+#define EPOCH_GRAD_TIME 0x4u     /* ... and for epoch_time_gradient (implies EPOCH_GRAD_BRANCH; the
+                                  * 4-state kernels then run per tree level, and an HBM budget on the
+                                  * 4-state path is refused) */
 
 #define EPOCH_KERNEL_AUTO 0      /* pick the specialised kernels where they exist */
 #define EPOCH_KERNEL_GENERIC 1   /* force the generic any-K kernels (reference GPU path) */
@@ -193,6 +196,19 @@ int root_log_likelihood(EpochInstance* inst, double* logL, double* site_logL);
  *     eigensystems were set.  Needs EPOCH_GRAD_Q.
  * Requires root_log_likelihood for the current state. */
 int log_likelihood_gradient(EpochInstance* inst, double* d_branch, double* d_Q);
+
+/* Node-height and epoch-boundary gradients (an addition: the paper fixes the
+ * transition times and names estimating them as the natural next step,
+ * Discussion).  Heights and boundaries enter logL only through the stretch
+ * durations of Eq. 7; branch rates are held fixed.
+ *   d_height: host [2N-1] or NULL: dlogL/dh_v for every node height (tips too).
+ *   d_boundary: host [M-1] or NULL: dlogL/db_m for every boundary.
+ * Intervals are half-open [b_{m-1}, b_m), so for a node exactly on a boundary
+ * (a tie) the value is the one-sided derivative for an increasing height or
+ * boundary.  Needs EPOCH_GRAD_TIME and root_log_likelihood for the current
+ * state; runs the branch-gradient pass first when it has not run for this
+ * state.  Computed in FP64 from the branch adjoints of that pass. */
+int epoch_time_gradient(EpochInstance* inst, double* d_height, double* d_boundary);
 
 /* One whole evaluation with a single host synchronisation: the transition
  * matrices (Eq. 3, 6, 7), the post-order partials (Eq. 4), the root

@@ -26,6 +26,7 @@ EPOCH_FP32 = 1
 EPOCH_FP64 = 2
 EPOCH_GRAD_BRANCH = 0x1
 EPOCH_GRAD_Q = 0x2
+EPOCH_GRAD_TIME = 0x4
 EPOCH_KERNEL_AUTO = 0
 EPOCH_KERNEL_GENERIC = 1
 
@@ -38,7 +39,7 @@ EXPORTED = [
     "epoch_plan_segments", "epoch_set_timing", "epoch_get_timing", "epoch_bandwidth_probe",
     "epoch_batch_create", "epoch_batch_evaluate", "epoch_batch_gradients", "epoch_batch_target_blocks",
     "epoch_batch_destroy", "epoch_set_option", "epoch_plan_walk", "epoch_workspace_bytes",
-    "epoch_eigen_residual_noalloc", "epoch_set_branch_rates", "epoch_get_work_counts",
+    "epoch_eigen_residual_noalloc", "epoch_set_branch_rates", "epoch_get_work_counts", "epoch_time_gradient",
 ]
 EPOCH_EVAL_LOGL = 0x1
 EPOCH_EVAL_GRAD_BRANCH = 0x2
@@ -121,6 +122,7 @@ def load() -> ctypes.CDLL:
         "epoch_eigen_residual_noalloc": (i32, [i32, i32, P, P, P, P, P, P, P]),
         "epoch_set_branch_rates": (i32, [P, i32, ip, dp]),
         "epoch_get_work_counts": (i32, [P, ctypes.POINTER(ctypes.c_int64)]),
+        "epoch_time_gradient": (i32, [P, dp, dp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libepochlik.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-HIP_SOURCES = ["epochlik.hip", "dispatch.hip", "kernels_generic.hip", "kernels_qgrad.hip", "kernels_nuc.hip", "kernels_probe.hip", "kernels_codon.hip", "kernels_pmfma.hip", "kernels_walk.hip", "kernels_eigcheck.hip", "incremental.hip", "batch.hip"]
+HIP_SOURCES = ["epochlik.hip", "dispatch.hip", "kernels_generic.hip", "kernels_qgrad.hip", "kernels_nuc.hip", "kernels_probe.hip", "kernels_codon.hip", "kernels_pmfma.hip", "kernels_walk.hip", "kernels_eigcheck.hip", "incremental.hip", "kernels_tgrad.hip", "batch.hip"]
 CPP_SOURCES = ["planner.cpp"]
 
 ARCH = os.environ.get("EPOCHLIK_ARCH", "gfx950")

@@ -162,10 +162,12 @@ int fastpath_post(EpochInstance* in) {
     EPOCH_PHASE(1, launch_post(in));
   }
   incremental_done(in);
+  in->eval_gen++;
   return EPOCH_OK;
 }
 
 int fastpath_root(EpochInstance* in) {
+  in->eval_gen++;  // new weights or root frequencies change the branch adjoints too
   if (!nuc(in) && !codon(in) && in->gen_nchunks > 1) return EPOCH_OK;  // formed with the chunks' partials
   EPOCH_PHASE(2, nuc(in) ? launch_nuc_root(in) : (codon(in) ? launch_codon_root(in) : launch_root_generic(in)));
   return EPOCH_OK;
@@ -186,6 +188,7 @@ int fastpath_gradient(EpochInstance* in, bool want_Q) {
     EPOCH_PHASE(4, launch_grad_branch_generic(in));
   }
   if (want_Q) EPOCH_PHASE(5, launch_grad_Q(in));
+  in->G_gen = in->eval_gen;
   return EPOCH_OK;
 }
 

@@ -105,7 +105,7 @@ struct WorkspaceItem {
 };
 std::vector<WorkspaceItem> workspace_items(const EpochConfig& c, int Kp) {
   const size_t N = c.n_tips, P = c.n_patterns, C = c.n_categories, R = c.precision == EPOCH_FP64 ? 8 : 4;
-  const bool grad = (c.flags & (EPOCH_GRAD_BRANCH | EPOCH_GRAD_Q)) != 0;
+  const bool grad = (c.flags & (EPOCH_GRAD_BRANCH | EPOCH_GRAD_Q | EPOCH_GRAD_TIME)) != 0;
   std::vector<WorkspaceItem> v = {{&EpochInstance::tips, N * P},
                                   {&EpochInstance::weights, P * sizeof(double)},
                                   {&EpochInstance::weightsT, P * R},
@@ -173,7 +173,7 @@ bool codon_budget_config(const EpochConfig& c) {
 // the dlogL/dP slots (at most one 64 x 64 FP32 slot per child branch and tile
 // of 64 patterns).
 size_t codon_bytes_per_pattern(const EpochConfig& c) {
-  const bool grad = (c.flags & (EPOCH_GRAD_BRANCH | EPOCH_GRAD_Q)) != 0;
+  const bool grad = (c.flags & (EPOCH_GRAD_BRANCH | EPOCH_GRAD_Q | EPOCH_GRAD_TIME)) != 0;
   const size_t Nm1 = (size_t)c.n_tips - 1;
   return Nm1 * (64 * sizeof(float) + sizeof(int32_t)) +
          (grad ? Nm1 * 64 * sizeof(float) + 2 * Nm1 * kCodonSlotBytes / 64 : 0);
@@ -182,7 +182,7 @@ size_t codon_bytes_per_pattern(const EpochConfig& c) {
 // Device bytes one pattern of a chunk costs on the generic path: partials and
 // scale exponents of every internal node, and outside vectors with a gradient.
 size_t generic_bytes_per_pattern(const EpochConfig& c) {
-  const bool grad = (c.flags & (EPOCH_GRAD_BRANCH | EPOCH_GRAD_Q)) != 0;
+  const bool grad = (c.flags & (EPOCH_GRAD_BRANCH | EPOCH_GRAD_Q | EPOCH_GRAD_TIME)) != 0;
   const size_t Nm1 = (size_t)c.n_tips - 1, R = c.precision == EPOCH_FP64 ? 8 : 4;
   const size_t row = (size_t)c.n_categories * padded_states(c.n_states) * R;
   return Nm1 * (row * (grad ? 2 : 1) + sizeof(int32_t));
@@ -218,7 +218,7 @@ int epoch_create(const EpochConfig* cfg, EpochInstance** out) {
   if (c.max_intervals < 1) return set_error(EPOCH_ERR_ARG, "max_intervals must be >= 1");
   if (c.precision != EPOCH_FP32 && c.precision != EPOCH_FP64)
     return set_error(EPOCH_ERR_ARG, "precision must be EPOCH_FP32 or EPOCH_FP64");
-  if (c.flags & ~(EPOCH_GRAD_BRANCH | EPOCH_GRAD_Q)) return set_error(EPOCH_ERR_ARG, "unknown flags");
+  if (c.flags & ~(EPOCH_GRAD_BRANCH | EPOCH_GRAD_Q | EPOCH_GRAD_TIME)) return set_error(EPOCH_ERR_ARG, "unknown flags");
   if (c.kernel_path != EPOCH_KERNEL_AUTO && c.kernel_path != EPOCH_KERNEL_GENERIC)
     return set_error(EPOCH_ERR_ARG, "unknown kernel_path");
   if (c.reserved != 0) return set_error(EPOCH_ERR_ARG, "reserved must be 0");
@@ -228,6 +228,9 @@ int epoch_create(const EpochConfig* cfg, EpochInstance** out) {
   const bool nuc_budget = c.hbm_budget_bytes > 0 && c.n_states == 4 && c.kernel_path == EPOCH_KERNEL_AUTO;
   const bool codon_budget = c.hbm_budget_bytes > 0 && codon_budget_config(c);
   const bool gen_budget = c.hbm_budget_bytes > 0 && !nuc_budget && !codon_budget;
+  if (nuc_budget && (c.flags & EPOCH_GRAD_TIME))
+    return set_error(EPOCH_ERR_ARG, "hbm_budget_bytes with the 4-state kernels cannot be combined with EPOCH_GRAD_TIME "
+                                    "(the time gradient needs the branch adjoints of the level kernels)");
   if (nuc_budget && (c.flags & EPOCH_GRAD_Q))
     return set_error(EPOCH_ERR_ARG,
                      "hbm_budget_bytes with the 4-state kernels cannot be combined with EPOCH_GRAD_Q "
@@ -256,6 +259,7 @@ int epoch_create(const EpochConfig* cfg, EpochInstance** out) {
   }
   auto* in = new EpochInstance();
   in->cfg = c;
+  if (c.flags & EPOCH_GRAD_TIME) in->cfg.flags |= EPOCH_GRAD_BRANCH;  // the time gradient reads the branch adjoints
   in->N = c.n_tips;
   in->P = c.n_patterns;
   in->K = c.n_states;
@@ -269,7 +273,7 @@ int epoch_create(const EpochConfig* cfg, EpochInstance** out) {
   in->stream = static_cast<hipStream_t>(c.stream);
   (void)hipGetDevice(&in->device);
   const size_t Kp = in->Kp, KK = Kp * Kp, S = in->S, C = in->C, n = in->n_nodes, R = in->real_size;
-  const bool grad = (c.flags & (EPOCH_GRAD_BRANCH | EPOCH_GRAD_Q)) != 0;
+  const bool grad = (c.flags & (EPOCH_GRAD_BRANCH | EPOCH_GRAD_Q | EPOCH_GRAD_TIME)) != 0;
   in->h_V.assign(S * KK, 0.0);
   in->h_Vinv.assign(S * KK, 0.0);
   in->h_lre.assign(S * Kp, 0.0);
@@ -406,7 +410,8 @@ int epoch_destroy(EpochInstance* in) {
                     &in->pre, &in->site, &in->blocksum, &in->result, &in->Gpart, &in->G, &in->dbranch,
                     &in->qseg, &in->qscratch, &in->chain_items, &in->chain_scratch, &in->dQ, &in->seglist, &in->gslots, &in->codon_dev, &in->codon_aux,
                     &in->eigTT, &in->eig64T, &in->qtau, &in->nuc_nodes, &in->walk_ops,
-                    &in->walk_tcol, &in->walk_dpart, &in->walk_dummy, &in->walk_slots})
+                    &in->walk_tcol, &in->walk_dpart, &in->walk_dummy, &in->walk_slots, &in->inc_dev, &in->tg_i,
+                    &in->tg_d})
     release(*b);
   delete in;
   return EPOCH_OK;
@@ -741,6 +746,7 @@ int set_tree_epochs(EpochInstance* in, const int32_t* parent, const double* heig
     EPOCH_TRY(upload(in, in->seglist.ptr, all.data(), all.size() * sizeof(int32_t)));
   }
   in->plan = std::move(plan);
+  if (in->cfg.flags & EPOCH_GRAD_TIME) EPOCH_TRY(tgrad_prepare(in));
   in->dirty.assign(in->n_nodes, 0);
   mark_dirty_all(in);
   in->have_tree = true;
@@ -801,6 +807,20 @@ int log_likelihood_gradient(EpochInstance* in, double* d_branch, double* d_Q) {
   EPOCH_TRY(fastpath_gradient(in, d_Q != nullptr));
   if (d_branch) EPOCH_TRY(download(in, d_branch, in->dbranch.ptr, (size_t)in->n_nodes * sizeof(double)));
   if (d_Q) EPOCH_TRY(download(in, d_Q, in->dQ.ptr, (size_t)in->S * in->K * in->K * sizeof(double)));
+  return EPOCH_OK;
+}
+
+int epoch_time_gradient(EpochInstance* in, double* d_height, double* d_boundary) {
+  if (!in) return set_error(EPOCH_ERR_ARG, "NULL instance");
+  if (!(in->cfg.flags & EPOCH_GRAD_TIME)) return set_error(EPOCH_ERR_STATE, "instance created without EPOCH_GRAD_TIME");
+  if (!in->logL_valid) return set_error(EPOCH_ERR_STATE, "root_log_likelihood has not been called for this state");
+  if (!d_height && !d_boundary) return EPOCH_OK;
+  if (in->G_gen != in->eval_gen) EPOCH_TRY(fastpath_gradient(in, false));  // the branch adjoints of this state
+  double *dh = nullptr, *db = nullptr;
+  EPOCH_TRY(launch_time_gradient(in, &dh, &db));
+  if (d_height) EPOCH_TRY(download(in, d_height, dh, (size_t)in->n_nodes * sizeof(double)));
+  if (d_boundary && in->tg_n_bound > 0)
+    EPOCH_TRY(download(in, d_boundary, db, (size_t)in->tg_n_bound * sizeof(double)));
   return EPOCH_OK;
 }
 

@@ -203,6 +203,14 @@ struct EpochInstance {
   epochlik::DevBuf inc_dev;        // device copy of the restricted lists
   int64_t work_P = 0, work_partials = 0;  // matrices and node partials formed by the last P stage / post-order pass
 
+  // node-height and boundary gradients (EPOCH_GRAD_TIME)
+  epochlik::DevBuf tg_i;           // int32 process above / below each node, crossing offsets, phi; int4 crossings
+  epochlik::DevBuf tg_d;           // double Q_s, end terms, crossing terms, outputs, scratch
+  size_t tg_cross_offset = 0;      // byte offset of the crossings in tg_i
+  int tg_n_cross = 0, tg_n_bound = 0;
+  uint64_t eval_gen = 0;           // bumped by every post-order pass and root reduction
+  uint64_t G_gen = ~0ull;          // eval_gen of the last gradient pass (the branch adjoints G on the device)
+
   // per-phase timing (epoch_set_timing)
   bool timing = false;
   hipEvent_t ev[EPOCH_N_PHASES][2] = {};
@@ -241,6 +249,10 @@ int ensure(DevBuf& b, size_t bytes);
 // FP64 eigensystem check (kernels_eigcheck.hip): d_out[0] receives the residual, scratch follows it
 int launch_eigen_check(EpochInstance* in, int s, const double* dQ, double* d_out);
 int eigen_check_tiles(int K);  // scratch rows (3 doubles each) per system
+int launch_q_reconstruct(EpochInstance* in, double* d_Q, double* part);  // Q_s = V B V^-1, FP64 [S][Kp][Kp]
+// node-height and boundary gradients (kernels_tgrad.hip)
+int tgrad_prepare(EpochInstance* in);
+int launch_time_gradient(EpochInstance* in, double** d_height, double** d_bound);
 int launch_eigen_check_n(hipStream_t st, int K, int n, int ld, long mat_stride, int vec_stride, const double* V,
                          const double* Vi, const double* lr, const double* li, const double* Q, double* part,
                          double* out);

@@ -30,7 +30,8 @@ __global__ __launch_bounds__(256) void eigen_check_tile_kernel(const double* __r
                                                                const double* __restrict__ li,
                                                                const double* __restrict__ Q, int K, int ld,
                                                                long mat_stride, int vec_stride,
-                                                               double* __restrict__ part) {
+                                                               double* __restrict__ part,
+                                                               double* __restrict__ rec_out) {
   const int s = blockIdx.y;
   const int nt = (K + kTile - 1) / kTile;
   const int ti = blockIdx.x / nt, tj = blockIdx.x % nt;
@@ -39,7 +40,7 @@ __global__ __launch_bounds__(256) void eigen_check_tile_kernel(const double* __r
   Vi += s * mat_stride;
   lr += (long)s * vec_stride;
   if (li) li += (long)s * vec_stride;
-  Q += (long)s * K * K;
+  if (Q) Q += (long)s * K * K;
   __shared__ double sVB[kTile][kTile + 1], sV[kTile][kTile + 1], sVi[kTile][kTile + 1];
   double rec = 0.0, id = 0.0;
   for (int l0 = 0; l0 < K; l0 += kTile) {
@@ -76,10 +77,11 @@ __global__ __launch_bounds__(256) void eigen_check_tile_kernel(const double* __r
   const int i = ti * kTile + ty, j = tj * kTile + tx;
   double vals[3] = {0.0, 0.0, 0.0};
   if (i < K && j < K) {
-    const double q = Q[i * K + j];
+    const double q = Q ? Q[i * K + j] : 0.0;
     vals[0] = fabs(rec - q);
     vals[1] = fabs(id - (i == j ? 1.0 : 0.0));
     vals[2] = fabs(q);
+    if (rec_out) rec_out[s * mat_stride + (long)i * ld + j] = rec;  // Q_s = V B V^-1, same layout as V
   }
   __shared__ double sm[256];
   for (int q = 0; q < 3; ++q) {
@@ -120,11 +122,22 @@ int launch_eigen_check_n(hipStream_t st, int K, int n, int ld, long mat_stride, 
                          double* out) {
   const int tiles = eigen_check_tiles(K);
   hipLaunchKernelGGL(eigen_check_tile_kernel, dim3(tiles, n), dim3(256), 0, st, V, Vi, lr, li, Q, K, ld, mat_stride,
-                     vec_stride, part);
+                     vec_stride, part, nullptr);
   int rc = hip_check(hipGetLastError(), "eigen check launch");
   if (rc) return rc;
   hipLaunchKernelGGL(eigen_check_finish_kernel, dim3((n + 255) / 256), dim3(256), 0, st, part, tiles, n, out);
   return hip_check(hipGetLastError(), "eigen check finish launch");
+}
+
+int launch_q_reconstruct(EpochInstance* in, double* d_Q, double* part) {
+  // every process's Q_s = V B V^-1 in FP64, padded layout [S][Kp][Kp] (padding left as it is)
+  const size_t KK = (size_t)in->Kp * in->Kp;
+  const double* base = static_cast<const double*>(in->eig64.ptr);
+  const double* lr = base + 2 * in->S * KK;
+  const double* li = lr + (size_t)in->S * in->Kp;
+  hipLaunchKernelGGL(eigen_check_tile_kernel, dim3(eigen_check_tiles(in->K), in->S), dim3(256), 0, in->stream, base,
+                     base + in->S * KK, lr, li, (const double*)nullptr, in->K, in->Kp, (long)KK, in->Kp, part, d_Q);
+  return hip_check(hipGetLastError(), "Q reconstruction launch");
 }
 
 int launch_eigen_check(EpochInstance* in, int s, const double* dQ, double* d_out) {

@@ -794,7 +794,8 @@ int walk_budget_threshold(const EpochInstance* in) {
 int walk_prepare(EpochInstance* in) {
   in->walk_ok = false;
   in->root_slot = in->plan.root - in->N;
-  if (in->path != 1 || in->walk_enable == 0) return EPOCH_OK;
+  // the time gradient reads the branch adjoints G that only the level kernels form
+  if (in->path != 1 || in->walk_enable == 0 || (in->cfg.flags & EPOCH_GRAD_TIME)) return EPOCH_OK;
   if (in->walk_enable < 0 && (in->fp64 || walk_tiles(in) > kWalkAutoTiles)) return EPOCH_OK;
   int rt = (in->cfg.flags & EPOCH_GRAD_Q) ? 2 : std::max(2, in->walk_recompute);
   if (in->budget > 0) {

@@ -29,7 +29,7 @@ bool fail(std::string& err, const char* msg, long a = -1, long b = -1) {
 // (0-based boundaries b_0..b_{M-2}).  Walk from the interval holding the
 // stretch just below hu down to the one holding the stretch just above hv.
 void segment_branch(double hu, double hv, int M, const double* b, const int32_t* phi,
-                    std::vector<int32_t>& proc, std::vector<double>& dur) {
+                    std::vector<int32_t>& proc, std::vector<double>& dur, std::vector<int32_t>& interval) {
   if (!(hu > hv)) return;
   // k_top: number of boundaries strictly below hu
   int k_top = 0;
@@ -42,6 +42,7 @@ void segment_branch(double hu, double hv, int M, const double* b, const int32_t*
     if (top > bot) {
       proc.push_back(phi[k]);
       dur.push_back(top - bot);
+      interval.push_back(k);
     }
     if (lo <= hv) break;
   }
@@ -162,12 +163,14 @@ int plan_tree(int n_tips, const int32_t* parent, const double* height, const dou
     P.tau[v] = tau;
     size_t before = P.seg_process.size();
     segment_branch(height[u], height[v], n_intervals, boundaries, interval_process, P.seg_process,
-                   P.seg_time);
+                   P.seg_time, P.seg_interval);
     for (size_t k = before; k < P.seg_process.size(); ++k)
       P.seg_frac.push_back(tau > 0 ? P.seg_time[k] / tau : 0.0);
     P.max_segments = std::max<int>(P.max_segments, (int)(P.seg_process.size() - before));
   }
   P.seg_offset[n] = (int32_t)P.seg_process.size();
+  if (n_intervals > 1) P.boundaries.assign(boundaries, boundaries + n_intervals - 1);
+  P.interval_process.assign(interval_process, interval_process + n_intervals);
   out = std::move(P);
   return 0;
 }

@@ -30,7 +30,10 @@ struct TreePlan {
   std::vector<int32_t> seg_process;  // [n_seg]
   std::vector<double> seg_time;      // [n_seg] duration in height units
   std::vector<double> seg_frac;      // [n_seg] duration / tau (0 when tau == 0)
+  std::vector<int32_t> seg_interval; // [n_seg] interval index of each segment
   int max_segments = 0;              // longest segment list of any branch
+  std::vector<double> boundaries;          // [M-1] ascending boundary heights
+  std::vector<int32_t> interval_process;   // [M] process of each interval
 };
 
 // Programs of the four-state tree-walk kernels (one wavefront carries a tile of

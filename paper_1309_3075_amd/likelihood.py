@@ -32,7 +32,7 @@ class EpochLikelihood:
     def __init__(self, n_tips: int, n_patterns: int, n_states: int, n_categories: int = 1,
                  n_processes: int = 1, max_intervals: int = 1, precision: str = "fp64",
                  grad_branch: bool = False, grad_Q: bool = False, kernel: str = "auto",
-                 stream=None, hbm_budget_bytes: int = 0, workspace=None):
+                 stream=None, hbm_budget_bytes: int = 0, workspace=None, grad_time: bool = False):
         lib = _abi.load()
         cfg = _abi.EpochConfig()
         cfg.n_tips = n_tips
@@ -42,7 +42,8 @@ class EpochLikelihood:
         cfg.n_processes = n_processes
         cfg.max_intervals = max_intervals
         cfg.precision = {"fp32": _abi.EPOCH_FP32, "fp64": _abi.EPOCH_FP64}[precision]
-        cfg.flags = (_abi.EPOCH_GRAD_BRANCH if grad_branch else 0) | (_abi.EPOCH_GRAD_Q if grad_Q else 0)
+        cfg.flags = (_abi.EPOCH_GRAD_BRANCH if grad_branch else 0) | (_abi.EPOCH_GRAD_Q if grad_Q else 0) | \
+            (_abi.EPOCH_GRAD_TIME if grad_time else 0)
         cfg.kernel_path = {"auto": _abi.EPOCH_KERNEL_AUTO, "generic": _abi.EPOCH_KERNEL_GENERIC}[kernel]
         cfg.reserved = 0
         cfg.hbm_budget_bytes = int(hbm_budget_bytes)
@@ -60,6 +61,7 @@ class EpochLikelihood:
         self.n_tips, self.n_patterns, self.n_states = n_tips, n_patterns, n_states
         self.n_categories, self.n_processes = n_categories, n_processes
         self.n_nodes = 2 * n_tips - 1
+        self.n_boundaries = 0
 
     @staticmethod
     def workspace_bytes(n_tips: int, n_patterns: int, n_states: int, n_categories: int = 1,
@@ -130,6 +132,7 @@ class EpochLikelihood:
         b = _f64(boundaries) if len(boundaries) else None
         phi = _i32(interval_process)
         check(self._lib.set_tree_epochs(self._h, _ip(par), _dp(h), _dp(r), len(phi), _dp(b), _ip(phi)))
+        self.n_boundaries = len(phi) - 1
 
     def set_branch_rates(self, nodes, rates):
         """New rates for the branches above `nodes` (epoch_set_branch_rates): the next
@@ -161,6 +164,14 @@ class EpochLikelihood:
         dq = np.zeros((self.n_processes, self.n_states, self.n_states)) if Q else None
         check(self._lib.log_likelihood_gradient(self._h, _dp(db), _dp(dq)))
         return db, dq
+
+    def time_gradient(self):
+        """(dlogL/dh for every node height [2N-1], dlogL/db for every boundary [M-1])
+        (epoch_time_gradient; needs grad_time and a log-likelihood for the current state)."""
+        dh = np.zeros(self.n_nodes)
+        db = np.zeros(max(self.n_boundaries, 0))
+        check(self._lib.epoch_time_gradient(self._h, _dp(dh), _dp(db) if len(db) else None))
+        return dh, db
 
     def evaluate(self, branch: bool = False, Q: bool = False, site: bool = False):
         """One whole evaluation with one host synchronisation (epoch_evaluate):
@@ -208,11 +219,11 @@ class EpochLikelihood:
 
 def from_problem(prob, precision: str = "fp64", grad_branch: bool = False, grad_Q: bool = False,
                  kernel: str = "auto", use_pi: bool = True, options: Optional[dict] = None,
-                 hbm_budget_bytes: int = 0, workspace=None) -> EpochLikelihood:
+                 hbm_budget_bytes: int = 0, workspace=None, grad_time: bool = False) -> EpochLikelihood:
     """Instance loaded with every input of a generated problem (options: see set_option)."""
     lik = EpochLikelihood(prob.n_tips, prob.n_patterns, prob.n_states, len(prob.cat_rates),
                           prob.n_processes, prob.n_intervals, precision, grad_branch, grad_Q, kernel,
-                          hbm_budget_bytes=hbm_budget_bytes, workspace=workspace)
+                          hbm_budget_bytes=hbm_budget_bytes, workspace=workspace, grad_time=grad_time)
     for k, v in (options or {}).items():
         lik.set_option(k, v)
     lik.set_tip_states(prob.tips)
