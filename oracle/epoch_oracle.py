@@ -115,13 +115,19 @@ def transition_matrices(prob):
 # ---------------------------------------------------------------------------
 
 
-def tip_partials(states, K):
-    """0/1 indicator vectors [P][K]; state K means missing (all ones)."""
+def tip_partials(states, K, ambiguity=None):
+    """0/1 indicator vectors [P][K] of the possible states (text after Eq. 4:
+    a (partially) observed tip): code < K one state, K every state (missing),
+    K + 1 + a the states of ambiguity set a."""
     states = np.asarray(states)
     L = np.zeros((states.shape[0], K))
-    obs = states < K
-    L[np.arange(states.shape[0])[obs], states[obs]] = 1.0
-    L[~obs] = 1.0
+    for p, st in enumerate(states):
+        if st < K:
+            L[p, st] = 1.0
+        elif st == K:
+            L[p, :] = 1.0
+        else:
+            L[p, :] = np.asarray(ambiguity)[st - K - 1]
     return L
 
 
@@ -150,7 +156,7 @@ def post_order(prob, P=None, rescale=True):
     part = [None] * n_nodes
     logscale = [np.zeros(npat) for _ in range(n_nodes)]
     for t in range(N):
-        L = tip_partials(prob.tips[t], K)
+        L = tip_partials(prob.tips[t], K, getattr(prob, "ambiguity", None))
         part[t] = np.broadcast_to(L, (C, npat, K)).copy()
     for u in range(N, n_nodes):      # children have smaller indices
         v, w = ch[u]

@@ -300,9 +300,10 @@ class Problem:
     pi_root: np.ndarray         # [K]
     cat_rates: np.ndarray       # [C]
     cat_weights: np.ndarray     # [C]
-    tips: np.ndarray            # [N][P] int32, value K = missing
+    tips: np.ndarray            # [N][P] int32, value K = missing, K + 1 + a = ambiguity set a
     weights: np.ndarray         # [P] float64
     seed: int = 0
+    ambiguity: Optional[np.ndarray] = None  # [A][K] 0/1 state sets of the tip codes K + 1 + a
 
     @property
     def n_tips(self):
@@ -463,7 +464,8 @@ def make_batch(n_problems: int = 64, replicate: int = 0, scale: float = 1.0) -> 
 def random_problem(rng: np.random.Generator, n_tips: int, n_states: int, n_patterns: int,
                    n_categories: int = 1, n_intervals: int = 2, n_processes: Optional[int] = None,
                    reversible: bool = True, tip_height_max: float = 0.0, missing_frac: float = 0.0,
-                   branch_rate_spread: float = 0.0, root_height: float = 1.0) -> Problem:
+                   branch_rate_spread: float = 0.0, root_height: float = 1.0,
+                   ambiguous_frac: float = 0.0, n_ambiguity_sets: int = 3) -> Problem:
     """Small random problem for tests: random Q's, random (not simulated) tip states."""
     K = n_states
     S = n_processes or n_intervals
@@ -490,10 +492,19 @@ def random_problem(rng: np.random.Generator, n_tips: int, n_states: int, n_patte
     tips = rng.integers(0, K, size=(n_tips, n_patterns)).astype(np.int32)
     if missing_frac > 0:
         tips[rng.random(tips.shape) < missing_frac] = K
+    amb = None
+    if ambiguous_frac > 0:
+        # partially observed tips: random state sets of 2 .. K-1 states (K >= 3), codes K + 1 + a
+        amb = np.zeros((n_ambiguity_sets, K), dtype=np.int32)
+        for a in range(n_ambiguity_sets):
+            size = int(rng.integers(2, max(3, K)))
+            amb[a, rng.choice(K, size=min(size, K), replace=False)] = 1
+        sel = rng.random(tips.shape) < ambiguous_frac
+        tips[sel] = K + 1 + rng.integers(0, n_ambiguity_sets, size=int(sel.sum()))
     weights = rng.integers(1, 6, size=n_patterns).astype(np.float64)
     br = np.exp(rng.normal(0.0, branch_rate_spread, size=parent.shape[0])) if branch_rate_spread else np.ones(parent.shape[0])
     pi_root = _dirichlet(rng, 3.0, K)
     return Problem(name="random", parent=parent, height=height, branch_rate=br,
                    boundaries=bounds, interval_process=phi, Q=Qs, pi_process=pis,
                    pi_root=pi_root, cat_rates=np.asarray(rates, float),
-                   cat_weights=np.asarray(wts, float), tips=tips, weights=weights)
+                   cat_weights=np.asarray(wts, float), tips=tips, weights=weights, ambiguity=amb)
