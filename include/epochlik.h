@@ -127,10 +127,19 @@ int epoch_create(const EpochConfig* cfg, EpochInstance** out);
 /* Free every device buffer of the instance (NULL is accepted). */
 int epoch_destroy(EpochInstance* inst);
 
-/* Tip data (text after Eq. 4: tips are 0/1 indicators of the observed state).
+/* Tip data (text after Eq. 4: tips are 0/1 indicators of the (partially)
+ * observed state).
  * states: host [N][P] row-major int32; value in [0, K) = observed state,
- * value K = missing (all-ones vector).  Any other value -> EPOCH_ERR_ARG. */
+ * value K = missing (all-ones vector), value K + 1 + a = ambiguity set a of
+ * epoch_set_tip_ambiguities (the indicator of the states in the set).  Any
+ * other value -> EPOCH_ERR_ARG. */
 int epoch_set_tip_states(EpochInstance* inst, const int32_t* states);
+
+/* Ambiguity sets for partially observed tips (text after Eq. 4): sets: host
+ * [n_codes] bit masks, bit j = state j possible (non-empty, states < K), so
+ * that tip code K + 1 + a stands for set a.  n_codes in [0, 255 - K].  The tip
+ * states must be set (again) afterwards. */
+int epoch_set_tip_ambiguities(EpochInstance* inst, int32_t n_codes, const uint64_t* sets);
 
 /* Pattern weights w_p: host [P], finite and >= 0. */
 int epoch_set_pattern_weights(EpochInstance* inst, const double* weights);

@@ -301,6 +301,7 @@ int epoch_create(const EpochConfig* cfg, EpochInstance** out) {
   A(in->eig64T, 2 * S * KK * sizeof(double));
   A(in->check, (KK + 1 + 3 * (size_t)eigen_check_tiles(in->K)) * sizeof(double));  // Q, residual, tile maxima
   A(in->tips, N * P);
+  A(in->amb, 256 * sizeof(uint64_t));
   A(in->weights, P * sizeof(double));
   A(in->weightsT, P * R);
   A(in->pi, Kp * sizeof(double));
@@ -351,6 +352,7 @@ int epoch_create(const EpochConfig* cfg, EpochInstance** out) {
   if (rc == EPOCH_OK) rc = hip_check(hipMemsetAsync(in->eig64.ptr, 0, in->eig64.bytes, in->stream), "memset");
   if (rc == EPOCH_OK) rc = hip_check(hipMemsetAsync(in->eigTT.ptr, 0, in->eigTT.bytes, in->stream), "memset");
   if (rc == EPOCH_OK) rc = hip_check(hipMemsetAsync(in->eig64T.ptr, 0, in->eig64T.bytes, in->stream), "memset");
+  if (rc == EPOCH_OK) rc = hip_check(hipMemsetAsync(in->amb.ptr, 0, in->amb.bytes, in->stream), "memset");
   if (rc == EPOCH_OK) rc = hip_check(hipStreamSynchronize(in->stream), "create sync");
   if (rc != EPOCH_OK) {
     std::string keep = g_error;
@@ -411,22 +413,50 @@ int epoch_destroy(EpochInstance* in) {
                     &in->qseg, &in->qscratch, &in->chain_items, &in->chain_scratch, &in->dQ, &in->seglist, &in->gslots, &in->codon_dev, &in->codon_aux,
                     &in->eigTT, &in->eig64T, &in->qtau, &in->nuc_nodes, &in->walk_ops,
                     &in->walk_tcol, &in->walk_dpart, &in->walk_dummy, &in->walk_slots, &in->inc_dev, &in->tg_i,
-                    &in->tg_d})
+                    &in->tg_d, &in->amb})
     release(*b);
   delete in;
+  return EPOCH_OK;
+}
+
+int epoch_set_tip_ambiguities(EpochInstance* in, int32_t n_codes, const uint64_t* sets) {
+  if (!in) return set_error(EPOCH_ERR_ARG, "NULL instance");
+  if (n_codes < 0 || n_codes > 255 - in->K)
+    return set_error(EPOCH_ERR_ARG, "n_codes must be in [0, %d] (codes K + 1 .. K + n_codes fit a byte)", 255 - in->K);
+  if (n_codes > 0 && !sets) return set_error(EPOCH_ERR_ARG, "sets must not be NULL");
+  const uint64_t all = in->K == 64 ? ~0ull : ((1ull << in->K) - 1);
+  for (int a = 0; a < n_codes; ++a)
+    if (sets[a] == 0 || (sets[a] & ~all))
+      return set_error(EPOCH_ERR_ARG, "ambiguity set %d is empty or names a state >= %d", a, in->K);
+  std::vector<uint64_t> h(256, 0);
+  std::copy(sets, sets + n_codes, h.begin());
+  EPOCH_TRY(upload(in, in->amb.ptr, h.data(), h.size() * sizeof(uint64_t)));
+  in->h_amb.assign(sets, sets + n_codes);
+  in->have_tips = false;  // the tip states are read with the new table: set them again
+  mark_dirty_all(in);
+  in->partials_valid = in->logL_valid = false;
   return EPOCH_OK;
 }
 
 int epoch_set_tip_states(EpochInstance* in, const int32_t* states) {
   if (!in || !states) return set_error(EPOCH_ERR_ARG, "instance and states must not be NULL");
   const size_t n = (size_t)in->N * in->P;
+  const int max_code = in->K + (int)in->h_amb.size();
   std::vector<uint8_t> h(n);
   for (size_t k = 0; k < n; ++k) {
     const int32_t s = states[k];
-    if (s < 0 || s > in->K)
+    if (s < 0 || s > max_code)
       return set_error(EPOCH_ERR_ARG, "tip state %d at (%zu, %zu) outside [0, %d]", s, k / in->P,
-                       k % in->P, in->K);
+                       k % in->P, max_code);
     h[k] = (uint8_t)s;
+  }
+  if (in->path == 1) {
+    // the 4-state kernels read a tip as its state set (bit i = state i): one state, all four
+    // when missing, or the caller's ambiguity set
+    uint8_t code_set[256];
+    for (int s = 0; s <= max_code; ++s)
+      code_set[s] = (uint8_t)(s < 4 ? 1u << s : (s == 4 ? 15u : (unsigned)in->h_amb[s - 5]));
+    for (size_t k = 0; k < n; ++k) h[k] = code_set[h[k]];
   }
   EPOCH_TRY(upload(in, in->tips.ptr, h.data(), n));
   mark_dirty_all(in);

@@ -38,6 +38,7 @@ struct CodonProblem {
   double* result;
   const int32_t* left;
   const int32_t* right;
+  const uint64_t* amb;    // [256] state sets of the ambiguity codes K + 1 + a (bit j = state j)
   const int32_t* gslots;  // [2 n_nodes]: dlogL/dP partial slots written per branch, then each branch's first slot
   int N, P, K, root, n_nodes;
   int tip_stride;         // row stride of tips (the instance's pattern count; P is this chunk's)
@@ -144,7 +145,9 @@ struct EpochInstance {
   epochlik::DevBuf eigTT;      // V^T[S][Kp][Kp], (V^-1)^T[S][Kp][Kp] in the compute type
   epochlik::DevBuf eig64T;     // the same in double
   epochlik::DevBuf check;      // double scratch for the eigen check
-  epochlik::DevBuf tips;       // uint8 [N][P]
+  epochlik::DevBuf tips;       // uint8 [N][P]: state codes (4-state kernels: state sets, bit i = state i)
+  epochlik::DevBuf amb;        // uint64 [256]: state sets of the ambiguity codes K + 1 .. K + n_amb
+  std::vector<uint64_t> h_amb; // the same on the host (n_amb entries)
   epochlik::DevBuf weights;    // double [P]
   epochlik::DevBuf weightsT;   // T [P]
   epochlik::DevBuf pi;         // double [Kp]

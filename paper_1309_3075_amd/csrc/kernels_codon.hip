@@ -126,20 +126,37 @@ __device__ inline void child_gemm(f4 (&S)[4], const float* __restrict__ Lg, int 
     }
 }
 
-// Tip states of patterns p0 + 4 g + v as LDS columns (missing state: column 64).
+// Tip states of patterns p0 + 4 g + v as LDS columns: an observed state is its
+// column, a missing one column 64 (the row sums), and the caller's ambiguity
+// set a is 65 + a (text after Eq. 4: tips are 0/1 indicators of the
+// possible states).
 __device__ inline void tip_columns(int (&col)[4], const uint8_t* __restrict__ tipst, int P, int p0, int K, int g) {
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int st = gptr(tipst)[min(p0 + 4 * g + v, P - 1)];
-    col[v] = st < K ? st : 64;
+    col[v] = st < K ? st : 64 + (st - K);
   }
 }
-// Tip child: S = P[i][state_p].
-__device__ inline void tip_lookup(f4 (&S)[4], const int (&col)[4], const float* __restrict__ sP, int r) {
+// Sum of row entries over an ambiguity set (rare: kept off the common path).
+__device__ __noinline__ float masked_row_sum(const float* __restrict__ row, uint64_t set) {
+  float acc = 0.f;
+  while (set) {
+    const int j = __builtin_ctzll(set);
+    acc += row[j];
+    set &= set - 1;
+  }
+  return acc;
+}
+// Tip child: S = P[i][state_p] (or the sum of P[i][.] over the tip's state set).
+__device__ inline void tip_lookup(f4 (&S)[4], const int (&col)[4], const float* __restrict__ sP, int r,
+                                  const uint64_t* __restrict__ amb) {
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) S[nt][v] = sP[(16 * nt + r) * LDP + col[v]];
+    for (int v = 0; v < 4; ++v) {
+      const float* row = sP + (16 * nt + r) * LDP;
+      S[nt][v] = col[v] <= 64 ? row[col[v]] : masked_row_sum(row, amb[col[v] - 65]);
+    }
 }
 
 // D-layout load of a [P][64] array: value at pattern p0 + 4 g + v, state 16 nt + r.
@@ -185,14 +202,14 @@ __global__ __launch_bounds__(256) void codon_post_level_kernel(const CodonProble
     } else {
       int col[4];
       tip_columns(col, pr.tips + (size_t)a * pr.tip_stride, P, p0, K, g);
-      tip_lookup(Sa, col, sPa, r);
+      tip_lookup(Sa, col, sPa, r, pr.amb);
     }
     if (Lb) {
       child_gemm(Sb, Lb, P, p0, sPb, g, r);
     } else {
       int col[4];
       tip_columns(col, pr.tips + (size_t)b * pr.tip_stride, P, p0, K, g);
-      tip_lookup(Sb, col, sPb, r);
+      tip_lookup(Sb, col, sPb, r, pr.amb);
     }
     int e[4];
 #pragma unroll
@@ -282,17 +299,20 @@ __device__ inline void grad_rows_internal(f4* G, const float* __restrict__ tcol,
   }
 }
 __device__ inline void grad_rows_tip(f4* G, const float* __restrict__ tcol, const float* __restrict__ sCF,
-                                     const int* __restrict__ sCol, int K, int g, int r) {
+                                     const int* __restrict__ sCol, int K, int g, int r,
+                                     const uint64_t* __restrict__ amb) {
 #pragma unroll 8
   for (int ks = 0; ks < TILE / 4; ++ks) {
     const int pl = 4 * ks + g;
     const float av = tcol[pl * LDP] * sCF[pl];
     const int col = sCol[pl];
+    // the tip's state set: one state, all K (missing), or an ambiguity set
+    const uint64_t set = col < 64 ? (1ull << col) : (col == 64 ? ~0ull : amb[col - 65]);
     f4 B;
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
       const int j = 16 * nt + r;
-      B[nt] = (col == j || (col == 64 && j < K)) ? 1.f : 0.f;
+      B[nt] = (j < K && ((set >> j) & 1)) ? 1.f : 0.f;
     }
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) G[nt] = mfma(av, B[nt], G[nt]);
@@ -404,11 +424,11 @@ __global__ __launch_bounds__(256, 2) void codon_pre_level_kernel(const CodonProb
     if (La)
       child_gemm_regs(Sa, cur.La, sPa, g, r);
     else
-      tip_lookup(Sa, cur.cola, sPa, r);
+      tip_lookup(Sa, cur.cola, sPa, r, pr.amb);
     if (Lb)
       child_gemm_regs(Sb, cur.Lb, sPb, g, r);
     else
-      tip_lookup(Sb, cur.colb, sPb, r);
+      tip_lookup(Sb, cur.colb, sPb, r, pr.amb);
     f4 Q[4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) Q[nt] = Qu ? cur.Q[nt] : f4{piv[nt], piv[nt], piv[nt], piv[nt]};
@@ -483,7 +503,7 @@ __global__ __launch_bounds__(256, 2) void codon_pre_level_kernel(const CodonProb
       if (Lc)
         grad_rows_internal(G, tcol, sCF, sL, g, r);
       else
-        grad_rows_tip(G, tcol, sCF, sCol[side], K, g, r);
+        grad_rows_tip(G, tcol, sCF, sCol[side], K, g, r, pr.amb);
     }
     __syncthreads();  // the next tile overwrites t, L, w_p / L_p and tip columns
     if (bt + 1 < n_tiles) cur = nxt;
@@ -583,7 +603,7 @@ __global__ __launch_bounds__(512, 1) void codon_pre_split_kernel(const CodonProb
     if (Lc)
       child_gemm_regs(S, cur.L, sPc, g, r);
     else
-      tip_lookup(S, cur.col, sPc, r);
+      tip_lookup(S, cur.col, sPc, r, pr.amb);
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
@@ -655,7 +675,7 @@ __global__ __launch_bounds__(512, 1) void codon_pre_split_kernel(const CodonProb
     if (Lc)
       grad_rows_internal(G, tcol, sh.sCF, sh.sL[s], g, r);
     else
-      grad_rows_tip(G, tcol, sh.sCF, sh.sCol[s], K, g, r);
+      grad_rows_tip(G, tcol, sh.sCF, sh.sCol[s], K, g, r, pr.amb);
     if (bt + 1 < n_tiles) cur = nxt;
   }
   EPOCH_GLOBAL float* dst = gptr(pr.Gpart + ((size_t)pr.gslots[pr.n_nodes + c] + blockIdx.x) * KK);
@@ -741,6 +761,7 @@ CodonProblem codon_descriptor(const EpochInstance* in, const int32_t* gslots, fl
   d.result = static_cast<double*>(in->result.ptr);
   d.left = in->d_left;
   d.right = in->d_right;
+  d.amb = static_cast<const uint64_t*>(in->amb.ptr);
   d.gslots = gslots;
   d.N = in->N;
   d.P = in->P;

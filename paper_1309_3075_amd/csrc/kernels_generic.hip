@@ -167,16 +167,26 @@ __global__ __launch_bounds__(256) void pstage_generic_kernel(
 // Post-order, one level: block = (internal node, tile of 256/KQ patterns);
 // thread = (pattern, state).  Children tiles staged through LDS per category.
 // ---------------------------------------------------------------------------
+// The 0/1 indicator of a tip state code (text after Eq. 4): code < K one state,
+// K every state (missing), K + 1 + a the caller's ambiguity set a.
+__device__ inline uint64_t tip_set(int st, int K, const uint64_t* __restrict__ amb) {
+  if (st < K) return 1ull << st;
+  if (st == K) return K == 64 ? ~0ull : ((1ull << K) - 1);
+  return amb[st - K - 1];
+}
+
 template <typename T>
 __device__ inline T child_vector(int child, int N, int p, int tstride, int K, int Kp, int i, const T* Prow,
-                                 const uint8_t* tips, const T* sL) {
+                                 const uint8_t* tips, const uint64_t* amb, const T* sL) {
   // (P_child L_child)(i) for a pattern; Prow points at row i of the child's matrix; tstride is the
   // row stride of the tip states (the instance's pattern count).
   if (child < N) {
     const int st = tips[(size_t)child * tstride + p];
     if (st < K) return Prow[st];
+    const uint64_t set = tip_set(st, K, amb);
     T r = 0;
-    for (int j = 0; j < K; ++j) r += Prow[j];
+    for (int j = 0; j < K; ++j)
+      if ((set >> j) & 1) r += Prow[j];
     return r;
   }
   T r = 0;
@@ -188,6 +198,7 @@ template <typename T, int KQ>
 __global__ __launch_bounds__(256) void post_level_generic_kernel(
     const int32_t* __restrict__ nodes, const int32_t* __restrict__ left,
     const int32_t* __restrict__ right, const T* __restrict__ Pm, const uint8_t* __restrict__ tips,
+    const uint64_t* __restrict__ amb,
     T* __restrict__ partials, int32_t* __restrict__ scales, int N, int P, int tstride, int K, int Kp, int C) {
   constexpr int TP = 256 / KQ;
   __shared__ T sA[256], sB[256];
@@ -205,8 +216,8 @@ __global__ __launch_bounds__(256) void post_level_generic_kernel(
     __syncthreads();
     T r = 0;
     if (pok && i < K) {
-      const T va = child_vector(a, N, p, tstride, K, Kp, i, Pm + ((size_t)a * C + c) * KK + (size_t)i * Kp, tips, sA + pl * KQ);
-      const T vb = child_vector(b, N, p, tstride, K, Kp, i, Pm + ((size_t)b * C + c) * KK + (size_t)i * Kp, tips, sB + pl * KQ);
+      const T va = child_vector(a, N, p, tstride, K, Kp, i, Pm + ((size_t)a * C + c) * KK + (size_t)i * Kp, tips, amb, sA + pl * KQ);
+      const T vb = child_vector(b, N, p, tstride, K, Kp, i, Pm + ((size_t)b * C + c) * KK + (size_t)i * Kp, tips, amb, sB + pl * KQ);
       r = va * vb;
     }
     x[c] = r;
@@ -280,6 +291,7 @@ template <typename T, int KQ>
 __global__ __launch_bounds__(256) void pre_level_generic_kernel(
     const int32_t* __restrict__ nodes, const int32_t* __restrict__ left,
     const int32_t* __restrict__ right, const T* __restrict__ Pm, const uint8_t* __restrict__ tips,
+    const uint64_t* __restrict__ amb,
     const T* __restrict__ partials, T* __restrict__ pre, const double* __restrict__ pi, int root,
     int N, int P, int tstride, int K, int Kp, int C) {
   constexpr int TP = 256 / KQ;
@@ -303,8 +315,8 @@ __global__ __launch_bounds__(256) void pre_level_generic_kernel(
     __syncthreads();
     T ta = 0, tb = 0;
     if (pok && i < K) {
-      const T va = child_vector(a, N, p, tstride, K, Kp, i, Pm + ((size_t)a * C + c) * KK + (size_t)i * Kp, tips, sA + pl * KQ);
-      const T vb = child_vector(b, N, p, tstride, K, Kp, i, Pm + ((size_t)b * C + c) * KK + (size_t)i * Kp, tips, sB + pl * KQ);
+      const T va = child_vector(a, N, p, tstride, K, Kp, i, Pm + ((size_t)a * C + c) * KK + (size_t)i * Kp, tips, amb, sA + pl * KQ);
+      const T vb = child_vector(b, N, p, tstride, K, Kp, i, Pm + ((size_t)b * C + c) * KK + (size_t)i * Kp, tips, amb, sB + pl * KQ);
       const T q = sQ[threadIdx.x];
       ta = q * vb;
       tb = q * va;
@@ -351,6 +363,7 @@ template <typename T, int KQ, int GPT>
 __global__ __launch_bounds__(256) void grad_G_generic_kernel(
     const int32_t* __restrict__ parent, const int32_t* __restrict__ left,
     const int32_t* __restrict__ right, const T* __restrict__ Pm, const uint8_t* __restrict__ tips,
+    const uint64_t* __restrict__ amb,
     const T* __restrict__ partials, const T* __restrict__ pre, const double* __restrict__ pi,
     const double* __restrict__ cat, const double* __restrict__ weights, int root, int N, int n_nodes,
     int P, int tstride, int K, int Kp, int C, int n_chunks, double* __restrict__ Gpart,
@@ -395,8 +408,8 @@ __global__ __launch_bounds__(256) void grad_G_generic_kernel(
       T lv = 0;  // L_v(i)
       T tvi = 0;
       if (pok && i < K) {
-        const T sv = child_vector(v, N, p, tstride, K, Kp, i, Pm + ((size_t)v * C + c) * KK + (size_t)i * Kp, tips, sV + pl * KQ);
-        const T sw = child_vector(w, N, p, tstride, K, Kp, i, Pm + ((size_t)w * C + c) * KK + (size_t)i * Kp, tips, sW + pl * KQ);
+        const T sv = child_vector(v, N, p, tstride, K, Kp, i, Pm + ((size_t)v * C + c) * KK + (size_t)i * Kp, tips, amb, sV + pl * KQ);
+        const T sw = child_vector(w, N, p, tstride, K, Kp, i, Pm + ((size_t)w * C + c) * KK + (size_t)i * Kp, tips, amb, sW + pl * KQ);
         const T q = sQ[threadIdx.x];
         tvi = q * sw;
         acc += T(cat[kMaxCategories + c]) * tvi * sv;
@@ -404,7 +417,7 @@ __global__ __launch_bounds__(256) void grad_G_generic_kernel(
           lv = sV[threadIdx.x];
         } else {
           const int st = tips[(size_t)v * tstride + p];
-          lv = (st >= K || st == i) ? T(1) : T(0);
+          lv = ((tip_set(st, K, amb) >> i) & 1) ? T(1) : T(0);
         }
       }
       tv[c] = tvi;
@@ -564,6 +577,7 @@ int post_dispatch(EpochInstance* in, const int32_t* d_nodes, const int32_t* leve
   const auto& pl = in->plan;
   const T* Pm = static_cast<const T*>(in->Pm.ptr);
   const uint8_t* tips = static_cast<const uint8_t*>(in->tips.ptr) + view_p0(in);
+  const uint64_t* amb = static_cast<const uint64_t*>(in->amb.ptr);
   T* part = static_cast<T*>(in->partials.ptr);
   int32_t* sc = static_cast<int32_t*>(in->scales.ptr);
   const int P = view_P(in);
@@ -574,7 +588,7 @@ int post_dispatch(EpochInstance* in, const int32_t* d_nodes, const int32_t* leve
     const int32_t* nodes = d_nodes + level_off[l];
 #define EPOCH_POST(Q)                                                                            \
   hipLaunchKernelGGL((post_level_generic_kernel<T, Q>), grid, dim3(256), 0, in->stream, nodes,    \
-                     in->d_left, in->d_right, Pm, tips, part, sc, in->N, P, in->P, in->K, in->Kp, in->C)
+                     in->d_left, in->d_right, Pm, tips, amb, part, sc, in->N, P, in->P, in->K, in->Kp, in->C)
     switch (KQ) {
       case 4: EPOCH_POST(4); break;
       case 8: EPOCH_POST(8); break;
@@ -612,6 +626,7 @@ int pre_dispatch(EpochInstance* in) {
   const auto& pl = in->plan;
   const T* Pm = static_cast<const T*>(in->Pm.ptr);
   const uint8_t* tips = static_cast<const uint8_t*>(in->tips.ptr) + view_p0(in);
+  const uint64_t* amb = static_cast<const uint64_t*>(in->amb.ptr);
   const T* part = static_cast<const T*>(in->partials.ptr);
   T* pre = static_cast<T*>(in->pre.ptr);
   const double* pi = static_cast<const double*>(in->pi.ptr);
@@ -623,7 +638,7 @@ int pre_dispatch(EpochInstance* in) {
     const int32_t* nodes = in->d_level_nodes + pl.level_offset[l];
 #define EPOCH_PRE(Q)                                                                            \
   hipLaunchKernelGGL((pre_level_generic_kernel<T, Q>), grid, dim3(256), 0, in->stream, nodes,    \
-                     in->d_left, in->d_right, Pm, tips, part, pre, pi, pl.root, in->N, P, in->P,  \
+                     in->d_left, in->d_right, Pm, tips, amb, part, pre, pi, pl.root, in->N, P, in->P,  \
                      in->K, in->Kp, in->C)
     switch (KQ) {
       case 4: EPOCH_PRE(4); break;
@@ -641,6 +656,7 @@ template <typename T, int KQ, int GP>
 void grad_G_launch(EpochInstance* in, dim3 grid, bool fused) {
   const T* Pm = static_cast<const T*>(in->Pm.ptr);
   const uint8_t* tips = static_cast<const uint8_t*>(in->tips.ptr) + view_p0(in);
+  const uint64_t* amb = static_cast<const uint64_t*>(in->amb.ptr);
   const T* part = static_cast<const T*>(in->partials.ptr);
   const T* pre = static_cast<const T*>(in->pre.ptr);
   const double* pi = static_cast<const double*>(in->pi.ptr);
@@ -648,7 +664,7 @@ void grad_G_launch(EpochInstance* in, dim3 grid, bool fused) {
   const double* wts = static_cast<const double*>(in->weights.ptr) + view_p0(in);
   double* Gp = static_cast<double*>(in->Gpart.ptr);
   hipLaunchKernelGGL((grad_G_generic_kernel<T, KQ, GP>), grid, dim3(256), 0, in->stream,
-                     in->d_parent, in->d_left, in->d_right, Pm, tips, part, pre, pi, cat, wts,
+                     in->d_parent, in->d_left, in->d_right, Pm, tips, amb, part, pre, pi, cat, wts,
                      in->plan.root, in->N, in->n_nodes, view_P(in), in->P, in->K, in->Kp, in->C, in->n_chunks, Gp,
                      static_cast<const T*>(in->dPm.ptr), fused ? static_cast<double*>(in->G.ptr) : nullptr,
                      static_cast<double*>(in->dbranch.ptr));

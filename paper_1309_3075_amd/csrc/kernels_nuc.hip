@@ -121,8 +121,8 @@ __device__ inline V4<T> child_vec(const ChildBuf<T, KIND>& cb, const NucCtx<T>& 
   } else if constexpr (KIND == kInternal) {
     return cb.x;
   } else {
-    const V4<T> u = x.sTip[(s0 * 8 + x.c) * 5 + (cb.st1 < 4 ? cb.st1 : 4)];
-    const V4<T> w = x.sTip[((s0 + 1) * 8 + x.c) * 5 + (cb.st2 < 4 ? cb.st2 : 4)];
+    const V4<T> u = x.sTip[(s0 * 8 + x.c) * 16 + cb.st1];
+    const V4<T> w = x.sTip[((s0 + 1) * 8 + x.c) * 16 + cb.st2];
     V4<T> r;
 #pragma unroll
     for (int i = 0; i < 4; ++i) r.v[i] = u.v[i] * w.v[i];
@@ -147,14 +147,17 @@ __device__ inline int child_normalise(V4<T>& v, const ChildBuf<T, KIND>& cb, boo
   }
 }
 
-// Stage the transposed tip matrices of cherry children: slots 0-1 for child a,
-// 2-3 for child b.  Called by every thread of the block before a barrier.
+// Stage the tip lookups of cherry children: for every state set j (1..15),
+// column j = sum over the states in j of column P[:, state], so a tip lookup is
+// one LDS read for an observed, ambiguous or missing state alike.  Slots 0-1
+// for child a, 2-3 for child b.  Called by every thread of the block before a
+// barrier.
 template <typename T>
 __device__ inline void stage_cherry_tips(V4<T>* sTip, const T* __restrict__ Pm, const int32_t* __restrict__ left,
                                          const int32_t* __restrict__ right, int N, int C, int a, int b, bool ca,
                                          bool cb) {
-  for (int t = threadIdx.x; t < 4 * C * 5; t += blockDim.x) {
-    const int slot = t / (C * 5), c = (t / 5) % C, j = t % 5;
+  for (int t = threadIdx.x; t < 4 * C * 16; t += blockDim.x) {
+    const int slot = t / (C * 16), c = (t / 16) % C, j = t % 16;
     const int owner = slot < 2 ? a : b;
     if (!(slot < 2 ? ca : cb)) continue;
     const int tip = (slot & 1) ? right[owner] : left[owner];
@@ -162,13 +165,11 @@ __device__ inline void stage_cherry_tips(V4<T>* sTip, const T* __restrict__ Pm, 
     V4<T> col;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      if (j < 4) {
-        col.v[i] = M[4 * i + j];
-      } else {
-        col.v[i] = (M[4 * i] + M[4 * i + 1]) + (M[4 * i + 2] + M[4 * i + 3]);
-      }
+      const T m0 = (j & 1) ? M[4 * i] : T(0), m1 = (j & 2) ? M[4 * i + 1] : T(0);
+      const T m2 = (j & 4) ? M[4 * i + 2] : T(0), m3 = (j & 8) ? M[4 * i + 3] : T(0);
+      col.v[i] = (m0 + m1) + (m2 + m3);
     }
-    sTip[(slot * 8 + c) * 5 + j] = col;
+    sTip[(slot * 8 + c) * 16 + j] = col;
   }
 }
 
@@ -233,7 +234,7 @@ __global__ __launch_bounds__(256) void nuc_post_level_kernel(
     V4<T>* __restrict__ part_out, const int32_t* __restrict__ scale_in, int32_t* __restrict__ scale_out,
     int N, int P, int C, int R) {
   constexpr int TPW = 64 / CP;  // patterns per wavefront tile
-  __shared__ V4<T> sTip[4 * 8 * 5];
+  __shared__ V4<T> sTip[4 * 8 * 16];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int cl = lane & (CP - 1);
@@ -384,8 +385,8 @@ __device__ inline void pre_tiles(const NucCtx<T>& x, int u, int a, int b, int fi
     }
     if constexpr (NX == 2 && KA == kCherry) {
       const V4<T> qa = matvec_t(Pa, ta);
-      cherry_tip_grads<T>(qa, x.sTip[(0 * 8 + c) * 5 + (ca.st1 < 4 ? ca.st1 : 4)],
-                          x.sTip[(1 * 8 + c) * 5 + (ca.st2 < 4 ? ca.st2 : 4)], ca.st1, ca.st2, f, gx[0], gx[1]);
+      cherry_tip_grads<T>(qa, x.sTip[(0 * 8 + c) * 16 + ca.st1], x.sTip[(1 * 8 + c) * 16 + ca.st2], ca.st1, ca.st2,
+                          f, gx[0], gx[1]);
     } else if constexpr (KA != kTip) {
       V4<T> qa = matvec_t(Pa, ta);
       const T ma = group_max_cp<CP>(cat_ok ? max4(qa) : T(0));
@@ -397,8 +398,8 @@ __device__ inline void pre_tiles(const NucCtx<T>& x, int u, int a, int b, int fi
     if constexpr (NX >= 1 && KB == kCherry) {
       constexpr int h = NX == 2 ? 2 : 0;
       const V4<T> qb = matvec_t(Pb, tb);
-      cherry_tip_grads<T>(qb, x.sTip[(2 * 8 + c) * 5 + (cb.st1 < 4 ? cb.st1 : 4)],
-                          x.sTip[(3 * 8 + c) * 5 + (cb.st2 < 4 ? cb.st2 : 4)], cb.st1, cb.st2, f, gx[h], gx[h + 1]);
+      cherry_tip_grads<T>(qb, x.sTip[(2 * 8 + c) * 16 + cb.st1], x.sTip[(3 * 8 + c) * 16 + cb.st2], cb.st1, cb.st2,
+                          f, gx[h], gx[h + 1]);
     } else if constexpr (KB != kTip) {
       V4<T> qb = matvec_t(Pb, tb);
       const T mb = group_max_cp<CP>(cat_ok ? max4(qb) : T(0));
@@ -449,7 +450,7 @@ __global__ __launch_bounds__(256) void nuc_pre_level_kernel(
   constexpr int TPW = 64 / CP;
   constexpr int NG = 2 + 2 * NX;  // branches receiving dlogL/dP from this block
   __shared__ T sG[4][NG][CP][16];
-  __shared__ V4<T> sTip[4 * 8 * 5];
+  __shared__ V4<T> sTip[4 * 8 * 16];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int cl = lane & (CP - 1);

@@ -170,7 +170,7 @@ __device__ inline void walk_step(const WalkArgs<T>& g, const Lane<T, NT>& L, con
   V4<T> ca[NT], cb[NT], dca[NT], dcb[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    const size_t ka5 = ta * 5 + (cur[t].sta < 4 ? cur[t].sta : 4), kb5 = tb * 5 + (cur[t].stb < 4 ? cur[t].stb : 4);
+    const size_t ka5 = ta * 16 + (cur[t].sta & 15), kb5 = tb * 16 + (cur[t].stb & 15);  // state-set columns
     ca[t] = g.tcol[ka5];
     cb[t] = g.tcol[kb5];
     if constexpr (PRE) {
@@ -282,7 +282,7 @@ __global__ __launch_bounds__(256) void nuc_walk_kernel(const WalkArgs<T> g) {
   L.wc = L.cat_ok ? T(g.cat[kMaxCategories + L.c]) : T(0);
 #pragma unroll
   for (int i = 0; i < 4; ++i) L.qroot.v[i] = T(g.pi[i]);
-  L.tcol_d = (size_t)g.N * g.C * 5;  // offset of the dP/dl columns
+  L.tcol_d = (size_t)g.N * g.C * 16;  // offset of the dP/dl columns
   const int n = g.n_ops;
   const int n_groups = (g.n_tiles + NT - 1) / NT;
 
@@ -425,10 +425,10 @@ struct FetchM {
 };
 
 // Tip indicator: one-hot for an observed state, all ones for a missing one.
-__device__ inline V4<float> tip_vector(int st) {
+__device__ inline V4<float> tip_vector(int mask) {  // the tip's state set as a 0/1 vector
   V4<float> x;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) x.v[k] = (st == k || st >= 4) ? 1.f : 0.f;
+  for (int k = 0; k < 4; ++k) x.v[k] = ((mask >> k) & 1) ? 1.f : 0.f;
   return x;
 }
 
@@ -615,16 +615,20 @@ __global__ __launch_bounds__(256) void walk_transpose_kernel(const float* __rest
 template <typename T>
 __global__ __launch_bounds__(256) void walk_tipcol_kernel(const T* __restrict__ Pm, const T* __restrict__ dPm, int N,
                                                           int C, V4<T>* __restrict__ tcol) {
-  const int per = N * C * 5;
+  // column j (a state set, 1..15) = sum over its states of column P[:, state]
+  const int per = N * C * 16;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (dPm ? 2 : 1) * per) return;
   const int m = t / per, r = t % per;
-  const int v = r / (C * 5), c = (r / 5) % C, j = r % 5;
+  const int v = r / (C * 16), c = (r / 16) % C, j = r % 16;
   const T* M = (m ? dPm : Pm) + ((size_t)v * C + c) * 16;
   V4<T> col;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-    col.v[i] = j < 4 ? M[4 * i + j] : (M[4 * i] + M[4 * i + 1]) + (M[4 * i + 2] + M[4 * i + 3]);
+  for (int i = 0; i < 4; ++i) {
+    const T m0 = (j & 1) ? M[4 * i] : T(0), m1 = (j & 2) ? M[4 * i + 1] : T(0);
+    const T m2 = (j & 4) ? M[4 * i + 2] : T(0), m3 = (j & 8) ? M[4 * i + 3] : T(0);
+    col.v[i] = (m0 + m1) + (m2 + m3);
+  }
   tcol[t] = col;
 }
 
@@ -745,7 +749,7 @@ int walk_tiles(const EpochInstance* in) {
 
 size_t walk_tcol_bytes(const EpochInstance* in) {
   if (!in->fp64) return (size_t)in->n_nodes * in->C * 16 * sizeof(float);  // transposed P
-  return (size_t)2 * in->N * in->C * 5 * 4 * sizeof(double);                // tip columns of P and dP/dl
+  return (size_t)2 * in->N * in->C * 16 * 4 * sizeof(double);               // state-set columns of P and dP/dl
 }
 
 size_t walk_dpart_rows_bytes(const EpochInstance* in) {
@@ -875,7 +879,7 @@ int launch_walk_tipcol(EpochInstance* in) {
     return hip_check(hipGetLastError(), "walk_transpose launch");
   }
   const bool grad = in->dPm.ptr != nullptr && (in->cfg.flags & (EPOCH_GRAD_BRANCH | EPOCH_GRAD_Q));
-  const int n = (grad ? 2 : 1) * in->N * in->C * 5;
+  const int n = (grad ? 2 : 1) * in->N * in->C * 16;
   const int blocks = (n + 255) / 256;
   if (in->fp64)
     hipLaunchKernelGGL((walk_tipcol_kernel<double>), dim3(blocks), dim3(256), 0, in->stream,

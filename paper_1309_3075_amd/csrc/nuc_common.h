@@ -32,11 +32,14 @@ struct M4 {
   T m[16];
 };
 
+// Tip states of the 4-state kernels are state sets: bit i set = state i
+// possible (text after Eq. 4: a tip is a 0/1 indicator of the (partially)
+// observed state; one state, an ambiguity set, or all four when missing).
 template <typename T>
-__device__ inline V4<T> onehot(int st) {
+__device__ inline V4<T> onehot(int mask) {
   V4<T> r;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) r.v[i] = (st >= 4 || st == i) ? T(1) : T(0);
+  for (int i = 0; i < 4; ++i) r.v[i] = ((mask >> i) & 1) ? T(1) : T(0);
   return r;
 }
 

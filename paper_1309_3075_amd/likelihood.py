@@ -98,6 +98,16 @@ class EpochLikelihood:
         s = _i32(states)
         check(self._lib.epoch_set_tip_states(self._h, _ip(s)))
 
+    def set_tip_ambiguities(self, sets):
+        """Ambiguity sets: `sets` is [n_codes][K] 0/1 (or bit masks); tip code K + 1 + a then stands
+        for set a.  The tip states must be set again afterwards."""
+        arr = np.asarray(sets)
+        if arr.ndim == 2:
+            arr = np.array([sum(1 << j for j in range(arr.shape[1]) if row[j]) for row in arr], dtype=np.uint64)
+        m = np.ascontiguousarray(arr, dtype=np.uint64)
+        ptr = m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)) if len(m) else None
+        check(self._lib.epoch_set_tip_ambiguities(self._h, int(len(m)), ptr))
+
     def set_pattern_weights(self, w):
         w = _f64(w)
         check(self._lib.epoch_set_pattern_weights(self._h, _dp(w)))
@@ -226,6 +236,8 @@ def from_problem(prob, precision: str = "fp64", grad_branch: bool = False, grad_
                           hbm_budget_bytes=hbm_budget_bytes, workspace=workspace, grad_time=grad_time)
     for k, v in (options or {}).items():
         lik.set_option(k, v)
+    if getattr(prob, "ambiguity", None) is not None:
+        lik.set_tip_ambiguities(prob.ambiguity)
     lik.set_tip_states(prob.tips)
     lik.set_pattern_weights(prob.weights)
     lik.set_categories(prob.cat_rates, prob.cat_weights)
