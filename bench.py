@@ -210,8 +210,10 @@ def run_cpu_baseline(prob, sample_patterns, want_Q, want_grad=True):
 
 
 def time_instance(lik, steps, warmup, want_grad, want_Q):
-    """Evaluations/s of one instance through epoch_evaluate, with per-phase device times."""
+    """Evaluations/s of one instance through epoch_evaluate, with per-phase device times.  Every
+    step is a whole evaluation: incremental re-evaluation is switched off."""
     import torch
+    lik.set_option("incremental", 0)
 
     def step():
         lL, _, db, dq = lik.evaluate(branch=want_grad, Q=want_Q)

@@ -65,7 +65,7 @@ __global__ __launch_bounds__(64) void gather_results(const double* const* __rest
 }
 
 uint64_t member_signature(const EpochInstance* in) {
-  uint64_t h = (uint64_t)in->tree_generation * 1000003ull + (in->eig_fp64 ? 7 : 0);
+  uint64_t h = (uint64_t)in->tree_generation * 1000003ull + (in->eig_fp64 ? 7 : 0) + (in->tips_amb ? 11 : 0);
   return h ^ (in->option_generation * 0x9E3779B97F4A7C15ull);
 }
 

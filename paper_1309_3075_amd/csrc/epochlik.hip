@@ -450,6 +450,8 @@ int epoch_set_tip_states(EpochInstance* in, const int32_t* states) {
                        k % in->P, max_code);
     h[k] = (uint8_t)s;
   }
+  in->tips_amb = false;
+  for (size_t k = 0; k < n && !in->tips_amb; ++k) in->tips_amb = h[k] > in->K;
   if (in->path == 1) {
     // the 4-state kernels read a tip as its state set (bit i = state i): one state, all four
     // when missing, or the caller's ambiguity set

@@ -48,6 +48,8 @@ void mark_dirty_process(EpochInstance* in, int s) {
 
 bool incremental_eligible(const EpochInstance* in) {
   if (!in->inc_enable || in->dirty_all || !in->inc_base || !in->have_tree) return false;
+  // only a recorded change is re-evaluated in part: evaluating an unchanged state runs in full
+  if (std::find(in->dirty.begin(), in->dirty.end(), (uint8_t)1) == in->dirty.end()) return false;
   // the dlogL/dQ adjoint reads per-segment products the P stage keeps for every chain
   if (in->cfg.flags & EPOCH_GRAD_Q) return false;
   switch (in->path) {
@@ -93,6 +95,7 @@ int build_lists(EpochInstance* in) {
   if (in->path == 2) {
     const auto& sc = in->codon_sched;
     L.codon = sc;
+    L.codon.amb = in->tips_amb;
     L.codon.items.clear();
     L.codon.level_off.assign(1, 0);
     for (int l = 1; l <= sc.n_levels; ++l) {

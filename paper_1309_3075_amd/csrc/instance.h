@@ -77,6 +77,7 @@ struct CodonSchedule {
   std::vector<size_t> slot_total;  // dlogL/dP partial slots of each problem
   int n_levels = 0, max_tiles = 0, max_pattern_blocks = 0, n_problems = 0;
   int split_blocks = 0;  // pre-order levels of at most this many blocks put each child branch on its own wavefronts
+  bool amb = false;      // some problem has tips with ambiguity codes (the kernels' ambiguity instantiation)
 };
 
 // Incremental re-evaluation (MCMC proposals): the work of one restricted pass.
@@ -148,6 +149,7 @@ struct EpochInstance {
   epochlik::DevBuf tips;       // uint8 [N][P]: state codes (4-state kernels: state sets, bit i = state i)
   epochlik::DevBuf amb;        // uint64 [256]: state sets of the ambiguity codes K + 1 .. K + n_amb
   std::vector<uint64_t> h_amb; // the same on the host (n_amb entries)
+  bool tips_amb = false;       // some tip state is an ambiguity code
   epochlik::DevBuf weights;    // double [P]
   epochlik::DevBuf weightsT;   // T [P]
   epochlik::DevBuf pi;         // double [Kp]

@@ -148,15 +148,21 @@ __device__ __noinline__ float masked_row_sum(const float* __restrict__ row, uint
   return acc;
 }
 // Tip child: S = P[i][state_p] (or the sum of P[i][.] over the tip's state set).
+// AMB: the problem has tips with ambiguity codes (a separate instantiation, so
+// the common case keeps its registers).
+template <bool AMB>
 __device__ inline void tip_lookup(f4 (&S)[4], const int (&col)[4], const float* __restrict__ sP, int r,
                                   const uint64_t* __restrict__ amb) {
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const float* row = sP + (16 * nt + r) * LDP;
-      S[nt][v] = col[v] <= 64 ? row[col[v]] : masked_row_sum(row, amb[col[v] - 65]);
-    }
+    for (int v = 0; v < 4; ++v) S[nt][v] = sP[(16 * nt + r) * LDP + (AMB ? min(col[v], 64) : col[v])];
+  if (AMB && max(max(col[0], col[1]), max(col[2], col[3])) > 64) {  // an ambiguity set
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      if (col[v] > 64)
+        for (int nt = 0; nt < 4; ++nt) S[nt][v] = masked_row_sum(sP + (16 * nt + r) * LDP, amb[col[v] - 65]);
+  }
 }
 
 // D-layout load of a [P][64] array: value at pattern p0 + 4 g + v, state 16 nt + r.
@@ -170,6 +176,7 @@ __device__ inline void load_dlayout(f4 (&X)[4], const float* __restrict__ base, 
 }
 
 // ---------------------------------------------------------------------------
+template <bool AMB>
 __global__ __launch_bounds__(256) void codon_post_level_kernel(const CodonProblem* __restrict__ probs,
                                                                 const int2* __restrict__ items, int R) {
   __shared__ __align__(16) float sPa[KP * LDP];
@@ -202,14 +209,14 @@ __global__ __launch_bounds__(256) void codon_post_level_kernel(const CodonProble
     } else {
       int col[4];
       tip_columns(col, pr.tips + (size_t)a * pr.tip_stride, P, p0, K, g);
-      tip_lookup(Sa, col, sPa, r, pr.amb);
+      tip_lookup<AMB>(Sa, col, sPa, r, pr.amb);
     }
     if (Lb) {
       child_gemm(Sb, Lb, P, p0, sPb, g, r);
     } else {
       int col[4];
       tip_columns(col, pr.tips + (size_t)b * pr.tip_stride, P, p0, K, g);
-      tip_lookup(Sb, col, sPb, r, pr.amb);
+      tip_lookup<AMB>(Sb, col, sPb, r, pr.amb);
     }
     int e[4];
 #pragma unroll
@@ -298,6 +305,7 @@ __device__ inline void grad_rows_internal(f4* G, const float* __restrict__ tcol,
     for (int nt = 0; nt < 4; ++nt) G[nt] = mfma(av, B[nt], G[nt]);
   }
 }
+template <bool AMB>
 __device__ inline void grad_rows_tip(f4* G, const float* __restrict__ tcol, const float* __restrict__ sCF,
                                      const int* __restrict__ sCol, int K, int g, int r,
                                      const uint64_t* __restrict__ amb) {
@@ -306,13 +314,16 @@ __device__ inline void grad_rows_tip(f4* G, const float* __restrict__ tcol, cons
     const int pl = 4 * ks + g;
     const float av = tcol[pl * LDP] * sCF[pl];
     const int col = sCol[pl];
-    // the tip's state set: one state, all K (missing), or an ambiguity set
-    const uint64_t set = col < 64 ? (1ull << col) : (col == 64 ? ~0ull : amb[col - 65]);
     f4 B;
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
       const int j = 16 * nt + r;
-      B[nt] = (j < K && ((set >> j) & 1)) ? 1.f : 0.f;
+      B[nt] = (col == j || (col == 64 && j < K)) ? 1.f : 0.f;
+    }
+    if (AMB && col > 64) {  // the 0/1 row of an ambiguity set
+      const uint64_t set = amb[col - 65];
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) B[nt] = ((set >> (16 * nt + r)) & 1) ? 1.f : 0.f;
     }
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) G[nt] = mfma(av, B[nt], G[nt]);
@@ -373,6 +384,7 @@ __device__ inline void child_gemm_regs(f4 (&S)[4], const f4 (&a)[4], const float
     }
 }
 
+template <bool AMB>
 __global__ __launch_bounds__(256, 2) void codon_pre_level_kernel(const CodonProblem* __restrict__ probs,
                                                                const int2* __restrict__ items, int R) {
   __shared__ __align__(16) float sPa[KP * LDP];
@@ -424,11 +436,11 @@ __global__ __launch_bounds__(256, 2) void codon_pre_level_kernel(const CodonProb
     if (La)
       child_gemm_regs(Sa, cur.La, sPa, g, r);
     else
-      tip_lookup(Sa, cur.cola, sPa, r, pr.amb);
+      tip_lookup<AMB>(Sa, cur.cola, sPa, r, pr.amb);
     if (Lb)
       child_gemm_regs(Sb, cur.Lb, sPb, g, r);
     else
-      tip_lookup(Sb, cur.colb, sPb, r, pr.amb);
+      tip_lookup<AMB>(Sb, cur.colb, sPb, r, pr.amb);
     f4 Q[4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) Q[nt] = Qu ? cur.Q[nt] : f4{piv[nt], piv[nt], piv[nt], piv[nt]};
@@ -503,7 +515,7 @@ __global__ __launch_bounds__(256, 2) void codon_pre_level_kernel(const CodonProb
       if (Lc)
         grad_rows_internal(G, tcol, sCF, sL, g, r);
       else
-        grad_rows_tip(G, tcol, sCF, sCol[side], K, g, r, pr.amb);
+        grad_rows_tip<AMB>(G, tcol, sCF, sCol[side], K, g, r, pr.amb);
     }
     __syncthreads();  // the next tile overwrites t, L, w_p / L_p and tip columns
     if (bt + 1 < n_tiles) cur = nxt;
@@ -557,6 +569,7 @@ __device__ inline void split_load_tile(SplitTileLoads& ld, const CodonProblem& p
   if (Qu) load_dlayout(ld.Q, Qu, P, p0, g, r);
 }
 
+template <bool AMB>
 __global__ __launch_bounds__(512, 1) void codon_pre_split_kernel(const CodonProblem* __restrict__ probs,
                                                                 const int2* __restrict__ items, int R) {
   __shared__ PreSplitShared sh;
@@ -603,7 +616,7 @@ __global__ __launch_bounds__(512, 1) void codon_pre_split_kernel(const CodonProb
     if (Lc)
       child_gemm_regs(S, cur.L, sPc, g, r);
     else
-      tip_lookup(S, cur.col, sPc, r, pr.amb);
+      tip_lookup<AMB>(S, cur.col, sPc, r, pr.amb);
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
@@ -675,7 +688,7 @@ __global__ __launch_bounds__(512, 1) void codon_pre_split_kernel(const CodonProb
     if (Lc)
       grad_rows_internal(G, tcol, sh.sCF, sh.sL[s], g, r);
     else
-      grad_rows_tip(G, tcol, sh.sCF, sh.sCol[s], K, g, r, pr.amb);
+      grad_rows_tip<AMB>(G, tcol, sh.sCF, sh.sCol[s], K, g, r, pr.amb);
     if (bt + 1 < n_tiles) cur = nxt;
   }
   EPOCH_GLOBAL float* dst = gptr(pr.Gpart + ((size_t)pr.gslots[pr.n_nodes + c] + blockIdx.x) * KK);
@@ -819,6 +832,8 @@ void codon_build_schedule(const std::vector<const EpochInstance*>& insts, int ta
   }
   for (size_t q = 0; q < insts.size(); ++q)
     for (int v = 0; v < insts[q]->n_nodes; ++v) out.reduce_items.push_back(make_int2((int)q, v));
+  out.amb = false;
+  for (auto* in : insts) out.amb = out.amb || in->tips_amb;
   out.n_levels = n_levels;
   out.max_tiles = max_tiles;
   out.max_pattern_blocks = max_pblocks;
@@ -831,7 +846,10 @@ int codon_launch_post(const CodonSchedule& sc, const CodonProblem* d_probs, cons
     if (!n) continue;
     const int R = sc.level_R[l - 1];
     const int blocks = (sc.max_tiles + R - 1) / R;
-    hipLaunchKernelGGL(codon_post_level_kernel, dim3(blocks, n), dim3(256), 0, st, d_probs, d_items + b, R);
+    if (sc.amb)
+      hipLaunchKernelGGL(codon_post_level_kernel<true>, dim3(blocks, n), dim3(256), 0, st, d_probs, d_items + b, R);
+    else
+      hipLaunchKernelGGL(codon_post_level_kernel<false>, dim3(blocks, n), dim3(256), 0, st, d_probs, d_items + b, R);
   }
   return hip_check(hipGetLastError(), "codon_post_level launch");
 }
@@ -852,9 +870,15 @@ int codon_launch_pre_grad(const CodonSchedule& sc, const CodonProblem* d_probs, 
     const int R = sc.level_R[l - 1];
     const int blocks = (sc.max_tiles + R - 1) / R;
     if ((long)blocks * n <= sc.split_blocks)
-      hipLaunchKernelGGL(codon_pre_split_kernel, dim3(blocks, n), dim3(512), 0, st, d_probs, d_items + b, R);
+      if (sc.amb)
+        hipLaunchKernelGGL(codon_pre_split_kernel<true>, dim3(blocks, n), dim3(512), 0, st, d_probs, d_items + b, R);
+      else
+        hipLaunchKernelGGL(codon_pre_split_kernel<false>, dim3(blocks, n), dim3(512), 0, st, d_probs, d_items + b, R);
     else
-      hipLaunchKernelGGL(codon_pre_level_kernel, dim3(blocks, n), dim3(256), 0, st, d_probs, d_items + b, R);
+      if (sc.amb)
+        hipLaunchKernelGGL(codon_pre_level_kernel<true>, dim3(blocks, n), dim3(256), 0, st, d_probs, d_items + b, R);
+      else
+        hipLaunchKernelGGL(codon_pre_level_kernel<false>, dim3(blocks, n), dim3(256), 0, st, d_probs, d_items + b, R);
   }
   int rc = hip_check(hipGetLastError(), "codon_pre_level launch");
   if (rc) return rc;
@@ -923,6 +947,7 @@ const int2* dev_reduce_items(EpochInstance* in) { return dev_items(in) + in->cod
 // Post-order pass.  In chunks, each chunk's root reduction follows its partials
 // (the next chunk overwrites them), and the chunk log-likelihoods are summed.
 int launch_codon_post(EpochInstance* in) {
+  in->codon_sched.amb = in->tips_amb;
   const int nc = in->codon_nchunks;
   if (nc == 1) return codon_launch_post(in->codon_sched, dev_probs(in), dev_items(in), in->stream);
   for (int j = 0; j < nc; ++j) {
@@ -945,6 +970,7 @@ int launch_codon_root(EpochInstance* in) {
 // Pre-order pass and dlogL/dP.  In chunks, each chunk's partials are formed
 // again first (only one chunk's fit), and dlogL/dP accumulates over chunks.
 int launch_codon_pre_grad(EpochInstance* in) {
+  in->codon_sched.amb = in->tips_amb;
   const int nc = in->codon_nchunks;
   double* dpart = static_cast<double*>(in->codon_aux.ptr);
   for (int j = 0; j < nc; ++j) {

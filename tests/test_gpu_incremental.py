@@ -100,16 +100,19 @@ def test_one_branch_and_one_process_proposals(name):
         ref = O.log_likelihood(cur)
         assert rel(logL, ref) <= TOL_LOGL[precision]
 
-    # -- one process: new rates for process 1 (every branch with a stretch in its intervals)
-    Q1 = _perturbed_reversible(prob.Q[1], prob.pi_process[1], np.random.default_rng(3))
+    # -- one process: new rates for the process of interval 1 (every branch with a stretch in its
+    #    intervals)
+    s1 = int(prob.interval_process[1])
+    Q1 = _perturbed_reversible(prob.Q[s1], prob.pi_process[s1], np.random.default_rng(3))
     cur.Q = list(prob.Q)
-    cur.Q[1] = Q1
-    lik.set_rate_matrix(1, Q1, prob.pi_process[1])
+    cur.Q[s1] = Q1
+    lik.set_rate_matrix(s1, Q1, prob.pi_process[s1])
     logL, _, db, _ = lik.evaluate(branch=True)
     from paper_1309_3075_amd import _abi
     off_, proc, _ = _abi.plan_segments(prob.parent, prob.height, prob.boundaries, prob.interval_process,
                                        prob.n_processes)
-    touched = [v for v in range(n) if prob.parent[v] >= 0 and np.any(proc[off_[v]:off_[v + 1]] == 1)]
+    touched = [v for v in range(n) if prob.parent[v] >= 0 and np.any(proc[off_[v]:off_[v + 1]] == s1)]
+    assert touched
     assert lik.work_counts() == (len(touched) * C, _expected_partials(prob, touched, path))
     want_logL, want_db = _fresh(cur, precision, kernel, options)
     assert logL == want_logL and np.array_equal(db, want_db)
@@ -118,7 +121,7 @@ def test_one_branch_and_one_process_proposals(name):
     assert_grad(db, ref_b, TOL_GRAD[precision], "dlogL/dl after the proposal")
 
     # -- rejecting the proposals restores the original state and its bits
-    lik.set_rate_matrix(1, prob.Q[1], prob.pi_process[1])
+    lik.set_rate_matrix(s1, prob.Q[s1], prob.pi_process[s1])
     lik.set_branch_rates([tip, internal], [prob.branch_rate[tip], prob.branch_rate[internal]])
     logL, _, db, _ = lik.evaluate(branch=True)
     assert logL == logL0 and np.array_equal(db, db0)
