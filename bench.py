@@ -40,6 +40,8 @@ WORKLOADS = {
        "logL + branch-length and rate-matrix gradients",
     4: "40-state asymmetric CTMC, 12 processes over 48 intervals, 2000-taxon tree, 1 pattern, "
        "logL + branch-length and rate-matrix gradients",
+    6: "20-state reversible model (amino-acid-sized; padded to 64 on the matrix cores), 4 epochs, 128-taxon tree, "
+       "10000 patterns, 1 category, logL + branch-length and rate-matrix gradients",
 }
 
 
@@ -241,8 +243,8 @@ def roofline(prob, precision, kernel, phases, steps, want_Q, config, traffic_ok)
     dom = max(("post_order", "pre_order_dP", "transition_matrices") + (("grad_Q",) if want_Q else ()),
               key=lambda k: phases[k][0])
     dom_ms = phases[dom][0] / steps
-    path = ("nuc" if prob.n_states == 4 else ("codon" if prob.n_states > 48 and precision == "fp32"
-                                               and len(prob.cat_rates) == 1 else "generic"))
+    path = ("nuc" if prob.n_states == 4 else ("codon" if (prob.n_states > 48 or 16 < prob.n_states <= 32)
+                                               and precision == "fp32" and len(prob.cat_rates) == 1 else "generic"))
     if kernel == "generic":
         path = "generic"
     cp = 1 if len(prob.cat_rates) <= 1 else (2 if len(prob.cat_rates) <= 2 else (4 if len(prob.cat_rates) <= 4 else 8))
@@ -441,7 +443,7 @@ def main():
     config = 2 if headline else args.config
     if config == 5:
         return run_batch(args)
-    want_Q = args.grad_q or config in (3, 4)
+    want_Q = args.grad_q or config in (3, 4, 6)
     want_grad = config != 1  # the 16-taxon workload is a plain log-likelihood
     use_pi = config != 4
     log(f"bench: generating config C{config} ...")
@@ -485,7 +487,7 @@ def main():
 
     sample = None
     if not args.no_cpu_baseline:
-        sample = args.cpu_sample or min(prob.n_patterns, {1: 1000, 2: 30000, 3: 3000, 4: 1}.get(config, 1000))
+        sample = args.cpu_sample or min(prob.n_patterns, {1: 1000, 2: 30000, 3: 3000, 4: 1, 6: 3000}.get(config, 1000))
         log(f"bench: cpu baseline on {sample} patterns ...")
         sub, ref_logL, ref_b, ref_q, cpu = run_cpu_baseline(prob, sample, want_Q, want_grad)
         result["cpu_baseline"] = cpu

@@ -128,6 +128,15 @@ int padded_states(int K) {
   return (K + 15) / 16 * 16;
 }
 
+// 17..32 states in FP32 with one category (a 20-state amino-acid model, say) run on the
+// 64-state matrix-core kernels, padded to 64 states (the padding states are never observed
+// and their transition rows are the identity).
+bool small_codon_config(const EpochConfig& c) {
+  return c.n_states > 16 && c.n_states <= 32 && c.precision == EPOCH_FP32 && c.n_categories == 1 &&
+         c.kernel_path == EPOCH_KERNEL_AUTO;
+}
+int padded_states(const EpochConfig& c) { return small_codon_config(c) ? 64 : padded_states(c.n_states); }
+
 #define EPOCH_TRY(expr)          \
   do {                           \
     int _rc = (expr);            \
@@ -165,8 +174,8 @@ int choose_chunks(EpochInstance* in) {
 
 // The 64-state path takes an HBM budget by evaluating the patterns in chunks.
 bool codon_budget_config(const EpochConfig& c) {
-  return c.n_states > 48 && c.n_states <= 64 && c.precision == EPOCH_FP32 && c.n_categories == 1 &&
-         c.kernel_path == EPOCH_KERNEL_AUTO;
+  return ((c.n_states > 48 && c.n_states <= 64) || (c.n_states > 16 && c.n_states <= 32)) &&
+         c.precision == EPOCH_FP32 && c.n_categories == 1 && c.kernel_path == EPOCH_KERNEL_AUTO;
 }
 // Device bytes one pattern of a chunk costs on the 64-state path: partials and
 // scale exponents of every internal node, outside vectors with a gradient, and
@@ -184,7 +193,7 @@ size_t codon_bytes_per_pattern(const EpochConfig& c) {
 size_t generic_bytes_per_pattern(const EpochConfig& c) {
   const bool grad = (c.flags & (EPOCH_GRAD_BRANCH | EPOCH_GRAD_Q | EPOCH_GRAD_TIME)) != 0;
   const size_t Nm1 = (size_t)c.n_tips - 1, R = c.precision == EPOCH_FP64 ? 8 : 4;
-  const size_t row = (size_t)c.n_categories * padded_states(c.n_states) * R;
+  const size_t row = (size_t)c.n_categories * padded_states(c) * R;
   return Nm1 * (row * (grad ? 2 : 1) + sizeof(int32_t));
 }
 
@@ -242,9 +251,9 @@ int epoch_create(const EpochConfig* cfg, EpochInstance** out) {
                      (long long)c.hbm_budget_bytes, chunk_pattern_bytes * (size_t)std::min(c.n_patterns, 64));
   if (c.workspace && c.hbm_budget_bytes > 0)
     return set_error(EPOCH_ERR_ARG, "a workspace cannot be combined with hbm_budget_bytes");
-  if (c.workspace && (c.workspace_bytes < 0 || (size_t)c.workspace_bytes < workspace_total(c, padded_states(c.n_states))))
+  if (c.workspace && (c.workspace_bytes < 0 || (size_t)c.workspace_bytes < workspace_total(c, padded_states(c))))
     return set_error(EPOCH_ERR_ARG, "workspace_bytes %lld is below the %zu bytes epoch_workspace_bytes asks for",
-                     (long long)c.workspace_bytes, workspace_total(c, padded_states(c.n_states)));
+                     (long long)c.workspace_bytes, workspace_total(c, padded_states(c)));
   if (c.workspace && (reinterpret_cast<uintptr_t>(c.workspace) & 255))
     return set_error(EPOCH_ERR_ARG, "workspace must be 256-byte aligned");
   const size_t N = c.n_tips, P = c.n_patterns;
@@ -263,7 +272,7 @@ int epoch_create(const EpochConfig* cfg, EpochInstance** out) {
   in->N = c.n_tips;
   in->P = c.n_patterns;
   in->K = c.n_states;
-  in->Kp = padded_states(c.n_states);
+  in->Kp = padded_states(c);
   in->C = c.n_categories;
   in->S = c.n_processes;
   in->n_nodes = 2 * c.n_tips - 1;
@@ -897,6 +906,12 @@ int epoch_evaluate(EpochInstance* in, uint32_t what, double* logL, double* site_
   return EPOCH_OK;
 }
 
+int epoch_get_kernel_path(EpochInstance* in, int32_t* out) {
+  if (!in || !out) return set_error(EPOCH_ERR_ARG, "NULL argument");
+  *out = in->path;
+  return EPOCH_OK;
+}
+
 int epoch_get_transition_matrices(EpochInstance* in, double* out) {
   if (!in || !out) return set_error(EPOCH_ERR_ARG, "NULL argument");
   if (!in->P_valid) return set_error(EPOCH_ERR_STATE, "update_transition_matrices has not been called");
@@ -940,7 +955,7 @@ int epoch_workspace_bytes(const EpochConfig* cfg, int64_t* out) {
   if (cfg->n_tips < 2 || cfg->n_patterns < 1 || cfg->n_states < 2 || cfg->n_states > 64 || cfg->n_categories < 1 ||
       cfg->n_categories > kMaxCategories || (cfg->precision != EPOCH_FP32 && cfg->precision != EPOCH_FP64))
     return set_error(EPOCH_ERR_ARG, "invalid configuration");
-  *out = (int64_t)workspace_total(*cfg, padded_states(cfg->n_states));
+  *out = (int64_t)workspace_total(*cfg, padded_states(*cfg));
   return EPOCH_OK;
 }
 

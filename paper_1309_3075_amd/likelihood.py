@@ -150,6 +150,12 @@ class EpochLikelihood:
         n, r = _i32(nodes), _f64(rates)
         check(self._lib.epoch_set_branch_rates(self._h, int(n.shape[0]), _ip(n), _dp(r)))
 
+    def kernel_path(self) -> str:
+        """'generic', 'nucleotide' or 'matrix_core64' (epoch_get_kernel_path)."""
+        v = ctypes.c_int32(-1)
+        check(self._lib.epoch_get_kernel_path(self._h, ctypes.byref(v)))
+        return {0: "generic", 1: "nucleotide", 2: "matrix_core64"}[v.value]
+
     def work_counts(self):
         """(transition matrices, internal-node partials) formed by the last evaluation."""
         out = np.zeros(2, dtype=np.int64)

@@ -365,7 +365,8 @@ def _dirichlet(rng, alpha, k):
 
 def make_config(index: int, replicate: int = 0, *, n_tips=None, n_patterns=None,
                 tip_height_max: float = 0.0) -> Problem:
-    """The five workloads (index 1..5 as C1..C5), optionally shrunk for tests.
+    """The five workloads (index 1..5 as C1..C5) and a 20-state variant (index 6), optionally
+    shrunk for tests.
 
     C5 returns one problem per call; use :func:`make_batch` for the batch.
     """
@@ -412,6 +413,25 @@ def make_config(index: int, replicate: int = 0, *, n_tips=None, n_patterns=None,
         phi = np.array([0, 1, 2, 3], dtype=np.int32)
         rates, wts = np.ones(1), np.ones(1)
         pi_root = pic
+        weights_mode = "counts"
+    elif index == 6:
+        # 20-state (amino-acid-sized) variant of the codon workload: random reversible
+        # rates per epoch (exchangeabilities Dir(1), frequencies Dir(5)), 4 epochs, 128 taxa
+        N = n_tips or 128
+        P = n_patterns or 10_000
+        Qs, pis = [], []
+        for _ in range(4):
+            pi = _dirichlet(rng, 5.0, 20)
+            R = rng.dirichlet(np.ones(190))
+            Rm = np.zeros((20, 20))
+            Rm[np.triu_indices(20, 1)] = R
+            Rm = Rm + Rm.T
+            Qs.append(_normalise_reversible(Rm * pi[None, :], pi))
+            pis.append(pi)
+        bounds = np.array([0.25, 0.5, 0.75])
+        phi = np.array([0, 1, 2, 3], dtype=np.int32)
+        rates, wts = np.ones(1), np.ones(1)
+        pi_root = pis[-1]
         weights_mode = "counts"
     elif index == 4:
         N = n_tips or 2000
