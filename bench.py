@@ -384,7 +384,7 @@ def run_batch_leg(n, scale, steps, warmup, precision="fp32", grad_q=False, tune=
                        f"1000-20000 patterns each (x{scale}), one replayed hipGraph per step, logL + branch gradients"
                        + (" + rate-matrix gradients" if grad_q else ""),
            "problems_per_s": round(n * steps / wall, 3), "ms_per_batch": round(ms, 4),
-           "tuned_target_blocks": batch.target_blocks(),
+           "tuned_target_blocks": batch.target_blocks(), "tuned_split_blocks": batch.split_blocks(),
            "roofline": {"bound": "mfma", "kernel": "whole batched graph (codon_post/pre_level dominant)",
                         "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                         "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None,

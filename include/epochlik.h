@@ -357,8 +357,11 @@ int epoch_batch_evaluate(EpochBatch* batch, uint32_t what, double* logL);
  * log_likelihood_gradient; either may be NULL). */
 int epoch_batch_gradients(EpochBatch* batch, int32_t i, double* d_branch, double* d_Q);
 
-/* Tuned number of blocks per pre-order launch in use (for reporting). */
+/* Tuned launch shape in use (for reporting): blocks each merged level launch
+ * aims for, and the widest pre-order level (in blocks) that runs each child
+ * branch on its own wavefronts (0 = none). */
 int epoch_batch_target_blocks(EpochBatch* batch, int32_t* out);
+int epoch_batch_split_blocks(EpochBatch* batch, int32_t* out);
 
 int epoch_batch_destroy(EpochBatch* batch);
 

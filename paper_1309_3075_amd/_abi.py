@@ -40,7 +40,7 @@ EXPORTED = [
     "epoch_batch_create", "epoch_batch_evaluate", "epoch_batch_gradients", "epoch_batch_target_blocks",
     "epoch_batch_destroy", "epoch_set_option", "epoch_plan_walk", "epoch_workspace_bytes",
     "epoch_eigen_residual_noalloc", "epoch_set_branch_rates", "epoch_get_work_counts", "epoch_time_gradient",
-    "epoch_set_tip_ambiguities", "epoch_get_kernel_path",
+    "epoch_set_tip_ambiguities", "epoch_get_kernel_path", "epoch_batch_split_blocks",
 ]
 EPOCH_EVAL_LOGL = 0x1
 EPOCH_EVAL_GRAD_BRANCH = 0x2
@@ -126,6 +126,7 @@ def load() -> ctypes.CDLL:
         "epoch_time_gradient": (i32, [P, dp, dp]),
         "epoch_set_tip_ambiguities": (i32, [P, i32, ctypes.POINTER(ctypes.c_uint64)]),
         "epoch_get_kernel_path": (i32, [P, ctypes.POINTER(i32)]),
+        "epoch_batch_split_blocks": (i32, [P, ctypes.POINTER(i32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -292,7 +292,8 @@ std::string tune_key(EpochBatch* b) {
   long tot_p = 0;
   for (auto* in : b->insts) tot_p += in->P;
   std::ostringstream k;
-  k << arch.substr(0, arch.find(':')) << "/codon/n" << b->insts.size() << "/P" << (tot_p / (long)b->insts.size() / 1000);
+  k << arch.substr(0, arch.find(':')) << "/codon/K" << b->insts[0]->K << "/fp32/n" << b->insts.size() << "/P"
+    << (tot_p / (long)b->insts.size() / 1000);
   return k.str();
 }
 
@@ -336,11 +337,29 @@ void tune_store(const std::string& path, const std::string& key, int value) {
   f << "}\n";
 }
 
+// Timed replays of one launch shape (warm-up and capture first); ms of 3 replays.
+int time_shape(EpochBatch* b, uint32_t what, hipEvent_t e0, hipEvent_t e1, float* ms) {
+  b->signature.clear();  // forces a new schedule and capture
+  int rc = replay(b, what);
+  if (!rc) rc = hip_check(hipEventRecord(e0, b->stream), "tune record");
+  for (int k = 0; k < 3 && !rc; ++k) rc = replay(b, what);
+  if (!rc) rc = hip_check(hipEventRecord(e1, b->stream), "tune record");
+  if (!rc) rc = hip_check(hipEventSynchronize(e1), "tune sync");
+  if (!rc) rc = hip_check(hipEventElapsedTime(ms, e0, e1), "tune elapsed");
+  return rc;
+}
+
+// The launch shape of the merged 64-state levels, measured on this device: first the blocks
+// each level launch aims for (tiles per block follow from it), then, at the best of those,
+// the widest pre-order level that still takes the side-split kernel (each child branch on its
+// own wavefronts).  Cached per architecture, state count and batch shape.
 int autotune(EpochBatch* b) {
   const std::string key = tune_key(b);
-  int v = 0;
-  if (!b->tune_path.empty() && tune_lookup(b->tune_path, key, v)) {
+  int v = 0, sv = 0;
+  if (!b->tune_path.empty() && tune_lookup(b->tune_path, key + "/target_blocks", v) &&
+      tune_lookup(b->tune_path, key + "/split_blocks", sv)) {
     b->target_blocks = v;
+    b->split_blocks = sv - 1;  // stored + 1 (0 is a valid choice)
     return EPOCH_OK;
   }
   // tune the evaluation every member supports: the branch gradient only when every member keeps
@@ -356,29 +375,38 @@ int autotune(EpochBatch* b) {
   if (!rc) rc = hip_check(hipEventCreate(&e1), "tune event");
   if (rc) return rc;
   float best = 1e30f;
-  int best_t = b->target_blocks;
+  int best_t = b->target_blocks, best_s = b->split_blocks;
   for (int t : {512, 1024, 2048, 4096, 8192, 16384}) {
     b->target_blocks = t;
-    b->signature.clear();  // forces a new schedule and capture
-    rc = replay(b, what);  // warm-up (and capture)
-    if (!rc) rc = hip_check(hipEventRecord(e0, b->stream), "tune record");
-    for (int k = 0; k < 3 && !rc; ++k) rc = replay(b, what);
-    if (!rc) rc = hip_check(hipEventRecord(e1, b->stream), "tune record");
-    if (!rc) rc = hip_check(hipEventSynchronize(e1), "tune sync");
     float ms = 0.f;
-    if (!rc) rc = hip_check(hipEventElapsedTime(&ms, e0, e1), "tune elapsed");
+    rc = time_shape(b, what, e0, e1, &ms);
     if (rc) break;
     if (ms < best) {
       best = ms;
       best_t = t;
     }
   }
+  b->target_blocks = best_t;
+  if (!rc && all_grad)  // the split kernel is a pre-order kernel: only the gradient replays see it
+    for (int sb : {0, 64, 1024, 4096}) {
+      b->split_blocks = sb;
+      float ms = 0.f;
+      rc = time_shape(b, what, e0, e1, &ms);
+      if (rc) break;
+      if (ms < best) {
+        best = ms;
+        best_s = sb;
+      }
+    }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
-  b->target_blocks = best_t;
+  b->split_blocks = best_s;
   b->signature.clear();
-  if (!b->tune_path.empty()) tune_store(b->tune_path, key, best_t);
+  if (!b->tune_path.empty()) {
+    tune_store(b->tune_path, key + "/target_blocks", best_t);
+    tune_store(b->tune_path, key + "/split_blocks", best_s + 1);
+  }
   return EPOCH_OK;
 }
 
@@ -465,6 +493,12 @@ int epoch_batch_gradients(EpochBatch* b, int32_t i, double* d_branch, double* d_
 int epoch_batch_target_blocks(EpochBatch* b, int32_t* out) {
   if (!b || !out) return set_error(EPOCH_ERR_ARG, "NULL argument");
   *out = b->target_blocks;
+  return EPOCH_OK;
+}
+
+int epoch_batch_split_blocks(EpochBatch* b, int32_t* out) {
+  if (!b || !out) return set_error(EPOCH_ERR_ARG, "NULL argument");
+  *out = b->split_blocks;
   return EPOCH_OK;
 }
 

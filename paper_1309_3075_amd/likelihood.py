@@ -286,6 +286,11 @@ class EpochBatchEvaluator:
         check(self._lib.epoch_batch_target_blocks(self._h, ctypes.byref(v)))
         return v.value
 
+    def split_blocks(self) -> int:
+        v = ctypes.c_int32(0)
+        check(self._lib.epoch_batch_split_blocks(self._h, ctypes.byref(v)))
+        return v.value
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             self._lib.epoch_batch_destroy(self._h)

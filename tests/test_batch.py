@@ -45,7 +45,7 @@ def test_codon_batch_matches_oracle_and_single_instances():
     # the tuned shape is read back from the cache by a new batch
     b2 = EpochBatchEvaluator(members, tune_cache=cache)
     b2.evaluate(grad_branch=False)
-    assert b2.target_blocks() == batch.target_blocks()
+    assert b2.target_blocks() == batch.target_blocks() and b2.split_blocks() == batch.split_blocks()
     b2.close()
     batch.close()
     for m in members:
