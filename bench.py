@@ -86,10 +86,12 @@ def algorithmic_flops(prob):
     return {"post_order": post, "pre_order_dP": pre, "transition_matrices": chain, "grad_Q": adjoint}
 
 
-def fp64_reconstruction(prob, use_pi):
-    """Whether the library forms exp(tQ) in FP64 for this problem: it does so in FP32 instances when
-    some eigenvector matrix has infinity-norm condition number above 32 (the same rule, evaluated here
-    on the eigensystems the binding hands over)."""
+def fp64_reconstruction(prob, use_pi, mode=0):
+    """Whether the library forms exp(tQ) in FP64 for this problem in an FP32 instance: with the default
+    eigen_precision 0 it does so when some eigenvector matrix has infinity-norm condition number above
+    32 (the same rule, evaluated here on the eigensystems the binding hands over); 1 never, 2 always."""
+    if mode:
+        return mode == 2
     from paper_1309_3075_amd.eigen import eigensystem
     for s, Q in enumerate(prob.Q):
         e = eigensystem(Q, prob.pi_process[s] if use_pi else None)
@@ -282,9 +284,10 @@ def roofline(prob, precision, kernel, phases, steps, want_Q, config, traffic_ok)
     return r
 
 
-def gpu_parity(sub, precision, kernel, use_pi, ref_logL, ref_b, ref_q, want_grad, want_Q):
+def gpu_parity(sub, precision, kernel, use_pi, ref_logL, ref_b, ref_q, want_grad, want_Q, options=None):
     from paper_1309_3075_amd.likelihood import from_problem
-    with from_problem(sub, precision, grad_branch=want_grad, grad_Q=want_Q, kernel=kernel, use_pi=use_pi) as small:
+    with from_problem(sub, precision, grad_branch=want_grad, grad_Q=want_Q, kernel=kernel, use_pi=use_pi,
+                      options=options) as small:
         g_logL, _, g_b, g_q = small.evaluate(branch=want_grad, Q=want_Q)
     out = {"sample_patterns": sub.n_patterns, "logL_rel_err": abs(g_logL - ref_logL) / abs(ref_logL)}
     for key, g, r in (("grad_branch", g_b, ref_b), ("grad_Q", g_q, ref_q)):
@@ -328,6 +331,36 @@ def proposal_leg(prob, steps, use_pi=True):
                          "mean_partials_formed": round(float(np.mean(work)), 2)}
     out["speedup_incremental_over_full"] = round(out["incremental"]["proposals_per_s"] / out["full"]["proposals_per_s"], 3)
     out["what"] = "one random branch rate changed per step, then logL (FP32, no gradient)"
+    return out
+
+
+def precision_leg(prob, config, steps, want_grad, want_Q, use_pi, parity):
+    """The other arithmetics of the same workload, each with its parity against the oracle on the
+    CPU-baseline sample when one was drawn: the transition matrices and dlogL/dQ chains of the FP32
+    instance formed the other way (FP32 products where the conditioning rule picks FP64, FP64 where it
+    picks FP32), and the FP64 instance."""
+    from paper_1309_3075_amd import _abi
+    from paper_1309_3075_amd.likelihood import from_problem
+    out = {}
+    if fp64_reconstruction(prob, use_pi):
+        variants = [("fp32_products", "fp32", {"eigen_precision": 1})]
+    else:
+        variants = [("fp64_reconstruction", "fp32", {"eigen_precision": 2})]
+    variants.append(("fp64_instance", "fp64", {}))
+    for name, precision, options in variants:
+        leg = {"options": options}
+        try:
+            with from_problem(prob, precision, grad_branch=want_grad, grad_Q=want_Q, use_pi=use_pi,
+                              options=options) as lik:
+                v, ms, _, _ = time_instance(lik, steps, 2, want_grad, want_Q)
+            leg.update({"evals_per_s": round(v, 3), "ms_per_eval": round(ms, 4)})
+            if parity is not None:
+                sub, ref_logL, ref_b, ref_q = parity
+                leg["parity_vs_oracle"] = gpu_parity(sub, precision, "auto", use_pi, ref_logL, ref_b, ref_q,
+                                                     want_grad, want_Q, options)
+        except _abi.EpochError as e:  # e.g. a NaN log-likelihood from FP32 products of ill-conditioned systems
+            leg["error"] = str(e)
+        out[name] = leg
     return out
 
 
@@ -493,6 +526,12 @@ def main():
         result["cpu_baseline"] = cpu
         result["parity_vs_oracle"] = gpu_parity(sub, args.precision, args.kernel, use_pi, ref_logL, ref_b, ref_q,
                                                 want_grad, want_Q)
+    if not headline and config in (3, 4, 6) and args.precision == "fp32" and args.kernel == "auto" \
+            and args.patterns is None:
+        log("bench: FP32-products and FP64 legs ...")
+        result["fp64_reconstruction_default"] = fp64_reconstruction(prob, use_pi)
+        result["other_precisions"] = precision_leg(prob, config, max(3, args.steps // 2), want_grad, want_Q, use_pi,
+                                                   (sub, ref_logL, ref_b, ref_q) if sample else None)
 
     if headline and args.precision == "fp32" and args.kernel == "auto" and args.patterns is None:
         # the metric's FP64 half on the same workload: the fast kernels and the plain generic FP64 path

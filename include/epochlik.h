@@ -56,8 +56,11 @@ extern "C" {
 #define EPOCH_ERR_STATE (-2)     /* call-order violation (a required set_/update_ step missing) */
 #define EPOCH_ERR_OOM (-3)       /* device allocation failed */
 #define EPOCH_ERR_HIP (-4)       /* a HIP runtime call failed */
-#define EPOCH_ERR_NUMERIC (-5)   /* non-finite likelihood (e.g. zero probability data) */
+#define EPOCH_ERR_NUMERIC (-5)   /* NaN or +inf likelihood (non-finite inputs), or a gradient asked
+                                  * for a state whose log-likelihood is -inf */
 #define EPOCH_WARN_EIGEN_RESIDUAL 1 /* eigensystem reconstruction residual above 1e-8 (relative) */
+#define EPOCH_WARN_UNDERFLOW 2   /* some pattern's likelihood is zero in the working precision:
+                                  * logL = -inf is returned (see root_log_likelihood) */
 
 #define EPOCH_FP32 1
 #define EPOCH_FP64 2
@@ -119,12 +122,16 @@ const char* epoch_version(void);
  * configuration's pattern-sized buffers; *out receives it.  No device work. */
 int epoch_workspace_bytes(const EpochConfig* cfg, int64_t* out);
 
-/* Create an instance: validates cfg (before any HIP call), then allocates the
- * device buffers whose size depends only on cfg (the pattern-sized ones inside
- * cfg->workspace when it is set).  *out receives the handle. */
+/* Create an instance (Methods, coarse-grain parallel implementation: an
+ * instance holds a fixed set of device buffers, allocated when it is created
+ * and not grown afterwards).  Validates cfg (before any HIP call), then
+ * allocates the device buffers whose size depends only on cfg (the
+ * pattern-sized ones inside cfg->workspace when it is set); the tree-sized
+ * ones follow at set_tree_epochs.  *out receives the handle. */
 int epoch_create(const EpochConfig* cfg, EpochInstance** out);
 
-/* Free every device buffer of the instance (NULL is accepted). */
+/* Free every device buffer of the instance (the buffer pool of the same
+ * passage); NULL is accepted. */
 int epoch_destroy(EpochInstance* inst);
 
 /* Tip data (text after Eq. 4: tips are 0/1 indicators of the (partially)
@@ -193,8 +200,18 @@ int update_partials(EpochInstance* inst);
 
 /* logL = sum_p w_p log L_p (text after Eq. 4), reduced in FP64.
  *   logL: host double (required); site_logL: host [P] or NULL.
- * Requires update_partials, pattern weights, root frequencies.  Returns
- * EPOCH_ERR_NUMERIC if logL is not finite. */
+ * Requires update_partials, pattern weights, root frequencies.
+ * Underflow: partials are rescaled per pattern by a power of two shared by
+ * the rate categories (Eq. 4 is evaluated with the largest entry over states
+ * and categories kept near 1), so a category far less likely than the best
+ * one at some node is flushed to zero there; when, for one pattern, a
+ * category that dominates one subtree and another that dominates a second
+ * subtree are each flushed in the other, the pattern's likelihood is zero in
+ * the working precision (FP32 reaches this far sooner than FP64).  Data that
+ * are impossible under the model (a zero-length branch between different
+ * states) give the same zero.  Either way logL = -inf and the site values are
+ * written, EPOCH_WARN_UNDERFLOW is returned, and gradients of this state are
+ * refused (EPOCH_ERR_NUMERIC).  A NaN or +inf logL returns EPOCH_ERR_NUMERIC. */
 int root_log_likelihood(EpochInstance* inst, double* logL, double* site_logL);
 
 /* Gradient of logL (an addition to the paper):
@@ -203,7 +220,8 @@ int root_log_likelihood(EpochInstance* inst, double* logL, double* site_logL);
  *     Needs EPOCH_GRAD_BRANCH.
  *   d_Q: host [S][K][K] or NULL: dlogL/dQ_s entrywise, for the Q_s whose
  *     eigensystems were set.  Needs EPOCH_GRAD_Q.
- * Requires root_log_likelihood for the current state. */
+ * Requires root_log_likelihood for the current state, with a finite
+ * log-likelihood (EPOCH_ERR_NUMERIC after EPOCH_WARN_UNDERFLOW). */
 int log_likelihood_gradient(EpochInstance* inst, double* d_branch, double* d_Q);
 
 /* Node-height and epoch-boundary gradients (an addition: the paper fixes the
@@ -230,8 +248,10 @@ int epoch_time_gradient(EpochInstance* inst, double* d_height, double* d_boundar
  *   d_branch, d_Q: host outs as in log_likelihood_gradient, required when
  *     EPOCH_EVAL_GRAD_BRANCH / EPOCH_EVAL_GRAD_Q are set (ignored otherwise).
  * Needs every input set (as the separate calls do) and the instance flags for
- * the requested gradients (EPOCH_ERR_STATE otherwise).  A non-finite logL
- * returns EPOCH_ERR_NUMERIC after the outputs are written. */
+ * the requested gradients (EPOCH_ERR_STATE otherwise).  A logL of -inf
+ * returns EPOCH_WARN_UNDERFLOW with logL and the site values written and the
+ * requested gradient outputs filled with NaN; a NaN or +inf logL returns
+ * EPOCH_ERR_NUMERIC after the outputs are written. */
 #define EPOCH_EVAL_LOGL 0x1u
 #define EPOCH_EVAL_GRAD_BRANCH 0x2u
 #define EPOCH_EVAL_GRAD_Q 0x4u
@@ -260,8 +280,8 @@ int epoch_set_timing(EpochInstance* inst, int32_t enable);
  * each (either may be NULL).  Synchronises the stream. */
 int epoch_get_timing(EpochInstance* inst, double* ms_out, int64_t* counts_out);
 
-/* Kernel-selection options of an instance (performance only: every setting
- * computes the same quantities).  Takes effect for the next evaluation; a key
+/* Kernel-selection options of an instance (performance and rounding only:
+ * every setting computes the same quantities).  Takes effect for the next evaluation; a key
  * that changes the schedule re-plans the current tree.
  *   EPOCH_OPT_TREE_WALK (fixed at 1 under hbm_budget_bytes): 1 = 4-state pruning and branch gradients as one
  *     traversal of the whole tree per tile of patterns; 0 = one launch per
@@ -292,6 +312,13 @@ int epoch_get_timing(EpochInstance* inst, double* ms_out, int64_t* counts_out);
  *     pre-order tree level launched with at most this many blocks runs each
  *     child branch on its own wavefronts (same results, shorter per-wavefront
  *     work for levels too narrow to fill the GPU); 0 = never.
+ *   EPOCH_OPT_EIGEN_PRECISION: 0, 1 or 2 (default 0), FP32 instances only:
+ *     the arithmetic of the transition matrices V exp(r t Lambda) V^-1 and
+ *     their ordered products (Eq. 6-7) and of the dlogL/dQ chains.  0 = FP64
+ *     when some process's eigenvector matrix has infinity-norm condition
+ *     number cond(V) = |V| |V^-1| above 32 (FP32 rounding of the
+ *     reconstruction grows like cond(V) 2^-24), else FP32; 1 = FP32 always;
+ *     2 = FP64 always.  The matrices are stored in FP32 either way.
  * Returns EPOCH_ERR_ARG for an unknown key or a value out of range. */
 #define EPOCH_OPT_TREE_WALK 1
 #define EPOCH_OPT_WALK_RECOMPUTE 2
@@ -302,6 +329,7 @@ int epoch_get_timing(EpochInstance* inst, double* ms_out, int64_t* counts_out);
 #define EPOCH_OPT_TARGET_BLOCKS 7
 #define EPOCH_OPT_CHAIN_SPLIT 8
 #define EPOCH_OPT_INCREMENTAL 9
+#define EPOCH_OPT_EIGEN_PRECISION 10
 int epoch_set_option(EpochInstance* inst, int32_t key, int64_t value);
 
 /* ---- Incremental re-evaluation for MCMC proposals (Introduction: the method
@@ -350,11 +378,15 @@ int epoch_batch_create(EpochInstance* const* insts, int32_t n, const char* tune_
 
 /* Evaluate every member: logL: host [n] out.  what: EPOCH_EVAL_* bits (logL
  * is always computed).  Gradients stay on the device; read them with
- * epoch_batch_gradients.  Synchronises the batch's own stream. */
+ * epoch_batch_gradients.  Synchronises the batch's own stream.  As for one
+ * instance (root_log_likelihood): a member whose logL is -inf makes the call
+ * return EPOCH_WARN_UNDERFLOW (every logL written) and has no gradient; a NaN
+ * or +inf logL returns EPOCH_ERR_NUMERIC. */
 int epoch_batch_evaluate(EpochBatch* batch, uint32_t what, double* logL);
 
 /* Gradients of member i from the last evaluation (host arrays as in
- * log_likelihood_gradient; either may be NULL). */
+ * log_likelihood_gradient; either may be NULL).  EPOCH_ERR_NUMERIC for a
+ * member whose logL was -inf. */
 int epoch_batch_gradients(EpochBatch* batch, int32_t i, double* d_branch, double* d_Q);
 
 /* Tuned launch shape in use (for reporting): blocks each merged level launch

@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import warnings
 from typing import Optional, Sequence
 
 import numpy as np
@@ -22,6 +23,7 @@ EPOCH_ERR_OOM = -3
 EPOCH_ERR_HIP = -4
 EPOCH_ERR_NUMERIC = -5
 EPOCH_WARN_EIGEN_RESIDUAL = 1
+EPOCH_WARN_UNDERFLOW = 2
 EPOCH_FP32 = 1
 EPOCH_FP64 = 2
 EPOCH_GRAD_BRANCH = 0x1
@@ -159,7 +161,14 @@ def _i32(a):
     return np.ascontiguousarray(a, dtype=np.int32)
 
 
+class EpochUnderflowWarning(RuntimeWarning):
+    """A pattern's likelihood is zero in the working precision: logL is -inf and the state has no gradient."""
+
+
 def check(code: int, allow_warning: bool = True) -> int:
+    if code == EPOCH_WARN_UNDERFLOW and allow_warning:
+        warnings.warn(EpochUnderflowWarning(load().epoch_last_error().decode()), stacklevel=3)
+        return code
     if code == EPOCH_OK or (allow_warning and code > 0):
         return code
     msg = load().epoch_last_error().decode()
@@ -199,6 +208,7 @@ EPOCH_OPT_SPLIT_BLOCKS = 6
 EPOCH_OPT_TARGET_BLOCKS = 7
 EPOCH_OPT_CHAIN_SPLIT = 8
 EPOCH_OPT_INCREMENTAL = 9
+EPOCH_OPT_EIGEN_PRECISION = 10
 
 
 def plan_walk(parent, height, recompute_tips: int = 2):

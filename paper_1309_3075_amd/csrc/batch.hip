@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <limits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -465,18 +466,29 @@ int epoch_batch_evaluate(EpochBatch* b, uint32_t what, double* logL) {
     EpochInstance* in = b->insts[q];
     mark_dirty_all(in);  // the graph's launches are not tracked: the member's next single evaluation is full
     in->P_valid = in->partials_valid = true;
-    in->logL_valid = std::isfinite(logL[q]);
-    in->grad_ready = (what & (kGradBranch | kGradQ)) != 0;
-    in->gradQ_ready = (what & kGradQ) != 0;
+    const bool under = logL[q] == -std::numeric_limits<double>::infinity();
+    in->logL_valid = std::isfinite(logL[q]) || under;
+    in->logL_underflow = under;
+    in->grad_ready = (what & (kGradBranch | kGradQ)) != 0 && !under;
+    in->gradQ_ready = (what & kGradQ) != 0 && !under;
   }
-  for (size_t q = 0; q < n; ++q)
-    if (!std::isfinite(logL[q])) return set_error(EPOCH_ERR_NUMERIC, "batch member %zu: log-likelihood not finite", q);
+  int first_under = -1;
+  for (size_t q = 0; q < n; ++q) {
+    if (std::isnan(logL[q]) || logL[q] == std::numeric_limits<double>::infinity())
+      return set_error(EPOCH_ERR_NUMERIC, "batch member %zu: log-likelihood not finite", q);
+    if (first_under < 0 && logL[q] == -std::numeric_limits<double>::infinity()) first_under = (int)q;
+  }
+  if (first_under >= 0)
+    return set_error(EPOCH_WARN_UNDERFLOW, "batch member %d: a pattern's likelihood is zero in the working precision "
+                     "(logL = -inf; no gradient for that member)", first_under);
   return EPOCH_OK;
 }
 
 int epoch_batch_gradients(EpochBatch* b, int32_t i, double* d_branch, double* d_Q) {
   if (!b || i < 0 || i >= (int)b->insts.size()) return set_error(EPOCH_ERR_ARG, "bad batch member index");
   EpochInstance* in = b->insts[i];
+  if ((d_branch || d_Q) && in->logL_valid && in->logL_underflow)
+    return set_error(EPOCH_ERR_NUMERIC, "batch member %d: the log-likelihood is -inf: no gradient", i);
   if (d_branch && !in->grad_ready) return set_error(EPOCH_ERR_STATE, "the last batch evaluation had no gradient");
   if (d_Q && !in->gradQ_ready) return set_error(EPOCH_ERR_STATE, "the last batch evaluation had no dlogL/dQ");
   int rc = EPOCH_OK;

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <string>
 #include <vector>
 
@@ -89,6 +90,13 @@ int phase_end(EpochInstance* in, int k) {
 namespace {
 
 // Above this condition number of V the FP32 path reconstructs exp(tQ) in FP64.
+// FP32 reconstruction errs by about cond(V) 2^-24 of the largest entry, which
+// is large next to the small entries of P and dP/dt that weigh most in the
+// gradients.  Measured against the FP64 oracle with FP32 products throughout:
+// the 61-state codon systems (cond 50-65) keep logL within 4e-7 but put one
+// branch-gradient component of a 64-problem batch 1.9e-3 off (the FP32
+// tolerance is 1e-3), and the 40-state asymmetric trait systems (cond 250-2,800,
+// 48 intervals) miss logL by 3e-3 on 200 taxa and give NaN on 2,000.
 constexpr double kCondFP32 = 32.0;
 
 void release(DevBuf& b) {
@@ -532,6 +540,19 @@ int epoch_set_root_frequencies(EpochInstance* in, const double* pi) {
   return EPOCH_OK;
 }
 
+// Arithmetic of exp(tQ) = V exp(t Lambda) V^-1 and of the dlogL/dQ chains in an
+// FP32 instance: FP64 when some eigenvector matrix has infinity-norm condition
+// number above kCondFP32 (EPOCH_OPT_EIGEN_PRECISION 0), always FP32 (1), or
+// always FP64 (2).  Returns whether it changed.
+static bool choose_eig_precision(EpochInstance* in) {
+  const bool was = in->eig_fp64;
+  in->eig_fp64 = in->eig_mode == 2;
+  if (in->eig_mode == 0)
+    for (int k = 0; k < in->S; ++k)
+      if (in->cond[k] > kCondFP32) in->eig_fp64 = true;
+  return was != in->eig_fp64;
+}
+
 int set_epoch_eigensystems(EpochInstance* in, int32_t s, const double* V, const double* Vinv,
                            const double* lambda_re, const double* lambda_im, const double* Q,
                            double* residual_out) {
@@ -600,13 +621,9 @@ int set_epoch_eigensystems(EpochInstance* in, int32_t s, const double* V, const 
       ni = std::max(ni, ri);
     }
     in->cond[s] = nv * ni;
-    const bool was_fp64 = in->eig_fp64;
-    in->eig_fp64 = false;
-    for (int k = 0; k < in->S; ++k)
-      if (in->cond[k] > kCondFP32) in->eig_fp64 = true;
     // a new eigensystem changes the factors of process s only (Eq. 6-7), unless the
     // arithmetic of every reconstruction changes with it
-    if (was_fp64 != in->eig_fp64 || !in->have_eig[s]) mark_dirty_all(in);
+    if (choose_eig_precision(in) || !in->have_eig[s]) mark_dirty_all(in);
     else mark_dirty_process(in, s);
   }
   // upload this process's slices in double and in the compute type
@@ -821,6 +838,23 @@ int update_partials(EpochInstance* in) {
   return EPOCH_OK;
 }
 
+// The state after a log-likelihood reached the host: -inf (a pattern's
+// likelihood is zero in the working precision) is a warning that leaves the
+// state queryable but without gradients; NaN or +inf is an error.
+static int classify_logL(EpochInstance* in, double v) {
+  in->logL_underflow = false;
+  if (std::isnan(v) || v == std::numeric_limits<double>::infinity()) {
+    in->logL_valid = false;
+    return set_error(EPOCH_ERR_NUMERIC, "log-likelihood is not finite (%g)", v);
+  }
+  in->logL_valid = true;
+  if (v == -std::numeric_limits<double>::infinity()) {
+    in->logL_underflow = true;
+    return set_error(EPOCH_WARN_UNDERFLOW, "a pattern's likelihood is zero in the working precision (logL = -inf)");
+  }
+  return EPOCH_OK;
+}
+
 int root_log_likelihood(EpochInstance* in, double* logL, double* site_logL) {
   if (!in || !logL) return set_error(EPOCH_ERR_ARG, "instance and logL must not be NULL");
   if (!in->partials_valid) return set_error(EPOCH_ERR_STATE, "update_partials has not been called");
@@ -829,12 +863,7 @@ int root_log_likelihood(EpochInstance* in, double* logL, double* site_logL) {
   EPOCH_TRY(fastpath_root(in));
   EPOCH_TRY(download(in, logL, in->result.ptr, sizeof(double)));
   if (site_logL) EPOCH_TRY(download(in, site_logL, in->site.ptr, (size_t)in->P * sizeof(double)));
-  if (!std::isfinite(*logL)) {
-    in->logL_valid = false;
-    return set_error(EPOCH_ERR_NUMERIC, "log-likelihood is not finite (%g)", *logL);
-  }
-  in->logL_valid = true;
-  return EPOCH_OK;
+  return classify_logL(in, *logL);
 }
 
 int log_likelihood_gradient(EpochInstance* in, double* d_branch, double* d_Q) {
@@ -844,6 +873,7 @@ int log_likelihood_gradient(EpochInstance* in, double* d_branch, double* d_Q) {
   if (d_Q && !(in->cfg.flags & EPOCH_GRAD_Q))
     return set_error(EPOCH_ERR_STATE, "instance created without EPOCH_GRAD_Q");
   if (!in->logL_valid) return set_error(EPOCH_ERR_STATE, "root_log_likelihood has not been called for this state");
+  if (in->logL_underflow) return set_error(EPOCH_ERR_NUMERIC, "the log-likelihood of this state is -inf: no gradient");
   if (!d_branch && !d_Q) return EPOCH_OK;
   EPOCH_TRY(fastpath_gradient(in, d_Q != nullptr));
   if (d_branch) EPOCH_TRY(download(in, d_branch, in->dbranch.ptr, (size_t)in->n_nodes * sizeof(double)));
@@ -855,6 +885,7 @@ int epoch_time_gradient(EpochInstance* in, double* d_height, double* d_boundary)
   if (!in) return set_error(EPOCH_ERR_ARG, "NULL instance");
   if (!(in->cfg.flags & EPOCH_GRAD_TIME)) return set_error(EPOCH_ERR_STATE, "instance created without EPOCH_GRAD_TIME");
   if (!in->logL_valid) return set_error(EPOCH_ERR_STATE, "root_log_likelihood has not been called for this state");
+  if (in->logL_underflow) return set_error(EPOCH_ERR_NUMERIC, "the log-likelihood of this state is -inf: no gradient");
   if (!d_height && !d_boundary) return EPOCH_OK;
   if (in->G_gen != in->eval_gen) EPOCH_TRY(fastpath_gradient(in, false));  // the branch adjoints of this state
   double *dh = nullptr, *db = nullptr;
@@ -901,9 +932,12 @@ int epoch_evaluate(EpochInstance* in, uint32_t what, double* logL, double* site_
                                        hipMemcpyDeviceToHost, in->stream), "gradient download"));
   EPOCH_TRY(hip_check(hipStreamSynchronize(in->stream), "evaluation sync"));
   in->P_valid = in->partials_valid = true;
-  if (!std::isfinite(*logL)) return set_error(EPOCH_ERR_NUMERIC, "log-likelihood is not finite (%g)", *logL);
-  in->logL_valid = true;
-  return EPOCH_OK;
+  const int rc = classify_logL(in, *logL);
+  if (rc == EPOCH_WARN_UNDERFLOW) {  // the gradient pass divided by zero site likelihoods
+    if (gb) std::fill(d_branch, d_branch + in->n_nodes, std::numeric_limits<double>::quiet_NaN());
+    if (gq) std::fill(d_Q, d_Q + (size_t)in->S * in->K * in->K, std::numeric_limits<double>::quiet_NaN());
+  }
+  return rc;
 }
 
 int epoch_get_kernel_path(EpochInstance* in, int32_t* out) {
@@ -1009,6 +1043,13 @@ int epoch_set_option(EpochInstance* in, int32_t key, int64_t value) {
       if (value < 1 || value > (1 << 30)) return set_error(EPOCH_ERR_ARG, "EPOCH_OPT_TARGET_BLOCKS out of range");
       in->codon_target_blocks = (int)value;
       break;
+    case EPOCH_OPT_EIGEN_PRECISION:
+      if (value < 0 || value > 2) return set_error(EPOCH_ERR_ARG, "EPOCH_OPT_EIGEN_PRECISION takes 0, 1 or 2");
+      in->eig_mode = (int)value;
+      choose_eig_precision(in);
+      in->P_valid = in->partials_valid = in->logL_valid = false;
+      in->pstage_split = false;
+      return EPOCH_OK;
     case EPOCH_OPT_SPLIT_BLOCKS:
       if (value < 0 || value > (1 << 30)) return set_error(EPOCH_ERR_ARG, "EPOCH_OPT_SPLIT_BLOCKS out of range");
       in->codon_split_blocks = (int)value;

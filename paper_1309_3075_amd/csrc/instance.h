@@ -108,10 +108,12 @@ struct EpochInstance {
   // FP32 instances reconstruct exp(tQ) from the eigensystem in FP64 when some
   // V is ill-conditioned (the FP32 rounding error grows like cond(V) * 2^-24).
   bool eig_fp64 = false;
+  int eig_mode = 0;  // EPOCH_OPT_EIGEN_PRECISION
   double h_cat_rates[8] = {0}, h_cat_weights[8] = {0};
   bool have_tips = false, have_weights = false, have_cats = false, have_pi = false;
   bool have_tree = false;
   bool P_valid = false, partials_valid = false, logL_valid = false;
+  bool logL_underflow = false;  // the last logL was -inf (EPOCH_WARN_UNDERFLOW): no gradient of this state
   bool grad_ready = false, gradQ_ready = false;  // gradients left on the device by a batch evaluation
   uint64_t tree_generation = 0;                   // bumped by set_tree_epochs
   uint64_t option_generation = 0;                 // bumped by every epoch_set_option call

@@ -208,12 +208,14 @@ class EpochLikelihood:
 
     def set_option(self, key: str, value: int):
         """Kernel-selection option (epoch_set_option): 'tree_walk', 'walk_recompute', 'walk_blocks',
-        'walk_tiles', 'level_min_tiles', 'split_blocks', 'target_blocks', 'chain_split', 'incremental'."""
+        'walk_tiles', 'level_min_tiles', 'split_blocks', 'target_blocks', 'chain_split', 'incremental',
+        'eigen_precision'."""
         k = {"tree_walk": _abi.EPOCH_OPT_TREE_WALK, "walk_recompute": _abi.EPOCH_OPT_WALK_RECOMPUTE,
              "walk_blocks": _abi.EPOCH_OPT_WALK_BLOCKS, "walk_tiles": _abi.EPOCH_OPT_WALK_TILES,
              "level_min_tiles": _abi.EPOCH_OPT_LEVEL_MIN_TILES,
              "split_blocks": _abi.EPOCH_OPT_SPLIT_BLOCKS, "target_blocks": _abi.EPOCH_OPT_TARGET_BLOCKS,
-             "chain_split": _abi.EPOCH_OPT_CHAIN_SPLIT, "incremental": _abi.EPOCH_OPT_INCREMENTAL}[key]
+             "chain_split": _abi.EPOCH_OPT_CHAIN_SPLIT, "incremental": _abi.EPOCH_OPT_INCREMENTAL,
+             "eigen_precision": _abi.EPOCH_OPT_EIGEN_PRECISION}[key]
         check(self._lib.epoch_set_option(self._h, k, int(value)))
 
     def set_timing(self, enable: bool = True):

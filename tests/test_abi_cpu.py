@@ -33,6 +33,17 @@ def test_library_exports_every_declared_symbol():
     assert b"epochlik" in lib.epoch_version()
 
 
+def test_header_constants_match_the_binding():
+    """Every EPOCH_* integer constant the header defines has the same value in the binding."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    defs = dict(re.findall(r"^#define\s+(EPOCH_\w+)\s+\(?(-?(?:0x[0-9a-fA-F]+|\d+))u?\)?", text, flags=re.M))
+    assert {"EPOCH_WARN_UNDERFLOW", "EPOCH_ERR_NUMERIC", "EPOCH_OPT_INCREMENTAL"} <= set(defs)
+    for name, val in defs.items():
+        if hasattr(_abi, name):
+            assert getattr(_abi, name) == int(val, 0), name
+    assert _abi.EPOCH_WARN_UNDERFLOW > 0 > _abi.EPOCH_ERR_NUMERIC
+
+
 def _cfg(**kw):
     c = _abi.EpochConfig()
     c.n_tips, c.n_patterns, c.n_states, c.n_categories = 4, 10, 4, 1
