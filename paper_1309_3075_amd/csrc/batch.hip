@@ -132,8 +132,8 @@ int build_schedule(EpochBatch* b) {
   std::vector<std::vector<int32_t>> gs;
   codon_build_schedule(cin, b->target_blocks, b->sched, gs);
   b->sched.split_blocks = b->split_blocks;
-  const size_t n = b->insts.size();
   const auto& sc = b->sched;
+  const size_t n = (size_t)sc.n_problems;  // one problem per member and rate category
   size_t total = 0;
   for (size_t q = 0; q < n; ++q) total += sc.slot_total[q];
   int rc0 = ensure(b->gpart, std::max<size_t>(1, total) * kCodonSlotBytes);
@@ -149,7 +149,8 @@ int build_schedule(EpochBatch* b) {
                    "batch gslots upload");
     if (rc) return rc;
     float* region = static_cast<float*>(b->gpart.ptr) + off * (kCodonSlotBytes / sizeof(float));
-    desc[q] = codon_descriptor(b->insts[q], static_cast<const int32_t*>(b->gslots[q].ptr), region);
+    desc[q] = codon_descriptor(b->insts[sc.desc_inst[q]], sc.desc_cat[q], static_cast<const int32_t*>(b->gslots[q].ptr),
+                               region);
     off += sc.slot_total[q];
   }
   const size_t bytes = sizeof(CodonProblem) * n + sizeof(int2) * (sc.items.size() + sc.reduce_items.size());
@@ -187,7 +188,8 @@ int enqueue(EpochBatch* b, uint32_t what, const double* const* d_result_ptrs) {
   }
   if (b->merged) {
     const CodonProblem* probs = static_cast<const CodonProblem*>(b->dev.ptr);
-    const int2* items = reinterpret_cast<const int2*>(static_cast<const char*>(b->dev.ptr) + sizeof(CodonProblem) * n);
+    const int2* items = reinterpret_cast<const int2*>(static_cast<const char*>(b->dev.ptr) +
+                                                      sizeof(CodonProblem) * b->sched.n_problems);
     const int2* red = items + b->sched.items.size();
     int rc = codon_launch_post(b->sched, probs, items, b->stream);
     if (!rc) rc = codon_launch_root(b->sched, probs, b->stream);
@@ -290,11 +292,15 @@ std::string tune_key(EpochBatch* b) {
   hipDeviceProp_t prop;
   std::string arch = "unknown";
   if (hipGetDeviceProperties(&prop, b->insts[0]->device) == hipSuccess) arch = prop.gcnArchName;
-  long tot_p = 0;
-  for (auto* in : b->insts) tot_p += in->P;
+  long tot_p = 0, tot_c = 0;
+  for (auto* in : b->insts) {
+    tot_p += in->P;
+    tot_c += in->C;
+  }
   std::ostringstream k;
   k << arch.substr(0, arch.find(':')) << "/codon/K" << b->insts[0]->K << "/fp32/n" << b->insts.size() << "/P"
     << (tot_p / (long)b->insts.size() / 1000);
+  if (tot_c != (long)b->insts.size()) k << "/C" << tot_c;  // rate categories multiply the work
   return k.str();
 }
 

@@ -111,14 +111,15 @@ struct WorkspaceItem {
   DevBuf EpochInstance::*buf;
   size_t bytes;
 };
+size_t scale_sets(const EpochConfig& c);
 std::vector<WorkspaceItem> workspace_items(const EpochConfig& c, int Kp) {
   const size_t N = c.n_tips, P = c.n_patterns, C = c.n_categories, R = c.precision == EPOCH_FP64 ? 8 : 4;
   const bool grad = (c.flags & (EPOCH_GRAD_BRANCH | EPOCH_GRAD_Q | EPOCH_GRAD_TIME)) != 0;
   std::vector<WorkspaceItem> v = {{&EpochInstance::tips, N * P},
                                   {&EpochInstance::weights, P * sizeof(double)},
-                                  {&EpochInstance::weightsT, P * R},
+                                  {&EpochInstance::weightsT, P * R * scale_sets(c)},
                                   {&EpochInstance::partials, (N - 1) * C * P * Kp * R},
-                                  {&EpochInstance::scales, (N - 1) * P * sizeof(int32_t)},
+                                  {&EpochInstance::scales, (N - 1) * P * sizeof(int32_t) * scale_sets(c)},
                                   {&EpochInstance::site, P * sizeof(double)}};
   if (grad) v.push_back({&EpochInstance::pre, (N - 1) * C * P * Kp * R});
   return v;
@@ -136,14 +137,19 @@ int padded_states(int K) {
   return (K + 15) / 16 * 16;
 }
 
-// 17..32 states in FP32 with one category (a 20-state amino-acid model, say) run on the
-// 64-state matrix-core kernels, padded to 64 states (the padding states are never observed
-// and their transition rows are the identity).
-bool small_codon_config(const EpochConfig& c) {
-  return c.n_states > 16 && c.n_states <= 32 && c.precision == EPOCH_FP32 && c.n_categories == 1 &&
-         c.kernel_path == EPOCH_KERNEL_AUTO;
+// FP32 problems of 49..64 states, and of 17..32 states (a 20-state amino-acid model, say,
+// padded to 64 states: the padding states are never observed and their transition rows
+// are the identity), run on the 64-state matrix-core kernels: with any number of rate
+// categories, or with one category under an HBM budget (pattern chunks).
+bool codon_config(const EpochConfig& c) {
+  return ((c.n_states > 48 && c.n_states <= 64) || (c.n_states > 16 && c.n_states <= 32)) &&
+         c.precision == EPOCH_FP32 && c.kernel_path == EPOCH_KERNEL_AUTO &&
+         (c.n_categories == 1 || c.hbm_budget_bytes == 0);
 }
+bool small_codon_config(const EpochConfig& c) { return codon_config(c) && c.n_states <= 32; }
 int padded_states(const EpochConfig& c) { return small_codon_config(c) ? 64 : padded_states(c.n_states); }
+// The 64-state kernels keep one scale exponent and one weight row per rate category.
+size_t scale_sets(const EpochConfig& c) { return codon_config(c) ? (size_t)c.n_categories : 1; }
 
 #define EPOCH_TRY(expr)          \
   do {                           \
@@ -320,7 +326,7 @@ int epoch_create(const EpochConfig* cfg, EpochInstance** out) {
   A(in->tips, N * P);
   A(in->amb, 256 * sizeof(uint64_t));
   A(in->weights, P * sizeof(double));
-  A(in->weightsT, P * R);
+  A(in->weightsT, P * R * scale_sets(c));
   A(in->pi, Kp * sizeof(double));
   A(in->cat, 2 * kMaxCategories * sizeof(double));
   A(in->Pm, n * C * KK * R);
@@ -345,7 +351,7 @@ int epoch_create(const EpochConfig* cfg, EpochInstance** out) {
     in->walk_enable = 1;  // partials are sized at set_tree_epochs, within the budget
   } else {
     A(in->partials, (N - 1) * C * P * Kp * R);
-    A(in->scales, (N - 1) * P * sizeof(int32_t));
+    A(in->scales, (N - 1) * P * sizeof(int32_t) * scale_sets(c));
     if (grad) A(in->pre, (N - 1) * C * P * Kp * R);
   }
   A(in->site, P * sizeof(double));

@@ -26,7 +26,7 @@ struct CodonProblem {
   float* part;
   float* pre;
   int32_t* scales;
-  const float* weightsT;
+  float* weightsT;         // FP32 pattern weights (with several categories: w_p times the category's posterior share)
   const double* weights;
   const double* pi;
   float* Gpart;
@@ -40,8 +40,12 @@ struct CodonProblem {
   const int32_t* right;
   const uint64_t* amb;    // [256] state sets of the ambiguity codes K + 1 + a (bit j = state j)
   const int32_t* gslots;  // [2 n_nodes]: dlogL/dP partial slots written per branch, then each branch's first slot
+  const double* cat;      // [2 kMaxCategories]: category rates, then weights
   int N, P, K, root, n_nodes;
   int tip_stride;         // row stride of tips (the instance's pattern count; P is this chunk's)
+  int pm_stride;          // floats from one node's transition matrix (and G, dP) to the next: C x 64 x 64
+  int cat_index, n_cats;  // this descriptor's rate category and the instance's category count; the
+                          // descriptors of one instance's categories are consecutive, category 0 first
 };
 
 // Device pointers of one problem's P stage (one instance, or one member of a batch).
@@ -75,6 +79,7 @@ struct CodonSchedule {
   std::vector<int> level_R;        // 64-pattern tiles per block of the launches of each level
   std::vector<int2> reduce_items;  // every (problem, node)
   std::vector<size_t> slot_total;  // dlogL/dP partial slots of each problem
+  std::vector<int> desc_inst, desc_cat;  // each problem's instance (index in the list given) and rate category
   int n_levels = 0, max_tiles = 0, max_pattern_blocks = 0, n_problems = 0;
   int split_blocks = 0;  // pre-order levels of at most this many blocks put each child branch on its own wavefronts
   bool amb = false;      // some problem has tips with ambiguity codes (the kernels' ambiguity instantiation)
@@ -310,7 +315,7 @@ int launch_codon_post_schedule(EpochInstance* in, const CodonSchedule& sc, const
 int launch_codon_root(EpochInstance* in);
 int launch_codon_pre_grad(EpochInstance* in);
 int codon_prepare(EpochInstance* in);
-CodonProblem codon_descriptor(const EpochInstance* in, const int32_t* gslots, float* gpart);
+CodonProblem codon_descriptor(const EpochInstance* in, int c, const int32_t* gslots, float* gpart);
 constexpr size_t kCodonSlotBytes = 64 * 64 * sizeof(float);  // one FP32 64x64 partial of dlogL/dP
 void codon_build_schedule(const std::vector<const EpochInstance*>& insts, int target_blocks, CodonSchedule& out,
                           std::vector<std::vector<int32_t>>& gslots);

@@ -1,8 +1,11 @@
 // 64-state (codon) kernels on FP32 matrix cores (v_mfma_f32_16x16x4f32).
 //
-// Applies to FP32 instances with 48 < K <= 64 (padded to 64) and one rate
-// category.  Layout as elsewhere: partials / outside vectors [slot][P][64],
-// transition matrices [node][64][64] row-major.
+// Applies to FP32 instances with 48 < K <= 64 or 16 < K <= 32 (padded to 64).
+// Each rate category is a problem of its own (a descriptor of its own): its
+// partials / outside vectors [slot][P][64] and scale exponents [slot][P] are
+// the category's region of the instance's buffers, its transition matrices
+// every C-th 64 x 64 row-major block of [node][category]; the root reduction
+// combines the categories.
 //
 // MFMA operand mapping (16x16x4, wavefront of 64 lanes, g = lane / 16,
 // r = lane % 16):  A[m][k]: m = r, k = g;  B[k][n]: k = g, n = r;
@@ -24,6 +27,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cstring>
 
 #include "device_common.h"
@@ -190,8 +194,8 @@ __global__ __launch_bounds__(256) void codon_post_level_kernel(const CodonProble
   const int u = it.y;
   const int a = pr.left[u], b = pr.right[u];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
-  stage_matrix(sPa, pr.Pm + (size_t)a * KK);
-  stage_matrix(sPb, pr.Pm + (size_t)b * KK);
+  stage_matrix(sPa, pr.Pm + (size_t)a * pr.pm_stride);
+  stage_matrix(sPb, pr.Pm + (size_t)b * pr.pm_stride);
   __syncthreads();
   stage_row_sums(sPa, K);
   stage_row_sums(sPb, K);
@@ -242,21 +246,51 @@ __global__ __launch_bounds__(256) void codon_post_level_kernel(const CodonProble
 }
 
 // ---------------------------------------------------------------------------
-// Root: one thread per pattern, L_p = sum_i pi_i x_root(p, i) in FP64; block
-// partial sums of w_p log L_p per problem (blockIdx.y).
+// Root: one thread per pattern, in FP64; block partial sums of w_p log L_p per
+// instance (blockIdx.y runs over descriptors; those of categories above 0 have
+// nothing to do).  One category: L_p = sum_i pi_i x_root(p, i) 2^E_p.  Several
+// (text after Eq. 4, rate categories): each category c has its own scale
+// exponent E_c, so L_p = 2^Emax sum_c w_c l_c 2^(E_c - Emax) with
+// l_c = sum_i pi_i x_c(p, i); the pre-order pass of category c then weighs
+// pattern p by w_p w_c l_c 2^E_c / L_p (its posterior share), written to that
+// category's weightsT.
 __global__ __launch_bounds__(256) void codon_root_kernel(const CodonProblem* __restrict__ probs) {
   __shared__ double sm[256];
   const CodonProblem& pr = probs[blockIdx.y];
+  if (pr.cat_index != 0) return;  // uniform
   const int P = pr.P, K = pr.K;
   if ((int)blockIdx.x * 256 >= P) return;  // uniform
   const int p = blockIdx.x * 256 + threadIdx.x;
   const size_t slot = pr.root - pr.N;
   double contrib = 0.0;
   if (p < P) {
-    double L = 0.0;
-    const float* x = pr.part + (slot * P + p) * KP;
-    for (int i = 0; i < K; ++i) L += pr.pi[i] * (double)x[i];
-    const double s = log(L) + (double)pr.scales[slot * P + p] * kLn2;
+    double s;
+    if (pr.n_cats == 1) {
+      double L = 0.0;
+      const float* x = pr.part + (slot * P + p) * KP;
+      for (int i = 0; i < K; ++i) L += pr.pi[i] * (double)x[i];
+      s = log(L) + (double)pr.scales[slot * P + p] * kLn2;
+    } else {
+      double l[kMaxCategories];
+      int e[kMaxCategories], emax = INT_MIN;
+      for (int c = 0; c < pr.n_cats; ++c) {
+        const CodonProblem& pc = probs[blockIdx.y + c];
+        const float* x = pc.part + (slot * P + p) * KP;
+        double acc = 0.0;
+        for (int i = 0; i < K; ++i) acc += pr.pi[i] * (double)x[i];
+        l[c] = pr.cat[kMaxCategories + c] * acc;
+        e[c] = pc.scales[slot * P + p];
+        if (l[c] > 0.0) emax = max(emax, e[c]);
+      }
+      double L = 0.0;
+      for (int c = 0; c < pr.n_cats; ++c) {
+        l[c] = l[c] > 0.0 ? ldexp(l[c], e[c] - emax) : 0.0;
+        L += l[c];
+      }
+      s = L > 0.0 ? log(L) + (double)emax * kLn2 : -INFINITY;
+      for (int c = 0; c < pr.n_cats; ++c)
+        probs[blockIdx.y + c].weightsT[p] = L > 0.0 ? (float)(pr.weights[p] * (l[c] / L)) : 0.f;
+    }
     pr.site[p] = s;
     contrib = pr.weights[p] * s;
   }
@@ -268,6 +302,7 @@ __global__ __launch_bounds__(256) void codon_root_kernel(const CodonProblem* __r
 __global__ __launch_bounds__(256) void codon_final_kernel(const CodonProblem* __restrict__ probs) {
   __shared__ double sm[256];
   const CodonProblem& pr = probs[blockIdx.x];
+  if (pr.cat_index != 0) return;  // uniform
   const int nb = (pr.P + 255) / 256;
   double acc = 0.0;
   for (int k = threadIdx.x; k < nb; k += 256) acc += pr.blocksum[k];
@@ -406,8 +441,8 @@ __global__ __launch_bounds__(256, 2) void codon_pre_level_kernel(const CodonProb
   }
   const int n_tiles = min(R, (P - base + TILE - 1) / TILE);  // uniform over the block
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
-  stage_matrix(sPa, pr.Pm + (size_t)a * KK);
-  stage_matrix(sPb, pr.Pm + (size_t)b * KK);
+  stage_matrix(sPa, pr.Pm + (size_t)a * pr.pm_stride);
+  stage_matrix(sPb, pr.Pm + (size_t)b * pr.pm_stride);
   __syncthreads();
   stage_row_sums(sPa, K);
   stage_row_sums(sPb, K);
@@ -590,7 +625,7 @@ __global__ __launch_bounds__(512, 1) void codon_pre_split_kernel(const CodonProb
   const int c = s ? b : a;
   {  // threads 0..255 stage P_left, 256..511 P_right
     const int h = threadIdx.x >> 8;
-    stage_matrix(sh.sP[h], pr.Pm + (size_t)(h ? b : a) * KK, threadIdx.x & 255);
+    stage_matrix(sh.sP[h], pr.Pm + (size_t)(h ? b : a) * pr.pm_stride, threadIdx.x & 255);
     __syncthreads();
     stage_row_sums(sh.sP[h], K, threadIdx.x & 255);
     __syncthreads();
@@ -722,13 +757,15 @@ __global__ __launch_bounds__(256) void codon_grad_reduce_kernel(const CodonProbl
   }
   for (; k < ns; ++k) s0 += (double)src[(size_t)k * KK];
   double s = (s0 + s1) + (s2 + s3);
-  if (accumulate) s += pr.G[(size_t)v * KK + e];  // earlier pattern chunks
-  pr.G[(size_t)v * KK + e] = s;
-  const double d = block_sum<256>(s * (double)pr.dPm[(size_t)v * KK + e], sm);
+  if (accumulate) s += pr.G[(size_t)v * pr.pm_stride + e];  // earlier pattern chunks
+  pr.G[(size_t)v * pr.pm_stride + e] = s;
+  const double d = block_sum<256>(s * (double)pr.dPm[(size_t)v * pr.pm_stride + e], sm);
   if (threadIdx.x == 0) dpart[blockIdx.x] = d;
 }
 
-// dlogL/dl of each branch from the chunk shares, in a fixed order.
+// dlogL/dl of each branch from the chunk shares, in a fixed order: the sum over
+// rate categories of <G_c, dP_c/dl> (the reduce items of an instance's
+// categories are consecutive runs of n_nodes, category 0 first).
 __global__ __launch_bounds__(256) void codon_dbranch_kernel(const CodonProblem* __restrict__ probs,
                                                             const int2* __restrict__ items, int n_items,
                                                             const double* __restrict__ dpart) {
@@ -736,8 +773,10 @@ __global__ __launch_bounds__(256) void codon_dbranch_kernel(const CodonProblem* 
   if (i >= n_items) return;
   const int2 it = items[i];
   const CodonProblem& pr = probs[it.x];
+  if (pr.cat_index != 0) return;
   double d = 0.0;
-  for (int c = 0; c < kReduceChunks; ++c) d += dpart[(size_t)i * kReduceChunks + c];
+  for (int c = 0; c < pr.n_cats; ++c)
+    for (int k = 0; k < kReduceChunks; ++k) d += dpart[((size_t)i + (size_t)c * pr.n_nodes) * kReduceChunks + k];
   pr.dbranch[it.y] = it.y == pr.root ? 0.0 : d;
 }
 
@@ -755,19 +794,24 @@ int codon_tiles_per_block(int tiles, int n_items, int target_blocks, int r_max) 
 
 }  // namespace
 
-CodonProblem codon_descriptor(const EpochInstance* in, const int32_t* gslots, float* gpart) {
+// The descriptor of rate category c of an instance: its transition matrices,
+// dP/dl and G are every C-th 64 x 64 block ([node][category]); its partials,
+// outside vectors, scale exponents and weights are the c-th of C equal regions.
+CodonProblem codon_descriptor(const EpochInstance* in, int c, const int32_t* gslots, float* gpart) {
+  const size_t C = in->C, Nm1 = in->N - 1, P = in->P;
   CodonProblem d{};
-  d.Pm = static_cast<const float*>(in->Pm.ptr);
+  d.Pm = static_cast<const float*>(in->Pm.ptr) + c * KK;
   d.tips = static_cast<const uint8_t*>(in->tips.ptr);
-  d.part = static_cast<float*>(in->partials.ptr);
-  d.pre = static_cast<float*>(in->pre.ptr);
-  d.scales = static_cast<int32_t*>(in->scales.ptr);
-  d.weightsT = static_cast<const float*>(in->weightsT.ptr);
+  d.part = static_cast<float*>(in->partials.ptr) + c * Nm1 * P * KP;
+  d.pre = in->pre.ptr ? static_cast<float*>(in->pre.ptr) + c * Nm1 * P * KP : nullptr;
+  d.scales = static_cast<int32_t*>(in->scales.ptr) + c * Nm1 * P;
+  d.weightsT = static_cast<float*>(in->weightsT.ptr) + c * P;
   d.weights = static_cast<const double*>(in->weights.ptr);
   d.pi = static_cast<const double*>(in->pi.ptr);
+  d.cat = static_cast<const double*>(in->cat.ptr);
   d.Gpart = gpart;
-  d.dPm = static_cast<const float*>(in->dPm.ptr);
-  d.G = static_cast<double*>(in->G.ptr);
+  d.dPm = in->dPm.ptr ? static_cast<const float*>(in->dPm.ptr) + c * KK : nullptr;
+  d.G = in->G.ptr ? static_cast<double*>(in->G.ptr) + c * KK : nullptr;
   d.dbranch = static_cast<double*>(in->dbranch.ptr);
   d.site = static_cast<double*>(in->site.ptr);
   d.blocksum = static_cast<double*>(in->blocksum.ptr);
@@ -782,34 +826,48 @@ CodonProblem codon_descriptor(const EpochInstance* in, const int32_t* gslots, fl
   d.K = in->K;
   d.root = in->plan.root;
   d.n_nodes = in->n_nodes;
+  d.pm_stride = (int)(C * KK);
+  d.cat_index = c;
+  d.n_cats = (int)C;
   return d;
 }
 
 // Merged level schedule over one or more problems (levels counted from the
-// tips).  Each level gets R 64-pattern tiles per block, with R chosen so that
-// the level's launch has about target_blocks blocks; every block of a node
-// writes one dlogL/dP slot for each of the node's two child branches.
-// gslots[q] holds, per node, the number of slots of its branch and then the
-// index of its first slot in problem q's slot array.
+// tips).  Each instance contributes one problem per rate category (its
+// descriptors, consecutive, category 0 first: desc_inst / desc_cat).  Each
+// level gets R 64-pattern tiles per block, with R chosen so that the level's
+// launch has about target_blocks blocks; every block of a node writes one
+// dlogL/dP slot for each of the node's two child branches.  gslots[q] holds,
+// per node, the number of slots of its branch and then the index of its first
+// slot in problem q's slot array.
 void codon_build_schedule(const std::vector<const EpochInstance*>& insts, int target_blocks, CodonSchedule& out,
                           std::vector<std::vector<int32_t>>& gslots) {
   out.items.clear();
   out.level_off.assign(1, 0);
   out.level_R.clear();
   out.reduce_items.clear();
+  out.desc_inst.clear();
+  out.desc_cat.clear();
+  for (size_t i = 0; i < insts.size(); ++i)
+    for (int c = 0; c < insts[i]->C; ++c) {
+      out.desc_inst.push_back((int)i);
+      out.desc_cat.push_back(c);
+    }
+  const size_t nd = out.desc_inst.size();
+  auto inst = [&](size_t q) { return insts[out.desc_inst[q]]; };
   int n_levels = 0, max_tiles = 0, max_pblocks = 0;
   for (auto* in : insts) {
     n_levels = std::max(n_levels, in->plan.n_levels);
     max_tiles = std::max(max_tiles, (codon_chunk_patterns(in) + TILE - 1) / TILE);
     max_pblocks = std::max(max_pblocks, (codon_chunk_patterns(in) + 255) / 256);
   }
-  gslots.assign(insts.size(), {});
-  out.slot_total.assign(insts.size(), 0);
-  for (size_t q = 0; q < insts.size(); ++q) gslots[q].assign(2 * (size_t)insts[q]->n_nodes, 0);
+  gslots.assign(nd, {});
+  out.slot_total.assign(nd, 0);
+  for (size_t q = 0; q < nd; ++q) gslots[q].assign(2 * (size_t)inst(q)->n_nodes, 0);
   for (int l = 1; l <= n_levels; ++l) {
     const size_t begin = out.items.size();
-    for (size_t q = 0; q < insts.size(); ++q) {
-      const auto& pl = insts[q]->plan;
+    for (size_t q = 0; q < nd; ++q) {
+      const auto& pl = inst(q)->plan;
       if (l > pl.n_levels) continue;
       for (int k = pl.level_offset[l]; k < pl.level_offset[l + 1]; ++k) out.items.push_back(make_int2((int)q, pl.level_nodes[k]));
     }
@@ -819,10 +877,10 @@ void codon_build_schedule(const std::vector<const EpochInstance*>& insts, int ta
     out.level_R.push_back(R);
     for (size_t k = begin; k < out.items.size(); ++k) {
       const int q = out.items[k].x, u = out.items[k].y;
-      const auto& pl = insts[q]->plan;
-      const int tiles = (codon_chunk_patterns(insts[q]) + TILE - 1) / TILE;
+      const auto& pl = inst(q)->plan;
+      const int tiles = (codon_chunk_patterns(inst(q)) + TILE - 1) / TILE;
       const int used = (tiles + R - 1) / R;
-      const int n = insts[q]->n_nodes;
+      const int n = inst(q)->n_nodes;
       for (int child : {pl.left[u], pl.right[u]}) {
         gslots[q][child] = used;
         gslots[q][n + child] = (int32_t)out.slot_total[q];
@@ -830,14 +888,14 @@ void codon_build_schedule(const std::vector<const EpochInstance*>& insts, int ta
       }
     }
   }
-  for (size_t q = 0; q < insts.size(); ++q)
-    for (int v = 0; v < insts[q]->n_nodes; ++v) out.reduce_items.push_back(make_int2((int)q, v));
+  for (size_t q = 0; q < nd; ++q)
+    for (int v = 0; v < inst(q)->n_nodes; ++v) out.reduce_items.push_back(make_int2((int)q, v));
   out.amb = false;
   for (auto* in : insts) out.amb = out.amb || in->tips_amb;
   out.n_levels = n_levels;
   out.max_tiles = max_tiles;
   out.max_pattern_blocks = max_pblocks;
-  out.n_problems = (int)insts.size();
+  out.n_problems = (int)nd;
 }
 
 int codon_launch_post(const CodonSchedule& sc, const CodonProblem* d_probs, const int2* d_items, hipStream_t st) {
@@ -901,24 +959,31 @@ int codon_prepare(EpochInstance* in) {
   in->codon_sched.split_blocks = in->codon_split_blocks;
   const auto& sc = in->codon_sched;
   const bool grad = (in->cfg.flags & (EPOCH_GRAD_BRANCH | EPOCH_GRAD_Q)) != 0;
-  int rc = ensure(in->gslots, gslots[0].size() * sizeof(int32_t));
-  if (!rc && grad) rc = ensure(in->Gpart, std::max<size_t>(1, sc.slot_total[0]) * kCodonSlotBytes);
+  const int C = in->C;  // one problem per category (C > 1 only without pattern chunks)
+  const size_t gs = gslots[0].size();
+  int rc = ensure(in->gslots, C * gs * sizeof(int32_t));
+  if (!rc && grad) rc = ensure(in->Gpart, std::max<size_t>(1, C * sc.slot_total[0]) * kCodonSlotBytes);
   if (!rc && grad) rc = ensure(in->codon_aux, codon_dpart_bytes(sc));
   if (rc) return rc;
   const int nc = in->codon_nchunks;
-  std::vector<CodonProblem> desc(nc);
-  const CodonProblem d = codon_descriptor(in, static_cast<const int32_t*>(in->gslots.ptr), static_cast<float*>(in->Gpart.ptr));
-  for (int j = 0; j < nc; ++j) {
-    const int p0 = j * codon_chunk_patterns(in);
-    desc[j] = d;
-    desc[j].P = std::min(in->P - p0, codon_chunk_patterns(in));
-    desc[j].tips = d.tips + p0;
-    desc[j].weightsT = d.weightsT + p0;
-    desc[j].weights = d.weights + p0;
-    desc[j].site = d.site + p0;
-    desc[j].result = nc > 1 ? d.result + 1 + j : d.result;
+  std::vector<CodonProblem> desc(nc * C);
+  for (int c = 0; c < C; ++c) {
+    const CodonProblem d =
+        codon_descriptor(in, c, static_cast<const int32_t*>(in->gslots.ptr) + c * gs,
+                         static_cast<float*>(in->Gpart.ptr) + c * sc.slot_total[0] * (kCodonSlotBytes / sizeof(float)));
+    for (int j = 0; j < nc; ++j) {  // nc > 1 only with one category
+      const int p0 = j * codon_chunk_patterns(in);
+      CodonProblem& dj = desc[j * C + c];
+      dj = d;
+      dj.P = std::min(in->P - p0, codon_chunk_patterns(in));
+      dj.tips = d.tips + p0;
+      dj.weightsT = d.weightsT + p0;
+      dj.weights = d.weights + p0;
+      dj.site = d.site + p0;
+      dj.result = nc > 1 ? d.result + 1 + j : d.result;
+    }
   }
-  const size_t dbytes = sizeof(CodonProblem) * nc;
+  const size_t dbytes = sizeof(CodonProblem) * desc.size();
   const size_t bytes = dbytes + sizeof(int2) * (sc.items.size() + sc.reduce_items.size());
   rc = ensure(in->codon_dev, bytes);
   if (rc) return rc;
@@ -927,10 +992,12 @@ int codon_prepare(EpochInstance* in) {
   memcpy(h.data() + dbytes, sc.items.data(), sizeof(int2) * sc.items.size());
   memcpy(h.data() + dbytes + sizeof(int2) * sc.items.size(), sc.reduce_items.data(),
          sizeof(int2) * sc.reduce_items.size());
+  std::vector<int32_t> hg(C * gs);
+  for (int c = 0; c < C; ++c) std::copy(gslots[c].begin(), gslots[c].end(), hg.begin() + c * gs);
   rc = hip_check(hipMemcpyAsync(in->codon_dev.ptr, h.data(), bytes, hipMemcpyHostToDevice, in->stream), "codon schedule upload");
   if (!rc)
-    rc = hip_check(hipMemcpyAsync(in->gslots.ptr, gslots[0].data(), gslots[0].size() * sizeof(int32_t),
-                                  hipMemcpyHostToDevice, in->stream), "gslots upload");
+    rc = hip_check(hipMemcpyAsync(in->gslots.ptr, hg.data(), hg.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                  in->stream), "gslots upload");
   if (!rc) rc = hip_check(hipStreamSynchronize(in->stream), "codon schedule sync");
   return rc;
 }
@@ -939,7 +1006,7 @@ namespace {
 const CodonProblem* dev_probs(EpochInstance* in) { return static_cast<const CodonProblem*>(in->codon_dev.ptr); }
 const int2* dev_items(EpochInstance* in) {
   return reinterpret_cast<const int2*>(static_cast<const char*>(in->codon_dev.ptr) +
-                                       sizeof(CodonProblem) * in->codon_nchunks);
+                                       sizeof(CodonProblem) * in->codon_nchunks * in->C);
 }
 const int2* dev_reduce_items(EpochInstance* in) { return dev_items(in) + in->codon_sched.items.size(); }
 }  // namespace

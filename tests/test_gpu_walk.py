@@ -266,15 +266,23 @@ def test_generic_hbm_budget_streams_pattern_chunks(K, C, kernel, precision):
         logL, site = lik.log_likelihood(site=True)
         db, dq = lik.gradient(branch=True, Q=True)
         one = lik.evaluate(branch=True, Q=True, site=True)
+        path = lik.kernel_path()
     with from_problem(prob, precision, **kw) as lik:
         ref = lik.evaluate(branch=True, Q=True, site=True)
+        same_kernels = lik.kernel_path() == path
     want = O.log_likelihood(prob)
     ob, oq = O.gradient(prob)
     assert abs(logL - want) <= TOL_LOGL[precision] * abs(want)
     assert np.linalg.norm(db - ob) <= TOL_GRAD[precision] * np.linalg.norm(ob)
     assert np.linalg.norm(dq - oq) <= TOL_GRAD[precision] * np.linalg.norm(oq)
+    assert np.array_equal(one[1], site)
+    if not same_kernels:
+        # several categories of 17-32 states: without a budget the matrix-core kernels take them
+        # (they take a budget with one category only), so the two instances round differently
+        np.testing.assert_allclose(site, ref[1], rtol=TOL_LOGL[precision] * 10)
+        return
     # per-pattern values are those of the unbudgeted instance; only sums over chunks regroup
-    assert np.array_equal(site, ref[1]) and np.array_equal(one[1], ref[1])
+    assert np.array_equal(site, ref[1])
     assert abs(logL - ref[0]) <= 1e-13 * abs(want) and abs(one[0] - logL) <= 1e-13 * abs(want)
     tol = 1e-12 if precision == "fp64" else 1e-5
     assert np.linalg.norm(db - ref[2]) <= tol * np.linalg.norm(ob)
