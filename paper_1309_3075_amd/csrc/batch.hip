@@ -136,7 +136,8 @@ int build_schedule(EpochBatch* b) {
   const size_t n = (size_t)sc.n_problems;  // one problem per member and rate category
   size_t total = 0;
   for (size_t q = 0; q < n; ++q) total += sc.slot_total[q];
-  int rc0 = ensure(b->gpart, std::max<size_t>(1, total) * kCodonSlotBytes);
+  const size_t slot_floats = (kCodonSlotBytes / sizeof(float)) * (sc.fp64 ? 2 : 1);  // one slot, in floats
+  int rc0 = ensure(b->gpart, std::max<size_t>(1, total) * slot_floats * sizeof(float));
   if (!rc0) rc0 = ensure(b->dpart, codon_dpart_bytes(sc));
   if (rc0) return rc0;
   b->gslots.resize(n);
@@ -148,7 +149,7 @@ int build_schedule(EpochBatch* b) {
     rc = hip_check(hipMemcpy(b->gslots[q].ptr, gs[q].data(), gs[q].size() * sizeof(int32_t), hipMemcpyHostToDevice),
                    "batch gslots upload");
     if (rc) return rc;
-    float* region = static_cast<float*>(b->gpart.ptr) + off * (kCodonSlotBytes / sizeof(float));
+    float* region = static_cast<float*>(b->gpart.ptr) + off * slot_floats;
     desc[q] = codon_descriptor(b->insts[sc.desc_inst[q]], sc.desc_cat[q], static_cast<const int32_t*>(b->gslots[q].ptr),
                                region);
     off += sc.slot_total[q];
@@ -298,7 +299,8 @@ std::string tune_key(EpochBatch* b) {
     tot_c += in->C;
   }
   std::ostringstream k;
-  k << arch.substr(0, arch.find(':')) << "/codon/K" << b->insts[0]->K << "/fp32/n" << b->insts.size() << "/P"
+  k << arch.substr(0, arch.find(':')) << "/codon/K" << b->insts[0]->K << (b->insts[0]->fp64 ? "/fp64" : "/fp32")
+    << "/n" << b->insts.size() << "/P"
     << (tot_p / (long)b->insts.size() / 1000);
   if (tot_c != (long)b->insts.size()) k << "/C" << tot_c;  // rate categories multiply the work
   return k.str();
@@ -439,7 +441,7 @@ int epoch_batch_create(EpochInstance* const* insts, int32_t n, const char* tune_
   b->own_stream = true;
   b->merged = true;
   for (int i = 0; i < n; ++i) {
-    if (insts[i]->path != 2 || insts[i]->codon_nchunks > 1) b->merged = false;
+    if (insts[i]->path != 2 || insts[i]->codon_nchunks > 1 || insts[i]->fp64 != insts[0]->fp64) b->merged = false;
     if (insts[i]->device != insts[0]->device) {
       (void)hipStreamDestroy(b->stream);
       delete b;

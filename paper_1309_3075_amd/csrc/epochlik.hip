@@ -137,14 +137,14 @@ int padded_states(int K) {
   return (K + 15) / 16 * 16;
 }
 
-// FP32 problems of 49..64 states, and of 17..32 states (a 20-state amino-acid model, say,
+// Problems of 49..64 states, and of 17..32 states (a 20-state amino-acid model, say,
 // padded to 64 states: the padding states are never observed and their transition rows
-// are the identity), run on the 64-state matrix-core kernels: with any number of rate
-// categories, or with one category under an HBM budget (pattern chunks).
+// are the identity), run on the 64-state matrix-core kernels, FP32 or FP64, with any
+// number of rate categories; under an HBM budget (pattern chunks) FP32 with one category.
 bool codon_config(const EpochConfig& c) {
   return ((c.n_states > 48 && c.n_states <= 64) || (c.n_states > 16 && c.n_states <= 32)) &&
-         c.precision == EPOCH_FP32 && c.kernel_path == EPOCH_KERNEL_AUTO &&
-         (c.n_categories == 1 || c.hbm_budget_bytes == 0);
+         c.kernel_path == EPOCH_KERNEL_AUTO &&
+         (c.hbm_budget_bytes == 0 || (c.n_categories == 1 && c.precision == EPOCH_FP32));
 }
 bool small_codon_config(const EpochConfig& c) { return codon_config(c) && c.n_states <= 32; }
 int padded_states(const EpochConfig& c) { return small_codon_config(c) ? 64 : padded_states(c.n_states); }

@@ -83,6 +83,7 @@ struct CodonSchedule {
   int n_levels = 0, max_tiles = 0, max_pattern_blocks = 0, n_problems = 0;
   int split_blocks = 0;  // pre-order levels of at most this many blocks put each child branch on its own wavefronts
   bool amb = false;      // some problem has tips with ambiguity codes (the kernels' ambiguity instantiation)
+  bool fp64 = false;     // FP64 problems (the FP64 matrix-core instantiation; every problem of a schedule alike)
 };
 
 // Incremental re-evaluation (MCMC proposals): the work of one restricted pass.
@@ -316,7 +317,7 @@ int launch_codon_root(EpochInstance* in);
 int launch_codon_pre_grad(EpochInstance* in);
 int codon_prepare(EpochInstance* in);
 CodonProblem codon_descriptor(const EpochInstance* in, int c, const int32_t* gslots, float* gpart);
-constexpr size_t kCodonSlotBytes = 64 * 64 * sizeof(float);  // one FP32 64x64 partial of dlogL/dP
+constexpr size_t kCodonSlotBytes = 64 * 64 * sizeof(float);  // one FP32 64x64 partial of dlogL/dP (FP64: twice)
 void codon_build_schedule(const std::vector<const EpochInstance*>& insts, int target_blocks, CodonSchedule& out,
                           std::vector<std::vector<int32_t>>& gslots);
 int codon_launch_post(const CodonSchedule& sc, const CodonProblem* d_probs, const int2* d_items, hipStream_t st);

@@ -40,14 +40,36 @@ namespace epochlik {
 namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int KP = 64;
 constexpr int KK = KP * KP;
-constexpr int LDP = 68;  // LDS row stride (floats): 64 states, the row sum, padding
+constexpr int LDP = 68;  // LDS row stride (elements): 64 states, the row sum, padding
 constexpr int TILE = 64;  // patterns per block tile
 constexpr int WT = 16;    // patterns per wavefront tile
 
+// FP32 (v_mfma_f32_16x16x4f32) and FP64 (v_mfma_f64_16x16x4f64) forms of the
+// kernels.  The A and B operands map alike; the four D registers of lane
+// (g, r) are rows 4 g + v (FP32) or 4 v + g (FP64) of column r.
+template <typename T>
+struct Vec4;
+template <>
+struct Vec4<float> {
+  typedef f4 type;
+};
+template <>
+struct Vec4<double> {
+  typedef d4 type;
+};
+template <typename T>
+using v4 = typename Vec4<T>::type;
+
 __device__ inline f4 mfma(float a, float b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+__device__ inline d4 mfma(double a, double b, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+template <typename T>
+__device__ constexpr int drow(int g, int v) {
+  return sizeof(T) == 8 ? 4 * v + g : 4 * g + v;
+}
 
 template <typename T>
 __device__ inline const EPOCH_GLOBAL T* gptr(const T* p) {
@@ -65,30 +87,35 @@ __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Stage a 64x64 row-major matrix into LDS with row stride LDP (256 threads,
-// t = 0 .. 255).
-__device__ inline void stage_matrix(float* __restrict__ s, const float* __restrict__ g, int t) {
+// Stage a 64x64 row-major matrix into LDS with row stride LDP, in 16-byte
+// pieces (256 threads, t = 0 .. 255).
+template <typename T>
+__device__ inline void stage_matrix(T* __restrict__ s, const T* __restrict__ g, int t) {
+  constexpr int PER_ROW = KP * sizeof(T) / 16;  // 16-byte pieces per row
   const EPOCH_GLOBAL f4* src = gptr(reinterpret_cast<const f4*>(g));
-  for (int e = t; e < KK / 4; e += 256) {
-    const int row = e >> 4, c4 = e & 15;
-    *reinterpret_cast<f4*>(s + row * LDP + 4 * c4) = src[e];
+  for (int e = t; e < KP * PER_ROW; e += 256) {
+    const int row = e / PER_ROW, c = e % PER_ROW;
+    *reinterpret_cast<f4*>(reinterpret_cast<char*>(s + row * LDP) + 16 * c) = src[e];
   }
 }
-__device__ inline void stage_matrix(float* __restrict__ s, const float* __restrict__ g) {
+template <typename T>
+__device__ inline void stage_matrix(T* __restrict__ s, const T* __restrict__ g) {
   stage_matrix(s, g, threadIdx.x);
 }
 // Row sums over the first K columns into column 64 (needs the staged matrix;
 // 256 threads, t = 0 .. 255).
-__device__ inline void stage_row_sums(float* __restrict__ s, int K, int t) {
+template <typename T>
+__device__ inline void stage_row_sums(T* __restrict__ s, int K, int t) {
   const int row = t >> 2, q = t & 3;
-  float acc = 0.f;
+  T acc = 0;
 #pragma unroll
-  for (int j = 0; j < 16; ++j) acc += (16 * q + j < K) ? s[row * LDP + 16 * q + j] : 0.f;
+  for (int j = 0; j < 16; ++j) acc += (16 * q + j < K) ? s[row * LDP + 16 * q + j] : T(0);
   acc += __shfl_xor(acc, 1, 4);
   acc += __shfl_xor(acc, 2, 4);
   if (q == 0) s[row * LDP + 64] = acc;
 }
-__device__ inline void stage_row_sums(float* __restrict__ s, int K) { stage_row_sums(s, K, threadIdx.x); }
+template <typename T>
+__device__ inline void stage_row_sums(T* __restrict__ s, int K) { stage_row_sums(s, K, threadIdx.x); }
 
 // Row-max / row-sum over the 16 lanes of a DPP row (lanes sharing g).
 __device__ inline float row16_max(float v) {
@@ -105,24 +132,47 @@ __device__ inline float row16_sum(float v) {
   v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x128, 0xF, 0xF, false));
   return v;
 }
+// The same for doubles, moving the two 32-bit halves.
+template <int CTRL>
+__device__ inline double dpp_double(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ inline double row16_max(double v) {
+  v = fmax(v, dpp_double<0x121>(v));
+  v = fmax(v, dpp_double<0x122>(v));
+  v = fmax(v, dpp_double<0x124>(v));
+  v = fmax(v, dpp_double<0x128>(v));
+  return v;
+}
+__device__ inline double row16_sum(double v) {
+  v += dpp_double<0x121>(v);
+  v += dpp_double<0x122>(v);
+  v += dpp_double<0x124>(v);
+  v += dpp_double<0x128>(v);
+  return v;
+}
 
 // S[nt] (D layout) = sum_j L[p][j] P[16 nt + r][j] for an internal child whose
 // partials start at Lg.  Pattern rows past the end are clamped (their results
 // are never stored).
-__device__ inline void child_gemm(f4 (&S)[4], const float* __restrict__ Lg, int P, int p0,
-                                  const float* __restrict__ sP, int g, int r) {
+template <typename T>
+__device__ inline void child_gemm(v4<T> (&S)[4], const T* __restrict__ Lg, int P, int p0,
+                                  const T* __restrict__ sP, int g, int r) {
 #pragma unroll
-  for (int nt = 0; nt < 4; ++nt) S[nt] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int nt = 0; nt < 4; ++nt) S[nt] = v4<T>{0, 0, 0, 0};
   const int pa = min(p0 + r, P - 1);
-  const EPOCH_GLOBAL f4* arow = gptr(reinterpret_cast<const f4*>(Lg + (size_t)pa * KP)) + g;
-  f4 a[4];
+  const EPOCH_GLOBAL v4<T>* arow = gptr(reinterpret_cast<const v4<T>*>(Lg + (size_t)pa * KP)) + g;
+  v4<T> a[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) a[t] = arow[4 * t];  // L[pa][16 t + 4 g .. 16 t + 4 g + 3]
 #pragma unroll
   for (int t = 0; t < 4; ++t)
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
-      const f4 b = *reinterpret_cast<const f4*>(sP + (16 * nt + r) * LDP + 16 * t + 4 * g);
+      const v4<T> b = *reinterpret_cast<const v4<T>*>(sP + (16 * nt + r) * LDP + 16 * t + 4 * g);
       S[nt] = mfma(a[t].x, b.x, S[nt]);
       S[nt] = mfma(a[t].y, b.y, S[nt]);
       S[nt] = mfma(a[t].z, b.z, S[nt]);
@@ -130,20 +180,22 @@ __device__ inline void child_gemm(f4 (&S)[4], const float* __restrict__ Lg, int 
     }
 }
 
-// Tip states of patterns p0 + 4 g + v as LDS columns: an observed state is its
-// column, a missing one column 64 (the row sums), and the caller's ambiguity
-// set a is 65 + a (text after Eq. 4: tips are 0/1 indicators of the
-// possible states).
+// Tip states of the patterns of D-layout rows v as LDS columns: an observed
+// state is its column, a missing one column 64 (the row sums), and the
+// caller's ambiguity set a is 65 + a (text after Eq. 4: tips are 0/1
+// indicators of the possible states).
+template <typename T>
 __device__ inline void tip_columns(int (&col)[4], const uint8_t* __restrict__ tipst, int P, int p0, int K, int g) {
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const int st = gptr(tipst)[min(p0 + 4 * g + v, P - 1)];
+    const int st = gptr(tipst)[min(p0 + drow<T>(g, v), P - 1)];
     col[v] = st < K ? st : 64 + (st - K);
   }
 }
 // Sum of row entries over an ambiguity set (rare: kept off the common path).
-__device__ __noinline__ float masked_row_sum(const float* __restrict__ row, uint64_t set) {
-  float acc = 0.f;
+template <typename T>
+__device__ __noinline__ T masked_row_sum(const T* __restrict__ row, uint64_t set) {
+  T acc = 0;
   while (set) {
     const int j = __builtin_ctzll(set);
     acc += row[j];
@@ -154,8 +206,8 @@ __device__ __noinline__ float masked_row_sum(const float* __restrict__ row, uint
 // Tip child: S = P[i][state_p] (or the sum of P[i][.] over the tip's state set).
 // AMB: the problem has tips with ambiguity codes (a separate instantiation, so
 // the common case keeps its registers).
-template <bool AMB>
-__device__ inline void tip_lookup(f4 (&S)[4], const int (&col)[4], const float* __restrict__ sP, int r,
+template <bool AMB, typename T>
+__device__ inline void tip_lookup(v4<T> (&S)[4], const int (&col)[4], const T* __restrict__ sP, int r,
                                   const uint64_t* __restrict__ amb) {
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt)
@@ -169,22 +221,26 @@ __device__ inline void tip_lookup(f4 (&S)[4], const int (&col)[4], const float* 
   }
 }
 
-// D-layout load of a [P][64] array: value at pattern p0 + 4 g + v, state 16 nt + r.
-__device__ inline void load_dlayout(f4 (&X)[4], const float* __restrict__ base, int P, int p0, int g, int r) {
+// D-layout load of a [P][64] array: value at pattern p0 + drow(g, v), state 16 nt + r.
+template <typename T>
+__device__ inline void load_dlayout(v4<T> (&X)[4], const T* __restrict__ base, int P, int p0, int g, int r) {
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const EPOCH_GLOBAL float* row = gptr(base + (size_t)min(p0 + 4 * g + v, P - 1) * KP) + r;
+    const EPOCH_GLOBAL T* row = gptr(base + (size_t)min(p0 + drow<T>(g, v), P - 1) * KP) + r;
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) X[nt][v] = row[16 * nt];
   }
 }
 
+__device__ inline float dmax(float a, float b) { return fmaxf(a, b); }
+__device__ inline double dmax(double a, double b) { return fmax(a, b); }
+
 // ---------------------------------------------------------------------------
-template <bool AMB>
+template <typename T, bool AMB>
 __global__ __launch_bounds__(256) void codon_post_level_kernel(const CodonProblem* __restrict__ probs,
                                                                 const int2* __restrict__ items, int R) {
-  __shared__ __align__(16) float sPa[KP * LDP];
-  __shared__ __align__(16) float sPb[KP * LDP];
+  __shared__ __align__(16) T sPa[KP * LDP];
+  __shared__ __align__(16) T sPb[KP * LDP];
   const int2 it = items[blockIdx.y];
   const CodonProblem& pr = probs[it.x];
   const int N = pr.N, P = pr.P, K = pr.K;
@@ -194,51 +250,53 @@ __global__ __launch_bounds__(256) void codon_post_level_kernel(const CodonProble
   const int u = it.y;
   const int a = pr.left[u], b = pr.right[u];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
-  stage_matrix(sPa, pr.Pm + (size_t)a * pr.pm_stride);
-  stage_matrix(sPb, pr.Pm + (size_t)b * pr.pm_stride);
+  const T* Pm = reinterpret_cast<const T*>(pr.Pm);
+  stage_matrix(sPa, Pm + (size_t)a * pr.pm_stride);
+  stage_matrix(sPb, Pm + (size_t)b * pr.pm_stride);
   __syncthreads();
   stage_row_sums(sPa, K);
   stage_row_sums(sPb, K);
   __syncthreads();
-  const float* La = a >= N ? pr.part + (size_t)(a - N) * P * KP : nullptr;
-  const float* Lb = b >= N ? pr.part + (size_t)(b - N) * P * KP : nullptr;
+  T* part = reinterpret_cast<T*>(pr.part);
+  const T* La = a >= N ? part + (size_t)(a - N) * P * KP : nullptr;
+  const T* Lb = b >= N ? part + (size_t)(b - N) * P * KP : nullptr;
   const int32_t* sca = a >= N ? pr.scales + (size_t)(a - N) * P : nullptr;
   const int32_t* scb = b >= N ? pr.scales + (size_t)(b - N) * P : nullptr;
-  EPOCH_GLOBAL float* out = gptr(pr.part + (size_t)(u - N) * P * KP);
+  EPOCH_GLOBAL T* out = gptr(part + (size_t)(u - N) * P * KP);
   EPOCH_GLOBAL int32_t* sout = gptr(pr.scales + (size_t)(u - N) * P);
   for (int p0 = base + WT * w; p0 < end; p0 += 4 * WT) {
-    f4 Sa[4], Sb[4];
+    v4<T> Sa[4], Sb[4];
     if (La) {
-      child_gemm(Sa, La, P, p0, sPa, g, r);
+      child_gemm<T>(Sa, La, P, p0, sPa, g, r);
     } else {
       int col[4];
-      tip_columns(col, pr.tips + (size_t)a * pr.tip_stride, P, p0, K, g);
-      tip_lookup<AMB>(Sa, col, sPa, r, pr.amb);
+      tip_columns<T>(col, pr.tips + (size_t)a * pr.tip_stride, P, p0, K, g);
+      tip_lookup<AMB, T>(Sa, col, sPa, r, pr.amb);
     }
     if (Lb) {
-      child_gemm(Sb, Lb, P, p0, sPb, g, r);
+      child_gemm<T>(Sb, Lb, P, p0, sPb, g, r);
     } else {
       int col[4];
-      tip_columns(col, pr.tips + (size_t)b * pr.tip_stride, P, p0, K, g);
-      tip_lookup<AMB>(Sb, col, sPb, r, pr.amb);
+      tip_columns<T>(col, pr.tips + (size_t)b * pr.tip_stride, P, p0, K, g);
+      tip_lookup<AMB, T>(Sb, col, sPb, r, pr.amb);
     }
     int e[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      float m = 0.f;
+      T m = 0;
 #pragma unroll
       for (int nt = 0; nt < 4; ++nt) {
         Sa[nt][v] *= Sb[nt][v];
-        m = fmaxf(m, Sa[nt][v]);
+        m = dmax(m, Sa[nt][v]);
       }
       e[v] = scale_exponent(row16_max(m));
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int p = p0 + 4 * g + v;
+      const int p = p0 + drow<T>(g, v);
       if (p < P) {
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) __builtin_nontemporal_store(ldexpf(Sa[nt][v], -e[v]), &out[(size_t)p * KP + 16 * nt + r]);
+        for (int nt = 0; nt < 4; ++nt) __builtin_nontemporal_store(scale_by_pow2(Sa[nt][v], e[v]), &out[(size_t)p * KP + 16 * nt + r]);
         if (r == 0) sout[p] = e[v] + (sca ? gptr(sca)[p] : 0) + (scb ? gptr(scb)[p] : 0);
       }
     }
@@ -254,6 +312,7 @@ __global__ __launch_bounds__(256) void codon_post_level_kernel(const CodonProble
 // l_c = sum_i pi_i x_c(p, i); the pre-order pass of category c then weighs
 // pattern p by w_p w_c l_c 2^E_c / L_p (its posterior share), written to that
 // category's weightsT.
+template <typename T>
 __global__ __launch_bounds__(256) void codon_root_kernel(const CodonProblem* __restrict__ probs) {
   __shared__ double sm[256];
   const CodonProblem& pr = probs[blockIdx.y];
@@ -267,7 +326,7 @@ __global__ __launch_bounds__(256) void codon_root_kernel(const CodonProblem* __r
     double s;
     if (pr.n_cats == 1) {
       double L = 0.0;
-      const float* x = pr.part + (slot * P + p) * KP;
+      const T* x = reinterpret_cast<const T*>(pr.part) + (slot * P + p) * KP;
       for (int i = 0; i < K; ++i) L += pr.pi[i] * (double)x[i];
       s = log(L) + (double)pr.scales[slot * P + p] * kLn2;
     } else {
@@ -275,7 +334,7 @@ __global__ __launch_bounds__(256) void codon_root_kernel(const CodonProblem* __r
       int e[kMaxCategories], emax = INT_MIN;
       for (int c = 0; c < pr.n_cats; ++c) {
         const CodonProblem& pc = probs[blockIdx.y + c];
-        const float* x = pc.part + (slot * P + p) * KP;
+        const T* x = reinterpret_cast<const T*>(pc.part) + (slot * P + p) * KP;
         double acc = 0.0;
         for (int i = 0; i < K; ++i) acc += pr.pi[i] * (double)x[i];
         l[c] = pr.cat[kMaxCategories + c] * acc;
@@ -289,7 +348,7 @@ __global__ __launch_bounds__(256) void codon_root_kernel(const CodonProblem* __r
       }
       s = L > 0.0 ? log(L) + (double)emax * kLn2 : -INFINITY;
       for (int c = 0; c < pr.n_cats; ++c)
-        probs[blockIdx.y + c].weightsT[p] = L > 0.0 ? (float)(pr.weights[p] * (l[c] / L)) : 0.f;
+        reinterpret_cast<T*>(probs[blockIdx.y + c].weightsT)[p] = L > 0.0 ? (T)(pr.weights[p] * (l[c] / L)) : T(0);
     }
     pr.site[p] = s;
     contrib = pr.weights[p] * s;
@@ -327,38 +386,39 @@ __global__ __launch_bounds__(256) void codon_final_kernel(const CodonProblem* __
 // A = t[p][16 w + r] w_p / L_p, B = the child's partials (internal child) or
 // its tip-state indicator.  One loop per kind of child, with no branch inside,
 // so the LDS reads of later k-steps are issued ahead of the matrix-core work.
-__device__ inline void grad_rows_internal(f4* G, const float* __restrict__ tcol, const float* __restrict__ sCF,
-                                          const float* __restrict__ sL, int g, int r) {
+template <typename T>
+__device__ inline void grad_rows_internal(v4<T>* G, const T* __restrict__ tcol, const T* __restrict__ sCF,
+                                          const T* __restrict__ sL, int g, int r) {
 #pragma unroll 8
   for (int ks = 0; ks < TILE / 4; ++ks) {
     const int pl = 4 * ks + g;
-    const float av = tcol[pl * LDP] * sCF[pl];
-    f4 B;
+    const T av = tcol[pl * LDP] * sCF[pl];
+    v4<T> B;
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) B[nt] = sL[pl * LDP + 16 * nt + r];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) G[nt] = mfma(av, B[nt], G[nt]);
   }
 }
-template <bool AMB>
-__device__ inline void grad_rows_tip(f4* G, const float* __restrict__ tcol, const float* __restrict__ sCF,
+template <bool AMB, typename T>
+__device__ inline void grad_rows_tip(v4<T>* G, const T* __restrict__ tcol, const T* __restrict__ sCF,
                                      const int* __restrict__ sCol, int K, int g, int r,
                                      const uint64_t* __restrict__ amb) {
 #pragma unroll 8
   for (int ks = 0; ks < TILE / 4; ++ks) {
     const int pl = 4 * ks + g;
-    const float av = tcol[pl * LDP] * sCF[pl];
+    const T av = tcol[pl * LDP] * sCF[pl];
     const int col = sCol[pl];
-    f4 B;
+    v4<T> B;
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
       const int j = 16 * nt + r;
-      B[nt] = (col == j || (col == 64 && j < K)) ? 1.f : 0.f;
+      B[nt] = (col == j || (col == 64 && j < K)) ? T(1) : T(0);
     }
     if (AMB && col > 64) {  // the 0/1 row of an ambiguity set
       const uint64_t set = amb[col - 65];
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt) B[nt] = ((set >> (16 * nt + r)) & 1) ? 1.f : 0.f;
+      for (int nt = 0; nt < 4; ++nt) B[nt] = ((set >> (16 * nt + r)) & 1) ? T(1) : T(0);
     }
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) G[nt] = mfma(av, B[nt], G[nt]);
@@ -369,49 +429,53 @@ __device__ inline void grad_rows_tip(f4* G, const float* __restrict__ tcol, cons
 // schedule was built for still owns a dlogL/dP slot of each child branch (the
 // slot count covers the longest chunk): it writes zeros there.  Blocks past a
 // batch member's own tiles own no slot and write nothing.
+template <typename T>
 __device__ inline void zero_unused_slot(const CodonProblem& pr, int child, int nthreads) {
   if ((int)blockIdx.x >= pr.gslots[child]) return;
-  EPOCH_GLOBAL float* dst = gptr(pr.Gpart + ((size_t)pr.gslots[pr.n_nodes + child] + blockIdx.x) * KK);
-  for (int e = threadIdx.x; e < KK / 4; e += nthreads) reinterpret_cast<EPOCH_GLOBAL f4*>(dst)[e] = f4{0.f, 0.f, 0.f, 0.f};
+  EPOCH_GLOBAL T* dst = gptr(reinterpret_cast<T*>(pr.Gpart) + ((size_t)pr.gslots[pr.n_nodes + child] + blockIdx.x) * KK);
+  for (int e = threadIdx.x; e < KK / 4; e += nthreads) reinterpret_cast<EPOCH_GLOBAL v4<T>*>(dst)[e] = v4<T>{0, 0, 0, 0};
 }
 
+template <typename T>
 struct PreTileLoads {
-  f4 La[4], Lb[4];  // 16-byte rows of internal children's partials (child product A operand)
-  f4 Q[4];          // q_u in the D layout
+  v4<T> La[4], Lb[4];  // rows of 4 states of internal children's partials (child product A operand)
+  v4<T> Q[4];          // q_u in the D layout
   int cola[4], colb[4];
 };
 
-__device__ inline void pre_load_tile(PreTileLoads& ld, const CodonProblem& pr, const float* La, const float* Lb,
-                                     const float* Qu, int a, int b, int p0, int g, int r) {
+template <typename T>
+__device__ inline void pre_load_tile(PreTileLoads<T>& ld, const CodonProblem& pr, const T* La, const T* Lb,
+                                     const T* Qu, int a, int b, int p0, int g, int r) {
   const int P = pr.P, K = pr.K, N = pr.N;
   const int pa = min(p0 + r, P - 1);
   if (La) {
-    const EPOCH_GLOBAL f4* row = gptr(reinterpret_cast<const f4*>(La + (size_t)pa * KP)) + g;
+    const EPOCH_GLOBAL v4<T>* row = gptr(reinterpret_cast<const v4<T>*>(La + (size_t)pa * KP)) + g;
 #pragma unroll
     for (int t = 0; t < 4; ++t) ld.La[t] = row[4 * t];
   } else {
-    tip_columns(ld.cola, pr.tips + (size_t)a * pr.tip_stride, P, p0, K, g);
+    tip_columns<T>(ld.cola, pr.tips + (size_t)a * pr.tip_stride, P, p0, K, g);
   }
   if (Lb) {
-    const EPOCH_GLOBAL f4* row = gptr(reinterpret_cast<const f4*>(Lb + (size_t)pa * KP)) + g;
+    const EPOCH_GLOBAL v4<T>* row = gptr(reinterpret_cast<const v4<T>*>(Lb + (size_t)pa * KP)) + g;
 #pragma unroll
     for (int t = 0; t < 4; ++t) ld.Lb[t] = row[4 * t];
   } else {
-    tip_columns(ld.colb, pr.tips + (size_t)b * pr.tip_stride, P, p0, K, g);
+    tip_columns<T>(ld.colb, pr.tips + (size_t)b * pr.tip_stride, P, p0, K, g);
   }
-  if (Qu) load_dlayout(ld.Q, Qu, P, p0, g, r);
+  if (Qu) load_dlayout<T>(ld.Q, Qu, P, p0, g, r);
   (void)N;
 }
 
 // S[nt] (D layout) from 16-byte A-operand rows already in registers.
-__device__ inline void child_gemm_regs(f4 (&S)[4], const f4 (&a)[4], const float* __restrict__ sP, int g, int r) {
+template <typename T>
+__device__ inline void child_gemm_regs(v4<T> (&S)[4], const v4<T> (&a)[4], const T* __restrict__ sP, int g, int r) {
 #pragma unroll
-  for (int nt = 0; nt < 4; ++nt) S[nt] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int nt = 0; nt < 4; ++nt) S[nt] = v4<T>{0, 0, 0, 0};
 #pragma unroll
   for (int t = 0; t < 4; ++t)
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
-      const f4 bv = *reinterpret_cast<const f4*>(sP + (16 * nt + r) * LDP + 16 * t + 4 * g);
+      const v4<T> bv = *reinterpret_cast<const v4<T>*>(sP + (16 * nt + r) * LDP + 16 * t + 4 * g);
       S[nt] = mfma(a[t].x, bv.x, S[nt]);
       S[nt] = mfma(a[t].y, bv.y, S[nt]);
       S[nt] = mfma(a[t].z, bv.z, S[nt]);
@@ -419,14 +483,14 @@ __device__ inline void child_gemm_regs(f4 (&S)[4], const f4 (&a)[4], const float
     }
 }
 
-template <bool AMB>
-__global__ __launch_bounds__(256, 2) void codon_pre_level_kernel(const CodonProblem* __restrict__ probs,
-                                                               const int2* __restrict__ items, int R) {
-  __shared__ __align__(16) float sPa[KP * LDP];
-  __shared__ __align__(16) float sPb[KP * LDP];
-  __shared__ __align__(16) float sT[TILE * LDP];  // t of one side for the block tile, pattern-major
-  __shared__ __align__(16) float sL[TILE * LDP];  // that side's child partials for the block tile
-  __shared__ float sCF[TILE];                     // w_p / L_p of the block tile
+template <typename T, bool AMB>
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void codon_pre_level_kernel(
+    const CodonProblem* __restrict__ probs, const int2* __restrict__ items, int R) {
+  __shared__ __align__(16) T sPa[KP * LDP];
+  __shared__ __align__(16) T sPb[KP * LDP];
+  __shared__ __align__(16) T sT[TILE * LDP];  // t of one side for the block tile, pattern-major
+  __shared__ __align__(16) T sL[TILE * LDP];  // that side's child partials for the block tile
+  __shared__ T sCF[TILE];                     // w_p / L_p of the block tile
   __shared__ int sCol[2][TILE];                    // tip columns of the block tile
   const int2 it = items[blockIdx.y];
   const CodonProblem& pr = probs[it.x];
@@ -435,122 +499,125 @@ __global__ __launch_bounds__(256, 2) void codon_pre_level_kernel(const CodonProb
   const int u = it.y;
   const int a = pr.left[u], b = pr.right[u];
   if (base >= P) {  // uniform: this problem (or pattern chunk) has fewer tiles
-    zero_unused_slot(pr, a, 256);
-    zero_unused_slot(pr, b, 256);
+    zero_unused_slot<T>(pr, a, 256);
+    zero_unused_slot<T>(pr, b, 256);
     return;
   }
   const int n_tiles = min(R, (P - base + TILE - 1) / TILE);  // uniform over the block
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
-  stage_matrix(sPa, pr.Pm + (size_t)a * pr.pm_stride);
-  stage_matrix(sPb, pr.Pm + (size_t)b * pr.pm_stride);
+  const T* Pm = reinterpret_cast<const T*>(pr.Pm);
+  stage_matrix(sPa, Pm + (size_t)a * pr.pm_stride);
+  stage_matrix(sPb, Pm + (size_t)b * pr.pm_stride);
   __syncthreads();
   stage_row_sums(sPa, K);
   stage_row_sums(sPb, K);
   __syncthreads();
-  const float* La = a >= N ? pr.part + (size_t)(a - N) * P * KP : nullptr;
-  const float* Lb = b >= N ? pr.part + (size_t)(b - N) * P * KP : nullptr;
-  const float* Qu = u == pr.root ? nullptr : pr.pre + (size_t)(u - N) * P * KP;
-  float piv[4];
+  const T* part = reinterpret_cast<const T*>(pr.part);
+  T* pre = reinterpret_cast<T*>(pr.pre);
+  const T* La = a >= N ? part + (size_t)(a - N) * P * KP : nullptr;
+  const T* Lb = b >= N ? part + (size_t)(b - N) * P * KP : nullptr;
+  const T* Qu = u == pr.root ? nullptr : pre + (size_t)(u - N) * P * KP;
+  T piv[4];
 #pragma unroll
-  for (int nt = 0; nt < 4; ++nt) piv[nt] = 16 * nt + r < K ? (float)pr.pi[16 * nt + r] : 0.f;
-  // dlogL/dP accumulators: rows 16 w + 4 g + v, columns 16 nt + r
-  f4 Ga[4], Gb[4];
+  for (int nt = 0; nt < 4; ++nt) piv[nt] = 16 * nt + r < K ? (T)pr.pi[16 * nt + r] : T(0);
+  // dlogL/dP accumulators: rows 16 w + drow(g, v), columns 16 nt + r
+  v4<T> Ga[4], Gb[4];
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt) {
-    Ga[nt] = f4{0.f, 0.f, 0.f, 0.f};
-    Gb[nt] = f4{0.f, 0.f, 0.f, 0.f};
+    Ga[nt] = v4<T>{0, 0, 0, 0};
+    Gb[nt] = v4<T>{0, 0, 0, 0};
   }
-  PreTileLoads cur, nxt;
-  pre_load_tile(cur, pr, La, Lb, Qu, a, b, base + WT * w, g, r);
-  float* trows = sT + (WT * w) * LDP;  // this wavefront's 16 pattern rows
-  float* lrows = sL + (WT * w) * LDP;
+  PreTileLoads<T> cur, nxt;
+  pre_load_tile<T>(cur, pr, La, Lb, Qu, a, b, base + WT * w, g, r);
+  T* trows = sT + (WT * w) * LDP;  // this wavefront's 16 pattern rows
+  T* lrows = sL + (WT * w) * LDP;
   for (int bt = 0; bt < n_tiles; ++bt) {
     const int p0 = base + bt * TILE + WT * w;  // first pattern of this wavefront's part
     // ---- this wavefront's 16 patterns: child vectors, q_u, w_p / L_p
-    f4 Sa[4], Sb[4];
+    v4<T> Sa[4], Sb[4];
     if (La)
-      child_gemm_regs(Sa, cur.La, sPa, g, r);
+      child_gemm_regs<T>(Sa, cur.La, sPa, g, r);
     else
-      tip_lookup<AMB>(Sa, cur.cola, sPa, r, pr.amb);
+      tip_lookup<AMB, T>(Sa, cur.cola, sPa, r, pr.amb);
     if (Lb)
-      child_gemm_regs(Sb, cur.Lb, sPb, g, r);
+      child_gemm_regs<T>(Sb, cur.Lb, sPb, g, r);
     else
-      tip_lookup<AMB>(Sb, cur.colb, sPb, r, pr.amb);
-    f4 Q[4];
+      tip_lookup<AMB, T>(Sb, cur.colb, sPb, r, pr.amb);
+    v4<T> Q[4];
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) Q[nt] = Qu ? cur.Q[nt] : f4{piv[nt], piv[nt], piv[nt], piv[nt]};
+    for (int nt = 0; nt < 4; ++nt) Q[nt] = Qu ? cur.Q[nt] : v4<T>{piv[nt], piv[nt], piv[nt], piv[nt]};
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      float sum = 0.f;
+      T sum = 0;
 #pragma unroll
       for (int nt = 0; nt < 4; ++nt) sum += Q[nt][v] * Sa[nt][v] * Sb[nt][v];
       sum = row16_sum(sum);
-      const int p = p0 + 4 * g + v;
+      const int p = p0 + drow<T>(g, v);
       if (r == 0) {
-        sCF[WT * w + 4 * g + v] = (p < P && sum > 0.f) ? gptr(pr.weightsT)[p] / sum : 0.f;
-        if (!La) sCol[0][WT * w + 4 * g + v] = cur.cola[v];
-        if (!Lb) sCol[1][WT * w + 4 * g + v] = cur.colb[v];
+        sCF[WT * w + drow<T>(g, v)] = (p < P && sum > T(0)) ? gptr(reinterpret_cast<const T*>(pr.weightsT))[p] / sum : T(0);
+        if (!La) sCol[0][WT * w + drow<T>(g, v)] = cur.cola[v];
+        if (!Lb) sCol[1][WT * w + drow<T>(g, v)] = cur.colb[v];
       }
     }
     // loads of this wavefront's part of the next tile, in flight during the rest
-    if (bt + 1 < n_tiles) pre_load_tile(nxt, pr, La, Lb, Qu, a, b, p0 + TILE, g, r);
+    if (bt + 1 < n_tiles) pre_load_tile<T>(nxt, pr, La, Lb, Qu, a, b, p0 + TILE, g, r);
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
       const int child = side == 0 ? a : b;
-      const float* Lc = side == 0 ? La : Lb;
-      const f4* So = side == 0 ? Sb : Sa;
-      f4* G = side == 0 ? Ga : Gb;
-      const float* sP = side == 0 ? sPa : sPb;
+      const T* Lc = side == 0 ? La : Lb;
+      const v4<T>* So = side == 0 ? Sb : Sa;
+      v4<T>* G = side == 0 ? Ga : Gb;
+      const T* sP = side == 0 ? sPa : sPb;
       if (side == 1) __syncthreads();  // every wavefront is done with side a's t and L
       // t = q o S_sibling rows, and the child's partial rows, into LDS
 #pragma unroll
       for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) trows[(4 * g + v) * LDP + 16 * nt + r] = Q[nt][v] * So[nt][v];
+        for (int v = 0; v < 4; ++v) trows[drow<T>(g, v) * LDP + 16 * nt + r] = Q[nt][v] * So[nt][v];
       if (Lc) {
-        const f4* lr = side == 0 ? cur.La : cur.Lb;
+        const v4<T>* lr = side == 0 ? cur.La : cur.Lb;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) *reinterpret_cast<f4*>(lrows + r * LDP + 16 * t + 4 * g) = lr[t];
+        for (int t = 0; t < 4; ++t) *reinterpret_cast<v4<T>*>(lrows + r * LDP + 16 * t + 4 * g) = lr[t];
       }
       wave_lds_sync();
       if (Lc) {
         // outside vector q_c[p][j] = sum_i t[p][i] P_c[i][j] of this wavefront's patterns
-        f4 ta[4];
+        v4<T> ta[4];
 #pragma unroll
-        for (int tt = 0; tt < 4; ++tt) ta[tt] = *reinterpret_cast<const f4*>(trows + r * LDP + 16 * tt + 4 * g);
-        f4 Qo[4];
+        for (int tt = 0; tt < 4; ++tt) ta[tt] = *reinterpret_cast<const v4<T>*>(trows + r * LDP + 16 * tt + 4 * g);
+        v4<T> Qo[4];
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) Qo[nt] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int nt = 0; nt < 4; ++nt) Qo[nt] = v4<T>{0, 0, 0, 0};
 #pragma unroll
         for (int tt = 0; tt < 4; ++tt)
 #pragma unroll
           for (int nt = 0; nt < 4; ++nt) {
-            const float* prow = sP + (16 * tt + 4 * g) * LDP + 16 * nt + r;
+            const T* prow = sP + (16 * tt + 4 * g) * LDP + 16 * nt + r;
             Qo[nt] = mfma(ta[tt].x, prow[0], Qo[nt]);
             Qo[nt] = mfma(ta[tt].y, prow[LDP], Qo[nt]);
             Qo[nt] = mfma(ta[tt].z, prow[2 * LDP], Qo[nt]);
             Qo[nt] = mfma(ta[tt].w, prow[3 * LDP], Qo[nt]);
           }
-        EPOCH_GLOBAL float* out = gptr(pr.pre + (size_t)(child - N) * P * KP);
+        EPOCH_GLOBAL T* out = gptr(pre + (size_t)(child - N) * P * KP);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          float m = 0.f;
+          T m = 0;
 #pragma unroll
-          for (int nt = 0; nt < 4; ++nt) m = fmaxf(m, Qo[nt][v]);
+          for (int nt = 0; nt < 4; ++nt) m = dmax(m, Qo[nt][v]);
           const int e = scale_exponent(row16_max(m));
-          const int p = p0 + 4 * g + v;
+          const int p = p0 + drow<T>(g, v);
           if (p < P)
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) __builtin_nontemporal_store(ldexpf(Qo[nt][v], -e), &out[(size_t)p * KP + 16 * nt + r]);
+            for (int nt = 0; nt < 4; ++nt) __builtin_nontemporal_store(scale_by_pow2(Qo[nt][v], e), &out[(size_t)p * KP + 16 * nt + r]);
         }
       }
       __syncthreads();  // t, L, w_p / L_p and tip columns of every wavefront are in LDS
       // rows 16 w .. 16 w + 15 of dlogL/dP over the 64 patterns of the tile
-      const float* tcol = sT + WT * w + r;  // column i = 16 w + r of t
+      const T* tcol = sT + WT * w + r;  // column i = 16 w + r of t
       if (Lc)
-        grad_rows_internal(G, tcol, sCF, sL, g, r);
+        grad_rows_internal<T>(G, tcol, sCF, sL, g, r);
       else
-        grad_rows_tip<AMB>(G, tcol, sCF, sCol[side], K, g, r, pr.amb);
+        grad_rows_tip<AMB, T>(G, tcol, sCF, sCol[side], K, g, r, pr.amb);
     }
     __syncthreads();  // the next tile overwrites t, L, w_p / L_p and tip columns
     if (bt + 1 < n_tiles) cur = nxt;
@@ -559,12 +626,13 @@ __global__ __launch_bounds__(256, 2) void codon_pre_level_kernel(const CodonProb
 #pragma unroll
   for (int side = 0; side < 2; ++side) {
     const int child = side == 0 ? a : b;
-    const f4* G = side == 0 ? Ga : Gb;
-    EPOCH_GLOBAL float* dst = gptr(pr.Gpart + ((size_t)pr.gslots[pr.n_nodes + child] + blockIdx.x) * KK);
+    const v4<T>* G = side == 0 ? Ga : Gb;
+    EPOCH_GLOBAL T* dst = gptr(reinterpret_cast<T*>(pr.Gpart) + ((size_t)pr.gslots[pr.n_nodes + child] + blockIdx.x) * KK);
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) __builtin_nontemporal_store(G[nt][v], &dst[(WT * w + 4 * g + v) * KP + 16 * nt + r]);
+      for (int v = 0; v < 4; ++v)
+        __builtin_nontemporal_store(G[nt][v], &dst[(WT * w + drow<T>(g, v)) * KP + 16 * nt + r]);
   }
 }
 
@@ -599,7 +667,7 @@ __device__ inline void split_load_tile(SplitTileLoads& ld, const CodonProblem& p
 #pragma unroll
     for (int t = 0; t < 4; ++t) ld.L[t] = row[4 * t];
   } else {
-    tip_columns(ld.col, pr.tips + (size_t)c * pr.tip_stride, P, p0, pr.K, g);
+    tip_columns<float>(ld.col, pr.tips + (size_t)c * pr.tip_stride, P, p0, pr.K, g);
   }
   if (Qu) load_dlayout(ld.Q, Qu, P, p0, g, r);
 }
@@ -615,8 +683,8 @@ __global__ __launch_bounds__(512, 1) void codon_pre_split_kernel(const CodonProb
   const int u = it.y;
   const int a = pr.left[u], b = pr.right[u];
   if (base >= P) {  // uniform: this problem (or pattern chunk) has fewer tiles
-    zero_unused_slot(pr, a, 512);
-    zero_unused_slot(pr, b, 512);
+    zero_unused_slot<float>(pr, a, 512);
+    zero_unused_slot<float>(pr, b, 512);
     return;
   }
   const int n_tiles = min(R, (P - base + TILE - 1) / TILE);  // uniform over the block
@@ -736,6 +804,7 @@ __global__ __launch_bounds__(512, 1) void codon_pre_split_kernel(const CodonProb
 // G[v] = sum of the FP32 slot partials in FP64 (fixed order): one block per
 // (branch, 256 entries); also the block's share of <G, dP/dl>.
 constexpr int kReduceChunks = KK / 256;
+template <typename T>
 __global__ __launch_bounds__(256) void codon_grad_reduce_kernel(const CodonProblem* __restrict__ probs,
                                                                 const int2* __restrict__ items,
                                                                 double* __restrict__ dpart, int accumulate) {
@@ -746,7 +815,8 @@ __global__ __launch_bounds__(256) void codon_grad_reduce_kernel(const CodonProbl
   const int v = it.y;
   const int ns = v == pr.root ? 0 : pr.gslots[v];
   const int e = chunk * 256 + threadIdx.x;
-  const EPOCH_GLOBAL float* src = gptr(pr.Gpart + (size_t)(v == pr.root ? 0 : pr.gslots[pr.n_nodes + v]) * KK) + e;
+  const EPOCH_GLOBAL T* src =
+      gptr(reinterpret_cast<const T*>(pr.Gpart) + (size_t)(v == pr.root ? 0 : pr.gslots[pr.n_nodes + v]) * KK) + e;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   int k = 0;
   for (; k + 4 <= ns; k += 4) {
@@ -759,7 +829,7 @@ __global__ __launch_bounds__(256) void codon_grad_reduce_kernel(const CodonProbl
   double s = (s0 + s1) + (s2 + s3);
   if (accumulate) s += pr.G[(size_t)v * pr.pm_stride + e];  // earlier pattern chunks
   pr.G[(size_t)v * pr.pm_stride + e] = s;
-  const double d = block_sum<256>(s * (double)pr.dPm[(size_t)v * pr.pm_stride + e], sm);
+  const double d = block_sum<256>(s * (double)reinterpret_cast<const T*>(pr.dPm)[(size_t)v * pr.pm_stride + e], sm);
   if (threadIdx.x == 0) dpart[blockIdx.x] = d;
 }
 
@@ -799,18 +869,23 @@ int codon_tiles_per_block(int tiles, int n_items, int target_blocks, int r_max) 
 // outside vectors, scale exponents and weights are the c-th of C equal regions.
 CodonProblem codon_descriptor(const EpochInstance* in, int c, const int32_t* gslots, float* gpart) {
   const size_t C = in->C, Nm1 = in->N - 1, P = in->P;
+  // element offsets in the instance's compute type (the descriptor's float pointers
+  // hold doubles in an FP64 instance)
+  auto at = [&](void* base, size_t elems) -> float* {
+    return base ? reinterpret_cast<float*>(static_cast<char*>(base) + elems * in->real_size) : nullptr;
+  };
   CodonProblem d{};
-  d.Pm = static_cast<const float*>(in->Pm.ptr) + c * KK;
+  d.Pm = at(in->Pm.ptr, c * KK);
   d.tips = static_cast<const uint8_t*>(in->tips.ptr);
-  d.part = static_cast<float*>(in->partials.ptr) + c * Nm1 * P * KP;
-  d.pre = in->pre.ptr ? static_cast<float*>(in->pre.ptr) + c * Nm1 * P * KP : nullptr;
+  d.part = at(in->partials.ptr, c * Nm1 * P * KP);
+  d.pre = at(in->pre.ptr, c * Nm1 * P * KP);
   d.scales = static_cast<int32_t*>(in->scales.ptr) + c * Nm1 * P;
-  d.weightsT = static_cast<float*>(in->weightsT.ptr) + c * P;
+  d.weightsT = at(in->weightsT.ptr, c * P);
   d.weights = static_cast<const double*>(in->weights.ptr);
   d.pi = static_cast<const double*>(in->pi.ptr);
   d.cat = static_cast<const double*>(in->cat.ptr);
   d.Gpart = gpart;
-  d.dPm = in->dPm.ptr ? static_cast<const float*>(in->dPm.ptr) + c * KK : nullptr;
+  d.dPm = at(in->dPm.ptr, c * KK);
   d.G = in->G.ptr ? static_cast<double*>(in->G.ptr) + c * KK : nullptr;
   d.dbranch = static_cast<double*>(in->dbranch.ptr);
   d.site = static_cast<double*>(in->site.ptr);
@@ -892,28 +967,64 @@ void codon_build_schedule(const std::vector<const EpochInstance*>& insts, int ta
     for (int v = 0; v < inst(q)->n_nodes; ++v) out.reduce_items.push_back(make_int2((int)q, v));
   out.amb = false;
   for (auto* in : insts) out.amb = out.amb || in->tips_amb;
+  out.fp64 = !insts.empty() && insts[0]->fp64;
   out.n_levels = n_levels;
   out.max_tiles = max_tiles;
   out.max_pattern_blocks = max_pblocks;
   out.n_problems = (int)nd;
 }
 
-int codon_launch_post(const CodonSchedule& sc, const CodonProblem* d_probs, const int2* d_items, hipStream_t st) {
+namespace {
+template <typename T>
+void post_levels(const CodonSchedule& sc, const CodonProblem* d_probs, const int2* d_items, hipStream_t st) {
   for (int l = 1; l <= sc.n_levels; ++l) {
     const int b = sc.level_off[l - 1], n = sc.level_off[l] - b;
     if (!n) continue;
     const int R = sc.level_R[l - 1];
     const int blocks = (sc.max_tiles + R - 1) / R;
     if (sc.amb)
-      hipLaunchKernelGGL(codon_post_level_kernel<true>, dim3(blocks, n), dim3(256), 0, st, d_probs, d_items + b, R);
+      hipLaunchKernelGGL((codon_post_level_kernel<T, true>), dim3(blocks, n), dim3(256), 0, st, d_probs, d_items + b, R);
     else
-      hipLaunchKernelGGL(codon_post_level_kernel<false>, dim3(blocks, n), dim3(256), 0, st, d_probs, d_items + b, R);
+      hipLaunchKernelGGL((codon_post_level_kernel<T, false>), dim3(blocks, n), dim3(256), 0, st, d_probs, d_items + b, R);
   }
+}
+
+// FP32: levels of at most split_blocks blocks on the side-split kernel.  FP64:
+// the level kernel throughout (the split kernel's LDS would not hold doubles).
+template <typename T>
+void pre_levels(const CodonSchedule& sc, const CodonProblem* d_probs, const int2* d_items, hipStream_t st) {
+  for (int l = sc.n_levels; l >= 1; --l) {
+    const int b = sc.level_off[l - 1], n = sc.level_off[l] - b;
+    if (!n) continue;
+    const int R = sc.level_R[l - 1];
+    const int blocks = (sc.max_tiles + R - 1) / R;
+    if (sizeof(T) == 4 && (long)blocks * n <= sc.split_blocks) {
+      if (sc.amb)
+        hipLaunchKernelGGL(codon_pre_split_kernel<true>, dim3(blocks, n), dim3(512), 0, st, d_probs, d_items + b, R);
+      else
+        hipLaunchKernelGGL(codon_pre_split_kernel<false>, dim3(blocks, n), dim3(512), 0, st, d_probs, d_items + b, R);
+    } else if (sc.amb) {
+      hipLaunchKernelGGL((codon_pre_level_kernel<T, true>), dim3(blocks, n), dim3(256), 0, st, d_probs, d_items + b, R);
+    } else {
+      hipLaunchKernelGGL((codon_pre_level_kernel<T, false>), dim3(blocks, n), dim3(256), 0, st, d_probs, d_items + b, R);
+    }
+  }
+}
+}  // namespace
+
+int codon_launch_post(const CodonSchedule& sc, const CodonProblem* d_probs, const int2* d_items, hipStream_t st) {
+  if (sc.fp64)
+    post_levels<double>(sc, d_probs, d_items, st);
+  else
+    post_levels<float>(sc, d_probs, d_items, st);
   return hip_check(hipGetLastError(), "codon_post_level launch");
 }
 
 int codon_launch_root(const CodonSchedule& sc, const CodonProblem* d_probs, hipStream_t st) {
-  hipLaunchKernelGGL(codon_root_kernel, dim3(sc.max_pattern_blocks, sc.n_problems), dim3(256), 0, st, d_probs);
+  if (sc.fp64)
+    hipLaunchKernelGGL(codon_root_kernel<double>, dim3(sc.max_pattern_blocks, sc.n_problems), dim3(256), 0, st, d_probs);
+  else
+    hipLaunchKernelGGL(codon_root_kernel<float>, dim3(sc.max_pattern_blocks, sc.n_problems), dim3(256), 0, st, d_probs);
   hipLaunchKernelGGL(codon_final_kernel, dim3(sc.n_problems), dim3(256), 0, st, d_probs);
   return hip_check(hipGetLastError(), "codon_root launch");
 }
@@ -922,27 +1033,19 @@ size_t codon_dpart_bytes(const CodonSchedule& sc) { return sc.reduce_items.size(
 
 int codon_launch_pre_grad(const CodonSchedule& sc, const CodonProblem* d_probs, const int2* d_items,
                           const int2* d_reduce_items, double* dpart, hipStream_t st, bool accumulate, bool finish) {
-  for (int l = sc.n_levels; l >= 1; --l) {
-    const int b = sc.level_off[l - 1], n = sc.level_off[l] - b;
-    if (!n) continue;
-    const int R = sc.level_R[l - 1];
-    const int blocks = (sc.max_tiles + R - 1) / R;
-    if ((long)blocks * n <= sc.split_blocks)
-      if (sc.amb)
-        hipLaunchKernelGGL(codon_pre_split_kernel<true>, dim3(blocks, n), dim3(512), 0, st, d_probs, d_items + b, R);
-      else
-        hipLaunchKernelGGL(codon_pre_split_kernel<false>, dim3(blocks, n), dim3(512), 0, st, d_probs, d_items + b, R);
-    else
-      if (sc.amb)
-        hipLaunchKernelGGL(codon_pre_level_kernel<true>, dim3(blocks, n), dim3(256), 0, st, d_probs, d_items + b, R);
-      else
-        hipLaunchKernelGGL(codon_pre_level_kernel<false>, dim3(blocks, n), dim3(256), 0, st, d_probs, d_items + b, R);
-  }
+  if (sc.fp64)
+    pre_levels<double>(sc, d_probs, d_items, st);
+  else
+    pre_levels<float>(sc, d_probs, d_items, st);
   int rc = hip_check(hipGetLastError(), "codon_pre_level launch");
   if (rc) return rc;
   const int n_items = (int)sc.reduce_items.size();
-  hipLaunchKernelGGL(codon_grad_reduce_kernel, dim3((unsigned)(n_items * kReduceChunks)), dim3(256), 0, st, d_probs,
-                     d_reduce_items, dpart, accumulate ? 1 : 0);
+  if (sc.fp64)
+    hipLaunchKernelGGL(codon_grad_reduce_kernel<double>, dim3((unsigned)(n_items * kReduceChunks)), dim3(256), 0, st,
+                       d_probs, d_reduce_items, dpart, accumulate ? 1 : 0);
+  else
+    hipLaunchKernelGGL(codon_grad_reduce_kernel<float>, dim3((unsigned)(n_items * kReduceChunks)), dim3(256), 0, st,
+                       d_probs, d_reduce_items, dpart, accumulate ? 1 : 0);
   if (finish)
     hipLaunchKernelGGL(codon_dbranch_kernel, dim3((unsigned)((n_items + 255) / 256)), dim3(256), 0, st, d_probs,
                        d_reduce_items, n_items, static_cast<const double*>(dpart));
@@ -962,7 +1065,8 @@ int codon_prepare(EpochInstance* in) {
   const int C = in->C;  // one problem per category (C > 1 only without pattern chunks)
   const size_t gs = gslots[0].size();
   int rc = ensure(in->gslots, C * gs * sizeof(int32_t));
-  if (!rc && grad) rc = ensure(in->Gpart, std::max<size_t>(1, C * sc.slot_total[0]) * kCodonSlotBytes);
+  const size_t slot_floats = (kCodonSlotBytes / sizeof(float)) * (in->fp64 ? 2 : 1);  // one slot, in floats
+  if (!rc && grad) rc = ensure(in->Gpart, std::max<size_t>(1, C * sc.slot_total[0]) * slot_floats * sizeof(float));
   if (!rc && grad) rc = ensure(in->codon_aux, codon_dpart_bytes(sc));
   if (rc) return rc;
   const int nc = in->codon_nchunks;
@@ -970,7 +1074,7 @@ int codon_prepare(EpochInstance* in) {
   for (int c = 0; c < C; ++c) {
     const CodonProblem d =
         codon_descriptor(in, c, static_cast<const int32_t*>(in->gslots.ptr) + c * gs,
-                         static_cast<float*>(in->Gpart.ptr) + c * sc.slot_total[0] * (kCodonSlotBytes / sizeof(float)));
+                         static_cast<float*>(in->Gpart.ptr) + c * sc.slot_total[0] * slot_floats);
     for (int j = 0; j < nc; ++j) {  // nc > 1 only with one category
       const int p0 = j * codon_chunk_patterns(in);
       CodonProblem& dj = desc[j * C + c];
