@@ -372,6 +372,11 @@ def run_codon_leg(steps, warmup, with_parity):
     lik = from_problem(prob, "fp32", grad_branch=True, grad_Q=True)
     eps, ms, phases, _ = time_instance(lik, steps, warmup, True, True)
     lik.close()
+    # the same evaluation in FP64: on the FP64 matrix cores, and on the plain generic FP64 kernels
+    with from_problem(prob, "fp64", grad_branch=True, grad_Q=True) as l64:
+        e64, ms64, _, _ = time_instance(l64, max(3, steps // 2), 2, True, True)
+    with from_problem(prob, "fp64", grad_branch=True, grad_Q=True, kernel="generic") as lg:
+        eg, msg, _, _ = time_instance(lg, 3, 1, True, True)
     proposals = proposal_leg(prob, 4 * steps)
     aflops = algorithmic_flops(prob)
     total = sum(aflops.values())
@@ -380,6 +385,10 @@ def run_codon_leg(steps, warmup, with_parity):
            "whole_eval_TFLOPs": round(total / (ms * 1e-3) / 1e12, 3),
            "whole_eval_frac_fp32_peak": round(total / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4),
            "phases_ms_per_eval": {k: round(v[0] / steps, 4) for k, v in phases.items()},
+           "fp64": {"evals_per_s": round(e64, 2), "ms_per_eval": round(ms64, 4),
+                    "generic_fp64_evals_per_s": round(eg, 2), "generic_fp64_ms_per_eval": round(msg, 4),
+                    "speedup_fp32_over_fp64": round(eps / e64, 3),
+                    "speedup_fp32_over_generic_fp64": round(eps / eg, 3)},
            "one_branch_proposals": proposals}
     if with_parity:
         sub = pattern_subset(prob, 1000)
@@ -452,10 +461,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=None,
                     help="benchmark one workload alone (1-5); default: the headline workload with every leg")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--precision", default=None, choices=["fp32", "fp64"],
+                    help="default: FP64 for the 16-taxon workload (as it is stated), FP32 otherwise")
     ap.add_argument("--kernel", default="auto", choices=["auto", "generic"])
     ap.add_argument("--patterns", type=int, default=None, help="override the pattern count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra-legs", action="store_true",
+                    help="time the workload only (no other-precision legs): for profiling one configuration")
     ap.add_argument("--cpu-sample", type=int, default=None)
     ap.add_argument("--grad-q", action="store_true", help="also form dlogL/dQ (default for configs 3, 4)")
     ap.add_argument("--batch", type=int, default=None, help="number of problems for config 5 (default 64)")
@@ -474,6 +486,8 @@ def main():
     torch.cuda.set_device(0)
     headline = args.config is None
     config = 2 if headline else args.config
+    if args.precision is None:
+        args.precision = "fp64" if config == 1 else "fp32"
     if config == 5:
         return run_batch(args)
     want_Q = args.grad_q or config in (3, 4, 6)
@@ -527,7 +541,7 @@ def main():
         result["parity_vs_oracle"] = gpu_parity(sub, args.precision, args.kernel, use_pi, ref_logL, ref_b, ref_q,
                                                 want_grad, want_Q)
     if not headline and config in (3, 4, 6) and args.precision == "fp32" and args.kernel == "auto" \
-            and args.patterns is None:
+            and args.patterns is None and not args.no_extra_legs:
         log("bench: FP32-products and FP64 legs ...")
         result["fp64_reconstruction_default"] = fp64_reconstruction(prob, use_pi)
         result["other_precisions"] = precision_leg(prob, config, max(3, args.steps // 2), want_grad, want_Q, use_pi,
