@@ -40,7 +40,7 @@ WORKLOADS = {
        "logL + branch-length and rate-matrix gradients",
     4: "40-state asymmetric CTMC, 12 processes over 48 intervals, 2000-taxon tree, 1 pattern, "
        "logL + branch-length and rate-matrix gradients",
-    6: "20-state reversible model (amino-acid-sized; padded to 64 on the matrix cores), 4 epochs, 128-taxon tree, "
+    6: "20-state reversible model (amino-acid-sized; padded to 32 on the matrix cores), 4 epochs, 128-taxon tree, "
        "10000 patterns, 1 category, logL + branch-length and rate-matrix gradients",
 }
 

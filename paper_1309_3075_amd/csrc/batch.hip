@@ -136,7 +136,7 @@ int build_schedule(EpochBatch* b) {
   const size_t n = (size_t)sc.n_problems;  // one problem per member and rate category
   size_t total = 0;
   for (size_t q = 0; q < n; ++q) total += sc.slot_total[q];
-  const size_t slot_floats = (kCodonSlotBytes / sizeof(float)) * (sc.fp64 ? 2 : 1);  // one slot, in floats
+  const size_t slot_floats = (size_t)(16 * sc.nt) * (16 * sc.nt) * (sc.fp64 ? 2 : 1);  // one slot, in floats
   int rc0 = ensure(b->gpart, std::max<size_t>(1, total) * slot_floats * sizeof(float));
   if (!rc0) rc0 = ensure(b->dpart, codon_dpart_bytes(sc));
   if (rc0) return rc0;
@@ -441,7 +441,9 @@ int epoch_batch_create(EpochInstance* const* insts, int32_t n, const char* tune_
   b->own_stream = true;
   b->merged = true;
   for (int i = 0; i < n; ++i) {
-    if (insts[i]->path != 2 || insts[i]->codon_nchunks > 1 || insts[i]->fp64 != insts[0]->fp64) b->merged = false;
+    if (insts[i]->path != 2 || insts[i]->codon_nchunks > 1 || insts[i]->fp64 != insts[0]->fp64 ||
+        insts[i]->Kp != insts[0]->Kp)
+      b->merged = false;
     if (insts[i]->device != insts[0]->device) {
       (void)hipStreamDestroy(b->stream);
       delete b;

@@ -17,7 +17,7 @@ int fastpath_init(EpochInstance* in) {
   in->path = 0;
   if (in->cfg.kernel_path == EPOCH_KERNEL_AUTO) {
     if (in->K == 4) in->path = 1;
-    else if (in->Kp == 64 && (in->K > 48 || (in->K > 16 && in->K <= 32)) &&
+    else if (((in->Kp == 64 && in->K > 48) || (in->Kp == 32 && in->K > 16)) &&
              (in->budget == 0 || (in->C == 1 && !in->fp64)))
       in->path = 2;
   }

@@ -137,17 +137,17 @@ int padded_states(int K) {
   return (K + 15) / 16 * 16;
 }
 
-// Problems of 49..64 states, and of 17..32 states (a 20-state amino-acid model, say,
-// padded to 64 states: the padding states are never observed and their transition rows
-// are the identity), run on the 64-state matrix-core kernels, FP32 or FP64, with any
-// number of rate categories; under an HBM budget (pattern chunks) FP32 with one category.
+// Problems of 49..64 states (padded to 64), and of 17..32 states (a 20-state amino-acid
+// model, say, padded to 32: the padding states are never observed and their transition
+// rows are the identity), run on the matrix-core 64- / 32-state kernels, FP32 or FP64,
+// with any number of rate categories; under an HBM budget (pattern chunks) FP32 with
+// one category.
 bool codon_config(const EpochConfig& c) {
   return ((c.n_states > 48 && c.n_states <= 64) || (c.n_states > 16 && c.n_states <= 32)) &&
          c.kernel_path == EPOCH_KERNEL_AUTO &&
          (c.hbm_budget_bytes == 0 || (c.n_categories == 1 && c.precision == EPOCH_FP32));
 }
-bool small_codon_config(const EpochConfig& c) { return codon_config(c) && c.n_states <= 32; }
-int padded_states(const EpochConfig& c) { return small_codon_config(c) ? 64 : padded_states(c.n_states); }
+int padded_states(const EpochConfig& c) { return padded_states(c.n_states); }
 // The 64-state kernels keep one scale exponent and one weight row per rate category.
 size_t scale_sets(const EpochConfig& c) { return codon_config(c) ? (size_t)c.n_categories : 1; }
 
@@ -197,9 +197,9 @@ bool codon_budget_config(const EpochConfig& c) {
 // of 64 patterns).
 size_t codon_bytes_per_pattern(const EpochConfig& c) {
   const bool grad = (c.flags & (EPOCH_GRAD_BRANCH | EPOCH_GRAD_Q | EPOCH_GRAD_TIME)) != 0;
-  const size_t Nm1 = (size_t)c.n_tips - 1;
-  return Nm1 * (64 * sizeof(float) + sizeof(int32_t)) +
-         (grad ? Nm1 * 64 * sizeof(float) + 2 * Nm1 * kCodonSlotBytes / 64 : 0);
+  const size_t Nm1 = (size_t)c.n_tips - 1, Kp = padded_states(c.n_states);
+  return Nm1 * (Kp * sizeof(float) + sizeof(int32_t)) +
+         (grad ? Nm1 * Kp * sizeof(float) + 2 * Nm1 * Kp * Kp * sizeof(float) / 64 : 0);
 }
 
 // Device bytes one pattern of a chunk costs on the generic path: partials and

@@ -84,6 +84,7 @@ struct CodonSchedule {
   int split_blocks = 0;  // pre-order levels of at most this many blocks put each child branch on its own wavefronts
   bool amb = false;      // some problem has tips with ambiguity codes (the kernels' ambiguity instantiation)
   bool fp64 = false;     // FP64 problems (the FP64 matrix-core instantiation; every problem of a schedule alike)
+  int nt = 4;            // 16-state tiles of the padded states: 4 (64 states) or 2 (32); every problem alike
 };
 
 // Incremental re-evaluation (MCMC proposals): the work of one restricted pass.

@@ -42,11 +42,28 @@ namespace {
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int KP = 64;
-constexpr int KK = KP * KP;
-constexpr int LDP = 68;  // LDS row stride (elements): 64 states, the row sum, padding
+// Padded state counts: NT tiles of 16 states, 64 (NT = 4) or 32 (NT = 2).  The
+// namespace-level KP, KK, LDP are the 64-state values (the side-split kernel
+// and the host); the kernels templated on NT declare their own.
+template <int NT>
+struct Dim {
+  static constexpr int KP = 16 * NT;   // padded states
+  static constexpr int KK = KP * KP;   // entries of a transition matrix
+  static constexpr int LDP = KP + 4;   // LDS row stride (elements): the states, the row sum, padding
+  static constexpr int NCT = NT * NT / 4;  // 16 x 16 tiles of dlogL/dP per wavefront in the gradient phase
+};
+constexpr int KP = Dim<4>::KP;
+constexpr int KK = Dim<4>::KK;
+constexpr int LDP = Dim<4>::LDP;
 constexpr int TILE = 64;  // patterns per block tile
 constexpr int WT = 16;    // patterns per wavefront tile
+#define EPOCH_DIMS(NT)                     \
+  constexpr int KP = Dim<NT>::KP;          \
+  constexpr int KK = Dim<NT>::KK;          \
+  constexpr int LDP = Dim<NT>::LDP;        \
+  (void)KP;                                \
+  (void)KK;                                \
+  (void)LDP
 
 // FP32 (v_mfma_f32_16x16x4f32) and FP64 (v_mfma_f64_16x16x4f64) forms of the
 // kernels.  The A and B operands map alike; the four D registers of lane
@@ -87,10 +104,11 @@ __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Stage a 64x64 row-major matrix into LDS with row stride LDP, in 16-byte
+// Stage a KP x KP row-major matrix into LDS with row stride LDP, in 16-byte
 // pieces (256 threads, t = 0 .. 255).
-template <typename T>
+template <int NT, typename T>
 __device__ inline void stage_matrix(T* __restrict__ s, const T* __restrict__ g, int t) {
+  EPOCH_DIMS(NT);
   constexpr int PER_ROW = KP * sizeof(T) / 16;  // 16-byte pieces per row
   const EPOCH_GLOBAL f4* src = gptr(reinterpret_cast<const f4*>(g));
   for (int e = t; e < KP * PER_ROW; e += 256) {
@@ -98,24 +116,26 @@ __device__ inline void stage_matrix(T* __restrict__ s, const T* __restrict__ g, 
     *reinterpret_cast<f4*>(reinterpret_cast<char*>(s + row * LDP) + 16 * c) = src[e];
   }
 }
-template <typename T>
+template <int NT, typename T>
 __device__ inline void stage_matrix(T* __restrict__ s, const T* __restrict__ g) {
-  stage_matrix(s, g, threadIdx.x);
+  stage_matrix<NT>(s, g, threadIdx.x);
 }
-// Row sums over the first K columns into column 64 (needs the staged matrix;
-// 256 threads, t = 0 .. 255).
-template <typename T>
+// Row sums over the first K columns into column KP (needs the staged matrix;
+// 256 threads, t = 0 .. 255: TPR threads per row, CPT columns each).
+template <int NT, typename T>
 __device__ inline void stage_row_sums(T* __restrict__ s, int K, int t) {
-  const int row = t >> 2, q = t & 3;
+  EPOCH_DIMS(NT);
+  constexpr int TPR = 256 / KP, CPT = KP / TPR;
+  const int row = t / TPR, q = t % TPR;
   T acc = 0;
 #pragma unroll
-  for (int j = 0; j < 16; ++j) acc += (16 * q + j < K) ? s[row * LDP + 16 * q + j] : T(0);
-  acc += __shfl_xor(acc, 1, 4);
-  acc += __shfl_xor(acc, 2, 4);
-  if (q == 0) s[row * LDP + 64] = acc;
+  for (int j = 0; j < CPT; ++j) acc += (CPT * q + j < K) ? s[row * LDP + CPT * q + j] : T(0);
+#pragma unroll
+  for (int o = 1; o < TPR; o <<= 1) acc += __shfl_xor(acc, o, TPR);
+  if (q == 0) s[row * LDP + KP] = acc;
 }
-template <typename T>
-__device__ inline void stage_row_sums(T* __restrict__ s, int K) { stage_row_sums(s, K, threadIdx.x); }
+template <int NT, typename T>
+__device__ inline void stage_row_sums(T* __restrict__ s, int K) { stage_row_sums<NT>(s, K, threadIdx.x); }
 
 // Row-max / row-sum over the 16 lanes of a DPP row (lanes sharing g).
 __device__ inline float row16_max(float v) {
@@ -158,20 +178,21 @@ __device__ inline double row16_sum(double v) {
 // S[nt] (D layout) = sum_j L[p][j] P[16 nt + r][j] for an internal child whose
 // partials start at Lg.  Pattern rows past the end are clamped (their results
 // are never stored).
-template <typename T>
-__device__ inline void child_gemm(v4<T> (&S)[4], const T* __restrict__ Lg, int P, int p0,
+template <int NT, typename T>
+__device__ inline void child_gemm(v4<T> (&S)[NT], const T* __restrict__ Lg, int P, int p0,
                                   const T* __restrict__ sP, int g, int r) {
+  EPOCH_DIMS(NT);
 #pragma unroll
-  for (int nt = 0; nt < 4; ++nt) S[nt] = v4<T>{0, 0, 0, 0};
+  for (int nt = 0; nt < NT; ++nt) S[nt] = v4<T>{0, 0, 0, 0};
   const int pa = min(p0 + r, P - 1);
   const EPOCH_GLOBAL v4<T>* arow = gptr(reinterpret_cast<const v4<T>*>(Lg + (size_t)pa * KP)) + g;
-  v4<T> a[4];
+  v4<T> a[NT];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) a[t] = arow[4 * t];  // L[pa][16 t + 4 g .. 16 t + 4 g + 3]
+  for (int t = 0; t < NT; ++t) a[t] = arow[4 * t];  // L[pa][16 t + 4 g .. 16 t + 4 g + 3]
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
+    for (int nt = 0; nt < NT; ++nt) {
       const v4<T> b = *reinterpret_cast<const v4<T>*>(sP + (16 * nt + r) * LDP + 16 * t + 4 * g);
       S[nt] = mfma(a[t].x, b.x, S[nt]);
       S[nt] = mfma(a[t].y, b.y, S[nt]);
@@ -181,15 +202,16 @@ __device__ inline void child_gemm(v4<T> (&S)[4], const T* __restrict__ Lg, int P
 }
 
 // Tip states of the patterns of D-layout rows v as LDS columns: an observed
-// state is its column, a missing one column 64 (the row sums), and the
-// caller's ambiguity set a is 65 + a (text after Eq. 4: tips are 0/1
+// state is its column, a missing one column KP (the row sums), and the
+// caller's ambiguity set a is KP + 1 + a (text after Eq. 4: tips are 0/1
 // indicators of the possible states).
-template <typename T>
+template <int NT, typename T>
 __device__ inline void tip_columns(int (&col)[4], const uint8_t* __restrict__ tipst, int P, int p0, int K, int g) {
+  EPOCH_DIMS(NT);
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int st = gptr(tipst)[min(p0 + drow<T>(g, v), P - 1)];
-    col[v] = st < K ? st : 64 + (st - K);
+    col[v] = st < K ? st : KP + (st - K);
   }
 }
 // Sum of row entries over an ambiguity set (rare: kept off the common path).
@@ -206,29 +228,31 @@ __device__ __noinline__ T masked_row_sum(const T* __restrict__ row, uint64_t set
 // Tip child: S = P[i][state_p] (or the sum of P[i][.] over the tip's state set).
 // AMB: the problem has tips with ambiguity codes (a separate instantiation, so
 // the common case keeps its registers).
-template <bool AMB, typename T>
-__device__ inline void tip_lookup(v4<T> (&S)[4], const int (&col)[4], const T* __restrict__ sP, int r,
+template <int NT, bool AMB, typename T>
+__device__ inline void tip_lookup(v4<T> (&S)[NT], const int (&col)[4], const T* __restrict__ sP, int r,
                                   const uint64_t* __restrict__ amb) {
+  EPOCH_DIMS(NT);
 #pragma unroll
-  for (int nt = 0; nt < 4; ++nt)
+  for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) S[nt][v] = sP[(16 * nt + r) * LDP + (AMB ? min(col[v], 64) : col[v])];
-  if (AMB && max(max(col[0], col[1]), max(col[2], col[3])) > 64) {  // an ambiguity set
+    for (int v = 0; v < 4; ++v) S[nt][v] = sP[(16 * nt + r) * LDP + (AMB ? min(col[v], KP) : col[v])];
+  if (AMB && max(max(col[0], col[1]), max(col[2], col[3])) > KP) {  // an ambiguity set
 #pragma unroll
     for (int v = 0; v < 4; ++v)
-      if (col[v] > 64)
-        for (int nt = 0; nt < 4; ++nt) S[nt][v] = masked_row_sum(sP + (16 * nt + r) * LDP, amb[col[v] - 65]);
+      if (col[v] > KP)
+        for (int nt = 0; nt < NT; ++nt) S[nt][v] = masked_row_sum(sP + (16 * nt + r) * LDP, amb[col[v] - KP - 1]);
   }
 }
 
-// D-layout load of a [P][64] array: value at pattern p0 + drow(g, v), state 16 nt + r.
-template <typename T>
-__device__ inline void load_dlayout(v4<T> (&X)[4], const T* __restrict__ base, int P, int p0, int g, int r) {
+// D-layout load of a [P][KP] array: value at pattern p0 + drow(g, v), state 16 nt + r.
+template <int NT, typename T>
+__device__ inline void load_dlayout(v4<T> (&X)[NT], const T* __restrict__ base, int P, int p0, int g, int r) {
+  EPOCH_DIMS(NT);
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const EPOCH_GLOBAL T* row = gptr(base + (size_t)min(p0 + drow<T>(g, v), P - 1) * KP) + r;
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) X[nt][v] = row[16 * nt];
+    for (int nt = 0; nt < NT; ++nt) X[nt][v] = row[16 * nt];
   }
 }
 
@@ -236,9 +260,10 @@ __device__ inline float dmax(float a, float b) { return fmaxf(a, b); }
 __device__ inline double dmax(double a, double b) { return fmax(a, b); }
 
 // ---------------------------------------------------------------------------
-template <typename T, bool AMB>
+template <typename T, int NT, bool AMB>
 __global__ __launch_bounds__(256) void codon_post_level_kernel(const CodonProblem* __restrict__ probs,
                                                                 const int2* __restrict__ items, int R) {
+  EPOCH_DIMS(NT);
   __shared__ __align__(16) T sPa[KP * LDP];
   __shared__ __align__(16) T sPb[KP * LDP];
   const int2 it = items[blockIdx.y];
@@ -251,11 +276,11 @@ __global__ __launch_bounds__(256) void codon_post_level_kernel(const CodonProble
   const int a = pr.left[u], b = pr.right[u];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
   const T* Pm = reinterpret_cast<const T*>(pr.Pm);
-  stage_matrix(sPa, Pm + (size_t)a * pr.pm_stride);
-  stage_matrix(sPb, Pm + (size_t)b * pr.pm_stride);
+  stage_matrix<NT>(sPa, Pm + (size_t)a * pr.pm_stride);
+  stage_matrix<NT>(sPb, Pm + (size_t)b * pr.pm_stride);
   __syncthreads();
-  stage_row_sums(sPa, K);
-  stage_row_sums(sPb, K);
+  stage_row_sums<NT>(sPa, K);
+  stage_row_sums<NT>(sPb, K);
   __syncthreads();
   T* part = reinterpret_cast<T*>(pr.part);
   const T* La = a >= N ? part + (size_t)(a - N) * P * KP : nullptr;
@@ -265,27 +290,27 @@ __global__ __launch_bounds__(256) void codon_post_level_kernel(const CodonProble
   EPOCH_GLOBAL T* out = gptr(part + (size_t)(u - N) * P * KP);
   EPOCH_GLOBAL int32_t* sout = gptr(pr.scales + (size_t)(u - N) * P);
   for (int p0 = base + WT * w; p0 < end; p0 += 4 * WT) {
-    v4<T> Sa[4], Sb[4];
+    v4<T> Sa[NT], Sb[NT];
     if (La) {
-      child_gemm<T>(Sa, La, P, p0, sPa, g, r);
+      child_gemm<NT, T>(Sa, La, P, p0, sPa, g, r);
     } else {
       int col[4];
-      tip_columns<T>(col, pr.tips + (size_t)a * pr.tip_stride, P, p0, K, g);
-      tip_lookup<AMB, T>(Sa, col, sPa, r, pr.amb);
+      tip_columns<NT, T>(col, pr.tips + (size_t)a * pr.tip_stride, P, p0, K, g);
+      tip_lookup<NT, AMB, T>(Sa, col, sPa, r, pr.amb);
     }
     if (Lb) {
-      child_gemm<T>(Sb, Lb, P, p0, sPb, g, r);
+      child_gemm<NT, T>(Sb, Lb, P, p0, sPb, g, r);
     } else {
       int col[4];
-      tip_columns<T>(col, pr.tips + (size_t)b * pr.tip_stride, P, p0, K, g);
-      tip_lookup<AMB, T>(Sb, col, sPb, r, pr.amb);
+      tip_columns<NT, T>(col, pr.tips + (size_t)b * pr.tip_stride, P, p0, K, g);
+      tip_lookup<NT, AMB, T>(Sb, col, sPb, r, pr.amb);
     }
     int e[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       T m = 0;
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt) {
+      for (int nt = 0; nt < NT; ++nt) {
         Sa[nt][v] *= Sb[nt][v];
         m = dmax(m, Sa[nt][v]);
       }
@@ -296,7 +321,7 @@ __global__ __launch_bounds__(256) void codon_post_level_kernel(const CodonProble
       const int p = p0 + drow<T>(g, v);
       if (p < P) {
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) __builtin_nontemporal_store(scale_by_pow2(Sa[nt][v], e[v]), &out[(size_t)p * KP + 16 * nt + r]);
+        for (int nt = 0; nt < NT; ++nt) __builtin_nontemporal_store(scale_by_pow2(Sa[nt][v], e[v]), &out[(size_t)p * KP + 16 * nt + r]);
         if (r == 0) sout[p] = e[v] + (sca ? gptr(sca)[p] : 0) + (scb ? gptr(scb)[p] : 0);
       }
     }
@@ -312,8 +337,9 @@ __global__ __launch_bounds__(256) void codon_post_level_kernel(const CodonProble
 // l_c = sum_i pi_i x_c(p, i); the pre-order pass of category c then weighs
 // pattern p by w_p w_c l_c 2^E_c / L_p (its posterior share), written to that
 // category's weightsT.
-template <typename T>
+template <typename T, int NT>
 __global__ __launch_bounds__(256) void codon_root_kernel(const CodonProblem* __restrict__ probs) {
+  EPOCH_DIMS(NT);
   __shared__ double sm[256];
   const CodonProblem& pr = probs[blockIdx.y];
   if (pr.cat_index != 0) return;  // uniform
@@ -386,24 +412,31 @@ __global__ __launch_bounds__(256) void codon_final_kernel(const CodonProblem* __
 // A = t[p][16 w + r] w_p / L_p, B = the child's partials (internal child) or
 // its tip-state indicator.  One loop per kind of child, with no branch inside,
 // so the LDS reads of later k-steps are issued ahead of the matrix-core work.
-template <typename T>
+// With 32 states (NT = 2) the four wavefronts split the 2 x 2 tiles of
+// dlogL/dP instead: wavefront w takes row tile w % NT and NCT column tiles
+// from ct0 = (w / NT) NCT (for 64 states: rows 16 w .. 16 w + 15, every column).
+template <int NT, typename T>
 __device__ inline void grad_rows_internal(v4<T>* G, const T* __restrict__ tcol, const T* __restrict__ sCF,
-                                          const T* __restrict__ sL, int g, int r) {
+                                          const T* __restrict__ sL, int ct0, int g, int r) {
+  EPOCH_DIMS(NT);
+  constexpr int NCT = Dim<NT>::NCT;
 #pragma unroll 8
   for (int ks = 0; ks < TILE / 4; ++ks) {
     const int pl = 4 * ks + g;
     const T av = tcol[pl * LDP] * sCF[pl];
     v4<T> B;
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) B[nt] = sL[pl * LDP + 16 * nt + r];
+    for (int c = 0; c < NCT; ++c) B[c] = sL[pl * LDP + 16 * (ct0 + c) + r];
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) G[nt] = mfma(av, B[nt], G[nt]);
+    for (int c = 0; c < NCT; ++c) G[c] = mfma(av, B[c], G[c]);
   }
 }
-template <bool AMB, typename T>
+template <int NT, bool AMB, typename T>
 __device__ inline void grad_rows_tip(v4<T>* G, const T* __restrict__ tcol, const T* __restrict__ sCF,
-                                     const int* __restrict__ sCol, int K, int g, int r,
+                                     const int* __restrict__ sCol, int K, int ct0, int g, int r,
                                      const uint64_t* __restrict__ amb) {
+  EPOCH_DIMS(NT);
+  constexpr int NCT = Dim<NT>::NCT;
 #pragma unroll 8
   for (int ks = 0; ks < TILE / 4; ++ks) {
     const int pl = 4 * ks + g;
@@ -411,17 +444,17 @@ __device__ inline void grad_rows_tip(v4<T>* G, const T* __restrict__ tcol, const
     const int col = sCol[pl];
     v4<T> B;
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-      const int j = 16 * nt + r;
-      B[nt] = (col == j || (col == 64 && j < K)) ? T(1) : T(0);
+    for (int c = 0; c < NCT; ++c) {
+      const int j = 16 * (ct0 + c) + r;
+      B[c] = (col == j || (col == KP && j < K)) ? T(1) : T(0);
     }
-    if (AMB && col > 64) {  // the 0/1 row of an ambiguity set
-      const uint64_t set = amb[col - 65];
+    if (AMB && col > KP) {  // the 0/1 row of an ambiguity set
+      const uint64_t set = amb[col - KP - 1];
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt) B[nt] = ((set >> (16 * nt + r)) & 1) ? T(1) : T(0);
+      for (int c = 0; c < NCT; ++c) B[c] = ((set >> (16 * (ct0 + c) + r)) & 1) ? T(1) : T(0);
     }
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) G[nt] = mfma(av, B[nt], G[nt]);
+    for (int c = 0; c < NCT; ++c) G[c] = mfma(av, B[c], G[c]);
   }
 }
 
@@ -429,52 +462,55 @@ __device__ inline void grad_rows_tip(v4<T>* G, const T* __restrict__ tcol, const
 // schedule was built for still owns a dlogL/dP slot of each child branch (the
 // slot count covers the longest chunk): it writes zeros there.  Blocks past a
 // batch member's own tiles own no slot and write nothing.
-template <typename T>
+template <typename T, int NT>
 __device__ inline void zero_unused_slot(const CodonProblem& pr, int child, int nthreads) {
+  EPOCH_DIMS(NT);
   if ((int)blockIdx.x >= pr.gslots[child]) return;
   EPOCH_GLOBAL T* dst = gptr(reinterpret_cast<T*>(pr.Gpart) + ((size_t)pr.gslots[pr.n_nodes + child] + blockIdx.x) * KK);
   for (int e = threadIdx.x; e < KK / 4; e += nthreads) reinterpret_cast<EPOCH_GLOBAL v4<T>*>(dst)[e] = v4<T>{0, 0, 0, 0};
 }
 
-template <typename T>
+template <typename T, int NT>
 struct PreTileLoads {
-  v4<T> La[4], Lb[4];  // rows of 4 states of internal children's partials (child product A operand)
-  v4<T> Q[4];          // q_u in the D layout
+  v4<T> La[NT], Lb[NT];  // rows of 4 states of internal children's partials (child product A operand)
+  v4<T> Q[NT];           // q_u in the D layout
   int cola[4], colb[4];
 };
 
-template <typename T>
-__device__ inline void pre_load_tile(PreTileLoads<T>& ld, const CodonProblem& pr, const T* La, const T* Lb,
+template <int NT, typename T>
+__device__ inline void pre_load_tile(PreTileLoads<T, NT>& ld, const CodonProblem& pr, const T* La, const T* Lb,
                                      const T* Qu, int a, int b, int p0, int g, int r) {
+  EPOCH_DIMS(NT);
   const int P = pr.P, K = pr.K, N = pr.N;
   const int pa = min(p0 + r, P - 1);
   if (La) {
     const EPOCH_GLOBAL v4<T>* row = gptr(reinterpret_cast<const v4<T>*>(La + (size_t)pa * KP)) + g;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) ld.La[t] = row[4 * t];
+    for (int t = 0; t < NT; ++t) ld.La[t] = row[4 * t];
   } else {
-    tip_columns<T>(ld.cola, pr.tips + (size_t)a * pr.tip_stride, P, p0, K, g);
+    tip_columns<NT, T>(ld.cola, pr.tips + (size_t)a * pr.tip_stride, P, p0, K, g);
   }
   if (Lb) {
     const EPOCH_GLOBAL v4<T>* row = gptr(reinterpret_cast<const v4<T>*>(Lb + (size_t)pa * KP)) + g;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) ld.Lb[t] = row[4 * t];
+    for (int t = 0; t < NT; ++t) ld.Lb[t] = row[4 * t];
   } else {
-    tip_columns<T>(ld.colb, pr.tips + (size_t)b * pr.tip_stride, P, p0, K, g);
+    tip_columns<NT, T>(ld.colb, pr.tips + (size_t)b * pr.tip_stride, P, p0, K, g);
   }
-  if (Qu) load_dlayout<T>(ld.Q, Qu, P, p0, g, r);
+  if (Qu) load_dlayout<NT, T>(ld.Q, Qu, P, p0, g, r);
   (void)N;
 }
 
 // S[nt] (D layout) from 16-byte A-operand rows already in registers.
-template <typename T>
-__device__ inline void child_gemm_regs(v4<T> (&S)[4], const v4<T> (&a)[4], const T* __restrict__ sP, int g, int r) {
+template <int NT, typename T>
+__device__ inline void child_gemm_regs(v4<T> (&S)[NT], const v4<T> (&a)[NT], const T* __restrict__ sP, int g, int r) {
+  EPOCH_DIMS(NT);
 #pragma unroll
-  for (int nt = 0; nt < 4; ++nt) S[nt] = v4<T>{0, 0, 0, 0};
+  for (int nt = 0; nt < NT; ++nt) S[nt] = v4<T>{0, 0, 0, 0};
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
+    for (int nt = 0; nt < NT; ++nt) {
       const v4<T> bv = *reinterpret_cast<const v4<T>*>(sP + (16 * nt + r) * LDP + 16 * t + 4 * g);
       S[nt] = mfma(a[t].x, bv.x, S[nt]);
       S[nt] = mfma(a[t].y, bv.y, S[nt]);
@@ -483,9 +519,11 @@ __device__ inline void child_gemm_regs(v4<T> (&S)[4], const v4<T> (&a)[4], const
     }
 }
 
-template <typename T, bool AMB>
+template <typename T, int NT, bool AMB>
 __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void codon_pre_level_kernel(
     const CodonProblem* __restrict__ probs, const int2* __restrict__ items, int R) {
+  EPOCH_DIMS(NT);
+  constexpr int NCT = Dim<NT>::NCT;
   __shared__ __align__(16) T sPa[KP * LDP];
   __shared__ __align__(16) T sPb[KP * LDP];
   __shared__ __align__(16) T sT[TILE * LDP];  // t of one side for the block tile, pattern-major
@@ -499,58 +537,59 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void codon_pre_level_k
   const int u = it.y;
   const int a = pr.left[u], b = pr.right[u];
   if (base >= P) {  // uniform: this problem (or pattern chunk) has fewer tiles
-    zero_unused_slot<T>(pr, a, 256);
-    zero_unused_slot<T>(pr, b, 256);
+    zero_unused_slot<T, NT>(pr, a, 256);
+    zero_unused_slot<T, NT>(pr, b, 256);
     return;
   }
   const int n_tiles = min(R, (P - base + TILE - 1) / TILE);  // uniform over the block
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
   const T* Pm = reinterpret_cast<const T*>(pr.Pm);
-  stage_matrix(sPa, Pm + (size_t)a * pr.pm_stride);
-  stage_matrix(sPb, Pm + (size_t)b * pr.pm_stride);
+  stage_matrix<NT>(sPa, Pm + (size_t)a * pr.pm_stride);
+  stage_matrix<NT>(sPb, Pm + (size_t)b * pr.pm_stride);
   __syncthreads();
-  stage_row_sums(sPa, K);
-  stage_row_sums(sPb, K);
+  stage_row_sums<NT>(sPa, K);
+  stage_row_sums<NT>(sPb, K);
   __syncthreads();
   const T* part = reinterpret_cast<const T*>(pr.part);
   T* pre = reinterpret_cast<T*>(pr.pre);
   const T* La = a >= N ? part + (size_t)(a - N) * P * KP : nullptr;
   const T* Lb = b >= N ? part + (size_t)(b - N) * P * KP : nullptr;
   const T* Qu = u == pr.root ? nullptr : pre + (size_t)(u - N) * P * KP;
-  T piv[4];
+  T piv[NT];
 #pragma unroll
-  for (int nt = 0; nt < 4; ++nt) piv[nt] = 16 * nt + r < K ? (T)pr.pi[16 * nt + r] : T(0);
-  // dlogL/dP accumulators: rows 16 w + drow(g, v), columns 16 nt + r
-  v4<T> Ga[4], Gb[4];
+  for (int nt = 0; nt < NT; ++nt) piv[nt] = 16 * nt + r < K ? (T)pr.pi[16 * nt + r] : T(0);
+  // dlogL/dP accumulators: rows 16 rt + drow(g, v), columns 16 (ct0 + c) + r
+  const int rt = w % NT, ct0 = (w / NT) * NCT;
+  v4<T> Ga[NCT], Gb[NCT];
 #pragma unroll
-  for (int nt = 0; nt < 4; ++nt) {
-    Ga[nt] = v4<T>{0, 0, 0, 0};
-    Gb[nt] = v4<T>{0, 0, 0, 0};
+  for (int c = 0; c < NCT; ++c) {
+    Ga[c] = v4<T>{0, 0, 0, 0};
+    Gb[c] = v4<T>{0, 0, 0, 0};
   }
-  PreTileLoads<T> cur, nxt;
-  pre_load_tile<T>(cur, pr, La, Lb, Qu, a, b, base + WT * w, g, r);
+  PreTileLoads<T, NT> cur, nxt;
+  pre_load_tile<NT, T>(cur, pr, La, Lb, Qu, a, b, base + WT * w, g, r);
   T* trows = sT + (WT * w) * LDP;  // this wavefront's 16 pattern rows
   T* lrows = sL + (WT * w) * LDP;
   for (int bt = 0; bt < n_tiles; ++bt) {
     const int p0 = base + bt * TILE + WT * w;  // first pattern of this wavefront's part
     // ---- this wavefront's 16 patterns: child vectors, q_u, w_p / L_p
-    v4<T> Sa[4], Sb[4];
+    v4<T> Sa[NT], Sb[NT];
     if (La)
-      child_gemm_regs<T>(Sa, cur.La, sPa, g, r);
+      child_gemm_regs<NT, T>(Sa, cur.La, sPa, g, r);
     else
-      tip_lookup<AMB, T>(Sa, cur.cola, sPa, r, pr.amb);
+      tip_lookup<NT, AMB, T>(Sa, cur.cola, sPa, r, pr.amb);
     if (Lb)
-      child_gemm_regs<T>(Sb, cur.Lb, sPb, g, r);
+      child_gemm_regs<NT, T>(Sb, cur.Lb, sPb, g, r);
     else
-      tip_lookup<AMB, T>(Sb, cur.colb, sPb, r, pr.amb);
-    v4<T> Q[4];
+      tip_lookup<NT, AMB, T>(Sb, cur.colb, sPb, r, pr.amb);
+    v4<T> Q[NT];
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) Q[nt] = Qu ? cur.Q[nt] : v4<T>{piv[nt], piv[nt], piv[nt], piv[nt]};
+    for (int nt = 0; nt < NT; ++nt) Q[nt] = Qu ? cur.Q[nt] : v4<T>{piv[nt], piv[nt], piv[nt], piv[nt]};
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       T sum = 0;
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt) sum += Q[nt][v] * Sa[nt][v] * Sb[nt][v];
+      for (int nt = 0; nt < NT; ++nt) sum += Q[nt][v] * Sa[nt][v] * Sb[nt][v];
       sum = row16_sum(sum);
       const int p = p0 + drow<T>(g, v);
       if (r == 0) {
@@ -560,38 +599,38 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void codon_pre_level_k
       }
     }
     // loads of this wavefront's part of the next tile, in flight during the rest
-    if (bt + 1 < n_tiles) pre_load_tile<T>(nxt, pr, La, Lb, Qu, a, b, p0 + TILE, g, r);
+    if (bt + 1 < n_tiles) pre_load_tile<NT, T>(nxt, pr, La, Lb, Qu, a, b, p0 + TILE, g, r);
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
       const int child = side == 0 ? a : b;
       const T* Lc = side == 0 ? La : Lb;
-      const v4<T>* So = side == 0 ? Sb : Sa;
+      const v4<T>* So = side == 0 ? Sb : Sa;  // [NT]
       v4<T>* G = side == 0 ? Ga : Gb;
       const T* sP = side == 0 ? sPa : sPb;
       if (side == 1) __syncthreads();  // every wavefront is done with side a's t and L
       // t = q o S_sibling rows, and the child's partial rows, into LDS
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt)
+      for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
         for (int v = 0; v < 4; ++v) trows[drow<T>(g, v) * LDP + 16 * nt + r] = Q[nt][v] * So[nt][v];
       if (Lc) {
         const v4<T>* lr = side == 0 ? cur.La : cur.Lb;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) *reinterpret_cast<v4<T>*>(lrows + r * LDP + 16 * t + 4 * g) = lr[t];
+        for (int t = 0; t < NT; ++t) *reinterpret_cast<v4<T>*>(lrows + r * LDP + 16 * t + 4 * g) = lr[t];
       }
       wave_lds_sync();
       if (Lc) {
         // outside vector q_c[p][j] = sum_i t[p][i] P_c[i][j] of this wavefront's patterns
-        v4<T> ta[4];
+        v4<T> ta[NT];
 #pragma unroll
-        for (int tt = 0; tt < 4; ++tt) ta[tt] = *reinterpret_cast<const v4<T>*>(trows + r * LDP + 16 * tt + 4 * g);
-        v4<T> Qo[4];
+        for (int tt = 0; tt < NT; ++tt) ta[tt] = *reinterpret_cast<const v4<T>*>(trows + r * LDP + 16 * tt + 4 * g);
+        v4<T> Qo[NT];
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) Qo[nt] = v4<T>{0, 0, 0, 0};
+        for (int nt = 0; nt < NT; ++nt) Qo[nt] = v4<T>{0, 0, 0, 0};
 #pragma unroll
-        for (int tt = 0; tt < 4; ++tt)
+        for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
-          for (int nt = 0; nt < 4; ++nt) {
+          for (int nt = 0; nt < NT; ++nt) {
             const T* prow = sP + (16 * tt + 4 * g) * LDP + 16 * nt + r;
             Qo[nt] = mfma(ta[tt].x, prow[0], Qo[nt]);
             Qo[nt] = mfma(ta[tt].y, prow[LDP], Qo[nt]);
@@ -603,21 +642,21 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void codon_pre_level_k
         for (int v = 0; v < 4; ++v) {
           T m = 0;
 #pragma unroll
-          for (int nt = 0; nt < 4; ++nt) m = dmax(m, Qo[nt][v]);
+          for (int nt = 0; nt < NT; ++nt) m = dmax(m, Qo[nt][v]);
           const int e = scale_exponent(row16_max(m));
           const int p = p0 + drow<T>(g, v);
           if (p < P)
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) __builtin_nontemporal_store(scale_by_pow2(Qo[nt][v], e), &out[(size_t)p * KP + 16 * nt + r]);
+            for (int nt = 0; nt < NT; ++nt) __builtin_nontemporal_store(scale_by_pow2(Qo[nt][v], e), &out[(size_t)p * KP + 16 * nt + r]);
         }
       }
       __syncthreads();  // t, L, w_p / L_p and tip columns of every wavefront are in LDS
-      // rows 16 w .. 16 w + 15 of dlogL/dP over the 64 patterns of the tile
-      const T* tcol = sT + WT * w + r;  // column i = 16 w + r of t
+      // this wavefront's tiles of dlogL/dP over the 64 patterns of the tile
+      const T* tcol = sT + 16 * rt + r;  // column i = 16 rt + r of t
       if (Lc)
-        grad_rows_internal<T>(G, tcol, sCF, sL, g, r);
+        grad_rows_internal<NT, T>(G, tcol, sCF, sL, ct0, g, r);
       else
-        grad_rows_tip<AMB, T>(G, tcol, sCF, sCol[side], K, g, r, pr.amb);
+        grad_rows_tip<NT, AMB, T>(G, tcol, sCF, sCol[side], K, ct0, g, r, pr.amb);
     }
     __syncthreads();  // the next tile overwrites t, L, w_p / L_p and tip columns
     if (bt + 1 < n_tiles) cur = nxt;
@@ -629,10 +668,10 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void codon_pre_level_k
     const v4<T>* G = side == 0 ? Ga : Gb;
     EPOCH_GLOBAL T* dst = gptr(reinterpret_cast<T*>(pr.Gpart) + ((size_t)pr.gslots[pr.n_nodes + child] + blockIdx.x) * KK);
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt)
+    for (int c = 0; c < NCT; ++c)
 #pragma unroll
       for (int v = 0; v < 4; ++v)
-        __builtin_nontemporal_store(G[nt][v], &dst[(WT * w + drow<T>(g, v)) * KP + 16 * nt + r]);
+        __builtin_nontemporal_store(G[c][v], &dst[(16 * rt + drow<T>(g, v)) * KP + 16 * (ct0 + c) + r]);
   }
 }
 
@@ -667,9 +706,9 @@ __device__ inline void split_load_tile(SplitTileLoads& ld, const CodonProblem& p
 #pragma unroll
     for (int t = 0; t < 4; ++t) ld.L[t] = row[4 * t];
   } else {
-    tip_columns<float>(ld.col, pr.tips + (size_t)c * pr.tip_stride, P, p0, pr.K, g);
+    tip_columns<4, float>(ld.col, pr.tips + (size_t)c * pr.tip_stride, P, p0, pr.K, g);
   }
-  if (Qu) load_dlayout(ld.Q, Qu, P, p0, g, r);
+  if (Qu) load_dlayout<4, float>(ld.Q, Qu, P, p0, g, r);
 }
 
 template <bool AMB>
@@ -683,8 +722,8 @@ __global__ __launch_bounds__(512, 1) void codon_pre_split_kernel(const CodonProb
   const int u = it.y;
   const int a = pr.left[u], b = pr.right[u];
   if (base >= P) {  // uniform: this problem (or pattern chunk) has fewer tiles
-    zero_unused_slot<float>(pr, a, 512);
-    zero_unused_slot<float>(pr, b, 512);
+    zero_unused_slot<float, 4>(pr, a, 512);
+    zero_unused_slot<float, 4>(pr, b, 512);
     return;
   }
   const int n_tiles = min(R, (P - base + TILE - 1) / TILE);  // uniform over the block
@@ -693,9 +732,9 @@ __global__ __launch_bounds__(512, 1) void codon_pre_split_kernel(const CodonProb
   const int c = s ? b : a;
   {  // threads 0..255 stage P_left, 256..511 P_right
     const int h = threadIdx.x >> 8;
-    stage_matrix(sh.sP[h], pr.Pm + (size_t)(h ? b : a) * pr.pm_stride, threadIdx.x & 255);
+    stage_matrix<4>(sh.sP[h], pr.Pm + (size_t)(h ? b : a) * pr.pm_stride, threadIdx.x & 255);
     __syncthreads();
-    stage_row_sums(sh.sP[h], K, threadIdx.x & 255);
+    stage_row_sums<4>(sh.sP[h], K, threadIdx.x & 255);
     __syncthreads();
   }
   const float* sPc = sh.sP[s];
@@ -717,9 +756,9 @@ __global__ __launch_bounds__(512, 1) void codon_pre_split_kernel(const CodonProb
     const int p0 = base + bt * TILE + WT * w;
     f4 S[4];
     if (Lc)
-      child_gemm_regs(S, cur.L, sPc, g, r);
+      child_gemm_regs<4, float>(S, cur.L, sPc, g, r);
     else
-      tip_lookup<AMB>(S, cur.col, sPc, r, pr.amb);
+      tip_lookup<4, AMB, float>(S, cur.col, sPc, r, pr.amb);
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
@@ -789,9 +828,9 @@ __global__ __launch_bounds__(512, 1) void codon_pre_split_kernel(const CodonProb
     __syncthreads();  // t, L, w_p / L_p and tip columns of the whole tile are in LDS
     const float* tcol = sh.sT[s] + WT * w + r;
     if (Lc)
-      grad_rows_internal(G, tcol, sh.sCF, sh.sL[s], g, r);
+      grad_rows_internal<4, float>(G, tcol, sh.sCF, sh.sL[s], 0, g, r);
     else
-      grad_rows_tip<AMB>(G, tcol, sh.sCF, sh.sCol[s], K, g, r, pr.amb);
+      grad_rows_tip<4, AMB, float>(G, tcol, sh.sCF, sh.sCol[s], K, 0, g, r, pr.amb);
     if (bt + 1 < n_tiles) cur = nxt;
   }
   EPOCH_GLOBAL float* dst = gptr(pr.Gpart + ((size_t)pr.gslots[pr.n_nodes + c] + blockIdx.x) * KK);
@@ -803,11 +842,16 @@ __global__ __launch_bounds__(512, 1) void codon_pre_split_kernel(const CodonProb
 
 // G[v] = sum of the FP32 slot partials in FP64 (fixed order): one block per
 // (branch, 256 entries); also the block's share of <G, dP/dl>.
-constexpr int kReduceChunks = KK / 256;
-template <typename T>
+template <int NT>
+constexpr int reduce_chunks() {
+  return Dim<NT>::KK / 256;
+}
+template <typename T, int NT>
 __global__ __launch_bounds__(256) void codon_grad_reduce_kernel(const CodonProblem* __restrict__ probs,
                                                                 const int2* __restrict__ items,
                                                                 double* __restrict__ dpart, int accumulate) {
+  EPOCH_DIMS(NT);
+  constexpr int kReduceChunks = reduce_chunks<NT>();
   __shared__ double sm[256];
   const int2 it = items[blockIdx.x / kReduceChunks];
   const int chunk = blockIdx.x % kReduceChunks;
@@ -836,9 +880,11 @@ __global__ __launch_bounds__(256) void codon_grad_reduce_kernel(const CodonProbl
 // dlogL/dl of each branch from the chunk shares, in a fixed order: the sum over
 // rate categories of <G_c, dP_c/dl> (the reduce items of an instance's
 // categories are consecutive runs of n_nodes, category 0 first).
+template <int NT>
 __global__ __launch_bounds__(256) void codon_dbranch_kernel(const CodonProblem* __restrict__ probs,
                                                             const int2* __restrict__ items, int n_items,
                                                             const double* __restrict__ dpart) {
+  constexpr int kReduceChunks = reduce_chunks<NT>();
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= n_items) return;
   const int2 it = items[i];
@@ -875,18 +921,19 @@ CodonProblem codon_descriptor(const EpochInstance* in, int c, const int32_t* gsl
     return base ? reinterpret_cast<float*>(static_cast<char*>(base) + elems * in->real_size) : nullptr;
   };
   CodonProblem d{};
-  d.Pm = at(in->Pm.ptr, c * KK);
+  const size_t Kp = in->Kp, KKp = Kp * Kp;  // 64 or 32 padded states
+  d.Pm = at(in->Pm.ptr, c * KKp);
   d.tips = static_cast<const uint8_t*>(in->tips.ptr);
-  d.part = at(in->partials.ptr, c * Nm1 * P * KP);
-  d.pre = at(in->pre.ptr, c * Nm1 * P * KP);
+  d.part = at(in->partials.ptr, c * Nm1 * P * Kp);
+  d.pre = at(in->pre.ptr, c * Nm1 * P * Kp);
   d.scales = static_cast<int32_t*>(in->scales.ptr) + c * Nm1 * P;
   d.weightsT = at(in->weightsT.ptr, c * P);
   d.weights = static_cast<const double*>(in->weights.ptr);
   d.pi = static_cast<const double*>(in->pi.ptr);
   d.cat = static_cast<const double*>(in->cat.ptr);
   d.Gpart = gpart;
-  d.dPm = at(in->dPm.ptr, c * KK);
-  d.G = in->G.ptr ? static_cast<double*>(in->G.ptr) + c * KK : nullptr;
+  d.dPm = at(in->dPm.ptr, c * KKp);
+  d.G = in->G.ptr ? static_cast<double*>(in->G.ptr) + c * KKp : nullptr;
   d.dbranch = static_cast<double*>(in->dbranch.ptr);
   d.site = static_cast<double*>(in->site.ptr);
   d.blocksum = static_cast<double*>(in->blocksum.ptr);
@@ -901,7 +948,7 @@ CodonProblem codon_descriptor(const EpochInstance* in, int c, const int32_t* gsl
   d.K = in->K;
   d.root = in->plan.root;
   d.n_nodes = in->n_nodes;
-  d.pm_stride = (int)(C * KK);
+  d.pm_stride = (int)(C * KKp);
   d.cat_index = c;
   d.n_cats = (int)C;
   return d;
@@ -968,6 +1015,7 @@ void codon_build_schedule(const std::vector<const EpochInstance*>& insts, int ta
   out.amb = false;
   for (auto* in : insts) out.amb = out.amb || in->tips_amb;
   out.fp64 = !insts.empty() && insts[0]->fp64;
+  out.nt = !insts.empty() && insts[0]->Kp == 32 ? 2 : 4;
   out.n_levels = n_levels;
   out.max_tiles = max_tiles;
   out.max_pattern_blocks = max_pblocks;
@@ -975,7 +1023,7 @@ void codon_build_schedule(const std::vector<const EpochInstance*>& insts, int ta
 }
 
 namespace {
-template <typename T>
+template <typename T, int NT>
 void post_levels(const CodonSchedule& sc, const CodonProblem* d_probs, const int2* d_items, hipStream_t st) {
   for (int l = 1; l <= sc.n_levels; ++l) {
     const int b = sc.level_off[l - 1], n = sc.level_off[l] - b;
@@ -983,72 +1031,92 @@ void post_levels(const CodonSchedule& sc, const CodonProblem* d_probs, const int
     const int R = sc.level_R[l - 1];
     const int blocks = (sc.max_tiles + R - 1) / R;
     if (sc.amb)
-      hipLaunchKernelGGL((codon_post_level_kernel<T, true>), dim3(blocks, n), dim3(256), 0, st, d_probs, d_items + b, R);
+      hipLaunchKernelGGL((codon_post_level_kernel<T, NT, true>), dim3(blocks, n), dim3(256), 0, st, d_probs, d_items + b,
+                         R);
     else
-      hipLaunchKernelGGL((codon_post_level_kernel<T, false>), dim3(blocks, n), dim3(256), 0, st, d_probs, d_items + b, R);
+      hipLaunchKernelGGL((codon_post_level_kernel<T, NT, false>), dim3(blocks, n), dim3(256), 0, st, d_probs,
+                         d_items + b, R);
   }
 }
 
-// FP32: levels of at most split_blocks blocks on the side-split kernel.  FP64:
-// the level kernel throughout (the split kernel's LDS would not hold doubles).
-template <typename T>
+// 64-state FP32: levels of at most split_blocks blocks on the side-split
+// kernel.  FP64 (the split kernel's LDS would not hold doubles) and 32 states:
+// the level kernel throughout.
+template <typename T, int NT>
 void pre_levels(const CodonSchedule& sc, const CodonProblem* d_probs, const int2* d_items, hipStream_t st) {
   for (int l = sc.n_levels; l >= 1; --l) {
     const int b = sc.level_off[l - 1], n = sc.level_off[l] - b;
     if (!n) continue;
     const int R = sc.level_R[l - 1];
     const int blocks = (sc.max_tiles + R - 1) / R;
-    if (sizeof(T) == 4 && (long)blocks * n <= sc.split_blocks) {
+    if (sizeof(T) == 4 && NT == 4 && (long)blocks * n <= sc.split_blocks) {
       if (sc.amb)
         hipLaunchKernelGGL(codon_pre_split_kernel<true>, dim3(blocks, n), dim3(512), 0, st, d_probs, d_items + b, R);
       else
         hipLaunchKernelGGL(codon_pre_split_kernel<false>, dim3(blocks, n), dim3(512), 0, st, d_probs, d_items + b, R);
     } else if (sc.amb) {
-      hipLaunchKernelGGL((codon_pre_level_kernel<T, true>), dim3(blocks, n), dim3(256), 0, st, d_probs, d_items + b, R);
+      hipLaunchKernelGGL((codon_pre_level_kernel<T, NT, true>), dim3(blocks, n), dim3(256), 0, st, d_probs,
+                         d_items + b, R);
     } else {
-      hipLaunchKernelGGL((codon_pre_level_kernel<T, false>), dim3(blocks, n), dim3(256), 0, st, d_probs, d_items + b, R);
+      hipLaunchKernelGGL((codon_pre_level_kernel<T, NT, false>), dim3(blocks, n), dim3(256), 0, st, d_probs,
+                         d_items + b, R);
     }
   }
 }
+
+template <typename T, int NT>
+void root_launch(const CodonSchedule& sc, const CodonProblem* d_probs, hipStream_t st) {
+  hipLaunchKernelGGL((codon_root_kernel<T, NT>), dim3(sc.max_pattern_blocks, sc.n_problems), dim3(256), 0, st, d_probs);
+}
+
+template <typename T, int NT>
+void reduce_launch(const CodonSchedule& sc, const CodonProblem* d_probs, const int2* d_reduce_items, double* dpart,
+                   hipStream_t st, bool accumulate, bool finish) {
+  const int n_items = (int)sc.reduce_items.size();
+  hipLaunchKernelGGL((codon_grad_reduce_kernel<T, NT>), dim3((unsigned)(n_items * reduce_chunks<NT>())), dim3(256), 0,
+                     st, d_probs, d_reduce_items, dpart, accumulate ? 1 : 0);
+  if (finish)
+    hipLaunchKernelGGL(codon_dbranch_kernel<NT>, dim3((unsigned)((n_items + 255) / 256)), dim3(256), 0, st, d_probs,
+                       d_reduce_items, n_items, static_cast<const double*>(dpart));
+}
 }  // namespace
 
+// One call per compute type and padded state count (64: NT = 4, 32: NT = 2).
+#define EPOCH_CODON_DISPATCH(sc, FN, ...)      \
+  do {                                         \
+    if ((sc).fp64) {                           \
+      if ((sc).nt == 2)                        \
+        FN<double, 2>(__VA_ARGS__);            \
+      else                                     \
+        FN<double, 4>(__VA_ARGS__);            \
+    } else if ((sc).nt == 2) {                 \
+      FN<float, 2>(__VA_ARGS__);               \
+    } else {                                   \
+      FN<float, 4>(__VA_ARGS__);               \
+    }                                          \
+  } while (0)
+
 int codon_launch_post(const CodonSchedule& sc, const CodonProblem* d_probs, const int2* d_items, hipStream_t st) {
-  if (sc.fp64)
-    post_levels<double>(sc, d_probs, d_items, st);
-  else
-    post_levels<float>(sc, d_probs, d_items, st);
+  EPOCH_CODON_DISPATCH(sc, post_levels, sc, d_probs, d_items, st);
   return hip_check(hipGetLastError(), "codon_post_level launch");
 }
 
 int codon_launch_root(const CodonSchedule& sc, const CodonProblem* d_probs, hipStream_t st) {
-  if (sc.fp64)
-    hipLaunchKernelGGL(codon_root_kernel<double>, dim3(sc.max_pattern_blocks, sc.n_problems), dim3(256), 0, st, d_probs);
-  else
-    hipLaunchKernelGGL(codon_root_kernel<float>, dim3(sc.max_pattern_blocks, sc.n_problems), dim3(256), 0, st, d_probs);
+  EPOCH_CODON_DISPATCH(sc, root_launch, sc, d_probs, st);
   hipLaunchKernelGGL(codon_final_kernel, dim3(sc.n_problems), dim3(256), 0, st, d_probs);
   return hip_check(hipGetLastError(), "codon_root launch");
 }
 
-size_t codon_dpart_bytes(const CodonSchedule& sc) { return sc.reduce_items.size() * kReduceChunks * sizeof(double); }
+size_t codon_dpart_bytes(const CodonSchedule& sc) {
+  return sc.reduce_items.size() * (sc.nt == 2 ? reduce_chunks<2>() : reduce_chunks<4>()) * sizeof(double);
+}
 
 int codon_launch_pre_grad(const CodonSchedule& sc, const CodonProblem* d_probs, const int2* d_items,
                           const int2* d_reduce_items, double* dpart, hipStream_t st, bool accumulate, bool finish) {
-  if (sc.fp64)
-    pre_levels<double>(sc, d_probs, d_items, st);
-  else
-    pre_levels<float>(sc, d_probs, d_items, st);
+  EPOCH_CODON_DISPATCH(sc, pre_levels, sc, d_probs, d_items, st);
   int rc = hip_check(hipGetLastError(), "codon_pre_level launch");
   if (rc) return rc;
-  const int n_items = (int)sc.reduce_items.size();
-  if (sc.fp64)
-    hipLaunchKernelGGL(codon_grad_reduce_kernel<double>, dim3((unsigned)(n_items * kReduceChunks)), dim3(256), 0, st,
-                       d_probs, d_reduce_items, dpart, accumulate ? 1 : 0);
-  else
-    hipLaunchKernelGGL(codon_grad_reduce_kernel<float>, dim3((unsigned)(n_items * kReduceChunks)), dim3(256), 0, st,
-                       d_probs, d_reduce_items, dpart, accumulate ? 1 : 0);
-  if (finish)
-    hipLaunchKernelGGL(codon_dbranch_kernel, dim3((unsigned)((n_items + 255) / 256)), dim3(256), 0, st, d_probs,
-                       d_reduce_items, n_items, static_cast<const double*>(dpart));
+  EPOCH_CODON_DISPATCH(sc, reduce_launch, sc, d_probs, d_reduce_items, dpart, st, accumulate, finish);
   return hip_check(hipGetLastError(), "codon_grad_reduce launch");
 }
 
@@ -1065,7 +1133,7 @@ int codon_prepare(EpochInstance* in) {
   const int C = in->C;  // one problem per category (C > 1 only without pattern chunks)
   const size_t gs = gslots[0].size();
   int rc = ensure(in->gslots, C * gs * sizeof(int32_t));
-  const size_t slot_floats = (kCodonSlotBytes / sizeof(float)) * (in->fp64 ? 2 : 1);  // one slot, in floats
+  const size_t slot_floats = (size_t)in->Kp * in->Kp * (in->fp64 ? 2 : 1);  // one slot, in floats
   if (!rc && grad) rc = ensure(in->Gpart, std::max<size_t>(1, C * sc.slot_total[0]) * slot_floats * sizeof(float));
   if (!rc && grad) rc = ensure(in->codon_aux, codon_dpart_bytes(sc));
   if (rc) return rc;

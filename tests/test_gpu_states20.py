@@ -1,5 +1,5 @@
 """17- to 32-state models (a 20-state amino-acid-sized model) in FP32 with one category run on the
-64-state matrix-core kernels, padded to 64 states; against the FP64 oracle: logL, site
+matrix-core kernels, padded to 32 states; against the FP64 oracle: logL, site
 log-likelihoods, branch, rate-matrix and time gradients, ambiguous tips and incremental proposals."""
 import dataclasses
 
