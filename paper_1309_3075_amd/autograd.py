@@ -33,11 +33,13 @@ class EpochModel:
         self.lik.set_categories(prob.cat_rates, prob.cat_weights)
         self.lik.set_root_frequencies(prob.pi_root)
         self.reversible_pi = list(reversible_pi) if reversible_pi is not None else [None] * prob.n_processes
+        self.tree_set = False  # the tree is planned once; later forwards only set branch rates
         n = prob.parent.shape[0]
         self.tau = np.zeros(n)
         for v in range(n):
             if prob.parent[v] >= 0:
                 self.tau[v] = prob.height[prob.parent[v]] - prob.height[v]
+        self.branches = np.nonzero(prob.parent >= 0)[0].astype(np.int32)
 
     def branch_lengths(self) -> torch.Tensor:
         """l_v = r_v * tau_v of the generated problem (root entry 0)."""
@@ -59,7 +61,11 @@ class EpochLogLikelihood(torch.autograd.Function):
             raise ValueError("branch lengths must be positive")
         for s, Q in enumerate(Qs):
             model.lik.set_rate_matrix(s, Q.detach().cpu().double().numpy(), model.reversible_pi[s])
-        model.lik.set_tree(prob.parent, prob.height, rate, prob.boundaries, prob.interval_process)
+        if not model.tree_set:
+            model.lik.set_tree(prob.parent, prob.height, rate, prob.boundaries, prob.interval_process)
+            model.tree_set = True
+        else:
+            model.lik.set_branch_rates(model.branches, rate[model.branches])
         # The library instance is shared by every forward on this model, so the gradients of
         # this forward are formed now (one evaluation, one host synchronisation) and kept with
         # its context: a later forward cannot overwrite them before this backward runs.

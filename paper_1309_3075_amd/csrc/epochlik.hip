@@ -217,6 +217,41 @@ void invalidate_downstream(EpochInstance* in) {
   in->logL_valid = false;
 }
 
+// Host-to-device copies of one set_epoch_eigensystems call, staged in the
+// instance's pinned host buffer and enqueued on its stream without waiting; the
+// next call waits for them (stage_event) before it reuses the buffer.
+struct EigStage {
+  EpochInstance* in;
+  size_t off = 0;
+  int rc = EPOCH_OK;
+  template <typename D>
+  void put(void* dst, const double* src, size_t n) {  // n doubles, copied as D
+    if (rc) return;
+    off = (off + 15) / 16 * 16;
+    D* h = reinterpret_cast<D*>(static_cast<char*>(in->stage_host) + off);
+    for (size_t i = 0; i < n; ++i) h[i] = (D)src[i];
+    rc = hip_check(hipMemcpyAsync(dst, h, n * sizeof(D), hipMemcpyHostToDevice, in->stream), "eigensystem upload");
+    off += n * sizeof(D);
+  }
+};
+int stage_reserve(EpochInstance* in, size_t bytes) {
+  if (in->stage_pending) {
+    EPOCH_TRY(hip_check(hipEventSynchronize(in->stage_event), "eigensystem staging wait"));
+    in->stage_pending = false;
+  }
+  if (!in->stage_event) EPOCH_TRY(hip_check(hipEventCreateWithFlags(&in->stage_event, hipEventDisableTiming), "staging event"));
+  if (in->stage_bytes >= bytes) return EPOCH_OK;
+  if (in->stage_host) (void)hipHostFree(in->stage_host);
+  in->stage_host = nullptr;
+  in->stage_bytes = 0;
+  if (hipHostMalloc(&in->stage_host, bytes, hipHostMallocDefault) != hipSuccess) {
+    in->stage_host = nullptr;
+    return set_error(EPOCH_ERR_OOM, "pinned staging buffer of %zu bytes", bytes);
+  }
+  in->stage_bytes = bytes;
+  return EPOCH_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -426,6 +461,9 @@ int epoch_get_timing(EpochInstance* in, double* ms_out, int64_t* counts_out) {
 
 int epoch_destroy(EpochInstance* in) {
   if (!in) return EPOCH_OK;
+  if (in->stage_pending) (void)hipEventSynchronize(in->stage_event);  // staged copies still in flight
+  if (in->stage_event) (void)hipEventDestroy(in->stage_event);
+  if (in->stage_host) (void)hipHostFree(in->stage_host);
   for (int k = 0; k < EPOCH_N_PHASES; ++k)
     for (int j = 0; j < 2; ++j)
       if (in->ev[k][j]) (void)hipEventDestroy(in->ev[k][j]);
@@ -632,28 +670,29 @@ int set_epoch_eigensystems(EpochInstance* in, int32_t s, const double* V, const 
     if (choose_eig_precision(in) || !in->have_eig[s]) mark_dirty_all(in);
     else mark_dirty_process(in, s);
   }
-  // upload this process's slices in double and in the compute type
-  auto up_slice = [&](DevBuf& buf, size_t elem, bool as_float) -> int {
+  // this process's slices in double and in the compute type, and the transposed
+  // copies (rows of V^T and V^-T feed the adjoint chain), staged in pinned host
+  // memory and copied without waiting
+  const size_t R = in->real_size;
+  const size_t need = (2 * KK + 2 * Kp) * (8 + R) + 2 * KK * (8 + R) + (size_t)K * K * 8 + 16 * 16;
+  EPOCH_TRY(stage_reserve(in, need));
+  EigStage st{in};
+  auto slice = [&](DevBuf& buf, bool as_float) {
+    const size_t es = as_float ? sizeof(float) : sizeof(double);
     char* base = static_cast<char*>(buf.ptr);
-    struct Part {
-      size_t off, count;
-      const double* src;
-    } parts[4] = {{s * KK, KK, hV}, {S * KK + s * KK, KK, hVi}, {2 * S * KK + (size_t)s * Kp, (size_t)Kp, hr},
-                  {2 * S * KK + S * Kp + (size_t)s * Kp, (size_t)Kp, hi}};
-    for (auto& pt : parts) {
-      if (as_float) {
-        std::vector<float> f(pt.src, pt.src + pt.count);
-        EPOCH_TRY(upload(in, base + pt.off * elem, f.data(), pt.count * sizeof(float)));
-      } else {
-        EPOCH_TRY(upload(in, base + pt.off * elem, pt.src, pt.count * sizeof(double)));
-      }
+    const double* src[4] = {hV, hVi, hr, hi};
+    const size_t off[4] = {s * KK, S * KK + s * KK, 2 * S * KK + (size_t)s * Kp, 2 * S * KK + S * Kp + (size_t)s * Kp};
+    const size_t cnt[4] = {KK, KK, (size_t)Kp, (size_t)Kp};
+    for (int k = 0; k < 4; ++k) {
+      if (as_float)
+        st.put<float>(base + off[k] * es, src[k], cnt[k]);
+      else
+        st.put<double>(base + off[k] * es, src[k], cnt[k]);
     }
-    return EPOCH_OK;
   };
-  EPOCH_TRY(up_slice(in->eig64, sizeof(double), false));
-  EPOCH_TRY(up_slice(in->eigT, in->real_size, !in->fp64));
+  slice(in->eig64, false);
+  slice(in->eigT, !in->fp64);
   {
-    // transposed copies: rows of V^T and V^-T feed the adjoint chain
     std::vector<double> tV(KK), tVi(KK);
     for (int i = 0; i < Kp; ++i)
       for (int j = 0; j < Kp; ++j) {
@@ -661,25 +700,27 @@ int set_epoch_eigensystems(EpochInstance* in, int32_t s, const double* V, const 
         tVi[(size_t)j * Kp + i] = hVi[(size_t)i * Kp + j];
       }
     char* b64 = static_cast<char*>(in->eig64T.ptr);
-    EPOCH_TRY(upload(in, b64 + s * KK * sizeof(double), tV.data(), KK * sizeof(double)));
-    EPOCH_TRY(upload(in, b64 + (S * KK + s * KK) * sizeof(double), tVi.data(), KK * sizeof(double)));
+    st.put<double>(b64 + s * KK * sizeof(double), tV.data(), KK);
+    st.put<double>(b64 + (S * KK + s * KK) * sizeof(double), tVi.data(), KK);
     char* bT = static_cast<char*>(in->eigTT.ptr);
     if (in->fp64) {
-      EPOCH_TRY(upload(in, bT + s * KK * 8, tV.data(), KK * 8));
-      EPOCH_TRY(upload(in, bT + (S * KK + s * KK) * 8, tVi.data(), KK * 8));
+      st.put<double>(bT + s * KK * 8, tV.data(), KK);
+      st.put<double>(bT + (S * KK + s * KK) * 8, tVi.data(), KK);
     } else {
-      std::vector<float> fV(tV.begin(), tV.end()), fVi(tVi.begin(), tVi.end());
-      EPOCH_TRY(upload(in, bT + s * KK * 4, fV.data(), KK * 4));
-      EPOCH_TRY(upload(in, bT + (S * KK + s * KK) * 4, fVi.data(), KK * 4));
+      st.put<float>(bT + s * KK * 4, tV.data(), KK);
+      st.put<float>(bT + (S * KK + s * KK) * 4, tVi.data(), KK);
     }
   }
+  double* dQ = static_cast<double*>(in->check.ptr);
+  if (Q) st.put<double>(dQ, Q, (size_t)K * K);
+  EPOCH_TRY(st.rc);
+  EPOCH_TRY(hip_check(hipEventRecord(in->stage_event, in->stream), "eigensystem upload event"));
+  in->stage_pending = true;
   in->have_eig[s] = 1;
   invalidate_downstream(in);
   int ret = EPOCH_OK;
   if (Q) {
-    double* dQ = static_cast<double*>(in->check.ptr);
     double* dout = dQ + (size_t)Kp * Kp;
-    EPOCH_TRY(upload(in, dQ, Q, (size_t)K * K * sizeof(double)));
     EPOCH_TRY(launch_eigen_check(in, s, dQ, dout));
     double res = 0.0;
     EPOCH_TRY(download(in, &res, dout, sizeof(res)));

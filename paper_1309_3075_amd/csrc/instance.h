@@ -228,6 +228,11 @@ struct EpochInstance {
   // per-phase timing (epoch_set_timing)
   bool timing = false;
   hipEvent_t ev[EPOCH_N_PHASES][2] = {};
+  // pinned staging of set_epoch_eigensystems' copies (enqueued without waiting)
+  void* stage_host = nullptr;
+  size_t stage_bytes = 0;
+  hipEvent_t stage_event = nullptr;
+  bool stage_pending = false;
   bool ev_pending[EPOCH_N_PHASES] = {};
   double phase_ms[EPOCH_N_PHASES] = {};
   int64_t phase_count[EPOCH_N_PHASES] = {};
