@@ -334,6 +334,57 @@ def proposal_leg(prob, steps, use_pi=True):
     return out
 
 
+def rate_matrix_step_leg(prob, steps):
+    """Steps whose rate matrices change on every call, as in gradient-based fitting of the
+    substitution model: (a) every process's Q handed to an FP32 instance (host eigendecomposition,
+    asynchronous upload) followed by one evaluation with branch and rate-matrix gradients, with and
+    without the reconstruction-residual check; (b) the torch.autograd step: GY94 Q_s(kappa, omega_s)
+    built in torch, forward through the library, backward to kappa, omega_s and the branch lengths."""
+    import torch
+    from paper_1309_3075_amd.autograd import EpochLogLikelihood, EpochModel, gy94_q
+    from paper_1309_3075_amd.eigen import eigensystem
+    from paper_1309_3075_amd.likelihood import from_problem
+    out = {}
+    with from_problem(prob, "fp32", grad_branch=True, grad_Q=True) as lik:
+        lik.set_option("incremental", 0)
+        for check in (True, False):
+            for k in range(steps + 2):
+                if k == 2:
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                for s, Q in enumerate(prob.Q):
+                    lik.set_rate_matrix(s, Q * (1 + 1e-6 * (k % 3)), prob.pi_process[s], check_residual=check)
+                lik.evaluate(branch=True, Q=True)
+            torch.cuda.synchronize()
+            out["set_Q_then_eval_ms" + ("_residual_check" if check else "")] = \
+                round((time.perf_counter() - t0) * 1e3 / steps, 4)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for s, Q in enumerate(prob.Q):
+            eigensystem(Q, prob.pi_process[s])
+    out["host_eigendecompositions_ms"] = round((time.perf_counter() - t0) * 1e3 / steps, 4)
+    model = EpochModel(prob, "fp32", reversible_pi=prob.pi_process)
+    try:
+        pi = torch.tensor(prob.pi_process[0])
+        kappa = torch.tensor(2.0, dtype=torch.float64, requires_grad=True)
+        omegas = [torch.tensor(0.3 + 0.1 * s, dtype=torch.float64, requires_grad=True)
+                  for s in range(prob.n_processes)]
+        ell = model.branch_lengths().requires_grad_(True)
+        for k in range(steps + 2):
+            if k == 2:
+                t0 = time.perf_counter()
+            with torch.no_grad():
+                kappa.add_(0.01 if k % 2 else -0.01)
+            EpochLogLikelihood.apply(model, ell, *[gy94_q(kappa, om, pi) for om in omegas]).backward()
+        torch.cuda.synchronize()
+        out["autograd_step_ms"] = round((time.perf_counter() - t0) * 1e3 / steps, 4)
+    finally:
+        model.close()
+    out["what"] = (f"{prob.n_processes} rate matrices changed per step; FP32 instance; the host part is "
+                   "numpy's eigendecomposition of each Q")
+    return out
+
+
 def precision_leg(prob, config, steps, want_grad, want_Q, use_pi, parity):
     """The other arithmetics of the same workload, each with its parity against the oracle on the
     CPU-baseline sample when one was drawn: the transition matrices and dlogL/dQ chains of the FP32
@@ -378,6 +429,7 @@ def run_codon_leg(steps, warmup, with_parity):
     with from_problem(prob, "fp64", grad_branch=True, grad_Q=True, kernel="generic") as lg:
         eg, msg, _, _ = time_instance(lg, 3, 1, True, True)
     proposals = proposal_leg(prob, 4 * steps)
+    q_steps = rate_matrix_step_leg(prob, steps)
     aflops = algorithmic_flops(prob)
     total = sum(aflops.values())
     leg = {"workload": WORKLOADS[3], "evals_per_s": round(eps, 2), "ms_per_eval": round(ms, 4),
@@ -389,7 +441,7 @@ def run_codon_leg(steps, warmup, with_parity):
                     "generic_fp64_evals_per_s": round(eg, 2), "generic_fp64_ms_per_eval": round(msg, 4),
                     "speedup_fp32_over_fp64": round(eps / e64, 3),
                     "speedup_fp32_over_generic_fp64": round(eps / eg, 3)},
-           "one_branch_proposals": proposals}
+           "one_branch_proposals": proposals, "rate_matrix_steps": q_steps}
     if with_parity:
         sub = pattern_subset(prob, 1000)
         ref_logL, ref_b, ref_q, _ = oracle_timed(sub, True, True, host_threads())

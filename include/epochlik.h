@@ -259,9 +259,9 @@ int epoch_evaluate(EpochInstance* inst, uint32_t what, double* logL, double* sit
                    double* d_Q);
 
 /* Kernel family the instance runs (fixed at creation): *out = 0 generic any-K
- * kernels, 1 the 4-state kernels, 2 the matrix-core kernels of padded 64-state
- * problems (49..64 states, and 17..32 states padded to 64; FP32 or FP64; any
- * number of rate categories; under an HBM budget FP32 with one category). */
+ * kernels, 1 the 4-state kernels, 2 the matrix-core kernels (49..64 states
+ * padded to 64, and 17..32 states padded to 32; FP32 or FP64; any number of
+ * rate categories; under an HBM budget FP32 with one category). */
 int epoch_get_kernel_path(EpochInstance* inst, int32_t* out);
 
 /* Read back the transition matrices: host [2N-1][C][K][K] doubles (row-major,

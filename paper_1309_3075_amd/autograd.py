@@ -10,6 +10,7 @@ parameters with differentiable torch code (see ``gy94_q``, ``hky_q``,
 """
 from __future__ import annotations
 
+import functools
 from typing import List, Optional, Sequence
 
 import numpy as np
@@ -114,7 +115,10 @@ def gtr_q(exch: torch.Tensor, pi: torch.Tensor) -> torch.Tensor:
     return _normalise(R * pi[None, :], pi)
 
 
-def gy94_q(kappa: torch.Tensor, omega: torch.Tensor, pi_codon: torch.Tensor) -> torch.Tensor:
+@functools.lru_cache(maxsize=1)
+def _gy94_masks():
+    """Sense-codon pairs one nucleotide apart, and which of those are transitions and which change
+    the amino acid (universal code): fixed by the genetic code, so built once."""
     codons, aas = W.sense_codons()
     K = len(codons)
     single = np.zeros((K, K), bool)
@@ -128,8 +132,10 @@ def gy94_q(kappa: torch.Tensor, omega: torch.Tensor, pi_codon: torch.Tensor) -> 
                 p = diff[0]
                 trans[i, j] = W._IS_TRANSITION[codons[i][p], codons[j][p]]
                 nonsyn[i, j] = aas[i] != aas[j]
-    S = torch.tensor(single, dtype=torch.float64)
-    Tm = torch.tensor(trans, dtype=torch.float64)
-    Nm = torch.tensor(nonsyn, dtype=torch.float64)
+    return tuple(torch.tensor(m, dtype=torch.float64) for m in (single, trans, nonsyn))
+
+
+def gy94_q(kappa: torch.Tensor, omega: torch.Tensor, pi_codon: torch.Tensor) -> torch.Tensor:
+    S, Tm, Nm = _gy94_masks()
     R = S * (1.0 + Tm * (kappa - 1.0)) * (1.0 + Nm * (omega - 1.0))
     return _normalise(R * pi_codon[None, :], pi_codon)

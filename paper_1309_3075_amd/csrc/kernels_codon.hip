@@ -1,21 +1,23 @@
-// 64-state (codon) kernels on FP32 matrix cores (v_mfma_f32_16x16x4f32).
+// Codon-sized (and amino-acid-sized) kernels on the matrix cores: FP32
+// (v_mfma_f32_16x16x4f32) and FP64 (v_mfma_f64_16x16x4f64).
 //
-// Applies to FP32 instances with 48 < K <= 64 or 16 < K <= 32 (padded to 64).
-// Each rate category is a problem of its own (a descriptor of its own): its
-// partials / outside vectors [slot][P][64] and scale exponents [slot][P] are
-// the category's region of the instance's buffers, its transition matrices
-// every C-th 64 x 64 row-major block of [node][category]; the root reduction
-// combines the categories.
+// Applies to instances with 48 < K <= 64 (padded to KP = 64, NT = 4 tiles of
+// 16 states) or 16 < K <= 32 (padded to KP = 32, NT = 2).  Each rate category
+// is a problem of its own (a descriptor of its own): its partials / outside
+// vectors [slot][P][KP] and scale exponents [slot][P] are the category's
+// region of the instance's buffers, its transition matrices every C-th KP x KP
+// row-major block of [node][category]; the root reduction combines the
+// categories.
 //
 // MFMA operand mapping (16x16x4, wavefront of 64 lanes, g = lane / 16,
 // r = lane % 16):  A[m][k]: m = r, k = g;  B[k][n]: k = g, n = r;
-// D[m][n] (4 registers v): m = 4 g + v, n = r.
+// D[m][n] (4 registers v): FP32 m = 4 g + v, FP64 m = 4 v + g; n = r.
 //
 // Work split.  A block takes one internal node and R tiles of 64 patterns;
 // it stages the two child transition matrices in LDS (row sums in the
 // padding column, so a missing tip state is one more column), and each of
 // its four wavefronts then works alone on 16-pattern tiles: D-layout
-// registers hold pattern 4 g + v, state 16 nt + r of each 16x16 block nt.
+// registers hold pattern drow(g, v), state 16 nt + r of each 16x16 block nt.
 //   child vectors   S = L P^T     A = child partial rows (16-byte loads), B = P rows (LDS)
 //   post-order      x = S_a o S_b, per-pattern power-of-two scale (row reduction by DPP)
 //   dlogL/dP        G += sum_p (w_p / L_p) t_p L_p^T, contraction over the 16
