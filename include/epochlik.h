@@ -400,9 +400,11 @@ int epoch_batch_destroy(EpochBatch* batch);
 
 /* Attainable HBM bandwidth on the current device: a plain stream over a
  * library-allocated buffer of `bytes` (1 MiB .. 64 GiB), repeated `iters`
- * times on the default stream and timed with HIP events.  kind: 0 = copy
- * (counts read + write bytes), 1 = read-only, 2 = write-only.  *gbs receives
- * GB/s (1e9 bytes per second).  Allocates and frees its own buffers. */
+ * times on the default stream and timed with HIP events, for each of eight
+ * launch shapes (grid-stride or block-contiguous ranges, 1,024 to 65,536
+ * blocks); *gbs receives the best rate in GB/s (1e9 bytes per second).
+ * kind: 0 = copy (counts read + write bytes), 1 = read-only, 2 = write-only.
+ * Allocates and frees its own buffers. */
 int epoch_bandwidth_probe(int64_t bytes, int32_t kind, int32_t iters, double* gbs);
 
 /* For callers that cannot allocate device memory (code under HIP graph capture,
