@@ -170,7 +170,10 @@ int epoch_set_root_frequencies(EpochInstance* inst, const double* pi);
  *   Q: host K x K or NULL.  If given, an FP64 device kernel measures
  *   max|V B V^-1 - Q| / max|Q| and max|V V^-1 - I|; the larger is written to
  *   *residual_out (if not NULL) and EPOCH_WARN_EIGEN_RESIDUAL is returned when
- *   it exceeds 1e-8.  Invalidates transition matrices. */
+ *   it exceeds 1e-8; the call then waits for the check.  Without Q it does not
+ *   wait: the host arrays are converted into a library-owned pinned staging
+ *   buffer and uploaded asynchronously on the instance's stream (they may be
+ *   reused as soon as the call returns).  Invalidates transition matrices. */
 int set_epoch_eigensystems(EpochInstance* inst, int32_t s, const double* V, const double* Vinv,
                            const double* lambda_re, const double* lambda_im, const double* Q,
                            double* residual_out);
