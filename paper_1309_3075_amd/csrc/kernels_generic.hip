@@ -175,6 +175,40 @@ __device__ inline uint64_t tip_set(int st, int K, const uint64_t* __restrict__ a
   return amb[st - K - 1];
 }
 
+// sum_j M[j * stride] * v[j] over j < n, summed in order of j, with the loads of
+// up to 16 terms issued together (the matrix entries are mostly not in cache, so
+// one load per step would pay the memory latency n times).
+template <typename T>
+__device__ inline T dot_strided(const T* __restrict__ M, size_t stride, const T* v, int n) {
+  T r = 0;
+  int j = 0;
+  for (; j + 16 <= n; j += 16) {
+    T m[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) m[k] = M[(size_t)(j + k) * stride];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) r += m[k] * v[j + k];
+  }
+  if (j + 8 <= n) {
+    T m[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) m[k] = M[(size_t)(j + k) * stride];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) r += m[k] * v[j + k];
+    j += 8;
+  }
+  if (j + 4 <= n) {
+    T m[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) m[k] = M[(size_t)(j + k) * stride];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r += m[k] * v[j + k];
+    j += 4;
+  }
+  for (; j < n; ++j) r += M[(size_t)j * stride] * v[j];
+  return r;
+}
+
 template <typename T>
 __device__ inline T child_vector(int child, int N, int p, int tstride, int K, int Kp, int i, const T* Prow,
                                  const uint8_t* tips, const uint64_t* amb, const T* sL) {
@@ -189,9 +223,7 @@ __device__ inline T child_vector(int child, int N, int p, int tstride, int K, in
       if ((set >> j) & 1) r += Prow[j];
     return r;
   }
-  T r = 0;
-  for (int j = 0; j < K; ++j) r += Prow[j] * sL[j];
-  return r;
+  return dot_strided(Prow, 1, sL, K);
 }
 
 template <typename T, int KQ>
@@ -326,12 +358,8 @@ __global__ __launch_bounds__(256) void pre_level_generic_kernel(
     __syncthreads();
     T ra = 0, rb = 0;
     if (pok && i < K) {
-      const T* Pa = Pm + ((size_t)a * C + c) * KK;
-      const T* Pb = Pm + ((size_t)b * C + c) * KK;
-      for (int r = 0; r < K; ++r) {
-        ra += Pa[(size_t)r * Kp + i] * sTa[pl * KQ + r];
-        rb += Pb[(size_t)r * Kp + i] * sTb[pl * KQ + r];
-      }
+      ra = dot_strided(Pm + ((size_t)a * C + c) * KK + i, (size_t)Kp, sTa + pl * KQ, K);
+      rb = dot_strided(Pm + ((size_t)b * C + c) * KK + i, (size_t)Kp, sTb + pl * KQ, K);
     }
     qa[c] = ra;
     qb[c] = rb;
