@@ -713,7 +713,10 @@ int set_epoch_eigensystems(EpochInstance* in, int32_t s, const double* V, const 
   }
   double* dQ = static_cast<double*>(in->check.ptr);
   if (Q) st.put<double>(dQ, Q, (size_t)K * K);
-  EPOCH_TRY(st.rc);
+  if (st.rc) {  // copies enqueued before the failure may still read the staging buffer
+    (void)hipStreamSynchronize(in->stream);
+    return st.rc;
+  }
   EPOCH_TRY(hip_check(hipEventRecord(in->stage_event, in->stream), "eigensystem upload event"));
   in->stage_pending = true;
   in->have_eig[s] = 1;
