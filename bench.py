@@ -581,7 +581,13 @@ def main():
     result["measured_hbm_GBps"] = probe
     if roof["unit"] == "GB/s":
         roof["frac_of_measured_copy"] = round(roof["achieved"] / probe["copy"], 4)
-    result["algorithmic_flops_per_eval"] = algorithmic_flops(prob)
+    aflops = algorithmic_flops(prob)
+    result["algorithmic_flops_per_eval"] = aflops
+    # the metric's "partials GFLOP/s": algorithmic flops of the post-order pass (partials) and of the pre-order
+    # pass with dlogL/dP, each over its own device time
+    result["partials_GFLOP_per_s"] = {
+        k: round(aflops[k] / (phases[k][0] / args.steps * 1e-3) / 1e9, 1)
+        for k in ("post_order", "pre_order_dP") if k in phases and phases[k][0] > 0}
     log(f"bench: bandwidth probe {probe}")
 
     sample = None
