@@ -54,6 +54,12 @@ struct EpochBatch {
   hipGraphExec_t exec[8] = {};
   bool tuned = false;
   bool own_stream = false;
+  // branch streams of the captured graph: members whose launches are their own (not the
+  // merged levels) run on kBatchBranches streams forked from and joined back to `stream`
+  static constexpr int kBatchBranches = 4;
+  hipStream_t branch[kBatchBranches] = {};
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[kBatchBranches] = {};
 };
 
 namespace {
@@ -165,6 +171,48 @@ int build_schedule(EpochBatch* b) {
   return hip_check(hipMemcpy(b->dev.ptr, h.data(), bytes, hipMemcpyHostToDevice), "batch schedule upload");
 }
 
+int ensure_branches(EpochBatch* b) {
+  for (int k = 0; k < EpochBatch::kBatchBranches; ++k) {
+    if (!b->branch[k] && hipStreamCreateWithFlags(&b->branch[k], hipStreamNonBlocking) != hipSuccess) {
+      b->branch[k] = nullptr;
+      return set_error(EPOCH_ERR_HIP, "batch branch stream creation failed");
+    }
+    if (!b->join_ev[k] && hipEventCreateWithFlags(&b->join_ev[k], hipEventDisableTiming) != hipSuccess) {
+      b->join_ev[k] = nullptr;
+      return set_error(EPOCH_ERR_HIP, "batch event creation failed");
+    }
+  }
+  if (!b->fork_ev && hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming) != hipSuccess) {
+    b->fork_ev = nullptr;
+    return set_error(EPOCH_ERR_HIP, "batch event creation failed");
+  }
+  return EPOCH_OK;
+}
+
+// fn(q) for every member q in qs, member i of the list on branch stream i mod kBatchBranches (its
+// launches go to in->stream), after everything already on b->stream; b->stream then waits for
+// every branch.  Members touch only their own buffers, so the branches are independent.
+template <typename F>
+int fork_join(EpochBatch* b, const std::vector<size_t>& qs, F fn) {
+  if (qs.empty()) return EPOCH_OK;
+  const int K = (int)std::min<size_t>(EpochBatch::kBatchBranches, qs.size());
+  int rc = hip_check(hipEventRecord(b->fork_ev, b->stream), "batch fork");
+  for (int k = 0; k < K && !rc; ++k) rc = hip_check(hipStreamWaitEvent(b->branch[k], b->fork_ev, 0), "batch fork");
+  for (size_t i = 0; i < qs.size() && !rc; ++i) {
+    EpochInstance* in = b->insts[qs[i]];
+    const hipStream_t own = in->stream;
+    in->stream = b->branch[i % K];
+    rc = fn(qs[i]);
+    in->stream = own;
+  }
+  for (int k = 0; k < K; ++k) {  // join every forked branch, also after a failure (a capture must end joined)
+    int r = hip_check(hipEventRecord(b->join_ev[k], b->branch[k]), "batch join");
+    if (!r) r = hip_check(hipStreamWaitEvent(b->stream, b->join_ev[k], 0), "batch join");
+    if (!rc) rc = r;
+  }
+  return rc;
+}
+
 // Enqueue one evaluation of every member on b->stream (no host synchronisation).
 int enqueue(EpochBatch* b, uint32_t what, const double* const* d_result_ptrs) {
   const size_t n = b->insts.size();
@@ -174,9 +222,33 @@ int enqueue(EpochBatch* b, uint32_t what, const double* const* d_result_ptrs) {
     if (rc) return rc;
     for (size_t q : g.members) b->insts[q]->pstage_split = false;  // whole chains: the dQ chains follow suit
   }
-  for (size_t q : b->p_single) {
-    int rc = launch_pstage(b->insts[q]);
-    if (!rc) rc = fastpath_after_pstage(b->insts[q]);
+  const bool grad = (what & (kGradBranch | kGradQ)) != 0;
+  if (!b->merged) {
+    // every member on its own: P stage (unless its group ran above), partials, root and gradient
+    // on one branch, the members spread over the branches
+    std::vector<bool> single(n, false);
+    for (size_t q : b->p_single) single[q] = true;
+    std::vector<size_t> all(n);
+    for (size_t q = 0; q < n; ++q) all[q] = q;
+    int rc = fork_join(b, all, [&](size_t q) {
+      EpochInstance* in = b->insts[q];
+      int r = single[q] ? launch_pstage(in) : EPOCH_OK;
+      if (!r && single[q]) r = fastpath_after_pstage(in);
+      if (!r) r = fastpath_post(in);
+      if (!r) r = fastpath_root(in);
+      if (!r && grad) r = fastpath_gradient(in, (what & kGradQ) != 0);
+      return r;
+    });
+    if (rc) return rc;
+    hipLaunchKernelGGL(gather_results, dim3(1), dim3(64), 0, b->stream, d_result_ptrs, (int)n,
+                       static_cast<double*>(b->results.ptr));
+    return hip_check(hipGetLastError(), "batch gather launch");
+  }
+  {
+    int rc = fork_join(b, b->p_single, [&](size_t q) {
+      int r = launch_pstage(b->insts[q]);
+      return r ? r : fastpath_after_pstage(b->insts[q]);
+    });
     if (rc) return rc;
   }
   if (b->merged && (what & (kGradBranch | kGradQ))) {
@@ -196,19 +268,13 @@ int enqueue(EpochBatch* b, uint32_t what, const double* const* d_result_ptrs) {
     if (!rc) rc = codon_launch_root(b->sched, probs, b->stream);
     if (!rc && (what & (kGradBranch | kGradQ))) rc = codon_launch_pre_grad(b->sched, probs, items, red, static_cast<double*>(b->dpart.ptr), b->stream, false, true);
     if (rc) return rc;
-  } else {
-    for (auto* in : b->insts) {
-      int rc = fastpath_post(in);
-      if (!rc) rc = fastpath_root(in);
-      if (!rc && (what & (kGradBranch | kGradQ))) rc = fastpath_gradient(in, (what & kGradQ) != 0);
-      if (rc) return rc;
-    }
   }
-  if (b->merged && (what & kGradQ))
-    for (auto* in : b->insts) {
-      int rc = launch_grad_Q(in);
-      if (rc) return rc;
-    }
+  if (what & kGradQ) {  // dlogL/dQ of each member, on the branches
+    std::vector<size_t> all(n);
+    for (size_t q = 0; q < n; ++q) all[q] = q;
+    int rc = fork_join(b, all, [&](size_t q) { return launch_grad_Q(b->insts[q]); });
+    if (rc) return rc;
+  }
   hipLaunchKernelGGL(gather_results, dim3(1), dim3(64), 0, b->stream, d_result_ptrs, (int)n,
                      static_cast<double*>(b->results.ptr));
   return hip_check(hipGetLastError(), "batch gather launch");
@@ -248,6 +314,8 @@ int capture(EpochBatch* b, uint32_t what) {
     b->insts[q]->stream = b->stream;
     b->insts[q]->timing = false;
   }
+  rc = ensure_branches(b);
+  if (rc) return rc;
   rc = hip_check(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "begin capture");
   if (!rc) {
     int erc = enqueue(b, what, d_ptrs);
@@ -533,6 +601,11 @@ int epoch_batch_destroy(EpochBatch* b) {
   release_buf(b->pdescs);
   release_buf(b->results);
   for (auto& g : b->gslots) release_buf(g);
+  for (int k = 0; k < EpochBatch::kBatchBranches; ++k) {
+    if (b->branch[k]) (void)hipStreamDestroy(b->branch[k]);
+    if (b->join_ev[k]) (void)hipEventDestroy(b->join_ev[k]);
+  }
+  if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
   if (b->own_stream) (void)hipStreamDestroy(b->stream);
   delete b;
   return EPOCH_OK;
