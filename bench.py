@@ -490,6 +490,44 @@ def run_batch_leg(n, scale, steps, warmup, precision="fp32", grad_q=False, tune=
     return leg
 
 
+def run_nuc_batch_leg(n, steps):
+    """Batch of small 4-state problems (16-64 taxa, 300-3,000 patterns, FP32, branch gradients): each member
+    runs its own launches, spread over concurrent branches of one replayed graph; timed against the same
+    members evaluated one after another."""
+    import torch
+    from paper_1309_3075_amd import workloads as W
+    from paper_1309_3075_amd.likelihood import EpochBatchEvaluator, from_problem
+    rng = np.random.default_rng(5)
+    probs = [W.make_config(1, replicate=i, n_tips=int(rng.integers(16, 65)), n_patterns=int(rng.integers(300, 3001)))
+             for i in range(n)]
+    members = [from_problem(p, "fp32", grad_branch=True) for p in probs]
+    try:
+        for m in members:
+            m.evaluate(branch=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            for m in members:
+                m.evaluate(branch=True)
+        torch.cuda.synchronize()
+        serial = n * steps / (time.perf_counter() - t0)
+        batch = EpochBatchEvaluator(members)
+        batch.evaluate(grad_branch=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            batch.evaluate(grad_branch=True)
+        wall = time.perf_counter() - t0
+        batch.close()
+    finally:
+        for m in members:
+            m.close()
+    return {"workload": f"{n} small 4-state problems (C1 model, 16-64 taxa, 300-3000 patterns), FP32, logL + branch "
+                        "gradients, one replayed hipGraph per step",
+            "problems_per_s": round(n * steps / wall, 1), "ms_per_batch": round(wall * 1000 / steps, 4),
+            "serial_single_instances_problems_per_s": round(serial, 1)}
+
+
 def run_batch(args):
     leg = run_batch_leg(args.batch or 64, args.batch_scale, args.steps, args.warmup, args.precision, args.grad_q,
                         os.path.join(ROOT, "paper_1309_3075_amd", "tune_cache.json"))
@@ -628,6 +666,8 @@ def main():
         log("bench: batched codon leg ...")
         result["batch_C5"] = run_batch_leg(64, 1.0, max(3, args.steps // 4), 1,
                                            tune=os.path.join(ROOT, "paper_1309_3075_amd", "tune_cache.json"))
+        log("bench: batched small 4-state leg ...")
+        result["batch_small_nucleotide"] = run_nuc_batch_leg(64, max(5, args.steps))
     print(json.dumps(result), flush=True)
 
 

@@ -75,6 +75,40 @@ def test_nucleotide_batch_unmerged_path():
         m.close()
 
 
+def test_members_on_concurrent_branches_match_single_evaluations():
+    """Members that run their own launches are captured on four concurrent branches: eleven members
+    of three kernel families (4-state walk and level kernels, generic 20-state with dlogL/dQ, a
+    40-state member) give the bits of their single evaluations, on every replay."""
+    rng = np.random.default_rng(77)
+    probs, opts = [], []
+    for r in range(6):
+        probs.append(W.make_config(1, replicate=r, n_tips=int(rng.integers(10, 40)), n_patterns=int(rng.integers(50, 900))))
+        opts.append({"tree_walk": r % 2})
+    for r in range(4):
+        probs.append(W.random_problem(np.random.default_rng(300 + r), 12 + r, 20, 40 + 10 * r, n_categories=2,
+                                      n_intervals=3, reversible=True))
+        opts.append({})
+    probs.append(W.make_config(4, n_tips=40))
+    opts.append({})
+    members = [from_problem(p, "fp32", grad_branch=True, grad_Q=True, kernel="auto" if i < 6 else "generic",
+                            use_pi=i < 10, options=o) for i, (p, o) in enumerate(zip(probs, opts))]
+    try:
+        single = [m.evaluate(branch=True, Q=True) for m in members]
+        batch = EpochBatchEvaluator(members)
+        for _ in range(3):
+            logL = batch.evaluate(grad_branch=True, grad_Q=True)
+            for i in range(len(members)):
+                assert logL[i] == single[i][0], i
+                db, dq = batch.gradients(i, branch=True, Q=True)
+                assert np.array_equal(db, single[i][2]) and np.array_equal(dq, single[i][3]), i
+        for i in (0, 7, 10):
+            assert rel(logL[i], O.log_likelihood(probs[i])) <= TOL_LOGL["fp32"], i
+        batch.close()
+    finally:
+        for m in members:
+            m.close()
+
+
 def test_batch_with_a_pattern_chunked_codon_member():
     """A 64-state member under an HBM budget (pattern chunks) leaves the merged launches and is
     evaluated on its own inside the batch; every member still matches the oracle."""
