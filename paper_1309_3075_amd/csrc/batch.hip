@@ -56,7 +56,7 @@ struct EpochBatch {
   bool own_stream = false;
   // branch streams of the captured graph: members whose launches are their own (not the
   // merged levels) run on kBatchBranches streams forked from and joined back to `stream`
-  static constexpr int kBatchBranches = 4;
+  static constexpr int kBatchBranches = 16;
   hipStream_t branch[kBatchBranches] = {};
   hipEvent_t fork_ev = nullptr;
   hipEvent_t join_ev[kBatchBranches] = {};

@@ -76,7 +76,7 @@ def test_nucleotide_batch_unmerged_path():
 
 
 def test_members_on_concurrent_branches_match_single_evaluations():
-    """Members that run their own launches are captured on four concurrent branches: eleven members
+    """Members that run their own launches are captured on concurrent branches: eleven members
     of three kernel families (4-state walk and level kernels, generic 20-state with dlogL/dQ, a
     40-state member) give the bits of their single evaluations, on every replay."""
     rng = np.random.default_rng(77)
