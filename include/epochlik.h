@@ -372,7 +372,10 @@ int epoch_get_work_counts(EpochInstance* inst, int64_t* out);
  * A batch references n distinct, fully set-up instances (eigensystems, tree,
  * tips, weights, categories, root frequencies); it does not own them and they
  * must outlive it.  Members on the 64-state path share merged per-level
- * launches; the graph is captured at the first evaluation and replayed, and
+ * launches; every other member's launches (and each member's dlogL/dQ) form
+ * independent branches of the graph, which the GPU runs concurrently; a member's
+ * results are the bits of its single evaluation.  The graph is captured at the
+ * first evaluation and replayed, and
  * captured again when a member's tree or eigen-reconstruction precision
  * changes or epoch_set_option is called on a member.  tune_cache_path (or NULL) names a text file caching the tuned
  * launch shape per device and batch shape; it is read, and written after
