@@ -1,5 +1,7 @@
 // Codon-sized (and amino-acid-sized) kernels on the matrix cores: FP32
-// (v_mfma_f32_16x16x4f32) and FP64 (v_mfma_f64_16x16x4f64).
+// (v_mfma_f32_16x16x4f32) and FP64 (v_mfma_f64_16x16x4f64); an FP32 tip
+// child's dlogL/dP also on v_mfma_f32_16x16x32_bf16, with the FP32 operand
+// split exactly into three bf16 parts (grad_rows_tip_bf16).
 //
 // Applies to instances with 48 < K <= 64 (padded to KP = 64, NT = 4 tiles of
 // 16 states) or 16 < K <= 32 (padded to KP = 32, NT = 2).  Each rate category
@@ -433,12 +435,63 @@ __device__ inline void grad_rows_internal(v4<T>* G, const T* __restrict__ tcol, 
     for (int c = 0; c < NCT; ++c) G[c] = mfma(av, B[c], G[c]);
   }
 }
+// FP32 tip child without ambiguity codes, on the bf16 matrix cores
+// (v_mfma_f32_16x16x32_bf16, 32 patterns per instruction against 4): the B
+// operand is the 0/1 tip indicator, which bf16 holds exactly, and the A
+// operand t w_p / L_p is split into three bf16 parts h + m + l that add up to
+// the FP32 value (each part takes the next 8 significand bits, and the
+// remainders are exact in FP32), so the three products accumulated in FP32
+// give dlogL/dP to FP32 rounding, as the FP32 product would.  Lane (g, r)
+// supplies patterns 8 g .. 8 g + 7 of each 32-pattern block for row r of A
+// and column r of B; D has the FP32 layout.
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef int i4 __attribute__((ext_vector_type(4)));
+template <int NT>
+__device__ inline void grad_rows_tip_bf16(f4* G, const float* __restrict__ tcol, const float* __restrict__ sCF,
+                                          const int* __restrict__ sCol, int K, int ct0, int g, int r) {
+  EPOCH_DIMS(NT);
+  constexpr int NCT = Dim<NT>::NCT;
+#pragma unroll
+  for (int kb = 0; kb < TILE / 32; ++kb) {
+    const int p0 = 32 * kb + 8 * g;
+    const f4 cf0 = *reinterpret_cast<const f4*>(sCF + p0), cf1 = *reinterpret_cast<const f4*>(sCF + p0 + 4);
+    const float cf[8] = {cf0.x, cf0.y, cf0.z, cf0.w, cf1.x, cf1.y, cf1.z, cf1.w};
+    bf8 ah, am, al;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const float av = tcol[(p0 + e) * LDP] * cf[e];
+      const __bf16 h = (__bf16)av;
+      const float r1 = av - (float)h;
+      const __bf16 m = (__bf16)r1;
+      ah[e] = h;
+      am[e] = m;
+      al[e] = (__bf16)(r1 - (float)m);
+    }
+    const i4 cl0 = *reinterpret_cast<const i4*>(sCol + p0), cl1 = *reinterpret_cast<const i4*>(sCol + p0 + 4);
+    const int col[8] = {cl0.x, cl0.y, cl0.z, cl0.w, cl1.x, cl1.y, cl1.z, cl1.w};
+#pragma unroll
+    for (int c = 0; c < NCT; ++c) {
+      const int j = 16 * (ct0 + c) + r;
+      bf8 B;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) B[e] = (col[e] == j || (col[e] == KP && j < K)) ? (__bf16)1.0f : (__bf16)0.0f;
+      G[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, B, G[c], 0, 0, 0);
+      G[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, B, G[c], 0, 0, 0);
+      G[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, B, G[c], 0, 0, 0);
+    }
+  }
+}
+
 template <int NT, bool AMB, typename T>
 __device__ inline void grad_rows_tip(v4<T>* G, const T* __restrict__ tcol, const T* __restrict__ sCF,
                                      const int* __restrict__ sCol, int K, int ct0, int g, int r,
                                      const uint64_t* __restrict__ amb) {
   EPOCH_DIMS(NT);
   constexpr int NCT = Dim<NT>::NCT;
+  if constexpr (sizeof(T) == 4 && !AMB) {
+    grad_rows_tip_bf16<NT>(G, tcol, sCF, sCol, K, ct0, g, r);
+    return;
+  }
 #pragma unroll 8
   for (int ks = 0; ks < TILE / 4; ++ks) {
     const int pl = 4 * ks + g;
@@ -530,8 +583,8 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void codon_pre_level_k
   __shared__ __align__(16) T sPb[KP * LDP];
   __shared__ __align__(16) T sT[TILE * LDP];  // t of one side for the block tile, pattern-major
   __shared__ __align__(16) T sL[TILE * LDP];  // that side's child partials for the block tile
-  __shared__ T sCF[TILE];                     // w_p / L_p of the block tile
-  __shared__ int sCol[2][TILE];                    // tip columns of the block tile
+  __shared__ __align__(16) T sCF[TILE];         // w_p / L_p of the block tile
+  __shared__ __align__(16) int sCol[2][TILE];   // tip columns of the block tile
   const int2 it = items[blockIdx.y];
   const CodonProblem& pr = probs[it.x];
   const int N = pr.N, P = pr.P, K = pr.K;
@@ -690,8 +743,8 @@ struct PreSplitShared {
   __align__(16) float sS[2][TILE * LDP];  // each side's child vectors for the block tile
   __align__(16) float sT[2][TILE * LDP];  // each side's t = q o S_sibling
   __align__(16) float sL[2][TILE * LDP];  // each side's child partials
-  float sCF[TILE];
-  int sCol[2][TILE];
+  __align__(16) float sCF[TILE];
+  __align__(16) int sCol[2][TILE];
 };
 
 struct SplitTileLoads {
