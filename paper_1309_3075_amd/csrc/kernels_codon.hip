@@ -488,7 +488,7 @@ __device__ inline void grad_rows_tip(v4<T>* G, const T* __restrict__ tcol, const
                                      const uint64_t* __restrict__ amb) {
   EPOCH_DIMS(NT);
   constexpr int NCT = Dim<NT>::NCT;
-  if constexpr (sizeof(T) == 4 && !AMB) {
+  if constexpr (sizeof(T) == 4 && !AMB && NCT >= 4) {  // the split pays off over four column tiles, not one
     grad_rows_tip_bf16<NT>(G, tcol, sCF, sCol, K, ct0, g, r);
     return;
   }
