@@ -598,6 +598,14 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void codon_pre_level_k
   }
   const int n_tiles = min(R, (P - base + TILE - 1) / TILE);  // uniform over the block
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
+  const T* part = reinterpret_cast<const T*>(pr.part);
+  T* pre = reinterpret_cast<T*>(pr.pre);
+  const T* La = a >= N ? part + (size_t)(a - N) * P * KP : nullptr;
+  const T* Lb = b >= N ? part + (size_t)(b - N) * P * KP : nullptr;
+  const T* Qu = u == pr.root ? nullptr : pre + (size_t)(u - N) * P * KP;
+  // the first tile's loads go out before the matrices are staged, so the two wait together
+  PreTileLoads<T, NT> cur, nxt;
+  pre_load_tile<NT, T>(cur, pr, La, Lb, Qu, a, b, base + WT * w, g, r);
   const T* Pm = reinterpret_cast<const T*>(pr.Pm);
   stage_matrix<NT>(sPa, Pm + (size_t)a * pr.pm_stride);
   stage_matrix<NT>(sPb, Pm + (size_t)b * pr.pm_stride);
@@ -605,11 +613,6 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void codon_pre_level_k
   stage_row_sums<NT>(sPa, K);
   stage_row_sums<NT>(sPb, K);
   __syncthreads();
-  const T* part = reinterpret_cast<const T*>(pr.part);
-  T* pre = reinterpret_cast<T*>(pr.pre);
-  const T* La = a >= N ? part + (size_t)(a - N) * P * KP : nullptr;
-  const T* Lb = b >= N ? part + (size_t)(b - N) * P * KP : nullptr;
-  const T* Qu = u == pr.root ? nullptr : pre + (size_t)(u - N) * P * KP;
   T piv[NT];
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) piv[nt] = 16 * nt + r < K ? (T)pr.pi[16 * nt + r] : T(0);
@@ -621,12 +624,13 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void codon_pre_level_k
     Ga[c] = v4<T>{0, 0, 0, 0};
     Gb[c] = v4<T>{0, 0, 0, 0};
   }
-  PreTileLoads<T, NT> cur, nxt;
-  pre_load_tile<NT, T>(cur, pr, La, Lb, Qu, a, b, base + WT * w, g, r);
   T* trows = sT + (WT * w) * LDP;  // this wavefront's 16 pattern rows
   T* lrows = sL + (WT * w) * LDP;
   for (int bt = 0; bt < n_tiles; ++bt) {
     const int p0 = base + bt * TILE + WT * w;  // first pattern of this wavefront's part
+    T wts[4];  // pattern weights of this wavefront's rows, in flight during the child products
+#pragma unroll
+    for (int v = 0; v < 4; ++v) wts[v] = gptr(reinterpret_cast<const T*>(pr.weightsT))[min(p0 + drow<T>(g, v), P - 1)];
     // ---- this wavefront's 16 patterns: child vectors, q_u, w_p / L_p
     v4<T> Sa[NT], Sb[NT];
     if (La)
@@ -648,7 +652,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void codon_pre_level_k
       sum = row16_sum(sum);
       const int p = p0 + drow<T>(g, v);
       if (r == 0) {
-        sCF[WT * w + drow<T>(g, v)] = (p < P && sum > T(0)) ? gptr(reinterpret_cast<const T*>(pr.weightsT))[p] / sum : T(0);
+        sCF[WT * w + drow<T>(g, v)] = (p < P && sum > T(0)) ? wts[v] / sum : T(0);
         if (!La) sCol[0][WT * w + drow<T>(g, v)] = cur.cola[v];
         if (!Lb) sCol[1][WT * w + drow<T>(g, v)] = cur.colb[v];
       }
