@@ -179,32 +179,6 @@ __device__ inline double row16_sum(double v) {
   return v;
 }
 
-// S[nt] (D layout) = sum_j L[p][j] P[16 nt + r][j] for an internal child whose
-// partials start at Lg.  Pattern rows past the end are clamped (their results
-// are never stored).
-template <int NT, typename T>
-__device__ inline void child_gemm(v4<T> (&S)[NT], const T* __restrict__ Lg, int P, int p0,
-                                  const T* __restrict__ sP, int g, int r) {
-  EPOCH_DIMS(NT);
-#pragma unroll
-  for (int nt = 0; nt < NT; ++nt) S[nt] = v4<T>{0, 0, 0, 0};
-  const int pa = min(p0 + r, P - 1);
-  const EPOCH_GLOBAL v4<T>* arow = gptr(reinterpret_cast<const v4<T>*>(Lg + (size_t)pa * KP)) + g;
-  v4<T> a[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) a[t] = arow[4 * t];  // L[pa][16 t + 4 g .. 16 t + 4 g + 3]
-#pragma unroll
-  for (int t = 0; t < NT; ++t)
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      const v4<T> b = *reinterpret_cast<const v4<T>*>(sP + (16 * nt + r) * LDP + 16 * t + 4 * g);
-      S[nt] = mfma(a[t].x, b.x, S[nt]);
-      S[nt] = mfma(a[t].y, b.y, S[nt]);
-      S[nt] = mfma(a[t].z, b.z, S[nt]);
-      S[nt] = mfma(a[t].w, b.w, S[nt]);
-    }
-}
-
 // Tip states of the patterns of D-layout rows v as LDS columns: an observed
 // state is its column, a missing one column KP (the row sums), and the
 // caller's ambiguity set a is KP + 1 + a (text after Eq. 4: tips are 0/1
@@ -262,75 +236,6 @@ __device__ inline void load_dlayout(v4<T> (&X)[NT], const T* __restrict__ base, 
 
 __device__ inline float dmax(float a, float b) { return fmaxf(a, b); }
 __device__ inline double dmax(double a, double b) { return fmax(a, b); }
-
-// ---------------------------------------------------------------------------
-template <typename T, int NT, bool AMB>
-__global__ __launch_bounds__(256) void codon_post_level_kernel(const CodonProblem* __restrict__ probs,
-                                                                const int2* __restrict__ items, int R) {
-  EPOCH_DIMS(NT);
-  __shared__ __align__(16) T sPa[KP * LDP];
-  __shared__ __align__(16) T sPb[KP * LDP];
-  const int2 it = items[blockIdx.y];
-  const CodonProblem& pr = probs[it.x];
-  const int N = pr.N, P = pr.P, K = pr.K;
-  const int base = blockIdx.x * R * TILE;
-  if (base >= P) return;  // uniform: this problem has fewer tiles
-  const int end = min(P, base + R * TILE);
-  const int u = it.y;
-  const int a = pr.left[u], b = pr.right[u];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
-  const T* Pm = reinterpret_cast<const T*>(pr.Pm);
-  stage_matrix<NT>(sPa, Pm + (size_t)a * pr.pm_stride);
-  stage_matrix<NT>(sPb, Pm + (size_t)b * pr.pm_stride);
-  __syncthreads();
-  stage_row_sums<NT>(sPa, K);
-  stage_row_sums<NT>(sPb, K);
-  __syncthreads();
-  T* part = reinterpret_cast<T*>(pr.part);
-  const T* La = a >= N ? part + (size_t)(a - N) * P * KP : nullptr;
-  const T* Lb = b >= N ? part + (size_t)(b - N) * P * KP : nullptr;
-  const int32_t* sca = a >= N ? pr.scales + (size_t)(a - N) * P : nullptr;
-  const int32_t* scb = b >= N ? pr.scales + (size_t)(b - N) * P : nullptr;
-  EPOCH_GLOBAL T* out = gptr(part + (size_t)(u - N) * P * KP);
-  EPOCH_GLOBAL int32_t* sout = gptr(pr.scales + (size_t)(u - N) * P);
-  for (int p0 = base + WT * w; p0 < end; p0 += 4 * WT) {
-    v4<T> Sa[NT], Sb[NT];
-    if (La) {
-      child_gemm<NT, T>(Sa, La, P, p0, sPa, g, r);
-    } else {
-      int col[4];
-      tip_columns<NT, T>(col, pr.tips + (size_t)a * pr.tip_stride, P, p0, K, g);
-      tip_lookup<NT, AMB, T>(Sa, col, sPa, r, pr.amb);
-    }
-    if (Lb) {
-      child_gemm<NT, T>(Sb, Lb, P, p0, sPb, g, r);
-    } else {
-      int col[4];
-      tip_columns<NT, T>(col, pr.tips + (size_t)b * pr.tip_stride, P, p0, K, g);
-      tip_lookup<NT, AMB, T>(Sb, col, sPb, r, pr.amb);
-    }
-    int e[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      T m = 0;
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        Sa[nt][v] *= Sb[nt][v];
-        m = dmax(m, Sa[nt][v]);
-      }
-      e[v] = scale_exponent(row16_max(m));
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int p = p0 + drow<T>(g, v);
-      if (p < P) {
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) __builtin_nontemporal_store(scale_by_pow2(Sa[nt][v], e[v]), &out[(size_t)p * KP + 16 * nt + r]);
-        if (r == 0) sout[p] = e[v] + (sca ? gptr(sca)[p] : 0) + (scb ? gptr(scb)[p] : 0);
-      }
-    }
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Root: one thread per pattern, in FP64; block partial sums of w_p log L_p per
@@ -573,6 +478,85 @@ __device__ inline void child_gemm_regs(v4<T> (&S)[NT], const v4<T> (&a)[NT], con
       S[nt] = mfma(a[t].w, bv.w, S[nt]);
     }
 }
+
+// ---------------------------------------------------------------------------
+template <typename T, int NT, bool AMB>
+__global__ __launch_bounds__(256) void codon_post_level_kernel(const CodonProblem* __restrict__ probs,
+                                                                const int2* __restrict__ items, int R) {
+  EPOCH_DIMS(NT);
+  __shared__ __align__(16) T sPa[KP * LDP];
+  __shared__ __align__(16) T sPb[KP * LDP];
+  const int2 it = items[blockIdx.y];
+  const CodonProblem& pr = probs[it.x];
+  const int N = pr.N, P = pr.P, K = pr.K;
+  const int base = blockIdx.x * R * TILE;
+  if (base >= P) return;  // uniform: this problem has fewer tiles
+  const int end = min(P, base + R * TILE);
+  const int u = it.y;
+  const int a = pr.left[u], b = pr.right[u];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
+  T* part = reinterpret_cast<T*>(pr.part);
+  const T* La = a >= N ? part + (size_t)(a - N) * P * KP : nullptr;
+  const T* Lb = b >= N ? part + (size_t)(b - N) * P * KP : nullptr;
+  const int32_t* sca = a >= N ? pr.scales + (size_t)(a - N) * P : nullptr;
+  const int32_t* scb = b >= N ? pr.scales + (size_t)(b - N) * P : nullptr;
+  EPOCH_GLOBAL T* out = gptr(part + (size_t)(u - N) * P * KP);
+  EPOCH_GLOBAL int32_t* sout = gptr(pr.scales + (size_t)(u - N) * P);
+  // child rows (or tip columns) and the children's scale exponents of a tile: the first tile's loads
+  // go out before the matrices are staged, so the two memory round trips overlap; each later tile's
+  // at the end of the tile before it
+  auto load = [&](PreTileLoads<T, NT>& ld, int (&csc)[4], int p0) {
+    pre_load_tile<NT, T>(ld, pr, La, Lb, nullptr, a, b, p0, g, r);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int pc = min(p0 + drow<T>(g, v), P - 1);
+      csc[v] = (sca ? gptr(sca)[pc] : 0) + (scb ? gptr(scb)[pc] : 0);
+    }
+  };
+  PreTileLoads<T, NT> cur;
+  int csc[4];
+  load(cur, csc, base + WT * w);
+  const T* Pm = reinterpret_cast<const T*>(pr.Pm);
+  stage_matrix<NT>(sPa, Pm + (size_t)a * pr.pm_stride);
+  stage_matrix<NT>(sPb, Pm + (size_t)b * pr.pm_stride);
+  __syncthreads();
+  stage_row_sums<NT>(sPa, K);
+  stage_row_sums<NT>(sPb, K);
+  __syncthreads();
+  for (int p0 = base + WT * w; p0 < end; p0 += 4 * WT) {
+    v4<T> Sa[NT], Sb[NT];
+    if (La)
+      child_gemm_regs<NT, T>(Sa, cur.La, sPa, g, r);
+    else
+      tip_lookup<NT, AMB, T>(Sa, cur.cola, sPa, r, pr.amb);
+    if (Lb)
+      child_gemm_regs<NT, T>(Sb, cur.Lb, sPb, g, r);
+    else
+      tip_lookup<NT, AMB, T>(Sb, cur.colb, sPb, r, pr.amb);
+    int e[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      T m = 0;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        Sa[nt][v] *= Sb[nt][v];
+        m = dmax(m, Sa[nt][v]);
+      }
+      e[v] = scale_exponent(row16_max(m));
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int p = p0 + drow<T>(g, v);
+      if (p < P) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) __builtin_nontemporal_store(scale_by_pow2(Sa[nt][v], e[v]), &out[(size_t)p * KP + 16 * nt + r]);
+        if (r == 0) sout[p] = e[v] + csc[v];
+      }
+    }
+    if (p0 + 4 * WT < end) load(cur, csc, p0 + 4 * WT);
+  }
+}
+
 
 template <typename T, int NT, bool AMB>
 __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void codon_pre_level_kernel(
