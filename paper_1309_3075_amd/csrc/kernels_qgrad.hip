@@ -596,25 +596,29 @@ __global__ __launch_bounds__(256) void qgrad_hsum_kernel(int KK, int n_chunks, c
   reinterpret_cast<double2*>(Hsum)[(size_t)s * KK + e] = make_double2(a0.x + a1.x, a0.y + a1.y);
 }
 
-// dQ_s = V^-T Re(T^-T H_s T^T) V^T.  Block (s, band) forms rows 16 band ..
-// 16 band + 15: X = Re(T^-T H T^T) in LDS, then those rows of Y = V^-T X
-// (the 16 columns of V^-1 staged in LDS), then dQ rows = Y_rows V^T with V
-// replacing X in LDS, its rows padded to Kp + 1 doubles so that lanes reading
-// one column of different rows fall in different banks (Kp (Kp + 1) + 32 Kp
-// doubles).
+// dQ_s = V^-T Re(T^-T H_s T^T) V^T.  Block (s, band) forms rows kFinalRows band
+// .. kFinalRows (band + 1) - 1: X = Re(T^-T H T^T) in LDS, then those rows of
+// Y = V^-T X (the band's columns of V^-1 staged in LDS), then dQ rows =
+// Y_rows V^T with V replacing X in LDS, its rows padded to Kp + 1 doubles so
+// that lanes reading one column of different rows fall in different banks
+// (Kp (Kp + 1) + 2 kFinalRows Kp doubles).  Bands of 4 rows give S Kp / 4
+// blocks: every block forms the whole X, but the two products, serial per
+// thread, are 4 times shorter than with bands of 16.
+constexpr int kFinalRows = 4;
 __global__ __launch_bounds__(256) void qgrad_final_kernel(int K, int Kp, const double* __restrict__ Hsum,
                                                           const double* __restrict__ V, const double* __restrict__ Vi,
                                                           const double* __restrict__ li_all, double* __restrict__ dQ) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int s = blockIdx.x, r0 = 16 * blockIdx.y;
+  constexpr int BR = kFinalRows;
+  const int s = blockIdx.x, r0 = BR * blockIdx.y;
   const int KK = Kp * Kp;
   double* sX = reinterpret_cast<double*>(smem_raw);
-  double* sY = sX + Kp * (Kp + 1);  // 16 x Kp
-  double* sVi = sY + 16 * Kp;       // Kp x 16: columns r0 .. r0 + 15 of V^-1
+  double* sY = sX + Kp * (Kp + 1);  // BR x Kp
+  double* sVi = sY + BR * Kp;       // Kp x BR: columns r0 .. r0 + BR - 1 of V^-1
   const double* li = li_all + (size_t)s * Kp;
   const double2* H = reinterpret_cast<const double2*>(Hsum) + (size_t)s * KK;
   const double* Vis = Vi + (size_t)s * KK;
-  for (int e = threadIdx.x; e < 16 * Kp; e += 256) sVi[e] = Vis[(e >> 4) * Kp + r0 + (e & 15)];
+  for (int e = threadIdx.x; e < BR * Kp; e += 256) sVi[e] = Vis[(e / BR) * Kp + r0 + e % BR];
   for (int e = threadIdx.x; e < KK; e += 256) {
     const int a = e / Kp, b = e % Kp;
     const PairIdx pa = pair_of(li, a), pb = pair_of(li, b);
@@ -633,17 +637,17 @@ __global__ __launch_bounds__(256) void qgrad_final_kernel(int K, int Kp, const d
     sX[e] = re;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < 16 * Kp; e += 256) {
+  for (int e = threadIdx.x; e < BR * Kp; e += 256) {
     const int ii = e / Kp, j = e % Kp;
     double r = 0.0;
-    for (int l = 0; l < Kp; ++l) r += sVi[l * 16 + ii] * sX[l * Kp + j];
+    for (int l = 0; l < Kp; ++l) r += sVi[l * BR + ii] * sX[l * Kp + j];
     sY[e] = r;
   }
   __syncthreads();
   double* sV = sX;  // row stride Kp + 1
   for (int e = threadIdx.x; e < KK; e += 256) sV[(e / Kp) * (Kp + 1) + e % Kp] = V[(size_t)s * KK + e];
   __syncthreads();
-  for (int e = threadIdx.x; e < 16 * Kp; e += 256) {
+  for (int e = threadIdx.x; e < BR * Kp; e += 256) {
     const int i = r0 + e / Kp, j = e % Kp;
     if (i < K && j < K) {
       double r = 0.0;
@@ -689,7 +693,8 @@ int qgrad_mfma_launch(EpochInstance* in) {
                      (int)KK, in->q_chunks, static_cast<const double*>(Hpart), Hsum);
   rc = hip_check(hipGetLastError(), "qgrad_h launch");
   if (rc) return rc;
-  hipLaunchKernelGGL(qgrad_final_kernel, dim3(in->S, Kp / 16), dim3(256), (KK + 33 * Kp) * sizeof(double),
+  hipLaunchKernelGGL(qgrad_final_kernel, dim3(in->S, Kp / kFinalRows), dim3(256),
+                     (KK + (2 * kFinalRows + 1) * Kp) * sizeof(double),
                      in->stream, in->K, Kp, static_cast<const double*>(Hsum), b64, b64 + S * KK,
                      b64 + 2 * S * KK + S * Kp, static_cast<double*>(in->dQ.ptr));
   return hip_check(hipGetLastError(), "qgrad_final launch");
